@@ -1,0 +1,194 @@
+/*
+ * heom.h -- C ABI of the MI355X HEOM library (matrix-free HEOM Liouvillian
+ * apply, RK4 propagation, stationary state, spectra, batched solves and a
+ * learned block preconditioner), after arXiv 2306.07522.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Complex numbers are interleaved (re, im).  Host matrices are d x d,
+ *    row-major, complex double.
+ *  - An ADO vector is [N][d][d] complex (row-major blocks, ADO index major);
+ *    with R right-hand sides it is [N][d][d][R] (R innermost).  FP64 vectors
+ *    hold double pairs, FP32 vectors float pairs.  ADO 0 is the reduced
+ *    density operator.
+ *  - Fermionic ADOs are antisymmetric in their exponent indices: the stored
+ *    ADO of an exponent set S is rho_{[s_n .. s_1]} with s_n > ... > s_1 in
+ *    the exponent numbering below.  Bosonic ADOs are symmetric and are
+ *    stored once per multiset, unnormalised (no sqrt(n!) factors).
+ *  - Exponent numbering: bosonic exponents in bath-record order, then in
+ *    list order; fermionic exponents in bath-record order, then h, then
+ *    nu = +1 before nu = -1 (index = base + 2h + (nu == -1)).
+ *  - Device pointers are HIP device memory owned by the caller; `stream`
+ *    is a hipStream_t (NULL = default stream).  Host pointers are read
+ *    during the call only.
+ *  - No exception crosses the ABI.  Every entry point returns a status;
+ *    on error the outputs are unspecified and heom_last_error() returns a
+ *    thread-local message.
+ *  - A handle is immutable after build and may be used from several
+ *    streams at once provided each call has its own workspace.
+ */
+#ifndef HEOM_H
+#define HEOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t heom_status;
+enum {
+  HEOM_OK = 0,
+  HEOM_ERR_ARG = 1,           /* invalid argument                       */
+  HEOM_ERR_ALLOC = 2,         /* host or device allocation failed        */
+  HEOM_ERR_HIP = 3,           /* a HIP runtime call failed               */
+  HEOM_ERR_NOT_CONVERGED = 4, /* iterative solver hit its limit          */
+  HEOM_ERR_SINGULAR = 5,      /* breakdown / zero pivot                  */
+  HEOM_ERR_UNSUPPORTED = 6,   /* size or feature outside what is built   */
+  HEOM_ERR_NAN = 7            /* non-finite value detected               */
+};
+
+enum { HEOM_FP64 = 0, HEOM_FP32 = 1 };
+enum { HEOM_BOSON = 0, HEOM_FERMION = 1 };
+/* bosonic exponent type u (eq:C_beta_RI): real part, imaginary part, or
+ * both at once when chi is real */
+enum { HEOM_U_R = 0, HEOM_U_I = 1, HEOM_U_RI = 2 };
+enum { HEOM_PADE = 0, HEOM_MATSUBARA = 1 };
+
+typedef struct heom_hier heom_hier; /* opaque hierarchy + device tables  */
+typedef struct heom_nn heom_nn;     /* opaque learned preconditioner     */
+
+/* ------------------------------------------------------------------------
+ * Exponents (Methods: Lorentzian fermionic and Drude-Lorentz bosonic
+ * correlation functions; eq:C_f_exp, eq:C_b_exp)
+ * ---------------------------------------------------------------------- */
+
+/* [N-1/N] Pade (method HEOM_PADE) or Matsubara (HEOM_MATSUBARA)
+ * parameters of the Fermi (kind HEOM_FERMION) or Bose (HEOM_BOSON)
+ * function: n_F(x) ~ 1/2 - sum 2 kappa x/(x^2 + zeta^2),
+ * n_B(x) ~ 1/x - 1/2 + sum 2 kappa x/(x^2 + zeta^2).  kappa, zeta: host
+ * arrays of n doubles, zeta ascending.  n in [0, 64]. */
+heom_status heom_pade_params(int32_t kind, int32_t method, int32_t n, double *kappa, double *zeta);
+
+/* Lorentzian lead J = Gamma W^2 / ((w - mu)^2 + W^2) at temperature T with
+ * n_exp terms (h = 1 the J pole, h >= 2 distribution poles).  Outputs are
+ * host complex arrays of n_exp: eta and gamma for nu = +1 and nu = -1.
+ *   eta_1 = (Gamma W / 2) n_F(i W / T), gamma^nu_1 = W - nu i mu,
+ *   eta_h = -i kappa T Gamma W^2 / (W^2 - (zeta T)^2),
+ *   gamma^nu_h = zeta T - nu i mu. */
+heom_status heom_exponents_lorentz(double Gamma, double W, double mu, double T, int32_t n_exp,
+                                   int32_t method, double *eta_p, double *gam_p, double *eta_m,
+                                   double *gam_m);
+
+/* Drude-Lorentz bath J = 4 lam gamma w / (w^2 + gamma^2) (with the 1/2pi
+ * of eq:C_b) at temperature T, n_exp terms, all with real chi ("RI"):
+ *   xi_1 = lam gamma (cot(gamma / 2T) - i), chi_1 = gamma,
+ *   xi_l = 4 kappa lam gamma T (zeta T) / ((zeta T)^2 - gamma^2), chi_l = zeta T.
+ * xi, chi: host complex arrays of n_exp. */
+heom_status heom_exponents_drude_lorentz(double lam, double gamma, double T, int32_t n_exp,
+                                         int32_t method, double *xi, double *chi);
+
+/* ------------------------------------------------------------------------
+ * Hierarchy (eq:HEOM, the multi-index paragraph and the truncation rules)
+ * ---------------------------------------------------------------------- */
+
+/* One bath = one coupling operator and its exponents (Fig. 1b). */
+typedef struct {
+  int32_t kind;           /* HEOM_BOSON (V Hermitian) or HEOM_FERMION (d)   */
+  const double *op;       /* d x d complex: V, or the annihilation op d     */
+  int32_t n_exp;          /* boson: number of exponents; fermion: number of h */
+  /* boson */
+  const int32_t *u_type;  /* n_exp of HEOM_U_R / HEOM_U_I / HEOM_U_RI        */
+  const double *xi;       /* n_exp complex                                   */
+  const double *chi;      /* n_exp complex                                   */
+  /* fermion: h-paired lists for nu = +1 and nu = -1 */
+  const double *eta_p, *gam_p, *eta_m, *gam_m; /* n_exp complex each        */
+} heom_bath;
+
+typedef struct {
+  int64_t n_ado;          /* N                                               */
+  int32_t d;
+  int32_t n_bos_exp;      /* K_b                                             */
+  int32_t n_ferm_exp;     /* K_f                                             */
+  int32_t m_max, n_max;   /* effective truncation tiers                      */
+  int32_t parity;         /* +1 even, -1 odd                                 */
+  int32_t n_ops;          /* distinct operators (H, V's, d and d^dagger's)   */
+  int64_t n_edges;        /* tier-coupling terms (neighbour table entries)   */
+  int64_t n_leaf;         /* ADOs with no higher-tier neighbour              */
+  int32_t n_tiers;        /* number of (m + n) tiers                         */
+  int64_t tier_offset[34];/* first ADO of each tier, tier_offset[n_tiers] = N */
+  int64_t table_bytes;    /* device bytes of the neighbour/decay tables      */
+  int64_t vector_bytes_fp64; /* N d^2 * 16                                   */
+} heom_info;
+
+/* Build the hierarchy of ADOs for system Hamiltonian H (d x d Hermitian)
+ * coupled to n_baths baths, truncated at bosonic tier m_max and fermionic
+ * tier n_max, in parity sector `parity` (+1 even, -1 odd; eq:HEOM's p).
+ * Host-side only: device tables are uploaded on the first device call.
+ * parity_op: optional d x d fermionic parity operator; when given, H and
+ * every bosonic V must commute with it and every fermionic d anticommute
+ * (HEOM_ERR_ARG otherwise).  Checks: H and V Hermitian (1e-12 relative),
+ * K_f <= 64, d <= 64, N < 2^31.  *out is released with heom_free. */
+heom_status heom_build_hierarchy(int32_t d, const double *H, int32_t n_baths, const heom_bath *baths,
+                                 int32_t m_max, int32_t n_max, int32_t parity,
+                                 const double *parity_op, heom_hier **out);
+void heom_free(heom_hier *h);
+heom_status heom_hierarchy_info(const heom_hier *h, heom_info *out);
+
+/* Hierarchy dictionary (Fig. 1e): the multi-index of every ADO.
+ * bos_occ: host int32 [N][K_b] occupation of each bosonic exponent (may be
+ * NULL); ferm_mask: host uint64 [N] bit k set when fermionic exponent k is
+ * present (may be NULL); level: host int32 [N][2] = (m, n) (may be NULL). */
+heom_status heom_hierarchy_ados(const heom_hier *h, int32_t *bos_occ, uint64_t *ferm_mask, int32_t *level);
+
+/* Inverse lookup: the index of the ADO whose bosonic occupations are
+ * bos_occ[K_b] and whose fermionic exponents are ferm_ids[n_f] in the
+ * given order; *sign receives the permutation sign that relates the given
+ * order to the stored one (rho_given = sign * rho_stored).  *idx = -1 when
+ * the ADO is outside the hierarchy. */
+heom_status heom_ado_index(const heom_hier *h, const int32_t *bos_occ, const int32_t *ferm_ids,
+                           int32_t n_f, int64_t *idx, int32_t *sign);
+
+/* Host copy of the diagonal decay c_a = sum_k n_k chi_k + sum_{q in a} gamma_q
+ * (complex [N]) and of the neighbour table in CSR form: row_ptr [N+1],
+ * col [E] (neighbour ADO), kind [E] (0 bos up, 1 bos down, 2 ferm up,
+ * 3 ferm down), exp [E] (exponent index), mult [E] (bosonic multiplicity or
+ * fermionic reorder sign).  Any pointer may be NULL. */
+heom_status heom_hierarchy_tables(const heom_hier *h, double *decay, int64_t *row_ptr, int32_t *col,
+                                  int32_t *kind, int32_t *exp, int32_t *mult);
+
+/* ------------------------------------------------------------------------
+ * Liouvillian apply (eq:HEOM; the HEOMLS M acting on the ADO vector)
+ * ---------------------------------------------------------------------- */
+
+/* y = (M + shift I) x for n_rhs right-hand sides ([N][d][d][R] vectors).
+ * shift: host pointer to one complex number applied to every right-hand
+ * side, or NULL for zero.  precision HEOM_FP64 / HEOM_FP32 selects the
+ * element type of x and y.  x and y must not overlap.  Device tables are
+ * uploaded on the first call (this first call allocates).  Asynchronous on
+ * `stream`. */
+heom_status heom_apply(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                       const double *shift, void *stream);
+
+/* As heom_apply, with one shift per right-hand side: column r gets
+ * shifts_dev[r], a device array of n_rhs complex numbers of the same
+ * precision as x and y. */
+heom_status heom_apply_shifted(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                               const void *shifts_dev, void *stream);
+
+/* Apply with the top tier split into `n_chunks` column blocks (one launch
+ * per block plus one for the lower tiers) so that each block's neighbour
+ * reads stay cache-resident.  Same result as heom_apply up to rounding
+ * order.  n_chunks <= 0 picks the library default. */
+heom_status heom_apply_tiled(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev,
+                             int32_t n_rhs, const double *shift, int32_t n_chunks, void *stream);
+
+const char *heom_status_string(heom_status s);
+const char *heom_last_error(void);
+const char *heom_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEOM_H */

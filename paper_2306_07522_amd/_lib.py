@@ -1,0 +1,101 @@
+"""ctypes declarations of the C ABI in include/heom.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheom.so")
+
+heom_status = C.c_int32
+vp = C.c_void_p
+dp = C.POINTER(C.c_double)
+i32p = C.POINTER(C.c_int32)
+i64p = C.POINTER(C.c_int64)
+u64p = C.POINTER(C.c_uint64)
+
+HEOM_FP64, HEOM_FP32 = 0, 1
+HEOM_BOSON, HEOM_FERMION = 0, 1
+HEOM_U_R, HEOM_U_I, HEOM_U_RI = 0, 1, 2
+HEOM_PADE, HEOM_MATSUBARA = 0, 1
+HEOM_OP_PROPAGATE, HEOM_OP_STEADY, HEOM_OP_SPECTRUM = 0, 1, 2
+HEOM_PREC_NONE, HEOM_PREC_JACOBI, HEOM_PREC_NN = 0, 1, 2
+HEOM_SOLVE_FP64, HEOM_SOLVE_FP32_IR = 0, 1
+
+
+class heom_bath(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("op", dp), ("n_exp", C.c_int32), ("u_type", i32p), ("xi", dp), ("chi", dp),
+                ("eta_p", dp), ("gam_p", dp), ("eta_m", dp), ("gam_m", dp)]
+
+
+class heom_info(C.Structure):
+    _fields_ = [("n_ado", C.c_int64), ("d", C.c_int32), ("n_bos_exp", C.c_int32), ("n_ferm_exp", C.c_int32),
+                ("m_max", C.c_int32), ("n_max", C.c_int32), ("parity", C.c_int32), ("n_ops", C.c_int32),
+                ("n_edges", C.c_int64), ("n_leaf", C.c_int64), ("n_tiers", C.c_int32),
+                ("tier_offset", C.c_int64 * 34), ("table_bytes", C.c_int64), ("vector_bytes_fp64", C.c_int64)]
+
+
+class heom_solver_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("precond", C.c_int32),
+                ("mode", C.c_int32), ("inner_tol", C.c_double), ("max_refine", C.c_int32),
+                ("rhs_chunk", C.c_int32), ("nn", vp), ("fallback", C.c_int32), ("use_x0", C.c_int32)]
+
+
+class heom_solver_report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("refinements", C.c_int32), ("fell_back", C.c_int32), ("true_residual", C.c_double),
+                ("seconds", C.c_double), ("applies", C.c_int64)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "heom_version": (C.c_char_p, []),
+    "heom_last_error": (C.c_char_p, []),
+    "heom_status_string": (C.c_char_p, [heom_status]),
+    "heom_pade_params": (heom_status, [C.c_int32, C.c_int32, C.c_int32, dp, dp]),
+    "heom_exponents_lorentz": (heom_status, [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                             dp, dp, dp, dp]),
+    "heom_exponents_drude_lorentz": (heom_status, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, dp, dp]),
+    "heom_build_hierarchy": (heom_status, [C.c_int32, dp, C.c_int32, C.POINTER(heom_bath), C.c_int32, C.c_int32,
+                                           C.c_int32, dp, C.POINTER(vp)]),
+    "heom_free": (None, [vp]),
+    "heom_hierarchy_info": (heom_status, [vp, C.POINTER(heom_info)]),
+    "heom_hierarchy_ados": (heom_status, [vp, i32p, u64p, i32p]),
+    "heom_ado_index": (heom_status, [vp, i32p, i32p, C.c_int32, i64p, i32p]),
+    "heom_hierarchy_tables": (heom_status, [vp, dp, i64p, i32p, i32p, i32p, i32p]),
+    "heom_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, vp]),
+    "heom_apply_shifted": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp, vp]),
+    "heom_apply_tiled": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
+}
+
+_lib = None
+
+
+class HeomError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"heom status {status}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load libheom.so (built in-tree by build_lib.py); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2306_07522_amd/build_lib.py")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != 0:
+        msg = _lib.heom_last_error().decode() if _lib is not None else ""
+        raise HeomError(status, msg)

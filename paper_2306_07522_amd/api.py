@@ -1,0 +1,220 @@
+"""Python binding of the HEOM library: argument marshalling only.
+
+Every computation happens inside libheom.so (host setup in C++, every step
+of the hot path in HIP kernels); this module converts numpy arrays and torch
+tensors to the pointers and sizes of the C ABI (include/heom.h).  Device
+vectors are torch tensors (complex128 for FP64, complex64 for FP32) on the
+current HIP device; streams are torch's current stream unless given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _dptr(a):
+    return a.ctypes.data_as(L.dp)
+
+
+def _c128(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def lib():
+    return L.load()
+
+
+# ----------------------------------------------------------------- exponents
+def pade_params(kind: str, n: int, method: str = "pade"):
+    lb = lib()
+    k = np.zeros(max(n, 1))
+    z = np.zeros(max(n, 1))
+    L.check(lb.heom_pade_params(L.HEOM_FERMION if kind == "fermi" else L.HEOM_BOSON,
+                                L.HEOM_PADE if method == "pade" else L.HEOM_MATSUBARA, n, _dptr(k), _dptr(z)))
+    return k[:n], z[:n]
+
+
+def exponents_lorentz(Gamma, W, mu, T, n_exp, method="pade"):
+    lb = lib()
+    out = [np.zeros(n_exp, dtype=np.complex128) for _ in range(4)]
+    L.check(lb.heom_exponents_lorentz(Gamma, W, mu, T, n_exp, L.HEOM_PADE if method == "pade" else L.HEOM_MATSUBARA,
+                                      *[_dptr(o) for o in out]))
+    return dict(eta_p=out[0], gam_p=out[1], eta_m=out[2], gam_m=out[3])
+
+
+def exponents_drude_lorentz(lam, gamma, T, n_exp, method="matsubara"):
+    lb = lib()
+    xi = np.zeros(n_exp, dtype=np.complex128)
+    chi = np.zeros(n_exp, dtype=np.complex128)
+    L.check(lb.heom_exponents_drude_lorentz(lam, gamma, T, n_exp,
+                                            L.HEOM_PADE if method == "pade" else L.HEOM_MATSUBARA,
+                                            _dptr(xi), _dptr(chi)))
+    return xi, chi
+
+
+_UTYPE = {"R": L.HEOM_U_R, "I": L.HEOM_U_I, "RI": L.HEOM_U_RI}
+
+
+def _bath_struct(rec, keep):
+    """One bath record (physical spectral parameters or raw exponents) ->
+    heom_bath; arrays are appended to `keep` to outlive the call."""
+    b = L.heom_bath()
+    op = _c128(rec["op"])
+    keep.append(op)
+    b.op = _dptr(op)
+    if rec["kind"] == "boson":
+        b.kind = L.HEOM_BOSON
+        if rec.get("spectral") == "drude_lorentz":
+            xi, chi = exponents_drude_lorentz(rec["lam"], rec["gamma"], rec["T"], rec["n_exp"],
+                                              rec.get("method", "matsubara"))
+            ut = np.full(len(xi), L.HEOM_U_RI, dtype=np.int32)
+        else:
+            xi, chi = _c128(rec["xi"]), _c128(rec["chi"])
+            ut = np.array([_UTYPE[u] for u in rec["u_type"]], dtype=np.int32)
+        keep += [xi, chi, ut]
+        b.n_exp = len(xi)
+        b.u_type = ut.ctypes.data_as(L.i32p)
+        b.xi = _dptr(xi)
+        b.chi = _dptr(chi)
+    else:
+        b.kind = L.HEOM_FERMION
+        if rec.get("spectral") == "lorentz":
+            e = exponents_lorentz(rec["Gamma"], rec["W"], rec["mu"], rec["T"], rec["n_exp"], rec.get("method", "pade"))
+        else:
+            e = {k: _c128(rec[k]) for k in ("eta_p", "gam_p", "eta_m", "gam_m")}
+        keep += list(e.values())
+        b.n_exp = len(e["eta_p"])
+        b.eta_p, b.gam_p, b.eta_m, b.gam_m = (_dptr(e[k]) for k in ("eta_p", "gam_p", "eta_m", "gam_m"))
+    return b
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _precision_of(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return L.HEOM_FP64
+    if t.dtype == torch.complex64:
+        return L.HEOM_FP32
+    raise TypeError(f"ADO vectors must be complex128 or complex64 tensors, got {t.dtype}")
+
+
+def _devptr(t):
+    if not t.is_cuda:
+        raise ValueError("device vectors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device vectors must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Hierarchy:
+    """Handle of heom_build_hierarchy: ADO list, neighbour tables, operators."""
+
+    def __init__(self, H, baths, m_max, n_max, parity=+1, parity_op=None):
+        lb = lib()
+        H = _c128(H)
+        d = H.shape[0]
+        keep = []
+        structs = (L.heom_bath * max(len(baths), 1))()
+        for i, rec in enumerate(baths):
+            structs[i] = _bath_struct(rec, keep)
+        pop = None
+        if parity_op is not None:
+            pop = _c128(parity_op)
+        h = C.c_void_p()
+        L.check(lb.heom_build_hierarchy(d, _dptr(H), len(baths), structs, m_max, n_max, parity,
+                                        _dptr(pop) if pop is not None else None, C.byref(h)))
+        self._h = h
+        self._lib = lb
+        info = L.heom_info()
+        L.check(lb.heom_hierarchy_info(h, C.byref(info)))
+        self.info = info
+        self.N = info.n_ado
+        self.d = info.d
+        self.Kb = info.n_bos_exp
+        self.Kf = info.n_ferm_exp
+        self.parity = parity
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self._lib.heom_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tier_offsets(self):
+        return [self.info.tier_offset[t] for t in range(self.info.n_tiers + 1)]
+
+    def ados(self):
+        """(bos_occ [N][K_b], ferm_mask [N], level [N][2])."""
+        occ = np.zeros((self.N, max(self.Kb, 1)), dtype=np.int32)
+        mask = np.zeros(self.N, dtype=np.uint64)
+        lev = np.zeros((self.N, 2), dtype=np.int32)
+        L.check(self._lib.heom_hierarchy_ados(self._h, occ.ctypes.data_as(L.i32p), mask.ctypes.data_as(L.u64p),
+                                              lev.ctypes.data_as(L.i32p)))
+        return occ[:, : self.Kb], mask, lev
+
+    def index(self, bos_occ, ferm_ids):
+        occ = np.ascontiguousarray(np.asarray(bos_occ if len(bos_occ) else [0], dtype=np.int32))
+        ids = np.ascontiguousarray(np.asarray(ferm_ids if len(ferm_ids) else [0], dtype=np.int32))
+        idx = C.c_int64()
+        sgn = C.c_int32()
+        L.check(self._lib.heom_ado_index(self._h, occ.ctypes.data_as(L.i32p), ids.ctypes.data_as(L.i32p),
+                                         len(ferm_ids), C.byref(idx), C.byref(sgn)))
+        return idx.value, sgn.value
+
+    def tables(self):
+        E = self.info.n_edges
+        dec = np.zeros(self.N, dtype=np.complex128)
+        rp = np.zeros(self.N + 1, dtype=np.int64)
+        col, kind, expo, mult = (np.zeros(max(E, 1), dtype=np.int32) for _ in range(4))
+        L.check(self._lib.heom_hierarchy_tables(self._h, _dptr(dec), rp.ctypes.data_as(L.i64p),
+                                                *[a.ctypes.data_as(L.i32p) for a in (col, kind, expo, mult)]))
+        return dict(decay=dec, row_ptr=rp, col=col[:E], kind=kind[:E], exp=expo[:E], mult=mult[:E])
+
+    # ------------------------------------------------------------ device work
+    def apply(self, x, y=None, shift=None, n_rhs=1, stream=None, tiled=None):
+        """y = (M + shift) x on the GPU.  x: [N][d][d] or [N][d][d][R] tensor.
+        shift: complex scalar, or a device tensor of R shifts (per column)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        prec = _precision_of(x)
+        if y.dtype != x.dtype:
+            raise TypeError("x and y must have the same dtype")
+        if x.numel() != self.N * self.d * self.d * n_rhs:
+            raise ValueError("x has the wrong size for this hierarchy")
+        s = _stream_ptr(stream)
+        if isinstance(shift, torch.Tensor):
+            if shift.dtype != x.dtype or shift.numel() != n_rhs:
+                raise ValueError("per-RHS shifts: one complex of the vector dtype per column")
+            L.check(self._lib.heom_apply_shifted(self._h, prec, _devptr(x), _devptr(y), n_rhs, _devptr(shift), s))
+            return y
+        sh = None
+        if shift is not None:
+            sh = np.array([complex(shift).real, complex(shift).imag])
+        if tiled is not None:
+            L.check(self._lib.heom_apply_tiled(self._h, prec, _devptr(x), _devptr(y), n_rhs,
+                                               _dptr(sh) if sh is not None else None, int(tiled), s))
+        else:
+            L.check(self._lib.heom_apply(self._h, prec, _devptr(x), _devptr(y), n_rhs,
+                                         _dptr(sh) if sh is not None else None, s))
+        return y

@@ -1,0 +1,130 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "heom.h"
+
+namespace heom {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+heom_status fail(heom_status s, const std::string &msg);
+
+#define HEOM_HIP_CHECK(expr)                                                         \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess)                                                            \
+      return ::heom::fail(HEOM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define HEOM_TRY(expr)                \
+  do {                                \
+    heom_status _s = (expr);          \
+    if (_s != HEOM_OK) return _s;     \
+  } while (0)
+
+// ---------------------------------------------------------------- tables
+// Edge coefficient entry: the term  cl * O x_b + cr * x_b O  with O = ops[op];
+// the per-edge multiplier (bosonic multiplicity or fermionic reorder sign) is
+// applied on top.
+struct CoefEntry {
+  int op;
+  cd cl, cr;
+};
+
+// ELL form of every operator, left (rows of O) and right (rows of O^T).
+struct OpEll {
+  int n_ops = 0, d = 0, slots = 0;
+  std::vector<int32_t> cnt;  // [n_ops][2][d]
+  std::vector<int32_t> col;  // [n_ops][2][d][slots]
+  std::vector<cd> val;       // [n_ops][2][d][slots]
+};
+
+// Device copies of the tables, one set per precision for the values.
+struct DeviceTables {
+  int device = -1;
+  int64_t *row_ptr = nullptr;   // [N+1]
+  int2 *edges = nullptr;        // [E] (neighbour, packed coef/mult)
+  double2 *decay64 = nullptr;   // [N]
+  float2 *decay32 = nullptr;
+  int32_t *ell_cnt = nullptr;
+  int32_t *ell_col = nullptr;
+  double2 *ell_val64 = nullptr;
+  float2 *ell_val32 = nullptr;
+  int32_t *coef_op = nullptr;   // [n_coef]
+  double2 *coef64 = nullptr;    // [n_coef][2] (cl, cr)
+  float2 *coef32 = nullptr;
+  double *hdiag_re = nullptr;   // [d] real diagonal of H (Jacobi)
+  // tiled plan (top tier split into chunks)
+  int n_chunks = 0;
+  int4 *tasks = nullptr;        // all launches' tasks back to back
+  int2 *tedges = nullptr;       // edges in task order
+  std::vector<int64_t> task_off;  // [n_launch+1] into tasks
+  size_t bytes = 0;
+};
+
+struct Hier {
+  int d = 0, Kb = 0, Kf = 0, Lb = 0, Lf = 0, parity = 1;
+  std::vector<cd> H;  // d*d row-major
+  struct BosExp { int op, u; cd xi, chi; };
+  struct FermExp { int op_ann, nu, partner; cd eta, gamma; };
+  std::vector<BosExp> bexp;
+  std::vector<FermExp> fexp;
+  std::vector<std::vector<cd>> ops;  // ops[0] = H
+  // ADOs
+  int64_t N = 0;
+  std::vector<uint8_t> bocc;       // [N][Kb]
+  std::vector<uint64_t> fmask;     // [N]
+  std::vector<int32_t> lev;        // [N][2] (m, n)
+  std::vector<int64_t> tier_off;   // [n_tiers+1]
+  std::vector<cd> decay;           // [N]
+  std::vector<int64_t> row_ptr;    // [N+1]
+  std::vector<int32_t> ecol;       // [E]
+  std::vector<int32_t> einfo;      // [E] coef_id << 8 | (uint8) mult
+  std::vector<CoefEntry> coefs;
+  OpEll ell;
+  int64_t n_leaf = 0;
+  // bosonic code for dictionary lookups
+  std::vector<uint64_t> bos_pow;
+  std::vector<std::pair<uint64_t, uint64_t>> keys;  // sorted (fmask, bos code)
+  std::vector<int32_t> key_index;                   // ADO index of keys[r]
+  DeviceTables dev;
+};
+
+// host builder (host_hierarchy.cpp)
+heom_status build_hier(int d, const double *H, int n_baths, const heom_bath *baths, int m_max, int n_max,
+                       int parity, const double *parity_op, std::unique_ptr<Hier> &out);
+int64_t lookup_ado(const Hier &h, uint64_t fmask, uint64_t bcode);
+
+// device upload / kernels (device.hip)
+heom_status ensure_device(Hier &h);
+heom_status ensure_tiled_plan(Hier &h, int n_chunks);
+void free_device(Hier &h);
+
+struct ApplyArgs {
+  const void *x = nullptr;      // input vector
+  const void *k = nullptr;      // optional: input is x + kc * k
+  double kc = 0.0;
+  void *y = nullptr;
+  int n_rhs = 1;
+  const void *shifts = nullptr; // device complex[n_rhs] of the precision, or null
+  cd shift0 = 0.0;              // used when shifts == null
+  int border = 0;               // 1: replace y[0][0][0] by Tr rho_0 (steady-state row)
+};
+heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
+heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n_chunks, hipStream_t s);
+
+}  // namespace heom
+
+struct heom_hier {
+  std::unique_ptr<heom::Hier> impl;
+};

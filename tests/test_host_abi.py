@@ -1,0 +1,133 @@
+"""Host-side checks of the C-ABI library (CPU only, no device calls):
+symbol exports, exponent helpers against the oracle, and the hierarchy
+tables against the oracle's enumeration."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import exponents as ox
+from paper_2306_07522_amd import workloads as wl
+from tests.helpers import library_model, oracle_model, oracle_to_library_perm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _api():
+    from paper_2306_07522_amd import api
+    return api
+
+
+def test_library_exports_every_declared_symbol():
+    api = _api()
+    lib = api.lib()
+    hdr = open(os.path.join(ROOT, "include", "heom.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(heom_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) >= 15
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("kind", ["fermi", "bose"])
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 10])
+def test_pade_params_match_oracle(kind, n):
+    k, z = _api().pade_params(kind, n)
+    ko, zo = ox.pade_params_rational(kind, n)
+    assert np.allclose(z, zo, rtol=1e-12, atol=0)
+    assert np.allclose(k, ko, rtol=1e-10, atol=0)
+
+
+def test_exponent_helpers_match_oracle():
+    api = _api()
+    for method in ("pade", "matsubara"):
+        e = api.exponents_lorentz(2.0, 10.0, 1.0, 0.5, 5, method)
+        eo = ox.lorentz_fermion_exponents(2.0, 10.0, 1.0, 0.5, 5, method)
+        for k in e:
+            assert np.allclose(e[k], eo[k], rtol=1e-12, atol=1e-14), (method, k)
+        xi, chi = api.exponents_drude_lorentz(0.1, 0.5, 0.5, 4, method)
+        xo, co = ox.drude_lorentz_exponents(0.1, 0.5, 0.5, 4, method)
+        assert np.allclose(xi, xo, rtol=1e-12, atol=1e-15)
+        assert np.allclose(chi, co, rtol=1e-12, atol=0)
+
+
+def test_argument_errors_are_reported():
+    api = _api()
+    from paper_2306_07522_amd._lib import HeomError
+    with pytest.raises(HeomError):
+        api.Hierarchy(np.array([[0, 1], [0, 0]]), [], 0, 0)           # not Hermitian
+    cfg = wl.siam()
+    bad = np.eye(4)                                                   # parity op that H violates? H is diagonal -> even
+    with pytest.raises(HeomError):
+        # a fermionic coupling that is parity-even violates the parity check
+        api.Hierarchy(cfg["H"], [dict(cfg["baths"][0], op=np.diag([1.0, 0, 0, 0]))], 0, 1,
+                      parity_op=cfg["parity_op"])
+    with pytest.raises(HeomError):
+        api.exponents_lorentz(1.0, 10.0, 0.0, -1.0, 3)                # negative temperature
+
+
+@pytest.mark.parametrize("name", ["spin_boson", "siam", "charge_cavity_small", "random_mixed"])
+def test_same_ado_set_and_decay_as_oracle(name):
+    if name == "spin_boson":
+        cfg = wl.spin_boson()
+    elif name == "siam":
+        cfg = wl.siam(n_max=2)
+    elif name == "charge_cavity_small":
+        cfg = wl.charge_cavity(n_photon=2, n_bexp=2, n_fexp=2, m_max=2, n_max=2)
+    else:
+        rng = np.random.default_rng(5)
+        cfg = dict(H=np.diag(rng.standard_normal(3)).astype(complex),
+                   baths=wl.random_raw_baths(rng, 3, n_bos_exp=3, n_ferm_exp=2), m_max=3, n_max=3)
+    om = oracle_model(cfg)
+    lm = library_model(cfg)
+    assert lm.N == om.N
+    perm = oracle_to_library_perm(om, lm)
+    assert sorted(perm.tolist()) == list(range(lm.N))
+    # decay c_a = sum n_k chi_k + sum gamma_q
+    t = lm.tables()
+    for k, (j, q) in enumerate(om.hier.ados):
+        c = sum(om.bos[x]["chi"] for x in j) + sum(om.ferm[x]["gamma"] for x in q)
+        assert abs(t["decay"][perm[k]] - c) < 1e-12 * max(1, abs(c))
+    # neighbour sets: block columns of the oracle's block row = library edges + self
+    for k in range(0, om.N, max(1, om.N // 50)):
+        cols = {b for b, _, _ in om.block_terms(k)} - {k}
+        a = perm[k]
+        lib_cols = set(t["col"][t["row_ptr"][a]: t["row_ptr"][a + 1]].tolist())
+        assert {int(perm[b]) for b in cols} == lib_cols
+
+
+def test_counts_table3_and_workloads():
+    from tests.conftest import golden
+    g = golden("table3_ado_counts.json")
+    api = _api()
+    (d1,) = wl.jordan_wigner(1)
+    zero = np.zeros(2)
+    for n_max in (1, 2, 3, 4):
+        # 56 fermionic exponents: 28 records of (nu=+1, nu=-1) pairs
+        baths = [dict(kind="fermion", op=d1, eta_p=np.ones(1), gam_p=np.ones(1), eta_m=np.ones(1), gam_m=np.ones(1))
+                 for _ in range(28)]
+        h = api.Hierarchy(np.zeros((2, 2)), baths, 0, n_max)
+        assert h.N == g["counts"][str(n_max)][-1]
+    h = library_model(wl.two_orbital_anderson())
+    assert h.N == 213053 and h.info.n_edges == 2 * 832512
+    assert library_model(wl.spin_boson()).N == 35
+    assert library_model(wl.charge_cavity()).N == 3165
+
+
+def test_dictionary_lookup_and_sign():
+    cfg = wl.siam(n_max=3)
+    lm = library_model(cfg)
+    occ, mask, lev = lm.ados()
+    rng = np.random.default_rng(2)
+    for a in rng.integers(0, lm.N, 40):
+        ids = [k for k in range(64) if int(mask[a]) >> k & 1]
+        ids_desc = sorted(ids, reverse=True)
+        assert lm.index([], ids_desc) == (a, 1)
+        p = list(rng.permutation(ids_desc))
+        inv = sum(1 for i in range(len(p)) for j in range(i + 1, len(p)) if p[i] < p[j])
+        assert lm.index([], p) == (a, (-1) ** inv)
+    assert lm.index([], [0, 0])[0] == -1               # Pauli
+    assert lm.index([], [0, 1, 2, 3])[0] == -1         # beyond the tier
