@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--tiled", type=int, default=-1, help="-1: untiled apply; 0: default chunks; k: k chunks")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--calib", action="store_true",
+                   help="also run one plain device copy of the ADO vector (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -69,6 +71,11 @@ def gpu_apply_bench(args):
         evs[s][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.calib:
+        z = torch.empty_like(x)
+        z.copy_(x)
+        torch.cuda.synchronize()
+        del z
     kern_ms = sorted(a.elapsed_time(b) for a, b in evs)
     avg_ms = sum(kern_ms) / len(kern_ms)
     nbytes = algorithmic_bytes(h, w)

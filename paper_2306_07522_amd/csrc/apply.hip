@@ -1,35 +1,237 @@
 // Matrix-free HEOM Liouvillian apply (eq:HEOM), y = (M + shift) x.
 //
-// Every output ADO a is one task.  A task accumulates, for each element
-// (i, j) of rho_a and each right-hand side r,
-//   diag:  -(c_a - z_r) x_a[i][j] - i (H x_a)[i][j] + i (x_a H)[i][j]
-//   edges: sum over neighbours b of  cl (O x_b)[i][j] + cr (x_b O)[i][j]
-// where each edge names a coefficient-table entry (operator O and the two
-// complex coefficients of the superoperator A, B, C or D with the parity
-// projector folded in) and a small integer multiplier (bosonic multiplicity
-// or fermionic reorder sign).  Operators are stored in ELL form so that the
-// signed-permutation coupling operators of fermionic models cost one gather
-// per element, and dense ones cost d.
+// Every output ADO a is one task, and a task is a run of edge groups.  A
+// group names one operator O (H, a bosonic V, or a fermionic d / d^dagger)
+// and one coefficient pair (cl, cr) -- the superoperator A, B, C or D of
+// eq:HEOM with the parity projector folded in -- and contributes
+//     cl * O u + cr * u O,    u = sum_e w_e x_{b_e}
+// where w_e is the edge's integer multiplier (bosonic multiplicity or
+// fermionic reorder sign).  All fermionic "up" terms of an ADO that share
+// d^{nubar} form a single group, so the operator product is done once per
+// distinct operator rather than once per neighbour.  The self group
+// (op H, cl = -i, cr = +i) also carries the decay -(c_a - z) x_a.
+// Operators are stored in ELL form: the signed-permutation coupling
+// operators of fermionic models cost one gather per element.
 //
-// Layout: x, y are [N][d][d][R] complex, R innermost; one thread owns one
-// (i, j, r) cell of one task.
+// Two kernels:
+//   wave kernel   (d in {8, 16}, one right-hand side): one wavefront per
+//                 task; neighbour blocks are streamed with coalesced loads
+//                 into registers, the group sum u is staged once in the
+//                 wave's own LDS slice, and the operator gathers read LDS.
+//   cell kernel   (any d <= 32, any number of right-hand sides): one thread
+//                 per (i, j, r) cell, gathers straight from global memory.
+// Layout: x, y are [N][d][d][R] complex, R innermost.
 #include "device_common.h"
 #include "internal.h"
 
 namespace heom {
 
-template <typename T, int D>
-__global__ void __launch_bounds__(256)
-apply_kernel(const int4 *__restrict__ tasks, int64_t n_tasks, const int64_t *__restrict__ row_ptr,
-             const int2 *__restrict__ edges, const typename Cplx<T>::t *__restrict__ decay,
-             const int32_t *__restrict__ ell_cnt, const int32_t *__restrict__ ell_col,
-             const typename Cplx<T>::t *__restrict__ ell_val, int slots,
-             const int32_t *__restrict__ coef_op, const typename Cplx<T>::t *__restrict__ coef,
-             const typename Cplx<T>::t *__restrict__ x, const typename Cplx<T>::t *__restrict__ kvec, T kc,
-             typename Cplx<T>::t *__restrict__ y, int d_rt, int R, const typename Cplx<T>::t *__restrict__ shifts,
-             typename Cplx<T>::t shift0, int border) {
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+struct ApplyParams {
   using T2 = typename Cplx<T>::t;
-  const int d = D > 0 ? D : d_rt;
+  const int4 *tasks;
+  int64_t n_tasks;
+  const int4 *groups;
+  const int2 *gedges;
+  const T2 *decay;
+  const int32_t *ell_cnt;
+  const int32_t *ell_col;
+  const T2 *ell_val;
+  const int32_t *op_slots;  // per operator: padded ELL width (entries beyond a row's count are zero)
+  int slots;
+  // compact operator tables (wave kernel)
+  const int32_t *c_meta;
+  const int32_t *c_col;
+  const T2 *c_val;
+  int n_centries;
+  const T2 *hdiag;
+  int tpw;  // tasks per wave
+  const int32_t *coef_op;
+  const T2 *coef;
+  const T2 *x;
+  const T2 *kvec;
+  T kc;
+  T2 *y;
+  int d;
+  int R;
+  const T2 *shifts;
+  T2 shift0;
+  int border;
+};
+
+// ----------------------------------------------------------------- wave kernel
+template <typename T, int D, bool FUSE>
+__device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, int lane,
+                                           typename Cplx<T>::t (&v)[D * D / 64]) {
+  constexpr int DD = D * D;
+  const typename Cplx<T>::t *xb = P.x + b * DD;
+#pragma unroll
+  for (int s = 0; s < DD / 64; ++s) v[s] = xb[lane + 64 * s];
+  if (FUSE) {
+    const typename Cplx<T>::t *kb = P.kvec + b * DD;
+#pragma unroll
+    for (int s = 0; s < DD / 64; ++s) {
+      const typename Cplx<T>::t q = kb[lane + 64 * s];
+      v[s].x = fma(P.kc, q.x, v[s].x);
+      v[s].y = fma(P.kc, q.y, v[s].y);
+    }
+  }
+}
+
+// One wave processes tasks first, first + 4, ... (tpw of them).  Within a
+// task the next group's first neighbour block is prefetched while the
+// current group is finished; multi-edge groups stream two blocks at a time.
+template <typename T, int D, bool FUSE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) apply_wave_kernel(ApplyParams<T> P) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int DD = D * D;
+  constexpr int EPL = DD / 64;  // elements per lane
+  static_assert(DD % 64 == 0, "wave kernel needs d^2 divisible by 64");
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2 *sbuf = reinterpret_cast<T2 *>(smem);              // [4][DD] group staging, one slice per wave
+  T2 *tval = sbuf + 4 * DD;                             // compact operator values
+  int *tcol = reinterpret_cast<int *>(tval + P.n_centries);
+  // H diagonal, after the column table (16-byte aligned)
+  T2 *thd = reinterpret_cast<T2 *>((reinterpret_cast<uintptr_t>(tcol + P.n_centries) + 15) & ~(uintptr_t)15);
+  for (int e = threadIdx.x; e < P.n_centries; e += 256) {
+    tval[e] = P.c_val[e];
+    tcol[e] = P.c_col[e];
+  }
+  if (threadIdx.x < D) thd[threadIdx.x] = P.hdiag[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  // the task index is uniform across the wave: keep every table lookup scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T2 *buf = sbuf + wave * DD;
+  const int j = lane % D;
+  const int64_t first = ((int64_t)blockIdx.x * 4 * P.tpw) + wave;
+  for (int it = 0; it < P.tpw; ++it) {
+    const int64_t task = first + 4 * it;
+    if (task >= P.n_tasks) break;
+    const int4 tk = P.tasks[task];
+    const int64_t a = tk.x;
+    const int flags = tk.w;
+    const int64_t abase = a * DD;
+    T2 acc[EPL];
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) acc[s] = (flags & TASK_ACC) ? P.y[abase + lane + 64 * s] : T2{0, 0};
+    T2 trace{0, 0};
+    int g = tk.y;
+    if (g < tk.z) {
+      int4 gr = P.groups[g];
+      T2 vnext[EPL];
+      load_block<T, D, FUSE>(P, P.gedges[gr.x].x, lane, vnext);
+      for (; g < tk.z; ++g) {
+        T2 u[EPL];
+        {
+          const T w0 = (T)P.gedges[gr.x].y;
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) u[s] = T2{w0 * vnext[s].x, w0 * vnext[s].y};
+        }
+        int4 grn = gr;
+        if (g + 1 < tk.z) {  // prefetch the next group's first neighbour block
+          grn = P.groups[g + 1];
+          load_block<T, D, FUSE>(P, P.gedges[grn.x].x, lane, vnext);
+        }
+        int e = gr.x + 1;
+        for (; e + 1 < gr.y; e += 2) {
+          const int2 e0 = P.gedges[e], e1 = P.gedges[e + 1];
+          T2 v0[EPL], v1[EPL];
+          load_block<T, D, FUSE>(P, e0.x, lane, v0);
+          load_block<T, D, FUSE>(P, e1.x, lane, v1);
+          const T w0 = (T)e0.y, w1 = (T)e1.y;
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) {
+            u[s].x = fma(w0, v0[s].x, fma(w1, v1[s].x, u[s].x));
+            u[s].y = fma(w0, v0[s].y, fma(w1, v1[s].y, u[s].y));
+          }
+        }
+        if (e < gr.y) {
+          const int2 e0 = P.gedges[e];
+          T2 v0[EPL];
+          load_block<T, D, FUSE>(P, e0.x, lane, v0);
+          const T w0 = (T)e0.y;
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) {
+            u[s].x = fma(w0, v0[s].x, u[s].x);
+            u[s].y = fma(w0, v0[s].y, u[s].y);
+          }
+        }
+        if (gr.w) {
+          // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
+          const T2 z = P.shifts ? P.shifts[0] : P.shift0;
+          const T2 c = csub(P.decay[a], z);
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) {
+            const T2 dh = csub(thd[(lane + 64 * s) / D], thd[j]);
+            const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
+            acc[s] = csub(acc[s], cmul(f, u[s]));
+          }
+        }
+        const int cid = gr.z;
+        const int op = P.coef_op[cid];
+        const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
+        const bool need_trace = gr.w && P.border && a == 0;
+        if (ns > 0 || need_trace) {
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) buf[lane + 64 * s] = u[s];
+          wave_sync();
+          if (need_trace && lane == 0)
+            for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
+          if (ns > 0) {
+            const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
+            const int rbase = off + (D + j) * ns;
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) {
+              const int i = (lane + 64 * s) / D;
+              const int lbase = off + i * ns;
+              T2 L{0, 0}, Rv{0, 0};
+              if (isreal) {
+#pragma unroll 1
+                for (int t = 0; t < ns; ++t) {
+                  const T vl = tval[lbase + t].x, vr = tval[rbase + t].x;
+                  const T2 bl = buf[tcol[lbase + t] * D + j];
+                  const T2 br = buf[i * D + tcol[rbase + t]];
+                  L.x = fma(vl, bl.x, L.x); L.y = fma(vl, bl.y, L.y);
+                  Rv.x = fma(vr, br.x, Rv.x); Rv.y = fma(vr, br.y, Rv.y);
+                }
+              } else {
+#pragma unroll 1
+                for (int t = 0; t < ns; ++t) {
+                  L = cfma(tval[lbase + t], buf[tcol[lbase + t] * D + j], L);
+                  Rv = cfma(buf[i * D + tcol[rbase + t]], tval[rbase + t], Rv);
+                }
+              }
+              acc[s] = cfma(cl, L, acc[s]);
+              acc[s] = cfma(cr, Rv, acc[s]);
+            }
+          }
+          wave_sync();
+        }
+        gr = grn;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+      T2 v = acc[s];
+      if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;
+      P.y[abase + lane + 64 * s] = v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- cell kernel
+template <typename T, int D>
+__global__ void __launch_bounds__(256) apply_cell_kernel(ApplyParams<T> P) {
+  using T2 = typename Cplx<T>::t;
+  const int d = D > 0 ? D : P.d;
+  const int R = P.R;
   const int cells = d * d * R;
   int64_t task;
   int cell, cell_stride;
@@ -39,21 +241,16 @@ apply_kernel(const int4 *__restrict__ tasks, int64_t n_tasks, const int64_t *__r
     if (lt >= tpb) return;
     task = (int64_t)blockIdx.x * tpb + lt;
     cell = threadIdx.x - lt * cells;
-    cell_stride = cells;  // single pass
+    cell_stride = cells;
   } else {
     task = blockIdx.x;
     cell = threadIdx.x;
     cell_stride = 256;
   }
-  if (task >= n_tasks) return;
-  int64_t a, e0, e1;
-  int flags;
-  if (tasks) {
-    int4 t = tasks[task];
-    a = t.x; e0 = t.y; e1 = t.z; flags = t.w;
-  } else {
-    a = task; e0 = row_ptr[task]; e1 = row_ptr[task + 1]; flags = TASK_DIAG;
-  }
+  if (task >= P.n_tasks) return;
+  const int4 tk = P.tasks[task];
+  const int64_t a = tk.x;
+  const int flags = tk.w;
   const int dR = d * R;
   for (; cell < cells; cell += cell_stride) {
     const int i = cell / dR;
@@ -61,93 +258,113 @@ apply_kernel(const int4 *__restrict__ tasks, int64_t n_tasks, const int64_t *__r
     const int j = rem / R;
     const int r = rem - j * R;
     auto in = [&](int64_t b, int ii, int jj) -> T2 {
-      int64_t idx = ((b * d + ii) * d + jj) * R + r;
-      T2 v = x[idx];
-      if (kvec) {
-        T2 k = kvec[idx];
-        v.x = fma(kc, k.x, v.x);
-        v.y = fma(kc, k.y, v.y);
+      const int64_t idx = ((b * d + ii) * d + jj) * R + r;
+      T2 v = P.x[idx];
+      if (P.kvec) {
+        const T2 k = P.kvec[idx];
+        v.x = fma(P.kc, k.x, v.x);
+        v.y = fma(P.kc, k.y, v.y);
       }
       return v;
     };
     const int64_t out = ((a * d + i) * d + j) * R + r;
-    T2 acc = (flags & TASK_ACC) ? y[out] : T2{0, 0};
-    if (flags & TASK_DIAG) {
-      T2 xa = in(a, i, j);
-      T2 z = shifts ? shifts[r] : shift0;
-      T2 c = csub(decay[a], z);
-      acc = csub(acc, cmul(c, xa));
-      // -i (H x)[i][j] + i (x H)[i][j]; operator 0 is H
-      T2 hl{0, 0}, hr{0, 0};
-      {
-        const int nl = ell_cnt[i];
-        const int32_t *cl = ell_col + (size_t)i * slots;
-        const T2 *vl = ell_val + (size_t)i * slots;
-        for (int s = 0; s < nl; ++s) hl = cfma(vl[s], in(a, cl[s], j), hl);
-        const int nr = ell_cnt[d + j];
-        const int32_t *cr = ell_col + (size_t)(d + j) * slots;
-        const T2 *vr = ell_val + (size_t)(d + j) * slots;
-        for (int s = 0; s < nr; ++s) hr = cfma(in(a, i, cr[s]), vr[s], hr);
-      }
-      T2 dlt = csub(hr, hl);  // i (hr - hl)
-      acc.x -= dlt.y;
-      acc.y += dlt.x;
-    }
-    for (int64_t e = e0; e < e1; ++e) {
-      const int2 ed = edges[e];
-      const int64_t b = ed.x;
-      const int cid = (int)((uint32_t)ed.y >> 8);
-      const T mult = (T)(int8_t)(ed.y & 0xff);
-      const int op = coef_op[cid];
-      const T2 cl = cscale(coef[2 * cid], mult);
-      const T2 cr = cscale(coef[2 * cid + 1], mult);
+    T2 acc = (flags & TASK_ACC) ? P.y[out] : T2{0, 0};
+    for (int g = tk.y; g < tk.z; ++g) {
+      const int4 gr = P.groups[g];
+      const int op = P.coef_op[gr.z];
       const size_t rowL = ((size_t)op * 2) * d + i;
       const size_t rowR = ((size_t)op * 2 + 1) * d + j;
+      const int nl = P.ell_cnt[rowL], nr = P.ell_cnt[rowR];
       T2 L{0, 0}, Rv{0, 0};
-      const int nl = ell_cnt[rowL];
-      for (int s = 0; s < nl; ++s) L = cfma(ell_val[rowL * slots + s], in(b, ell_col[rowL * slots + s], j), L);
-      const int nr = ell_cnt[rowR];
-      for (int s = 0; s < nr; ++s) Rv = cfma(in(b, i, ell_col[rowR * slots + s]), ell_val[rowR * slots + s], Rv);
-      acc = cfma(cl, L, acc);
-      acc = cfma(cr, Rv, acc);
+      for (int e = gr.x; e < gr.y; ++e) {
+        const int2 ed = P.gedges[e];
+        const T w = (T)ed.y;
+        T2 l{0, 0}, rr{0, 0};
+        for (int t = 0; t < nl; ++t)
+          l = cfma(P.ell_val[rowL * P.slots + t], in(ed.x, P.ell_col[rowL * P.slots + t], j), l);
+        for (int t = 0; t < nr; ++t)
+          rr = cfma(in(ed.x, i, P.ell_col[rowR * P.slots + t]), P.ell_val[rowR * P.slots + t], rr);
+        L.x = fma(w, l.x, L.x); L.y = fma(w, l.y, L.y);
+        Rv.x = fma(w, rr.x, Rv.x); Rv.y = fma(w, rr.y, Rv.y);
+      }
+      if (gr.w) {
+        const T2 z = P.shifts ? P.shifts[r] : P.shift0;
+        acc = csub(acc, cmul(csub(P.decay[a], z), in(a, i, j)));
+      }
+      acc = cfma(P.coef[2 * gr.z], L, acc);
+      acc = cfma(P.coef[2 * gr.z + 1], Rv, acc);
     }
-    if (border && a == 0 && i == 0 && j == 0 && (flags & TASK_DIAG)) {
+    if (P.border && a == 0 && i == 0 && j == 0 && (flags & TASK_DIAG)) {
       T2 tr{0, 0};
       for (int ii = 0; ii < d; ++ii) tr = cadd(tr, in(0, ii, ii));
       acc = tr;
     }
-    y[out] = acc;
+    P.y[out] = acc;
   }
 }
 
 template <typename T>
-static heom_status launch_T(Hier &h, const ApplyArgs &a, const int4 *tasks, int64_t n_tasks, const int2 *edges,
-                            hipStream_t s) {
+static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1, hipStream_t s) {
   using T2 = typename Cplx<T>::t;
   DeviceTables &D = h.dev;
+  const int64_t n_tasks = t1 - t0;
+  if (n_tasks <= 0) return HEOM_OK;
+  constexpr bool dbl = std::is_same<T, double>::value;
+  ApplyParams<T> P;
+  P.tasks = pl.tasks + t0;
+  P.n_tasks = n_tasks;
+  P.groups = pl.groups;
+  P.gedges = pl.gedges;
+  P.decay = dbl ? (const T2 *)D.decay64 : (const T2 *)D.decay32;
+  P.ell_cnt = D.ell_cnt;
+  P.ell_col = D.ell_col;
+  P.ell_val = dbl ? (const T2 *)D.ell_val64 : (const T2 *)D.ell_val32;
+  P.op_slots = D.op_slots;
+  P.c_meta = D.c_meta;
+  P.c_col = D.c_col;
+  P.c_val = dbl ? (const T2 *)D.c_val64 : (const T2 *)D.c_val32;
+  P.n_centries = (int)h.ell.c_col.size();
+  P.hdiag = dbl ? (const T2 *)D.hdiag : (const T2 *)D.hdiag32;
+  P.slots = h.ell.slots;
+  P.coef_op = D.coef_op;
+  P.coef = dbl ? (const T2 *)D.coef64 : (const T2 *)D.coef32;
+  P.x = (const T2 *)a.x;
+  P.kvec = (const T2 *)a.k;
+  P.kc = (T)a.kc;
+  P.y = (T2 *)a.y;
+  P.d = h.d;
+  P.R = a.n_rhs;
+  P.shifts = (const T2 *)a.shifts;
+  P.shift0 = T2{(T)a.shift0.real(), (T)a.shift0.imag()};
+  P.border = a.border;
   const int d = h.d;
-  const int R = a.n_rhs;
-  const int cells = d * d * R;
-  if (n_tasks == 0) return HEOM_OK;
-  int64_t grid = cells <= 256 ? (n_tasks + (256 / cells) - 1) / (256 / cells) : n_tasks;
-  if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
-  const T2 *decay = std::is_same<T, double>::value ? (const T2 *)D.decay64 : (const T2 *)D.decay32;
-  const T2 *ev = std::is_same<T, double>::value ? (const T2 *)D.ell_val64 : (const T2 *)D.ell_val32;
-  const T2 *cf = std::is_same<T, double>::value ? (const T2 *)D.coef64 : (const T2 *)D.coef32;
-  T2 sh0{(T)a.shift0.real(), (T)a.shift0.imag()};
-  dim3 g((unsigned)grid), b(256);
-#define HEOM_LAUNCH(DD)                                                                                    \
-  hipLaunchKernelGGL((apply_kernel<T, DD>), g, b, 0, s, tasks, n_tasks, D.row_ptr, edges, decay, D.ell_cnt, \
-                     D.ell_col, ev, h.ell.slots, D.coef_op, cf, (const T2 *)a.x, (const T2 *)a.k, (T)a.kc,    \
-                     (T2 *)a.y, d, R, (const T2 *)a.shifts, sh0, a.border)
-  switch (d) {
-    case 2: HEOM_LAUNCH(2); break;
-    case 4: HEOM_LAUNCH(4); break;
-    case 8: HEOM_LAUNCH(8); break;
-    case 16: HEOM_LAUNCH(16); break;
-    default: HEOM_LAUNCH(0); break;
+  const size_t tab_bytes = (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 16 + (size_t)d * sizeof(T2);
+  const size_t smem = 4 * (size_t)d * d * sizeof(T2) + tab_bytes;
+  if (a.n_rhs == 1 && (d == 8 || d == 16) && smem <= 48 * 1024) {
+    P.tpw = n_tasks > 65536 ? 4 : 1;
+    const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
+    if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
+    dim3 g((unsigned)grid), b(256);
+    if (d == 8) {
+      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 8, true>), g, b, smem, s, P);
+      else hipLaunchKernelGGL((apply_wave_kernel<T, 8, false>), g, b, smem, s, P);
+    } else {
+      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true>), g, b, smem, s, P);
+      else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false>), g, b, smem, s, P);
+    }
+  } else {
+    const int cells = d * d * a.n_rhs;
+    const int64_t grid = cells <= 256 ? (n_tasks + (256 / cells) - 1) / (256 / cells) : n_tasks;
+    if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
+    dim3 g((unsigned)grid), b(256);
+    switch (d) {
+      case 2: hipLaunchKernelGGL((apply_cell_kernel<T, 2>), g, b, 0, s, P); break;
+      case 4: hipLaunchKernelGGL((apply_cell_kernel<T, 4>), g, b, 0, s, P); break;
+      case 8: hipLaunchKernelGGL((apply_cell_kernel<T, 8>), g, b, 0, s, P); break;
+      case 16: hipLaunchKernelGGL((apply_cell_kernel<T, 16>), g, b, 0, s, P); break;
+      default: hipLaunchKernelGGL((apply_cell_kernel<T, 0>), g, b, 0, s, P); break;
+    }
   }
-#undef HEOM_LAUNCH
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -160,10 +377,17 @@ static heom_status check_apply(Hier &h, int precision, const ApplyArgs &a) {
   return ensure_device(h);
 }
 
+static heom_status run_plan(Hier &h, int precision, const ApplyArgs &a, const Plan &pl, hipStream_t s) {
+  for (size_t l = 0; l + 1 < pl.task_off.size(); ++l) {
+    if (precision == HEOM_FP64) HEOM_TRY(launch_T<double>(h, a, pl, pl.task_off[l], pl.task_off[l + 1], s));
+    else HEOM_TRY(launch_T<float>(h, a, pl, pl.task_off[l], pl.task_off[l + 1], s));
+  }
+  return HEOM_OK;
+}
+
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s) {
   HEOM_TRY(check_apply(h, precision, a));
-  if (precision == HEOM_FP64) return launch_T<double>(h, a, nullptr, h.N, h.dev.edges, s);
-  return launch_T<float>(h, a, nullptr, h.N, h.dev.edges, s);
+  return run_plan(h, precision, a, h.dev.base, s);
 }
 
 heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n_chunks, hipStream_t s) {
@@ -177,13 +401,7 @@ heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n
     if (n_chunks < 1) n_chunks = 1;
   }
   HEOM_TRY(ensure_tiled_plan(h, n_chunks));
-  DeviceTables &D = h.dev;
-  for (size_t l = 0; l + 1 < D.task_off.size(); ++l) {
-    const int64_t t0 = D.task_off[l], t1 = D.task_off[l + 1];
-    if (precision == HEOM_FP64) HEOM_TRY(launch_T<double>(h, a, D.tasks + t0, t1 - t0, D.tedges, s));
-    else HEOM_TRY(launch_T<float>(h, a, D.tasks + t0, t1 - t0, D.tedges, s));
-  }
-  return HEOM_OK;
+  return run_plan(h, precision, a, h.dev.tiled, s);
 }
 
 }  // namespace heom

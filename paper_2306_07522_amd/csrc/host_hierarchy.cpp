@@ -412,6 +412,8 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
       h->coefs.push_back({dnu_op(k, h->fexp[k].nu), -I * p * eta, I * sgn_nb * std::conj(etabar)});
     }
   const int cb_up = 0, cb_dn = Kb, cf_up = 2 * Kb, cf_dn = 2 * Kb + 2 * Kf;
+  h->coef_H = (int)h->coefs.size();
+  h->coefs.push_back({0, -I, I});
 
   // ---- neighbour CSR
   h->row_ptr.assign(N + 1, 0);
@@ -483,6 +485,7 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
   E.cnt.assign((size_t)E.n_ops * 2 * d, 0);
   E.col.assign((size_t)E.n_ops * 2 * d * slots, 0);
   E.val.assign((size_t)E.n_ops * 2 * d * slots, 0.0);
+  E.op_slots.assign(E.n_ops, 0);
   for (int o = 0; o < E.n_ops; ++o) {
     auto &O = h->ops[o];
     for (int side = 0; side < 2; ++side)
@@ -497,6 +500,47 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
           ++c;
         }
         E.cnt[row] = c;
+        E.op_slots[o] = std::max(E.op_slots[o], c);
+      }
+  }
+  // compact ELL (H without its diagonal)
+  E.c_off.assign(E.n_ops, 0);
+  E.c_ns.assign(E.n_ops, 0);
+  E.c_real.assign(E.n_ops, 1);
+  E.c_col.clear();
+  E.c_val.clear();
+  E.hdiag.assign(d, 0.0);
+  for (int i = 0; i < d; ++i) E.hdiag[i] = h->H[i * d + i];
+  for (int o = 0; o < E.n_ops; ++o) {
+    auto &O = h->ops[o];
+    auto keep = [&](int r, int c) { return O[r * d + c] != 0.0 && !(o == 0 && r == c); };
+    int ns = 0;
+    for (int i = 0; i < d; ++i) {
+      int cl = 0, cr = 0;
+      for (int k = 0; k < d; ++k) {
+        cl += keep(i, k);
+        cr += keep(k, i);
+      }
+      ns = std::max(ns, std::max(cl, cr));
+    }
+    E.c_off[o] = (int32_t)E.c_col.size();
+    E.c_ns[o] = ns;
+    for (int side = 0; side < 2; ++side)
+      for (int i = 0; i < d; ++i) {
+        int c = 0;
+        for (int k = 0; k < d; ++k) {
+          int r0 = side == 0 ? i : k, c0 = side == 0 ? k : i;
+          if (!keep(r0, c0)) continue;
+          cd v = O[r0 * d + c0];
+          if (v.imag() != 0.0) E.c_real[o] = 0;
+          E.c_col.push_back(k);
+          E.c_val.push_back(v);
+          ++c;
+        }
+        for (; c < ns; ++c) {
+          E.c_col.push_back(0);
+          E.c_val.push_back(0.0);
+        }
       }
   }
   out = std::move(h);

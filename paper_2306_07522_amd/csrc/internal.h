@@ -44,31 +44,53 @@ struct CoefEntry {
 // ELL form of every operator, left (rows of O) and right (rows of O^T).
 struct OpEll {
   int n_ops = 0, d = 0, slots = 0;
+  std::vector<int32_t> op_slots;  // [n_ops]
   std::vector<int32_t> cnt;  // [n_ops][2][d]
   std::vector<int32_t> col;  // [n_ops][2][d][slots]
   std::vector<cd> val;       // [n_ops][2][d][slots]
+  // compact form for the wave kernel: op o owns entries [off[o], off[o] +
+  // 2 d ns[o]) laid out [side][row][slot]; operator 0 (H) keeps only its
+  // off-diagonal entries, its diagonal goes to hdiag.
+  std::vector<int32_t> c_off, c_ns, c_real;
+  std::vector<int32_t> c_col;
+  std::vector<cd> c_val;
+  std::vector<cd> hdiag;
+};
+
+// A launch plan: tasks (one output ADO each), each a run of edge groups.
+// A group shares one operator and one coefficient pair (cl, cr); its edges
+// carry a small integer weight, so the group contributes
+//   cl * O u + cr * u O,   u = sum_e w_e x_{b_e}.
+struct Plan {
+  int n_chunks = -1;             // -1: untiled single launch
+  int4 *tasks = nullptr;         // {a, g0, g1, flags}
+  int4 *groups = nullptr;        // {e0, e1, coef_id, self}
+  int2 *gedges = nullptr;        // {b, w}
+  std::vector<int64_t> task_off; // [n_launch + 1]
+  size_t bytes = 0;
 };
 
 // Device copies of the tables, one set per precision for the values.
 struct DeviceTables {
   int device = -1;
-  int64_t *row_ptr = nullptr;   // [N+1]
-  int2 *edges = nullptr;        // [E] (neighbour, packed coef/mult)
   double2 *decay64 = nullptr;   // [N]
   float2 *decay32 = nullptr;
   int32_t *ell_cnt = nullptr;
   int32_t *ell_col = nullptr;
+  int32_t *op_slots = nullptr;  // [n_ops] max row count of each operator
   double2 *ell_val64 = nullptr;
   float2 *ell_val32 = nullptr;
   int32_t *coef_op = nullptr;   // [n_coef]
   double2 *coef64 = nullptr;    // [n_coef][2] (cl, cr)
   float2 *coef32 = nullptr;
-  double *hdiag_re = nullptr;   // [d] real diagonal of H (Jacobi)
-  // tiled plan (top tier split into chunks)
-  int n_chunks = 0;
-  int4 *tasks = nullptr;        // all launches' tasks back to back
-  int2 *tedges = nullptr;       // edges in task order
-  std::vector<int64_t> task_off;  // [n_launch+1] into tasks
+  double2 *hdiag = nullptr;     // [d] diagonal of H
+  float2 *hdiag32 = nullptr;
+  int32_t *c_meta = nullptr;    // [n_ops][3] (off, ns, real) of the compact ELL
+  int32_t *c_col = nullptr;
+  double2 *c_val64 = nullptr;
+  float2 *c_val32 = nullptr;
+  Plan base;                    // untiled
+  Plan tiled;                   // top tier split into chunks
   size_t bytes = 0;
 };
 
@@ -90,7 +112,8 @@ struct Hier {
   std::vector<int64_t> row_ptr;    // [N+1]
   std::vector<int32_t> ecol;       // [E]
   std::vector<int32_t> einfo;      // [E] coef_id << 8 | (uint8) mult
-  std::vector<CoefEntry> coefs;
+  std::vector<CoefEntry> coefs;   // last entry: the H commutator (op 0, -i, +i)
+  int coef_H = 0;
   OpEll ell;
   int64_t n_leaf = 0;
   // bosonic code for dictionary lookups
@@ -109,6 +132,7 @@ int64_t lookup_ado(const Hier &h, uint64_t fmask, uint64_t bcode);
 heom_status ensure_device(Hier &h);
 heom_status ensure_tiled_plan(Hier &h, int n_chunks);
 void free_device(Hier &h);
+void free_plan(Plan &p);
 
 struct ApplyArgs {
   const void *x = nullptr;      // input vector
