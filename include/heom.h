@@ -184,6 +184,84 @@ heom_status heom_apply_shifted(heom_hier *h, int32_t precision, const void *x_de
 heom_status heom_apply_tiled(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev,
                              int32_t n_rhs, const double *shift, int32_t n_chunks, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Time propagation (Fig. 1d; fixed-step classical RK4)
+ * ---------------------------------------------------------------------- */
+
+/* Integrate dx/dt = M x from x(0) (in x_dev) for n_steps steps of dt; on
+ * return x_dev holds x(n_steps dt).  If rho0_traj_dev is not NULL it
+ * receives the reduced density operator (ADO 0, d*d complex of the given
+ * precision) after every save_every steps: n_steps / save_every entries.
+ * Workspace: heom_workspace_size(HEOM_OP_PROPAGATE).  graph_steps > 0
+ * captures that many steps in a hipGraph and replays it. */
+heom_status heom_propagate(heom_hier *h, int32_t precision, void *x_dev, double dt, int64_t n_steps,
+                           int64_t save_every, void *rho0_traj_dev, int32_t graph_steps, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Linear solves (stationary state and spectra)
+ * ---------------------------------------------------------------------- */
+enum { HEOM_OP_PROPAGATE = 0, HEOM_OP_STEADY = 1, HEOM_OP_SPECTRUM = 2 };
+enum { HEOM_PREC_NONE = 0, HEOM_PREC_JACOBI = 1, HEOM_PREC_NN = 2 };
+enum { HEOM_SOLVE_FP64 = 0, HEOM_SOLVE_FP32_IR = 1 };
+
+typedef struct {
+  int32_t restart;        /* GMRES restart length m (default 30)              */
+  int32_t max_iter;       /* total inner iterations (default 3000)            */
+  double tol;             /* relative true residual ||b - A x|| / ||b||       */
+  int32_t precond;        /* HEOM_PREC_*                                      */
+  int32_t mode;           /* HEOM_SOLVE_FP64 or HEOM_SOLVE_FP32_IR             */
+  double inner_tol;       /* FP32 inner tolerance for IR (default 1e-5)       */
+  int32_t max_refine;     /* IR outer steps (default 20)                      */
+  int32_t rhs_chunk;      /* spectra: right-hand sides per multi-RHS solve    */
+  const heom_nn *nn;      /* learned preconditioner for HEOM_PREC_NN          */
+  int32_t fallback;       /* 1: on NN stagnation/NaN restart with Jacobi      */
+  int32_t use_x0;         /* 1: x_dev holds the initial guess                 */
+} heom_solver_opts;
+
+typedef struct {
+  int32_t status;         /* HEOM_OK or HEOM_ERR_NOT_CONVERGED / _NAN          */
+  int32_t iterations;     /* inner iterations (summed over RHS chunks)         */
+  int32_t restarts;
+  int32_t refinements;    /* IR outer steps                                    */
+  int32_t fell_back;      /* 1 when the NN preconditioner was abandoned        */
+  double true_residual;   /* max over right-hand sides, FP64 apply             */
+  double seconds;
+  int64_t applies;        /* Liouvillian applies performed                     */
+} heom_solver_report;
+
+/* Defaults: restart 30, max_iter 3000, tol 1e-8, Jacobi, FP64, inner_tol
+ * 1e-5, max_refine 20, rhs_chunk 64, fallback on. */
+void heom_default_opts(heom_solver_opts *o);
+/* Device workspace (bytes) that `op` needs with options o (NULL = defaults).
+ * n_rhs: for HEOM_OP_SPECTRUM the number of columns of one chunk, i.e.
+ * rhs_chunk for a power spectrum and 2 rhs_chunk for a density of states;
+ * ignored otherwise. */
+heom_status heom_workspace_size(const heom_hier *h, int32_t op, const heom_solver_opts *o, int64_t n_rhs,
+                                size_t *bytes);
+
+/* Stationary state: solves B x = e_0 where B is M (even parity) with the
+ * equation of element (0,0) of ADO 0 replaced by Tr rho_0 = 1.  x_dev:
+ * FP64 [N][d][d] (initial guess if o->use_x0).  Synchronises the stream at
+ * every convergence check. */
+heom_status heom_steady(heom_hier *h, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* Spectra (Methods, "Numerical computation of the spectrum").
+ * kind 0 = density of states of the fermionic operator `op` (d x d host):
+ *   pi A(w) = -Re{Tr[op x_+,0] + Tr[op^dag x_-,0]},
+ *   (M_odd + i w) x_+ = op^dag rho_ss, (M_odd - i w) x_- = op rho_ss;
+ *   `even` is the even-parity hierarchy of rho_ss, `odd` the odd one.
+ * kind 1 = power spectral density of the bosonic operator `op`:
+ *   pi S(w) = -Re Tr[op^dag x_0], (M_even - i w) x = op rho_ss; odd = NULL.
+ * The right-hand side left-multiplies every ADO of x_ss (FP64, device).
+ * out_host: n_omega doubles.  Frequencies are solved rhs_chunk at a time
+ * as multi-RHS systems. */
+heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev, int32_t kind,
+                          const double *op, const double *omega, int64_t n_omega, double *out_host,
+                          const heom_solver_opts *o, heom_solver_report *r, void *ws, size_t ws_bytes,
+                          void *stream);
+
 const char *heom_status_string(heom_status s);
 const char *heom_last_error(void);
 const char *heom_version(void);

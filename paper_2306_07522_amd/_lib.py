@@ -66,6 +66,15 @@ SIGNATURES = {
     "heom_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, vp]),
     "heom_apply_shifted": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp, vp]),
     "heom_apply_tiled": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
+    "heom_default_opts": (None, [C.POINTER(heom_solver_opts)]),
+    "heom_workspace_size": (heom_status, [vp, C.c_int32, C.POINTER(heom_solver_opts), C.c_int64,
+                                          C.POINTER(C.c_size_t)]),
+    "heom_propagate": (heom_status, [vp, C.c_int32, vp, C.c_double, C.c_int64, C.c_int64, vp, C.c_int32, vp,
+                                     C.c_size_t, vp]),
+    "heom_steady": (heom_status, [vp, vp, C.POINTER(heom_solver_opts), C.POINTER(heom_solver_report), vp,
+                                  C.c_size_t, vp]),
+    "heom_spectrum": (heom_status, [vp, vp, vp, C.c_int32, dp, dp, C.c_int64, dp, C.POINTER(heom_solver_opts),
+                                    C.POINTER(heom_solver_report), vp, C.c_size_t, vp]),
 }
 
 _lib = None

@@ -218,3 +218,84 @@ class Hierarchy:
             L.check(self._lib.heom_apply(self._h, prec, _devptr(x), _devptr(y), n_rhs,
                                          _dptr(sh) if sh is not None else None, s))
         return y
+
+
+# ----------------------------------------------------------------- solvers
+_PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN}
+_MODE = {"fp64": L.HEOM_SOLVE_FP64, "fp32_ir": L.HEOM_SOLVE_FP32_IR}
+
+
+def solver_opts(**kw):
+    """heom_solver_opts from keyword overrides of the library defaults
+    (restart, max_iter, tol, precond, mode, inner_tol, max_refine, rhs_chunk,
+    nn, fallback, use_x0)."""
+    o = L.heom_solver_opts()
+    lib().heom_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "precond":
+            v = _PREC[v] if isinstance(v, str) else v
+        elif k == "mode":
+            v = _MODE[v] if isinstance(v, str) else v
+        elif k == "nn":
+            v = C.c_void_p(v.handle.value) if v is not None else None
+        setattr(o, k, v)
+    return o
+
+
+def report_dict(r):
+    return {f: getattr(r, f) for f, _ in L.heom_solver_report._fields_}
+
+
+def _workspace(h, op, opts, n_rhs=1):
+    import torch
+    nbytes = C.c_size_t()
+    L.check(lib().heom_workspace_size(h.handle, op, C.byref(opts) if opts is not None else None, n_rhs,
+                                      C.byref(nbytes)))
+    return torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device="cuda")
+
+
+def propagate(h, x, dt, n_steps, save_every=0, graph_steps=0, stream=None, ws=None):
+    """RK4 in place on the device vector x; returns the trajectory of ADO 0
+    ([n_steps // save_every][d][d]) when save_every > 0."""
+    import torch
+    prec = _precision_of(x)
+    traj = None
+    if save_every:
+        traj = torch.empty((n_steps // save_every, h.d, h.d), dtype=x.dtype, device=x.device)
+    if ws is None:
+        ws = _workspace(h, L.HEOM_OP_PROPAGATE, None)
+    L.check(lib().heom_propagate(h.handle, prec, _devptr(x), float(dt), int(n_steps), int(save_every),
+                                 _devptr(traj) if traj is not None else None, int(graph_steps),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return traj
+
+
+def steady_state(h, x=None, stream=None, **opts):
+    """Stationary ADOs (FP64 [N][d][d] device tensor) and the solver report."""
+    import torch
+    o = solver_opts(**opts)
+    if x is None:
+        x = torch.zeros((h.N, h.d, h.d), dtype=torch.complex128, device="cuda")
+    ws = _workspace(h, L.HEOM_OP_STEADY, o)
+    rep = L.heom_solver_report()
+    st = lib().heom_steady(h.handle, _devptr(x), C.byref(o), C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(),
+                           _stream_ptr(stream))
+    L.check(st)
+    return x, report_dict(rep)
+
+
+def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, **opts):
+    """Density of states (kind 'dos', odd-parity `odd`) or power spectral
+    density (kind 'psd') of operator `op` at the given frequencies."""
+    o = solver_opts(**opts)
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    out = np.zeros(len(om))
+    k = 0 if kind == "dos" else 1
+    cols = max(1, min(o.rhs_chunk, len(om))) * (2 if k == 0 else 1)
+    ws = _workspace(odd if k == 0 else even, L.HEOM_OP_SPECTRUM, o, cols)
+    opm = _c128(op)
+    rep = L.heom_solver_report()
+    L.check(lib().heom_spectrum(even.handle, odd.handle if odd is not None else None, _devptr(x_ss), k, _dptr(opm),
+                                _dptr(om), len(om), _dptr(out), C.byref(o), C.byref(rep),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return out, report_dict(rep)

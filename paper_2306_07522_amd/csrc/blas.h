@@ -1,0 +1,35 @@
+// Vector-kernel launchers used by the solvers (blas.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace heom {
+
+// out[i * R + r] = conj(V_i) . w per right-hand side (partial: k * nchunk * R scratch)
+template <typename T>
+heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, int R, double2 *partial, int nchunk,
+                 double2 *out, hipStream_t s);
+// w += sign * sum_i V_i h_i (per right-hand side)
+template <typename T>
+heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
+                         hipStream_t s);
+template <typename T>
+heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s);
+template <typename TX, typename TY>
+heom_status axpby(const void *x, double alpha, void *y, double beta, int64_t total, hipStream_t s);
+template <typename T>
+heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s);
+template <typename T>
+heom_status rk4_combine(void *x, const void *k1, const void *k2, const void *k3, const void *k4, double dt,
+                        int64_t total, hipStream_t s);
+template <typename T>
+heom_status save_rho0(const void *x, void *traj, int d2, int *counter, int64_t max_slots, hipStream_t s);
+heom_status fill_int(int *p, int v, int n, hipStream_t s);
+template <typename T>
+heom_status left_multiply(const double2 *x, const double2 *ops, int d, int64_t N, int R, const int *col_op, void *b,
+                          hipStream_t s);
+template <typename T>
+heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const int *col_op, double scale,
+                          double *out, hipStream_t s);
+
+}  // namespace heom

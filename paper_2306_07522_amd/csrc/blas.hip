@@ -1,0 +1,360 @@
+// Vector kernels for the solvers: multi-dot products (Arnoldi / CGS2),
+// basis updates, scaling, the Jacobi preconditioner, the RK4 combine, the
+// spectrum right-hand side and its trace readout.
+//
+// Vectors use the multi-RHS layout [n][R] (element-major, RHS innermost),
+// n = N d^2 complex elements per right-hand side.  Reductions accumulate in
+// double and are deterministic (fixed two-pass order, no atomics).
+#include "blas.h"
+#include "device_common.h"
+
+namespace heom {
+
+template <typename T> struct Acc2 { double x, y; };
+
+// --------------------------------------------------------------- multi-dot
+// partial[(i * nchunk + chunk) * R + r] = sum over the chunk's elements of
+// conj(V_i[e, r]) * w[e, r] for NI consecutive basis vectors i.
+template <typename T, int NI>
+__global__ void __launch_bounds__(256) mdot_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
+                                                   const typename Cplx<T>::t *__restrict__ w, int64_t n, int R,
+                                                   double2 *__restrict__ partial, int nchunk) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double2 red[NI][256];
+  const int i0 = blockIdx.y * NI;
+  const int chunk = blockIdx.x;
+  // thread -> (row slot, rhs); rows of the chunk are strided by rows_per_pass
+  const int rt = R < 256 ? R : 256;
+  const int rows_per_pass = 256 / rt;
+  const int tr = threadIdx.x % rt, trow = threadIdx.x / rt;
+  const int64_t e0 = n * chunk / nchunk, e1 = n * (chunk + 1) / nchunk;
+  for (int rbase = 0; rbase < R; rbase += rt) {
+    const int r = rbase + tr;
+    double ax[NI], ay[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) ax[q] = ay[q] = 0.0;
+    if (trow < rows_per_pass && r < R) {
+      for (int64_t e = e0 + trow; e < e1; e += rows_per_pass) {
+        const T2 b = w[e * R + r];
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+          if (i0 + q < k) {
+            const T2 a = V[(i0 + q) * ldv + e * R + r];
+            ax[q] += (double)a.x * b.x + (double)a.y * b.y;
+            ay[q] += (double)a.x * b.y - (double)a.y * b.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NI; ++q) red[q][threadIdx.x] = make_double2(ax[q], ay[q]);
+    __syncthreads();
+    // reduce over the row slots that share the same r
+    if (threadIdx.x < rt) {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        double sx = 0, sy = 0;
+        for (int t = 0; t < rows_per_pass; ++t) {
+          sx += red[q][t * rt + threadIdx.x].x;
+          sy += red[q][t * rt + threadIdx.x].y;
+        }
+        const int rr = rbase + threadIdx.x;
+        if (i0 + q < k && rr < R) partial[((int64_t)(i0 + q) * nchunk + chunk) * R + rr] = make_double2(sx, sy);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// out[i * R + r] = sum over chunks of partial
+__global__ void reduce_partials_kernel(const double2 *__restrict__ partial, int k, int nchunk, int R,
+                                       double2 *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)k * R) return;
+  const int i = (int)(idx / R), r = (int)(idx % R);
+  double sx = 0, sy = 0;
+  for (int c = 0; c < nchunk; ++c) {
+    const double2 p = partial[((int64_t)i * nchunk + c) * R + r];
+    sx += p.x;
+    sy += p.y;
+  }
+  out[idx] = make_double2(sx, sy);
+}
+
+// w[e, r] -= sum_{i < k} V_i[e, r] * h[i * R + r]   (h is complex double)
+template <typename T>
+__global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
+                                                           const double2 *__restrict__ h, typename Cplx<T>::t *__restrict__ w,
+                                                           int64_t n, int R, double sign) {
+  using T2 = typename Cplx<T>::t;
+  const int64_t total = n * R;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % R);
+    double sx = 0, sy = 0;
+    for (int i = 0; i < k; ++i) {
+      const T2 a = V[i * ldv + idx];
+      const double2 c = h[(int64_t)i * R + r];
+      sx += (double)a.x * c.x - (double)a.y * c.y;
+      sy += (double)a.x * c.y + (double)a.y * c.x;
+    }
+    T2 o = w[idx];
+    o.x = (T)((double)o.x + sign * sx);
+    o.y = (T)((double)o.y + sign * sy);
+    w[idx] = o;
+  }
+}
+
+// out[e, r] = w[e, r] * s[r]  (s complex double per RHS); out may alias w
+template <typename T>
+__global__ void scale_kernel(const typename Cplx<T>::t *__restrict__ w, const double2 *__restrict__ s,
+                             typename Cplx<T>::t *out, int64_t n, int R) {
+  using T2 = typename Cplx<T>::t;
+  const int64_t total = n * R;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const double2 c = s[idx % R];
+    const T2 a = w[idx];
+    out[idx] = T2{(T)((double)a.x * c.x - (double)a.y * c.y), (T)((double)a.x * c.y + (double)a.y * c.x)};
+  }
+}
+
+// y = alpha * x + beta * y  (real scalars; x and y of possibly different precision)
+template <typename TX, typename TY>
+__global__ void axpby_kernel(const typename Cplx<TX>::t *__restrict__ x, double alpha, typename Cplx<TY>::t *y,
+                             double beta, int64_t total) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const auto a = x[idx];
+    auto b = y[idx];
+    b.x = (TY)(alpha * (double)a.x + beta * (double)b.x);
+    b.y = (TY)(alpha * (double)a.y + beta * (double)b.y);
+    y[idx] = b;
+  }
+}
+
+// Jacobi: z = r / diag(M + shift) where the diagonal of the HEOMLS at
+// element (a, i, j) is -(c_a - z_r) - i (H_ii - H_jj); the bordered row
+// (ADO 0, element (0,0)) has diagonal 1; exact zeros are replaced by 1.
+template <typename T>
+__global__ void jacobi_kernel(const typename Cplx<T>::t *__restrict__ r, typename Cplx<T>::t *__restrict__ z,
+                              const double2 *__restrict__ decay, const double2 *__restrict__ hdiag, int d, int64_t N,
+                              int R, const double2 *__restrict__ shifts, int border) {
+  using T2 = typename Cplx<T>::t;
+  const int64_t total = N * d * d * R;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int rr = (int)(idx % R);
+    const int64_t e = idx / R;
+    const int64_t a = e / (d * d);
+    const int ij = (int)(e % (d * d));
+    const int i = ij / d, j = ij % d;
+    double2 dg;
+    const double2 c = decay[a];
+    const double2 zz = shifts ? shifts[rr] : make_double2(0.0, 0.0);
+    const double2 hi = hdiag[i], hj = hdiag[j];
+    // -(c - z) - i (hi - hj)
+    dg.x = -(c.x - zz.x) + (hi.y - hj.y);
+    dg.y = -(c.y - zz.y) - (hi.x - hj.x);
+    if (border && e == 0) dg = make_double2(1.0, 0.0);
+    const double m2 = dg.x * dg.x + dg.y * dg.y;
+    if (m2 == 0.0) dg = make_double2(1.0, 0.0);
+    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
+    const T2 v = r[idx];
+    // v / dg = v * conj(dg) / |dg|^2
+    z[idx] = T2{(T)(((double)v.x * dg.x + (double)v.y * dg.y) * inv), (T)(((double)v.y * dg.x - (double)v.x * dg.y) * inv)};
+  }
+}
+
+// RK4 combine: x += dt/6 (k1 + 2 k2 + 2 k3 + k4)
+template <typename T>
+__global__ void rk4_combine_kernel(typename Cplx<T>::t *__restrict__ x, const typename Cplx<T>::t *__restrict__ k1,
+                                   const typename Cplx<T>::t *__restrict__ k2, const typename Cplx<T>::t *__restrict__ k3,
+                                   const typename Cplx<T>::t *__restrict__ k4, T dt6, int64_t total) {
+  using T2 = typename Cplx<T>::t;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const T2 a = k1[idx], b = k2[idx], c = k3[idx], e = k4[idx];
+    T2 v = x[idx];
+    v.x += dt6 * (a.x + 2 * b.x + 2 * c.x + e.x);
+    v.y += dt6 * (a.y + 2 * b.y + 2 * c.y + e.y);
+    x[idx] = v;
+  }
+}
+
+// save ADO 0 into the trajectory slot counter[0] and advance the counter
+template <typename T>
+__global__ void save_rho0_kernel(const typename Cplx<T>::t *__restrict__ x, typename Cplx<T>::t *__restrict__ traj,
+                                 int d2, int *counter, int64_t max_slots) {
+  const int slot = *counter;
+  if (slot < max_slots)
+    for (int t = threadIdx.x; t < d2; t += blockDim.x) traj[(int64_t)slot * d2 + t] = x[t];
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = slot + 1;
+}
+
+__global__ void fill_int_kernel(int *p, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// b[(a, i, j), r] = (O_{sel(r)} x_a)[i][j]: left-multiply every ADO of the
+// FP64 single-RHS vector x by one of two d x d operators (column r uses
+// op[col_op[r]]).
+template <typename T>
+__global__ void left_multiply_kernel(const double2 *__restrict__ x, const double2 *__restrict__ ops, int d, int64_t N,
+                                     int R, const int *__restrict__ col_op, typename Cplx<T>::t *__restrict__ b) {
+  using T2 = typename Cplx<T>::t;
+  const int64_t total = N * d * d * R;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % R);
+    const int64_t e = idx / R;
+    const int64_t a = e / (d * d);
+    const int ij = (int)(e % (d * d));
+    const int i = ij / d, j = ij % d;
+    const double2 *O = ops + (int64_t)col_op[r] * d * d;
+    double sx = 0, sy = 0;
+    for (int k = 0; k < d; ++k) {
+      const double2 o = O[i * d + k];
+      const double2 v = x[(a * d + k) * d + j];
+      sx += o.x * v.x - o.y * v.y;
+      sy += o.x * v.y + o.y * v.x;
+    }
+    b[idx] = T2{(T)sx, (T)sy};
+  }
+}
+
+// out[r] = scale * Re Tr[O_{sel(r)} x_0^{(r)}]
+template <typename T>
+__global__ void trace_readout_kernel(const typename Cplx<T>::t *__restrict__ x, const double2 *__restrict__ ops, int d,
+                                     int R, const int *__restrict__ col_op, double scale, double *__restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const double2 *O = ops + (int64_t)col_op[r] * d * d;
+  double s = 0;
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) {
+      const double2 o = O[i * d + k];
+      const auto v = x[((int64_t)k * d + i) * R + r];
+      s += o.x * (double)v.x - o.y * (double)v.y;
+    }
+  out[r] = scale * s;
+}
+
+// --------------------------------------------------------------- launchers
+static inline unsigned grid_for(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+template <typename T>
+heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, int R, double2 *partial, int nchunk,
+                 double2 *out, hipStream_t s) {
+  if (k <= 0) return HEOM_OK;
+  constexpr int NI = 4;
+  dim3 g(nchunk, (k + NI - 1) / NI);
+  hipLaunchKernelGGL((mdot_kernel<T, NI>), g, dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv, k,
+                     (const typename Cplx<T>::t *)w, n, R, partial, nchunk);
+  const int64_t kr = (int64_t)k * R;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((kr + 255) / 256)), dim3(256), 0, s, partial, k, nchunk, R,
+                     out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
+                         hipStream_t s) {
+  if (k <= 0) return HEOM_OK;
+  hipLaunchKernelGGL(basis_update_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
+                     k, h, (typename Cplx<T>::t *)w, n, R, sign);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)w, sc,
+                     (typename Cplx<T>::t *)out, n, R);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename TX, typename TY>
+heom_status axpby(const void *x, double alpha, void *y, double beta, int64_t total, hipStream_t s) {
+  hipLaunchKernelGGL((axpby_kernel<TX, TY>), dim3(grid_for(total)), dim3(256), 0, s, (const typename Cplx<TX>::t *)x,
+                     alpha, (typename Cplx<TY>::t *)y, beta, total);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_kernel<T>, dim3(grid_for(h.N * h.d * h.d * R)), dim3(256), 0, s,
+                     (const typename Cplx<T>::t *)r, (typename Cplx<T>::t *)z, h.dev.decay64, h.dev.hdiag, h.d, h.N, R,
+                     shifts, border);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status rk4_combine(void *x, const void *k1, const void *k2, const void *k3, const void *k4, double dt, int64_t total,
+                        hipStream_t s) {
+  using T2 = typename Cplx<T>::t;
+  hipLaunchKernelGGL(rk4_combine_kernel<T>, dim3(grid_for(total)), dim3(256), 0, s, (T2 *)x, (const T2 *)k1,
+                     (const T2 *)k2, (const T2 *)k3, (const T2 *)k4, (T)(dt / 6.0), total);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status save_rho0(const void *x, void *traj, int d2, int *counter, int64_t max_slots, hipStream_t s) {
+  hipLaunchKernelGGL(save_rho0_kernel<T>, dim3(1), dim3(256), 0, s, (const typename Cplx<T>::t *)x,
+                     (typename Cplx<T>::t *)traj, d2, counter, max_slots);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+heom_status fill_int(int *p, int v, int n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status left_multiply(const double2 *x, const double2 *ops, int d, int64_t N, int R, const int *col_op, void *b,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(left_multiply_kernel<T>, dim3(grid_for(N * d * d * R)), dim3(256), 0, s, x, ops, d, N, R, col_op,
+                     (typename Cplx<T>::t *)b);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const int *col_op, double scale, double *out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(trace_readout_kernel<T>, dim3((R + 63) / 64), dim3(64), 0, s, (const typename Cplx<T>::t *)x, ops, d,
+                     R, col_op, scale, out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+#define HEOM_INST(T)                                                                                              \
+  template heom_status mdot<T>(const void *, int64_t, int, const void *, int64_t, int, double2 *, int, double2 *, \
+                               hipStream_t);                                                                       \
+  template heom_status basis_update<T>(const void *, int64_t, int, const double2 *, void *, int64_t, int, double,  \
+                                       hipStream_t);                                                               \
+  template heom_status scale_vec<T>(const void *, const double2 *, void *, int64_t, int, hipStream_t);             \
+  template heom_status jacobi<T>(const void *, void *, const Hier &, int, const double2 *, int, hipStream_t);       \
+  template heom_status rk4_combine<T>(void *, const void *, const void *, const void *, const void *, double,      \
+                                      int64_t, hipStream_t);                                                       \
+  template heom_status save_rho0<T>(const void *, void *, int, int *, int64_t, hipStream_t);                       \
+  template heom_status left_multiply<T>(const double2 *, const double2 *, int, int64_t, int, const int *, void *, \
+                                        hipStream_t);                                                              \
+  template heom_status trace_readout<T>(const void *, const double2 *, int, int, const int *, double, double *,    \
+                                        hipStream_t);
+HEOM_INST(double)
+HEOM_INST(float)
+template heom_status axpby<double, double>(const void *, double, void *, double, int64_t, hipStream_t);
+template heom_status axpby<float, float>(const void *, double, void *, double, int64_t, hipStream_t);
+template heom_status axpby<double, float>(const void *, double, void *, double, int64_t, hipStream_t);
+template heom_status axpby<float, double>(const void *, double, void *, double, int64_t, hipStream_t);
+
+}  // namespace heom

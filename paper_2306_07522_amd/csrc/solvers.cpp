@@ -1,0 +1,263 @@
+// Solvers around the Liouvillian apply: fixed-step RK4 propagation, the
+// stationary state and the frequency-domain spectra (Methods, "Numerical
+// computation of the spectrum"), all solved with restarted right-
+// preconditioned (flexible) GMRES on device vectors.
+//
+// GMRES keeps its Krylov basis on the device; each Arnoldi step orthogonalises
+// with classical Gram-Schmidt applied twice (CGS2, two multi-dot kernels and
+// two basis updates), and copies the (j+2) x R Hessenberg column to pinned
+// host memory where the Givens rotations run.  That copy is the only
+// synchronisation per iteration.  Right-hand sides are independent systems
+// that share every apply launch ([n][R] layout).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "blas.h"
+#include "internal.h"
+#include "solvers.h"
+
+namespace heom {
+
+// ------------------------------------------------------------- workspace
+void *WsArena::take(size_t bytes) {
+  size_t off = (used + 255) & ~(size_t)255;
+  if (off + bytes > size) return nullptr;
+  used = off + bytes;
+  return base + off;
+}
+
+PinnedBuf::~PinnedBuf() {
+  if (p) (void)hipHostFree(p);
+}
+heom_status PinnedBuf::ensure(size_t bytes) {
+  if (bytes <= cap) return HEOM_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+  HEOM_HIP_CHECK(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+  cap = bytes;
+  return HEOM_OK;
+}
+
+static int dot_chunks(int64_t n, int R) {
+  int64_t c = (n * R) / (256 * 64);
+  if (c < 1) c = 1;
+  if (c > 1024) c = 1024;
+  return (int)c;
+}
+
+size_t gmres_bytes(int64_t n, int R, int m, bool flexible, size_t w) {
+  const size_t vec = (size_t)n * R * w;
+  size_t b = (size_t)(m + 1) * vec + 2 * vec + 1024;
+  if (flexible) b += (size_t)m * vec + 256;
+  const int nch = dot_chunks(n, R);
+  b += (size_t)(m + 2) * nch * R * sizeof(double2) + 256;  // partials
+  b += 4 * (size_t)(m + 2) * R * sizeof(double2) + 1024;   // h, scale
+  return b;
+}
+
+// ------------------------------------------------------------- GMRES
+template <typename T>
+heom_status Gmres<T>::init(WsArena &ws, int64_t n_, int R_, int m_, bool flexible_) {
+  n = n_;
+  R = R_;
+  m = m_;
+  flexible = flexible_;
+  const size_t vec = (size_t)n * R * sizeof(T2);
+  V = (T2 *)ws.take((size_t)(m + 1) * vec);
+  w = (T2 *)ws.take(vec);
+  t = (T2 *)ws.take(vec);
+  Z = flexible ? (T2 *)ws.take((size_t)m * vec) : nullptr;
+  nchunk = dot_chunks(n, R);
+  partial = (double2 *)ws.take((size_t)(m + 2) * nchunk * R * sizeof(double2));
+  hdev = (double2 *)ws.take((size_t)2 * (m + 2) * R * sizeof(double2));
+  sdev = (double2 *)ws.take((size_t)2 * R * sizeof(double2));
+  if (!V || !w || !t || (flexible && !Z) || !partial || !hdev || !sdev)
+    return fail(HEOM_ERR_ARG, "solver workspace too small (see heom_workspace_size)");
+  HEOM_TRY(pin.ensure((size_t)2 * (m + 2) * R * sizeof(double2)));
+  H.assign((size_t)R * (m + 1) * m, cd(0));
+  cs.assign((size_t)R * m, 0.0);
+  sn.assign((size_t)R * m, cd(0));
+  g.assign((size_t)R * (m + 1), cd(0));
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status Gmres<T>::norms(const T2 *v, std::vector<double> &out, hipStream_t s) {
+  HEOM_TRY(mdot<T>(v, 0, 1, v, n, R, partial, nchunk, hdev, s));
+  HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, hdev, sizeof(double2) * R, hipMemcpyDeviceToHost, s));
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  const double2 *hp = (const double2 *)pin.p;
+  out.resize(R);
+  for (int r = 0; r < R; ++r) out[r] = std::sqrt(std::max(hp[r].x, 0.0));
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x_is_zero, GmresStats &st,
+                            hipStream_t s) {
+  const int64_t nr = n * R;
+  std::vector<double> bnorm, beta;
+  HEOM_TRY(norms(b, bnorm, s));
+  st.converged = false;
+  std::vector<int> kcol(R, 0);
+  std::vector<char> done(R, 0);
+  int iters = 0;
+  for (int cycle = 0;; ++cycle) {
+    // r = b - A x
+    if (x_is_zero && cycle == 0) {
+      HEOM_TRY((axpby<T, T>(b, 1.0, w, 0.0, nr, s)));
+    } else {
+      HEOM_TRY(A(x, w));
+      ++st.applies;
+      HEOM_TRY((axpby<T, T>(b, 1.0, w, -1.0, nr, s)));
+    }
+    HEOM_TRY(norms(w, beta, s));
+    bool all = true;
+    double worst = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const double rel = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
+      if (!std::isfinite(rel)) return fail(HEOM_ERR_NAN, "non-finite residual in GMRES");
+      worst = std::max(worst, rel);
+      done[r] = rel <= tol;
+      all = all && done[r];
+    }
+    st.residual = worst;
+    if (all) {
+      st.converged = true;
+      break;
+    }
+    if (iters >= max_iter) break;
+    ++st.restarts;
+    // V0 = r / beta
+    double2 *sc = (double2 *)pin.p;
+    for (int r = 0; r < R; ++r) sc[r] = make_double2(beta[r] > 0 && !done[r] ? 1.0 / beta[r] : 0.0, 0.0);
+    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, sc, sizeof(double2) * R, hipMemcpyHostToDevice, s));
+    HEOM_TRY(scale_vec<T>(w, sdev, V, n, R, s));
+    std::fill(g.begin(), g.end(), cd(0));
+    for (int r = 0; r < R; ++r) {
+      g[(size_t)r * (m + 1)] = done[r] ? 0.0 : beta[r];
+      kcol[r] = 0;
+    }
+    std::vector<char> active(R);
+    for (int r = 0; r < R; ++r) active[r] = !done[r] && beta[r] > 0;
+    int j = 0;
+    for (; j < m && iters < max_iter; ++j, ++iters) {
+      T2 *vj = V + (size_t)j * nr;
+      T2 *zj = flexible ? Z + (size_t)j * nr : t;
+      if (P) {
+        HEOM_TRY(P(vj, zj, flexible));
+      } else {
+        HEOM_HIP_CHECK(hipMemcpyAsync(zj, vj, sizeof(T2) * nr, hipMemcpyDeviceToDevice, s));
+      }
+      HEOM_TRY(A(zj, w));
+      ++st.applies;
+      // CGS2
+      double2 *h1 = hdev, *h2 = hdev + (size_t)(m + 2) * R;
+      HEOM_TRY(mdot<T>(V, nr, j + 1, w, n, R, partial, nchunk, h1, s));
+      HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, w, n, R, -1.0, s));
+      HEOM_TRY(mdot<T>(V, nr, j + 1, w, n, R, partial, nchunk, h2, s));
+      HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, w, n, R, -1.0, s));
+      HEOM_TRY(mdot<T>(w, 0, 1, w, n, R, partial, nchunk, h2 + (size_t)(j + 1) * R, s));
+      HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, hdev, sizeof(double2) * 2 * (m + 2) * R, hipMemcpyDeviceToHost, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      const double2 *hp1 = (const double2 *)pin.p;
+      const double2 *hp2 = hp1 + (size_t)(m + 2) * R;
+      std::vector<double2> scv(R);
+      bool all_done = true;
+      for (int r = 0; r < R; ++r) {
+        cd *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m
+        for (int i = 0; i <= j; ++i) {
+          Hc[(size_t)j * (m + 1) + i] = cd(hp1[(size_t)i * R + r].x + hp2[(size_t)i * R + r].x,
+                                           hp1[(size_t)i * R + r].y + hp2[(size_t)i * R + r].y);
+        }
+        const double hn = std::sqrt(std::max(hp2[(size_t)(j + 1) * R + r].x, 0.0));
+        if (!std::isfinite(hn)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+        Hc[(size_t)j * (m + 1) + j + 1] = hn;
+        const bool use = active[r] && hn > 1e-300;
+        scv[r] = make_double2(use ? 1.0 / hn : 0.0, 0.0);
+        if (!active[r]) continue;
+        // previous rotations
+        cd *col = &Hc[(size_t)j * (m + 1)];
+        for (int i = 0; i < j; ++i) {
+          const double c = cs[(size_t)r * m + i];
+          const cd sv = sn[(size_t)r * m + i];
+          const cd tmp = c * col[i] + sv * col[i + 1];
+          col[i + 1] = -std::conj(sv) * col[i] + c * col[i + 1];
+          col[i] = tmp;
+        }
+        // new rotation zeroing col[j+1]
+        const cd aa = col[j], bb = col[j + 1];
+        const double na = std::abs(aa), nb = std::abs(bb);
+        double c;
+        cd sv, rr;
+        if (nb == 0.0) { c = 1.0; sv = 0.0; rr = aa; }
+        else if (na == 0.0) { c = 0.0; sv = std::conj(bb) / nb; rr = nb; }
+        else {
+          const double nrm = std::sqrt(na * na + nb * nb);
+          c = na / nrm;
+          sv = (aa / na) * std::conj(bb) / nrm;
+          rr = (aa / na) * nrm;
+        }
+        cs[(size_t)r * m + j] = c;
+        sn[(size_t)r * m + j] = sv;
+        col[j] = rr;
+        col[j + 1] = 0.0;
+        cd *gr = &g[(size_t)r * (m + 1)];
+        gr[j + 1] = -std::conj(sv) * gr[j];
+        gr[j] = c * gr[j];
+        kcol[r] = j + 1;
+        const double rel = bnorm[r] > 0 ? std::abs(gr[j + 1]) / bnorm[r] : 0.0;
+        if (rel <= tol * 0.5 || !use) active[r] = 0;  // stop extending this system's basis
+        all_done = all_done && !active[r];
+      }
+      HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+      HEOM_TRY(scale_vec<T>(w, sdev, V + (size_t)(j + 1) * nr, n, R, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack
+      if (all_done) { ++j; ++iters; break; }
+    }
+    st.iterations = iters;
+    // y per RHS from the triangular system, then the update
+    int kmax = 0;
+    for (int r = 0; r < R; ++r) kmax = std::max(kmax, kcol[r]);
+    if (kmax == 0) continue;
+    double2 *yh = (double2 *)pin.p;
+    for (int i = 0; i < kmax; ++i)
+      for (int r = 0; r < R; ++r) yh[(size_t)i * R + r] = make_double2(0, 0);
+    for (int r = 0; r < R; ++r) {
+      const int k = kcol[r];
+      const cd *Hc = &H[((size_t)r * (m + 1)) * m];
+      std::vector<cd> y(k);
+      for (int i = k - 1; i >= 0; --i) {
+        cd acc = g[(size_t)r * (m + 1) + i];
+        for (int q = i + 1; q < k; ++q) acc -= Hc[(size_t)q * (m + 1) + i] * y[q];
+        const cd dgl = Hc[(size_t)i * (m + 1) + i];
+        y[i] = std::abs(dgl) > 0 ? acc / dgl : cd(0);
+      }
+      for (int i = 0; i < k; ++i) yh[(size_t)i * R + r] = make_double2(y[i].real(), y[i].imag());
+    }
+    HEOM_HIP_CHECK(hipMemcpyAsync(hdev, yh, sizeof(double2) * kmax * R, hipMemcpyHostToDevice, s));
+    if (flexible) {
+      HEOM_TRY(basis_update<T>(Z, nr, kmax, hdev, x, n, R, 1.0, s));
+    } else {
+      HEOM_HIP_CHECK(hipMemsetAsync(t, 0, sizeof(T2) * nr, s));
+      HEOM_TRY(basis_update<T>(V, nr, kmax, hdev, t, n, R, 1.0, s));
+      if (P) {
+        HEOM_TRY(P(t, w, false));
+        HEOM_TRY((axpby<T, T>(w, 1.0, x, 1.0, nr, s)));
+      } else {
+        HEOM_TRY((axpby<T, T>(t, 1.0, x, 1.0, nr, s)));
+      }
+    }
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    x_is_zero = false;
+  }
+  return HEOM_OK;
+}
+
+template struct Gmres<double>;
+template struct Gmres<float>;
+
+}  // namespace heom

@@ -1,0 +1,58 @@
+// Solver building blocks shared by the propagate / steady / spectrum drivers.
+#pragma once
+
+#include <functional>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace heom {
+
+// Bump allocator over a caller-owned device workspace.
+struct WsArena {
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+  WsArena(void *p, size_t n) : base((char *)p), size(n) {}
+  void *take(size_t bytes);
+};
+
+struct PinnedBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  ~PinnedBuf();
+  heom_status ensure(size_t bytes);
+};
+
+struct GmresStats {
+  int iterations = 0, restarts = 0;
+  int64_t applies = 0;
+  double residual = 0.0;  // max relative residual of the last true-residual check
+  bool converged = false;
+};
+
+size_t gmres_bytes(int64_t n, int R, int m, bool flexible, size_t elem_bytes);
+
+// Restarted right-preconditioned GMRES (FGMRES when flexible) on [n][R]
+// device vectors.  A(in, out): out = A in.  P(in, out, flexible): out =
+// M^{-1} in (may be empty for no preconditioning).
+template <typename T>
+struct Gmres {
+  using T2 = typename Cplx<T>::t;
+  int64_t n = 0;
+  int R = 1, m = 30;
+  bool flexible = false;
+  std::function<heom_status(const void *, void *)> A;
+  std::function<heom_status(const void *, void *, bool)> P;
+  T2 *V = nullptr, *Z = nullptr, *w = nullptr, *t = nullptr;
+  double2 *partial = nullptr, *hdev = nullptr, *sdev = nullptr;
+  int nchunk = 1;
+  PinnedBuf pin;
+  std::vector<cd> H, sn, g;
+  std::vector<double> cs;
+  heom_status init(WsArena &ws, int64_t n, int R, int m, bool flexible);
+  heom_status norms(const T2 *v, std::vector<double> &out, hipStream_t s);
+  // x: initial guess (ignored when x_is_zero; then x must hold zeros)
+  heom_status solve(const T2 *b, T2 *x, double tol, int max_iter, bool x_is_zero, GmresStats &st, hipStream_t s);
+};
+
+}  // namespace heom

@@ -1,0 +1,170 @@
+"""GPU parity of propagation, stationary state and spectra against the
+oracle (RK4 on the assembled HEOMLS, sparse LU) and closed forms.
+
+Bars: RK4 trajectories <= 1e-12 relative (FP64) / 1e-5 (FP32); linear
+solves are run to a 1e-12 relative true residual and compared with the LU
+solution to 1e-9 (the error is then set by the conditioning, stated in the
+assertion messages); spectra of the U = 0 level match the closed form.
+"""
+import numpy as np
+import pytest
+
+from oracle import solvers as osv
+from oracle.liouvillian import from_blocks, to_blocks
+from paper_2306_07522_amd import workloads as wl
+from tests.helpers import library_model, oracle_model, oracle_to_library_perm, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _api():
+    from paper_2306_07522_amd import api
+    return api
+
+
+def _initial(om, lm, perm, rho0):
+    xo = np.zeros((om.N, om.d, om.d), dtype=complex)
+    xo[0] = rho0
+    xl = np.zeros_like(xo)
+    xl[perm] = xo
+    return xo, xl
+
+
+@pytest.mark.parametrize("graph", [0, 100])
+def test_rk4_spin_boson(graph):
+    torch, api = _torch(), _api()
+    cfg = wl.spin_boson()
+    om, lm = oracle_model(cfg), library_model(cfg)
+    perm = oracle_to_library_perm(om, lm)
+    xo, xl = _initial(om, lm, perm, cfg["rho0"])
+    x = torch.from_numpy(xl).cuda()
+    traj = api.propagate(lm, x, cfg["dt"], cfg["n_steps"], save_every=100, graph_steps=graph)
+    xo_f, traj_o = osv.rk4(om.assemble(), from_blocks(xo), cfg["dt"], cfg["n_steps"], save_every=100, d=2)
+    e_x = rel_err(x.cpu().numpy()[perm], to_blocks(xo_f, om.N, om.d))
+    e_t = rel_err(traj.cpu().numpy(), np.array(traj_o))
+    assert e_x <= 1e-12 and e_t <= 1e-12, (e_x, e_t)
+    r = traj.cpu().numpy()
+    assert np.abs(np.trace(r, axis1=1, axis2=2) - 1).max() < 1e-12
+    assert np.abs(r - np.conj(np.transpose(r, (0, 2, 1)))).max() < 1e-12
+    # FP32 trajectory against the FP64 oracle
+    x32 = torch.from_numpy(xl.astype(np.complex64)).cuda()
+    traj32 = api.propagate(lm, x32, cfg["dt"], cfg["n_steps"], save_every=100, graph_steps=graph)
+    e32 = rel_err(traj32.cpu().numpy().astype(complex), np.array(traj_o))
+    assert e32 <= 1e-5, e32
+
+
+def test_rk4_graph_equals_eager():
+    torch, api = _torch(), _api()
+    cfg = wl.siam(n_max=2)
+    lm = library_model(cfg)
+    rng = np.random.default_rng(0)
+    x0 = wl.random_vector(rng, lm.N, lm.d)
+    xa = torch.from_numpy(x0).cuda()
+    xb = torch.from_numpy(x0).cuda()
+    ta = api.propagate(lm, xa, 0.002, 60, save_every=20, graph_steps=0)
+    tb = api.propagate(lm, xb, 0.002, 60, save_every=20, graph_steps=20)
+    assert torch.equal(xa, xb) and torch.equal(ta, tb)
+
+
+@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small"])
+def test_rk4_workloads(name):
+    torch, api = _torch(), _api()
+    if name == "charge_cavity":
+        cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=3)   # d = 8: wave kernel with fused stages
+    else:
+        cfg = wl.two_orbital_anderson(n_max=2)                    # d = 16: wave kernel with fused stages
+    om, lm = oracle_model(cfg), library_model(cfg)
+    perm = oracle_to_library_perm(om, lm)
+    rng = np.random.default_rng(5)
+    xo = wl.random_vector(rng, om.N, om.d) * 0.1
+    xl = np.empty_like(xo)
+    xl[perm] = xo
+    x = torch.from_numpy(xl).cuda()
+    api.propagate(lm, x, 0.01, 20)
+    ref, _ = osv.rk4(om.assemble(), from_blocks(xo), 0.01, 20)
+    e = rel_err(x.cpu().numpy()[perm], to_blocks(ref, om.N, om.d))
+    assert e <= 1e-12, e
+
+
+def _steady_check(cfg, mode, precond, tol_err, lu=True):
+    torch, api = _torch(), _api()
+    om, lm = oracle_model(cfg), library_model(cfg)
+    perm = oracle_to_library_perm(om, lm)
+    x, rep = api.steady_state(lm, tol=1e-12, mode=mode, precond=precond, restart=40, max_iter=4000)
+    xl = x.cpu().numpy()[perm]
+    assert rep["status"] == 0 and rep["true_residual"] <= 1e-12, rep
+    r0 = xl[0]
+    assert abs(np.trace(r0) - 1) < 1e-10
+    assert np.abs(r0 - r0.conj().T).max() < 1e-9
+    M = om.assemble()
+    res = np.linalg.norm(M @ from_blocks(xl)) / np.linalg.norm(from_blocks(xl))
+    assert res < 1e-9, res
+    if lu:
+        xs = to_blocks(osv.steady_state(M, om.d), om.N, om.d)
+        e = rel_err(xl, xs)
+        assert e <= tol_err, (e, rep)
+    return rep
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "none"])
+def test_steady_spin_boson(precond):
+    _steady_check(wl.spin_boson(), "fp64", precond, 1e-10)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+def test_steady_siam(mode):
+    _steady_check(wl.siam(n_max=2), mode, "jacobi", 1e-9)
+
+
+def test_steady_siam_full_tier():
+    # 10,701 ADOs: residual against the oracle's assembled matrix
+    _steady_check(wl.siam(), "fp64", "jacobi", None, lu=False)
+
+
+def _dos_closed_form(w, eps, Gamma, W, mus):
+    sigma = sum((Gamma * W / 2) / (w - mu + 1j * W) for mu in mus)
+    return -(1.0 / (w - eps - sigma)).imag / np.pi
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+def test_dos_resonant_level_closed_form(mode):
+    torch, api = _torch(), _api()
+    cfg = wl.resonant_level(eps=0.3, n_exp=3, n_max=2)
+    he, ho = library_model(cfg, +1), library_model(cfg, -1)
+    x, rep = api.steady_state(he, tol=1e-12)
+    om = np.linspace(-8, 8, 37)
+    A, rep = api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-11, mode=mode, rhs_chunk=16)
+    exact = _dos_closed_form(om, 0.3, 2.0, 10.0, (1.0, -1.0))
+    assert np.abs(A - exact).max() < 1e-8, (np.abs(A - exact).max(), rep)
+
+
+def test_dos_siam_vs_oracle():
+    torch, api = _torch(), _api()
+    cfg = wl.siam(n_max=2)
+    he, ho = library_model(cfg, +1), library_model(cfg, -1)
+    oe, oo = oracle_model(cfg, +1), oracle_model(cfg, -1)
+    x, _ = api.steady_state(he, tol=1e-12)
+    om = np.array([-7.0, -5.0, -1.0, 0.0, 0.5, 5.0])
+    A, rep = api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-12, rhs_chunk=4)
+    xs = osv.steady_state(oe.assemble(), oe.d)
+    Ao = osv.dos(oo.assemble(), xs, cfg["dops"][0], om, oe.N, oe.d)
+    assert np.abs(A - Ao).max() <= 1e-9 * np.abs(Ao).max(), (A, Ao)
+
+
+def test_psd_cavity_vs_oracle():
+    torch, api = _torch(), _api()
+    cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=2, m_max=2, n_max=1)
+    he = library_model(cfg, +1)
+    oe = oracle_model(cfg, +1)
+    x, _ = api.steady_state(he, tol=1e-12)
+    om = np.linspace(0.0, 2.0, 9)
+    S, rep = api.spectrum(he, None, x, cfg["aop"], om, kind="psd", tol=1e-12, rhs_chunk=5)
+    xs = osv.steady_state(oe.assemble(), oe.d)
+    So = osv.psd(oe.assemble(), xs, cfg["aop"], om, oe.N, oe.d)
+    assert np.abs(S - So).max() <= 1e-9 * np.abs(So).max(), (S, So)
