@@ -177,6 +177,14 @@ heom_status heom_apply(heom_hier *h, int32_t precision, const void *x_dev, void 
 heom_status heom_apply_shifted(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
                                const void *shifts_dev, void *stream);
 
+/* y = B x with B the stationary-state operator: M (even parity) with the
+ * equation of element (0,0) of ADO 0 replaced by the trace condition,
+ * (B x)_{0,00} = sum_i (x_0)_{ii} (the system heom_steady solves with
+ * right-hand side e_0).  Same conventions as heom_apply, one right-hand
+ * side. */
+heom_status heom_apply_steady_operator(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev,
+                                       void *stream);
+
 /* Apply with the top tier split into `n_chunks` column blocks (one launch
  * per block plus one for the lower tiers) so that each block's neighbour
  * reads stay cache-resident.  Same result as heom_apply up to rounding

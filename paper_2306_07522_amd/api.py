@@ -220,6 +220,15 @@ class Hierarchy:
         return y
 
 
+def apply_steady_operator(h, x, y=None, stream=None):
+    """y = B x, the bordered stationary-state operator (see heom.h)."""
+    import torch
+    if y is None:
+        y = torch.empty_like(x)
+    L.check(lib().heom_apply_steady_operator(h.handle, _precision_of(x), _devptr(x), _devptr(y), _stream_ptr(stream)))
+    return y
+
+
 # ----------------------------------------------------------------- solvers
 _PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN}
 _MODE = {"fp64": L.HEOM_SOLVE_FP64, "fp32_ir": L.HEOM_SOLVE_FP32_IR}

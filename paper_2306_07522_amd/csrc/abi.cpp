@@ -181,6 +181,18 @@ heom_status heom_apply_shifted(heom_hier *hw, int32_t precision, const void *x_d
   return launch_apply(*hw->impl, precision, a, (hipStream_t)stream);
 }
 
+heom_status heom_apply_steady_operator(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev,
+                                       void *stream) {
+  if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");
+  if (x_dev == y_dev) return fail(HEOM_ERR_ARG, "apply: x and y must not alias");
+  ApplyArgs a;
+  a.x = x_dev;
+  a.y = y_dev;
+  a.n_rhs = 1;
+  a.border = 1;
+  return launch_apply(*hw->impl, precision, a, (hipStream_t)stream);
+}
+
 heom_status heom_apply_tiled(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
                              const double *shift, int32_t n_chunks, void *stream) {
   if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");

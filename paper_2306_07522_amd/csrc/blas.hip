@@ -123,9 +123,15 @@ __global__ void axpby_kernel(const typename Cplx<TX>::t *__restrict__ x, double 
                              double beta, int64_t total) {
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const auto a = x[idx];
-    auto b = y[idx];
-    b.x = (TY)(alpha * (double)a.x + beta * (double)b.x);
-    b.y = (TY)(alpha * (double)a.y + beta * (double)b.y);
+    typename Cplx<TY>::t b;
+    if (beta == 0.0) {  // y is write-only: it may hold anything, NaN included
+      b.x = (TY)(alpha * (double)a.x);
+      b.y = (TY)(alpha * (double)a.y);
+    } else {
+      b = y[idx];
+      b.x = (TY)(alpha * (double)a.x + beta * (double)b.x);
+      b.y = (TY)(alpha * (double)a.y + beta * (double)b.y);
+    }
     y[idx] = b;
   }
 }

@@ -145,7 +145,10 @@ static heom_status solve_system(const LinearProblem &lp, const heom_solver_opts 
       HEOM_TRY((axpby<double, float>(r64, sc, r32, 0.0, nr, s)));
       HEOM_HIP_CHECK(hipMemsetAsync(d32, 0, sizeof(float2) * nr, s));
       GmresStats inner;
-      HEOM_TRY(gm.solve(r32, d32, o.inner_tol, o.max_iter - st.iterations, true, inner, s));
+      // each correction only needs a few digits: cap its iterations so a
+      // stagnating FP32 solve hands back to the FP64 residual early
+      const int cap = std::min(o.max_iter - st.iterations, std::max(4 * o.restart, 120));
+      HEOM_TRY(gm.solve(r32, d32, o.inner_tol, cap, true, inner, s));
       st.iterations += inner.iterations;
       st.restarts += inner.restarts;
       st.applies += inner.applies;
@@ -230,8 +233,33 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
   if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_ERR_ARG, "bad precision");
   if (save_every < 0 || (save_every > 0 && !traj_dev)) return fail(HEOM_ERR_ARG, "propagate: bad trajectory args");
   Hier &h = *hw->impl;
-  hipStream_t s = (hipStream_t)stream;
+  hipStream_t caller = (hipStream_t)stream;
   HEOM_TRY(ensure_device(h));
+  // Graph capture needs a non-default stream: run on a private stream that
+  // is ordered after, and before, the caller's stream.
+  const bool use_graph = graph_steps > 0 && n_steps >= graph_steps;
+  hipStream_t s = caller;
+  hipStream_t own = nullptr;
+  hipEvent_t ev = nullptr;
+  if (use_graph) {
+    HEOM_HIP_CHECK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    HEOM_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HEOM_HIP_CHECK(hipEventRecord(ev, caller));
+    HEOM_HIP_CHECK(hipStreamWaitEvent(own, ev, 0));
+    s = own;
+  }
+  struct Cleanup {
+    hipStream_t own, caller;
+    hipEvent_t ev;
+    ~Cleanup() {
+      if (own) {
+        (void)hipEventRecord(ev, own);
+        (void)hipStreamWaitEvent(caller, ev, 0);
+        (void)hipStreamDestroy(own);
+        (void)hipEventDestroy(ev);
+      }
+    }
+  } cleanup{own, caller, ev};
   const int64_t n = h.N * (int64_t)h.d * h.d;
   const size_t w = precision == HEOM_FP64 ? 16 : 8;
   WsArena arena(ws, ws_bytes);
@@ -263,7 +291,7 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
     return HEOM_OK;
   };
   int64_t done = 0;
-  if (graph_steps > 0 && n_steps >= graph_steps) {
+  if (use_graph) {
     if (save_every > 0 && graph_steps % save_every != 0)
       return fail(HEOM_ERR_ARG, "propagate: graph_steps must be a multiple of save_every");
     hipGraph_t graph = nullptr;

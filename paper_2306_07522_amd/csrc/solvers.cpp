@@ -11,6 +11,8 @@
 // that share every apply launch ([n][R] layout).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 
@@ -125,6 +127,10 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
       all = all && done[r];
     }
     st.residual = worst;
+    static const bool verbose = std::getenv("HEOMX_VERBOSE") != nullptr;
+    if (verbose)
+      std::fprintf(stderr, "heomx gmres<%s>: cycle %d iterations %d true residual %.3e (R=%d)\n",
+                   sizeof(T) == 8 ? "fp64" : "fp32", cycle, iters, worst, R);
     if (all) {
       st.converged = true;
       break;
