@@ -25,6 +25,19 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic per apply measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
+# Valid only for the apply source it was measured on: reported as null otherwise.
+MEASURED_TRAFFIC = {
+    ("fp64", "untiled"): {"apply_sha256_prefix": "b4282ebb32f23ee1", "bytes": 7_589_248_000},
+}
+
+
+def _apply_source_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2306_07522_amd", "csrc", "apply.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -124,6 +137,8 @@ def main():
     ms_step = r["wall"] * 1e3 / args.steps
     value = r["bytes"] / (ms_step * 1e-3) / 1e9
     achieved = r["bytes"] / (r["avg_kernel_ms"] * 1e-3) / 1e9
+    rec = MEASURED_TRAFFIC.get((args.precision, "untiled" if args.tiled < 0 else "tiled"))
+    traffic = rec["bytes"] if rec and rec["apply_sha256_prefix"] == _apply_source_sha() else None
     out = {
         "metric": "HEOM matvec GB/s; solve s @1e-8 resid, plain vs NN-preconditioned",
         "value": round(value, 2),
@@ -141,7 +156,7 @@ def main():
                    "n_ado": h.N, "d": h.d, "n_edges": h.info.n_edges, "precision": args.precision,
                    "apply": "untiled" if args.tiled < 0 else f"tiled({args.tiled})"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "kernel_ms": {"avg": round(r["avg_kernel_ms"], 4), "median": round(r["median_kernel_ms"], 4)},
         "bytes_per_step": r["bytes"],
     }
