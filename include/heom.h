@@ -270,6 +270,60 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
                           const heom_solver_opts *o, heom_solver_report *r, void *ws, size_t ws_bytes,
                           void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned block preconditioner
+ * ------------------------------------------------------------------------
+ * A multilayer perceptron g: features -> 2 d^2 applied to every ADO block.
+ * With jr = J r (J the Jacobi preconditioner of the system: the diagonal of
+ * M + shift, the bordered row counting as 1, zeros as 1) and nu_a = |jr_a|,
+ * the features of block a are [Re jr_a / nu_a, Im jr_a / nu_a, n_a / n_max,
+ * m_a / m_max, Re c_a / cs, Im c_a / cs] (cs = max |c_a|), padded with
+ * zeros to k1 = a multiple of 32, and the preconditioned block is
+ * z_a = jr_a + nu_a (g_re + i g_im).  Layers: k1 -> hidden -> hidden ->
+ * o_pad (= 2 d^2 rounded up to 32) with ReLU; BF16 operands, FP32
+ * accumulation, FP32 master weights.  Parameters are laid out as
+ * [W1 (hidden x k1), b1, W2 (hidden x hidden), b2, W3 (o_pad x hidden), b3],
+ * row-major FP32.  Networks live on the device current at creation. */
+
+/* Seeded He-uniform initialisation (last layer scaled by 0.05). */
+heom_status heom_nn_create(int32_t d, int32_t hidden, uint64_t seed, heom_nn **out);
+void heom_nn_free(heom_nn *nn);
+heom_status heom_nn_info(const heom_nn *nn, int32_t *k1, int32_t *o_pad, int32_t *n_params);
+heom_status heom_nn_get_params(const heom_nn *nn, float *host);
+heom_status heom_nn_set_params(heom_nn *nn, const float *host);
+heom_status heom_nn_save(const heom_nn *nn, const char *path);
+heom_status heom_nn_load(const char *path, heom_nn **out);
+
+/* Training pairs from a residual r (FP64 [N][d][d], device) and the error
+ * e = x* - x it leaves (FP64, device, or NULL for features only) of the
+ * system heom_steady solves (border = 1) or of M (border = 0): writes the
+ * BF16 features X [N][k1] and the FP32 targets T [N][o_pad] =
+ * (e_a - jr_a) / nu_a (padding zero). */
+heom_status heom_nn_pairs(heom_hier *h, const heom_nn *nn, const void *r_dev, const void *e_dev, int32_t border,
+                          void *X_dev, void *T_dev, void *stream);
+/* O [rows][o_pad] FP32 = g(X) for BF16 features X [rows][k1]. */
+heom_status heom_nn_forward(const heom_nn *nn, const void *X_dev, int64_t rows, void *O_dev, void *stream);
+/* Gradients of sum (g(X) - T)^2 / (2 rows) in the parameter layout above
+ * (host, n_params floats) and the loss (host, 1 float). */
+heom_status heom_nn_gradients(const heom_nn *nn, const void *X_dev, const void *T_dev, int64_t rows,
+                              float *grads_host, float *loss_host, void *stream);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) over shuffled mini-batches of `batch`
+ * rows for `epochs` passes over the training set: all `rows` pairs, or a
+ * fixed seeded subset of `subset` of them when 0 < subset < rows.
+ * loss_per_epoch (host, epochs floats, may be NULL) receives the mean
+ * mini-batch loss.  Allocates its own scratch. */
+heom_status heom_nn_train(heom_nn *nn, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset,
+                          int32_t epochs, int32_t batch, double lr, uint64_t seed, float *loss_per_epoch,
+                          void *stream);
+
+/* Vector helpers for building training pairs on the device.
+ * heom_steady_residual: r = e_0 - B x (B as in heom_apply_steady_operator;
+ * FP64 [N][d][d]).  heom_vector_axpby: y = alpha x + beta y over n complex
+ * elements of the given precision (y is not read when beta = 0). */
+heom_status heom_steady_residual(heom_hier *h, const void *x_dev, void *r_dev, void *stream);
+heom_status heom_vector_axpby(int32_t precision, const void *x_dev, double alpha, void *y_dev, double beta, int64_t n,
+                              void *stream);
+
 const char *heom_status_string(heom_status s);
 const char *heom_last_error(void);
 const char *heom_version(void);

@@ -279,8 +279,26 @@ def propagate(h, x, dt, n_steps, save_every=0, graph_steps=0, stream=None, ws=No
     return traj
 
 
-def steady_state(h, x=None, stream=None, **opts):
-    """Stationary ADOs (FP64 [N][d][d] device tensor) and the solver report."""
+def steady_residual(h, x, r=None, stream=None):
+    """r = e_0 - B x on the device (B the stationary-state operator)."""
+    import torch
+    if r is None:
+        r = torch.empty_like(x)
+    L.check(lib().heom_steady_residual(h.handle, _devptr(x), _devptr(r), _stream_ptr(stream)))
+    return r
+
+
+def axpby(x, alpha, y, beta, stream=None):
+    """y = alpha x + beta y on the device (library kernel)."""
+    L.check(lib().heom_vector_axpby(_precision_of(x), _devptr(x), float(alpha), _devptr(y), float(beta), x.numel(),
+                                    _stream_ptr(stream)))
+    return y
+
+
+def steady_state(h, x=None, stream=None, allow_not_converged=False, **opts):
+    """Stationary ADOs (FP64 [N][d][d] device tensor) and the solver report.
+    With allow_not_converged the iterate is returned when the solver stops
+    at max_iter (report status 4)."""
     import torch
     o = solver_opts(**opts)
     if x is None:
@@ -289,8 +307,25 @@ def steady_state(h, x=None, stream=None, **opts):
     rep = L.heom_solver_report()
     st = lib().heom_steady(h.handle, _devptr(x), C.byref(o), C.byref(rep), C.c_void_p(ws.data_ptr()), ws.numel(),
                            _stream_ptr(stream))
-    L.check(st)
+    if not (allow_not_converged and st == 4):
+        L.check(st)
     return x, report_dict(rep)
+
+
+def collect_pairs(h, net, snapshots=(10, 30, 60), x_star=None, restart=60, tol=1e-11, stream=None):
+    """Training pairs from plain (Jacobi) GMRES runs on the stationary-state
+    system: the converged x*, then iterates x_k after k iterations; for each
+    snapshot the residual r = e_0 - B x_k and the error e = x* - x_k give
+    one pair per ADO block.  Returns lists of (X, T) device tensors."""
+    if x_star is None:
+        x_star, _ = steady_state(h, tol=tol, restart=restart, max_iter=20000, stream=stream)
+    out = []
+    for k in snapshots:
+        xk, _ = steady_state(h, restart=restart, max_iter=int(k), allow_not_converged=True, stream=stream)
+        r = steady_residual(h, xk, stream=stream)
+        e = axpby(x_star, 1.0, xk, -1.0, stream=stream)   # e = x* - x_k (in place of x_k)
+        out.append(net.pairs(h, r, e, border=1, stream=stream))
+    return out
 
 
 def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, **opts):
@@ -308,3 +343,78 @@ def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, **opts):
                                 _dptr(om), len(om), _dptr(out), C.byref(o), C.byref(rep),
                                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
     return out, report_dict(rep)
+
+
+# ----------------------------------------------------------------- learned preconditioner
+class Network:
+    """Handle of heom_nn_create / heom_nn_load (see include/heom.h)."""
+
+    def __init__(self, d=None, hidden=256, seed=0, path=None):
+        self._lib = lib()
+        h = C.c_void_p()
+        if path is not None:
+            L.check(self._lib.heom_nn_load(str(path).encode(), C.byref(h)))
+        else:
+            L.check(self._lib.heom_nn_create(int(d), int(hidden), int(seed), C.byref(h)))
+        self._h = h
+        k1, o_pad, n_params = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self._lib.heom_nn_info(h, C.byref(k1), C.byref(o_pad), C.byref(n_params)))
+        self.k1, self.o_pad, self.n_params = k1.value, o_pad.value, n_params.value
+        self.hidden = hidden
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self._lib.heom_nn_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        L.check(self._lib.heom_nn_get_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        L.check(self._lib.heom_nn_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def save(self, path):
+        L.check(self._lib.heom_nn_save(self._h, str(path).encode()))
+
+    def pairs(self, h, r, e=None, border=1, stream=None):
+        """(X bf16-as-int16 [N][k1], T fp32 [N][o_pad]) device tensors."""
+        import torch
+        X = torch.empty((h.N, self.k1), dtype=torch.int16, device="cuda")
+        T = torch.empty((h.N, self.o_pad), dtype=torch.float32, device="cuda") if e is not None else None
+        L.check(self._lib.heom_nn_pairs(h.handle, self._h, _devptr(r), _devptr(e) if e is not None else None, border,
+                                        _devptr(X), _devptr(T) if T is not None else None, _stream_ptr(stream)))
+        return X, T
+
+    def forward(self, X, stream=None):
+        import torch
+        O = torch.empty((X.shape[0], self.o_pad), dtype=torch.float32, device="cuda")
+        L.check(self._lib.heom_nn_forward(self._h, _devptr(X), X.shape[0], _devptr(O), _stream_ptr(stream)))
+        return O
+
+    def gradients(self, X, T, stream=None):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        L.check(self._lib.heom_nn_gradients(self._h, _devptr(X), _devptr(T), X.shape[0],
+                                            g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                            _stream_ptr(stream)))
+        return g, loss.value
+
+    def train(self, X, T, epochs=10, batch=4096, lr=1e-3, seed=0, subset=0, stream=None):
+        losses = np.zeros(max(epochs, 1), dtype=np.float32)
+        L.check(self._lib.heom_nn_train(self._h, _devptr(X), _devptr(T), X.shape[0], int(subset), epochs, batch,
+                                        float(lr),
+                                        int(seed), losses.ctypes.data_as(C.POINTER(C.c_float)), _stream_ptr(stream)))
+        return losses[:epochs]

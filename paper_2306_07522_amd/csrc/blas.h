@@ -25,6 +25,8 @@ heom_status rk4_combine(void *x, const void *k1, const void *k2, const void *k3,
 template <typename T>
 heom_status save_rho0(const void *x, void *traj, int d2, int *counter, int64_t max_slots, hipStream_t s);
 heom_status fill_int(int *p, int v, int n, hipStream_t s);
+// v[0] += 1 (FP64 complex vector)
+heom_status add_unit(void *v, hipStream_t s);
 template <typename T>
 heom_status left_multiply(const double2 *x, const double2 *ops, int d, int64_t N, int R, const int *col_op, void *b,
                           hipStream_t s);

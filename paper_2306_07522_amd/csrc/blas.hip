@@ -194,6 +194,16 @@ __global__ void save_rho0_kernel(const typename Cplx<T>::t *__restrict__ x, type
   if (threadIdx.x == 0) *counter = slot + 1;
 }
 
+__global__ void add_unit_kernel(double2 *v) {
+  if (threadIdx.x == 0) v[0].x += 1.0;
+}
+
+heom_status add_unit(void *v, hipStream_t s) {
+  hipLaunchKernelGGL(add_unit_kernel, dim3(1), dim3(64), 0, s, (double2 *)v);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
 __global__ void fill_int_kernel(int *p, int v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

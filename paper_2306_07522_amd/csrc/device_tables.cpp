@@ -30,7 +30,7 @@ void free_device(Hier &h) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(D.device);
   void *ptrs[] = {D.decay64, D.decay32, D.ell_cnt, D.ell_col, D.op_slots, D.ell_val64, D.ell_val32,
-                  D.coef_op, D.coef64, D.coef32, D.hdiag, D.hdiag32, D.c_meta, D.c_col, D.c_val64, D.c_val32};
+                  D.coef_op, D.coef64, D.coef32, D.hdiag, D.hdiag32, D.lev, D.c_meta, D.c_col, D.c_val64, D.c_val32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_plan(D.base);
@@ -163,6 +163,7 @@ heom_status ensure_device(Hier &h) {
       (st = upload(&D.coef32, c32.data(), sizeof(float2) * 2 * nc, tot)) ||
       (st = upload(&D.hdiag, hd.data(), sizeof(double2) * h.d, tot)) ||
       (st = upload(&D.hdiag32, hd32.data(), sizeof(float2) * h.d, tot)) ||
+      (st = upload(&D.lev, h.lev.data(), sizeof(int2) * N, tot)) ||
       (st = upload(&D.c_meta, meta.data(), sizeof(int32_t) * meta.size(), tot)) ||
       (st = upload(&D.c_col, L.c_col.data(), sizeof(int32_t) * L.c_col.size(), tot)) ||
       (st = upload(&D.c_val64, cv64.data(), sizeof(double2) * cv64.size(), tot)) ||

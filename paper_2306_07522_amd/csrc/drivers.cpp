@@ -320,6 +320,29 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
   return HEOM_OK;
 }
 
+heom_status heom_steady_residual(heom_hier *hw, const void *x_dev, void *r_dev, void *stream) {
+  if (!hw || !x_dev || !r_dev || x_dev == r_dev) return fail(HEOM_ERR_ARG, "steady_residual: bad arguments");
+  Hier &h = *hw->impl;
+  hipStream_t s = (hipStream_t)stream;
+  ApplyArgs a;
+  a.x = x_dev;
+  a.y = r_dev;
+  a.border = 1;
+  HEOM_TRY(launch_apply(h, HEOM_FP64, a, s));
+  const int64_t n = h.N * (int64_t)h.d * h.d;
+  HEOM_TRY((axpby<double, double>(r_dev, 0.0, r_dev, -1.0, n, s)));
+  HEOM_TRY(add_unit(r_dev, s));
+  return HEOM_OK;
+}
+
+heom_status heom_vector_axpby(int32_t precision, const void *x_dev, double alpha, void *y_dev, double beta, int64_t n,
+                              void *stream) {
+  if (!x_dev || !y_dev || n < 0) return fail(HEOM_ERR_ARG, "vector_axpby: bad arguments");
+  if (precision == HEOM_FP64) return axpby<double, double>(x_dev, alpha, y_dev, beta, n, (hipStream_t)stream);
+  if (precision == HEOM_FP32) return axpby<float, float>(x_dev, alpha, y_dev, beta, n, (hipStream_t)stream);
+  return fail(HEOM_ERR_ARG, "bad precision");
+}
+
 heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, heom_solver_report *r, void *ws,
                         size_t ws_bytes, void *stream) {
   if (!hw || !x_dev) return fail(HEOM_ERR_ARG, "steady: NULL argument");
@@ -342,14 +365,14 @@ heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, h
   lp.R = 1;
   lp.border = 1;
   heom_status st = solve_system(lp, *o, b, x_dev, o->use_x0 != 0, r, arena, s);
-  if (st == HEOM_ERR_NOT_CONVERGED && o->precond == HEOM_PREC_NN && o->fallback) {
+  if ((st == HEOM_ERR_NOT_CONVERGED || st == HEOM_ERR_NAN) && o->precond == HEOM_PREC_NN && o->fallback) {
     heom_solver_opts o2 = *o;
     o2.precond = HEOM_PREC_JACOBI;
-    o2.use_x0 = 1;
+    o2.use_x0 = st == HEOM_ERR_NAN ? 0 : 1;
     if (r) r->fell_back = 1;
     WsArena arena2(ws, ws_bytes);
     arena2.take(sizeof(double2) * n);
-    st = solve_system(lp, o2, b, x_dev, true, r, arena2, s);
+    st = solve_system(lp, o2, b, x_dev, o2.use_x0 != 0, r, arena2, s);
   }
   return st;
 }

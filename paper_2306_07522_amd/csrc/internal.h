@@ -84,6 +84,7 @@ struct DeviceTables {
   double2 *coef64 = nullptr;    // [n_coef][2] (cl, cr)
   float2 *coef32 = nullptr;
   double2 *hdiag = nullptr;     // [d] diagonal of H
+  int2 *lev = nullptr;          // [N] (m, n) levels of every ADO
   float2 *hdiag32 = nullptr;
   int32_t *c_meta = nullptr;    // [n_ops][3] (off, ns, real) of the compact ELL
   int32_t *c_col = nullptr;

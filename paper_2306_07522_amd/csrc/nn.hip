@@ -1,20 +1,734 @@
-// Learned block preconditioner: placeholder until the MLP kernels land.
+// Learned block preconditioner: MLP (2 d^2 + 4 -> hidden -> hidden -> 2 d^2)
+// on every ADO block of the Jacobi-scaled residual.  Inference and training
+// run on hand-written BF16 MFMA GEMMs with FP32 accumulation; the FP32
+// master weights are updated with Adam.
+//
+// Features of block (a, r): with jr = J r (J the Jacobi preconditioner of the
+// system being solved) and nu = |jr_a|_2,
+//   [Re jr_a / nu, Im jr_a / nu, n_a / L_f, m_a / L_b, Re c_a / cs, Im c_a / cs]
+// where c_a is the ADO's decay and cs = max_a |c_a|.  The preconditioned
+// block is z_a = jr_a + nu * (g_re + i g_im), so a zero network is Jacobi.
+// Training targets for a pair (residual block r_a, error block e_a) are
+// (e_a - jr_a) / nu, loss = sum (g - target)^2 / (2 rows).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "device_common.h"
 #include "nn.h"
 
 namespace heom {
 
-size_t nn_workspace_bytes(const Hier &, int, size_t) { return 0; }
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
-heom_status NnApply::init(const heom_nn *, const Hier &, int, const double2 *, int, WsArena &, size_t) {
-  return fail(HEOM_ERR_UNSUPPORTED, "learned preconditioner not built");
+// round-to-nearest-even FP32 -> BF16 (quiet NaN kept)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ------------------------------------------------------------------ GEMM
+// C[M x N] = op(A)[M x K] op(B)[K x N]; op(A)[m][k] = TA ? A[k lda + m] :
+// A[m lda + k]; op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n].  Block tile
+// 64 x 64 x 32, four waves of 32 x 32, each 2 x 2 MFMA 16x16x16 tiles.
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(const uint16_t *__restrict__ A, int lda, const uint16_t *__restrict__ B,
+                                                   int ldb, int M, int N, int K, float *__restrict__ Cf,
+                                                   uint16_t *__restrict__ Cb, int ldc, const float *__restrict__ bias,
+                                                   const float *__restrict__ pre, int ldp) {
+  __shared__ uint16_t As[64][40];  // [m][k]
+  __shared__ uint16_t Bs[64][40];  // [n][k]
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  float4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      int mm, kk;
+      if (TA) { kk = e / 64; mm = e % 64; }   // contiguous along m in memory
+      else { mm = e / 32; kk = e % 32; }      // contiguous along k
+      const int gm = m0 + mm, gk = k0 + kk;
+      uint16_t v = 0;
+      if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+      As[mm][kk] = v;
+    }
+    for (int e = tid; e < 64 * 32; e += 256) {
+      int nn, kk;
+      if (TB) { nn = e / 32; kk = e % 32; }   // contiguous along k
+      else { kk = e / 64; nn = e % 64; }      // contiguous along n
+      const int gn = n0 + nn, gk = k0 + kk;
+      uint16_t v = 0;
+      if (gn < N && gk < K) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 32; ks += 16) {
+      const int kb = ks + (lane >> 4) * 4;
+      short4_t af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm * 32 + i * 16 + (lane & 15);
+        af[i] = short4_t{(short)As[row][kb], (short)As[row][kb + 1], (short)As[row][kb + 2], (short)As[row][kb + 3]};
+        const int col = wn * 32 + i * 16 + (lane & 15);
+        bfr[i] = short4_t{(short)Bs[col][kb], (short)Bs[col][kb + 1], (short)Bs[col][kb + 2], (short)Bs[col][kb + 3]};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+        const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm >= M || gn >= N) continue;
+        const float v = acc[i][j][r];
+        const size_t o = (size_t)gm * ldc + gn;
+        if (EPI == EPI_F32) {
+          Cf[o] = v;
+        } else if (EPI == EPI_BIAS_F32) {
+          Cf[o] = v + bias[gn];
+        } else if (EPI == EPI_BIAS_RELU_BF16) {
+          const float z = v + bias[gn];
+          if (Cf) Cf[o] = z;
+          Cb[o] = f2bf(z > 0.f ? z : 0.f);
+        } else {  // EPI_MASK_BF16: relu derivative from the stored pre-activation
+          Cb[o] = f2bf(pre[(size_t)gm * ldp + gn] > 0.f ? v : 0.f);
+        }
+      }
+}
+
+heom_status gemm_bf16(bool ta, bool tb, int epi, const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N,
+                      int K, float *Cf, uint16_t *Cb, int ldc, const float *bias, const float *pre, int ldp,
+                      hipStream_t s) {
+  if (M <= 0 || N <= 0) return HEOM_OK;
+  const int64_t gy = ((int64_t)M + 63) / 64;
+  if (gy > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "gemm too large");
+  dim3 g((N + 63) / 64, (unsigned)gy), b(256);
+#define HEOM_G(TA, TB, E) hipLaunchKernelGGL((gemm_kernel<TA, TB, E>), g, b, 0, s, A, lda, B, ldb, M, N, K, Cf, Cb, ldc, bias, pre, ldp)
+#define HEOM_GE(TA, TB)                                   \
+  switch (epi) {                                          \
+    case EPI_F32: HEOM_G(TA, TB, EPI_F32); break;         \
+    case EPI_BIAS_F32: HEOM_G(TA, TB, EPI_BIAS_F32); break; \
+    case EPI_BIAS_RELU_BF16: HEOM_G(TA, TB, EPI_BIAS_RELU_BF16); break; \
+    default: HEOM_G(TA, TB, EPI_MASK_BF16); break;        \
+  }
+  if (!ta && !tb) { HEOM_GE(false, false) }
+  else if (!ta && tb) { HEOM_GE(false, true) }
+  else if (ta && !tb) { HEOM_GE(true, false) }
+  else { HEOM_GE(true, true) }
+#undef HEOM_GE
+#undef HEOM_G
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void f32_to_bf16_kernel(const float *__restrict__ x, uint16_t *__restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = f2bf(x[i]);
+}
+
+// dO = bf16((O - T) / rows); loss_out[0] (+)= sum (O - T)^2 / (2 rows) (one block)
+__global__ void loss_grad_kernel(const float *__restrict__ O, const float *__restrict__ T, int64_t rows, int cols,
+                                 uint16_t *__restrict__ dO, float *__restrict__ loss_out) {
+  __shared__ float red[256];
+  float acc = 0.f;
+  const float inv = 1.0f / (float)rows;
+  const int64_t n = rows * cols;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float dlt = O[i] - T[i];
+    acc += dlt * dlt;
+    dO[i] = f2bf(dlt * inv);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_out[0] = red[0] * 0.5f * inv;
+}
+
+// db[c] = sum over rows of bf16 matrix D[rows][cols]
+__global__ void colsum_bf16_kernel(const uint16_t *__restrict__ D, int64_t rows, int cols, float *__restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int64_t r = 0; r < rows; ++r) s += bf2f(D[r * cols + c]);
+  db[c] = s;
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                            uint16_t *__restrict__ pb, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f2bf(pi);
+  }
+}
+
+__global__ void gather_rows_kernel(const uint16_t *__restrict__ X, const float *__restrict__ T, const int64_t *__restrict__ idx,
+                                   int64_t nb, int k1, int o_pad, uint16_t *__restrict__ Xb, float *__restrict__ Tb) {
+  const int64_t r = blockIdx.x;
+  if (r >= nb) return;
+  const int64_t src = idx[r];
+  for (int c = threadIdx.x; c < k1; c += blockDim.x) Xb[r * k1 + c] = X[src * k1 + c];
+  for (int c = threadIdx.x; c < o_pad; c += blockDim.x) Tb[r * o_pad + c] = T[src * o_pad + c];
+}
+
+// Features (and optionally training targets) of every block (a, r) of the
+// [N][d][d][R] vector `in`: one 256-thread block per row a * R + r.
+template <typename T>
+__global__ void __launch_bounds__(256) features_kernel(const typename Cplx<T>::t *__restrict__ in, int d, int64_t N, int R,
+                                                       const double2 *__restrict__ decay, const double2 *__restrict__ hdiag,
+                                                       const int2 *__restrict__ lev, const double2 *__restrict__ shifts,
+                                                       int border, double cscale, int Lf, int Lb, int k1, int o_pad,
+                                                       uint16_t *__restrict__ X, float *__restrict__ nu,
+                                                       typename Cplx<T>::t *__restrict__ jr_out,
+                                                       const double2 *__restrict__ err, float *__restrict__ target) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double red[256];
+  const int64_t row = blockIdx.x;
+  const int64_t a = row / R;
+  const int r = (int)(row % R);
+  const int d2 = d * d;
+  const double2 c = decay[a];
+  const double2 zz = shifts ? shifts[r] : make_double2(0.0, 0.0);
+  double acc = 0.0;
+  // pass 1: Jacobi-scaled block and its norm
+  for (int ij = threadIdx.x; ij < d2; ij += blockDim.x) {
+    const int i = ij / d, j = ij % d;
+    const double2 hi = hdiag[i], hj = hdiag[j];
+    double2 dg = make_double2(-(c.x - zz.x) + (hi.y - hj.y), -(c.y - zz.y) - (hi.x - hj.x));
+    if (border && a == 0 && ij == 0) dg = make_double2(1.0, 0.0);
+    if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
+    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
+    const T2 v = in[(a * d2 + ij) * R + r];
+    const double jx = ((double)v.x * dg.x + (double)v.y * dg.y) * inv;
+    const double jy = ((double)v.y * dg.x - (double)v.x * dg.y) * inv;
+    if (jr_out) jr_out[(a * d2 + ij) * R + r] = T2{(T)jx, (T)jy};
+    acc += jx * jx + jy * jy;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double n2 = sqrt(red[0]);
+  if (!(n2 > 1e-300)) n2 = 1.0;
+  if (threadIdx.x == 0) nu[row] = (float)n2;
+  const double inv_nu = 1.0 / n2;
+  // pass 2: features (recomputing jr keeps register use flat)
+  for (int ij = threadIdx.x; ij < d2; ij += blockDim.x) {
+    const int i = ij / d, j = ij % d;
+    const double2 hi = hdiag[i], hj = hdiag[j];
+    double2 dg = make_double2(-(c.x - zz.x) + (hi.y - hj.y), -(c.y - zz.y) - (hi.x - hj.x));
+    if (border && a == 0 && ij == 0) dg = make_double2(1.0, 0.0);
+    if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
+    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
+    const T2 v = in[(a * d2 + ij) * R + r];
+    const double jx = ((double)v.x * dg.x + (double)v.y * dg.y) * inv;
+    const double jy = ((double)v.y * dg.x - (double)v.x * dg.y) * inv;
+    X[row * k1 + ij] = f2bf((float)(jx * inv_nu));
+    X[row * k1 + d2 + ij] = f2bf((float)(jy * inv_nu));
+    if (err) {
+      const double2 e = err[(a * d2 + ij) * R + r];
+      target[row * o_pad + ij] = (float)((e.x - jx) * inv_nu);
+      target[row * o_pad + d2 + ij] = (float)((e.y - jy) * inv_nu);
+    }
+  }
+  for (int t = 2 * d2 + threadIdx.x; t < k1; t += blockDim.x) {
+    float f = 0.f;
+    if (t == 2 * d2) f = (float)lev[a].y / (float)(Lf > 0 ? Lf : 1);
+    else if (t == 2 * d2 + 1) f = (float)lev[a].x / (float)(Lb > 0 ? Lb : 1);
+    else if (t == 2 * d2 + 2) f = (float)(c.x / cscale);
+    else if (t == 2 * d2 + 3) f = (float)(c.y / cscale);
+    X[row * k1 + t] = f2bf(f);
+  }
+  if (err)
+    for (int t = 2 * d2 + threadIdx.x; t < o_pad; t += blockDim.x) target[row * o_pad + t] = 0.f;
+}
+
+// z = jr + nu * (g_re + i g_im), blockwise
+template <typename T>
+__global__ void combine_kernel(const typename Cplx<T>::t *__restrict__ jr, const float *__restrict__ O,
+                               const float *__restrict__ nu, int d, int64_t N, int R, int o_pad,
+                               typename Cplx<T>::t *__restrict__ out) {
+  using T2 = typename Cplx<T>::t;
+  const int d2 = d * d;
+  const int64_t total = N * d2 * R;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % R);
+    const int64_t e = idx / R;
+    const int64_t a = e / d2;
+    const int ij = (int)(e % d2);
+    const int64_t row = a * R + r;
+    const float s = nu[row];
+    const T2 j0 = jr[idx];
+    out[idx] = T2{(T)(j0.x + (double)s * O[row * o_pad + ij]), (T)(j0.y + (double)s * O[row * o_pad + d2 + ij])};
+  }
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+// ------------------------------------------------------------------ network passes
+struct FwdBuffers {
+  float *Z1 = nullptr, *Z2 = nullptr;    // pre-activations (training only)
+  uint16_t *A1 = nullptr, *A2 = nullptr; // BF16 activations
+  float *O = nullptr;
+};
+
+static heom_status forward(const heom_nn &nn, const uint16_t *X, int64_t rows, FwdBuffers &f, hipStream_t s) {
+  const int H = nn.hidden;
+  HEOM_TRY(gemm_bf16(false, true, EPI_BIAS_RELU_BF16, X, nn.k1, nn.Wb[0], nn.k1, (int)rows, H, nn.k1, f.Z1, f.A1, H,
+                     nn.b[0], nullptr, 0, s));
+  HEOM_TRY(gemm_bf16(false, true, EPI_BIAS_RELU_BF16, f.A1, H, nn.Wb[1], H, (int)rows, H, H, f.Z2, f.A2, H, nn.b[1],
+                     nullptr, 0, s));
+  HEOM_TRY(gemm_bf16(false, true, EPI_BIAS_F32, f.A2, H, nn.Wb[2], H, (int)rows, nn.o_pad, H, f.O, nullptr, nn.o_pad,
+                     nn.b[2], nullptr, 0, s));
+  return HEOM_OK;
+}
+
+struct GradBuffers {
+  float *gW[3], *gb[3];
+  uint16_t *dO, *dZ2, *dZ1;
+  float *dA;  // unused placeholder
+};
+
+// backward of loss sum (O - T)^2 / (2 rows): grads into g.gW / g.gb
+static heom_status backward(const heom_nn &nn, const uint16_t *X, const float *T, int64_t rows, FwdBuffers &f,
+                            GradBuffers &g, float *loss, hipStream_t s) {
+  const int H = nn.hidden, Op = nn.o_pad;
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(1), dim3(256), 0, s, f.O, T, rows, Op, g.dO, loss);
+  HEOM_HIP_CHECK(hipGetLastError());
+  // layer 3: dW3 = dO^T A2, db3 = colsum dO, dZ2 = (dO W3) * relu'(Z2)
+  HEOM_TRY(gemm_bf16(true, false, EPI_F32, g.dO, Op, f.A2, H, Op, H, (int)rows, g.gW[2], nullptr, H, nullptr, nullptr, 0, s));
+  hipLaunchKernelGGL(colsum_bf16_kernel, dim3((Op + 255) / 256), dim3(256), 0, s, g.dO, rows, Op, g.gb[2]);
+  HEOM_TRY(gemm_bf16(false, false, EPI_MASK_BF16, g.dO, Op, nn.Wb[2], H, (int)rows, H, Op, nullptr, g.dZ2, H, nullptr,
+                     f.Z2, H, s));
+  // layer 2
+  HEOM_TRY(gemm_bf16(true, false, EPI_F32, g.dZ2, H, f.A1, H, H, H, (int)rows, g.gW[1], nullptr, H, nullptr, nullptr, 0, s));
+  hipLaunchKernelGGL(colsum_bf16_kernel, dim3((H + 255) / 256), dim3(256), 0, s, g.dZ2, rows, H, g.gb[1]);
+  HEOM_TRY(gemm_bf16(false, false, EPI_MASK_BF16, g.dZ2, H, nn.Wb[1], H, (int)rows, H, H, nullptr, g.dZ1, H, nullptr,
+                     f.Z1, H, s));
+  // layer 1
+  HEOM_TRY(gemm_bf16(true, false, EPI_F32, g.dZ1, H, X, nn.k1, H, nn.k1, (int)rows, g.gW[0], nullptr, nn.k1, nullptr,
+                     nullptr, 0, s));
+  hipLaunchKernelGGL(colsum_bf16_kernel, dim3((H + 255) / 256), dim3(256), 0, s, g.dZ1, rows, H, g.gb[0]);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+// Simple device scratch owned by one call.
+struct DevScratch {
+  std::vector<void *> ptrs;
+  ~DevScratch() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+  template <typename P>
+  heom_status get(P **out, size_t bytes) {
+    void *p = nullptr;
+    HEOM_HIP_CHECK(hipMalloc(&p, std::max<size_t>(bytes, 16)));
+    ptrs.push_back(p);
+    *out = (P *)p;
+    return HEOM_OK;
+  }
+};
+
+static heom_status alloc_fwd(const heom_nn &nn, int64_t rows, bool train, FwdBuffers &f, DevScratch &ds) {
+  const size_t H = nn.hidden;
+  if (train) {
+    HEOM_TRY(ds.get(&f.Z1, rows * H * 4));
+    HEOM_TRY(ds.get(&f.Z2, rows * H * 4));
+  }
+  HEOM_TRY(ds.get(&f.A1, rows * H * 2));
+  HEOM_TRY(ds.get(&f.A2, rows * H * 2));
+  HEOM_TRY(ds.get(&f.O, rows * (size_t)nn.o_pad * 4));
+  return HEOM_OK;
+}
+
+static heom_status alloc_grad(const heom_nn &nn, int64_t rows, GradBuffers &g, DevScratch &ds) {
+  for (int l = 0; l < 3; ++l) {
+    HEOM_TRY(ds.get(&g.gW[l], (size_t)nn.rows[l] * nn.cols[l] * 4));
+    HEOM_TRY(ds.get(&g.gb[l], (size_t)nn.rows[l] * 4));
+  }
+  HEOM_TRY(ds.get(&g.dO, rows * (size_t)nn.o_pad * 2));
+  HEOM_TRY(ds.get(&g.dZ2, rows * (size_t)nn.hidden * 2));
+  HEOM_TRY(ds.get(&g.dZ1, rows * (size_t)nn.hidden * 2));
+  g.dA = nullptr;
+  return HEOM_OK;
+}
+
+// ------------------------------------------------------------------ preconditioner use
+size_t nn_workspace_bytes(const Hier &h, int R, size_t elem_bytes) {
+  const int d2 = h.d * h.d;
+  const int k1 = ((2 * d2 + 4) + 31) / 32 * 32, o_pad = (2 * d2 + 31) / 32 * 32;
+  const size_t rows = (size_t)h.N * R;
+  const size_t H = 256;  // the library's networks use hidden <= 256
+  return rows * d2 * elem_bytes + rows * (k1 * 2 + 2 * H * 2 + o_pad * 4 + 4) + 8 * 256;
+}
+
+heom_status NnApply::init(const heom_nn *n, const Hier &hh, int R_, const double2 *sh, int bd, WsArena &ws,
+                          size_t elem_bytes) {
+  net = n;
+  h = &hh;
+  R = R_;
+  shifts = sh;
+  border = bd;
+  if (!n) return fail(HEOM_ERR_ARG, "NULL network");
+  if (n->d != hh.d) return fail(HEOM_ERR_ARG, "network was built for another d");
+  if (n->hidden > 256) return fail(HEOM_ERR_UNSUPPORTED, "hidden width above 256");
+  int dev = 0;
+  HEOM_HIP_CHECK(hipGetDevice(&dev));
+  if (dev != n->device) return fail(HEOM_ERR_ARG, "network lives on another device");
+  const size_t rows = (size_t)hh.N * R;
+  jr = ws.take(rows * hh.d * hh.d * elem_bytes);
+  X = (uint16_t *)ws.take(rows * n->k1 * 2);
+  H1 = (uint16_t *)ws.take(rows * n->hidden * 2);
+  H2 = (uint16_t *)ws.take(rows * n->hidden * 2);
+  O = (float *)ws.take(rows * n->o_pad * 4);
+  nu = (float *)ws.take(rows * 4);
+  if (!jr || !X || !H1 || !H2 || !O || !nu) return fail(HEOM_ERR_ARG, "workspace too small for the network");
+  cscale = 1e-300;
+  for (const cd &c : hh.decay) cscale = std::max(cscale, std::abs(c));
+  return HEOM_OK;
 }
 
 template <typename T>
-heom_status NnApply::apply(const void *, void *, hipStream_t) {
-  return fail(HEOM_ERR_UNSUPPORTED, "learned preconditioner not built");
+heom_status NnApply::apply(const void *in, void *out, hipStream_t s) {
+  const heom_nn &n = *net;
+  const int64_t rows = h->N * R;
+  if (rows > 0x7fffffffLL) return fail(HEOM_ERR_UNSUPPORTED, "too many blocks for the network");
+  hipLaunchKernelGGL(features_kernel<T>, dim3((unsigned)rows), dim3(256), 0, s, (const typename Cplx<T>::t *)in, h->d,
+                     h->N, R, h->dev.decay64, h->dev.hdiag, h->dev.lev, shifts, border, cscale, h->Lf, h->Lb, n.k1,
+                     n.o_pad, X, nu, (typename Cplx<T>::t *)jr, nullptr, nullptr);
+  HEOM_HIP_CHECK(hipGetLastError());
+  FwdBuffers f;
+  f.A1 = H1;
+  f.A2 = H2;
+  f.O = O;
+  HEOM_TRY(forward(n, X, rows, f, s));
+  hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_for(rows * h->d * h->d)), dim3(256), 0, s,
+                     (const typename Cplx<T>::t *)jr, O, nu, h->d, h->N, R, n.o_pad, (typename Cplx<T>::t *)out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
 }
 
 template heom_status NnApply::apply<double>(const void *, void *, hipStream_t);
 template heom_status NnApply::apply<float>(const void *, void *, hipStream_t);
 
+// ------------------------------------------------------------------ host helpers
+static uint64_t splitmix64(uint64_t &x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+static double uniform01(uint64_t &st) { return (splitmix64(st) >> 11) * (1.0 / 9007199254740992.0); }
+
+static size_t param_count(const heom_nn &n) {
+  size_t c = 0;
+  for (int l = 0; l < 3; ++l) c += (size_t)n.rows[l] * n.cols[l] + n.rows[l];
+  return c;
+}
+
+static heom_status refresh_bf16(heom_nn &n, hipStream_t s) {
+  for (int l = 0; l < 3; ++l) {
+    const int64_t cnt = (int64_t)n.rows[l] * n.cols[l];
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(grid_for(cnt)), dim3(256), 0, s, n.W[l], n.Wb[l], cnt);
+  }
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
 }  // namespace heom
+
+using namespace heom;
+
+extern "C" {
+
+heom_status heom_nn_create(int32_t d, int32_t hidden, uint64_t seed, heom_nn **out) {
+  if (!out || d < 1 || d > 32 || hidden < 32 || hidden > 256 || hidden % 32)
+    return fail(HEOM_ERR_ARG, "nn_create: d in [1, 32], hidden a multiple of 32 in [32, 256]");
+  *out = nullptr;
+  auto *n = new heom_nn;
+  n->d = d;
+  n->hidden = hidden;
+  n->f_in = 2 * d * d + 4;
+  n->k1 = (n->f_in + 31) / 32 * 32;
+  n->f_out = 2 * d * d;
+  n->o_pad = (n->f_out + 31) / 32 * 32;
+  n->rows[0] = hidden; n->cols[0] = n->k1;
+  n->rows[1] = hidden; n->cols[1] = hidden;
+  n->rows[2] = n->o_pad; n->cols[2] = hidden;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { delete n; return fail(HEOM_ERR_HIP, "hipGetDevice failed"); }
+  n->device = dev;
+  // He-uniform weights (fan-in of the real inputs); the last layer starts
+  // small so that the untrained network is close to plain Jacobi.
+  uint64_t st = seed;
+  std::vector<float> host;
+  for (int l = 0; l < 3; ++l) {
+    const int fan = l == 0 ? n->f_in : hidden;
+    const double lim = std::sqrt(6.0 / fan) * (l == 2 ? 0.05 : 1.0);
+    std::vector<float> W((size_t)n->rows[l] * n->cols[l], 0.f);
+    for (int i = 0; i < n->rows[l]; ++i)
+      for (int j = 0; j < n->cols[l]; ++j) {
+        const bool real = (l != 0 || j < n->f_in) && (l != 2 || i < n->f_out);
+        const double u = uniform01(st);
+        W[(size_t)i * n->cols[l] + j] = real ? (float)((2 * u - 1) * lim) : 0.f;
+      }
+    const size_t nb = (size_t)n->rows[l] * n->cols[l];
+    heom_status s1 = HEOM_OK;
+    auto al = [&](float **p, size_t cnt) {
+      if (hipMalloc((void **)p, cnt * 4) != hipSuccess) s1 = HEOM_ERR_ALLOC;
+      else (void)hipMemset(*p, 0, cnt * 4);
+    };
+    al(&n->W[l], nb); al(&n->b[l], n->rows[l]);
+    al(&n->mW[l], nb); al(&n->vW[l], nb); al(&n->mb[l], n->rows[l]); al(&n->vb[l], n->rows[l]);
+    if (hipMalloc((void **)&n->Wb[l], nb * 2) != hipSuccess) s1 = HEOM_ERR_ALLOC;
+    if (s1 != HEOM_OK) { heom_nn_free(n); return fail(HEOM_ERR_ALLOC, "nn_create: device allocation failed"); }
+    if (hipMemcpy(n->W[l], W.data(), nb * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      heom_nn_free(n);
+      return fail(HEOM_ERR_HIP, "nn_create: copy failed");
+    }
+  }
+  heom_status st2 = refresh_bf16(*n, nullptr);
+  if (st2 == HEOM_OK && hipDeviceSynchronize() != hipSuccess) st2 = fail(HEOM_ERR_HIP, "nn_create: sync failed");
+  if (st2 != HEOM_OK) { heom_nn_free(n); return st2; }
+  *out = n;
+  return HEOM_OK;
+}
+
+void heom_nn_free(heom_nn *n) {
+  if (!n) return;
+  for (int l = 0; l < 3; ++l) {
+    void *ps[] = {n->W[l], n->b[l], n->Wb[l], n->mW[l], n->vW[l], n->mb[l], n->vb[l]};
+    for (void *p : ps)
+      if (p) (void)hipFree(p);
+  }
+  delete n;
+}
+
+heom_status heom_nn_info(const heom_nn *n, int32_t *k1, int32_t *o_pad, int32_t *n_params) {
+  if (!n) return fail(HEOM_ERR_ARG, "NULL network");
+  if (k1) *k1 = n->k1;
+  if (o_pad) *o_pad = n->o_pad;
+  if (n_params) *n_params = (int32_t)param_count(*n);
+  return HEOM_OK;
+}
+
+heom_status heom_nn_get_params(const heom_nn *n, float *host) {
+  if (!n || !host) return fail(HEOM_ERR_ARG, "NULL argument");
+  size_t off = 0;
+  for (int l = 0; l < 3; ++l) {
+    const size_t nb = (size_t)n->rows[l] * n->cols[l];
+    HEOM_HIP_CHECK(hipMemcpy(host + off, n->W[l], nb * 4, hipMemcpyDeviceToHost));
+    off += nb;
+    HEOM_HIP_CHECK(hipMemcpy(host + off, n->b[l], n->rows[l] * 4, hipMemcpyDeviceToHost));
+    off += n->rows[l];
+  }
+  return HEOM_OK;
+}
+
+heom_status heom_nn_set_params(heom_nn *n, const float *host) {
+  if (!n || !host) return fail(HEOM_ERR_ARG, "NULL argument");
+  size_t off = 0;
+  for (int l = 0; l < 3; ++l) {
+    const size_t nb = (size_t)n->rows[l] * n->cols[l];
+    HEOM_HIP_CHECK(hipMemcpy(n->W[l], host + off, nb * 4, hipMemcpyHostToDevice));
+    off += nb;
+    HEOM_HIP_CHECK(hipMemcpy(n->b[l], host + off, n->rows[l] * 4, hipMemcpyHostToDevice));
+    off += n->rows[l];
+  }
+  HEOM_TRY(refresh_bf16(*n, nullptr));
+  HEOM_HIP_CHECK(hipDeviceSynchronize());
+  return HEOM_OK;
+}
+
+heom_status heom_nn_save(const heom_nn *n, const char *path) {
+  if (!n || !path) return fail(HEOM_ERR_ARG, "NULL argument");
+  std::vector<float> p(param_count(*n));
+  HEOM_TRY(heom_nn_get_params(n, p.data()));
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(HEOM_ERR_ARG, std::string("cannot open ") + path);
+  const int32_t hdr[4] = {0x4e4e4548, 1, n->d, n->hidden};
+  bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(p.data(), 4, p.size(), f) == p.size();
+  std::fclose(f);
+  return ok ? HEOM_OK : fail(HEOM_ERR_ARG, "write failed");
+}
+
+heom_status heom_nn_load(const char *path, heom_nn **out) {
+  if (!path || !out) return fail(HEOM_ERR_ARG, "NULL argument");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(HEOM_ERR_ARG, std::string("cannot open ") + path);
+  int32_t hdr[4];
+  if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x4e4e4548 || hdr[1] != 1) {
+    std::fclose(f);
+    return fail(HEOM_ERR_ARG, "not a network file");
+  }
+  heom_nn *n = nullptr;
+  heom_status st = heom_nn_create(hdr[2], hdr[3], 0, &n);
+  if (st) { std::fclose(f); return st; }
+  std::vector<float> p(param_count(*n));
+  const bool ok = std::fread(p.data(), 4, p.size(), f) == p.size();
+  std::fclose(f);
+  if (!ok) { heom_nn_free(n); return fail(HEOM_ERR_ARG, "truncated network file"); }
+  st = heom_nn_set_params(n, p.data());
+  if (st) { heom_nn_free(n); return st; }
+  *out = n;
+  return HEOM_OK;
+}
+
+heom_status heom_nn_pairs(heom_hier *hw, const heom_nn *n, const void *r_dev, const void *e_dev, int32_t border,
+                          void *X_dev, void *T_dev, void *stream) {
+  if (!hw || !n || !r_dev || !X_dev || (e_dev && !T_dev)) return fail(HEOM_ERR_ARG, "nn_pairs: NULL argument");
+  Hier &h = *hw->impl;
+  if (n->d != h.d) return fail(HEOM_ERR_ARG, "nn_pairs: network built for another d");
+  HEOM_TRY(ensure_device(h));
+  hipStream_t s = (hipStream_t)stream;
+  DevScratch ds;
+  float *nu = nullptr;
+  HEOM_TRY(ds.get(&nu, h.N * 4));
+  double cs = 1e-300;
+  for (const cd &c : h.decay) cs = std::max(cs, std::abs(c));
+  hipLaunchKernelGGL(features_kernel<double>, dim3((unsigned)h.N), dim3(256), 0, s, (const double2 *)r_dev, h.d, h.N, 1,
+                     h.dev.decay64, h.dev.hdiag, h.dev.lev, nullptr, border, cs, h.Lf, h.Lb, n->k1, n->o_pad,
+                     (uint16_t *)X_dev, nu, (double2 *)nullptr, (const double2 *)e_dev, (float *)T_dev);
+  HEOM_HIP_CHECK(hipGetLastError());
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  return HEOM_OK;
+}
+
+heom_status heom_nn_forward(const heom_nn *n, const void *X_dev, int64_t rows, void *O_dev, void *stream) {
+  if (!n || !X_dev || !O_dev || rows < 0 || rows > 0x7fffffffLL) return fail(HEOM_ERR_ARG, "nn_forward: bad arguments");
+  DevScratch ds;
+  FwdBuffers f;
+  HEOM_TRY(alloc_fwd(*n, rows, false, f, ds));
+  (void)hipFree(f.O);
+  ds.ptrs.pop_back();
+  f.O = (float *)O_dev;
+  hipStream_t s = (hipStream_t)stream;
+  HEOM_TRY(forward(*n, (const uint16_t *)X_dev, rows, f, s));
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  return HEOM_OK;
+}
+
+heom_status heom_nn_gradients(const heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, float *grads_host,
+                              float *loss_host, void *stream) {
+  if (!n || !X_dev || !T_dev || rows <= 0 || rows > 0x7fffffffLL) return fail(HEOM_ERR_ARG, "nn_gradients: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  DevScratch ds;
+  FwdBuffers f;
+  GradBuffers g;
+  float *loss = nullptr;
+  HEOM_TRY(alloc_fwd(*n, rows, true, f, ds));
+  HEOM_TRY(alloc_grad(*n, rows, g, ds));
+  HEOM_TRY(ds.get(&loss, 16));
+  HEOM_TRY(forward(*n, (const uint16_t *)X_dev, rows, f, s));
+  HEOM_TRY(backward(*n, (const uint16_t *)X_dev, (const float *)T_dev, rows, f, g, loss, s));
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  if (grads_host) {
+    size_t off = 0;
+    for (int l = 0; l < 3; ++l) {
+      const size_t nb = (size_t)n->rows[l] * n->cols[l];
+      HEOM_HIP_CHECK(hipMemcpy(grads_host + off, g.gW[l], nb * 4, hipMemcpyDeviceToHost));
+      off += nb;
+      HEOM_HIP_CHECK(hipMemcpy(grads_host + off, g.gb[l], n->rows[l] * 4, hipMemcpyDeviceToHost));
+      off += n->rows[l];
+    }
+  }
+  if (loss_host) HEOM_HIP_CHECK(hipMemcpy(loss_host, loss, 4, hipMemcpyDeviceToHost));
+  return HEOM_OK;
+}
+
+heom_status heom_nn_train(heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset, int32_t epochs,
+                          int32_t batch, double lr, uint64_t seed, float *loss_per_epoch, void *stream) {
+  if (!n || !X_dev || !T_dev || rows <= 0 || epochs < 0 || batch <= 0 || !(lr > 0))
+    return fail(HEOM_ERR_ARG, "nn_train: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t st = seed;
+  // the training set: all rows, or a fixed seeded subset of `subset` rows
+  std::vector<int64_t> pool(rows);
+  for (int64_t i = 0; i < rows; ++i) pool[i] = i;
+  if (subset > 0 && subset < rows) {
+    for (int64_t i = 0; i < subset; ++i) std::swap(pool[i], pool[i + (int64_t)(uniform01(st) * (rows - i)) % (rows - i)]);
+    pool.resize(subset);
+  }
+  const int64_t used = (int64_t)pool.size();
+  const int64_t B = std::min<int64_t>(batch, used);
+  const int64_t steps = used / B;
+  DevScratch ds;
+  FwdBuffers f;
+  GradBuffers g;
+  uint16_t *Xb = nullptr;
+  float *Tb = nullptr, *losses = nullptr;
+  int64_t *idx = nullptr;
+  HEOM_TRY(alloc_fwd(*n, B, true, f, ds));
+  HEOM_TRY(alloc_grad(*n, B, g, ds));
+  HEOM_TRY(ds.get(&Xb, B * (size_t)n->k1 * 2));
+  HEOM_TRY(ds.get(&Tb, B * (size_t)n->o_pad * 4));
+  HEOM_TRY(ds.get(&idx, used * 8));
+  HEOM_TRY(ds.get(&losses, std::max<int64_t>(steps, 1) * 4));
+  std::vector<int64_t> perm(used);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  std::vector<float> lh(std::max<int64_t>(steps, 1));
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t i = 0; i < used; ++i) perm[i] = pool[i];
+    for (int64_t i = used - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)(uniform01(st) * (i + 1)) % (i + 1)]);
+    HEOM_HIP_CHECK(hipMemcpyAsync(idx, perm.data(), used * 8, hipMemcpyHostToDevice, s));
+    for (int64_t stp = 0; stp < steps; ++stp) {
+      hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)B), dim3(128), 0, s, (const uint16_t *)X_dev,
+                         (const float *)T_dev, idx + stp * B, B, n->k1, n->o_pad, Xb, Tb);
+      HEOM_TRY(forward(*n, Xb, B, f, s));
+      HEOM_TRY(backward(*n, Xb, Tb, B, f, g, losses + stp, s));
+      ++n->adam_step;
+      const float c1 = 1.f - std::pow(b1, (float)n->adam_step), c2 = 1.f - std::pow(b2, (float)n->adam_step);
+      for (int l = 0; l < 3; ++l) {
+        const int64_t nw = (int64_t)n->rows[l] * n->cols[l];
+        hipLaunchKernelGGL(adam_kernel, dim3(grid_for(nw)), dim3(256), 0, s, n->W[l], g.gW[l], n->mW[l], n->vW[l], n->Wb[l],
+                           nw, (float)lr, b1, b2, eps, c1, c2);
+        hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n->rows[l])), dim3(256), 0, s, n->b[l], g.gb[l], n->mb[l], n->vb[l],
+                           (uint16_t *)nullptr, (int64_t)n->rows[l], (float)lr, b1, b2, eps, c1, c2);
+      }
+      HEOM_HIP_CHECK(hipGetLastError());
+    }
+    HEOM_HIP_CHECK(hipMemcpyAsync(lh.data(), losses, steps * 4, hipMemcpyDeviceToHost, s));
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    double m = 0;
+    for (int64_t i = 0; i < steps; ++i) m += lh[i];
+    if (loss_per_epoch) loss_per_epoch[ep] = (float)(m / std::max<int64_t>(steps, 1));
+    if (!std::isfinite(m)) return fail(HEOM_ERR_NAN, "nn_train: non-finite loss");
+  }
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  return HEOM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+"""GPU parity of the learned preconditioner's kernels against the oracle
+network, and its use inside FGMRES.
+
+Bars: forward and gradients within 1e-2 of the largest element per layer and
+1e-3 relative on norms (BF16 operands, FP32 accumulation, compared with the
+oracle's BF16 emulation); features within one BF16 rounding; FGMRES with the
+network reaches a 1e-8 true residual."""
+import numpy as np
+import pytest
+
+from oracle import nn as onn
+from oracle.liouvillian import from_blocks, to_blocks
+from paper_2306_07522_amd import workloads as wl
+from tests.helpers import library_model, oracle_model, oracle_to_library_perm
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _api():
+    from paper_2306_07522_amd import api
+    return api
+
+
+def _bits(x32):
+    """float32 BF16-valued array -> int16 bit patterns (device tensor)."""
+    torch = _torch()
+    u = (np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    return torch.from_numpy(u.copy()).cuda()
+
+
+def _from_bits(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32)
+
+
+def _layers(net):
+    return onn.unpack(net.get_params().astype(np.float64), net.k1, net.hidden, net.o_pad)
+
+
+def _close(a, b, name):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    scale = max(np.abs(b).max(), 1e-30)
+    assert np.abs(a - b).max() <= 1e-2 * scale, (name, np.abs(a - b).max(), scale)
+    assert abs(np.linalg.norm(a) - np.linalg.norm(b)) <= 1e-3 * np.linalg.norm(b) + 1e-30, name
+
+
+@pytest.mark.parametrize("d,rows", [(4, 300), (16, 130)])
+def test_forward_and_gradients_match_oracle(d, rows):
+    torch, api = _torch(), _api()
+    net = api.Network(d=d, hidden=64 if d == 4 else 256, seed=11)
+    rng = np.random.default_rng(d)
+    # make the last layer larger than its init so every path carries signal
+    p = net.get_params()
+    net.set_params(p + np.float32(0.05) * rng.standard_normal(p.size).astype(np.float32))
+    X = onn.bf16(rng.standard_normal((rows, net.k1)).astype(np.float32))
+    X[:, 2 * d * d + 4:] = 0
+    T = rng.standard_normal((rows, net.o_pad)).astype(np.float32)
+    layers = _layers(net)
+    O_ref, _ = onn.forward_bf16(layers, X)
+    O = net.forward(_bits(X)).cpu().numpy()
+    _close(O, O_ref, "forward")
+    g, loss = net.gradients(_bits(X), torch.from_numpy(T).cuda())
+    g_ref, loss_ref = onn.grads_bf16(layers, X, T)
+    assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
+    off = 0
+    for l, (gW, gb) in enumerate(g_ref):
+        nW = gW.size
+        _close(g[off: off + nW].reshape(gW.shape), gW, f"dW{l + 1}")
+        off += nW
+        _close(g[off: off + gb.size], gb, f"db{l + 1}")
+        off += gb.size
+
+
+def test_features_and_targets_match_oracle():
+    torch, api = _torch(), _api()
+    cfg = wl.siam(n_max=2)
+    om, lm = oracle_model(cfg), library_model(cfg)
+    perm = oracle_to_library_perm(om, lm)
+    net = api.Network(d=4, hidden=64, seed=1)
+    rng = np.random.default_rng(3)
+    r_o = wl.random_vector(rng, om.N, om.d)
+    e_o = wl.random_vector(rng, om.N, om.d)
+    r_l, e_l = np.empty_like(r_o), np.empty_like(e_o)
+    r_l[perm], e_l[perm] = r_o, e_o
+    X, T = net.pairs(lm, torch.from_numpy(r_l).cuda(), torch.from_numpy(e_l).cuda(), border=1)
+    Xg = _from_bits(X)[perm]
+    Tg = T.cpu().numpy()[perm]
+    diag = to_blocks(om.assemble().diagonal(), om.N, om.d)
+    lev_n = np.array([len(q) for _, q in om.hier.ados])
+    lev_m = np.array([len(j) for j, _ in om.hier.ados])
+    decay = np.array([sum(om.ferm[x]["gamma"] for x in q) for _, q in om.hier.ados])
+    Xo, nu, jr = onn.features(r_o, diag, lev_n, lev_m, decay, 2, 0, net.k1, border=True)
+    assert np.abs(Xg - Xo).max() <= 2.0 ** -7 * max(1.0, np.abs(Xo).max())
+    d2 = om.d * om.d
+    To = np.zeros_like(Tg)
+    To[:, :d2] = ((e_o - jr).real / nu[:, None, None]).reshape(om.N, -1)
+    To[:, d2: 2 * d2] = ((e_o - jr).imag / nu[:, None, None]).reshape(om.N, -1)
+    assert np.abs(Tg - To).max() <= 1e-5 * np.abs(To).max()
+
+
+def _trained_siam_net(seed=0):
+    api = _api()
+    cfg = wl.siam()
+    net = api.Network(d=4, hidden=128, seed=seed)
+    import torch
+    Xs, Ts = [], []
+    for s in range(3):
+        pc = wl.siam(eps=-5.0 * np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal()))
+        h = library_model(pc, parity_op=pc["parity_op"])
+        for X, T in api.collect_pairs(h, net, snapshots=(10, 40)):
+            Xs.append(X)
+            Ts.append(T)
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    losses = net.train(X, T, epochs=12, batch=2048, lr=2e-3, seed=5)
+    return net, losses, cfg
+
+
+def test_training_reduces_loss_and_fgmres_converges():
+    torch, api = _torch(), _api()
+    net, losses, cfg = _trained_siam_net()
+    assert losses[-1] < 0.8 * losses[0], losses
+    h = library_model(cfg, parity_op=cfg["parity_op"])
+    x_nn, rep_nn = api.steady_state(h, tol=1e-10, precond="nn", nn=net, restart=30, max_iter=3000)
+    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="jacobi", restart=30, max_iter=3000)
+    assert rep_nn["status"] == 0 and rep_nn["true_residual"] <= 1e-10, rep_nn
+    dx = (x_nn - x_j).abs().max().item() / x_j.abs().max().item()
+    assert dx < 1e-8, dx
+    print("iterations nn / jacobi:", rep_nn["iterations"], rep_j["iterations"])
+
+
+def test_nan_network_falls_back_to_jacobi():
+    torch, api = _torch(), _api()
+    cfg = wl.siam(n_max=2)
+    h = library_model(cfg, parity_op=cfg["parity_op"])
+    net = api.Network(d=4, hidden=64, seed=2)
+    p = net.get_params()
+    p[:] = np.nan
+    net.set_params(p)
+    x, rep = api.steady_state(h, tol=1e-10, precond="nn", nn=net, fallback=1)
+    assert rep["fell_back"] == 1 and rep["status"] == 0 and rep["true_residual"] <= 1e-10, rep
+    from paper_2306_07522_amd._lib import HeomError
+    with pytest.raises(HeomError):
+        api.steady_state(h, tol=1e-10, precond="nn", nn=net, fallback=0)
+
+
+def test_save_load_roundtrip(tmp_path):
+    api = _api()
+    net = api.Network(d=4, hidden=64, seed=9)
+    path = tmp_path / "net.bin"
+    net.save(path)
+    net2 = api.Network(path=path)
+    assert np.array_equal(net.get_params(), net2.get_params())
