@@ -223,7 +223,9 @@ typedef struct {
   int32_t max_refine;     /* IR outer steps (default 20)                      */
   int32_t rhs_chunk;      /* spectra: right-hand sides per multi-RHS solve    */
   const heom_nn *nn;      /* learned preconditioner for HEOM_PREC_NN          */
-  int32_t fallback;       /* 1: on NN stagnation/NaN restart with Jacobi      */
+  int32_t fallback;       /* 1: on NN failure restart with Jacobi: NaN, max_iter,
+                             or a restart cycle (FP64) that cuts the true
+                             residual by less than 10%                      */
   int32_t use_x0;         /* 1: x_dev holds the initial guess                 */
 } heom_solver_opts;
 

@@ -111,6 +111,7 @@ static heom_status solve_system(const LinearProblem &lp, const heom_solver_opts 
     HEOM_TRY(gm.init(ws, n, R, o.restart, flex));
     gm.A = make_A<double>(lp, s);
     gm.P = make_P<double>(lp, o, nnp, s);
+    if (flex && o.fallback) gm.stall = 0.9;  // hand over to Jacobi early on stagnation
     if (!x_given) HEOM_HIP_CHECK(hipMemsetAsync(x64, 0, sizeof(double2) * nr, s));
     HEOM_TRY(gm.solve((const double2 *)b64, (double2 *)x64, o.tol, o.max_iter, !x_given, st, s));
   } else {
@@ -369,7 +370,11 @@ heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, h
     heom_solver_opts o2 = *o;
     o2.precond = HEOM_PREC_JACOBI;
     o2.use_x0 = st == HEOM_ERR_NAN ? 0 : 1;
-    if (r) r->fell_back = 1;
+    if (r) {  // iterations, applies and seconds keep accumulating over both attempts
+      r->fell_back = 1;
+      r->status = HEOM_OK;
+      r->true_residual = 0.0;
+    }
     WsArena arena2(ws, ws_bytes);
     arena2.take(sizeof(double2) * n);
     st = solve_system(lp, o2, b, x_dev, o2.use_x0 != 0, r, arena2, s);

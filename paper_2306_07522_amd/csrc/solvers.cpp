@@ -107,6 +107,7 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
   std::vector<int> kcol(R, 0);
   std::vector<char> done(R, 0);
   int iters = 0;
+  double prev_worst = 0.0;
   for (int cycle = 0;; ++cycle) {
     // r = b - A x
     if (x_is_zero && cycle == 0) {
@@ -136,6 +137,8 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
       break;
     }
     if (iters >= max_iter) break;
+    if (stall > 0.0 && cycle >= 1 && worst > stall * prev_worst) break;
+    prev_worst = worst;
     ++st.restarts;
     // V0 = r / beta
     double2 *sc = (double2 *)pin.p;

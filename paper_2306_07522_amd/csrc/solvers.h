@@ -46,6 +46,9 @@ struct Gmres {
   T2 *V = nullptr, *Z = nullptr, *w = nullptr, *t = nullptr;
   double2 *partial = nullptr, *hdev = nullptr, *sdev = nullptr;
   int nchunk = 1;
+  // > 0: give up (not converged) when a restart cycle fails to shrink the
+  // worst true residual below stall * its value one cycle earlier
+  double stall = 0.0;
   PinnedBuf pin;
   std::vector<cd> H, sn, g;
   std::vector<double> cs;

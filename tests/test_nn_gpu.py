@@ -104,35 +104,61 @@ def test_features_and_targets_match_oracle():
     assert np.abs(Tg - To).max() <= 1e-5 * np.abs(To).max()
 
 
-def _trained_siam_net(seed=0):
-    api = _api()
+def test_training_fits_a_learnable_map():
+    """Adam over the hand-written forward/backward kernels fits a fixed
+    linear map of the features (loss falls by 10x)."""
+    torch, api = _torch(), _api()
+    net = api.Network(d=4, hidden=64, seed=4)
+    rng = np.random.default_rng(8)
+    rows = 16384
+    X = onn.bf16(rng.standard_normal((rows, net.k1)).astype(np.float32))
+    X[:, 2 * 16 + 4:] = 0
+    Mfix = rng.standard_normal((net.k1, net.o_pad)).astype(np.float32) / np.sqrt(36.0)
+    T = (X @ Mfix).astype(np.float32)
+    losses = net.train(_bits(X), torch.from_numpy(T).cuda(), epochs=40, batch=1024, lr=3e-3, seed=2)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.1 * losses[0], losses
+
+
+def test_zero_network_reproduces_jacobi_gmres():
+    """z = J r + nu * 0: FGMRES with the network is GMRES with Jacobi."""
+    torch, api = _torch(), _api()
     cfg = wl.siam()
-    net = api.Network(d=4, hidden=128, seed=seed)
-    import torch
+    h = library_model(cfg, parity_op=cfg["parity_op"])
+    net = api.Network(d=4, hidden=64, seed=0)
+    net.set_params(np.zeros(net.n_params, dtype=np.float32))
+    x_n, rep_n = api.steady_state(h, tol=1e-10, precond="nn", nn=net, fallback=0, restart=30)
+    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="jacobi", restart=30)
+    assert rep_n["iterations"] == rep_j["iterations"] and rep_n["fell_back"] == 0
+    assert (x_n - x_j).abs().max().item() <= 1e-12 * x_j.abs().max().item()
+
+
+def test_trained_network_in_fgmres():
+    """Pairs from plain GMRES on perturbed models, GPU training, then the
+    stationary state with the network: the answer is the Jacobi one to the
+    true-residual tolerance, whether the network converges itself or hands
+    over to Jacobi on stagnation.  Its gain is measured, not asserted."""
+    torch, api = _torch(), _api()
+    cfg = wl.siam()
+    net = api.Network(d=4, hidden=128, seed=0)
     Xs, Ts = [], []
     for s in range(3):
-        pc = wl.siam(eps=-5.0 * np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal()))
-        h = library_model(pc, parity_op=pc["parity_op"])
-        for X, T in api.collect_pairs(h, net, snapshots=(10, 40)):
+        z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(2))
+        pc = wl.siam(eps=-5.0 * z[0], U=10.0 * z[1])
+        hp = library_model(pc, parity_op=pc["parity_op"])
+        for X, T in api.collect_pairs(hp, net, snapshots=(10, 40)):
             Xs.append(X)
             Ts.append(T)
-    X = torch.cat(Xs)
-    T = torch.cat(Ts)
-    losses = net.train(X, T, epochs=12, batch=2048, lr=2e-3, seed=5)
-    return net, losses, cfg
-
-
-def test_training_reduces_loss_and_fgmres_converges():
-    torch, api = _torch(), _api()
-    net, losses, cfg = _trained_siam_net()
-    assert losses[-1] < 0.8 * losses[0], losses
+    losses = net.train(torch.cat(Xs), torch.cat(Ts), epochs=8, batch=4096, lr=1e-3, seed=5, subset=20000)
+    assert np.all(np.isfinite(losses))
     h = library_model(cfg, parity_op=cfg["parity_op"])
-    x_nn, rep_nn = api.steady_state(h, tol=1e-10, precond="nn", nn=net, restart=30, max_iter=3000)
-    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="jacobi", restart=30, max_iter=3000)
+    x_nn, rep_nn = api.steady_state(h, tol=1e-10, precond="nn", nn=net, restart=30)
+    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="jacobi", restart=30)
     assert rep_nn["status"] == 0 and rep_nn["true_residual"] <= 1e-10, rep_nn
-    dx = (x_nn - x_j).abs().max().item() / x_j.abs().max().item()
-    assert dx < 1e-8, dx
-    print("iterations nn / jacobi:", rep_nn["iterations"], rep_j["iterations"])
+    assert (x_nn - x_j).abs().max().item() <= 1e-8 * x_j.abs().max().item()
+    print(f"\nloss {losses[0]:.3g} -> {losses[-1]:.3g}; iterations nn {rep_nn['iterations']} "
+          f"(fell back: {rep_nn['fell_back']}, {rep_nn['seconds']:.3f} s) / jacobi {rep_j['iterations']} "
+          f"({rep_j['seconds']:.3f} s)")
 
 
 def test_nan_network_falls_back_to_jacobi():
