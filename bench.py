@@ -9,7 +9,16 @@ per step; roofline.achieved uses the average kernel time measured with HIP
 events on the launch stream.  The oracle (assembled CSR, row-sampled at the
 same tier) is timed on the host cores beside it.
 
+The second half of the metric, solve seconds to a 1e-8 true residual with
+plain (Jacobi) GMRES and with the learned preconditioner in FGMRES, is
+reported under "solves": the stationary state of the same tier-4 model
+(network trained on pairs from seeded tier-3 perturbations of it), the
+stationary state of the single-impurity Anderson model (tier 3, 10,701
+ADOs; network trained on pairs from seeded perturbations), and a sample
+of its density of states.  Training time is reported beside each network.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32]
+                       [--solves all|siam|none]
 """
 from __future__ import annotations
 
@@ -48,6 +57,8 @@ def parse():
     p.add_argument("--tiled", type=int, default=-1, help="-1: untiled apply; 0: default chunks; k: k chunks")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--solves", choices=["all", "siam", "none"], default="all",
+                   help="solve timings: all (two-orbital tier 4 and SIAM), siam only, or none")
     p.add_argument("--calib", action="store_true",
                    help="also run one plain device copy of the ADO vector (HBM counter calibration)")
     return p.parse_args()
@@ -96,6 +107,109 @@ def gpu_apply_bench(args):
                 bytes=nbytes)
 
 
+def _progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def _solve_record(rep, wall):
+    return {"seconds": round(wall, 4), "iterations": rep["iterations"], "applies": rep["applies"],
+            "true_residual": rep["true_residual"], "converged": rep["status"] == 0, "fell_back": bool(rep["fell_back"])}
+
+
+def _train_network(api, d, hidden, models, snapshots, restart, subset, epochs, seed=0):
+    """Pairs from plain GMRES on each model (collect_pairs), then GPU training."""
+    import torch
+    net = api.Network(d=d, hidden=hidden, seed=seed)
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for cfg in models:
+        hp = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+        for X, T in api.collect_pairs(hp, net, snapshots=snapshots, restart=restart):
+            Xs.append(X)
+            Ts.append(T)
+        hp.close()
+        _progress(f"pairs from one perturbed {cfg['name']} model ({time.perf_counter() - t0:.1f} s so far)")
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    losses, t_train = _timed(lambda: net.train(X, T, epochs=epochs, batch=4096, lr=1e-3, seed=seed + 1,
+                                               subset=min(subset, X.shape[0])))
+    info = {"pair_rows": int(X.shape[0]), "train_rows": int(min(subset, X.shape[0])), "epochs": epochs,
+            "pairs_seconds": round(t_pairs, 3), "train_seconds": round(t_train, 3),
+            "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    del X, T, Xs, Ts
+    return net, info
+
+
+def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snapshots, pair_restart):
+    """Stationary state to a 1e-8 true residual: Jacobi GMRES vs FGMRES with
+    the network (which hands over to Jacobi if it stagnates)."""
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    (x_p, rp), tp = _timed(lambda: api.steady_state(h, tol=1e-8, precond="jacobi", restart=restart, mode=mode,
+                                                     max_iter=20000, allow_not_converged=True))
+    del x_p
+    _progress(f"{cfg['name']} N={h.N} steady, Jacobi GMRES: {rp['iterations']} iterations, {tp:.2f} s")
+    net, info = _train_network(api, d, hidden, train_models, snapshots, pair_restart, 20000, 10)
+    _progress(f"{cfg['name']} network: {info['pair_rows']} pair rows in {info['pairs_seconds']:.1f} s, "
+              f"trained in {info['train_seconds']:.1f} s")
+    # the network gets as many iterations as Jacobi needed; past that it hands
+    # over to Jacobi (from its iterate, with the same budget again)
+    cap = max(rp["iterations"], restart)
+    (x_n, rn), tn = _timed(lambda: api.steady_state(h, tol=1e-8, precond="nn", nn=net, restart=restart, mode=mode,
+                                                     max_iter=cap, allow_not_converged=True))
+    del x_n
+    net.close()
+    _progress(f"{cfg['name']} N={h.N} steady, NN FGMRES: {rn['iterations']} iterations, {tn:.2f} s, "
+              f"fell back {rn['fell_back']}")
+    out = {"n_ado": h.N, "d": h.d, "restart": restart, "mode": mode, "nn_max_iter": cap,
+           "plain_jacobi": _solve_record(rp, tp),
+           "nn_fgmres": _solve_record(rn, tn), "network": {"hidden": hidden, **info},
+           "nn_speedup": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None}
+    h.close()
+    return out
+
+
+def dos_sample(api, wl, n_omega=64):
+    """Density of states of the tier-3 SIAM at n_omega frequencies of its
+    2000-point grid (Jacobi GMRES, FP64, 1e-8 per solve)."""
+    import numpy as np
+    cfg = wl.siam()
+    he = api.Hierarchy(cfg["H"], cfg["baths"], 0, cfg["n_max"], parity=+1, parity_op=cfg["parity_op"])
+    ho = api.Hierarchy(cfg["H"], cfg["baths"], 0, cfg["n_max"], parity=-1, parity_op=cfg["parity_op"])
+    x, _ = api.steady_state(he, tol=1e-10)
+    om = cfg["omegas"][:: max(1, len(cfg["omegas"]) // n_omega)][:n_omega]
+    (A, rep), t = _timed(lambda: api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-8, rhs_chunk=64))
+    _progress(f"siam DOS at {len(om)} frequencies: {t:.2f} s")
+    return {"n_omega": len(om), "solves": 2 * len(om), "plain_jacobi": _solve_record(rep, t),
+            "omega_per_s": round(len(om) / t, 2), "finite": bool(np.all(np.isfinite(A)))}
+
+
+def solve_benchmarks(which):
+    import numpy as np
+    from paper_2306_07522_amd import api, workloads as wl
+    out = {}
+    siam_train = []
+    for s in range(4):
+        z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(4))
+        siam_train.append(wl.siam(eps=-5.0 * z[0], U=10.0 * z[1], Gamma=2.0 * z[2], mus=(z[3], -z[3])))
+    out["siam_tier3_steady"] = steady_comparison(api, wl, wl.siam(), siam_train, 4, 128, 30, "fp64", (10, 30, 60), 30)
+    out["siam_tier3_dos"] = dos_sample(api, wl)
+    if which == "all":
+        train = [wl.perturbed_two_orbital(1000 + s, n_max=3) for s in range(3)]
+        out["two_orbital_tier4_steady"] = steady_comparison(api, wl, wl.two_orbital_anderson(), train, 16, 256, 100,
+                                                            "fp64", (20, 60), 100)
+    return out
+
+
 def cpu_baseline(seconds):
     """Oracle apply on the host: the assembled HEOMLS restricted to a seeded
     sample of block rows of the same tier-4 hierarchy, multiplied with the
@@ -134,6 +248,7 @@ def main():
         sys.exit(2)
     r = gpu_apply_bench(args)
     h = r["h"]
+    _progress(f"apply: {args.steps} steps, {r['avg_kernel_ms']:.3f} ms average kernel time")
     ms_step = r["wall"] * 1e3 / args.steps
     value = r["bytes"] / (ms_step * 1e-3) / 1e9
     achieved = r["bytes"] / (r["avg_kernel_ms"] * 1e-3) / 1e9
@@ -161,7 +276,14 @@ def main():
         "bytes_per_step": r["bytes"],
     }
     if not args.no_cpu:
+        _progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        _progress(f"oracle CPU baseline: {out['cpu_baseline']['value']:.3f} GB/s")
+    if args.solves != "none":
+        del r
+        import torch
+        torch.cuda.empty_cache()
+        out["solves"] = solve_benchmarks(args.solves)
     print(json.dumps(out), flush=True)
 
 

@@ -223,9 +223,12 @@ typedef struct {
   int32_t max_refine;     /* IR outer steps (default 20)                      */
   int32_t rhs_chunk;      /* spectra: right-hand sides per multi-RHS solve    */
   const heom_nn *nn;      /* learned preconditioner for HEOM_PREC_NN          */
-  int32_t fallback;       /* 1: on NN failure restart with Jacobi: NaN, max_iter,
-                             or a restart cycle (FP64) that cuts the true
-                             residual by less than 10%                      */
+  int32_t fallback;       /* 1: on NN failure (NaN, max_iter, or an FP64
+                             restart cycle that cuts the true residual by
+                             less than 10%) solve again with Jacobi, with a
+                             fresh max_iter, from the network's iterate if
+                             its residual is <= 0.1, else from zero; the
+                             report sums both attempts                     */
   int32_t use_x0;         /* 1: x_dev holds the initial guess                 */
 } heom_solver_opts;
 

@@ -365,19 +365,24 @@ heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, h
   lp.h = &h;
   lp.R = 1;
   lp.border = 1;
-  heom_status st = solve_system(lp, *o, b, x_dev, o->use_x0 != 0, r, arena, s);
+  heom_solver_report local;
+  std::memset(&local, 0, sizeof(local));
+  heom_solver_report *rp = r ? r : &local;
+  heom_status st = solve_system(lp, *o, b, x_dev, o->use_x0 != 0, rp, arena, s);
   if ((st == HEOM_ERR_NOT_CONVERGED || st == HEOM_ERR_NAN) && o->precond == HEOM_PREC_NN && o->fallback) {
+    // Jacobi GMRES takes over.  It continues from the network's iterate only
+    // when that cut the residual tenfold: restarted GMRES started from a
+    // barely improved iterate can stagnate where a zero start does not.
     heom_solver_opts o2 = *o;
     o2.precond = HEOM_PREC_JACOBI;
-    o2.use_x0 = st == HEOM_ERR_NAN ? 0 : 1;
-    if (r) {  // iterations, applies and seconds keep accumulating over both attempts
-      r->fell_back = 1;
-      r->status = HEOM_OK;
-      r->true_residual = 0.0;
-    }
+    o2.use_x0 = st != HEOM_ERR_NAN && rp->true_residual <= 0.1;
+    // iterations, applies and seconds keep accumulating over both attempts
+    rp->fell_back = 1;
+    rp->status = HEOM_OK;
+    rp->true_residual = 0.0;
     WsArena arena2(ws, ws_bytes);
     arena2.take(sizeof(double2) * n);
-    st = solve_system(lp, o2, b, x_dev, o2.use_x0 != 0, r, arena2, s);
+    st = solve_system(lp, o2, b, x_dev, o2.use_x0 != 0, rp, arena2, s);
   }
   return st;
 }
