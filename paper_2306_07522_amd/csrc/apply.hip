@@ -52,6 +52,7 @@ struct ApplyParams {
   int n_centries;
   const T2 *hdiag;
   int tpw;  // tasks per wave
+  int xchunk;  // XCD remap super-chunk in blocks (multiple of 8; 0 = off)
   const int32_t *coef_op;
   const T2 *coef;
   const T2 *x;
@@ -84,7 +85,9 @@ __device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, i
   }
 }
 
-// One wave processes tasks first, first + 4, ... (tpw of them).  Within a
+// One wave processes tasks first, first + 4, ... (tpw of them).  Blocks are
+// remapped inside super-chunks of xchunk blocks so that each XCD (block b
+// runs on XCD b % 8) walks a contiguous run of tasks, which share parents.  Within a
 // task the next group's first neighbour block is prefetched while the
 // current group is finished; multi-edge groups stream two blocks at a time.
 template <typename T, int D, bool FUSE>
@@ -110,7 +113,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T2 *buf = sbuf + wave * DD;
   const int j = lane % D;
-  const int64_t first = ((int64_t)blockIdx.x * 4 * P.tpw) + wave;
+  int64_t blk = blockIdx.x;
+  if (P.xchunk > 0 && (int64_t)(blockIdx.x / P.xchunk + 1) * P.xchunk <= (int64_t)gridDim.x) {
+    // XCD-aware remap inside super-chunks of xchunk blocks: block b runs on
+    // XCD b % 8, which then walks a contiguous slice of the super-chunk
+    const int64_t sup = blockIdx.x / P.xchunk, r = blockIdx.x % P.xchunk;
+    blk = sup * P.xchunk + (r % 8) * (P.xchunk / 8) + r / 8;
+  }
+  const int64_t first = (blk * 4 * P.tpw) + wave;
   for (int it = 0; it < P.tpw; ++it) {
     const int64_t task = first + 4 * it;
     if (task >= P.n_tasks) break;
@@ -310,7 +320,7 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   const int64_t n_tasks = t1 - t0;
   if (n_tasks <= 0) return HEOM_OK;
   constexpr bool dbl = std::is_same<T, double>::value;
-  ApplyParams<T> P;
+  ApplyParams<T> P{};
   P.tasks = pl.tasks + t0;
   P.n_tasks = n_tasks;
   P.groups = pl.groups;
@@ -341,7 +351,8 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   const size_t tab_bytes = (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 16 + (size_t)d * sizeof(T2);
   const size_t smem = 4 * (size_t)d * d * sizeof(T2) + tab_bytes;
   if (a.n_rhs == 1 && (d == 8 || d == 16) && smem <= 48 * 1024) {
-    P.tpw = n_tasks > 65536 ? 4 : 1;
+    P.tpw = 1;
+    P.xchunk = 64;
     const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
     if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
     dim3 g((unsigned)grid), b(256);

@@ -145,7 +145,26 @@ heom_status ensure_device(Hier &h) {
   }
   PlanBuilder pb(h);
   std::vector<int64_t> es;
-  for (int64_t a = 0; a < N; ++a) {
+  std::vector<int64_t> order(N);
+  for (int64_t a = 0; a < N; ++a) order[a] = a;
+  {
+    // Task order: ADOs grouped into windows by their largest exponent label
+    // (stable, so tiers stay ascending inside a window).  A top-tier ADO and
+    // three of its four parents share its window, so the parents' up-term
+    // gathers find it in cache shortly after (or before) its own task.
+    std::vector<int> key(N, -1);
+    for (int64_t a = 0; a < N; ++a) {
+      int k = -1;
+      const uint64_t m = h.fmask[a];
+      if (m) k = 63 - __builtin_clzll(m);
+      for (int b = h.Kb - 1; b >= 0; --b)
+        if (h.bocc[(size_t)a * h.Kb + b]) { k = std::max(k, h.Kf + b); break; }
+      key[a] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int64_t p, int64_t q) { return key[p] < key[q]; });
+  }
+  for (int64_t oi = 0; oi < N; ++oi) {
+    const int64_t a = order[oi];
     es.clear();
     for (int64_t e = h.row_ptr[a]; e < h.row_ptr[a + 1]; ++e) es.push_back(e);
     pb.add_task(a, es, true, false);
