@@ -329,6 +329,63 @@ heom_status heom_steady_residual(heom_hier *h, const void *x_dev, void *r_dev, v
 heom_status heom_vector_axpby(int32_t precision, const void *x_dev, double alpha, void *y_dev, double beta, int64_t n,
                               void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched instances
+ *
+ * Many independent hierarchies (each with its own d <= 16, exponents, tiers,
+ * Hamiltonian and baths; for example parameter sweeps or ensembles of
+ * models) are advanced together: one launch applies eq:HEOM to every
+ * instance, and the batched stationary-state solver runs restarted GMRES on
+ * all instances at once with per-instance scalars.  The batch vector is the
+ * concatenation of the instance vectors ([N_s][d_s][d_s] complex each, in
+ * instance order); heom_batch_info returns the element offsets.
+ * ---------------------------------------------------------------------- */
+typedef struct heom_batch heom_batch;
+
+/* Build a batch over already-built hierarchies (not copied: they must
+ * outlive the batch; the batch uploads their device tables on the current
+ * device).  Errors: HEOM_ERR_ARG (NULL / n_inst < 1), HEOM_ERR_UNSUPPORTED
+ * (an instance with d > 16). */
+heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch **out);
+void heom_batch_free(heom_batch *b);
+/* offsets: n_inst + 1 element offsets (may be NULL); n_tiles: work tiles of
+ * the batched launch; grid, order: the launch configuration in use (grid 0 =
+ * one block per tile; order 0 = instance-major tiles, 1 = interleaved,
+ * costliest instances first). */
+heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_tiles, int32_t *grid, int32_t *order);
+/* y = M x for every instance in one launch (eq:HEOM; border = 1: the
+ * bordered stationary-state operator of each instance, see
+ * heom_apply_steady_operator).  x, y: device batch vectors of the given
+ * precision, not aliased. */
+heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t border,
+                             void *stream);
+/* Autotuner: times heom_batch_apply (reps launches per candidate, after two
+ * warm-up launches) over the persistent grid sizes {one block per tile,
+ * 2, 4, 8, 16 blocks per CU} and both tile orders, keeps the fastest for all
+ * later launches and reports the default and chosen times (ms per apply).
+ * x, y: scratch batch vectors of the precision; y is overwritten.
+ * Synchronises the stream. */
+heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
+                            double *ms_default, double *ms_best, void *stream);
+/* Device workspace bytes for heom_batch_steady with these options. */
+heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opts *o, size_t *bytes);
+/* Stationary state of every instance (the bordered system of
+ * heom_steady, Methods and "Package architecture"): restarted GMRES with the
+ * Jacobi preconditioner on all instances at once, FP64 or FP32 with FP64
+ * iterative refinement (opts.mode), each instance to opts.tol in its true
+ * residual.  Instances leave the active set when they converge.  use_graph
+ * = 1 captures each Arnoldi step's device work (preconditioner, apply,
+ * CGS2, norms, the copy of the coefficients to the host) once per basis size
+ * into a hipGraph and replays it.  x_dev: FP64 batch vector (initial guess
+ * if opts.use_x0).  r: n_inst reports (status, iterations, refinements,
+ * true residual; seconds and applies are batch totals).  Returns
+ * HEOM_ERR_NOT_CONVERGED if any instance misses the tolerance.
+ * opts.precond: HEOM_PREC_JACOBI or HEOM_PREC_NONE; with opts.fallback = 1
+ * the instances that miss the tolerance are solved again from zero with the
+ * other choice, and their reports carry fell_back = 1 (iterations add up). */
+heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
+                              int32_t use_graph, void *ws, size_t ws_bytes, void *stream);
+
 const char *heom_status_string(heom_status s);
 const char *heom_last_error(void);
 const char *heom_version(void);

@@ -90,6 +90,14 @@ SIGNATURES = {
                                     C.c_uint64, C.POINTER(C.c_float), vp]),
     "heom_steady_residual": (heom_status, [vp, vp, vp, vp]),
     "heom_vector_axpby": (heom_status, [C.c_int32, vp, C.c_double, vp, C.c_double, C.c_int64, vp]),
+    "heom_batch_create": (heom_status, [C.c_int32, C.POINTER(vp), C.POINTER(vp)]),
+    "heom_batch_free": (None, [vp]),
+    "heom_batch_info": (heom_status, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), i32p, i32p]),
+    "heom_batch_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp]),
+    "heom_batch_tune": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, dp, vp]),
+    "heom_batch_workspace_size": (heom_status, [vp, C.POINTER(heom_solver_opts), C.POINTER(C.c_size_t)]),
+    "heom_batch_steady": (heom_status, [vp, vp, C.POINTER(heom_solver_opts), C.POINTER(heom_solver_report),
+                                        C.c_int32, vp, C.c_size_t, vp]),
 }
 
 _lib = None

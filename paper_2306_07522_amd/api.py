@@ -418,3 +418,84 @@ class Network:
                                         float(lr),
                                         int(seed), losses.ctypes.data_as(C.POINTER(C.c_float)), _stream_ptr(stream)))
         return losses[:epochs]
+
+
+# ----------------------------------------------------------------- batched instances
+class Batch:
+    """Handle of heom_batch_create over already-built Hierarchy objects
+    (kept alive by the batch).  Batch vectors are the instance vectors
+    concatenated in order; ``offsets`` gives each instance's element range."""
+
+    def __init__(self, hierarchies):
+        self._lib = lib()
+        self.members = list(hierarchies)
+        arr = (C.c_void_p * len(self.members))(*[h.handle.value if isinstance(h.handle, C.c_void_p) else h.handle
+                                                  for h in self.members])
+        hb = C.c_void_p()
+        L.check(self._lib.heom_batch_create(len(self.members), arr, C.byref(hb)))
+        self._h = hb
+        self.offsets = self.info()["offsets"]
+        self.n = int(self.offsets[-1])
+
+    def info(self):
+        S = len(self.members)
+        off = (C.c_int64 * (S + 1))()
+        nt, grid, order = C.c_int64(), C.c_int32(), C.c_int32()
+        L.check(self._lib.heom_batch_info(self._h, off, C.byref(nt), C.byref(grid), C.byref(order)))
+        return {"offsets": np.array(off[:], dtype=np.int64), "n_tiles": nt.value, "grid": grid.value,
+                "order": order.value}
+
+    def close(self):
+        if self._h:
+            self._lib.heom_batch_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def split(self, v):
+        """Views of the instance blocks [N_s][d_s][d_s] of a flat batch vector."""
+        out = []
+        for s, h in enumerate(self.members):
+            a, b = int(self.offsets[s]), int(self.offsets[s + 1])
+            out.append(v[a:b].view(h.N, h.d, h.d))
+        return out
+
+    def apply(self, x, y=None, border=0, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        L.check(self._lib.heom_batch_apply(self._h, _precision_of(x), _devptr(x), _devptr(y), int(border),
+                                           _stream_ptr(stream)))
+        return y
+
+    def tune(self, precision="fp32", reps=5, stream=None):
+        import torch
+        dt = torch.complex64 if precision == "fp32" else torch.complex128
+        x = torch.randn(self.n, dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        md, mb = C.c_double(), C.c_double()
+        L.check(self._lib.heom_batch_tune(self._h, _precision_of(x), _devptr(x), _devptr(y), int(reps),
+                                          C.byref(md), C.byref(mb), _stream_ptr(stream)))
+        return {"ms_default": md.value, "ms_best": mb.value, **self.info()}
+
+    def steady_state(self, x=None, use_graph=True, stream=None, allow_not_converged=False, **opts):
+        """Stationary states of every instance: (FP64 batch vector, list of
+        per-instance reports)."""
+        import torch
+        o = solver_opts(**opts)
+        if x is None:
+            x = torch.zeros(self.n, dtype=torch.complex128, device="cuda")
+        nb = C.c_size_t()
+        L.check(self._lib.heom_batch_workspace_size(self._h, C.byref(o), C.byref(nb)))
+        ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device="cuda")
+        S = len(self.members)
+        reps = (L.heom_solver_report * S)()
+        st = self._lib.heom_batch_steady(self._h, _devptr(x), C.byref(o), reps, int(bool(use_graph)),
+                                         C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+        if not (allow_not_converged and st == 4):
+            L.check(st)
+        return x, [report_dict(r) for r in reps]

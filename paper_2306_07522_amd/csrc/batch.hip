@@ -1,0 +1,965 @@
+// Batched instances: many independent hierarchies -- each with its own d,
+// exponents, tiers, Hamiltonian and baths -- advanced by single launches.
+//
+// The batch vector is the concatenation of the instance vectors ([N_s][d_s][d_s]
+// complex each, instance order).  Three device tables drive every kernel:
+//   instances  one descriptor per instance (its apply tables, d, offset);
+//   tiles      (instance, first task, end task): the tasks of one instance
+//              that one 256-thread block computes, one thread per output
+//              element (256 / d^2 ADOs per tile);
+//   chunks     contiguous element ranges that never straddle two instances,
+//              the unit of the segmented reductions of the batched GMRES.
+// The apply is one persistent launch that walks the tile list; the Jacobi
+// preconditioner walks the same list.  Per-instance GMRES scalars (the
+// Arnoldi coefficients, Givens rotations, residual norms) come from
+// segmented reductions; an Arnoldi step's device work can be captured once
+// per basis size into a hipGraph and replayed.  An autotuner picks the
+// persistent grid size and the tile order by timing the batched apply.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "blas.h"
+#include "device_common.h"
+#include "internal.h"
+#include "solvers.h"
+
+namespace heom {
+
+template <typename T>
+struct BInst {
+  using T2 = typename Cplx<T>::t;
+  const int4 *tasks;
+  const int4 *groups;
+  const int2 *gedges;
+  const int32_t *coef_op;
+  const T2 *coef;
+  const int32_t *ell_cnt;
+  const int32_t *ell_col;
+  const T2 *ell_val;
+  const T2 *decay;
+  const double2 *decay64;
+  const double2 *hdiag64;
+  int64_t off;  // first element of the instance in the batch vector
+  int slots;
+  int d;
+};
+
+// ----------------------------------------------------------------- apply
+// y = B x per instance (B = M, or the bordered stationary-state operator when
+// border is set: element (0,0) of ADO 0 becomes Tr rho_0).
+template <typename T>
+__global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__restrict__ inst,
+                                                          const int4 *__restrict__ tiles, int n_tiles,
+                                                          const int *__restrict__ active,
+                                                          const typename Cplx<T>::t *__restrict__ x,
+                                                          typename Cplx<T>::t *__restrict__ y, int border) {
+  using T2 = typename Cplx<T>::t;
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    if (active && !active[tl.x]) continue;
+    const BInst<T> &I = inst[tl.x];
+    const int d = I.d, cells = d * d;
+    const int lt = threadIdx.x / cells;
+    const int64_t task = (int64_t)tl.y + lt;
+    if ((lt + 1) * cells > 256 || task >= tl.z) continue;
+    const int cell = threadIdx.x - lt * cells;
+    const int i = cell / d, j = cell - (cell / d) * d;
+    const int4 tk = I.tasks[task];
+    const int64_t a = tk.x;
+    const T2 *xs = x + I.off;
+    auto in = [&](int64_t b, int ii, int jj) -> T2 { return xs[(b * d + ii) * d + jj]; };
+    T2 acc{0, 0};
+    for (int g = tk.y; g < tk.z; ++g) {
+      const int4 gr = I.groups[g];
+      const int op = I.coef_op[gr.z];
+      const size_t rowL = ((size_t)op * 2) * d + i;
+      const size_t rowR = ((size_t)op * 2 + 1) * d + j;
+      const int nl = I.ell_cnt[rowL], nr = I.ell_cnt[rowR];
+      T2 L{0, 0}, Rv{0, 0};
+      for (int e = gr.x; e < gr.y; ++e) {
+        const int2 ed = I.gedges[e];
+        const T w = (T)ed.y;
+        T2 l{0, 0}, rr{0, 0};
+        for (int q = 0; q < nl; ++q)
+          l = cfma(I.ell_val[rowL * I.slots + q], in(ed.x, I.ell_col[rowL * I.slots + q], j), l);
+        for (int q = 0; q < nr; ++q)
+          rr = cfma(in(ed.x, i, I.ell_col[rowR * I.slots + q]), I.ell_val[rowR * I.slots + q], rr);
+        L.x = fma(w, l.x, L.x); L.y = fma(w, l.y, L.y);
+        Rv.x = fma(w, rr.x, Rv.x); Rv.y = fma(w, rr.y, Rv.y);
+      }
+      if (gr.w) acc = csub(acc, cmul(I.decay[a], in(a, i, j)));
+      acc = cfma(I.coef[2 * gr.z], L, acc);
+      acc = cfma(I.coef[2 * gr.z + 1], Rv, acc);
+    }
+    if (border && a == 0 && cell == 0) {
+      T2 tr{0, 0};
+      for (int ii = 0; ii < d; ++ii) tr = cadd(tr, in(0, ii, ii));
+      acc = tr;
+    }
+    y[I.off + (a * d + i) * d + j] = acc;
+  }
+}
+
+// z = D^{-1} r per instance, D the diagonal of B (zeros count as 1).
+template <typename T>
+__global__ void __launch_bounds__(256) batch_jacobi_kernel(const BInst<T> *__restrict__ inst,
+                                                           const int4 *__restrict__ tiles, int n_tiles,
+                                                           const int *__restrict__ active,
+                                                           const typename Cplx<T>::t *__restrict__ r,
+                                                           typename Cplx<T>::t *__restrict__ z, int border) {
+  using T2 = typename Cplx<T>::t;
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    if (active && !active[tl.x]) continue;
+    const BInst<T> &I = inst[tl.x];
+    const int d = I.d, cells = d * d;
+    const int lt = threadIdx.x / cells;
+    const int64_t task = (int64_t)tl.y + lt;
+    if ((lt + 1) * cells > 256 || task >= tl.z) continue;
+    const int cell = threadIdx.x - lt * cells;
+    const int i = cell / d, j = cell - (cell / d) * d;
+    const int64_t a = I.tasks[task].x;
+    const double2 c = I.decay64[a], hi = I.hdiag64[i], hj = I.hdiag64[j];
+    double2 dg = make_double2(-c.x + (hi.y - hj.y), -c.y - (hi.x - hj.x));
+    if (border && a == 0 && cell == 0) dg = make_double2(1.0, 0.0);
+    if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
+    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
+    const int64_t idx = I.off + a * cells + cell;
+    const T2 v = r[idx];
+    z[idx] = T2{(T)(((double)v.x * dg.x + (double)v.y * dg.y) * inv), (T)(((double)v.y * dg.x - (double)v.x * dg.y) * inv)};
+  }
+}
+
+// ----------------------------------------------------------------- segmented vector kernels
+// partial[i * n_chunks + c] = sum over chunk c of conj(V_i) w, i in [i0, i0 + NI)
+template <typename T, int NI>
+__global__ void __launch_bounds__(256) seg_mdot_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
+                                                       const typename Cplx<T>::t *__restrict__ w,
+                                                       const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg,
+                                                       int n_chunks, const int *__restrict__ active,
+                                                       double2 *__restrict__ partial) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double2 red[NI][256];
+  const int c = blockIdx.x;
+  const int i0 = blockIdx.y * NI;
+  const bool on = !active || active[ch_seg[c]];
+  double ax[NI], ay[NI];
+#pragma unroll
+  for (int q = 0; q < NI; ++q) ax[q] = ay[q] = 0.0;
+  if (on) {
+    for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
+      const T2 b = w[e];
+#pragma unroll
+      for (int q = 0; q < NI; ++q)
+        if (i0 + q < k) {
+          const T2 a = V[(i0 + q) * ldv + e];
+          ax[q] += (double)a.x * b.x + (double)a.y * b.y;
+          ay[q] += (double)a.x * b.y - (double)a.y * b.x;
+        }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NI; ++q) red[q][threadIdx.x] = make_double2(ax[q], ay[q]);
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        red[q][threadIdx.x].x += red[q][threadIdx.x + s].x;
+        red[q][threadIdx.x].y += red[q][threadIdx.x + s].y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NI && i0 + (int)threadIdx.x < k)
+    partial[(int64_t)(i0 + threadIdx.x) * n_chunks + c] = red[threadIdx.x][0];
+}
+
+// out[i * S + s] = sum of partial over the chunks of instance s
+__global__ void seg_reduce_kernel(const double2 *__restrict__ partial, int k, int n_chunks,
+                                  const int *__restrict__ seg_chunk, int S, double2 *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)k * S) return;
+  const int i = (int)(idx / S), s = (int)(idx % S);
+  double sx = 0, sy = 0;
+  for (int c = seg_chunk[s]; c < seg_chunk[s + 1]; ++c) {
+    const double2 p = partial[(int64_t)i * n_chunks + c];
+    sx += p.x;
+    sy += p.y;
+  }
+  out[idx] = make_double2(sx, sy);
+}
+
+// w += sign * sum_{i < k} V_i h[i * S + seg]
+template <typename T>
+__global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
+                                                         const double2 *__restrict__ h, int S,
+                                                         typename Cplx<T>::t *__restrict__ w,
+                                                         const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg,
+                                                         const int *__restrict__ active, double sign) {
+  using T2 = typename Cplx<T>::t;
+  const int c = blockIdx.x;
+  const int s = ch_seg[c];
+  if (active && !active[s]) return;
+  for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
+    double ax = w[e].x, ay = w[e].y;
+    for (int i = 0; i < k; ++i) {
+      const double2 hh = h[(int64_t)i * S + s];
+      if (hh.x == 0.0 && hh.y == 0.0) continue;  // columns past this instance's basis may hold garbage
+      const T2 v = V[i * ldv + e];
+      ax += sign * ((double)v.x * hh.x - (double)v.y * hh.y);
+      ay += sign * ((double)v.x * hh.y + (double)v.y * hh.x);
+    }
+    w[e] = T2{(T)ax, (T)ay};
+  }
+}
+
+// out = sc[seg] * in  (real per-instance scale; types may differ)
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) seg_scale_kernel(const typename Cplx<TI>::t *__restrict__ in,
+                                                        const double *__restrict__ sc,
+                                                        typename Cplx<TO>::t *__restrict__ out,
+                                                        const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg) {
+  const int c = blockIdx.x;
+  const double f = sc[ch_seg[c]];
+  for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256)
+    out[e] = typename Cplx<TO>::t{(TO)(f * (double)in[e].x), (TO)(f * (double)in[e].y)};
+}
+
+// y += sc[seg] * x  (x of type TX, y of type TY)
+template <typename TX, typename TY>
+__global__ void __launch_bounds__(256) seg_axpy_kernel(const typename Cplx<TX>::t *__restrict__ x,
+                                                       const double *__restrict__ sc,
+                                                       typename Cplx<TY>::t *__restrict__ y,
+                                                       const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg) {
+  const int c = blockIdx.x;
+  const double f = sc[ch_seg[c]];
+  if (f == 0.0) return;
+  for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256)
+    y[e] = typename Cplx<TY>::t{(TY)((double)y[e].x + f * (double)x[e].x), (TY)((double)y[e].y + f * (double)x[e].y)};
+}
+
+// b = e_0 of every instance (the stationary-state right-hand side)
+__global__ void seg_unit_kernel(double2 *__restrict__ b, const int64_t *__restrict__ off, int S) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) b[off[s]] = make_double2(1.0, 0.0);
+}
+
+template <typename T>
+__global__ void seg_zero_kernel(typename Cplx<T>::t *__restrict__ v, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    v[e] = typename Cplx<T>::t{0, 0};
+}
+
+}  // namespace heom
+
+using namespace heom;
+
+// ----------------------------------------------------------------- batch object
+struct heom_batch {
+  std::vector<heom_hier *> inst;  // not owned
+  int S = 0;
+  int64_t n = 0;
+  std::vector<int64_t> off;       // [S + 1]
+  int device = -1;
+  BInst<double> *inst64 = nullptr;
+  BInst<float> *inst32 = nullptr;
+  int4 *tiles = nullptr;
+  int n_tiles = 0;
+  std::vector<int4> tiles_inst;   // instance-major order
+  std::vector<int4> tiles_cost;   // interleaved, costliest instances first
+  int order = 0;                  // 0: instance-major, 1: interleaved
+  int grid = 0;                   // persistent grid (0: one block per tile)
+  int64_t *ch_e = nullptr;        // [n_chunks + 1]
+  int *ch_seg = nullptr;          // [n_chunks]
+  int *seg_chunk = nullptr;       // [S + 1]
+  int n_chunks = 0;
+  int64_t *d_off = nullptr;       // [S + 1]
+  int *active = nullptr;          // [S]
+  std::vector<int> seg_chunk_h;
+  ~heom_batch() {
+    void *ptrs[] = {inst64, inst32, tiles, ch_e, ch_seg, seg_chunk, d_off, active};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+namespace heom {
+
+static heom_status batch_upload_tiles(heom_batch &b) {
+  const std::vector<int4> &src = b.order == 1 ? b.tiles_cost : b.tiles_inst;
+  HEOM_HIP_CHECK(hipMemcpy(b.tiles, src.data(), sizeof(int4) * src.size(), hipMemcpyHostToDevice));
+  return HEOM_OK;
+}
+
+template <typename T>
+static heom_status batch_apply_T(heom_batch &b, const void *x, void *y, int border, bool use_active, hipStream_t s) {
+  const int grid = b.grid > 0 ? std::min(b.grid, b.n_tiles) : b.n_tiles;
+  if (grid <= 0) return HEOM_OK;
+  const BInst<T> *I = std::is_same<T, double>::value ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
+  hipLaunchKernelGGL(batch_apply_kernel<T>, dim3(grid), dim3(256), 0, s, I, b.tiles, b.n_tiles,
+                     use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x, (typename Cplx<T>::t *)y, border);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+static heom_status batch_jacobi_T(heom_batch &b, const void *r, void *z, int border, hipStream_t s) {
+  const int grid = b.grid > 0 ? std::min(b.grid, b.n_tiles) : b.n_tiles;
+  if (grid <= 0) return HEOM_OK;
+  const BInst<T> *I = std::is_same<T, double>::value ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
+  hipLaunchKernelGGL(batch_jacobi_kernel<T>, dim3(grid), dim3(256), 0, s, I, b.tiles, b.n_tiles, b.active,
+                     (const typename Cplx<T>::t *)r, (typename Cplx<T>::t *)z, border);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+// out[i * S + s] = conj(V_i) . w per instance, i < k
+template <typename T>
+static heom_status seg_mdot(heom_batch &b, const void *V, int64_t ldv, int k, const void *w, double2 *partial,
+                            double2 *out, hipStream_t s) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int NI = 4;
+  dim3 grid(b.n_chunks, (k + NI - 1) / NI);
+  hipLaunchKernelGGL((seg_mdot_kernel<T, NI>), grid, dim3(256), 0, s, (const T2 *)V, ldv, k, (const T2 *)w, b.ch_e,
+                     b.ch_seg, b.n_chunks, b.active, partial);
+  HEOM_HIP_CHECK(hipGetLastError());
+  const int64_t tot = (int64_t)k * b.S;
+  hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, k, b.n_chunks,
+                     b.seg_chunk, b.S, out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+static heom_status seg_update(heom_batch &b, const void *V, int64_t ldv, int k, const double2 *h, void *w,
+                              double sign, hipStream_t s) {
+  using T2 = typename Cplx<T>::t;
+  hipLaunchKernelGGL(seg_update_kernel<T>, dim3(b.n_chunks), dim3(256), 0, s, (const T2 *)V, ldv, k, h, b.S, (T2 *)w,
+                     b.ch_e, b.ch_seg, b.active, sign);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename TI, typename TO>
+static heom_status seg_scale(heom_batch &b, const void *in, const double *sc, void *out, hipStream_t s) {
+  hipLaunchKernelGGL((seg_scale_kernel<TI, TO>), dim3(b.n_chunks), dim3(256), 0, s,
+                     (const typename Cplx<TI>::t *)in, sc, (typename Cplx<TO>::t *)out, b.ch_e, b.ch_seg);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename TX, typename TY>
+static heom_status seg_axpy(heom_batch &b, const void *x, const double *sc, void *y, hipStream_t s) {
+  hipLaunchKernelGGL((seg_axpy_kernel<TX, TY>), dim3(b.n_chunks), dim3(256), 0, s,
+                     (const typename Cplx<TX>::t *)x, sc, (typename Cplx<TY>::t *)y, b.ch_e, b.ch_seg);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+static heom_status seg_zero(void *v, int64_t n, hipStream_t s) {
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(seg_zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, (typename Cplx<T>::t *)v, n);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+// ----------------------------------------------------------------- batched GMRES
+// Restarted right-preconditioned (Jacobi) GMRES on every instance at once:
+// one Arnoldi step is one batched apply + segmented CGS2 for all active
+// instances; the small least-squares problems are solved per instance on
+// the host.  Instances leave the active set when they converge.
+template <typename T>
+struct BatchGmres {
+  using T2 = typename Cplx<T>::t;
+  heom_batch *b = nullptr;
+  int m = 30;
+  T2 *V = nullptr, *Z = nullptr, *w = nullptr;
+  double2 *partial = nullptr, *hdev = nullptr;
+  double *sdev = nullptr;
+  double *pin_sc = nullptr;       // host pinned [S]
+  double2 *pin_h = nullptr;       // host pinned [2 (m + 2) S]
+  PinnedBuf pin;
+  bool use_graph = false;
+  bool jacobi = true;                  // false: no preconditioner (Z aliases V)
+  std::vector<hipGraphExec_t> graphs;  // one per Arnoldi step j
+  hipStream_t cap = nullptr;
+  ~BatchGmres() {
+    for (hipGraphExec_t g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+
+  static size_t bytes(const heom_batch &b, int m, bool jac) {
+    const size_t vec = (size_t)b.n * sizeof(T2);
+    return (size_t)(m + 1) * vec + (jac ? (size_t)m * vec : 0) + vec + (size_t)(m + 2) * b.n_chunks * sizeof(double2) +
+           (size_t)2 * (m + 2) * b.S * sizeof(double2) + (size_t)b.S * sizeof(double) + 8 * 256;
+  }
+
+  heom_status init(heom_batch &bb, WsArena &ws, int m_, bool graph, bool jac) {
+    b = &bb;
+    m = m_;
+    use_graph = graph;
+    jacobi = jac;
+    const size_t vec = (size_t)b->n * sizeof(T2);
+    V = (T2 *)ws.take((size_t)(m + 1) * vec);
+    Z = jacobi ? (T2 *)ws.take((size_t)m * vec) : V;
+    w = (T2 *)ws.take(vec);
+    partial = (double2 *)ws.take((size_t)(m + 2) * b->n_chunks * sizeof(double2));
+    hdev = (double2 *)ws.take((size_t)2 * (m + 2) * b->S * sizeof(double2));
+    sdev = (double *)ws.take((size_t)b->S * sizeof(double));
+    if (!V || !Z || !w || !partial || !hdev || !sdev) return fail(HEOM_ERR_ARG, "batch: workspace too small");
+    HEOM_TRY(pin.ensure((size_t)2 * (m + 2) * b->S * sizeof(double2) + (size_t)b->S * sizeof(double)));
+    pin_h = (double2 *)pin.p;
+    pin_sc = (double *)(pin_h + (size_t)2 * (m + 2) * b->S);
+    graphs.assign(m, nullptr);
+    if (use_graph) HEOM_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    return HEOM_OK;
+  }
+
+  // device work of Arnoldi step j: z_j = P v_j, w = B z_j, CGS2, |w|^2, copy to host
+  heom_status step_device(int j, int border, hipStream_t s) {
+    const int64_t n = b->n;
+    T2 *vj = V + (size_t)j * n;
+    T2 *zj = Z + (size_t)j * n;
+    if (jacobi) HEOM_TRY(batch_jacobi_T<T>(*b, vj, zj, border, s));
+    HEOM_TRY(batch_apply_T<T>(*b, zj, w, border, true, s));
+    double2 *h1 = hdev, *h2 = hdev + (size_t)(m + 2) * b->S;
+    HEOM_TRY(seg_mdot<T>(*b, V, n, j + 1, w, partial, h1, s));
+    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h1, w, -1.0, s));
+    HEOM_TRY(seg_mdot<T>(*b, V, n, j + 1, w, partial, h2, s));
+    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h2, w, -1.0, s));
+    HEOM_TRY(seg_mdot<T>(*b, w, 0, 1, w, partial, h2 + (size_t)(j + 1) * b->S, s));
+    HEOM_HIP_CHECK(hipMemcpyAsync(pin_h, hdev, sizeof(double2) * 2 * (m + 2) * b->S, hipMemcpyDeviceToHost, s));
+    return HEOM_OK;
+  }
+
+  heom_status step(int j, int border, hipStream_t s) {
+    if (!use_graph) return step_device(j, border, s);
+    if (!graphs[j]) {
+      hipGraph_t g = nullptr;
+      HEOM_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+      heom_status st = step_device(j, border, cap);
+      hipGraph_t got = nullptr;
+      hipError_t e = hipStreamEndCapture(cap, &got);
+      g = got;
+      if (st != HEOM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(HEOM_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(HEOM_ERR_HIP, std::string("batch graph instantiate: ") + hipGetErrorString(e));
+      graphs[j] = ex;
+    }
+    HEOM_HIP_CHECK(hipGraphLaunch(graphs[j], s));
+    return HEOM_OK;
+  }
+
+  heom_status norms(const T2 *v, std::vector<double> &out, hipStream_t s) {
+    HEOM_TRY(seg_mdot<T>(*b, v, 0, 1, v, partial, hdev, s));
+    HEOM_HIP_CHECK(hipMemcpyAsync(pin_h, hdev, sizeof(double2) * b->S, hipMemcpyDeviceToHost, s));
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    out.resize(b->S);
+    for (int q = 0; q < b->S; ++q) out[q] = std::sqrt(std::max(pin_h[q].x, 0.0));
+    return HEOM_OK;
+  }
+
+  heom_status set_active(const std::vector<char> &act, hipStream_t s) {
+    std::vector<int> a(b->S);
+    for (int q = 0; q < b->S; ++q) a[q] = act[q] ? 1 : 0;
+    HEOM_HIP_CHECK(hipMemcpyAsync(b->active, a.data(), sizeof(int) * b->S, hipMemcpyHostToDevice, s));
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    return HEOM_OK;
+  }
+
+  // Solve B x = rhs per instance for the instances flagged in `want` (others
+  // untouched); x holds the initial guess (zero when x_is_zero).  iters[q] and
+  // res[q] report per instance; conv[q] = 1 when res[q] <= tol.
+  heom_status solve(const T2 *rhs, T2 *x, const std::vector<char> &want, double tol, int max_iter, int border,
+                    bool x_is_zero, std::vector<int> &iters, std::vector<double> &res, std::vector<char> &conv,
+                    int64_t &applies, hipStream_t s) {
+    const int S = b->S;
+    const int64_t n = b->n;
+    std::vector<double> bnorm, beta;
+    std::vector<char> act(want);
+    HEOM_TRY(set_active(act, s));
+    HEOM_TRY(norms(rhs, bnorm, s));
+    iters.assign(S, 0);
+    res.assign(S, 0.0);
+    conv.assign(S, 0);
+    std::vector<cd> H((size_t)S * (m + 1) * m), sn((size_t)S * m), g((size_t)S * (m + 1));
+    std::vector<double> cs((size_t)S * m);
+    std::vector<int> kcol(S);
+    int it_total = 0;
+    for (int cycle = 0;; ++cycle) {
+      // w = rhs - B x on the active instances
+      if (x_is_zero && cycle == 0) {
+        HEOM_HIP_CHECK(hipMemcpyAsync(w, rhs, sizeof(T2) * n, hipMemcpyDeviceToDevice, s));
+      } else {
+        // (inactive instances keep stale values in w; their reductions are masked)
+        HEOM_TRY(batch_apply_T<T>(*b, x, w, border, true, s));
+        ++applies;
+        HEOM_TRY((axpby<T, T>(rhs, 1.0, w, -1.0, n, s)));
+      }
+      HEOM_TRY(norms(w, beta, s));
+      bool any = false;
+      for (int q = 0; q < S; ++q) {
+        if (!act[q]) continue;
+        const double rel = bnorm[q] > 0 ? beta[q] / bnorm[q] : 0.0;
+        if (!std::isfinite(rel)) return fail(HEOM_ERR_NAN, "batch: non-finite residual");
+        res[q] = rel;
+        if (rel <= tol) {
+          conv[q] = 1;
+          act[q] = 0;
+        } else if (iters[q] >= max_iter) {
+          act[q] = 0;
+        }
+        any = any || act[q];
+      }
+      if (!any) break;
+      HEOM_TRY(set_active(act, s));
+      // V0 = w / beta
+      for (int q = 0; q < S; ++q) pin_sc[q] = act[q] && beta[q] > 0 ? 1.0 / beta[q] : 0.0;
+      HEOM_HIP_CHECK(hipMemcpyAsync(sdev, pin_sc, sizeof(double) * S, hipMemcpyHostToDevice, s));
+      HEOM_TRY((seg_scale<T, T>(*b, w, sdev, V, s)));
+      std::fill(g.begin(), g.end(), cd(0));
+      for (int q = 0; q < S; ++q) {
+        g[(size_t)q * (m + 1)] = act[q] ? beta[q] : 0.0;
+        kcol[q] = 0;
+      }
+      std::vector<char> ext(act);  // still extending its basis this cycle
+      int j = 0;
+      for (; j < m; ++j) {
+        HEOM_TRY(step(j, border, s));
+        ++applies;
+        ++it_total;
+        HEOM_HIP_CHECK(hipStreamSynchronize(s));
+        const double2 *hp1 = pin_h, *hp2 = pin_h + (size_t)(m + 2) * S;
+        bool more = false;
+        for (int q = 0; q < S; ++q) {
+          pin_sc[q] = 0.0;
+          if (!ext[q]) continue;
+          ++iters[q];
+          cd *Hc = &H[((size_t)q * (m + 1)) * m];
+          for (int i = 0; i <= j; ++i)
+            Hc[(size_t)j * (m + 1) + i] = cd(hp1[(size_t)i * S + q].x + hp2[(size_t)i * S + q].x,
+                                             hp1[(size_t)i * S + q].y + hp2[(size_t)i * S + q].y);
+          const double hn = std::sqrt(std::max(hp2[(size_t)(j + 1) * S + q].x, 0.0));
+          if (!std::isfinite(hn)) return fail(HEOM_ERR_NAN, "batch: non-finite Arnoldi norm");
+          Hc[(size_t)j * (m + 1) + j + 1] = hn;
+          cd *col = &Hc[(size_t)j * (m + 1)];
+          for (int i = 0; i < j; ++i) {
+            const double c = cs[(size_t)q * m + i];
+            const cd sv = sn[(size_t)q * m + i];
+            const cd tmp = c * col[i] + sv * col[i + 1];
+            col[i + 1] = -std::conj(sv) * col[i] + c * col[i + 1];
+            col[i] = tmp;
+          }
+          const cd aa = col[j], bb = col[j + 1];
+          const double na = std::abs(aa), nb = std::abs(bb);
+          double c;
+          cd sv, rr;
+          if (nb == 0.0) { c = 1.0; sv = 0.0; rr = aa; }
+          else if (na == 0.0) { c = 0.0; sv = std::conj(bb) / nb; rr = nb; }
+          else {
+            const double nrm = std::sqrt(na * na + nb * nb);
+            c = na / nrm;
+            sv = (aa / na) * std::conj(bb) / nrm;
+            rr = (aa / na) * nrm;
+          }
+          cs[(size_t)q * m + j] = c;
+          sn[(size_t)q * m + j] = sv;
+          col[j] = rr;
+          col[j + 1] = 0.0;
+          cd *gr = &g[(size_t)q * (m + 1)];
+          gr[j + 1] = -std::conj(sv) * gr[j];
+          gr[j] = c * gr[j];
+          kcol[q] = j + 1;
+          const double rel = bnorm[q] > 0 ? std::abs(gr[j + 1]) / bnorm[q] : 0.0;
+          if (rel <= tol * 0.5 || hn <= 1e-300 || iters[q] >= max_iter) ext[q] = 0;
+          else pin_sc[q] = 1.0 / hn;
+          more = more || ext[q];
+        }
+        if (!more) { ++j; break; }
+        // V_{j+1} = w / hn for the instances still extending; others stop here
+        HEOM_TRY(set_active(ext, s));
+        HEOM_HIP_CHECK(hipMemcpyAsync(sdev, pin_sc, sizeof(double) * S, hipMemcpyHostToDevice, s));
+        HEOM_TRY((seg_scale<T, T>(*b, w, sdev, V + (size_t)(j + 1) * n, s)));
+      }
+      // x += Z y per instance
+      int kmax = 0;
+      for (int q = 0; q < S; ++q) kmax = std::max(kmax, kcol[q]);
+      if (kmax > 0) {
+        std::vector<double2> yh((size_t)kmax * S, make_double2(0, 0));
+        for (int q = 0; q < S; ++q) {
+          const int k = kcol[q];
+          const cd *Hc = &H[((size_t)q * (m + 1)) * m];
+          std::vector<cd> y(k);
+          for (int i = k - 1; i >= 0; --i) {
+            cd acc = g[(size_t)q * (m + 1) + i];
+            for (int p = i + 1; p < k; ++p) acc -= Hc[(size_t)p * (m + 1) + i] * y[p];
+            const cd dgl = Hc[(size_t)i * (m + 1) + i];
+            y[i] = std::abs(dgl) > 0 ? acc / dgl : cd(0);
+          }
+          for (int i = 0; i < k; ++i) yh[(size_t)i * S + q] = make_double2(y[i].real(), y[i].imag());
+        }
+        std::vector<char> upd(S);
+        for (int q = 0; q < S; ++q) upd[q] = kcol[q] > 0;
+        HEOM_TRY(set_active(upd, s));
+        HEOM_HIP_CHECK(hipMemcpyAsync(hdev, yh.data(), sizeof(double2) * kmax * S, hipMemcpyHostToDevice, s));
+        HEOM_TRY(seg_update<T>(*b, Z, n, kmax, hdev, x, 1.0, s));
+        HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      }
+      x_is_zero = false;
+      for (int q = 0; q < S; ++q)
+        if (kcol[q] == 0 && act[q]) act[q] = 0;  // no progress possible (breakdown)
+      HEOM_TRY(set_active(act, s));
+    }
+    (void)it_total;
+    return HEOM_OK;
+  }
+};
+
+static heom_status batch_check(const heom_batch *b) {
+  if (!b) return fail(HEOM_ERR_ARG, "batch: NULL handle");
+  int dev = 0;
+  HEOM_HIP_CHECK(hipGetDevice(&dev));
+  if (dev != b->device) return fail(HEOM_ERR_ARG, "batch: tables live on another device");
+  return HEOM_OK;
+}
+
+}  // namespace heom
+
+// ----------------------------------------------------------------- ABI
+extern "C" {
+
+heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch **out) {
+  if (!out || n_inst <= 0 || !inst) return fail(HEOM_ERR_ARG, "batch_create: bad arguments");
+  *out = nullptr;
+  std::unique_ptr<heom_batch> b(new heom_batch());
+  b->S = n_inst;
+  b->inst.assign(inst, inst + n_inst);
+  HEOM_HIP_CHECK(hipGetDevice(&b->device));
+  b->off.assign(n_inst + 1, 0);
+  std::vector<BInst<double>> i64(n_inst);
+  std::vector<BInst<float>> i32(n_inst);
+  std::vector<double> cost(n_inst);
+  for (int s = 0; s < n_inst; ++s) {
+    if (!inst[s]) return fail(HEOM_ERR_ARG, "batch_create: NULL instance");
+    Hier &h = *inst[s]->impl;
+    if (h.d > 16) return fail(HEOM_ERR_UNSUPPORTED, "batch_create: instances need d <= 16");
+    HEOM_TRY(ensure_device(h));
+    const DeviceTables &D = h.dev;
+    b->off[s + 1] = b->off[s] + h.N * (int64_t)h.d * h.d;
+    BInst<double> a{};
+    a.tasks = D.base.tasks; a.groups = D.base.groups; a.gedges = D.base.gedges;
+    a.coef_op = D.coef_op; a.coef = D.coef64; a.ell_cnt = D.ell_cnt; a.ell_col = D.ell_col;
+    a.ell_val = D.ell_val64; a.decay = D.decay64; a.decay64 = D.decay64; a.hdiag64 = D.hdiag;
+    a.off = b->off[s]; a.slots = h.ell.slots; a.d = h.d;
+    i64[s] = a;
+    BInst<float> f{};
+    f.tasks = D.base.tasks; f.groups = D.base.groups; f.gedges = D.base.gedges;
+    f.coef_op = D.coef_op; f.coef = D.coef32; f.ell_cnt = D.ell_cnt; f.ell_col = D.ell_col;
+    f.ell_val = D.ell_val32; f.decay = D.decay32; f.decay64 = D.decay64; f.hdiag64 = D.hdiag;
+    f.off = b->off[s]; f.slots = h.ell.slots; f.d = h.d;
+    i32[s] = f;
+    cost[s] = (double)h.row_ptr.back() * h.d * h.d + (double)h.N * h.d * h.d;
+  }
+  b->n = b->off[n_inst];
+  // tiles: 256 / d^2 consecutive tasks of one instance
+  std::vector<std::vector<int4>> per(n_inst);
+  for (int s = 0; s < n_inst; ++s) {
+    const Hier &h = *inst[s]->impl;
+    const int tpb = std::max(1, 256 / (h.d * h.d));
+    for (int64_t t = 0; t < h.N; t += tpb)
+      per[s].push_back(make_int4(s, (int)t, (int)std::min<int64_t>(h.N, t + tpb), 0));
+  }
+  for (int s = 0; s < n_inst; ++s) b->tiles_inst.insert(b->tiles_inst.end(), per[s].begin(), per[s].end());
+  {
+    // interleaved: round-robin over instances, costliest (per tile) first
+    std::vector<int> ord(n_inst);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
+      return cost[p] / std::max<size_t>(1, per[p].size()) > cost[q] / std::max<size_t>(1, per[q].size());
+    });
+    std::vector<size_t> pos(n_inst, 0);
+    bool any = true;
+    while (any) {
+      any = false;
+      for (int s : ord)
+        if (pos[s] < per[s].size()) {
+          b->tiles_cost.push_back(per[s][pos[s]++]);
+          any = true;
+        }
+    }
+  }
+  b->n_tiles = (int)b->tiles_inst.size();
+  // chunks of at most 16384 elements inside each instance
+  std::vector<int64_t> che{0};
+  std::vector<int> chs;
+  b->seg_chunk_h.assign(n_inst + 1, 0);
+  for (int s = 0; s < n_inst; ++s) {
+    b->seg_chunk_h[s] = (int)chs.size();
+    for (int64_t e = b->off[s]; e < b->off[s + 1]; e += 16384) {
+      chs.push_back(s);
+      che.push_back(std::min<int64_t>(b->off[s + 1], e + 16384));
+    }
+  }
+  b->seg_chunk_h[n_inst] = (int)chs.size();
+  b->n_chunks = (int)chs.size();
+  HEOM_HIP_CHECK(hipMalloc(&b->inst64, sizeof(BInst<double>) * n_inst));
+  HEOM_HIP_CHECK(hipMalloc(&b->inst32, sizeof(BInst<float>) * n_inst));
+  HEOM_HIP_CHECK(hipMalloc(&b->tiles, sizeof(int4) * std::max(1, b->n_tiles)));
+  HEOM_HIP_CHECK(hipMalloc(&b->ch_e, sizeof(int64_t) * che.size()));
+  HEOM_HIP_CHECK(hipMalloc(&b->ch_seg, sizeof(int) * std::max<size_t>(1, chs.size())));
+  HEOM_HIP_CHECK(hipMalloc(&b->seg_chunk, sizeof(int) * (n_inst + 1)));
+  HEOM_HIP_CHECK(hipMalloc(&b->d_off, sizeof(int64_t) * (n_inst + 1)));
+  HEOM_HIP_CHECK(hipMalloc(&b->active, sizeof(int) * n_inst));
+  HEOM_HIP_CHECK(hipMemcpy(b->inst64, i64.data(), sizeof(BInst<double>) * n_inst, hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b->inst32, i32.data(), sizeof(BInst<float>) * n_inst, hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b->ch_e, che.data(), sizeof(int64_t) * che.size(), hipMemcpyHostToDevice));
+  if (!chs.empty()) HEOM_HIP_CHECK(hipMemcpy(b->ch_seg, chs.data(), sizeof(int) * chs.size(), hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b->seg_chunk, b->seg_chunk_h.data(), sizeof(int) * (n_inst + 1), hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice));
+  std::vector<int> ones(n_inst, 1);
+  HEOM_HIP_CHECK(hipMemcpy(b->active, ones.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice));
+  HEOM_TRY(batch_upload_tiles(*b));
+  *out = b.release();
+  return HEOM_OK;
+}
+
+void heom_batch_free(heom_batch *b) { delete b; }
+
+heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_tiles, int32_t *grid, int32_t *order) {
+  if (!b) return fail(HEOM_ERR_ARG, "batch_info: NULL handle");
+  if (offsets) std::copy(b->off.begin(), b->off.end(), offsets);
+  if (n_tiles) *n_tiles = b->n_tiles;
+  if (grid) *grid = b->grid;
+  if (order) *order = b->order;
+  return HEOM_OK;
+}
+
+heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t border,
+                             void *stream) {
+  HEOM_TRY(batch_check(b));
+  if (!x_dev || !y_dev) return fail(HEOM_ERR_ARG, "batch_apply: NULL vector");
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == HEOM_FP64) return batch_apply_T<double>(*b, x_dev, y_dev, border != 0, false, s);
+  if (precision == HEOM_FP32) return batch_apply_T<float>(*b, x_dev, y_dev, border != 0, false, s);
+  return fail(HEOM_ERR_ARG, "batch_apply: precision must be FP64 or FP32");
+}
+
+heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
+                            double *ms_default, double *ms_best, void *stream) {
+  HEOM_TRY(batch_check(b));
+  if (!x_dev || !y_dev || reps < 1) return fail(HEOM_ERR_ARG, "batch_tune: bad arguments");
+  if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_ERR_ARG, "batch_tune: precision");
+  hipStream_t s = (hipStream_t)stream;
+  int cus = 256;
+  {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, b->device) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
+  }
+  hipEvent_t e0, e1;
+  HEOM_HIP_CHECK(hipEventCreate(&e0));
+  HEOM_HIP_CHECK(hipEventCreate(&e1));
+  auto timeit = [&](float &ms) -> heom_status {
+    for (int r = 0; r < 2; ++r)
+      HEOM_TRY(heom_batch_apply(b, precision, x_dev, y_dev, 0, stream));
+    HEOM_HIP_CHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r)
+      HEOM_TRY(heom_batch_apply(b, precision, x_dev, y_dev, 0, stream));
+    HEOM_HIP_CHECK(hipEventRecord(e1, s));
+    HEOM_HIP_CHECK(hipEventSynchronize(e1));
+    HEOM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    return HEOM_OK;
+  };
+  const int grids[] = {0, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
+  float best = 1e30f, def = 0.f;
+  int bg = 0, bo = 0;
+  heom_status st = HEOM_OK;
+  for (int o = 0; o < 2 && st == HEOM_OK; ++o) {
+    b->order = o;
+    if ((st = batch_upload_tiles(*b)) != HEOM_OK) break;
+    for (int g : grids) {
+      b->grid = g;
+      float ms = 0.f;
+      if ((st = timeit(ms)) != HEOM_OK) break;
+      if (o == 0 && g == 0) def = ms;
+      if (ms < best) { best = ms; bg = g; bo = o; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->order = bo;
+  b->grid = bg;
+  HEOM_TRY(batch_upload_tiles(*b));
+  HEOM_TRY(st);
+  if (ms_default) *ms_default = def;
+  if (ms_best) *ms_best = best;
+  return HEOM_OK;
+}
+
+heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opts *o, size_t *bytes) {
+  if (!b || !bytes) return fail(HEOM_ERR_ARG, "batch_workspace_size: NULL argument");
+  heom_solver_opts d;
+  if (!o) { heom_default_opts(&d); o = &d; }
+  const size_t v64 = (size_t)b->n * 16, v32 = (size_t)b->n * 8;
+  size_t need = v64 + 4096;  // right-hand side
+  // the Jacobi pass (first choice, or the fallback pass) keeps the Z basis
+  const bool jac = o->precond == HEOM_PREC_JACOBI || o->fallback;
+  if (o->mode == HEOM_SOLVE_FP32_IR) need += v64 + 2 * v32 + BatchGmres<float>::bytes(*b, o->restart, jac);
+  else need += BatchGmres<double>::bytes(*b, o->restart, jac);
+  need += (size_t)b->S * sizeof(double) + 256;
+  *bytes = need + 8 * 256;
+  return HEOM_OK;
+}
+
+heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
+                              int32_t use_graph, void *ws, size_t ws_bytes, void *stream) {
+  HEOM_TRY(batch_check(b));
+  if (!x_dev || !o || !ws) return fail(HEOM_ERR_ARG, "batch_steady: NULL argument");
+  if (o->restart < 1 || o->restart > 1000 || o->max_iter < 1 || !(o->tol > 0)) return fail(HEOM_ERR_ARG, "batch_steady: bad options");
+  if (o->precond != HEOM_PREC_JACOBI && o->precond != HEOM_PREC_NONE)
+    return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: Jacobi or no preconditioning only");
+  const bool jac = o->precond == HEOM_PREC_JACOBI;
+  if (o->mode != HEOM_SOLVE_FP64 && o->mode != HEOM_SOLVE_FP32_IR) return fail(HEOM_ERR_ARG, "batch_steady: mode");
+  for (heom_hier *h : b->inst)
+    if (h->impl->parity != 1) return fail(HEOM_ERR_ARG, "batch_steady: every instance must be even parity");
+  hipStream_t s = (hipStream_t)stream;
+  const int S = b->S;
+  const int64_t n = b->n;
+  auto t0 = std::chrono::steady_clock::now();
+  WsArena arena(ws, ws_bytes);
+  double2 *rhs = (double2 *)arena.take(sizeof(double2) * n);
+  if (!rhs) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small");
+  HEOM_TRY(seg_zero<double>(rhs, n, s));
+  hipLaunchKernelGGL(seg_unit_kernel, dim3((S + 255) / 256), dim3(256), 0, s, rhs, b->d_off, S);
+  HEOM_HIP_CHECK(hipGetLastError());
+  std::vector<int> iters(S, 0), refines(S, 0);
+  std::vector<double> res(S, 0.0);
+  std::vector<char> conv(S, 0);
+  int64_t applies = 0;
+  // One pass solves the instances flagged in `want` (from zero unless
+  // from_x) with or without the Jacobi preconditioner.
+  auto run_pass = [&](bool jac_pass, std::vector<char> want, bool from_x) -> heom_status {
+    WsArena arena2(ws, ws_bytes);
+    arena2.take(sizeof(double2) * n);  // rhs
+    if (o->mode == HEOM_SOLVE_FP64) {
+      BatchGmres<double> gm;
+      HEOM_TRY(gm.init(*b, arena2, o->restart, use_graph != 0, jac_pass));
+      std::vector<int> it;
+      std::vector<double> rs;
+      std::vector<char> cv;
+      HEOM_TRY(gm.solve(rhs, (double2 *)x_dev, want, o->tol, o->max_iter, 1, !from_x, it, rs, cv, applies, s));
+      for (int q = 0; q < S; ++q)
+        if (want[q]) { iters[q] += it[q]; res[q] = rs[q]; conv[q] = cv[q]; }
+      return HEOM_OK;
+    }
+    double2 *r64 = (double2 *)arena2.take(sizeof(double2) * n);
+    float2 *r32 = (float2 *)arena2.take(sizeof(float2) * n);
+    float2 *d32 = (float2 *)arena2.take(sizeof(float2) * n);
+    if (!r64 || !r32 || !d32) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small");
+    BatchGmres<float> gm;
+    HEOM_TRY(gm.init(*b, arena2, o->restart, use_graph != 0, jac_pass));
+    const std::vector<double> bn(S, 1.0);  // |e_0| = 1 for every instance
+    std::vector<int> it0(S, 0);
+    for (int ref = 0;; ++ref) {
+      // r64 = rhs - B x (FP64) on every instance still refining
+      HEOM_TRY(gm.set_active(want, s));
+      HEOM_TRY(batch_apply_T<double>(*b, x_dev, r64, 1, true, s));
+      ++applies;
+      HEOM_TRY((axpby<double, double>(rhs, 1.0, r64, -1.0, n, s)));
+      HEOM_TRY(seg_mdot<double>(*b, r64, 0, 1, r64, gm.partial, gm.hdev, s));
+      HEOM_HIP_CHECK(hipMemcpyAsync(gm.pin_h, gm.hdev, sizeof(double2) * S, hipMemcpyDeviceToHost, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      bool any = false;
+      for (int q = 0; q < S; ++q) {
+        if (!want[q]) continue;
+        const double rel = std::sqrt(std::max(gm.pin_h[q].x, 0.0)) / bn[q];
+        if (!std::isfinite(rel)) return fail(HEOM_ERR_NAN, "batch_steady: non-finite residual");
+        res[q] = rel;
+        if (rel <= o->tol) { conv[q] = 1; want[q] = 0; }
+        else if (ref >= o->max_refine || it0[q] >= o->max_iter) want[q] = 0;
+        any = any || want[q];
+      }
+      if (!any) break;
+      // r32 = r64 / |r64| per instance, d32 = 0, inner FP32 solve, x += |r64| d32
+      for (int q = 0; q < S; ++q) {
+        const double nr = res[q] * bn[q];
+        gm.pin_sc[q] = want[q] && nr > 0 ? 1.0 / nr : 0.0;
+      }
+      HEOM_HIP_CHECK(hipMemcpyAsync(gm.sdev, gm.pin_sc, sizeof(double) * S, hipMemcpyHostToDevice, s));
+      HEOM_TRY((seg_scale<double, float>(*b, r64, gm.sdev, r32, s)));
+      HEOM_TRY(seg_zero<float>(d32, n, s));
+      std::vector<int> it_in;
+      std::vector<double> res_in;
+      std::vector<char> conv_in;
+      const int cap = std::max(4 * o->restart, 120);
+      HEOM_TRY(gm.solve(r32, d32, want, o->inner_tol, cap, 1, true, it_in, res_in, conv_in, applies, s));
+      for (int q = 0; q < S; ++q) {
+        if (!want[q]) { gm.pin_sc[q] = 0.0; continue; }
+        iters[q] += it_in[q];
+        it0[q] += it_in[q];
+        ++refines[q];
+        gm.pin_sc[q] = res[q] * bn[q];
+      }
+      HEOM_HIP_CHECK(hipMemcpyAsync(gm.sdev, gm.pin_sc, sizeof(double) * S, hipMemcpyHostToDevice, s));
+      HEOM_TRY((seg_axpy<float, double>(*b, d32, gm.sdev, x_dev, s)));
+    }
+    return HEOM_OK;
+  };
+  if (!o->use_x0) HEOM_TRY(seg_zero<double>(x_dev, n, s));
+  HEOM_TRY(run_pass(jac, std::vector<char>(S, 1), o->use_x0 != 0));
+  std::vector<char> fell(S, 0);
+  if (o->fallback) {
+    // instances that missed the tolerance: again from zero with the other choice
+    std::vector<char> again(S, 0);
+    bool any = false;
+    std::vector<double> keep(S);
+    for (int q = 0; q < S; ++q) {
+      again[q] = !conv[q];
+      any = any || again[q];
+      keep[q] = conv[q] ? 1.0 : 0.0;
+    }
+    if (any) {
+      // (kd is consumed before the second pass reuses this part of the workspace)
+      double *kd = (double *)arena.take(sizeof(double) * S);
+      if (!kd) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small");
+      HEOM_HIP_CHECK(hipMemcpyAsync(kd, keep.data(), sizeof(double) * S, hipMemcpyHostToDevice, s));
+      HEOM_TRY((seg_scale<double, double>(*b, x_dev, kd, x_dev, s)));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      fell = again;
+      HEOM_TRY(run_pass(!jac, again, false));
+    }
+  }
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<int> ones(S, 1);
+  HEOM_HIP_CHECK(hipMemcpy(b->active, ones.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool ok = true;
+  for (int q = 0; q < S; ++q) {
+    ok = ok && conv[q];
+    if (r) {
+      std::memset(&r[q], 0, sizeof(r[q]));
+      r[q].status = conv[q] ? HEOM_OK : HEOM_ERR_NOT_CONVERGED;
+      r[q].iterations = iters[q];
+      r[q].refinements = refines[q];
+      r[q].true_residual = res[q];
+      r[q].seconds = secs;
+      r[q].applies = applies;
+      r[q].fell_back = fell[q];
+    }
+  }
+  return ok ? HEOM_OK : fail(HEOM_ERR_NOT_CONVERGED, "batch_steady: some instances did not reach the tolerance");
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""Batched instances on the GPU: one launch for the apply of many uneven
+hierarchies, the batched stationary-state solver (FP64 and FP32 with FP64
+refinement, eager and hipGraph-replayed), and the launch autotuner.
+
+References: the single-instance library path (itself parity-checked against
+the oracle in test_apply_gpu / test_solvers_gpu) and, for small instances,
+the oracle directly."""
+import numpy as np
+import pytest
+
+from oracle.liouvillian import from_blocks, to_blocks
+from oracle.solvers import steady_state as oracle_steady
+from paper_2306_07522_amd import workloads as wl
+from tests.helpers import oracle_model, oracle_to_library_perm
+
+pytestmark = pytest.mark.gpu
+
+_INST = None
+
+
+def _instances():
+    global _INST
+    if _INST is None:
+        _INST = wl.batch_instances(512, seed=4242)
+    return _INST
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _build(cfgs):
+    from paper_2306_07522_amd import api
+    hs = [api.Hierarchy(c["H"], c["baths"], c["m_max"], c["n_max"], parity_op=c.get("parity_op")) for c in cfgs]
+    return hs, api.Batch(hs)
+
+
+def _pick(n, max_n_ado=4000):
+    """First n instances with at most max_n_ado ADOs (all four d values occur)."""
+    from paper_2306_07522_amd import api
+    out = []
+    for c in _instances():
+        h = api.Hierarchy(c["H"], c["baths"], c["m_max"], c["n_max"], parity_op=c.get("parity_op"))
+        ok = h.N <= max_n_ado
+        h.close()
+        if ok:
+            out.append(c)
+        if len(out) == n:
+            break
+    return out
+
+
+def _pick_converging(n, precond="none", max_n_ado=4000, restart=40):
+    """First n instances whose single-instance solve converges to 1e-12 with
+    this preconditioner (the reference for the batched solve)."""
+    from paper_2306_07522_amd import api
+    out = []
+    for c in _instances():
+        h = api.Hierarchy(c["H"], c["baths"], c["m_max"], c["n_max"], parity_op=c.get("parity_op"))
+        if h.N <= max_n_ado:
+            x, rep = api.steady_state(h, tol=1e-12, restart=restart, max_iter=3000, precond=precond,
+                                      allow_not_converged=True)
+            if rep["status"] == 0:
+                out.append((c, x))
+        h.close()
+        if len(out) == n:
+            break
+    return out
+
+
+def _rel(a, b):
+    return (a - b).abs().max().item() / max(b.abs().max().item(), 1e-300)
+
+
+@pytest.mark.parametrize("border", [0, 1])
+def test_batch_apply_matches_single_instance_applies(border):
+    torch = _torch()
+    from paper_2306_07522_amd import api
+    cfgs = _pick(40)
+    assert {c["d"] for c in cfgs} == {2, 4, 8, 16}
+    hs, b = _build(cfgs)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn(b.n, dtype=torch.complex128, device="cuda", generator=g)
+    y = b.apply(x, border=border)
+    y32 = b.apply(x.to(torch.complex64), border=border)
+    for h, xs, ys, ys32 in zip(hs, b.split(x), b.split(y), b.split(y32)):
+        ref = api.apply_steady_operator(h, xs.contiguous()) if border else h.apply(xs.contiguous())
+        assert _rel(ys, ref) <= 1e-12
+        assert _rel(ys32.to(torch.complex128), ref) <= 1e-5
+
+
+def test_batch_apply_matches_oracle():
+    torch = _torch()
+    cfgs = [c for c in _pick(60, max_n_ado=300) if c["d"] <= 8][:6]
+    hs, b = _build(cfgs)
+    rng = np.random.default_rng(5)
+    xs = [wl.random_vector(rng, h.N, h.d) for h in hs]
+    x = torch.from_numpy(np.concatenate([v.reshape(-1) for v in xs])).cuda()
+    y = b.apply(x).cpu().numpy()
+    for s, (c, h) in enumerate(zip(cfgs, hs)):
+        om = oracle_model(c)
+        perm = oracle_to_library_perm(om, h)
+        ys = y[b.offsets[s]: b.offsets[s + 1]].reshape(h.N, h.d, h.d)
+        ref = to_blocks(om.assemble() @ from_blocks(xs[s][perm]), om.N, om.d)
+        assert np.abs(ys[perm] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+def test_batch_steady_matches_single_solves(mode):
+    torch = _torch()
+    from paper_2306_07522_amd import api
+    picked = _pick_converging(16)
+    cfgs = [c for c, _ in picked]
+    assert len({c["d"] for c in cfgs}) >= 3
+    hs, b = _build(cfgs)
+    tol = 1e-11 if mode == "fp64" else 1e-9
+    x, reps = b.steady_state(tol=tol, restart=40, max_iter=4000, mode=mode, precond="none", fallback=0)
+    assert all(r["status"] == 0 and r["true_residual"] <= tol for r in reps), reps
+    for h, xs, (_, xr) in zip(hs, b.split(x), picked):
+        assert _rel(xs, xr) <= (1e-8 if mode == "fp64" else 1e-6)
+        # judged by the plain FP64 apply
+        r = api.steady_residual(h, xs.contiguous())
+        assert r.abs().pow(2).sum().sqrt().item() <= 10 * tol
+
+
+def test_batch_jacobi_matches_single_jacobi_iterations():
+    """Same preconditioner, same arithmetic order per instance: the batched
+    solver takes the single solver's iterations."""
+    torch = _torch()
+    from paper_2306_07522_amd import api
+    picked = _pick_converging(8, precond="jacobi")
+    cfgs = [c for c, _ in picked]
+    hs, b = _build(cfgs)
+    x, reps = b.steady_state(tol=1e-10, restart=40, max_iter=3000, precond="jacobi", fallback=0)
+    for h, xs, rep in zip(hs, b.split(x), reps):
+        xr, r1 = api.steady_state(h, tol=1e-10, restart=40, max_iter=3000, precond="jacobi")
+        assert rep["status"] == 0 and abs(rep["iterations"] - r1["iterations"]) <= 1
+        assert _rel(xs, xr) <= 1e-8
+
+
+def test_batch_steady_matches_oracle_direct_solve():
+    torch = _torch()
+    cfgs = [c for c in _pick(60, max_n_ado=120) if c["d"] <= 4][:4]
+    hs, b = _build(cfgs)
+    x, reps = b.steady_state(tol=1e-12, restart=40, max_iter=4000, precond="none", fallback=1)
+    assert all(r["status"] == 0 for r in reps), reps
+    for s, (c, h) in enumerate(zip(cfgs, hs)):
+        om = oracle_model(c)
+        perm = oracle_to_library_perm(om, h)
+        ref = to_blocks(oracle_steady(om.assemble(), om.d), om.N, om.d)
+        xs = x[b.offsets[s]: b.offsets[s + 1]].cpu().numpy().reshape(h.N, h.d, h.d)[perm]
+        assert np.abs(xs - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_batch_graph_replay_equals_eager():
+    torch = _torch()
+    cfgs = [c for c, _ in _pick_converging(16)]
+    hs, b = _build(cfgs)
+    kw = dict(tol=1e-9, restart=40, max_iter=4000, mode="fp32_ir", precond="none", fallback=0,
+              allow_not_converged=True)
+    xe, re = b.steady_state(use_graph=False, **kw)
+    xg, rg = b.steady_state(use_graph=True, **kw)
+    xg2, _ = b.steady_state(use_graph=True, **kw)
+    assert sum(r["status"] == 0 for r in re) >= 12
+    assert [r["iterations"] for r in re] == [r["iterations"] for r in rg]
+    assert torch.equal(xe, xg) and torch.equal(xg, xg2)
+
+
+def test_autotuner_keeps_results():
+    torch = _torch()
+    cfgs = _pick(64)
+    hs, b = _build(cfgs)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    x = torch.randn(b.n, dtype=torch.complex64, device="cuda", generator=g)
+    y0 = b.apply(x)
+    t = b.tune("fp32", reps=3)
+    assert t["ms_best"] <= t["ms_default"] * 1.05 and t["grid"] >= 0 and t["order"] in (0, 1)
+    y1 = b.apply(x)
+    assert torch.equal(y0, y1)
+
+
+def test_full_batch_of_512_instances():
+    """The full seeded batch (512 instances, d in {2,4,8,16}, tiers 2-6, 3-12
+    exponents) in FP32 with FP64 refinement, no preconditioner first and
+    Jacobi for the instances that miss 1e-8.  Restarted GMRES does not
+    reach 1e-8 on every weakly damped spin-boson instance within the
+    iteration cap: the test checks that every converged report is true
+    (plain FP64 single-instance apply on a sample), that the Anderson
+    family converges, and that at least half of the batch does."""
+    torch = _torch()
+    from paper_2306_07522_amd import api
+    cfgs = _instances()
+    hs, b = _build(cfgs)
+    b.tune("fp32", reps=2)
+    x, reps = b.steady_state(tol=1e-8, restart=30, max_iter=2400, mode="fp32_ir", precond="none", fallback=1,
+                             allow_not_converged=True)
+    conv = np.array([r["status"] == 0 for r in reps])
+    fam = np.array([c["family"] for c in cfgs])
+    assert conv.sum() >= 256, conv.sum()
+    assert conv[fam == "anderson"].mean() >= 0.99
+    for r in reps:
+        assert (r["status"] == 0) == (r["true_residual"] <= 1e-8)
+    views = b.split(x)
+    idx = np.flatnonzero(conv)
+    for s in np.random.default_rng(1).choice(idx, 12, replace=False):
+        r = api.steady_residual(hs[s], views[s].contiguous())
+        assert r.abs().pow(2).sum().sqrt().item() <= 1.5e-8
+    print(f"\nbatch: {b.n} elements, {conv.sum()} of {len(conv)} converged "
+          f"(fell back {sum(r['fell_back'] for r in reps)}), {reps[0]['seconds']:.2f} s")
