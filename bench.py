@@ -15,7 +15,9 @@ reported under "solves": the stationary state of the same tier-4 model
 (network trained on pairs from seeded tier-3 perturbations of it), the
 stationary state of the single-impurity Anderson model (tier 3, 10,701
 ADOs; network trained on pairs from seeded perturbations), and a sample
-of its density of states.  Training time is reported beside each network.
+of its density of states.  Training time is reported beside each network;
+GMRES without a preconditioner is timed too.  "batch_512_instances" times
+the batched path on 512 seeded uneven instances.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32]
                        [--solves all|siam|none]
@@ -154,6 +156,10 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     """Stationary state to a 1e-8 true residual: Jacobi GMRES vs FGMRES with
     the network (which hands over to Jacobi if it stagnates)."""
     h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    (x_0, r0), t0 = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=restart, mode=mode,
+                                                     max_iter=20000, allow_not_converged=True))
+    del x_0
+    _progress(f"{cfg['name']} N={h.N} steady, GMRES without preconditioner: {r0['iterations']} iterations, {t0:.2f} s")
     (x_p, rp), tp = _timed(lambda: api.steady_state(h, tol=1e-8, precond="jacobi", restart=restart, mode=mode,
                                                      max_iter=20000, allow_not_converged=True))
     del x_p
@@ -170,17 +176,20 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     net.close()
     _progress(f"{cfg['name']} N={h.N} steady, NN FGMRES: {rn['iterations']} iterations, {tn:.2f} s, "
               f"fell back {rn['fell_back']}")
+    best = min([t for t, r in ((t0, r0), (tp, rp)) if r["status"] == 0], default=None)
     out = {"n_ado": h.N, "d": h.d, "restart": restart, "mode": mode, "nn_max_iter": cap,
-           "plain_jacobi": _solve_record(rp, tp),
+           "plain_none": _solve_record(r0, t0), "plain_jacobi": _solve_record(rp, tp),
            "nn_fgmres": _solve_record(rn, tn), "network": {"hidden": hidden, **info},
-           "nn_speedup": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None}
+           "nn_speedup_vs_jacobi": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None,
+           "nn_speedup_vs_best_plain": round(best / tn, 4) if best and tn > 0 and rn["status"] == 0 else None}
     h.close()
     return out
 
 
 def dos_sample(api, wl, n_omega=64):
     """Density of states of the tier-3 SIAM at n_omega frequencies of its
-    2000-point grid (Jacobi GMRES, FP64, 1e-8 per solve)."""
+    2000-point grid (Jacobi GMRES, FP64, 1e-8 per solve; 2 solves per
+    frequency)."""
     import numpy as np
     cfg = wl.siam()
     he = api.Hierarchy(cfg["H"], cfg["baths"], 0, cfg["n_max"], parity=+1, parity_op=cfg["parity_op"])
@@ -193,6 +202,108 @@ def dos_sample(api, wl, n_omega=64):
             "omega_per_s": round(len(om) / t, 2), "finite": bool(np.all(np.isfinite(A)))}
 
 
+def batch_benchmark(api, wl):
+    """512 seeded uneven instances (spin-boson / Anderson, d in {2,4,8,16},
+    tiers 2-6, 3-12 exponents): one batched apply against 512 single
+    launches, the autotuned launch, and every stationary state in FP32 with
+    FP64 refinement to 1e-8 (no preconditioner, Jacobi for the instances
+    that miss it), hipGraph-replayed Arnoldi steps."""
+    import torch
+    cfgs = wl.batch_instances(512, seed=4242)
+    hs = [api.Hierarchy(c["H"], c["baths"], c["m_max"], c["n_max"], parity_op=c.get("parity_op")) for c in cfgs]
+    b = api.Batch(hs)
+    tune = b.tune("fp32", reps=5)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(b.n, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    xs, ys = b.split(x), b.split(y)
+    for _ in range(2):
+        b.apply(x, y)
+        for h, a, c in zip(hs, xs, ys):
+            h.apply(a, c)
+    reps = 5
+    _, t_batch = _timed(lambda: [b.apply(x, y) for _ in range(reps)])
+    _, t_single = _timed(lambda: [[h.apply(a, c) for h, a, c in zip(hs, xs, ys)] for _ in range(reps)])
+    edges = sum(h.info.n_edges for h in hs)
+    nbytes = 2 * b.n * 8 + 8 * (sum(h.N for h in hs) + len(hs)) + 8 * edges + 8 * sum(h.N for h in hs)
+    del x, y, xs, ys
+    _progress(f"batch apply: {t_batch / reps * 1e3:.3f} ms vs {t_single / reps * 1e3:.3f} ms for 512 single launches")
+    (xb, rb), tb = _timed(lambda: b.steady_state(tol=1e-8, restart=30, max_iter=2400, mode="fp32_ir", precond="none",
+                                                 fallback=1, use_graph=True, allow_not_converged=True))
+    del xb
+    conv = [r["status"] == 0 for r in rb]
+    fam = [c["family"] for c in cfgs]
+    _progress(f"batch steady: {sum(conv)} of {len(conv)} converged in {tb:.1f} s")
+    out = {"n_instances": len(hs), "n_elements": b.n, "fp32_vector_mb": round(b.n * 8 / 1e6, 1),
+           "apply_ms_batched": round(t_batch / reps * 1e3, 4), "apply_ms_512_single_launches": round(t_single / reps * 1e3, 4),
+           "apply_gbs_batched": round(nbytes / (t_batch / reps) / 1e9, 2),
+           "tuner": {"ms_default": round(tune["ms_default"], 4), "ms_best": round(tune["ms_best"], 4),
+                     "grid": tune["grid"], "order": tune["order"]},
+           "steady": {"seconds": round(tb, 3), "tol": 1e-8, "mode": "fp32_ir", "restart": 30, "max_iter": 2400,
+                      "converged": int(sum(conv)),
+                      "converged_anderson": int(sum(c for c, f in zip(conv, fam) if f == "anderson")),
+                      "converged_spin_boson": int(sum(c for c, f in zip(conv, fam) if f == "spin_boson")),
+                      "fell_back_to_jacobi": int(sum(r["fell_back"] for r in rb)),
+                      "max_iterations": int(max(r["iterations"] for r in rb))}}
+    b.close()
+    for h in hs:
+        h.close()
+    return out
+
+
+def propagation_benchmarks(api, wl):
+    """RK4 on the paper's workloads: the spin-boson model (35 ADOs, 2,000
+    steps of dt = 0.01, eager launches and hipGraph-captured steps) and the
+    charge-cavity model (3,165 ADOs of 20x20, t = 0 -> 200 with dt = 0.01,
+    20,000 steps), both FP64, rho_0 saved every step."""
+    import numpy as np
+    import torch
+    out = {}
+    cfg = wl.spin_boson()
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"])
+    x0 = torch.zeros((h.N, h.d, h.d), dtype=torch.complex128, device="cuda")
+    x0[0] = torch.from_numpy(cfg["rho0"]).cuda()
+    rec = {"n_ado": h.N, "d": h.d, "steps": cfg["n_steps"], "dt": cfg["dt"]}
+    for name, gs in (("eager", 0), ("graph", 100)):
+        x = x0.clone()
+        api.propagate(h, x, cfg["dt"], 100, save_every=1, graph_steps=gs)  # warm-up (and graph build)
+        x = x0.clone()
+        traj, t = _timed(lambda: api.propagate(h, x, cfg["dt"], cfg["n_steps"], save_every=1, graph_steps=gs))
+        rec[f"us_per_step_{name}"] = round(t / cfg["n_steps"] * 1e6, 3)
+        rec[f"trace_rho0_end_{name}"] = float(torch.diagonal(traj[-1]).sum().real.item())
+    out["spin_boson_rk4"] = rec
+    _progress(f"spin-boson RK4: {rec['us_per_step_eager']:.1f} us/step eager, {rec['us_per_step_graph']:.1f} us/step graph")
+    h.close()
+    cfg = wl.charge_cavity()
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    rng = np.random.default_rng(0)
+    rho = np.diag(rng.uniform(size=h.d)).astype(np.complex128)
+    rho /= np.trace(rho)
+    x = torch.zeros((h.N, h.d, h.d), dtype=torch.complex128, device="cuda")
+    x[0] = torch.from_numpy(rho).cuda()
+    n_steps, dt = 20000, 0.01
+    api.propagate(h, x.clone(), dt, 50, graph_steps=50)
+    traj, t = _timed(lambda: api.propagate(h, x, dt, n_steps, save_every=100, graph_steps=100))
+    step_bytes = 4 * algorithmic_bytes(h, 16) + 6 * h.N * h.d * h.d * 16
+    out["charge_cavity_rk4"] = {"n_ado": h.N, "d": h.d, "steps": n_steps, "dt": dt, "seconds": round(t, 3),
+                                "us_per_step": round(t / n_steps * 1e6, 3),
+                                "gbs_algorithmic": round(step_bytes * n_steps / t / 1e9, 2),
+                                "cache_resident": True,
+                                "trace_rho0_end": float(torch.diagonal(traj[-1]).sum().real.item())}
+    _progress(f"charge-cavity RK4: {n_steps} steps in {t:.2f} s")
+    # cavity power spectrum at its 1024 frequencies
+    he = h
+    xs, _ = api.steady_state(he, tol=1e-10)
+    (S, rep), t = _timed(lambda: api.spectrum(he, None, xs, cfg["aop"], cfg["omegas"], kind="psd", tol=1e-8,
+                                              rhs_chunk=64))
+    out["charge_cavity_psd"] = {"n_omega": len(cfg["omegas"]), "seconds": round(t, 3),
+                                "omega_per_s": round(len(cfg["omegas"]) / t, 2), "iterations": rep["iterations"],
+                                "true_residual": rep["true_residual"], "finite": bool(np.all(np.isfinite(S)))}
+    _progress(f"charge-cavity PSD at {len(cfg['omegas'])} frequencies: {t:.2f} s")
+    h.close()
+    return out
+
+
 def solve_benchmarks(which):
     import numpy as np
     from paper_2306_07522_amd import api, workloads as wl
@@ -202,11 +313,13 @@ def solve_benchmarks(which):
         z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(4))
         siam_train.append(wl.siam(eps=-5.0 * z[0], U=10.0 * z[1], Gamma=2.0 * z[2], mus=(z[3], -z[3])))
     out["siam_tier3_steady"] = steady_comparison(api, wl, wl.siam(), siam_train, 4, 128, 30, "fp64", (10, 30, 60), 30)
-    out["siam_tier3_dos"] = dos_sample(api, wl)
+    out["siam_tier3_dos"] = dos_sample(api, wl, n_omega=2000)
     if which == "all":
+        out.update(propagation_benchmarks(api, wl))
         train = [wl.perturbed_two_orbital(1000 + s, n_max=3) for s in range(3)]
         out["two_orbital_tier4_steady"] = steady_comparison(api, wl, wl.two_orbital_anderson(), train, 16, 256, 100,
                                                             "fp64", (20, 60), 100)
+        out["batch_512_instances"] = batch_benchmark(api, wl)
     return out
 
 

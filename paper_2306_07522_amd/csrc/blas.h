@@ -9,10 +9,11 @@ namespace heom {
 template <typename T>
 heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, int R, double2 *partial, int nchunk,
                  double2 *out, hipStream_t s);
-// w += sign * sum_i V_i h_i (per right-hand side)
+// w += sign * sum_i V_i h_i (per right-hand side), then w *= post[r].x when
+// post is given (fused normalisation)
 template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
-                         hipStream_t s);
+                         hipStream_t s, const double2 *post = nullptr);
 template <typename T>
 heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s);
 template <typename TX, typename TY>

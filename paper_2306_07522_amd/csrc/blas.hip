@@ -85,7 +85,8 @@ __global__ void reduce_partials_kernel(const double2 *__restrict__ partial, int 
 template <typename T>
 __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
                                                            const double2 *__restrict__ h, typename Cplx<T>::t *__restrict__ w,
-                                                           int64_t n, int R, double sign) {
+                                                           int64_t n, int R, double sign,
+                                                           const double2 *__restrict__ post) {
   using T2 = typename Cplx<T>::t;
   const int64_t total = n * R;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -98,8 +99,13 @@ __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T
       sy += (double)a.x * c.y + (double)a.y * c.x;
     }
     T2 o = w[idx];
-    o.x = (T)((double)o.x + sign * sx);
-    o.y = (T)((double)o.y + sign * sy);
+    double ox = (double)o.x + sign * sx, oy = (double)o.y + sign * sy;
+    if (post) {  // fused normalisation: real scale per right-hand side
+      ox *= post[r].x;
+      oy *= post[r].x;
+    }
+    o.x = (T)ox;
+    o.y = (T)oy;
     w[idx] = o;
   }
 }
@@ -277,10 +283,10 @@ heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, in
 
 template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
-                         hipStream_t s) {
-  if (k <= 0) return HEOM_OK;
+                         hipStream_t s, const double2 *post) {
+  if (k <= 0 && !post) return HEOM_OK;
   hipLaunchKernelGGL(basis_update_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
-                     k, h, (typename Cplx<T>::t *)w, n, R, sign);
+                     k, h, (typename Cplx<T>::t *)w, n, R, sign, post);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -356,7 +362,7 @@ heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const
   template heom_status mdot<T>(const void *, int64_t, int, const void *, int64_t, int, double2 *, int, double2 *, \
                                hipStream_t);                                                                       \
   template heom_status basis_update<T>(const void *, int64_t, int, const double2 *, void *, int64_t, int, double,  \
-                                       hipStream_t);                                                               \
+                                       hipStream_t, const double2 *);                                              \
   template heom_status scale_vec<T>(const void *, const double2 *, void *, int64_t, int, hipStream_t);             \
   template heom_status jacobi<T>(const void *, void *, const Hier &, int, const double2 *, int, hipStream_t);       \
   template heom_status rk4_combine<T>(void *, const void *, const void *, const void *, const void *, double,      \

@@ -155,38 +155,89 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
     int j = 0;
     for (; j < m && iters < max_iter; ++j, ++iters) {
       T2 *vj = V + (size_t)j * nr;
-      T2 *zj = flexible ? Z + (size_t)j * nr : t;
-      if (P) {
-        HEOM_TRY(P(vj, zj, flexible));
-      } else {
-        HEOM_HIP_CHECK(hipMemcpyAsync(zj, vj, sizeof(T2) * nr, hipMemcpyDeviceToDevice, s));
-      }
-      HEOM_TRY(A(zj, w));
+      T2 *vn = V + (size_t)(j + 1) * nr;  // w = A z_j is built in the next basis slot
+      T2 *zj = P ? (flexible ? Z + (size_t)j * nr : t) : vj;
+      if (P) HEOM_TRY(P(vj, zj, flexible));
+      HEOM_TRY(A(zj, vn));
       ++st.applies;
-      // CGS2
+      // Classical Gram-Schmidt with selective reorthogonalisation (the test
+      // of Daniel, Gragg, Kaufman and Stewart): one pass gives h = V^H w and
+      // |w|^2 together, and |w - V h|^2 follows by Pythagoras.  When the
+      // projection removed more than half of |w|^2 a second pass re-projects;
+      // otherwise the update and the normalisation are one fused pass.
       double2 *h1 = hdev, *h2 = hdev + (size_t)(m + 2) * R;
-      HEOM_TRY(mdot<T>(V, nr, j + 1, w, n, R, partial, nchunk, h1, s));
-      HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, w, n, R, -1.0, s));
-      HEOM_TRY(mdot<T>(V, nr, j + 1, w, n, R, partial, nchunk, h2, s));
-      HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, w, n, R, -1.0, s));
-      HEOM_TRY(mdot<T>(w, 0, 1, w, n, R, partial, nchunk, h2 + (size_t)(j + 1) * R, s));
-      HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, hdev, sizeof(double2) * 2 * (m + 2) * R, hipMemcpyDeviceToHost, s));
+      const size_t hb = sizeof(double2) * (size_t)(j + 2) * R;
+      HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h1, s));
+      HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, hb, hipMemcpyDeviceToHost, s));
       HEOM_HIP_CHECK(hipStreamSynchronize(s));
-      const double2 *hp1 = (const double2 *)pin.p;
-      const double2 *hp2 = hp1 + (size_t)(m + 2) * R;
-      std::vector<double2> scv(R);
+      std::vector<double2> hv1((size_t)(j + 2) * R), hv2((size_t)(j + 2) * R, make_double2(0.0, 0.0));
+      std::memcpy(hv1.data(), pin.p, hb);
+      auto sumsq = [&](const std::vector<double2> &hv, int r) {
+        double p = 0.0;
+        for (int i = 0; i <= j; ++i) p += hv[(size_t)i * R + r].x * hv[(size_t)i * R + r].x +
+                                         hv[(size_t)i * R + r].y * hv[(size_t)i * R + r].y;
+        return p;
+      };
+      std::vector<double> hn(R, 0.0);
+      std::vector<double2> scv(R, make_double2(0.0, 0.0));
+      auto scales = [&]() {
+        for (int r = 0; r < R; ++r) scv[r] = make_double2(active[r] && hn[r] > 1e-300 ? 1.0 / hn[r] : 0.0, 0.0);
+      };
+      bool reorth = false;
+      for (int r = 0; r < R; ++r) {
+        if (!active[r]) continue;
+        const double ww = hv1[(size_t)(j + 1) * R + r].x, w1 = ww - sumsq(hv1, r);
+        if (!std::isfinite(ww) || !std::isfinite(w1)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+        if (w1 > 0.5 * ww) hn[r] = std::sqrt(w1);
+        else reorth = true;
+      }
+      if (!reorth) {
+        scales();
+        HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+        HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s, sdev));
+      } else {
+        HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s));
+        HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h2, s));
+        HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2, hb, hipMemcpyDeviceToHost, s));
+        HEOM_HIP_CHECK(hipStreamSynchronize(s));
+        std::memcpy(hv2.data(), pin.p, hb);
+        bool explicit_norm = false;
+        for (int r = 0; r < R; ++r) {
+          if (!active[r]) continue;
+          const double w1 = hv2[(size_t)(j + 1) * R + r].x, w2 = w1 - sumsq(hv2, r);
+          if (!std::isfinite(w2)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+          if (w2 > 1e-2 * w1) hn[r] = std::sqrt(w2);
+          else explicit_norm = true;  // cancellation again: measure the norm directly
+        }
+        if (!explicit_norm) {
+          scales();
+          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+          HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s, sdev));
+        } else {
+          HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s));
+          HEOM_TRY(mdot<T>(vn, 0, 1, vn, n, R, partial, nchunk, h2 + (size_t)(j + 1) * R, s));
+          HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2 + (size_t)(j + 1) * R, sizeof(double2) * R, hipMemcpyDeviceToHost, s));
+          HEOM_HIP_CHECK(hipStreamSynchronize(s));
+          for (int r = 0; r < R; ++r) {
+            const double v = ((const double2 *)pin.p)[r].x;
+            if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+            hn[r] = std::sqrt(std::max(v, 0.0));
+          }
+          scales();
+          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+          HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, R, s));
+        }
+      }
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
         cd *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m
         for (int i = 0; i <= j; ++i) {
-          Hc[(size_t)j * (m + 1) + i] = cd(hp1[(size_t)i * R + r].x + hp2[(size_t)i * R + r].x,
-                                           hp1[(size_t)i * R + r].y + hp2[(size_t)i * R + r].y);
+          Hc[(size_t)j * (m + 1) + i] = cd(hv1[(size_t)i * R + r].x + hv2[(size_t)i * R + r].x,
+                                           hv1[(size_t)i * R + r].y + hv2[(size_t)i * R + r].y);
         }
-        const double hn = std::sqrt(std::max(hp2[(size_t)(j + 1) * R + r].x, 0.0));
-        if (!std::isfinite(hn)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
-        Hc[(size_t)j * (m + 1) + j + 1] = hn;
-        const bool use = active[r] && hn > 1e-300;
-        scv[r] = make_double2(use ? 1.0 / hn : 0.0, 0.0);
+        Hc[(size_t)j * (m + 1) + j + 1] = hn[r];
+        const bool use = active[r] && hn[r] > 1e-300;
         if (!active[r]) continue;
         // previous rotations
         cd *col = &Hc[(size_t)j * (m + 1)];
@@ -222,9 +273,6 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
         if (rel <= tol * 0.5 || !use) active[r] = 0;  // stop extending this system's basis
         all_done = all_done && !active[r];
       }
-      HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
-      HEOM_TRY(scale_vec<T>(w, sdev, V + (size_t)(j + 1) * nr, n, R, s));
-      HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack
       if (all_done) { ++j; ++iters; break; }
     }
     st.iterations = iters;
