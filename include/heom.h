@@ -211,14 +211,22 @@ heom_status heom_propagate(heom_hier *h, int32_t precision, void *x_dev, double 
  * ---------------------------------------------------------------------- */
 enum { HEOM_OP_PROPAGATE = 0, HEOM_OP_STEADY = 1, HEOM_OP_SPECTRUM = 2 };
 enum { HEOM_PREC_NONE = 0, HEOM_PREC_JACOBI = 1, HEOM_PREC_NN = 2 };
-enum { HEOM_SOLVE_FP64 = 0, HEOM_SOLVE_FP32_IR = 1 };
+/* HEOM_SOLVE_SHIFTED (heom_spectrum only, precond HEOM_PREC_NONE): all
+ * frequencies share one Krylov space of the unshifted operator (restarted
+ * full orthogonalisation, whose residuals stay parallel across shifts);
+ * only the trace readout of each solution is accumulated, so memory does not
+ * grow with the number of frequencies.  The report's true residual is the
+ * largest of the FOM residual estimates and of the true residuals of three
+ * probe frequencies (first, middle, last), measured with the plain apply. */
+enum { HEOM_SOLVE_FP64 = 0, HEOM_SOLVE_FP32_IR = 1, HEOM_SOLVE_SHIFTED = 2 };
 
 typedef struct {
   int32_t restart;        /* GMRES restart length m (default 30)              */
   int32_t max_iter;       /* total inner iterations (default 3000)            */
   double tol;             /* relative true residual ||b - A x|| / ||b||       */
   int32_t precond;        /* HEOM_PREC_*                                      */
-  int32_t mode;           /* HEOM_SOLVE_FP64 or HEOM_SOLVE_FP32_IR             */
+  int32_t mode;           /* HEOM_SOLVE_FP64, HEOM_SOLVE_FP32_IR, or (spectra)
+                             HEOM_SOLVE_SHIFTED                               */
   double inner_tol;       /* FP32 inner tolerance for IR (default 1e-5)       */
   int32_t max_refine;     /* IR outer steps (default 20)                      */
   int32_t rhs_chunk;      /* spectra: right-hand sides per multi-RHS solve    */

@@ -231,7 +231,7 @@ def apply_steady_operator(h, x, y=None, stream=None):
 
 # ----------------------------------------------------------------- solvers
 _PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN}
-_MODE = {"fp64": L.HEOM_SOLVE_FP64, "fp32_ir": L.HEOM_SOLVE_FP32_IR}
+_MODE = {"fp64": L.HEOM_SOLVE_FP64, "fp32_ir": L.HEOM_SOLVE_FP32_IR, "shifted": L.HEOM_SOLVE_SHIFTED}
 
 
 def solver_opts(**kw):

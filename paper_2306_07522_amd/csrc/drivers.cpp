@@ -176,7 +176,10 @@ static heom_status check_opts(const heom_solver_opts *o) {
   if (o->restart < 1 || o->restart > 500) return fail(HEOM_ERR_ARG, "restart must be in [1, 500]");
   if (o->max_iter < 1) return fail(HEOM_ERR_ARG, "max_iter must be positive");
   if (!(o->tol > 0)) return fail(HEOM_ERR_ARG, "tol must be positive");
-  if (o->mode != HEOM_SOLVE_FP64 && o->mode != HEOM_SOLVE_FP32_IR) return fail(HEOM_ERR_ARG, "bad solve mode");
+  if (o->mode != HEOM_SOLVE_FP64 && o->mode != HEOM_SOLVE_FP32_IR && o->mode != HEOM_SOLVE_SHIFTED)
+    return fail(HEOM_ERR_ARG, "bad solve mode");
+  if (o->mode == HEOM_SOLVE_SHIFTED && o->precond != HEOM_PREC_NONE)
+    return fail(HEOM_ERR_ARG, "the multi-shift mode takes no preconditioner");
   if (o->precond < HEOM_PREC_NONE || o->precond > HEOM_PREC_NN) return fail(HEOM_ERR_ARG, "bad preconditioner");
   return HEOM_OK;
 }
@@ -217,6 +220,10 @@ heom_status heom_workspace_size(const heom_hier *hw, int32_t op, const heom_solv
   HEOM_TRY(check_opts(o));
   if (op == HEOM_OP_STEADY) {
     *bytes = (size_t)n * 16 + solve_bytes(h, 1, *o) + 4096;
+    return HEOM_OK;
+  }
+  if (op == HEOM_OP_SPECTRUM && o->mode == HEOM_SOLVE_SHIFTED) {
+    *bytes = shifted_bytes(h, *o) + 8192;
     return HEOM_OK;
   }
   if (op == HEOM_OP_SPECTRUM) {
@@ -348,6 +355,7 @@ heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, h
                         size_t ws_bytes, void *stream) {
   if (!hw || !x_dev) return fail(HEOM_ERR_ARG, "steady: NULL argument");
   HEOM_TRY(check_opts(o));
+  if (o->mode == HEOM_SOLVE_SHIFTED) return fail(HEOM_ERR_ARG, "steady: the multi-shift mode is for spectra");
   Hier &h = *hw->impl;
   if (h.parity != 1) return fail(HEOM_ERR_ARG, "steady: the stationary state lives in the even-parity hierarchy");
   hipStream_t s = (hipStream_t)stream;
@@ -401,6 +409,8 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
   hipStream_t s = (hipStream_t)stream;
   HEOM_TRY(ensure_device(hs));
   if (r) std::memset(r, 0, sizeof(*r));
+  if (o->mode == HEOM_SOLVE_SHIFTED)
+    return spectrum_shifted(hs, (const double2 *)x_ss_dev, kind, op, omega, n_omega, out_host, *o, r, ws, ws_bytes, s);
   const int d = hs.d;
   const int64_t n = hs.N * (int64_t)d * d;
   const int per = kind == 0 ? 2 : 1;

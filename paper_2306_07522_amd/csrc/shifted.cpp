@@ -1,0 +1,325 @@
+// Multi-shift spectra: every frequency from one Krylov space.
+//
+// The spectrum solves (Methods, "Numerical computation of the spectrum") are
+// (M + sigma_k) x_k = b for thousands of shifts sigma_k = +-i omega_k with
+// one right-hand side b per readout.  Without a preconditioner the Krylov
+// space K_m(M + sigma, b) does not depend on sigma, so one Arnoldi process
+// on M serves all shifts.  Restarting uses the full orthogonalisation method
+// (FOM): its residuals are all parallel to the next Arnoldi vector,
+//   b - (M + sigma_k) x_k = -h_{m+1,m} (e_m^T y_k) v_{m+1},
+// so the next cycle restarts every shift from the same vector with its own
+// scalar weight (restarted FOM for shifted systems, Simoncini 2003).
+//
+// The spectrum only needs the trace readout Tr[O x_k,0] of ADO 0, which is
+// linear in x_k.  Each Arnoldi vector v_j therefore contributes the scalar
+// Tr[O v_j,0] once, and no solution vector is ever stored: the memory is the
+// Krylov basis alone, independent of the number of frequencies.  A few probe
+// shifts do keep their solution vectors, so that the true residual
+// |b - (M + sigma) x| / |b| is measured with the plain apply at the end.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "blas.h"
+#include "internal.h"
+#include "solvers.h"
+
+namespace heom {
+
+namespace {
+
+struct ShiftSystem {
+  std::vector<cd> sigma;  // per frequency
+  int col_b = 0;          // right-hand side = ops[col_b] . x_ss
+  int col_r = 0;          // readout Tr[ops[col_r] x_0]
+};
+
+// Solve (H + sigma I) y = g0 e_1 for the upper-Hessenberg k x k matrix H
+// (column-major, leading dimension ld) by Gaussian elimination with partial
+// pivoting between neighbouring rows.  Returns false when singular.
+bool hessenberg_solve(const std::vector<cd> &H, int ld, int k, cd sigma, cd g0, std::vector<cd> &y) {
+  std::vector<cd> A((size_t)k * k), rhs(k, cd(0));
+  for (int c = 0; c < k; ++c)
+    for (int r = 0; r < k; ++r) A[(size_t)c * k + r] = (r <= c + 1) ? H[(size_t)c * ld + r] : cd(0);
+  for (int i = 0; i < k; ++i) A[(size_t)i * k + i] += sigma;
+  rhs[0] = g0;
+  for (int i = 0; i + 1 < k; ++i) {
+    // rows i and i+1 only (Hessenberg)
+    if (std::abs(A[(size_t)i * k + i + 1]) > std::abs(A[(size_t)i * k + i])) {
+      for (int c = i; c < k; ++c) std::swap(A[(size_t)c * k + i], A[(size_t)c * k + i + 1]);
+      std::swap(rhs[i], rhs[i + 1]);
+    }
+    const cd p = A[(size_t)i * k + i];
+    if (p == cd(0)) return false;
+    const cd f = A[(size_t)i * k + i + 1] / p;
+    if (f != cd(0)) {
+      for (int c = i; c < k; ++c) A[(size_t)c * k + i + 1] -= f * A[(size_t)c * k + i];
+      rhs[i + 1] -= f * rhs[i];
+    }
+  }
+  y.assign(k, cd(0));
+  for (int i = k - 1; i >= 0; --i) {
+    cd acc = rhs[i];
+    for (int c = i + 1; c < k; ++c) acc -= A[(size_t)c * k + i] * y[c];
+    const cd p = A[(size_t)i * k + i];
+    if (p == cd(0)) return false;
+    y[i] = acc / p;
+  }
+  for (const cd &v : y)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return false;
+  return true;
+}
+
+}  // namespace
+
+size_t shifted_bytes(const Hier &h, const heom_solver_opts &o) {
+  const int64_t n = h.N * (int64_t)h.d * h.d;
+  const size_t vec = (size_t)n * 16;
+  const int m = o.restart;
+  const int nprobe = 3;
+  int64_t nch = std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
+  return (size_t)(m + 1) * vec + (size_t)(nprobe + 2) * vec + (size_t)(m + 3) * nch * sizeof(double2) +
+         4 * (size_t)(m + 3) * sizeof(double2) + 2 * (size_t)h.d * h.d * 16 + 16 * 1024;
+}
+
+// One right-hand side, all shifts: readout[k] = Tr[ops[col_r] x_k,0].
+static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd, const std::vector<double2> &ops_h,
+                               const ShiftSystem &sys, const heom_solver_opts &o, std::vector<cd> &readout,
+                               heom_solver_report *rep, WsArena &ws, hipStream_t s) {
+  const int d = h.d;
+  const int64_t n = h.N * (int64_t)d * d;
+  const int K = (int)sys.sigma.size();
+  const int m = o.restart;
+  readout.assign(K, cd(0));
+  if (K == 0) return HEOM_OK;
+  const size_t vec = (size_t)n * sizeof(double2);
+  double2 *V = (double2 *)ws.take((size_t)(m + 1) * vec);
+  double2 *b = (double2 *)ws.take(vec);
+  double2 *r = (double2 *)ws.take(vec);
+  const int nprobe = std::min(3, K);
+  std::vector<double2 *> xp(nprobe);
+  for (int p = 0; p < nprobe; ++p) xp[p] = (double2 *)ws.take(vec);
+  const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
+  double2 *partial = (double2 *)ws.take((size_t)(m + 3) * nch * sizeof(double2));
+  double2 *hdev = (double2 *)ws.take(2 * (size_t)(m + 3) * sizeof(double2));
+  double2 *sdev = (double2 *)ws.take(2 * sizeof(double2));
+  if (!V || !b || !r || !partial || !hdev || !sdev) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
+  for (double2 *p : xp)
+    if (!p) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
+  PinnedBuf pin;
+  HEOM_TRY(pin.ensure(sizeof(double2) * ((size_t)2 * (m + 3) + (size_t)d * d)));
+  double2 *ph = (double2 *)pin.p;
+  double2 *pblk = ph + 2 * (m + 3);
+  // b = ops[col_b] . x_ss on every ADO
+  int *colb = (int *)ws.take(sizeof(int) * 2);
+  if (!colb) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
+  HEOM_HIP_CHECK(hipMemcpyAsync(colb, &sys.col_b, sizeof(int), hipMemcpyHostToDevice, s));
+  HEOM_TRY(left_multiply<double>(x_ss, opsd, d, h.N, 1, colb, b, s));
+  for (double2 *p : xp) HEOM_HIP_CHECK(hipMemsetAsync(p, 0, vec, s));
+  auto norm2 = [&](const double2 *v, double &out) -> heom_status {
+    HEOM_TRY(mdot<double>(v, 0, 1, v, n, 1, partial, nch, hdev, s));
+    HEOM_HIP_CHECK(hipMemcpyAsync(ph, hdev, sizeof(double2), hipMemcpyDeviceToHost, s));
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    out = std::max(ph[0].x, 0.0);
+    return HEOM_OK;
+  };
+  double bb = 0;
+  HEOM_TRY(norm2(b, bb));
+  const double bnorm = std::sqrt(bb);
+  if (!(bnorm > 0)) return HEOM_OK;  // zero right-hand side: zero response
+  // trace functional of an ADO-0 block
+  const double2 *R0 = ops_h.data() + (size_t)sys.col_r * d * d;
+  auto readv = [&](const double2 *v, cd &t) -> heom_status {
+    HEOM_HIP_CHECK(hipMemcpyAsync(pblk, v, sizeof(double2) * d * d, hipMemcpyDeviceToHost, s));
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    cd acc(0);
+    for (int i = 0; i < d; ++i)
+      for (int k = 0; k < d; ++k)
+        acc += cd(R0[i * d + k].x, R0[i * d + k].y) * cd(pblk[k * d + i].x, pblk[k * d + i].y);
+    t = acc;
+    return HEOM_OK;
+  };
+  // V_0 = b / |b|; every shift starts with residual gamma_k V_0, gamma_k = |b|
+  double2 sc = make_double2(1.0 / bnorm, 0.0);
+  HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &sc, sizeof(double2), hipMemcpyHostToDevice, s));
+  HEOM_TRY(scale_vec<double>(b, sdev, V, n, 1, s));
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<cd> gamma(K, cd(bnorm));
+  std::vector<char> active(K, 1);
+  std::vector<int> probe_k(nprobe);
+  for (int p = 0; p < nprobe; ++p) probe_k[p] = nprobe == 1 ? 0 : (int)((int64_t)p * (K - 1) / (nprobe - 1));
+  std::vector<cd> H((size_t)(m + 1) * m), t(m + 1);
+  int iters = 0, cycles = 0;
+  int64_t applies = 0;
+  double worst_est = 1.0;
+  while (true) {
+    // Arnoldi on M (no shift) with selective reorthogonalisation
+    std::fill(H.begin(), H.end(), cd(0));
+    int kk = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double2 *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
+      HEOM_TRY(readv(vj, t[j]));
+      ApplyArgs a;
+      a.x = vj;
+      a.y = vn;
+      HEOM_TRY(launch_apply(h, HEOM_FP64, a, s));
+      ++applies;
+      ++iters;
+      std::vector<double2> h1(j + 2), h2(j + 2, make_double2(0, 0));
+      HEOM_TRY(mdot<double>(V, n, j + 2, vn, n, 1, partial, nch, hdev, s));
+      HEOM_HIP_CHECK(hipMemcpyAsync(ph, hdev, sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      std::memcpy(h1.data(), ph, sizeof(double2) * (j + 2));
+      double p1 = 0;
+      for (int i = 0; i <= j; ++i) p1 += h1[i].x * h1[i].x + h1[i].y * h1[i].y;
+      const double ww = h1[j + 1].x;
+      double hn2 = ww - p1;
+      if (!std::isfinite(ww)) return fail(HEOM_ERR_NAN, "spectrum: non-finite Arnoldi vector");
+      const double2 *hproj = hdev;
+      if (!(hn2 > 0.5 * ww)) {
+        HEOM_TRY(basis_update<double>(V, n, j + 1, hdev, vn, n, 1, -1.0, s));
+        HEOM_TRY(mdot<double>(V, n, j + 2, vn, n, 1, partial, nch, hdev + (m + 3), s));
+        HEOM_HIP_CHECK(hipMemcpyAsync(ph, hdev + (m + 3), sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, s));
+        HEOM_HIP_CHECK(hipStreamSynchronize(s));
+        std::memcpy(h2.data(), ph, sizeof(double2) * (j + 2));
+        double p2 = 0;
+        for (int i = 0; i <= j; ++i) p2 += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+        hn2 = h2[j + 1].x - p2;
+        hproj = hdev + (m + 3);
+        if (!(hn2 > 1e-2 * h2[j + 1].x)) {
+          HEOM_TRY(basis_update<double>(V, n, j + 1, hproj, vn, n, 1, -1.0, s));
+          HEOM_TRY(norm2(vn, hn2));
+          hproj = nullptr;
+        }
+      }
+      for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = cd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+      double hn = std::sqrt(std::max(hn2, 0.0));
+      double hscale = 0;
+      for (int i = 0; i <= j; ++i) hscale = std::max(hscale, std::abs(H[(size_t)j * (m + 1) + i]));
+      if (!(hn > 1e-14 * std::max(hscale, 1e-300))) {
+        hn = 0.0;
+        breakdown = true;  // invariant subspace: the projected solutions are exact
+      }
+      H[(size_t)j * (m + 1) + j + 1] = hn;
+      sc = make_double2(hn > 0 ? 1.0 / hn : 0.0, 0.0);
+      HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &sc, sizeof(double2), hipMemcpyHostToDevice, s));
+      if (hproj) HEOM_TRY(basis_update<double>(V, n, j + 1, hproj, vn, n, 1, -1.0, s, sdev));
+      else HEOM_TRY(scale_vec<double>(vn, sdev, vn, n, 1, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      kk = j + 1;
+      if (breakdown || iters >= o.max_iter) break;
+    }
+    ++cycles;
+    // per shift: (H + sigma) y = gamma e_1, readout += t . y, new residual weight
+    const cd hlast = H[(size_t)(kk - 1) * (m + 1) + kk];
+    std::vector<cd> y;
+    bool any = false;
+    worst_est = 0;
+    std::vector<std::vector<cd>> yprobe(nprobe);
+    for (int k = 0; k < K; ++k) {
+      if (!active[k]) continue;
+      if (!hessenberg_solve(H, m + 1, kk, sys.sigma[k], gamma[k], y))
+        return fail(HEOM_ERR_SINGULAR, "spectrum: singular projected shifted system");
+      cd acc(0);
+      for (int j = 0; j < kk; ++j) acc += y[j] * t[j];
+      readout[k] += acc;
+      for (int p = 0; p < nprobe; ++p)
+        if (probe_k[p] == k) yprobe[p] = y;
+      gamma[k] = breakdown ? cd(0) : -hlast * y[kk - 1];
+      const double est = std::abs(gamma[k]) / bnorm;
+      if (est <= o.tol) active[k] = 0;
+      else any = true;
+      worst_est = std::max(worst_est, est);
+    }
+    // probes: x_p += V y_p
+    for (int p = 0; p < nprobe; ++p) {
+      if (yprobe[p].empty()) continue;
+      std::vector<double2> yh(kk);
+      for (int j = 0; j < kk; ++j) yh[j] = make_double2(yprobe[p][j].real(), yprobe[p][j].imag());
+      HEOM_HIP_CHECK(hipMemcpyAsync(hdev, yh.data(), sizeof(double2) * kk, hipMemcpyHostToDevice, s));
+      HEOM_TRY(basis_update<double>(V, n, kk, hdev, xp[p], n, 1, 1.0, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    }
+    if (!any || breakdown || iters >= o.max_iter) break;
+    // restart from the common residual direction v_{kk}
+    HEOM_HIP_CHECK(hipMemcpyAsync(V, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
+  }
+  // true residuals of the probes with the plain apply
+  double worst_true = 0;
+  for (int p = 0; p < nprobe; ++p) {
+    ApplyArgs a;
+    a.x = xp[p];
+    a.y = r;
+    a.shift0 = sys.sigma[probe_k[p]];
+    HEOM_TRY(launch_apply(h, HEOM_FP64, a, s));
+    ++applies;
+    HEOM_TRY((axpby<double, double>(b, 1.0, r, -1.0, n, s)));
+    double rr = 0;
+    HEOM_TRY(norm2(r, rr));
+    worst_true = std::max(worst_true, std::sqrt(rr) / bnorm);
+  }
+  bool conv = true;
+  for (int k = 0; k < K; ++k) conv = conv && !active[k];
+  if (rep) {
+    rep->iterations += iters;
+    rep->restarts += cycles;
+    rep->applies += applies;
+    rep->true_residual = std::max(rep->true_residual, std::max(worst_true, conv ? 0.0 : worst_est));
+    if (!conv || worst_true > o.tol * 10) rep->status = HEOM_ERR_NOT_CONVERGED;
+  }
+  if (!conv) return fail(HEOM_ERR_NOT_CONVERGED, "spectrum: some shifts did not converge");
+  return HEOM_OK;
+}
+
+heom_status spectrum_shifted(Hier &hs, const double2 *x_ss, int kind, const double *op, const double *omega,
+                             int64_t n_omega, double *out_host, const heom_solver_opts &o, heom_solver_report *r,
+                             void *ws, size_t ws_bytes, hipStream_t s) {
+  const int d = hs.d;
+  auto t0 = std::chrono::steady_clock::now();
+  WsArena arena(ws, ws_bytes);
+  double2 *opsd = (double2 *)arena.take(2 * (size_t)d * d * sizeof(double2));
+  if (!opsd) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
+  std::vector<double2> ops(2 * d * d);  // ops[0] = op, ops[1] = op^dagger
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) {
+      ops[i * d + k] = make_double2(op[2 * (i * d + k)], op[2 * (i * d + k) + 1]);
+      ops[d * d + i * d + k] = make_double2(op[2 * (k * d + i)], -op[2 * (k * d + i) + 1]);
+    }
+  HEOM_HIP_CHECK(hipMemcpyAsync(opsd, ops.data(), ops.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  std::vector<ShiftSystem> systems;
+  if (kind == 0) {
+    // (M + i w) x_+ = op^dag rho -> Tr[op x_+];  (M - i w) x_- = op rho -> Tr[op^dag x_-]
+    ShiftSystem a, b;
+    a.col_b = 1; a.col_r = 0;
+    b.col_b = 0; b.col_r = 1;
+    for (int64_t q = 0; q < n_omega; ++q) {
+      a.sigma.push_back(cd(0.0, omega[q]));
+      b.sigma.push_back(cd(0.0, -omega[q]));
+    }
+    systems = {a, b};
+  } else {
+    // (M - i w) x = op rho -> Tr[op^dag x]
+    ShiftSystem a;
+    a.col_b = 0; a.col_r = 1;
+    for (int64_t q = 0; q < n_omega; ++q) a.sigma.push_back(cd(0.0, -omega[q]));
+    systems = {a};
+  }
+  const size_t mark = arena.used;
+  std::vector<double> acc(n_omega, 0.0);
+  heom_status worst = HEOM_OK;
+  for (const ShiftSystem &sys : systems) {
+    arena.used = mark;
+    std::vector<cd> ro;
+    heom_status st = shifted_fom(hs, x_ss, opsd, ops, sys, o, ro, r, arena, s);
+    if (st != HEOM_OK && st != HEOM_ERR_NOT_CONVERGED) return st;
+    if (st != HEOM_OK) worst = st;
+    for (int64_t q = 0; q < n_omega; ++q) acc[q] += -ro[q].real() / 3.14159265358979323846;
+  }
+  std::copy(acc.begin(), acc.end(), out_host);
+  if (r) r->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return worst == HEOM_OK ? HEOM_OK : fail(worst, "spectrum: some frequencies did not converge");
+}
+
+}  // namespace heom

@@ -58,4 +58,10 @@ struct Gmres {
   heom_status solve(const T2 *b, T2 *x, double tol, int max_iter, bool x_is_zero, GmresStats &st, hipStream_t s);
 };
 
+// Multi-shift spectra (shifted.cpp): every frequency from one Krylov space.
+size_t shifted_bytes(const Hier &h, const heom_solver_opts &o);
+heom_status spectrum_shifted(Hier &hs, const double2 *x_ss, int kind, const double *op, const double *omega,
+                             int64_t n_omega, double *out_host, const heom_solver_opts &o, heom_solver_report *r,
+                             void *ws, size_t ws_bytes, hipStream_t s);
+
 }  // namespace heom

@@ -132,32 +132,37 @@ def _dos_closed_form(w, eps, Gamma, W, mus):
     return -(1.0 / (w - eps - sigma)).imag / np.pi
 
 
-@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir", "shifted"])
 def test_dos_resonant_level_closed_form(mode):
     torch, api = _torch(), _api()
     cfg = wl.resonant_level(eps=0.3, n_exp=3, n_max=2)
     he, ho = library_model(cfg, +1), library_model(cfg, -1)
     x, rep = api.steady_state(he, tol=1e-12)
     om = np.linspace(-8, 8, 37)
-    A, rep = api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-11, mode=mode, rhs_chunk=16)
+    extra = dict(precond="none", restart=60) if mode == "shifted" else {}
+    A, rep = api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-11, mode=mode, rhs_chunk=16, **extra)
     exact = _dos_closed_form(om, 0.3, 2.0, 10.0, (1.0, -1.0))
     assert np.abs(A - exact).max() < 1e-8, (np.abs(A - exact).max(), rep)
 
 
-def test_dos_siam_vs_oracle():
+@pytest.mark.parametrize("mode", ["fp64", "shifted"])
+def test_dos_siam_vs_oracle(mode):
     torch, api = _torch(), _api()
     cfg = wl.siam(n_max=2)
     he, ho = library_model(cfg, +1), library_model(cfg, -1)
     oe, oo = oracle_model(cfg, +1), oracle_model(cfg, -1)
     x, _ = api.steady_state(he, tol=1e-12)
     om = np.array([-7.0, -5.0, -1.0, 0.0, 0.5, 5.0])
-    A, rep = api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-12, rhs_chunk=4)
+    extra = dict(precond="none", restart=60) if mode == "shifted" else {}
+    A, rep = api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-12, rhs_chunk=4, mode=mode, **extra)
+    assert rep["true_residual"] <= 1e-11, rep
     xs = osv.steady_state(oe.assemble(), oe.d)
     Ao = osv.dos(oo.assemble(), xs, cfg["dops"][0], om, oe.N, oe.d)
     assert np.abs(A - Ao).max() <= 1e-9 * np.abs(Ao).max(), (A, Ao)
 
 
-def test_psd_cavity_vs_oracle():
+@pytest.mark.parametrize("mode", ["fp64", "shifted"])
+def test_psd_cavity_vs_oracle(mode):
     torch, api = _torch(), _api()
     cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=2, m_max=2, n_max=1, lam=0.2, gamma=1.0, T=1.0, Gamma=0.5)
     he = library_model(cfg, +1)
@@ -166,7 +171,9 @@ def test_psd_cavity_vs_oracle():
     # w = 0 is excluded: M is singular in the even sector (the stationary
     # state is its null vector) and <a> != 0 for this model
     om = np.linspace(0.25, 2.0, 8)
-    S, rep = api.spectrum(he, None, x, cfg["aop"], om, kind="psd", tol=1e-12, rhs_chunk=5)
+    extra = dict(precond="none", restart=60) if mode == "shifted" else {}
+    S, rep = api.spectrum(he, None, x, cfg["aop"], om, kind="psd", tol=1e-12, rhs_chunk=5, mode=mode, **extra)
+    assert rep["true_residual"] <= 1e-11, rep
     xs = osv.steady_state(oe.assemble(), oe.d)
     So = osv.psd(oe.assemble(), xs, cfg["aop"], om, oe.N, oe.d)
     assert np.abs(S - So).max() <= 1e-9 * np.abs(So).max(), (S, So)
