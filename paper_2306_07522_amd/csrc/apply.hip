@@ -21,8 +21,6 @@
 //   cell kernel   (any d <= 32, any number of right-hand sides): one thread
 //                 per (i, j, r) cell, gathers straight from global memory.
 // Layout: x, y are [N][d][d][R] complex, R innermost.
-#include <cstdlib>
-
 #include "device_common.h"
 #include "internal.h"
 
@@ -238,158 +236,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
   }
 }
 
-// ----------------------------------------------------------------- ring kernel
-// Same task decomposition as the wave kernel, but a task's edges are one
-// flat stream (its groups' edges are contiguous) read through a ring of K
-// register blocks: the loads of the next K neighbour blocks are in flight
-// while the current group is staged and multiplied, whatever the group
-// sizes.  This keeps K x 4 KB (FP64, d = 16) in flight per wave instead of
-// one block.
-template <typename T, int D>
-__device__ __forceinline__ void finish_group(const ApplyParams<T> &P, const int4 &gr, int64_t a, int lane, int j,
-                                             typename Cplx<T>::t (&u)[D * D / 64], typename Cplx<T>::t (&acc)[D * D / 64],
-                                             typename Cplx<T>::t *buf, const typename Cplx<T>::t *tval,
-                                             const int *tcol, const typename Cplx<T>::t *thd,
-                                             typename Cplx<T>::t &trace) {
-  using T2 = typename Cplx<T>::t;
-  constexpr int EPL = D * D / 64;
-  if (gr.w) {
-    // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
-    const T2 z = P.shifts ? P.shifts[0] : P.shift0;
-    const T2 c = csub(P.decay[a], z);
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-      const T2 dh = csub(thd[(lane + 64 * s) / D], thd[j]);
-      const T2 f{c.x - dh.y, c.y + dh.x};
-      acc[s] = csub(acc[s], cmul(f, u[s]));
-    }
-  }
-  const int cid = gr.z;
-  const int op = P.coef_op[cid];
-  const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
-  const bool need_trace = gr.w && P.border && a == 0;
-  if (ns > 0 || need_trace) {
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) buf[lane + 64 * s] = u[s];
-    wave_sync();
-    if (need_trace && lane == 0)
-      for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
-    if (ns > 0) {
-      const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
-      const int rbase = off + (D + j) * ns;
-#pragma unroll
-      for (int s = 0; s < EPL; ++s) {
-        const int i = (lane + 64 * s) / D;
-        const int lbase = off + i * ns;
-        T2 L{0, 0}, Rv{0, 0};
-        if (isreal) {
-#pragma unroll 1
-          for (int t = 0; t < ns; ++t) {
-            const T vl = tval[lbase + t].x, vr = tval[rbase + t].x;
-            const T2 bl = buf[tcol[lbase + t] * D + j];
-            const T2 br = buf[i * D + tcol[rbase + t]];
-            L.x = fma(vl, bl.x, L.x); L.y = fma(vl, bl.y, L.y);
-            Rv.x = fma(vr, br.x, Rv.x); Rv.y = fma(vr, br.y, Rv.y);
-          }
-        } else {
-#pragma unroll 1
-          for (int t = 0; t < ns; ++t) {
-            L = cfma(tval[lbase + t], buf[tcol[lbase + t] * D + j], L);
-            Rv = cfma(buf[i * D + tcol[rbase + t]], tval[rbase + t], Rv);
-          }
-        }
-        acc[s] = cfma(cl, L, acc[s]);
-        acc[s] = cfma(cr, Rv, acc[s]);
-      }
-    }
-    wave_sync();
-  }
-}
-
-template <typename T, int D, int K>
-__global__ void __launch_bounds__(256) apply_ring_kernel(ApplyParams<T> P) {
-  using T2 = typename Cplx<T>::t;
-  constexpr int DD = D * D;
-  constexpr int EPL = DD / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T2 *sbuf = reinterpret_cast<T2 *>(smem);
-  T2 *tval = sbuf + 4 * DD;
-  int *tcol = reinterpret_cast<int *>(tval + P.n_centries);
-  T2 *thd = reinterpret_cast<T2 *>((reinterpret_cast<uintptr_t>(tcol + P.n_centries) + 15) & ~(uintptr_t)15);
-  for (int e = threadIdx.x; e < P.n_centries; e += 256) {
-    tval[e] = P.c_val[e];
-    tcol[e] = P.c_col[e];
-  }
-  if (threadIdx.x < D) thd[threadIdx.x] = P.hdiag[threadIdx.x];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  T2 *buf = sbuf + wave * DD;
-  const int j = lane % D;
-  int64_t blk = blockIdx.x;
-  if (P.xchunk > 0 && (int64_t)(blockIdx.x / P.xchunk + 1) * P.xchunk <= (int64_t)gridDim.x) {
-    const int64_t sup = blockIdx.x / P.xchunk, r = blockIdx.x % P.xchunk;
-    blk = sup * P.xchunk + (r % 8) * (P.xchunk / 8) + r / 8;
-  }
-  const int64_t task = blk * 4 + wave;
-  if (task >= P.n_tasks) return;
-  const int4 tk = P.tasks[task];
-  const int64_t a = tk.x;
-  const int flags = tk.w;
-  const int64_t abase = a * DD;
-  T2 acc[EPL];
-#pragma unroll
-  for (int s = 0; s < EPL; ++s) acc[s] = (flags & TASK_ACC) ? P.y[abase + lane + 64 * s] : T2{0, 0};
-  T2 trace{0, 0};
-  if (tk.y < tk.z) {
-    const int E0 = P.groups[tk.y].x, E1 = P.groups[tk.z - 1].y;
-    T2 ring[K][EPL];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (E0 + k < E1) {
-        const T2 *xb = P.x + (int64_t)P.gedges[E0 + k].x * DD;
-#pragma unroll
-        for (int s = 0; s < EPL; ++s) ring[k][s] = xb[lane + 64 * s];
-      }
-    int g = tk.y;
-    int4 gr = P.groups[g];
-    T2 u[EPL];
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) u[s] = T2{0, 0};
-    for (int base = E0; base < E1; base += K) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int e = base + k;
-        if (e < E1) {
-          const T w = (T)P.gedges[e].y;
-#pragma unroll
-          for (int s = 0; s < EPL; ++s) {
-            u[s].x = fma(w, ring[k][s].x, u[s].x);
-            u[s].y = fma(w, ring[k][s].y, u[s].y);
-          }
-          if (e + K < E1) {  // refill this slot K edges ahead
-            const T2 *xb = P.x + (int64_t)P.gedges[e + K].x * DD;
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) ring[k][s] = xb[lane + 64 * s];
-          }
-          if (e + 1 == gr.y) {
-            finish_group<T, D>(P, gr, a, lane, j, u, acc, buf, tval, tcol, thd, trace);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) u[s] = T2{0, 0};
-            if (++g < tk.z) gr = P.groups[g];
-          }
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < EPL; ++s) {
-    T2 v = acc[s];
-    if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;
-    P.y[abase + lane + 64 * s] = v;
-  }
-}
-
 // ----------------------------------------------------------------- cell kernel
 template <typename T, int D>
 __global__ void __launch_bounds__(256) apply_cell_kernel(ApplyParams<T> P) {
@@ -510,18 +356,11 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
     const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
     if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
     dim3 g((unsigned)grid), b(256);
-    static const int ringk = [] { const char *e = std::getenv("HEOMX_RING"); return e ? std::atoi(e) : 0; }();
-    const int64_t grid4 = (n_tasks + 3) / 4;
-    dim3 g4((unsigned)grid4);
     if (d == 8) {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 8, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 8, false>), g, b, smem, s, P);
     } else {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true>), g, b, smem, s, P);
-      else if (ringk == 2) hipLaunchKernelGGL((apply_ring_kernel<T, 16, 2>), g4, b, smem, s, P);
-      else if (ringk == 3) hipLaunchKernelGGL((apply_ring_kernel<T, 16, 3>), g4, b, smem, s, P);
-      else if (ringk == 4) hipLaunchKernelGGL((apply_ring_kernel<T, 16, 4>), g4, b, smem, s, P);
-      else if (ringk == 6) hipLaunchKernelGGL((apply_ring_kernel<T, 16, 6>), g4, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false>), g, b, smem, s, P);
     }
   } else {

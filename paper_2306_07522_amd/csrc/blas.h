@@ -9,6 +9,12 @@ namespace heom {
 template <typename T>
 heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, int R, double2 *partial, int nchunk,
                  double2 *out, hipStream_t s);
+// One right-hand side: out[i] = conj(V_i) . w, out[k + i] = conj(V_i) . u
+// (i < k) and out[2k] = w . w, in one pass over the basis
+// (partial: (2k + 1) * nchunk scratch)
+template <typename T>
+heom_status mdot2(const void *V, int64_t ldv, int k, const void *w, const void *u, int64_t n, double2 *partial,
+                  int nchunk, double2 *out, hipStream_t s);
 // w += sign * sum_i V_i h_i (per right-hand side), then w *= post[r].x when
 // post is given (fused normalisation)
 template <typename T>

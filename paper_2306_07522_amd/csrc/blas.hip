@@ -66,6 +66,59 @@ __global__ void __launch_bounds__(256) mdot_kernel(const typename Cplx<T>::t *__
   }
 }
 
+// Single right-hand side, two vectors in one pass over the basis:
+// partial[i] = conj(V_i) . w, partial[k + i] = conj(V_i) . u (i < k) and
+// partial[2k] = w . w (chunk-wise, layout [slot][chunk]).
+template <typename T, int NI>
+__global__ void __launch_bounds__(256) mdot2_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
+                                                    const typename Cplx<T>::t *__restrict__ w,
+                                                    const typename Cplx<T>::t *__restrict__ u, int64_t n,
+                                                    double2 *__restrict__ partial, int nchunk) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double2 red[2 * NI + 1][256];
+  const int i0 = blockIdx.y * NI;
+  const int chunk = blockIdx.x;
+  const int64_t e0 = n * chunk / nchunk, e1 = n * (chunk + 1) / nchunk;
+  double ax[NI], ay[NI], cx[NI], cy[NI], ww = 0.0;
+#pragma unroll
+  for (int q = 0; q < NI; ++q) ax[q] = ay[q] = cx[q] = cy[q] = 0.0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const T2 bw = w[e], bu = u[e];
+    if (blockIdx.y == 0) ww += (double)bw.x * bw.x + (double)bw.y * bw.y;
+#pragma unroll
+    for (int q = 0; q < NI; ++q)
+      if (i0 + q < k) {
+        const T2 a = V[(i0 + q) * ldv + e];
+        ax[q] += (double)a.x * bw.x + (double)a.y * bw.y;
+        ay[q] += (double)a.x * bw.y - (double)a.y * bw.x;
+        cx[q] += (double)a.x * bu.x + (double)a.y * bu.y;
+        cy[q] += (double)a.x * bu.y - (double)a.y * bu.x;
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    red[q][threadIdx.x] = make_double2(ax[q], ay[q]);
+    red[NI + q][threadIdx.x] = make_double2(cx[q], cy[q]);
+  }
+  red[2 * NI][threadIdx.x] = make_double2(ww, 0.0);
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+#pragma unroll
+      for (int q = 0; q < 2 * NI + 1; ++q) {
+        red[q][threadIdx.x].x += red[q][threadIdx.x + st].x;
+        red[q][threadIdx.x].y += red[q][threadIdx.x + st].y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NI && i0 + (int)threadIdx.x < k) {
+    partial[(int64_t)(i0 + threadIdx.x) * nchunk + chunk] = red[threadIdx.x][0];
+    partial[(int64_t)(k + i0 + threadIdx.x) * nchunk + chunk] = red[NI + threadIdx.x][0];
+  }
+  if (blockIdx.y == 0 && threadIdx.x == 0) partial[(int64_t)(2 * k) * nchunk + chunk] = red[2 * NI][0];
+}
+
 // out[i * R + r] = sum over chunks of partial
 __global__ void reduce_partials_kernel(const double2 *__restrict__ partial, int k, int nchunk, int R,
                                        double2 *__restrict__ out) {
@@ -282,6 +335,21 @@ heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, in
 }
 
 template <typename T>
+heom_status mdot2(const void *V, int64_t ldv, int k, const void *w, const void *u, int64_t n, double2 *partial,
+                  int nchunk, double2 *out, hipStream_t s) {
+  if (k <= 0) return HEOM_OK;
+  constexpr int NI = 4;
+  dim3 g(nchunk, (k + NI - 1) / NI);
+  hipLaunchKernelGGL((mdot2_kernel<T, NI>), g, dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv, k,
+                     (const typename Cplx<T>::t *)w, (const typename Cplx<T>::t *)u, n, partial, nchunk);
+  const int64_t kk = 2 * (int64_t)k + 1;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, partial, (int)kk,
+                     nchunk, 1, out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
                          hipStream_t s, const double2 *post) {
   if (k <= 0 && !post) return HEOM_OK;
@@ -361,6 +429,8 @@ heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const
 #define HEOM_INST(T)                                                                                              \
   template heom_status mdot<T>(const void *, int64_t, int, const void *, int64_t, int, double2 *, int, double2 *, \
                                hipStream_t);                                                                       \
+  template heom_status mdot2<T>(const void *, int64_t, int, const void *, const void *, int64_t, double2 *, int,     \
+                                double2 *, hipStream_t);                                                          \
   template heom_status basis_update<T>(const void *, int64_t, int, const double2 *, void *, int64_t, int, double,  \
                                        hipStream_t, const double2 *);                                              \
   template heom_status scale_vec<T>(const void *, const double2 *, void *, int64_t, int, hipStream_t);             \

@@ -55,7 +55,7 @@ size_t gmres_bytes(int64_t n, int R, int m, bool flexible, size_t w) {
   size_t b = (size_t)(m + 1) * vec + 2 * vec + 1024;
   if (flexible) b += (size_t)m * vec + 256;
   const int nch = dot_chunks(n, R);
-  b += (size_t)(m + 2) * nch * R * sizeof(double2) + 256;  // partials
+  b += (size_t)std::max(m + 2, R == 1 ? 2 * m + 3 : 0) * nch * R * sizeof(double2) + 256;  // partials
   b += 4 * (size_t)(m + 2) * R * sizeof(double2) + 1024;   // h, scale
   return b;
 }
@@ -73,13 +73,14 @@ heom_status Gmres<T>::init(WsArena &ws, int64_t n_, int R_, int m_, bool flexibl
   t = (T2 *)ws.take(vec);
   Z = flexible ? (T2 *)ws.take((size_t)m * vec) : nullptr;
   nchunk = dot_chunks(n, R);
-  partial = (double2 *)ws.take((size_t)(m + 2) * nchunk * R * sizeof(double2));
+  partial = (double2 *)ws.take((size_t)std::max(m + 2, R == 1 ? 2 * m + 3 : 0) * nchunk * R * sizeof(double2));
   hdev = (double2 *)ws.take((size_t)2 * (m + 2) * R * sizeof(double2));
   sdev = (double2 *)ws.take((size_t)2 * R * sizeof(double2));
   if (!V || !w || !t || (flexible && !Z) || !partial || !hdev || !sdev)
     return fail(HEOM_ERR_ARG, "solver workspace too small (see heom_workspace_size)");
   HEOM_TRY(pin.ensure((size_t)2 * (m + 2) * R * sizeof(double2)));
   H.assign((size_t)R * (m + 1) * m, cd(0));
+  G.assign((size_t)(m + 1) * (m + 1), cd(0));
   cs.assign((size_t)R * m, 0.0);
   sn.assign((size_t)R * m, cd(0));
   g.assign((size_t)R * (m + 1), cd(0));
@@ -167,65 +168,121 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
       // otherwise the update and the normalisation are one fused pass.
       double2 *h1 = hdev, *h2 = hdev + (size_t)(m + 2) * R;
       const size_t hb = sizeof(double2) * (size_t)(j + 2) * R;
-      HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h1, s));
-      HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, hb, hipMemcpyDeviceToHost, s));
-      HEOM_HIP_CHECK(hipStreamSynchronize(s));
       std::vector<double2> hv1((size_t)(j + 2) * R), hv2((size_t)(j + 2) * R, make_double2(0.0, 0.0));
-      std::memcpy(hv1.data(), pin.p, hb);
-      auto sumsq = [&](const std::vector<double2> &hv, int r) {
-        double p = 0.0;
-        for (int i = 0; i <= j; ++i) p += hv[(size_t)i * R + r].x * hv[(size_t)i * R + r].x +
-                                         hv[(size_t)i * R + r].y * hv[(size_t)i * R + r].y;
-        return p;
-      };
       std::vector<double> hn(R, 0.0);
       std::vector<double2> scv(R, make_double2(0.0, 0.0));
       auto scales = [&]() {
         for (int r = 0; r < R; ++r) scv[r] = make_double2(active[r] && hn[r] > 1e-300 ? 1.0 / hn[r] : 0.0, 0.0);
       };
-      bool reorth = false;
-      for (int r = 0; r < R; ++r) {
-        if (!active[r]) continue;
-        const double ww = hv1[(size_t)(j + 1) * R + r].x, w1 = ww - sumsq(hv1, r);
-        if (!std::isfinite(ww) || !std::isfinite(w1)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
-        if (w1 > 0.5 * ww) hn[r] = std::sqrt(w1);
-        else reorth = true;
-      }
-      if (!reorth) {
-        scales();
-        HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
-        HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s, sdev));
-      } else {
-        HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s));
-        HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h2, s));
-        HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2, hb, hipMemcpyDeviceToHost, s));
+      if (R == 1) {
+        // Two-pass classical Gram-Schmidt with the Gram matrix: one pass over
+        // the basis gives a = V^H w, the new Gram column c = V^H v_j and
+        // |w|^2; the reorthogonalised coefficients follow from the measured
+        // Gram matrix G = V^H V as h = a + (a - G a) (the second projection
+        // of CGS2 without re-reading the basis), |w - V h|^2 from
+        // |w|^2 - 2 Re(h^H a) + h^H G h, and a second pass applies the
+        // update and the normalisation together.
+        HEOM_TRY(mdot2<T>(V, nr, j + 1, vn, vj, n, partial, nchunk, h1, s));
+        HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, sizeof(double2) * (2 * j + 3), hipMemcpyDeviceToHost, s));
         HEOM_HIP_CHECK(hipStreamSynchronize(s));
-        std::memcpy(hv2.data(), pin.p, hb);
-        bool explicit_norm = false;
+        const double2 *pp = (const double2 *)pin.p;
+        std::vector<cd> a(j + 1), hh(j + 1);
+        for (int i = 0; i <= j; ++i) {
+          a[i] = cd(pp[i].x, pp[i].y);
+          const cd c(pp[j + 1 + i].x, pp[j + 1 + i].y);
+          G[(size_t)j * (m + 1) + i] = c;                // G[i][j] (column j)
+          G[(size_t)i * (m + 1) + j] = std::conj(c);     // G[j][i]
+        }
+        const double ww = pp[2 * j + 2].x;
+        if (!std::isfinite(ww)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+        for (int i = 0; i <= j; ++i) {
+          cd ga(0);
+          for (int q = 0; q <= j; ++q) ga += G[(size_t)q * (m + 1) + i] * a[q];
+          hh[i] = 2.0 * a[i] - ga;
+        }
+        double w2 = ww;
+        for (int i = 0; i <= j; ++i) w2 -= 2.0 * (std::conj(hh[i]) * a[i]).real();
+        cd hgh(0);
+        for (int i = 0; i <= j; ++i) {
+          cd gh(0);
+          for (int q = 0; q <= j; ++q) gh += G[(size_t)q * (m + 1) + i] * hh[q];
+          hgh += std::conj(hh[i]) * gh;
+        }
+        w2 += hgh.real();
+        for (int i = 0; i <= j; ++i) hv1[i] = make_double2(hh[i].real(), hh[i].imag());
+        HEOM_HIP_CHECK(hipMemcpyAsync(h1, hv1.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
+        if (std::isfinite(w2) && w2 > 1e-6 * ww) {
+          hn[0] = std::sqrt(w2);
+          scales();
+          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2), hipMemcpyHostToDevice, s));
+          HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s, sdev));
+        } else {  // cancellation: measure the norm directly
+          HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s));
+          HEOM_TRY(mdot<T>(vn, 0, 1, vn, n, 1, partial, nchunk, h2, s));
+          HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2, sizeof(double2), hipMemcpyDeviceToHost, s));
+          HEOM_HIP_CHECK(hipStreamSynchronize(s));
+          const double v = ((const double2 *)pin.p)[0].x;
+          if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+          hn[0] = std::sqrt(std::max(v, 0.0));
+          scales();
+          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2), hipMemcpyHostToDevice, s));
+          HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, 1, s));
+        }
+      } else {
+        HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h1, s));
+        HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, hb, hipMemcpyDeviceToHost, s));
+        HEOM_HIP_CHECK(hipStreamSynchronize(s));
+        std::memcpy(hv1.data(), pin.p, hb);
+        auto sumsq = [&](const std::vector<double2> &hv, int r) {
+          double p = 0.0;
+          for (int i = 0; i <= j; ++i) p += hv[(size_t)i * R + r].x * hv[(size_t)i * R + r].x +
+                                           hv[(size_t)i * R + r].y * hv[(size_t)i * R + r].y;
+          return p;
+        };
+        bool reorth = false;
         for (int r = 0; r < R; ++r) {
           if (!active[r]) continue;
-          const double w1 = hv2[(size_t)(j + 1) * R + r].x, w2 = w1 - sumsq(hv2, r);
-          if (!std::isfinite(w2)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
-          if (w2 > 1e-2 * w1) hn[r] = std::sqrt(w2);
-          else explicit_norm = true;  // cancellation again: measure the norm directly
+          const double ww = hv1[(size_t)(j + 1) * R + r].x, w1 = ww - sumsq(hv1, r);
+          if (!std::isfinite(ww) || !std::isfinite(w1)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+          if (w1 > 0.5 * ww) hn[r] = std::sqrt(w1);
+          else reorth = true;
         }
-        if (!explicit_norm) {
+        if (!reorth) {
           scales();
           HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
-          HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s, sdev));
+          HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s, sdev));
         } else {
-          HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s));
-          HEOM_TRY(mdot<T>(vn, 0, 1, vn, n, R, partial, nchunk, h2 + (size_t)(j + 1) * R, s));
-          HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2 + (size_t)(j + 1) * R, sizeof(double2) * R, hipMemcpyDeviceToHost, s));
+          HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s));
+          HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h2, s));
+          HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2, hb, hipMemcpyDeviceToHost, s));
           HEOM_HIP_CHECK(hipStreamSynchronize(s));
+          std::memcpy(hv2.data(), pin.p, hb);
+          bool explicit_norm = false;
           for (int r = 0; r < R; ++r) {
-            const double v = ((const double2 *)pin.p)[r].x;
-            if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
-            hn[r] = std::sqrt(std::max(v, 0.0));
+            if (!active[r]) continue;
+            const double w1 = hv2[(size_t)(j + 1) * R + r].x, w2 = w1 - sumsq(hv2, r);
+            if (!std::isfinite(w2)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+            if (w2 > 1e-2 * w1) hn[r] = std::sqrt(w2);
+            else explicit_norm = true;  // cancellation again: measure the norm directly
           }
-          scales();
-          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
-          HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, R, s));
+          if (!explicit_norm) {
+            scales();
+            HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+            HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s, sdev));
+          } else {
+            HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s));
+            HEOM_TRY(mdot<T>(vn, 0, 1, vn, n, R, partial, nchunk, h2 + (size_t)(j + 1) * R, s));
+            HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2 + (size_t)(j + 1) * R, sizeof(double2) * R, hipMemcpyDeviceToHost, s));
+            HEOM_HIP_CHECK(hipStreamSynchronize(s));
+            for (int r = 0; r < R; ++r) {
+              const double v = ((const double2 *)pin.p)[r].x;
+              if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+              hn[r] = std::sqrt(std::max(v, 0.0));
+            }
+            scales();
+            HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+            HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, R, s));
+          }
         }
       }
       HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack

@@ -51,6 +51,7 @@ struct Gmres {
   double stall = 0.0;
   PinnedBuf pin;
   std::vector<cd> H, sn, g;
+  std::vector<cd> G;  // Gram matrix of the current basis (single right-hand side)
   std::vector<double> cs;
   heom_status init(WsArena &ws, int64_t n, int R, int m, bool flexible);
   heom_status norms(const T2 *v, std::vector<double> &out, hipStream_t s);
