@@ -14,8 +14,9 @@ plain (Jacobi) GMRES and with the learned preconditioner in FGMRES, is
 reported under "solves": the stationary state of the same tier-4 model
 (network trained on pairs from seeded tier-3 perturbations of it), the
 stationary state of the single-impurity Anderson model (tier 3, 10,701
-ADOs; network trained on pairs from seeded perturbations), and a sample
-of its density of states.  Training time is reported beside each network;
+ADOs; network trained on pairs from seeded perturbations), and the densities
+of states of both models on their full grids (2,000 and 4,096 frequencies)
+with the multi-shift solver.  Training time is reported beside each network;
 GMRES without a preconditioner is timed too.  "batch_512_instances" times
 the batched path on 512 seeded uneven instances.
 
@@ -40,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "b4282ebb32f23ee1", "bytes": 7_589_248_000},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "9dce8daac3cc38c9", "bytes": 6_755_700_843},
 }
 
 
@@ -152,12 +153,13 @@ def _train_network(api, d, hidden, models, snapshots, restart, subset, epochs, s
     return net, info
 
 
-def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snapshots, pair_restart):
+def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snapshots, pair_restart,
+                      restart_none=None):
     """Stationary state to a 1e-8 true residual: Jacobi GMRES vs FGMRES with
     the network (which hands over to Jacobi if it stagnates)."""
     h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
-    (x_0, r0), t0 = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=restart, mode=mode,
-                                                     max_iter=20000, allow_not_converged=True))
+    (x_0, r0), t0 = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=restart_none or restart,
+                                                     mode=mode, max_iter=20000, allow_not_converged=True))
     del x_0
     _progress(f"{cfg['name']} N={h.N} steady, GMRES without preconditioner: {r0['iterations']} iterations, {t0:.2f} s")
     (x_p, rp), tp = _timed(lambda: api.steady_state(h, tol=1e-8, precond="jacobi", restart=restart, mode=mode,
@@ -177,7 +179,8 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     _progress(f"{cfg['name']} N={h.N} steady, NN FGMRES: {rn['iterations']} iterations, {tn:.2f} s, "
               f"fell back {rn['fell_back']}")
     best = min([t for t, r in ((t0, r0), (tp, rp)) if r["status"] == 0], default=None)
-    out = {"n_ado": h.N, "d": h.d, "restart": restart, "mode": mode, "nn_max_iter": cap,
+    out = {"n_ado": h.N, "d": h.d, "restart": restart, "restart_none": restart_none or restart, "mode": mode,
+           "nn_max_iter": cap,
            "plain_none": _solve_record(r0, t0), "plain_jacobi": _solve_record(rp, tp),
            "nn_fgmres": _solve_record(rn, tn), "network": {"hidden": hidden, **info},
            "nn_speedup_vs_jacobi": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None,
@@ -186,20 +189,34 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     return out
 
 
-def dos_sample(api, wl, n_omega=64):
-    """Density of states of the tier-3 SIAM at n_omega frequencies of its
-    2000-point grid (Jacobi GMRES, FP64, 1e-8 per solve; 2 solves per
-    frequency)."""
+def dos_benchmark(api, wl, cfg, restart=60, sample=64):
+    """Density of states on the model's full frequency grid with the
+    multi-shift solver (one Krylov space for all frequencies, FP64, 1e-8),
+    beside the per-frequency path (multi-RHS Jacobi GMRES, 1e-8) on an
+    evenly spaced sample of the grid, with the largest difference."""
     import numpy as np
-    cfg = wl.siam()
-    he = api.Hierarchy(cfg["H"], cfg["baths"], 0, cfg["n_max"], parity=+1, parity_op=cfg["parity_op"])
-    ho = api.Hierarchy(cfg["H"], cfg["baths"], 0, cfg["n_max"], parity=-1, parity_op=cfg["parity_op"])
-    x, _ = api.steady_state(he, tol=1e-10)
-    om = cfg["omegas"][:: max(1, len(cfg["omegas"]) // n_omega)][:n_omega]
-    (A, rep), t = _timed(lambda: api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-8, rhs_chunk=64))
-    _progress(f"siam DOS at {len(om)} frequencies: {t:.2f} s")
-    return {"n_omega": len(om), "solves": 2 * len(om), "plain_jacobi": _solve_record(rep, t),
-            "omega_per_s": round(len(om) / t, 2), "finite": bool(np.all(np.isfinite(A)))}
+    he = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=+1, parity_op=cfg["parity_op"])
+    ho = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=-1, parity_op=cfg["parity_op"])
+    x, _ = api.steady_state(he, tol=1e-10, precond="none", restart=60, max_iter=5000)
+    om = cfg["omegas"]
+    (A, rep), t = _timed(lambda: api.spectrum(he, ho, x, cfg["dops"][0], om, kind="dos", tol=1e-8, mode="shifted",
+                                              precond="none", restart=restart, max_iter=5000))
+    _progress(f"{cfg['name']} DOS at {len(om)} frequencies (multi-shift): {t:.2f} s")
+    out = {"n_ado": he.N, "n_omega": len(om), "solves": 2 * len(om), "multi_shift": _solve_record(rep, t),
+           "omega_per_s": round(len(om) / t, 2),
+           "sum_rule_window": float(A.sum() * (om[1] - om[0])), "finite": bool(np.all(np.isfinite(A)))}
+    if sample:
+        idx = np.linspace(0, len(om) - 1, sample).astype(int)
+        (As, rs), ts = _timed(lambda: api.spectrum(he, ho, x, cfg["dops"][0], om[idx], kind="dos", tol=1e-8,
+                                                   rhs_chunk=min(64, sample), precond="jacobi"))
+        out["per_frequency_jacobi_sample"] = {"n_omega": sample, **_solve_record(rs, ts),
+                                              "omega_per_s": round(sample / ts, 2),
+                                              "max_abs_diff_vs_multi_shift": float(np.abs(As - A[idx]).max()),
+                                              "max_abs_dos": float(np.abs(A).max())}
+        _progress(f"{cfg['name']} DOS per-frequency sample of {sample}: {ts:.2f} s")
+    he.close()
+    ho.close()
+    return out
 
 
 def batch_benchmark(api, wl):
@@ -293,10 +310,16 @@ def propagation_benchmarks(api, wl):
     _progress(f"charge-cavity RK4: {n_steps} steps in {t:.2f} s")
     # cavity power spectrum at its 1024 frequencies
     he = h
-    xs, _ = api.steady_state(he, tol=1e-10)
+    # weak couplings (lambda = 0.01, Gamma = 0.01) make this stationary state
+    # slow for restarted GMRES: its reached residual is reported with the PSD
+    (xs, rs), tss = _timed(lambda: api.steady_state(he, tol=1e-8, precond="none", restart=100, max_iter=4000,
+                                                    allow_not_converged=True))
+    _progress(f"charge-cavity steady state: {rs['iterations']} iterations, residual {rs['true_residual']:.2e}")
     (S, rep), t = _timed(lambda: api.spectrum(he, None, xs, cfg["aop"], cfg["omegas"], kind="psd", tol=1e-8,
-                                              rhs_chunk=64))
-    out["charge_cavity_psd"] = {"n_omega": len(cfg["omegas"]), "seconds": round(t, 3),
+                                              mode="shifted", precond="none", restart=60, max_iter=5000,
+                                              allow_not_converged=True))
+    out["charge_cavity_steady"] = _solve_record(rs, tss)
+    out["charge_cavity_psd"] = {"n_omega": len(cfg["omegas"]), "solver": "multi-shift", "seconds": round(t, 3),
                                 "omega_per_s": round(len(cfg["omegas"]) / t, 2), "iterations": rep["iterations"],
                                 "true_residual": rep["true_residual"], "finite": bool(np.all(np.isfinite(S)))}
     _progress(f"charge-cavity PSD at {len(cfg['omegas'])} frequencies: {t:.2f} s")
@@ -313,12 +336,13 @@ def solve_benchmarks(which):
         z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(4))
         siam_train.append(wl.siam(eps=-5.0 * z[0], U=10.0 * z[1], Gamma=2.0 * z[2], mus=(z[3], -z[3])))
     out["siam_tier3_steady"] = steady_comparison(api, wl, wl.siam(), siam_train, 4, 128, 30, "fp64", (10, 30, 60), 30)
-    out["siam_tier3_dos"] = dos_sample(api, wl, n_omega=2000)
+    out["siam_tier3_dos"] = dos_benchmark(api, wl, wl.siam())
     if which == "all":
         out.update(propagation_benchmarks(api, wl))
         train = [wl.perturbed_two_orbital(1000 + s, n_max=3) for s in range(3)]
         out["two_orbital_tier4_steady"] = steady_comparison(api, wl, wl.two_orbital_anderson(), train, 16, 256, 100,
-                                                            "fp64", (20, 60), 100)
+                                                            "fp64", (20, 60), 100, restart_none=60)
+        out["two_orbital_tier4_dos"] = dos_benchmark(api, wl, wl.two_orbital_anderson(), sample=0)
         out["batch_512_instances"] = batch_benchmark(api, wl)
     return out
 

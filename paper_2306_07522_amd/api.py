@@ -328,9 +328,11 @@ def collect_pairs(h, net, snapshots=(10, 30, 60), x_star=None, restart=60, tol=1
     return out
 
 
-def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, **opts):
+def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, allow_not_converged=False, **opts):
     """Density of states (kind 'dos', odd-parity `odd`) or power spectral
-    density (kind 'psd') of operator `op` at the given frequencies."""
+    density (kind 'psd') of operator `op` at the given frequencies.  With
+    allow_not_converged the values are returned when some frequency misses
+    the tolerance (report status 4)."""
     o = solver_opts(**opts)
     om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
     out = np.zeros(len(om))
@@ -339,9 +341,11 @@ def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, **opts):
     ws = _workspace(odd if k == 0 else even, L.HEOM_OP_SPECTRUM, o, cols)
     opm = _c128(op)
     rep = L.heom_solver_report()
-    L.check(lib().heom_spectrum(even.handle, odd.handle if odd is not None else None, _devptr(x_ss), k, _dptr(opm),
-                                _dptr(om), len(om), _dptr(out), C.byref(o), C.byref(rep),
-                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    st = lib().heom_spectrum(even.handle, odd.handle if odd is not None else None, _devptr(x_ss), k, _dptr(opm),
+                             _dptr(om), len(om), _dptr(out), C.byref(o), C.byref(rep),
+                             C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    if not (allow_not_converged and st == 4):
+        L.check(st)
     return out, report_dict(rep)
 
 
