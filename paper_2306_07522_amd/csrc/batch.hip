@@ -193,6 +193,93 @@ __global__ void seg_reduce_kernel(const double2 *__restrict__ partial, int k, in
   out[idx] = make_double2(sx, sy);
 }
 
+// Two vectors in one pass over the basis, per instance:
+// partial[i] = conj(V_i) . w, partial[k + i] = conj(V_i) . u (i < k), partial[2k] = w . w
+template <typename T, int NI>
+__global__ void __launch_bounds__(256) seg_mdot2_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
+                                                        const typename Cplx<T>::t *__restrict__ w,
+                                                        const typename Cplx<T>::t *__restrict__ u,
+                                                        const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg,
+                                                        int n_chunks, const int *__restrict__ active,
+                                                        double2 *__restrict__ partial) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double2 red[2 * NI + 1][256];
+  const int c = blockIdx.x;
+  const int i0 = blockIdx.y * NI;
+  const bool on = !active || active[ch_seg[c]];
+  double ax[NI], ay[NI], cx[NI], cy[NI], ww = 0.0;
+#pragma unroll
+  for (int q = 0; q < NI; ++q) ax[q] = ay[q] = cx[q] = cy[q] = 0.0;
+  if (on) {
+    for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
+      const T2 bw = w[e], bu = u[e];
+      if (blockIdx.y == 0) ww += (double)bw.x * bw.x + (double)bw.y * bw.y;
+#pragma unroll
+      for (int q = 0; q < NI; ++q)
+        if (i0 + q < k) {
+          const T2 a = V[(i0 + q) * ldv + e];
+          ax[q] += (double)a.x * bw.x + (double)a.y * bw.y;
+          ay[q] += (double)a.x * bw.y - (double)a.y * bw.x;
+          cx[q] += (double)a.x * bu.x + (double)a.y * bu.y;
+          cy[q] += (double)a.x * bu.y - (double)a.y * bu.x;
+        }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    red[q][threadIdx.x] = make_double2(ax[q], ay[q]);
+    red[NI + q][threadIdx.x] = make_double2(cx[q], cy[q]);
+  }
+  red[2 * NI][threadIdx.x] = make_double2(ww, 0.0);
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+#pragma unroll
+      for (int q = 0; q < 2 * NI + 1; ++q) {
+        red[q][threadIdx.x].x += red[q][threadIdx.x + st].x;
+        red[q][threadIdx.x].y += red[q][threadIdx.x + st].y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NI && i0 + (int)threadIdx.x < k) {
+    partial[(int64_t)(i0 + threadIdx.x) * n_chunks + c] = red[threadIdx.x][0];
+    partial[(int64_t)(k + i0 + threadIdx.x) * n_chunks + c] = red[NI + threadIdx.x][0];
+  }
+  if (blockIdx.y == 0 && threadIdx.x == 0) partial[(int64_t)(2 * k) * n_chunks + c] = red[2 * NI][0];
+}
+
+// Per instance (one thread each): record the new Gram column c = V^H v_j
+// and form the twice-projected coefficients h = a + (a - G a), a = V^H w
+// (CGS2's second projection from the measured Gram matrix G = V^H V).
+// red: [(2k + 1)][S] reduced a, c, |w|^2; G: [S][ldg][ldg] column-major.
+__global__ void batch_gram_kernel(double2 *__restrict__ G, const double2 *__restrict__ red, int j, int S, int ldg,
+                                  const int *__restrict__ active, double2 *__restrict__ hout) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int k = j + 1;
+  if (active && !active[s]) {
+    for (int i = 0; i < k; ++i) hout[(int64_t)i * S + s] = make_double2(0.0, 0.0);
+    return;
+  }
+  double2 *Gs = G + (size_t)s * ldg * ldg;
+  for (int i = 0; i < k; ++i) {
+    const double2 c = red[(int64_t)(k + i) * S + s];
+    Gs[(size_t)j * ldg + i] = c;
+    Gs[(size_t)i * ldg + j] = make_double2(c.x, -c.y);
+  }
+  for (int i = 0; i < k; ++i) {
+    double gx = 0.0, gy = 0.0;
+    for (int q = 0; q < k; ++q) {
+      const double2 g = Gs[(size_t)q * ldg + i], a = red[(int64_t)q * S + s];
+      gx += g.x * a.x - g.y * a.y;
+      gy += g.x * a.y + g.y * a.x;
+    }
+    const double2 a = red[(int64_t)i * S + s];
+    hout[(int64_t)i * S + s] = make_double2(2.0 * a.x - gx, 2.0 * a.y - gy);
+  }
+}
+
 // w += sign * sum_{i < k} V_i h[i * S + seg]
 template <typename T>
 __global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
@@ -335,6 +422,23 @@ static heom_status seg_mdot(heom_batch &b, const void *V, int64_t ldv, int k, co
 }
 
 template <typename T>
+static heom_status seg_mdot2(heom_batch &b, const void *V, int64_t ldv, int k, const void *w, const void *u,
+                             double2 *partial, double2 *out, hipStream_t s) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int NI = 4;
+  dim3 grid(b.n_chunks, (k + NI - 1) / NI);
+  hipLaunchKernelGGL((seg_mdot2_kernel<T, NI>), grid, dim3(256), 0, s, (const T2 *)V, ldv, k, (const T2 *)w,
+                     (const T2 *)u, b.ch_e, b.ch_seg, b.n_chunks, b.active, partial);
+  HEOM_HIP_CHECK(hipGetLastError());
+  const int kk = 2 * k + 1;
+  const int64_t tot = (int64_t)kk * b.S;
+  hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, kk, b.n_chunks,
+                     b.seg_chunk, b.S, out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
 static heom_status seg_update(heom_batch &b, const void *V, int64_t ldv, int k, const double2 *h, void *w,
                               double sign, hipStream_t s) {
   using T2 = typename Cplx<T>::t;
@@ -379,10 +483,10 @@ struct BatchGmres {
   heom_batch *b = nullptr;
   int m = 30;
   T2 *V = nullptr, *Z = nullptr, *w = nullptr;
-  double2 *partial = nullptr, *hdev = nullptr;
+  double2 *partial = nullptr, *hdev = nullptr, *gram = nullptr;
   double *sdev = nullptr;
   double *pin_sc = nullptr;       // host pinned [S]
-  double2 *pin_h = nullptr;       // host pinned [2 (m + 2) S]
+  double2 *pin_h = nullptr;       // host pinned: step coefficients [(m + 1) S] and norms [S]
   PinnedBuf pin;
   bool use_graph = false;
   bool jacobi = true;                  // false: no preconditioner (Z aliases V)
@@ -396,8 +500,9 @@ struct BatchGmres {
 
   static size_t bytes(const heom_batch &b, int m, bool jac) {
     const size_t vec = (size_t)b.n * sizeof(T2);
-    return (size_t)(m + 1) * vec + (jac ? (size_t)m * vec : 0) + vec + (size_t)(m + 2) * b.n_chunks * sizeof(double2) +
-           (size_t)2 * (m + 2) * b.S * sizeof(double2) + (size_t)b.S * sizeof(double) + 8 * 256;
+    return (size_t)(m + 1) * vec + (jac ? (size_t)m * vec : 0) + vec + (size_t)(2 * m + 3) * b.n_chunks * sizeof(double2) +
+           (size_t)(3 * m + 5) * b.S * sizeof(double2) + (size_t)b.S * (m + 1) * (m + 1) * sizeof(double2) +
+           (size_t)b.S * sizeof(double) + 8 * 256;
   }
 
   heom_status init(heom_batch &bb, WsArena &ws, int m_, bool graph, bool jac) {
@@ -409,32 +514,41 @@ struct BatchGmres {
     V = (T2 *)ws.take((size_t)(m + 1) * vec);
     Z = jacobi ? (T2 *)ws.take((size_t)m * vec) : V;
     w = (T2 *)ws.take(vec);
-    partial = (double2 *)ws.take((size_t)(m + 2) * b->n_chunks * sizeof(double2));
-    hdev = (double2 *)ws.take((size_t)2 * (m + 2) * b->S * sizeof(double2));
+    partial = (double2 *)ws.take((size_t)(2 * m + 3) * b->n_chunks * sizeof(double2));
+    // hdev: [0, (2m+3) S) reduced a, c, |w|^2;  then h [(m+1) S] and |w'|^2 [S]
+    hdev = (double2 *)ws.take((size_t)(3 * m + 5) * b->S * sizeof(double2));
+    gram = (double2 *)ws.take((size_t)b->S * (m + 1) * (m + 1) * sizeof(double2));
     sdev = (double *)ws.take((size_t)b->S * sizeof(double));
-    if (!V || !Z || !w || !partial || !hdev || !sdev) return fail(HEOM_ERR_ARG, "batch: workspace too small");
-    HEOM_TRY(pin.ensure((size_t)2 * (m + 2) * b->S * sizeof(double2) + (size_t)b->S * sizeof(double)));
+    if (!V || !Z || !w || !partial || !hdev || !gram || !sdev) return fail(HEOM_ERR_ARG, "batch: workspace too small");
+    HEOM_TRY(pin.ensure((size_t)(m + 2) * b->S * sizeof(double2) + (size_t)(m + 1) * b->S * sizeof(double2) +
+                        (size_t)b->S * sizeof(double)));
     pin_h = (double2 *)pin.p;
-    pin_sc = (double *)(pin_h + (size_t)2 * (m + 2) * b->S);
+    pin_sc = (double *)(pin_h + (size_t)(2 * m + 3) * b->S);
     graphs.assign(m, nullptr);
     if (use_graph) HEOM_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     return HEOM_OK;
   }
 
-  // device work of Arnoldi step j: z_j = P v_j, w = B z_j, CGS2, |w|^2, copy to host
+  double2 *h_out() const { return hdev + (size_t)(2 * m + 3) * b->S; }   // [(m+1)][S] coefficients
+  double2 *n_out() const { return h_out() + (size_t)(m + 1) * b->S; }    // [S] |w'|^2
+
+  // Device work of Arnoldi step j: z_j = P v_j, w = B z_j, then CGS2 in two
+  // passes over the basis: one two-vector multi-dot (a = V^H w, the Gram
+  // column V^H v_j, |w|^2), the per-instance Gram correction, one update;
+  // then |w|^2 and the copy of the coefficients to the host.
   heom_status step_device(int j, int border, hipStream_t s) {
     const int64_t n = b->n;
     T2 *vj = V + (size_t)j * n;
     T2 *zj = Z + (size_t)j * n;
     if (jacobi) HEOM_TRY(batch_jacobi_T<T>(*b, vj, zj, border, s));
     HEOM_TRY(batch_apply_T<T>(*b, zj, w, border, true, s));
-    double2 *h1 = hdev, *h2 = hdev + (size_t)(m + 2) * b->S;
-    HEOM_TRY(seg_mdot<T>(*b, V, n, j + 1, w, partial, h1, s));
-    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h1, w, -1.0, s));
-    HEOM_TRY(seg_mdot<T>(*b, V, n, j + 1, w, partial, h2, s));
-    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h2, w, -1.0, s));
-    HEOM_TRY(seg_mdot<T>(*b, w, 0, 1, w, partial, h2 + (size_t)(j + 1) * b->S, s));
-    HEOM_HIP_CHECK(hipMemcpyAsync(pin_h, hdev, sizeof(double2) * 2 * (m + 2) * b->S, hipMemcpyDeviceToHost, s));
+    HEOM_TRY(seg_mdot2<T>(*b, V, n, j + 1, w, vj, partial, hdev, s));
+    hipLaunchKernelGGL(batch_gram_kernel, dim3((b->S + 255) / 256), dim3(256), 0, s, gram, hdev, j, b->S, m + 1,
+                       b->active, h_out());
+    HEOM_HIP_CHECK(hipGetLastError());
+    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h_out(), w, -1.0, s));
+    HEOM_TRY(seg_mdot<T>(*b, w, 0, 1, w, partial, n_out(), s));
+    HEOM_HIP_CHECK(hipMemcpyAsync(pin_h, h_out(), sizeof(double2) * (m + 2) * b->S, hipMemcpyDeviceToHost, s));
     return HEOM_OK;
   }
 
@@ -541,17 +655,15 @@ struct BatchGmres {
         ++applies;
         ++it_total;
         HEOM_HIP_CHECK(hipStreamSynchronize(s));
-        const double2 *hp1 = pin_h, *hp2 = pin_h + (size_t)(m + 2) * S;
+        const double2 *hp1 = pin_h, *hnrm = pin_h + (size_t)(m + 1) * S;
         bool more = false;
         for (int q = 0; q < S; ++q) {
           pin_sc[q] = 0.0;
           if (!ext[q]) continue;
           ++iters[q];
           cd *Hc = &H[((size_t)q * (m + 1)) * m];
-          for (int i = 0; i <= j; ++i)
-            Hc[(size_t)j * (m + 1) + i] = cd(hp1[(size_t)i * S + q].x + hp2[(size_t)i * S + q].x,
-                                             hp1[(size_t)i * S + q].y + hp2[(size_t)i * S + q].y);
-          const double hn = std::sqrt(std::max(hp2[(size_t)(j + 1) * S + q].x, 0.0));
+          for (int i = 0; i <= j; ++i) Hc[(size_t)j * (m + 1) + i] = cd(hp1[(size_t)i * S + q].x, hp1[(size_t)i * S + q].y);
+          const double hn = std::sqrt(std::max(hnrm[q].x, 0.0));
           if (!std::isfinite(hn)) return fail(HEOM_ERR_NAN, "batch: non-finite Arnoldi norm");
           Hc[(size_t)j * (m + 1) + j + 1] = hn;
           cd *col = &Hc[(size_t)j * (m + 1)];
