@@ -67,17 +67,29 @@ struct ApplyParams {
 };
 
 // ----------------------------------------------------------------- wave kernel
+template <int D>
+struct WaveShape {
+  static constexpr int DD = D * D;
+  static constexpr int EPL = (DD + 63) / 64;   // elements per lane
+  static constexpr bool FULL = DD % 64 == 0;   // no masked tail
+  static constexpr bool UJ = 64 % D == 0;      // column index the same for all of a lane's elements
+  static __device__ __forceinline__ bool on(int lane, int s) { return FULL || lane + 64 * s < DD; }
+  static __device__ __forceinline__ int col(int lane, int s) { return UJ ? lane % D : (lane + 64 * s) % D; }
+};
+
 template <typename T, int D, bool FUSE>
 __device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, int lane,
-                                           typename Cplx<T>::t (&v)[D * D / 64]) {
+                                           typename Cplx<T>::t (&v)[WaveShape<D>::EPL]) {
+  using W = WaveShape<D>;
   constexpr int DD = D * D;
   const typename Cplx<T>::t *xb = P.x + b * DD;
 #pragma unroll
-  for (int s = 0; s < DD / 64; ++s) v[s] = xb[lane + 64 * s];
+  for (int s = 0; s < W::EPL; ++s) v[s] = W::on(lane, s) ? xb[lane + 64 * s] : typename Cplx<T>::t{0, 0};
   if (FUSE) {
     const typename Cplx<T>::t *kb = P.kvec + b * DD;
 #pragma unroll
-    for (int s = 0; s < DD / 64; ++s) {
+    for (int s = 0; s < W::EPL; ++s) {
+      if (!W::on(lane, s)) continue;
       const typename Cplx<T>::t q = kb[lane + 64 * s];
       v[s].x = fma(P.kc, q.x, v[s].x);
       v[s].y = fma(P.kc, q.y, v[s].y);
@@ -91,11 +103,12 @@ __device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, i
 // task the next group's first neighbour block is prefetched while the
 // current group is finished; multi-edge groups stream two blocks at a time.
 template <typename T, int D, bool FUSE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) apply_wave_kernel(ApplyParams<T> P) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WaveShape<D>::EPL > 4 ? 2 : 4)))
+apply_wave_kernel(ApplyParams<T> P) {
   using T2 = typename Cplx<T>::t;
+  using W = WaveShape<D>;
   constexpr int DD = D * D;
-  constexpr int EPL = DD / 64;  // elements per lane
-  static_assert(DD % 64 == 0, "wave kernel needs d^2 divisible by 64");
+  constexpr int EPL = W::EPL;
   extern __shared__ __align__(16) unsigned char smem[];
   T2 *sbuf = reinterpret_cast<T2 *>(smem);              // [4][DD] group staging, one slice per wave
   T2 *tval = sbuf + 4 * DD;                             // compact operator values
@@ -112,7 +125,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
   // the task index is uniform across the wave: keep every table lookup scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T2 *buf = sbuf + wave * DD;
-  const int j = lane % D;
   int64_t blk = blockIdx.x;
   if (P.xchunk > 0 && (int64_t)(blockIdx.x / P.xchunk + 1) * P.xchunk <= (int64_t)gridDim.x) {
     // XCD-aware remap inside super-chunks of xchunk blocks: block b runs on
@@ -130,7 +142,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
     const int64_t abase = a * DD;
     T2 acc[EPL];
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) acc[s] = (flags & TASK_ACC) ? P.y[abase + lane + 64 * s] : T2{0, 0};
+    for (int s = 0; s < EPL; ++s) acc[s] = (flags & TASK_ACC) && W::on(lane, s) ? P.y[abase + lane + 64 * s] : T2{0, 0};
     T2 trace{0, 0};
     int g = tk.y;
     if (g < tk.z) {
@@ -179,7 +191,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
           const T2 c = csub(P.decay[a], z);
 #pragma unroll
           for (int s = 0; s < EPL; ++s) {
-            const T2 dh = csub(thd[(lane + 64 * s) / D], thd[j]);
+            const T2 dh = csub(thd[(lane + 64 * s) / D], thd[W::col(lane, s)]);
             const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
             acc[s] = csub(acc[s], cmul(f, u[s]));
           }
@@ -190,16 +202,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
         const bool need_trace = gr.w && P.border && a == 0;
         if (ns > 0 || need_trace) {
 #pragma unroll
-          for (int s = 0; s < EPL; ++s) buf[lane + 64 * s] = u[s];
+          for (int s = 0; s < EPL; ++s)
+            if (W::on(lane, s)) buf[lane + 64 * s] = u[s];
           wave_sync();
           if (need_trace && lane == 0)
             for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
           if (ns > 0) {
             const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
-            const int rbase = off + (D + j) * ns;
 #pragma unroll
             for (int s = 0; s < EPL; ++s) {
+              if (!W::on(lane, s)) continue;
               const int i = (lane + 64 * s) / D;
+              const int j = W::col(lane, s);
+              const int rbase = off + (D + j) * ns;
               const int lbase = off + i * ns;
               T2 L{0, 0}, Rv{0, 0};
               if (isreal) {
@@ -229,6 +244,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) a
     }
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
+      if (!W::on(lane, s)) continue;
       T2 v = acc[s];
       if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;
       P.y[abase + lane + 64 * s] = v;
@@ -350,7 +366,7 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   const int d = h.d;
   const size_t tab_bytes = (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 16 + (size_t)d * sizeof(T2);
   const size_t smem = 4 * (size_t)d * d * sizeof(T2) + tab_bytes;
-  if (a.n_rhs == 1 && (d == 8 || d == 16) && smem <= 48 * 1024) {
+  if (a.n_rhs == 1 && (d == 8 || d == 16 || d == 20) && smem <= 48 * 1024) {
     P.tpw = 1;
     P.xchunk = 64;
     const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
@@ -359,6 +375,9 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
     if (d == 8) {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 8, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 8, false>), g, b, smem, s, P);
+    } else if (d == 20) {
+      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 20, true>), g, b, smem, s, P);
+      else hipLaunchKernelGGL((apply_wave_kernel<T, 20, false>), g, b, smem, s, P);
     } else {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false>), g, b, smem, s, P);
