@@ -201,7 +201,9 @@ heom_status heom_apply_tiled(heom_hier *h, int32_t precision, const void *x_dev,
  * receives the reduced density operator (ADO 0, d*d complex of the given
  * precision) after every save_every steps: n_steps / save_every entries.
  * Workspace: heom_workspace_size(HEOM_OP_PROPAGATE).  graph_steps > 0
- * captures that many steps in a hipGraph and replays it. */
+ * captures that many steps in a hipGraph and replays it.  Hierarchies of at
+ * most 1024 complex elements (N d^2) run many whole steps per launch in one
+ * workgroup instead (graph_steps is then ignored). */
 heom_status heom_propagate(heom_hier *h, int32_t precision, void *x_dev, double dt, int64_t n_steps,
                            int64_t save_every, void *rho0_traj_dev, int32_t graph_steps, void *ws,
                            size_t ws_bytes, void *stream);

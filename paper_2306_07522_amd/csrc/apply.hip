@@ -329,6 +329,122 @@ __global__ void __launch_bounds__(256) apply_cell_kernel(ApplyParams<T> P) {
   }
 }
 
+// ----------------------------------------------------------------- small-system RK4
+// Whole RK4 steps of a hierarchy with N d^2 <= 1024 elements in one
+// workgroup: thread t owns one output element (task t / d^2, cell t % d^2)
+// and keeps x, the RK4 accumulator and the stage result in registers; only
+// the stage input lives in LDS, where the neighbour gathers of the apply
+// read it.  One launch runs many steps, so a step costs four barriers
+// instead of five kernel launches (small systems are launch-latency bound).
+template <typename T>
+__global__ void __launch_bounds__(1024) rk4_small_kernel(ApplyParams<T> P, typename Cplx<T>::t *__restrict__ x, T dt, int64_t steps,
+                                                         int64_t save_every, int64_t step0, int64_t n_saves,
+                                                         typename Cplx<T>::t *__restrict__ traj) {
+  using T2 = typename Cplx<T>::t;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T2 *u = reinterpret_cast<T2 *>(smem);
+  const int d = P.d, dd = d * d;
+  const int t = threadIdx.x;
+  const int64_t n = P.n_tasks * dd;
+  const bool own = t < n;
+  int64_t a = 0;
+  int i = 0, j = 0, g0 = 0, g1 = 0;
+  if (own) {
+    const int4 tk = P.tasks[t / dd];
+    a = tk.x;
+    g0 = tk.y;
+    g1 = tk.z;
+    i = (t % dd) / d;
+    j = (t % dd) % d;
+  }
+  const int64_t e = a * dd + (int64_t)i * d + j;
+  T2 xv = own ? x[e] : T2{0, 0};
+  auto stage = [&](const T2 &in) -> T2 {
+    __syncthreads();  // previous readers of u are done
+    if (own) u[e] = in;
+    __syncthreads();
+    T2 acc{0, 0};
+    if (!own) return acc;
+    for (int g = g0; g < g1; ++g) {
+      const int4 gr = P.groups[g];
+      const int op = P.coef_op[gr.z];
+      const size_t rowL = ((size_t)op * 2) * d + i;
+      const size_t rowR = ((size_t)op * 2 + 1) * d + j;
+      const int nl = P.ell_cnt[rowL], nr = P.ell_cnt[rowR];
+      T2 L{0, 0}, Rv{0, 0};
+      for (int ed = gr.x; ed < gr.y; ++ed) {
+        const int2 edge = P.gedges[ed];
+        const T w = (T)edge.y;
+        const T2 *ub = u + (int64_t)edge.x * dd;
+        T2 l{0, 0}, rr{0, 0};
+        for (int q = 0; q < nl; ++q) l = cfma(P.ell_val[rowL * P.slots + q], ub[P.ell_col[rowL * P.slots + q] * d + j], l);
+        for (int q = 0; q < nr; ++q) rr = cfma(ub[i * d + P.ell_col[rowR * P.slots + q]], P.ell_val[rowR * P.slots + q], rr);
+        L.x = fma(w, l.x, L.x); L.y = fma(w, l.y, L.y);
+        Rv.x = fma(w, rr.x, Rv.x); Rv.y = fma(w, rr.y, Rv.y);
+      }
+      if (gr.w) acc = csub(acc, cmul(P.decay[a], u[e]));
+      acc = cfma(P.coef[2 * gr.z], L, acc);
+      acc = cfma(P.coef[2 * gr.z + 1], Rv, acc);
+    }
+    return acc;
+  };
+  const T h2 = dt / 2, h6 = dt / 6, h3 = dt / 3;
+  for (int64_t st = 0; st < steps; ++st) {
+    const T2 k1 = stage(xv);
+    T2 acc{xv.x + h6 * k1.x, xv.y + h6 * k1.y};
+    const T2 k2 = stage(T2{xv.x + h2 * k1.x, xv.y + h2 * k1.y});
+    acc.x += h3 * k2.x; acc.y += h3 * k2.y;
+    const T2 k3 = stage(T2{xv.x + h2 * k2.x, xv.y + h2 * k2.y});
+    acc.x += h3 * k3.x; acc.y += h3 * k3.y;
+    const T2 k4 = stage(T2{xv.x + dt * k3.x, xv.y + dt * k3.y});
+    acc.x += h6 * k4.x; acc.y += h6 * k4.y;
+    xv = acc;
+    const int64_t gs = step0 + st + 1;
+    if (save_every > 0 && gs % save_every == 0 && own && a == 0) {
+      const int64_t slot = gs / save_every - 1;
+      if (slot < n_saves) traj[slot * dd + (int64_t)i * d + j] = xv;
+    }
+  }
+  if (own) x[e] = xv;
+}
+
+template <typename T>
+static heom_status launch_rk4_small_T(Hier &h, void *x, double dt, int64_t steps, int64_t save_every, int64_t step0,
+                                      int64_t n_saves, void *traj, hipStream_t s) {
+  using T2 = typename Cplx<T>::t;
+  DeviceTables &D = h.dev;
+  constexpr bool dbl = std::is_same<T, double>::value;
+  ApplyParams<T> P{};
+  P.tasks = D.base.tasks;
+  P.n_tasks = D.base.task_off.back();
+  P.groups = D.base.groups;
+  P.gedges = D.base.gedges;
+  P.decay = dbl ? (const T2 *)D.decay64 : (const T2 *)D.decay32;
+  P.ell_cnt = D.ell_cnt;
+  P.ell_col = D.ell_col;
+  P.ell_val = dbl ? (const T2 *)D.ell_val64 : (const T2 *)D.ell_val32;
+  P.slots = h.ell.slots;
+  P.coef_op = D.coef_op;
+  P.coef = dbl ? (const T2 *)D.coef64 : (const T2 *)D.coef32;
+  P.d = h.d;
+  P.R = 1;
+  const size_t smem = (size_t)h.N * h.d * h.d * sizeof(T2);
+  hipLaunchKernelGGL(rk4_small_kernel<T>, dim3(1), dim3(1024), smem, s, P, (typename Cplx<T>::t *)x, (T)dt, steps, save_every, step0,
+                     n_saves, (T2 *)traj);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+bool rk4_small_fits(const Hier &h) { return h.N * (int64_t)h.d * h.d <= 1024; }
+
+heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t steps, int64_t save_every,
+                             int64_t step0, int64_t n_saves, void *traj, hipStream_t s) {
+  HEOM_TRY(ensure_device(h));
+  if (!rk4_small_fits(h)) return fail(HEOM_ERR_UNSUPPORTED, "rk4_small: more than 1024 elements");
+  if (precision == HEOM_FP64) return launch_rk4_small_T<double>(h, x, dt, steps, save_every, step0, n_saves, traj, s);
+  return launch_rk4_small_T<float>(h, x, dt, steps, save_every, step0, n_saves, traj, s);
+}
+
 template <typename T>
 static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1, hipStream_t s) {
   using T2 = typename Cplx<T>::t;

@@ -243,6 +243,14 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
   Hier &h = *hw->impl;
   hipStream_t caller = (hipStream_t)stream;
   HEOM_TRY(ensure_device(h));
+  if (rk4_small_fits(h)) {
+    // small hierarchies: many whole steps per launch, in one workgroup
+    const int64_t n_saves = save_every > 0 ? n_steps / save_every : 0;
+    for (int64_t done = 0; done < n_steps; done += 4096)
+      HEOM_TRY(launch_rk4_small(h, precision, x_dev, dt, std::min<int64_t>(4096, n_steps - done), save_every, done,
+                                n_saves, traj_dev, caller));
+    return HEOM_OK;
+  }
   // Graph capture needs a non-default stream: run on a private stream that
   // is ordered after, and before, the caller's stream.
   const bool use_graph = graph_steps > 0 && n_steps >= graph_steps;

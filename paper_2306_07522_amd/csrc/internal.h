@@ -146,6 +146,10 @@ struct ApplyArgs {
   int border = 0;               // 1: replace y[0][0][0] by Tr rho_0 (steady-state row)
 };
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
+// whole RK4 steps in one workgroup for hierarchies of at most 1024 elements
+bool rk4_small_fits(const Hier &h);
+heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t steps, int64_t save_every,
+                             int64_t step0, int64_t n_saves, void *traj, hipStream_t s);
 heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n_chunks, hipStream_t s);
 
 }  // namespace heom

@@ -72,11 +72,15 @@ def test_rk4_graph_equals_eager():
     assert torch.equal(xa, xb) and torch.equal(ta, tb)
 
 
-@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small"])
+@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small", "siam_tier1", "cavity_d20"])
 def test_rk4_workloads(name):
     torch, api = _torch(), _api()
     if name == "charge_cavity":
         cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=3)   # d = 8: wave kernel with fused stages
+    elif name == "siam_tier1":
+        cfg = wl.siam(n_max=1)                                    # 41 ADOs x 16: one-workgroup RK4 kernel
+    elif name == "cavity_d20":
+        cfg = wl.charge_cavity(n_photon=10, n_bexp=2, n_fexp=2, m_max=1, n_max=1)  # d = 20: masked wave kernel
     else:
         cfg = wl.two_orbital_anderson(n_max=2)                    # d = 16: wave kernel with fused stages
     om, lm = oracle_model(cfg), library_model(cfg)
