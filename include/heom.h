@@ -212,7 +212,12 @@ heom_status heom_propagate(heom_hier *h, int32_t precision, void *x_dev, double 
  * Linear solves (stationary state and spectra)
  * ---------------------------------------------------------------------- */
 enum { HEOM_OP_PROPAGATE = 0, HEOM_OP_STEADY = 1, HEOM_OP_SPECTRUM = 2 };
-enum { HEOM_PREC_NONE = 0, HEOM_PREC_JACOBI = 1, HEOM_PREC_NN = 2 };
+/* Preconditioners (right): none; Jacobi, the inverse diagonal of the system;
+ * the learned network (HEOM_PREC_NN, see below); SCALED, division by the
+ * modulus of the diagonal, a positive scaling that leaves the orientation of
+ * the operator's left-half-plane spectrum alone (Jacobi's complex phases
+ * rotate parts of it around the origin, which can slow restarted GMRES). */
+enum { HEOM_PREC_NONE = 0, HEOM_PREC_JACOBI = 1, HEOM_PREC_NN = 2, HEOM_PREC_SCALED = 3 };
 /* HEOM_SOLVE_SHIFTED (heom_spectrum only, precond HEOM_PREC_NONE): all
  * frequencies share one Krylov space of the unshifted operator (restarted
  * full orthogonalisation, whose residuals stay parallel across shifts);

@@ -19,7 +19,7 @@ HEOM_BOSON, HEOM_FERMION = 0, 1
 HEOM_U_R, HEOM_U_I, HEOM_U_RI = 0, 1, 2
 HEOM_PADE, HEOM_MATSUBARA = 0, 1
 HEOM_OP_PROPAGATE, HEOM_OP_STEADY, HEOM_OP_SPECTRUM = 0, 1, 2
-HEOM_PREC_NONE, HEOM_PREC_JACOBI, HEOM_PREC_NN = 0, 1, 2
+HEOM_PREC_NONE, HEOM_PREC_JACOBI, HEOM_PREC_NN, HEOM_PREC_SCALED = 0, 1, 2, 3
 HEOM_SOLVE_FP64, HEOM_SOLVE_FP32_IR, HEOM_SOLVE_SHIFTED = 0, 1, 2
 
 

@@ -230,7 +230,7 @@ def apply_steady_operator(h, x, y=None, stream=None):
 
 
 # ----------------------------------------------------------------- solvers
-_PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN}
+_PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN, "scaled": L.HEOM_PREC_SCALED}
 _MODE = {"fp64": L.HEOM_SOLVE_FP64, "fp32_ir": L.HEOM_SOLVE_FP32_IR, "shifted": L.HEOM_SOLVE_SHIFTED}
 
 

@@ -24,8 +24,11 @@ template <typename T>
 heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s);
 template <typename TX, typename TY>
 heom_status axpby(const void *x, double alpha, void *y, double beta, int64_t total, hipStream_t s);
+// z = D^{-1} r with D the diagonal of (M + shift) (bordered: element (0,0) of
+// ADO 0 counts 1; zeros count 1); modulus = 1 divides by |D| instead
 template <typename T>
-heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s);
+heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s,
+                   int modulus = 0);
 template <typename T>
 heom_status rk4_combine(void *x, const void *k1, const void *k2, const void *k3, const void *k4, double dt,
                         int64_t total, hipStream_t s);

@@ -201,7 +201,7 @@ __global__ void axpby_kernel(const typename Cplx<TX>::t *__restrict__ x, double 
 template <typename T>
 __global__ void jacobi_kernel(const typename Cplx<T>::t *__restrict__ r, typename Cplx<T>::t *__restrict__ z,
                               const double2 *__restrict__ decay, const double2 *__restrict__ hdiag, int d, int64_t N,
-                              int R, const double2 *__restrict__ shifts, int border) {
+                              int R, const double2 *__restrict__ shifts, int border, int modulus) {
   using T2 = typename Cplx<T>::t;
   const int64_t total = N * d * d * R;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -220,6 +220,7 @@ __global__ void jacobi_kernel(const typename Cplx<T>::t *__restrict__ r, typenam
     if (border && e == 0) dg = make_double2(1.0, 0.0);
     const double m2 = dg.x * dg.x + dg.y * dg.y;
     if (m2 == 0.0) dg = make_double2(1.0, 0.0);
+    else if (modulus) dg = make_double2(sqrt(m2), 0.0);  // |diagonal|: a positive scaling
     const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
     const T2 v = r[idx];
     // v / dg = v * conj(dg) / |dg|^2
@@ -376,10 +377,11 @@ heom_status axpby(const void *x, double alpha, void *y, double beta, int64_t tot
 }
 
 template <typename T>
-heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s) {
+heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s,
+                   int modulus) {
   hipLaunchKernelGGL(jacobi_kernel<T>, dim3(grid_for(h.N * h.d * h.d * R)), dim3(256), 0, s,
                      (const typename Cplx<T>::t *)r, (typename Cplx<T>::t *)z, h.dev.decay64, h.dev.hdiag, h.d, h.N, R,
-                     shifts, border);
+                     shifts, border, modulus);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -434,7 +436,7 @@ heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const
   template heom_status basis_update<T>(const void *, int64_t, int, const double2 *, void *, int64_t, int, double,  \
                                        hipStream_t, const double2 *);                                              \
   template heom_status scale_vec<T>(const void *, const double2 *, void *, int64_t, int, hipStream_t);             \
-  template heom_status jacobi<T>(const void *, void *, const Hier &, int, const double2 *, int, hipStream_t);       \
+  template heom_status jacobi<T>(const void *, void *, const Hier &, int, const double2 *, int, hipStream_t, int);  \
   template heom_status rk4_combine<T>(void *, const void *, const void *, const void *, const void *, double,      \
                                       int64_t, hipStream_t);                                                       \
   template heom_status save_rho0<T>(const void *, void *, int, int *, int64_t, hipStream_t);                       \

@@ -70,9 +70,9 @@ static std::function<heom_status(const void *, void *)> make_A(const LinearProbl
 template <typename T>
 static std::function<heom_status(const void *, void *, bool)> make_P(const LinearProblem &lp, const heom_solver_opts &o,
                                                                     NnApply *nn, hipStream_t s) {
-  if (o.precond == HEOM_PREC_JACOBI)
+  if (o.precond == HEOM_PREC_JACOBI || o.precond == HEOM_PREC_SCALED)
     return [=](const void *in, void *out, bool) -> heom_status {
-      return jacobi<T>(in, out, *lp.h, lp.R, lp.shifts64, lp.border, s);
+      return jacobi<T>(in, out, *lp.h, lp.R, lp.shifts64, lp.border, s, o.precond == HEOM_PREC_SCALED);
     };
   if (o.precond == HEOM_PREC_NN && nn)
     return [=](const void *in, void *out, bool) -> heom_status { return nn->apply<T>(in, out, s); };
@@ -180,7 +180,7 @@ static heom_status check_opts(const heom_solver_opts *o) {
     return fail(HEOM_ERR_ARG, "bad solve mode");
   if (o->mode == HEOM_SOLVE_SHIFTED && o->precond != HEOM_PREC_NONE)
     return fail(HEOM_ERR_ARG, "the multi-shift mode takes no preconditioner");
-  if (o->precond < HEOM_PREC_NONE || o->precond > HEOM_PREC_NN) return fail(HEOM_ERR_ARG, "bad preconditioner");
+  if (o->precond < HEOM_PREC_NONE || o->precond > HEOM_PREC_SCALED) return fail(HEOM_ERR_ARG, "bad preconditioner");
   return HEOM_OK;
 }
 

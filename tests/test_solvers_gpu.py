@@ -116,9 +116,14 @@ def _steady_check(cfg, mode, precond, tol_err, lu=True):
     return rep
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "none"])
+@pytest.mark.parametrize("precond", ["jacobi", "none", "scaled"])
 def test_steady_spin_boson(precond):
     _steady_check(wl.spin_boson(), "fp64", precond, 1e-10)
+
+
+@pytest.mark.parametrize("precond", ["none", "scaled"])
+def test_steady_siam_other_preconditioners(precond):
+    _steady_check(wl.siam(n_max=2), "fp64", precond, 1e-9)
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
