@@ -189,7 +189,7 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     return out
 
 
-def dos_benchmark(api, wl, cfg, restart=60, sample=64):
+def dos_benchmark(api, wl, cfg, restart=40, sample=64):
     """Density of states on the model's full frequency grid with the
     multi-shift solver (one Krylov space for all frequencies, FP64, 1e-8),
     beside the per-frequency path (multi-RHS Jacobi GMRES, 1e-8) on an

@@ -79,7 +79,7 @@ size_t shifted_bytes(const Hier &h, const heom_solver_opts &o) {
   const int m = o.restart;
   const int nprobe = 3;
   int64_t nch = std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
-  return (size_t)(m + 1) * vec + (size_t)(nprobe + 2) * vec + (size_t)(m + 3) * nch * sizeof(double2) +
+  return (size_t)(m + 1) * vec + (size_t)(nprobe + 2) * vec + (size_t)(2 * m + 3) * nch * sizeof(double2) +
          4 * (size_t)(m + 3) * sizeof(double2) + 2 * (size_t)h.d * h.d * 16 + 16 * 1024;
 }
 
@@ -101,7 +101,7 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
   std::vector<double2 *> xp(nprobe);
   for (int p = 0; p < nprobe; ++p) xp[p] = (double2 *)ws.take(vec);
   const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
-  double2 *partial = (double2 *)ws.take((size_t)(m + 3) * nch * sizeof(double2));
+  double2 *partial = (double2 *)ws.take((size_t)(2 * m + 3) * nch * sizeof(double2));
   double2 *hdev = (double2 *)ws.take(2 * (size_t)(m + 3) * sizeof(double2));
   double2 *sdev = (double2 *)ws.take(2 * sizeof(double2));
   if (!V || !b || !r || !partial || !hdev || !sdev) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
@@ -149,12 +149,12 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
   std::vector<char> active(K, 1);
   std::vector<int> probe_k(nprobe);
   for (int p = 0; p < nprobe; ++p) probe_k[p] = nprobe == 1 ? 0 : (int)((int64_t)p * (K - 1) / (nprobe - 1));
-  std::vector<cd> H((size_t)(m + 1) * m), t(m + 1);
+  std::vector<cd> H((size_t)(m + 1) * m), t(m + 1), G((size_t)(m + 1) * (m + 1));
   int iters = 0, cycles = 0;
   int64_t applies = 0;
   double worst_est = 1.0;
   while (true) {
-    // Arnoldi on M (no shift) with selective reorthogonalisation
+    // Arnoldi on M (no shift)
     std::fill(H.begin(), H.end(), cd(0));
     int kk = 0;
     bool breakdown = false;
@@ -167,34 +167,44 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
       HEOM_TRY(launch_apply(h, HEOM_FP64, a, s));
       ++applies;
       ++iters;
-      std::vector<double2> h1(j + 2), h2(j + 2, make_double2(0, 0));
-      HEOM_TRY(mdot<double>(V, n, j + 2, vn, n, 1, partial, nch, hdev, s));
-      HEOM_HIP_CHECK(hipMemcpyAsync(ph, hdev, sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, s));
+      // Gram-matrix CGS2: one two-vector pass gives a = V^H w, the Gram
+      // column V^H v_j and |w|^2; h = a + (a - G a); one fused update +
+      // normalisation pass (explicit norm when the formula cancels)
+      HEOM_TRY(mdot2<double>(V, n, j + 1, vn, vj, n, partial, nch, hdev, s));
+      HEOM_HIP_CHECK(hipMemcpyAsync(ph, hdev, sizeof(double2) * (2 * j + 3), hipMemcpyDeviceToHost, s));
       HEOM_HIP_CHECK(hipStreamSynchronize(s));
-      std::memcpy(h1.data(), ph, sizeof(double2) * (j + 2));
-      double p1 = 0;
-      for (int i = 0; i <= j; ++i) p1 += h1[i].x * h1[i].x + h1[i].y * h1[i].y;
-      const double ww = h1[j + 1].x;
-      double hn2 = ww - p1;
-      if (!std::isfinite(ww)) return fail(HEOM_ERR_NAN, "spectrum: non-finite Arnoldi vector");
-      const double2 *hproj = hdev;
-      if (!(hn2 > 0.5 * ww)) {
-        HEOM_TRY(basis_update<double>(V, n, j + 1, hdev, vn, n, 1, -1.0, s));
-        HEOM_TRY(mdot<double>(V, n, j + 2, vn, n, 1, partial, nch, hdev + (m + 3), s));
-        HEOM_HIP_CHECK(hipMemcpyAsync(ph, hdev + (m + 3), sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, s));
-        HEOM_HIP_CHECK(hipStreamSynchronize(s));
-        std::memcpy(h2.data(), ph, sizeof(double2) * (j + 2));
-        double p2 = 0;
-        for (int i = 0; i <= j; ++i) p2 += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
-        hn2 = h2[j + 1].x - p2;
-        hproj = hdev + (m + 3);
-        if (!(hn2 > 1e-2 * h2[j + 1].x)) {
-          HEOM_TRY(basis_update<double>(V, n, j + 1, hproj, vn, n, 1, -1.0, s));
-          HEOM_TRY(norm2(vn, hn2));
-          hproj = nullptr;
-        }
+      std::vector<cd> av(j + 1), hv(j + 1);
+      for (int i = 0; i <= j; ++i) {
+        av[i] = cd(ph[i].x, ph[i].y);
+        const cd c(ph[j + 1 + i].x, ph[j + 1 + i].y);
+        G[(size_t)j * (m + 1) + i] = c;
+        G[(size_t)i * (m + 1) + j] = std::conj(c);
       }
-      for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = cd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+      const double ww = ph[2 * j + 2].x;
+      if (!std::isfinite(ww)) return fail(HEOM_ERR_NAN, "spectrum: non-finite Arnoldi vector");
+      for (int i = 0; i <= j; ++i) {
+        cd ga(0);
+        for (int q = 0; q <= j; ++q) ga += G[(size_t)q * (m + 1) + i] * av[q];
+        hv[i] = 2.0 * av[i] - ga;
+      }
+      double hn2 = ww;
+      for (int i = 0; i <= j; ++i) hn2 -= 2.0 * (std::conj(hv[i]) * av[i]).real();
+      for (int i = 0; i <= j; ++i) {
+        cd gh(0);
+        for (int q = 0; q <= j; ++q) gh += G[(size_t)q * (m + 1) + i] * hv[q];
+        hn2 += (std::conj(hv[i]) * gh).real();
+      }
+      std::vector<double2> hup(j + 1);
+      for (int i = 0; i <= j; ++i) {
+        hup[i] = make_double2(hv[i].real(), hv[i].imag());
+        H[(size_t)j * (m + 1) + i] = hv[i];
+      }
+      HEOM_HIP_CHECK(hipMemcpyAsync(hdev, hup.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
+      const bool fused = std::isfinite(hn2) && hn2 > 1e-6 * ww;
+      if (!fused) {
+        HEOM_TRY(basis_update<double>(V, n, j + 1, hdev, vn, n, 1, -1.0, s));
+        HEOM_TRY(norm2(vn, hn2));
+      }
       double hn = std::sqrt(std::max(hn2, 0.0));
       double hscale = 0;
       for (int i = 0; i <= j; ++i) hscale = std::max(hscale, std::abs(H[(size_t)j * (m + 1) + i]));
@@ -205,7 +215,7 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
       H[(size_t)j * (m + 1) + j + 1] = hn;
       sc = make_double2(hn > 0 ? 1.0 / hn : 0.0, 0.0);
       HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &sc, sizeof(double2), hipMemcpyHostToDevice, s));
-      if (hproj) HEOM_TRY(basis_update<double>(V, n, j + 1, hproj, vn, n, 1, -1.0, s, sdev));
+      if (fused) HEOM_TRY(basis_update<double>(V, n, j + 1, hdev, vn, n, 1, -1.0, s, sdev));
       else HEOM_TRY(scale_vec<double>(vn, sdev, vn, n, 1, s));
       HEOM_HIP_CHECK(hipStreamSynchronize(s));
       kk = j + 1;
