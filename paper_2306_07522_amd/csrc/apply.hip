@@ -21,82 +21,11 @@
 //   cell kernel   (any d <= 32, any number of right-hand sides): one thread
 //                 per (i, j, r) cell, gathers straight from global memory.
 // Layout: x, y are [N][d][d][R] complex, R innermost.
-#include "device_common.h"
-#include "internal.h"
+#include "apply_wave.h"
 
 namespace heom {
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T>
-struct ApplyParams {
-  using T2 = typename Cplx<T>::t;
-  const int4 *tasks;
-  int64_t n_tasks;
-  const int4 *groups;
-  const int2 *gedges;
-  const T2 *decay;
-  const int32_t *ell_cnt;
-  const int32_t *ell_col;
-  const T2 *ell_val;
-  const int32_t *op_slots;  // per operator: padded ELL width (entries beyond a row's count are zero)
-  int slots;
-  // compact operator tables (wave kernel)
-  const int32_t *c_meta;
-  const int32_t *c_col;
-  const T2 *c_val;
-  int n_centries;
-  const T2 *hdiag;
-  int tpw;  // tasks per wave
-  int xchunk;  // XCD remap super-chunk in blocks (multiple of 8; 0 = off)
-  const int32_t *coef_op;
-  const T2 *coef;
-  const T2 *x;
-  const T2 *kvec;
-  T kc;
-  T2 *y;
-  int d;
-  int R;
-  const T2 *shifts;
-  T2 shift0;
-  int border;
-};
-
 // ----------------------------------------------------------------- wave kernel
-template <int D>
-struct WaveShape {
-  static constexpr int DD = D * D;
-  static constexpr int EPL = (DD + 63) / 64;   // elements per lane
-  static constexpr bool FULL = DD % 64 == 0;   // no masked tail
-  static constexpr bool UJ = 64 % D == 0;      // column index the same for all of a lane's elements
-  static __device__ __forceinline__ bool on(int lane, int s) { return FULL || lane + 64 * s < DD; }
-  static __device__ __forceinline__ int col(int lane, int s) { return UJ ? lane % D : (lane + 64 * s) % D; }
-};
-
-template <typename T, int D, bool FUSE>
-__device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, int lane,
-                                           typename Cplx<T>::t (&v)[WaveShape<D>::EPL]) {
-  using W = WaveShape<D>;
-  constexpr int DD = D * D;
-  const typename Cplx<T>::t *xb = P.x + b * DD;
-#pragma unroll
-  for (int s = 0; s < W::EPL; ++s) v[s] = W::on(lane, s) ? xb[lane + 64 * s] : typename Cplx<T>::t{0, 0};
-  if (FUSE) {
-    const typename Cplx<T>::t *kb = P.kvec + b * DD;
-#pragma unroll
-    for (int s = 0; s < W::EPL; ++s) {
-      if (!W::on(lane, s)) continue;
-      const typename Cplx<T>::t q = kb[lane + 64 * s];
-      v[s].x = fma(P.kc, q.x, v[s].x);
-      v[s].y = fma(P.kc, q.y, v[s].y);
-    }
-  }
-}
-
 // One wave processes tasks first, first + 4, ... (tpw of them).  Blocks are
 // remapped inside super-chunks of xchunk blocks so that each XCD (block b
 // runs on XCD b % 8) walks a contiguous run of tasks, which share parents.  Within a
@@ -106,9 +35,7 @@ template <typename T, int D, bool FUSE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WaveShape<D>::EPL > 4 ? 2 : 4)))
 apply_wave_kernel(ApplyParams<T> P) {
   using T2 = typename Cplx<T>::t;
-  using W = WaveShape<D>;
   constexpr int DD = D * D;
-  constexpr int EPL = W::EPL;
   extern __shared__ __align__(16) unsigned char smem[];
   T2 *sbuf = reinterpret_cast<T2 *>(smem);              // [4][DD] group staging, one slice per wave
   T2 *tval = sbuf + 4 * DD;                             // compact operator values
@@ -136,119 +63,7 @@ apply_wave_kernel(ApplyParams<T> P) {
   for (int it = 0; it < P.tpw; ++it) {
     const int64_t task = first + 4 * it;
     if (task >= P.n_tasks) break;
-    const int4 tk = P.tasks[task];
-    const int64_t a = tk.x;
-    const int flags = tk.w;
-    const int64_t abase = a * DD;
-    T2 acc[EPL];
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) acc[s] = (flags & TASK_ACC) && W::on(lane, s) ? P.y[abase + lane + 64 * s] : T2{0, 0};
-    T2 trace{0, 0};
-    int g = tk.y;
-    if (g < tk.z) {
-      int4 gr = P.groups[g];
-      T2 vnext[EPL];
-      load_block<T, D, FUSE>(P, P.gedges[gr.x].x, lane, vnext);
-      for (; g < tk.z; ++g) {
-        T2 u[EPL];
-        {
-          const T w0 = (T)P.gedges[gr.x].y;
-#pragma unroll
-          for (int s = 0; s < EPL; ++s) u[s] = T2{w0 * vnext[s].x, w0 * vnext[s].y};
-        }
-        int4 grn = gr;
-        if (g + 1 < tk.z) {  // prefetch the next group's first neighbour block
-          grn = P.groups[g + 1];
-          load_block<T, D, FUSE>(P, P.gedges[grn.x].x, lane, vnext);
-        }
-        int e = gr.x + 1;
-        for (; e + 1 < gr.y; e += 2) {
-          const int2 e0 = P.gedges[e], e1 = P.gedges[e + 1];
-          T2 v0[EPL], v1[EPL];
-          load_block<T, D, FUSE>(P, e0.x, lane, v0);
-          load_block<T, D, FUSE>(P, e1.x, lane, v1);
-          const T w0 = (T)e0.y, w1 = (T)e1.y;
-#pragma unroll
-          for (int s = 0; s < EPL; ++s) {
-            u[s].x = fma(w0, v0[s].x, fma(w1, v1[s].x, u[s].x));
-            u[s].y = fma(w0, v0[s].y, fma(w1, v1[s].y, u[s].y));
-          }
-        }
-        if (e < gr.y) {
-          const int2 e0 = P.gedges[e];
-          T2 v0[EPL];
-          load_block<T, D, FUSE>(P, e0.x, lane, v0);
-          const T w0 = (T)e0.y;
-#pragma unroll
-          for (int s = 0; s < EPL; ++s) {
-            u[s].x = fma(w0, v0[s].x, u[s].x);
-            u[s].y = fma(w0, v0[s].y, u[s].y);
-          }
-        }
-        if (gr.w) {
-          // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
-          const T2 z = P.shifts ? P.shifts[0] : P.shift0;
-          const T2 c = csub(P.decay[a], z);
-#pragma unroll
-          for (int s = 0; s < EPL; ++s) {
-            const T2 dh = csub(thd[(lane + 64 * s) / D], thd[W::col(lane, s)]);
-            const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
-            acc[s] = csub(acc[s], cmul(f, u[s]));
-          }
-        }
-        const int cid = gr.z;
-        const int op = P.coef_op[cid];
-        const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
-        const bool need_trace = gr.w && P.border && a == 0;
-        if (ns > 0 || need_trace) {
-#pragma unroll
-          for (int s = 0; s < EPL; ++s)
-            if (W::on(lane, s)) buf[lane + 64 * s] = u[s];
-          wave_sync();
-          if (need_trace && lane == 0)
-            for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
-          if (ns > 0) {
-            const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) {
-              if (!W::on(lane, s)) continue;
-              const int i = (lane + 64 * s) / D;
-              const int j = W::col(lane, s);
-              const int rbase = off + (D + j) * ns;
-              const int lbase = off + i * ns;
-              T2 L{0, 0}, Rv{0, 0};
-              if (isreal) {
-#pragma unroll 1
-                for (int t = 0; t < ns; ++t) {
-                  const T vl = tval[lbase + t].x, vr = tval[rbase + t].x;
-                  const T2 bl = buf[tcol[lbase + t] * D + j];
-                  const T2 br = buf[i * D + tcol[rbase + t]];
-                  L.x = fma(vl, bl.x, L.x); L.y = fma(vl, bl.y, L.y);
-                  Rv.x = fma(vr, br.x, Rv.x); Rv.y = fma(vr, br.y, Rv.y);
-                }
-              } else {
-#pragma unroll 1
-                for (int t = 0; t < ns; ++t) {
-                  L = cfma(tval[lbase + t], buf[tcol[lbase + t] * D + j], L);
-                  Rv = cfma(buf[i * D + tcol[rbase + t]], tval[rbase + t], Rv);
-                }
-              }
-              acc[s] = cfma(cl, L, acc[s]);
-              acc[s] = cfma(cr, Rv, acc[s]);
-            }
-          }
-          wave_sync();
-        }
-        gr = grn;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-      if (!W::on(lane, s)) continue;
-      T2 v = acc[s];
-      if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;
-      P.y[abase + lane + 64 * s] = v;
-    }
+    wave_task<T, D, FUSE>(P, task, lane, buf, tval, tcol, thd);
   }
 }
 

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "apply_wave.h"
 #include "blas.h"
 #include "device_common.h"
 #include "internal.h"
@@ -45,32 +46,30 @@ struct BInst {
   int64_t off;  // first element of the instance in the batch vector
   int slots;
   int d;
+  int wave;     // 1: d in {8, 16}, computed by the wave formulation (one wavefront per ADO)
 };
 
 // ----------------------------------------------------------------- apply
 // y = B x per instance (B = M, or the bordered stationary-state operator when
-// border is set: element (0,0) of ADO 0 becomes Tr rho_0).
+// border is set: element (0,0) of ADO 0 becomes Tr rho_0).  Tiles of
+// instances with d in {8, 16} hold four tasks, one per wavefront, computed by
+// the wave formulation with the instance's operator tables staged in LDS;
+// other tiles hold 256 / d^2 tasks, one thread per output element.
 template <typename T>
-__global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__restrict__ inst,
-                                                          const int4 *__restrict__ tiles, int n_tiles,
-                                                          const int *__restrict__ active,
-                                                          const typename Cplx<T>::t *__restrict__ x,
-                                                          typename Cplx<T>::t *__restrict__ y, int border) {
+__device__ __forceinline__ void batch_cell_tile(const BInst<T> &I, const int4 &tl, const typename Cplx<T>::t *x,
+                                                typename Cplx<T>::t *y, int border) {
   using T2 = typename Cplx<T>::t;
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const int4 tl = tiles[t];
-    if (active && !active[tl.x]) continue;
-    const BInst<T> &I = inst[tl.x];
-    const int d = I.d, cells = d * d;
-    const int lt = threadIdx.x / cells;
-    const int64_t task = (int64_t)tl.y + lt;
-    if ((lt + 1) * cells > 256 || task >= tl.z) continue;
-    const int cell = threadIdx.x - lt * cells;
-    const int i = cell / d, j = cell - (cell / d) * d;
+  const int d = I.d, cells = d * d;
+  const int tpb = cells <= 256 ? 256 / cells : 1;
+  const int lt = threadIdx.x / cells;
+  if (lt >= tpb) return;
+  const int cell = threadIdx.x - lt * cells;
+  const int i = cell / d, j = cell - (cell / d) * d;
+  const T2 *xs = x + I.off;
+  auto in = [&](int64_t b, int ii, int jj) -> T2 { return xs[(b * d + ii) * d + jj]; };
+  for (int64_t task = (int64_t)tl.y + lt; task < tl.z; task += tpb) {
     const int4 tk = I.tasks[task];
     const int64_t a = tk.x;
-    const T2 *xs = x + I.off;
-    auto in = [&](int64_t b, int ii, int jj) -> T2 { return xs[(b * d + ii) * d + jj]; };
     T2 acc{0, 0};
     for (int g = tk.y; g < tk.z; ++g) {
       const int4 gr = I.groups[g];
@@ -103,6 +102,51 @@ __global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__rest
   }
 }
 
+template <typename T, int D>
+__device__ __forceinline__ void batch_wave_tile(const ApplyParams<T> &Pi, const BInst<T> &I, const int4 &tl,
+                                                const typename Cplx<T>::t *x, typename Cplx<T>::t *y, int border,
+                                                unsigned char *smem) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int DD = D * D;
+  ApplyParams<T> P = Pi;
+  P.x = x + I.off;
+  P.y = y + I.off;
+  P.border = border;
+  T2 *sbuf = reinterpret_cast<T2 *>(smem);
+  T2 *tval = sbuf + 4 * DD;
+  int *tcol = reinterpret_cast<int *>(tval + P.n_centries);
+  T2 *thd = reinterpret_cast<T2 *>((reinterpret_cast<uintptr_t>(tcol + P.n_centries) + 15) & ~(uintptr_t)15);
+  __syncthreads();  // the previous tile is done with the tables
+  for (int e = threadIdx.x; e < P.n_centries; e += 256) {
+    tval[e] = P.c_val[e];
+    tcol[e] = P.c_col[e];
+  }
+  if (threadIdx.x < D) thd[threadIdx.x] = P.hdiag[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t task = (int64_t)tl.y + wave;
+  if (task < tl.z) wave_task<T, D, false>(P, task, lane, sbuf + wave * DD, tval, tcol, thd);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__restrict__ inst,
+                                                          const ApplyParams<T> *__restrict__ prm,
+                                                          const int4 *__restrict__ tiles, int n_tiles,
+                                                          const int *__restrict__ active,
+                                                          const typename Cplx<T>::t *__restrict__ x,
+                                                          typename Cplx<T>::t *__restrict__ y, int border) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    if (active && !active[tl.x]) continue;
+    const BInst<T> &I = inst[tl.x];
+    if (I.wave && I.d == 16) batch_wave_tile<T, 16>(prm[tl.x], I, tl, x, y, border, smem);
+    else if (I.wave && I.d == 8) batch_wave_tile<T, 8>(prm[tl.x], I, tl, x, y, border, smem);
+    else batch_cell_tile<T>(I, tl, x, y, border);
+  }
+}
+
 // z = D^{-1} r per instance, D the diagonal of B (zeros count as 1).
 template <typename T>
 __global__ void __launch_bounds__(256) batch_jacobi_kernel(const BInst<T> *__restrict__ inst,
@@ -116,20 +160,22 @@ __global__ void __launch_bounds__(256) batch_jacobi_kernel(const BInst<T> *__res
     if (active && !active[tl.x]) continue;
     const BInst<T> &I = inst[tl.x];
     const int d = I.d, cells = d * d;
+    const int tpb = cells <= 256 ? 256 / cells : 1;
     const int lt = threadIdx.x / cells;
-    const int64_t task = (int64_t)tl.y + lt;
-    if ((lt + 1) * cells > 256 || task >= tl.z) continue;
+    if (lt >= tpb) continue;
     const int cell = threadIdx.x - lt * cells;
     const int i = cell / d, j = cell - (cell / d) * d;
-    const int64_t a = I.tasks[task].x;
-    const double2 c = I.decay64[a], hi = I.hdiag64[i], hj = I.hdiag64[j];
-    double2 dg = make_double2(-c.x + (hi.y - hj.y), -c.y - (hi.x - hj.x));
-    if (border && a == 0 && cell == 0) dg = make_double2(1.0, 0.0);
-    if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
-    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
-    const int64_t idx = I.off + a * cells + cell;
-    const T2 v = r[idx];
-    z[idx] = T2{(T)(((double)v.x * dg.x + (double)v.y * dg.y) * inv), (T)(((double)v.y * dg.x - (double)v.x * dg.y) * inv)};
+    for (int64_t task = (int64_t)tl.y + lt; task < tl.z; task += tpb) {
+      const int64_t a = I.tasks[task].x;
+      const double2 c = I.decay64[a], hi = I.hdiag64[i], hj = I.hdiag64[j];
+      double2 dg = make_double2(-c.x + (hi.y - hj.y), -c.y - (hi.x - hj.x));
+      if (border && a == 0 && cell == 0) dg = make_double2(1.0, 0.0);
+      if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
+      const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
+      const int64_t idx = I.off + a * cells + cell;
+      const T2 v = r[idx];
+      z[idx] = T2{(T)(((double)v.x * dg.x + (double)v.y * dg.y) * inv), (T)(((double)v.y * dg.x - (double)v.x * dg.y) * inv)};
+    }
   }
 }
 
@@ -354,6 +400,9 @@ struct heom_batch {
   int device = -1;
   BInst<double> *inst64 = nullptr;
   BInst<float> *inst32 = nullptr;
+  ApplyParams<double> *prm64 = nullptr;  // wave-formulation tables per instance
+  ApplyParams<float> *prm32 = nullptr;
+  size_t smem64 = 0, smem32 = 0;         // LDS of the batched apply launch
   int4 *tiles = nullptr;
   int n_tiles = 0;
   std::vector<int4> tiles_inst;   // instance-major order
@@ -368,7 +417,7 @@ struct heom_batch {
   int *active = nullptr;          // [S]
   std::vector<int> seg_chunk_h;
   ~heom_batch() {
-    void *ptrs[] = {inst64, inst32, tiles, ch_e, ch_seg, seg_chunk, d_off, active};
+    void *ptrs[] = {inst64, inst32, prm64, prm32, tiles, ch_e, ch_seg, seg_chunk, d_off, active};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -386,9 +435,12 @@ template <typename T>
 static heom_status batch_apply_T(heom_batch &b, const void *x, void *y, int border, bool use_active, hipStream_t s) {
   const int grid = b.grid > 0 ? std::min(b.grid, b.n_tiles) : b.n_tiles;
   if (grid <= 0) return HEOM_OK;
-  const BInst<T> *I = std::is_same<T, double>::value ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
-  hipLaunchKernelGGL(batch_apply_kernel<T>, dim3(grid), dim3(256), 0, s, I, b.tiles, b.n_tiles,
-                     use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x, (typename Cplx<T>::t *)y, border);
+  constexpr bool dbl = std::is_same<T, double>::value;
+  const BInst<T> *I = dbl ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
+  const ApplyParams<T> *Pm = dbl ? (const ApplyParams<T> *)b.prm64 : (const ApplyParams<T> *)b.prm32;
+  hipLaunchKernelGGL(batch_apply_kernel<T>, dim3(grid), dim3(256), dbl ? b.smem64 : b.smem32, s, I, Pm, b.tiles,
+                     b.n_tiles, use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x, (typename Cplx<T>::t *)y,
+                     border);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -762,7 +814,10 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
   b->off.assign(n_inst + 1, 0);
   std::vector<BInst<double>> i64(n_inst);
   std::vector<BInst<float>> i32(n_inst);
+  std::vector<ApplyParams<double>> p64(n_inst);
+  std::vector<ApplyParams<float>> p32(n_inst);
   std::vector<double> cost(n_inst);
+  constexpr size_t kLdsMax = 64 * 1024;
   for (int s = 0; s < n_inst; ++s) {
     if (!inst[s]) return fail(HEOM_ERR_ARG, "batch_create: NULL instance");
     Hier &h = *inst[s]->impl;
@@ -783,13 +838,37 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
     f.off = b->off[s]; f.slots = h.ell.slots; f.d = h.d;
     i32[s] = f;
     cost[s] = (double)h.row_ptr.back() * h.d * h.d + (double)h.N * h.d * h.d;
+    // wave formulation for d in {8, 16}: its LDS (4 staging blocks, the
+    // compact operator tables and the H diagonal) must fit
+    const size_t nce = h.ell.c_col.size();
+    const size_t lds64 = 4 * (size_t)h.d * h.d * 16 + nce * (16 + 4) + 16 + (size_t)h.d * 16;
+    const size_t lds32 = 4 * (size_t)h.d * h.d * 8 + nce * (8 + 4) + 16 + (size_t)h.d * 8;
+    const bool wave = (h.d == 8 || h.d == 16) && lds64 <= kLdsMax;
+    i64[s].wave = i32[s].wave = wave;
+    if (wave) {
+      b->smem64 = std::max(b->smem64, lds64);
+      b->smem32 = std::max(b->smem32, lds32);
+    }
+    ApplyParams<double> q{};
+    q.tasks = D.base.tasks; q.n_tasks = h.N; q.groups = D.base.groups; q.gedges = D.base.gedges;
+    q.decay = D.decay64; q.ell_cnt = D.ell_cnt; q.ell_col = D.ell_col; q.ell_val = D.ell_val64;
+    q.op_slots = D.op_slots; q.slots = h.ell.slots; q.c_meta = D.c_meta; q.c_col = D.c_col; q.c_val = D.c_val64;
+    q.n_centries = (int)nce; q.hdiag = D.hdiag; q.coef_op = D.coef_op; q.coef = D.coef64; q.d = h.d; q.R = 1;
+    p64[s] = q;
+    ApplyParams<float> r{};
+    r.tasks = D.base.tasks; r.n_tasks = h.N; r.groups = D.base.groups; r.gedges = D.base.gedges;
+    r.decay = D.decay32; r.ell_cnt = D.ell_cnt; r.ell_col = D.ell_col; r.ell_val = D.ell_val32;
+    r.op_slots = D.op_slots; r.slots = h.ell.slots; r.c_meta = D.c_meta; r.c_col = D.c_col; r.c_val = D.c_val32;
+    r.n_centries = (int)nce; r.hdiag = D.hdiag32; r.coef_op = D.coef_op; r.coef = D.coef32; r.d = h.d; r.R = 1;
+    p32[s] = r;
   }
   b->n = b->off[n_inst];
-  // tiles: 256 / d^2 consecutive tasks of one instance
+  // tiles: four tasks (one per wavefront) of a wave-formulation instance,
+  // else 256 / d^2 consecutive tasks of one instance
   std::vector<std::vector<int4>> per(n_inst);
   for (int s = 0; s < n_inst; ++s) {
     const Hier &h = *inst[s]->impl;
-    const int tpb = std::max(1, 256 / (h.d * h.d));
+    const int tpb = i64[s].wave ? 4 : std::max(1, 256 / (h.d * h.d));
     for (int64_t t = 0; t < h.N; t += tpb)
       per[s].push_back(make_int4(s, (int)t, (int)std::min<int64_t>(h.N, t + tpb), 0));
   }
@@ -828,6 +907,10 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
   b->n_chunks = (int)chs.size();
   HEOM_HIP_CHECK(hipMalloc(&b->inst64, sizeof(BInst<double>) * n_inst));
   HEOM_HIP_CHECK(hipMalloc(&b->inst32, sizeof(BInst<float>) * n_inst));
+  HEOM_HIP_CHECK(hipMalloc(&b->prm64, sizeof(ApplyParams<double>) * n_inst));
+  HEOM_HIP_CHECK(hipMalloc(&b->prm32, sizeof(ApplyParams<float>) * n_inst));
+  HEOM_HIP_CHECK(hipMemcpy(b->prm64, p64.data(), sizeof(ApplyParams<double>) * n_inst, hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b->prm32, p32.data(), sizeof(ApplyParams<float>) * n_inst, hipMemcpyHostToDevice));
   HEOM_HIP_CHECK(hipMalloc(&b->tiles, sizeof(int4) * std::max(1, b->n_tiles)));
   HEOM_HIP_CHECK(hipMalloc(&b->ch_e, sizeof(int64_t) * che.size()));
   HEOM_HIP_CHECK(hipMalloc(&b->ch_seg, sizeof(int) * std::max<size_t>(1, chs.size())));
