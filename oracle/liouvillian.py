@@ -32,7 +32,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .hierarchy import OracleHierarchy
+from .hierarchy import OracleHierarchy, ferm_importance_rank, importance_value
 
 
 # ---------------------------------------------------------------------------
@@ -93,18 +93,28 @@ def _pf(parity: int) -> int:
 class OracleHEOM:
     """Sparse HEOMLS for given H, baths, truncation and parity."""
 
-    def __init__(self, H, baths, m_max, n_max, parity=+1, ferm_perm=None):
+    def __init__(self, H, baths, m_max, n_max, parity=+1, ferm_perm=None, importance_threshold=0.0):
         """ferm_perm: optional relabelling of the fermionic exponents (new
         position i holds old exponent ferm_perm[i]); used to check that
-        physical results do not depend on the exponent order."""
+        physical results do not depend on the exponent order.
+        importance_threshold > 0: leave out the ADOs of eq:importance below
+        it (levels m > 1 or n > 1); terms that reach a left-out ADO are
+        dropped like those beyond the tier cutoff."""
         self.H = np.asarray(H, dtype=np.complex128)
         self.d = self.H.shape[0]
         self.bos, self.ferm = flatten_baths(baths)
+        self.ferm_rank = ferm_importance_rank([len(r["eta_p"]) for r in baths if r["kind"] != "boson"])
         if ferm_perm is not None:
             inv = {old: new for new, old in enumerate(ferm_perm)}
             self.ferm = [dict(self.ferm[old], partner=inv[self.ferm[old]["partner"]]) for old in ferm_perm]
         self.parity = parity
-        self.hier = OracleHierarchy(len(self.bos), m_max, len(self.ferm), n_max)
+        imp = None
+        if importance_threshold > 0:
+            if ferm_perm is not None:
+                raise ValueError("importance pruning with a relabelled exponent list is not defined")
+            imp = lambda j, q: importance_value(j, q, self.bos, self.ferm, self.ferm_rank)
+        self.hier = OracleHierarchy(len(self.bos), m_max, len(self.ferm), n_max, importance=imp,
+                                    threshold=importance_threshold)
         self.N = len(self.hier)
         self._cache = {}
 
@@ -194,6 +204,8 @@ class OracleHEOM:
             qw = q[pos]
             rest = q[:pos] + q[pos + 1:]
             b, sgn = hier.lookup(j, rest)
+            if b is None:            # left out by the importance threshold
+                continue
             assert sgn == 1
             for c, S in self._terms_C(qw, n - 1):
                 out.append((b, -1j * (-1) ** (n - w) * c, S))
@@ -202,6 +214,8 @@ class OracleHEOM:
             jr = j[r]
             rest = j[:r] + j[r + 1:]
             b, _ = hier.lookup(rest, q)
+            if b is None:            # left out by the importance threshold
+                continue
             for c, S in self._terms_D(jr):
                 out.append((b, -1j * c, S))
         return out

@@ -219,3 +219,51 @@ def test_psd_sum_rule_cavity_small():
     S = osv.psd(M, x, a, om, me.N, me.d)
     n_ss = np.trace(a.conj().T @ a @ r0).real
     assert abs(np.trapezoid(S, om) - n_ss) < 3e-4 * n_ss
+
+
+# --------------------------------------------------------------------------- importance pruning
+def _table3():
+    import json, pathlib
+    return json.loads((pathlib.Path(__file__).parent / "golden" / "table3_importance.json").read_text())
+
+
+def _example1_baths():
+    """Example 1's leads (Table 1): 2 leads x 2 spins, 7 exponential terms each."""
+    t = _table3()["model"]
+    d_up, d_dn = wl.jordan_wigner(2)
+    return [wl.lorentz_lead(op, t["Gamma"], t["W"], mu, t["T"], t["n_terms"]) for mu in (0.0, 0.0)
+            for op in (d_up, d_dn)]
+
+
+@pytest.mark.parametrize("n_max", [2, 3, 4])
+def test_importance_counts_table3(n_max):
+    """The oracle's importance pruning reproduces Table 3 exactly."""
+    from oracle.hierarchy import OracleHierarchy, ferm_importance_rank, importance_value
+    from oracle.liouvillian import flatten_baths
+    t = _table3()
+    baths = ox.exponent_records(_example1_baths())
+    bos, ferm = flatten_baths(baths)
+    rank = ferm_importance_rank([len(r["eta_p"]) for r in baths])
+    assert len(ferm) == 56
+    full = OracleHierarchy(0, 0, 56, n_max)
+    vals = {key: importance_value(key[0], key[1], bos, ferm, rank) for key in full.ados}
+    for th, want in zip(t["thresholds"], t["counts"][str(n_max)]):
+        got = sum(1 for (j, q), v in vals.items() if len(q) <= 1 or v >= th) if th > 0 else len(full.ados)
+        assert got == want, (n_max, th, got, want)
+
+
+def test_pruned_hierarchy_drops_terms_of_missing_ados():
+    """A pruned HEOMLS is the full one restricted to the kept ADOs (rows and
+    columns): no term reaches a left-out ADO and every kept term survives."""
+    cfg = wl.siam(n_max=2, n_exp=3)
+    b = ox.exponent_records(cfg["baths"])
+    full = OracleHEOM(cfg["H"], b, 0, 2)
+    prn = OracleHEOM(cfg["H"], b, 0, 2, importance_threshold=1e-2)
+    assert 0 < prn.N < full.N
+    keep = np.array([full.hier.index[key] for key in prn.hier.ados])
+    d2 = full.d * full.d
+    idx = (keep[:, None] * d2 + np.arange(d2)[None, :]).reshape(-1)
+    Mf, Mp = full.assemble(), prn.assemble()
+    # both are column-stacked per ADO block: block a occupies [a d^2, (a+1) d^2)
+    sub = Mf[idx][:, idx]
+    assert abs(sub - Mp).max() < 1e-15
