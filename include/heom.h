@@ -133,6 +133,20 @@ typedef struct {
 heom_status heom_build_hierarchy(int32_t d, const double *H, int32_t n_baths, const heom_bath *baths,
                                  int32_t m_max, int32_t n_max, int32_t parity,
                                  const double *parity_op, heom_hier **out);
+/* As heom_build_hierarchy, leaving out the ADOs of low importance (the
+ * truncation paragraph after eq:HEOM, eq:importance): an ADO with bosonic
+ * level m > 1 or fermionic level n > 1 is dropped when
+ *   |prod_r xi_{j_r} / (Re chi_{j_r} sum_{x<=r} Re chi_{j_x})| *
+ *   |prod_w eta_{q_w} / (Re gamma_{q_w} sum_{x<=w} Re gamma_{q_x})|
+ * is below importance_threshold (>= 0; 0 keeps every ADO).  The products
+ * run over the ADO's exponents in list order: bosonic exponents in bath
+ * order, fermionic ones per bath with the nu = +1 terms h = 1.. first and
+ * then the nu = -1 terms (the order that reproduces the counts of Table 3).
+ * Terms of eq:HEOM that would reach a dropped ADO are left out, as for ADOs
+ * beyond the tier cutoff. */
+heom_status heom_build_hierarchy_pruned(int32_t d, const double *H, int32_t n_baths, const heom_bath *baths,
+                                        int32_t m_max, int32_t n_max, int32_t parity, const double *parity_op,
+                                        double importance_threshold, heom_hier **out);
 void heom_free(heom_hier *h);
 heom_status heom_hierarchy_info(const heom_hier *h, heom_info *out);
 

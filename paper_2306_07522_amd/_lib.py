@@ -58,6 +58,8 @@ SIGNATURES = {
     "heom_exponents_drude_lorentz": (heom_status, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, dp, dp]),
     "heom_build_hierarchy": (heom_status, [C.c_int32, dp, C.c_int32, C.POINTER(heom_bath), C.c_int32, C.c_int32,
                                            C.c_int32, dp, C.POINTER(vp)]),
+    "heom_build_hierarchy_pruned": (heom_status, [C.c_int32, dp, C.c_int32, C.POINTER(heom_bath), C.c_int32,
+                                                  C.c_int32, C.c_int32, dp, C.c_double, C.POINTER(vp)]),
     "heom_free": (None, [vp]),
     "heom_hierarchy_info": (heom_status, [vp, C.POINTER(heom_info)]),
     "heom_hierarchy_ados": (heom_status, [vp, i32p, u64p, i32p]),

@@ -120,7 +120,7 @@ def _devptr(t):
 class Hierarchy:
     """Handle of heom_build_hierarchy: ADO list, neighbour tables, operators."""
 
-    def __init__(self, H, baths, m_max, n_max, parity=+1, parity_op=None):
+    def __init__(self, H, baths, m_max, n_max, parity=+1, parity_op=None, importance_threshold=0.0):
         lb = lib()
         H = _c128(H)
         d = H.shape[0]
@@ -132,8 +132,13 @@ class Hierarchy:
         if parity_op is not None:
             pop = _c128(parity_op)
         h = C.c_void_p()
-        L.check(lb.heom_build_hierarchy(d, _dptr(H), len(baths), structs, m_max, n_max, parity,
-                                        _dptr(pop) if pop is not None else None, C.byref(h)))
+        if importance_threshold > 0:
+            L.check(lb.heom_build_hierarchy_pruned(d, _dptr(H), len(baths), structs, m_max, n_max, parity,
+                                                   _dptr(pop) if pop is not None else None,
+                                                   float(importance_threshold), C.byref(h)))
+        else:
+            L.check(lb.heom_build_hierarchy(d, _dptr(H), len(baths), structs, m_max, n_max, parity,
+                                            _dptr(pop) if pop is not None else None, C.byref(h)))
         self._h = h
         self._lib = lb
         info = L.heom_info()

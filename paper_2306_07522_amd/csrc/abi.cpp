@@ -46,7 +46,26 @@ heom_status heom_build_hierarchy(int32_t d, const double *H, int32_t n_baths, co
   *out = nullptr;
   try {
     std::unique_ptr<Hier> h;
-    HEOM_TRY(build_hier(d, H, n_baths, baths, m_max, n_max, parity, parity_op, h));
+    HEOM_TRY(build_hier(d, H, n_baths, baths, m_max, n_max, parity, parity_op, 0.0, h));
+    auto *w = new heom_hier;
+    w->impl = std::move(h);
+    *out = w;
+    return HEOM_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(HEOM_ERR_ALLOC, "host allocation failed while building the hierarchy");
+  } catch (const std::exception &e) {
+    return fail(HEOM_ERR_ARG, e.what());
+  }
+}
+
+heom_status heom_build_hierarchy_pruned(int32_t d, const double *H, int32_t n_baths, const heom_bath *baths,
+                                        int32_t m_max, int32_t n_max, int32_t parity, const double *parity_op,
+                                        double importance_threshold, heom_hier **out) {
+  if (!out) return fail(HEOM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  try {
+    std::unique_ptr<Hier> h;
+    HEOM_TRY(build_hier(d, H, n_baths, baths, m_max, n_max, parity, parity_op, importance_threshold, h));
     auto *w = new heom_hier;
     w->impl = std::move(h);
     *out = w;

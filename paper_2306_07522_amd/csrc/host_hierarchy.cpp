@@ -243,7 +243,8 @@ static bool next_multiset(std::vector<int> &c, int K) {
 }
 
 heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *baths, int m_max, int n_max,
-                       int parity, const double *parity_op, std::unique_ptr<Hier> &out) {
+                       int parity, const double *parity_op, double importance_threshold, std::unique_ptr<Hier> &out) {
+  if (!(importance_threshold >= 0.0)) return fail(HEOM_ERR_ARG, "importance threshold must be >= 0");
   if (d < 1 || d > 64) return fail(HEOM_ERR_ARG, "d must be in [1, 64]");
   if (!Hp) return fail(HEOM_ERR_ARG, "H is NULL");
   if (parity != 1 && parity != -1) return fail(HEOM_ERR_ARG, "parity must be +1 or -1");
@@ -295,9 +296,9 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
       int base = (int)h->fexp.size();
       for (int k = 0; k < b.n_exp; ++k) {
         h->fexp.push_back({op_ann, +1, base + 2 * k + 1, cd(b.eta_p[2 * k], b.eta_p[2 * k + 1]),
-                           cd(b.gam_p[2 * k], b.gam_p[2 * k + 1])});
+                           cd(b.gam_p[2 * k], b.gam_p[2 * k + 1]), base + k});
         h->fexp.push_back({op_ann, -1, base + 2 * k, cd(b.eta_m[2 * k], b.eta_m[2 * k + 1]),
-                           cd(b.gam_m[2 * k], b.gam_m[2 * k + 1])});
+                           cd(b.gam_m[2 * k], b.gam_m[2 * k + 1]), base + b.n_exp + k});
       }
     } else {
       return fail(HEOM_ERR_ARG, "bath kind must be HEOM_BOSON or HEOM_FERMION");
@@ -320,7 +321,30 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
 
   // ---- enumerate: tier t = m + n ascending; n ascending; fermionic subsets
   // lexicographic (ascending index tuples); bosonic multisets lexicographic.
+  // With an importance threshold, ADOs beyond levels (m, n) <= (1, 1) whose
+  // eq:importance value is below it are not enumerated.
   const int Kb = h->Kb, Kf = h->Kf;
+  h->importance_threshold = importance_threshold;
+  std::vector<int> by_rank(Kf);
+  for (int k = 0; k < Kf; ++k) by_rank[h->fexp[k].rank] = k;
+  auto important = [&](const std::vector<int> &bc, uint64_t mask, int m, int n) -> bool {
+    if (importance_threshold <= 0.0 || (m <= 1 && n <= 1)) return true;
+    double v = 1.0, sum = 0.0;
+    for (int x : bc) {  // multiset in ascending exponent order
+      const double rc = h->bexp[x].chi.real();
+      sum += rc;
+      v *= std::abs(h->bexp[x].xi) / rc / sum;
+    }
+    sum = 0.0;
+    for (int r = 0; r < Kf; ++r) {  // fermionic exponents in importance order
+      const int k = by_rank[r];
+      if (!(mask >> k & 1ull)) continue;
+      const double rg = h->fexp[k].gamma.real();
+      sum += rg;
+      v *= std::abs(h->fexp[k].eta) / rg / sum;
+    }
+    return !(v < importance_threshold);
+  };
   std::vector<std::pair<uint64_t, uint64_t>> keys;
   h->tier_off.clear();
   for (int t = 0; t <= h->Lb + h->Lf; ++t) {
@@ -338,7 +362,7 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
         while (bmore) {
           uint64_t code = 0;
           for (int x : bc) code += h->bos_pow[x];
-          keys.push_back({mask, code});
+          if (important(bc, mask, m, n)) keys.push_back({mask, code});
           if ((int64_t)keys.size() >= (1ll << 31) - 1) return fail(HEOM_ERR_UNSUPPORTED, "more than 2^31 ADOs");
           bmore = (m > 0) && next_multiset(bc, Kb);
         }
@@ -452,6 +476,7 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
       if (!(mask >> k & 1ull)) continue;
       uint64_t bm = mask & ~(1ull << k);
       int64_t b = find(bm, code);
+      if (b < 0) continue;  // left out by the importance threshold
       int s = (__builtin_popcountll(k + 1 < 64 ? bm >> (k + 1) : 0ull) & 1) ? -1 : 1;
       push(b, cf_dn + 2 * k + ((n - 1) & 1), s);
     }
@@ -460,6 +485,7 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
       int occ = h->bocc[a * Kb + k];
       if (!occ) continue;
       int64_t b = find(mask, code - h->bos_pow[k]);
+      if (b < 0) continue;  // left out by the importance threshold
       push(b, cb_dn + k, occ);
     }
     if (!has_up) ++n_leaf;

@@ -97,9 +97,12 @@ struct DeviceTables {
 
 struct Hier {
   int d = 0, Kb = 0, Kf = 0, Lb = 0, Lf = 0, parity = 1;
+  double importance_threshold = 0.0;
   std::vector<cd> H;  // d*d row-major
   struct BosExp { int op, u; cd xi, chi; };
-  struct FermExp { int op_ann, nu, partner; cd eta, gamma; };
+  // rank: position in the order eq:importance runs over (per bath: nu = +1
+  // terms h = 1.., then nu = -1 terms)
+  struct FermExp { int op_ann, nu, partner; cd eta, gamma; int rank; };
   std::vector<BosExp> bexp;
   std::vector<FermExp> fexp;
   std::vector<std::vector<cd>> ops;  // ops[0] = H
@@ -126,7 +129,7 @@ struct Hier {
 
 // host builder (host_hierarchy.cpp)
 heom_status build_hier(int d, const double *H, int n_baths, const heom_bath *baths, int m_max, int n_max,
-                       int parity, const double *parity_op, std::unique_ptr<Hier> &out);
+                       int parity, const double *parity_op, double importance_threshold, std::unique_ptr<Hier> &out);
 int64_t lookup_ado(const Hier &h, uint64_t fmask, uint64_t bcode);
 
 // device upload / kernels (device.hip)

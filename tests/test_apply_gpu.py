@@ -199,3 +199,28 @@ def test_steady_operator_bordered(name):
     y32 = api.apply_steady_operator(lm, torch.from_numpy(xl.astype(np.complex64)).cuda()).cpu().numpy()[perm]
     yo32 = to_blocks(B @ from_blocks(xl.astype(np.complex64).astype(complex)[perm]), om.N, om.d)
     assert rel_err(y32.astype(complex), yo32) <= FP32_TOL
+
+
+# --------------------------------------------------------------------------- importance pruning
+@pytest.mark.parametrize("name,th,parity", [("siam", 3e-3, +1), ("siam", 3e-3, -1), ("cavity", 1e-3, +1),
+                                             ("two_orbital", 1e-3, +1)])
+def test_apply_pruned_hierarchy(name, th, parity):
+    """Pruned hierarchies (eq:importance): irregular ADO sets with missing
+    parents and children, against the oracle's pruned assembly."""
+    from oracle import exponents as ox
+    from oracle.liouvillian import OracleHEOM
+    from paper_2306_07522_amd import api
+    if name == "siam":
+        cfg = wl.siam(n_max=3, n_exp=3)
+    elif name == "cavity":
+        cfg = wl.charge_cavity(n_photon=3, n_bexp=3, n_fexp=2, m_max=3, n_max=2, lam=0.2, gamma=1.0, T=1.0,
+                               Gamma=0.5)
+    else:
+        cfg = wl.two_orbital_anderson(n_max=3)
+    om = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), cfg["m_max"], cfg["n_max"], parity=parity,
+                    importance_threshold=th)
+    lm = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=parity,
+                       parity_op=cfg.get("parity_op"), importance_threshold=th)
+    full = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=parity)
+    assert lm.N == om.N < full.N
+    _parity_check(cfg, parity=parity, seeds=(0, 1), om=om, lm=lm)

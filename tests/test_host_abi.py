@@ -131,3 +131,61 @@ def test_dictionary_lookup_and_sign():
         assert lm.index([], p) == (a, (-1) ** inv)
     assert lm.index([], [0, 0])[0] == -1               # Pauli
     assert lm.index([], [0, 1, 2, 3])[0] == -1         # beyond the tier
+
+
+# --------------------------------------------------------------------------- importance pruning (host build)
+def _table3():
+    import json, pathlib
+    return json.loads((pathlib.Path(__file__).parent / "golden" / "table3_importance.json").read_text())
+
+
+def _example1(n_max, th):
+    t = _table3()["model"]
+    d_up, d_dn = wl.jordan_wigner(2)
+    baths = [wl.lorentz_lead(op, t["Gamma"], t["W"], 0.0, t["T"], t["n_terms"]) for _ in range(2)
+             for op in (d_up, d_dn)]
+    H = -5.0 * (d_up.T @ d_up + d_dn.T @ d_dn) + 10.0 * (d_up.T @ d_up) @ (d_dn.T @ d_dn)
+    return _api().Hierarchy(H, baths, 0, n_max, importance_threshold=th)
+
+
+@pytest.mark.parametrize("n_max", [2, 3, 4])
+def test_library_importance_counts_table3(n_max):
+    t = _table3()
+    for th, want in zip(t["thresholds"], t["counts"][str(n_max)]):
+        if th == 0.0 and n_max == 4:
+            continue  # 396,607 ADOs: covered by the unpruned count tests
+        h = _example1(n_max, th)
+        assert h.N == want, (n_max, th, h.N, want)
+        h.close()
+
+
+@pytest.mark.parametrize("n_max", [5, 6])
+def test_library_importance_counts_table3_deep(n_max):
+    """Rows 5 and 6 at the thresholds whose hierarchies stay small (the
+    enumeration still visits all 4.2 M / 36.7 M candidate sets)."""
+    t = _table3()
+    for th, want in list(zip(t["thresholds"], t["counts"][str(n_max)]))[:4]:
+        h = _example1(n_max, th)
+        assert h.N == want, (n_max, th, h.N, want)
+        h.close()
+
+
+def test_library_pruned_ados_match_oracle():
+    from oracle.liouvillian import OracleHEOM
+    cfg = wl.siam(n_max=3, n_exp=3)
+    om = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), 0, 3, importance_threshold=3e-3)
+    api = _api()
+    lm = api.Hierarchy(cfg["H"], cfg["baths"], 0, 3, importance_threshold=3e-3)
+    full = api.Hierarchy(cfg["H"], cfg["baths"], 0, 3)
+    assert 0 < lm.N == om.N < full.N
+    # same ADO sets: map the oracle's sets (oracle numbering) to the library's masks
+    occ, mask, _ = lm.ados()
+    lib_sets = {int(m) for m in mask}
+    # both sides number the fermionic exponents alike (per bath: h-major, nu = +1 then -1)
+    ora_sets = set()
+    for _, q in om.hier.ados:
+        m = 0
+        for k in q:
+            m |= 1 << k
+        ora_sets.add(m)
+    assert lib_sets == ora_sets
