@@ -186,3 +186,20 @@ def test_psd_cavity_vs_oracle(mode):
     xs = osv.steady_state(oe.assemble(), oe.d)
     So = osv.psd(oe.assemble(), xs, cfg["aop"], om, oe.N, oe.d)
     assert np.abs(S - So).max() <= 1e-9 * np.abs(So).max(), (S, So)
+
+
+def test_steady_pruned_hierarchy_vs_oracle():
+    """Stationary state of an importance-pruned hierarchy (eq:importance)
+    against the oracle's direct solve of the pruned HEOMLS."""
+    torch, api = _torch(), _api()
+    from oracle import exponents as ox
+    from oracle.liouvillian import OracleHEOM
+    cfg = wl.siam(n_max=3, n_exp=3)
+    th = 3e-3
+    om = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), 0, 3, importance_threshold=th)
+    lm = api.Hierarchy(cfg["H"], cfg["baths"], 0, 3, parity_op=cfg["parity_op"], importance_threshold=th)
+    perm = oracle_to_library_perm(om, lm)
+    x, rep = api.steady_state(lm, tol=1e-12, restart=40, max_iter=4000)
+    assert rep["status"] == 0, rep
+    xs = to_blocks(osv.steady_state(om.assemble(), om.d), om.N, om.d)
+    assert rel_err(x.cpu().numpy()[perm], xs) <= 1e-9
