@@ -111,6 +111,15 @@ class HeomError(RuntimeError):
         self.status = status
 
 
+def _hip_runtimes():
+    """Paths of the libamdhip64 copies mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 def load():
     """Load libheom.so (built in-tree by build_lib.py); raise if it is missing."""
     global _lib
@@ -118,7 +127,16 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2306_07522_amd/build_lib.py")
+    # The binding hands the library torch's device pointers and streams, which
+    # are only valid inside the HIP runtime that torch loaded.  Importing torch
+    # first makes the dynamic linker resolve libheom's libamdhip64.so.7 to that
+    # same copy; loading libheom first would map a second runtime.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are mapped in this process (" + ", ".join(runtimes) +
+                          "): libheom must share the one that owns torch's tensors and streams")
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name, None)
         if fn is None:

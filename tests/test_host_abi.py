@@ -32,6 +32,24 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_library_shares_torchs_hip_runtime():
+    """Loading libheom before anything imports torch must still leave a single
+    HIP runtime in the process (torch's), since torch's pointers and streams
+    are passed straight through the ABI."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2306_07522_amd import _lib\n"
+            "_lib.load()\n"
+            "import torch, os\n"
+            "print(_lib._hip_runtimes()); print(os.path.dirname(torch.__file__))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    runtimes, torch_dir = out.stdout.strip().splitlines()[-2:]
+    runtimes = __import__("ast").literal_eval(runtimes)
+    assert len(runtimes) == 1 and runtimes[0].startswith(torch_dir), runtimes
+
+
 @pytest.mark.parametrize("kind", ["fermi", "bose"])
 @pytest.mark.parametrize("n", [1, 2, 4, 6, 10])
 def test_pade_params_match_oracle(kind, n):
