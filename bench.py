@@ -41,14 +41,18 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "5868819a02f9e1e1", "bytes": 6_753_545_387},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "b5b3a7e19b077d1d", "bytes": 6_754_132_674},
 }
 
 
 def _apply_source_sha():
+    """Hash of the apply kernels' sources (the launch code and the per-wave task)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2306_07522_amd", "csrc", "apply.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("apply.hip", "apply_wave.h"):
+        with open(os.path.join(ROOT, "paper_2306_07522_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
