@@ -231,7 +231,15 @@ enum { HEOM_OP_PROPAGATE = 0, HEOM_OP_STEADY = 1, HEOM_OP_SPECTRUM = 2 };
  * modulus of the diagonal, a positive scaling that leaves the orientation of
  * the operator's left-half-plane spectrum alone (Jacobi's complex phases
  * rotate parts of it around the origin, which can slow restarted GMRES). */
-enum { HEOM_PREC_NONE = 0, HEOM_PREC_JACOBI = 1, HEOM_PREC_NN = 2, HEOM_PREC_SCALED = 3 };
+/* HEOM_PREC_BLOCK: per ADO, the exact inverse of the ADO's own terms of
+ * eq:HEOM, -(c_a - z) X - i[H, X], applied in the eigenbasis of H
+ * (H = U diag(E) U^H, so X -> U ((U^H X U) / D) U^H with
+ * D_ij = -(c_a - z) - i(E_i - E_j)).  Entries with |D_ij| below the slowest
+ * bath decay rate (min Re chi, Re gamma) are divided by minus that rate
+ * instead.  It keeps the whole coherent part of each ADO's dynamics, where
+ * Jacobi keeps only the diagonal of H; with weak baths this is the part that
+ * stalls restarted GMRES.  Requires d <= 32 (HEOM_ERR_UNSUPPORTED otherwise). */
+enum { HEOM_PREC_NONE = 0, HEOM_PREC_JACOBI = 1, HEOM_PREC_NN = 2, HEOM_PREC_SCALED = 3, HEOM_PREC_BLOCK = 4 };
 /* HEOM_SOLVE_SHIFTED (heom_spectrum only, precond HEOM_PREC_NONE): all
  * frequencies share one Krylov space of the unshifted operator (restarted
  * full orthogonalisation, whose residuals stay parallel across shifts);
@@ -259,6 +267,14 @@ typedef struct {
                              its residual is <= 0.1, else from zero; the
                              report sums both attempts                     */
   int32_t use_x0;         /* 1: x_dev holds the initial guess                 */
+  int32_t deflate;        /* heom_steady only: 0 = plain restarts; k > 0 =
+                             deflated restarting (GMRES-DR, Morgan 2002):
+                             each restart keeps the k harmonic Ritz vectors
+                             of smallest harmonic Ritz value and the
+                             residual, so slow modes of the operator stay
+                             in the Krylov space.  1 <= k <= 31,
+                             k <= restart - 2, precond not HEOM_PREC_NN;
+                             other entry points reject k != 0            */
 } heom_solver_opts;
 
 typedef struct {
@@ -354,6 +370,17 @@ heom_status heom_nn_train(heom_nn *nn, const void *X_dev, const void *T_dev, int
  * heom_steady_residual: r = e_0 - B x (B as in heom_apply_steady_operator;
  * FP64 [N][d][d]).  heom_vector_axpby: y = alpha x + beta y over n complex
  * elements of the given precision (y is not read when beta = 0). */
+/* z = P^{-1} r for a fixed preconditioner precond (HEOM_PREC_JACOBI,
+ * HEOM_PREC_SCALED or HEOM_PREC_BLOCK), the map the solvers apply on the
+ * right.  r_dev, z_dev: device [N][d][d][n_rhs] complex vectors of the given
+ * precision, not aliased.  shifts_dev: NULL, or a device array of n_rhs
+ * complex doubles (FP64 whatever the precision), the shift z of column r as
+ * in heom_apply_shifted.  border = 1 (one right-hand side) preconditions the
+ * stationary-state operator of heom_apply_steady_operator (Jacobi divides
+ * element (0,0) of ADO 0 by 1; the block map is unchanged).  Asynchronous on
+ * stream; the first call on a hierarchy uploads its tables. */
+heom_status heom_precondition(heom_hier *h, int32_t precision, int32_t precond, const void *r_dev, void *z_dev,
+                              int32_t n_rhs, const void *shifts_dev, int32_t border, void *stream);
 heom_status heom_steady_residual(heom_hier *h, const void *x_dev, void *r_dev, void *stream);
 heom_status heom_vector_axpby(int32_t precision, const void *x_dev, double alpha, void *y_dev, double beta, int64_t n,
                               void *stream);

@@ -19,7 +19,7 @@ HEOM_BOSON, HEOM_FERMION = 0, 1
 HEOM_U_R, HEOM_U_I, HEOM_U_RI = 0, 1, 2
 HEOM_PADE, HEOM_MATSUBARA = 0, 1
 HEOM_OP_PROPAGATE, HEOM_OP_STEADY, HEOM_OP_SPECTRUM = 0, 1, 2
-HEOM_PREC_NONE, HEOM_PREC_JACOBI, HEOM_PREC_NN, HEOM_PREC_SCALED = 0, 1, 2, 3
+HEOM_PREC_NONE, HEOM_PREC_JACOBI, HEOM_PREC_NN, HEOM_PREC_SCALED, HEOM_PREC_BLOCK = 0, 1, 2, 3, 4
 HEOM_SOLVE_FP64, HEOM_SOLVE_FP32_IR, HEOM_SOLVE_SHIFTED = 0, 1, 2
 
 
@@ -38,7 +38,8 @@ class heom_info(C.Structure):
 class heom_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("precond", C.c_int32),
                 ("mode", C.c_int32), ("inner_tol", C.c_double), ("max_refine", C.c_int32),
-                ("rhs_chunk", C.c_int32), ("nn", vp), ("fallback", C.c_int32), ("use_x0", C.c_int32)]
+                ("rhs_chunk", C.c_int32), ("nn", vp), ("fallback", C.c_int32), ("use_x0", C.c_int32),
+                ("deflate", C.c_int32)]
 
 
 class heom_solver_report(C.Structure):
@@ -97,6 +98,7 @@ SIGNATURES = {
     "heom_batch_info": (heom_status, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), i32p, i32p]),
     "heom_batch_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp]),
     "heom_batch_tune": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, dp, vp]),
+    "heom_precondition": (heom_status, [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, C.c_int32, vp]),
     "heom_batch_workspace_size": (heom_status, [vp, C.POINTER(heom_solver_opts), C.POINTER(C.c_size_t)]),
     "heom_batch_steady": (heom_status, [vp, vp, C.POINTER(heom_solver_opts), C.POINTER(heom_solver_report),
                                         C.c_int32, vp, C.c_size_t, vp]),

@@ -235,14 +235,15 @@ def apply_steady_operator(h, x, y=None, stream=None):
 
 
 # ----------------------------------------------------------------- solvers
-_PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN, "scaled": L.HEOM_PREC_SCALED}
+_PREC = {"none": L.HEOM_PREC_NONE, "jacobi": L.HEOM_PREC_JACOBI, "nn": L.HEOM_PREC_NN, "scaled": L.HEOM_PREC_SCALED,
+         "block": L.HEOM_PREC_BLOCK}
 _MODE = {"fp64": L.HEOM_SOLVE_FP64, "fp32_ir": L.HEOM_SOLVE_FP32_IR, "shifted": L.HEOM_SOLVE_SHIFTED}
 
 
 def solver_opts(**kw):
     """heom_solver_opts from keyword overrides of the library defaults
     (restart, max_iter, tol, precond, mode, inner_tol, max_refine, rhs_chunk,
-    nn, fallback, use_x0)."""
+    nn, fallback, use_x0, deflate)."""
     o = L.heom_solver_opts()
     lib().heom_default_opts(C.byref(o))
     for k, v in kw.items():
@@ -252,6 +253,8 @@ def solver_opts(**kw):
             v = _MODE[v] if isinstance(v, str) else v
         elif k == "nn":
             v = C.c_void_p(v.handle.value) if v is not None else None
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solver option {k!r}")
         setattr(o, k, v)
     return o
 
@@ -298,6 +301,26 @@ def axpby(x, alpha, y, beta, stream=None):
     L.check(lib().heom_vector_axpby(_precision_of(x), _devptr(x), float(alpha), _devptr(y), float(beta), x.numel(),
                                     _stream_ptr(stream)))
     return y
+
+
+def precondition(h, r, precond="block", shifts=None, n_rhs=1, border=False, stream=None):
+    """z = P^{-1} r for a fixed preconditioner ('jacobi', 'scaled', 'block');
+    r: [N][d][d] or [N][d][d][n_rhs] complex device tensor; shifts: optional
+    tensor of n_rhs complex shifts (passed to the library as complex128)."""
+    import torch
+    z = torch.empty_like(r)
+    R = int(n_rhs)
+    if r.numel() != h.N * h.d * h.d * R:
+        raise ValueError("r has the wrong size for this hierarchy")
+    p = _PREC[precond] if isinstance(precond, str) else precond
+    sh = None
+    if shifts is not None:
+        sh = shifts.to(device=r.device, dtype=torch.complex128).contiguous()
+        if sh.numel() != R:
+            raise ValueError("one shift per column")
+    L.check(lib().heom_precondition(h.handle, _precision_of(r), int(p), _devptr(r), _devptr(z), int(R),
+                                    _devptr(sh) if sh is not None else None, int(bool(border)), _stream_ptr(stream)))
+    return z
 
 
 def steady_state(h, x=None, stream=None, allow_not_converged=False, **opts):

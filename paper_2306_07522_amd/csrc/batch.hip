@@ -1027,6 +1027,7 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
     return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: Jacobi or no preconditioning only");
   const bool jac = o->precond == HEOM_PREC_JACOBI;
   if (o->mode != HEOM_SOLVE_FP64 && o->mode != HEOM_SOLVE_FP32_IR) return fail(HEOM_ERR_ARG, "batch_steady: mode");
+  if (o->deflate != 0) return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: no deflated restarting");
   for (heom_hier *h : b->inst)
     if (h->impl->parity != 1) return fail(HEOM_ERR_ARG, "batch_steady: every instance must be even parity");
   hipStream_t s = (hipStream_t)stream;

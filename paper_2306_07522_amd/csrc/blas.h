@@ -20,12 +20,21 @@ heom_status mdot2(const void *V, int64_t ldv, int k, const void *w, const void *
 template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
                          hipStream_t s, const double2 *post = nullptr);
+// In-place change of basis: V_c <- sum_{i < n_in} V_i Q[i + c * n_in] for
+// c < n_out <= kRotateMax (Q: device, column-major, complex double)
+constexpr int kRotateMax = 32;
+template <typename T>
+heom_status basis_rotate(void *V, int64_t ldv, int n_in, const double2 *Q, int n_out, int64_t n, hipStream_t s);
 template <typename T>
 heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s);
 template <typename TX, typename TY>
 heom_status axpby(const void *x, double alpha, void *y, double beta, int64_t total, hipStream_t s);
 // z = D^{-1} r with D the diagonal of (M + shift) (bordered: element (0,0) of
 // ADO 0 counts 1; zeros count 1); modulus = 1 divides by |D| instead
+// Block preconditioner (block_prec.hip): per ADO and right-hand side the
+// exact inverse of -(c_a - z) - i[H, .] in the eigenbasis of H; d <= 32
+template <typename T>
+heom_status block_prec(const void *r, void *z, const Hier &h, int R, const double2 *shifts, hipStream_t s);
 template <typename T>
 heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s,
                    int modulus = 0);

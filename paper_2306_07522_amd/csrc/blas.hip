@@ -163,6 +163,38 @@ __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T
   }
 }
 
+// V_c <- sum_i V_i Q[i, c] for c < n_out (Q column-major, n_in x n_out,
+// n_out <= kRotateMax), in place: each thread reads all n_in entries of its
+// element before it writes any, and no other thread touches that element.
+template <typename T>
+__global__ void __launch_bounds__(256) basis_rotate_kernel(typename Cplx<T>::t *V, int64_t ldv, int n_in,
+                                                           const double2 *__restrict__ Q, int n_out, int64_t n) {
+  using T2 = typename Cplx<T>::t;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double ax[kRotateMax], ay[kRotateMax];
+#pragma unroll
+    for (int c = 0; c < kRotateMax; ++c) {
+      ax[c] = 0.0;
+      ay[c] = 0.0;
+    }
+    for (int i = 0; i < n_in; ++i) {
+      const T2 v = V[i * ldv + e];
+      const double vx = v.x, vy = v.y;
+#pragma unroll
+      for (int c = 0; c < kRotateMax; ++c) {
+        if (c < n_out) {
+          const double2 q = Q[(int64_t)c * n_in + i];
+          ax[c] += vx * q.x - vy * q.y;
+          ay[c] += vx * q.y + vy * q.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kRotateMax; ++c)
+      if (c < n_out) V[c * ldv + e] = T2{(T)ax[c], (T)ay[c]};
+  }
+}
+
 // out[e, r] = w[e, r] * s[r]  (s complex double per RHS); out may alias w
 template <typename T>
 __global__ void scale_kernel(const typename Cplx<T>::t *__restrict__ w, const double2 *__restrict__ s,
@@ -361,6 +393,15 @@ heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, vo
 }
 
 template <typename T>
+heom_status basis_rotate(void *V, int64_t ldv, int n_in, const double2 *Q, int n_out, int64_t n, hipStream_t s) {
+  if (n_out < 1 || n_out > kRotateMax || n_in < n_out) return fail(HEOM_ERR_ARG, "basis_rotate: bad column counts");
+  hipLaunchKernelGGL(basis_rotate_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, (typename Cplx<T>::t *)V, ldv, n_in, Q,
+                     n_out, n);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
 heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s) {
   hipLaunchKernelGGL(scale_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)w, sc,
                      (typename Cplx<T>::t *)out, n, R);
@@ -436,6 +477,7 @@ heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const
   template heom_status basis_update<T>(const void *, int64_t, int, const double2 *, void *, int64_t, int, double,  \
                                        hipStream_t, const double2 *);                                              \
   template heom_status scale_vec<T>(const void *, const double2 *, void *, int64_t, int, hipStream_t);             \
+  template heom_status basis_rotate<T>(void *, int64_t, int, const double2 *, int, int64_t, hipStream_t);            \
   template heom_status jacobi<T>(const void *, void *, const Hier &, int, const double2 *, int, hipStream_t, int);  \
   template heom_status rk4_combine<T>(void *, const void *, const void *, const void *, const void *, double,      \
                                       int64_t, hipStream_t);                                                       \

@@ -1,0 +1,36 @@
+// Small dense complex linear algebra on the host, for the projected
+// (restart-length sized) matrices of the Krylov solvers.  All matrices are
+// column-major: A[i + j * lda] is row i, column j.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+namespace heom {
+
+using cd = std::complex<double>;
+
+// Eigenvalues w[n] and unit right eigenvectors (columns of vecs, n x n) of a
+// general complex n x n matrix A (copied).  Householder reduction to upper
+// Hessenberg form, then the implicitly shifted complex QR iteration with
+// Wilkinson shifts (Schur form T and Schur vectors Z), then the eigenvectors
+// of T by back substitution, mapped back through Z.  Returns false if the QR
+// iteration did not converge.
+bool eig_general(int n, const std::vector<cd> &A, std::vector<cd> &w, std::vector<cd> &vecs);
+
+// Eigen-decomposition of a Hermitian n x n matrix A = U diag(E) U^H by
+// cyclic complex Jacobi rotations (orthonormal U also for degenerate
+// eigenvalues); E ascending.  Returns false if the sweeps did not converge.
+bool eigh_jacobi(int n, const std::vector<cd> &A, std::vector<double> &E, std::vector<cd> &U);
+
+// Solve A x = b (n x n, A copied) by Gaussian elimination with partial
+// pivoting; returns false for an exactly singular pivot.
+bool lu_solve(int n, const std::vector<cd> &A, std::vector<cd> &x);
+
+// Orthonormalise the columns of P (rows x cols, in place) with two passes of
+// classical Gram-Schmidt per column; a column whose remaining norm falls
+// below drop_tol times its original norm is removed.  Returns the number of
+// columns kept (they are packed to the front).
+int orthonormalise_columns(int rows, int cols, std::vector<cd> &P, double drop_tol);
+
+}  // namespace heom

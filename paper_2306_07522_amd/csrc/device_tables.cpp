@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "dense.h"
 #include "internal.h"
 #include "device_common.h"
 
@@ -30,7 +31,8 @@ void free_device(Hier &h) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(D.device);
   void *ptrs[] = {D.decay64, D.decay32, D.ell_cnt, D.ell_col, D.op_slots, D.ell_val64, D.ell_val32,
-                  D.coef_op, D.coef64, D.coef32, D.hdiag, D.hdiag32, D.lev, D.c_meta, D.c_col, D.c_val64, D.c_val32};
+                  D.coef_op, D.coef64, D.coef32, D.hdiag, D.hdiag32, D.lev, D.c_meta, D.c_col, D.c_val64, D.c_val32,
+                  D.ueig, D.eval};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_plan(D.base);
@@ -135,6 +137,24 @@ heom_status ensure_device(Hier &h) {
     hd[i] = make_double2(L.hdiag[i].real(), L.hdiag[i].imag());
     hd32[i] = make_float2((float)L.hdiag[i].real(), (float)L.hdiag[i].imag());
   }
+  // eigen-decomposition of H for the block preconditioner (column-major copy in)
+  std::vector<cd> Hc((size_t)h.d * h.d), Ucol;
+  std::vector<double> Ev;
+  for (int i = 0; i < h.d; ++i)
+    for (int j = 0; j < h.d; ++j) Hc[i + (size_t)j * h.d] = h.H[(size_t)i * h.d + j];
+  if (!eigh_jacobi(h.d, Hc, Ev, Ucol)) return fail(HEOM_ERR_NAN, "eigen-decomposition of H did not converge");
+  std::vector<double2> ue((size_t)h.d * h.d);
+  for (int i = 0; i < h.d; ++i)
+    for (int k = 0; k < h.d; ++k) ue[(size_t)i * h.d + k] = make_double2(Ucol[i + (size_t)k * h.d].real(),
+                                                                         Ucol[i + (size_t)k * h.d].imag());
+  {
+    double dmin = 0.0;
+    for (const auto &b : h.bexp)
+      if (b.chi.real() > 0 && (dmin == 0.0 || b.chi.real() < dmin)) dmin = b.chi.real();
+    for (const auto &f : h.fexp)
+      if (f.gamma.real() > 0 && (dmin == 0.0 || f.gamma.real() < dmin)) dmin = f.gamma.real();
+    h.block_delta = dmin > 0 ? dmin : 1.0;
+  }
   std::vector<int32_t> meta(3 * L.n_ops);
   for (int o = 0; o < L.n_ops; ++o) { meta[3 * o] = L.c_off[o]; meta[3 * o + 1] = L.c_ns[o]; meta[3 * o + 2] = L.c_real[o]; }
   std::vector<double2> cv64(L.c_val.size());
@@ -183,6 +203,8 @@ heom_status ensure_device(Hier &h) {
       (st = upload(&D.hdiag, hd.data(), sizeof(double2) * h.d, tot)) ||
       (st = upload(&D.hdiag32, hd32.data(), sizeof(float2) * h.d, tot)) ||
       (st = upload(&D.lev, h.lev.data(), sizeof(int2) * N, tot)) ||
+      (st = upload(&D.ueig, ue.data(), sizeof(double2) * ue.size(), tot)) ||
+      (st = upload(&D.eval, Ev.data(), sizeof(double) * Ev.size(), tot)) ||
       (st = upload(&D.c_meta, meta.data(), sizeof(int32_t) * meta.size(), tot)) ||
       (st = upload(&D.c_col, L.c_col.data(), sizeof(int32_t) * L.c_col.size(), tot)) ||
       (st = upload(&D.c_val64, cv64.data(), sizeof(double2) * cv64.size(), tot)) ||

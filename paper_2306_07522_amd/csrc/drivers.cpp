@@ -74,6 +74,10 @@ static std::function<heom_status(const void *, void *, bool)> make_P(const Linea
     return [=](const void *in, void *out, bool) -> heom_status {
       return jacobi<T>(in, out, *lp.h, lp.R, lp.shifts64, lp.border, s, o.precond == HEOM_PREC_SCALED);
     };
+  if (o.precond == HEOM_PREC_BLOCK)
+    return [=](const void *in, void *out, bool) -> heom_status {
+      return block_prec<T>(in, out, *lp.h, lp.R, lp.shifts64, s);
+    };
   if (o.precond == HEOM_PREC_NN && nn)
     return [=](const void *in, void *out, bool) -> heom_status { return nn->apply<T>(in, out, s); };
   return nullptr;
@@ -112,6 +116,7 @@ static heom_status solve_system(const LinearProblem &lp, const heom_solver_opts 
     gm.A = make_A<double>(lp, s);
     gm.P = make_P<double>(lp, o, nnp, s);
     if (flex && o.fallback) gm.stall = 0.9;  // hand over to Jacobi early on stagnation
+    gm.deflate = o.deflate;
     if (!x_given) HEOM_HIP_CHECK(hipMemsetAsync(x64, 0, sizeof(double2) * nr, s));
     HEOM_TRY(gm.solve((const double2 *)b64, (double2 *)x64, o.tol, o.max_iter, !x_given, st, s));
   } else {
@@ -121,6 +126,7 @@ static heom_status solve_system(const LinearProblem &lp, const heom_solver_opts 
     if (!r64 || !r32 || !d32) return fail(HEOM_ERR_ARG, "solver workspace too small");
     Gmres<float> gm;
     HEOM_TRY(gm.init(ws, n, R, o.restart, flex));
+    gm.deflate = o.deflate;
     gm.A = make_A<float>(lp, s);
     gm.P = make_P<float>(lp, o, nnp, s);
     auto A64 = make_A<double>(lp, s);
@@ -180,7 +186,12 @@ static heom_status check_opts(const heom_solver_opts *o) {
     return fail(HEOM_ERR_ARG, "bad solve mode");
   if (o->mode == HEOM_SOLVE_SHIFTED && o->precond != HEOM_PREC_NONE)
     return fail(HEOM_ERR_ARG, "the multi-shift mode takes no preconditioner");
-  if (o->precond < HEOM_PREC_NONE || o->precond > HEOM_PREC_SCALED) return fail(HEOM_ERR_ARG, "bad preconditioner");
+  if (o->precond < HEOM_PREC_NONE || o->precond > HEOM_PREC_BLOCK) return fail(HEOM_ERR_ARG, "bad preconditioner");
+  if (o->deflate < 0 || o->deflate > kRotateMax - 1) return fail(HEOM_ERR_ARG, "deflate must be in [0, 31]");
+  if (o->deflate > 0) {
+    if (o->deflate + 2 > o->restart) return fail(HEOM_ERR_ARG, "deflate must be at most restart - 2");
+    if (o->precond == HEOM_PREC_NN) return fail(HEOM_ERR_ARG, "deflated restarting needs a fixed preconditioner");
+  }
   return HEOM_OK;
 }
 
@@ -359,6 +370,27 @@ heom_status heom_vector_axpby(int32_t precision, const void *x_dev, double alpha
   return fail(HEOM_ERR_ARG, "bad precision");
 }
 
+heom_status heom_precondition(heom_hier *hw, int32_t precision, int32_t precond, const void *r_dev, void *z_dev,
+                              int32_t n_rhs, const void *shifts_dev, int32_t border, void *stream) {
+  if (!hw || !r_dev || !z_dev) return fail(HEOM_ERR_ARG, "precondition: NULL argument");
+  if (r_dev == z_dev) return fail(HEOM_ERR_ARG, "precondition: r and z must not alias");
+  if (n_rhs < 1) return fail(HEOM_ERR_ARG, "precondition: n_rhs must be positive");
+  if (border && n_rhs != 1) return fail(HEOM_ERR_ARG, "precondition: border needs one right-hand side");
+  if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_ERR_ARG, "precondition: bad precision");
+  if (precond != HEOM_PREC_JACOBI && precond != HEOM_PREC_SCALED && precond != HEOM_PREC_BLOCK)
+    return fail(HEOM_ERR_ARG, "precondition: Jacobi, scaled or block only");
+  Hier &h = *hw->impl;
+  HEOM_TRY(ensure_device(h));
+  hipStream_t s = (hipStream_t)stream;
+  const double2 *sh = (const double2 *)shifts_dev;
+  const bool fp64 = precision == HEOM_FP64;
+  if (precond == HEOM_PREC_BLOCK)
+    return fp64 ? block_prec<double>(r_dev, z_dev, h, n_rhs, sh, s) : block_prec<float>(r_dev, z_dev, h, n_rhs, sh, s);
+  const int mod = precond == HEOM_PREC_SCALED;
+  return fp64 ? jacobi<double>(r_dev, z_dev, h, n_rhs, sh, border, s, mod)
+              : jacobi<float>(r_dev, z_dev, h, n_rhs, sh, border, s, mod);
+}
+
 heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, heom_solver_report *r, void *ws,
                         size_t ws_bytes, void *stream) {
   if (!hw || !x_dev) return fail(HEOM_ERR_ARG, "steady: NULL argument");
@@ -409,6 +441,7 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
   if (!even || !x_ss_dev || !op || !omega || !out_host || n_omega < 0) return fail(HEOM_ERR_ARG, "spectrum: NULL argument");
   HEOM_TRY(check_opts(o));
   if (kind != 0 && kind != 1) return fail(HEOM_ERR_ARG, "spectrum: kind must be 0 (DOS) or 1 (PSD)");
+  if (o->deflate != 0) return fail(HEOM_ERR_UNSUPPORTED, "spectrum: deflated restarting is for the stationary state");
   if (kind == 0 && !odd) return fail(HEOM_ERR_ARG, "spectrum: the density of states needs the odd-parity hierarchy");
   Hier &he = *even->impl;
   Hier &hs = kind == 0 ? *odd->impl : he;

@@ -86,6 +86,8 @@ struct DeviceTables {
   double2 *hdiag = nullptr;     // [d] diagonal of H
   int2 *lev = nullptr;          // [N] (m, n) levels of every ADO
   float2 *hdiag32 = nullptr;
+  double2 *ueig = nullptr;      // [d][d] row-major eigenvectors of H (H = U diag(E) U^H)
+  double *eval = nullptr;       // [d] eigenvalues of H, ascending
   int32_t *c_meta = nullptr;    // [n_ops][3] (off, ns, real) of the compact ELL
   int32_t *c_col = nullptr;
   double2 *c_val64 = nullptr;
@@ -98,6 +100,9 @@ struct DeviceTables {
 struct Hier {
   int d = 0, Kb = 0, Kf = 0, Lb = 0, Lf = 0, parity = 1;
   double importance_threshold = 0.0;
+  // block preconditioner: denominators of modulus below this are replaced by
+  // -block_delta (the slowest bath decay rate, min Re chi / Re gamma)
+  double block_delta = 1.0;
   std::vector<cd> H;  // d*d row-major
   struct BosExp { int op, u; cd xi, chi; };
   // rank: position in the order eq:importance runs over (per bath: nu = +1

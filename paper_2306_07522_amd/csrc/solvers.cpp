@@ -57,6 +57,7 @@ size_t gmres_bytes(int64_t n, int R, int m, bool flexible, size_t w) {
   const int nch = dot_chunks(n, R);
   b += (size_t)std::max(m + 2, R == 1 ? 2 * m + 3 : 0) * nch * R * sizeof(double2) + 256;  // partials
   b += 4 * (size_t)(m + 2) * R * sizeof(double2) + 1024;   // h, scale
+  b += (size_t)(m + 1) * kRotateMax * sizeof(double2) + 256;  // basis rotation (deflated restarts)
   return b;
 }
 
@@ -76,9 +77,10 @@ heom_status Gmres<T>::init(WsArena &ws, int64_t n_, int R_, int m_, bool flexibl
   partial = (double2 *)ws.take((size_t)std::max(m + 2, R == 1 ? 2 * m + 3 : 0) * nchunk * R * sizeof(double2));
   hdev = (double2 *)ws.take((size_t)2 * (m + 2) * R * sizeof(double2));
   sdev = (double2 *)ws.take((size_t)2 * R * sizeof(double2));
-  if (!V || !w || !t || (flexible && !Z) || !partial || !hdev || !sdev)
+  qdev = (double2 *)ws.take((size_t)(m + 1) * kRotateMax * sizeof(double2));
+  if (!V || !w || !t || (flexible && !Z) || !partial || !hdev || !sdev || !qdev)
     return fail(HEOM_ERR_ARG, "solver workspace too small (see heom_workspace_size)");
-  HEOM_TRY(pin.ensure((size_t)2 * (m + 2) * R * sizeof(double2)));
+  HEOM_TRY(pin.ensure(std::max((size_t)2 * (m + 2) * R, (size_t)(m + 1) * kRotateMax) * sizeof(double2)));
   H.assign((size_t)R * (m + 1) * m, cd(0));
   G.assign((size_t)(m + 1) * (m + 1), cd(0));
   cs.assign((size_t)R * m, 0.0);
@@ -98,9 +100,82 @@ heom_status Gmres<T>::norms(const T2 *v, std::vector<double> &out, hipStream_t s
   return HEOM_OK;
 }
 
+// One Arnoldi orthogonalisation for a single right-hand side, on
+// w = V_{j+1} (already A z_j): two-pass classical Gram-Schmidt with the
+// Gram matrix.  One pass over the basis gives a = V^H w, the new Gram column
+// c = V^H v_j and |w|^2; the reorthogonalised coefficients follow from the
+// measured Gram matrix G = V^H V as h = a + (a - G a) (the second projection
+// of CGS2 without re-reading the basis), |w - V h|^2 from
+// |w|^2 - 2 Re(h^H a) + h^H G h, and a second pass applies the update and
+// the normalisation together.  Returns h (j + 1 entries) and |w - V h|.
+template <typename T>
+heom_status Gmres<T>::gram_step(int j, std::vector<cd> &hc, double &hnorm, hipStream_t s) {
+  const int64_t nr = n;
+  T2 *vj = V + (size_t)j * nr;
+  T2 *vn = V + (size_t)(j + 1) * nr;
+  double2 *h1 = hdev, *h2 = hdev + (size_t)(m + 2);
+  HEOM_TRY(mdot2<T>(V, nr, j + 1, vn, vj, n, partial, nchunk, h1, s));
+  HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, sizeof(double2) * (2 * j + 3), hipMemcpyDeviceToHost, s));
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  const double2 *pp = (const double2 *)pin.p;
+  std::vector<cd> a(j + 1);
+  hc.assign(j + 1, cd(0));
+  for (int i = 0; i <= j; ++i) {
+    a[i] = cd(pp[i].x, pp[i].y);
+    const cd c(pp[j + 1 + i].x, pp[j + 1 + i].y);
+    G[(size_t)j * (m + 1) + i] = c;                // G[i][j] (column j)
+    G[(size_t)i * (m + 1) + j] = std::conj(c);     // G[j][i]
+  }
+  const double ww = pp[2 * j + 2].x;
+  if (!std::isfinite(ww)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+  for (int i = 0; i <= j; ++i) {
+    cd ga(0);
+    for (int q = 0; q <= j; ++q) ga += G[(size_t)q * (m + 1) + i] * a[q];
+    hc[i] = 2.0 * a[i] - ga;
+  }
+  double w2 = ww;
+  for (int i = 0; i <= j; ++i) w2 -= 2.0 * (std::conj(hc[i]) * a[i]).real();
+  cd hgh(0);
+  for (int i = 0; i <= j; ++i) {
+    cd gh(0);
+    for (int q = 0; q <= j; ++q) gh += G[(size_t)q * (m + 1) + i] * hc[q];
+    hgh += std::conj(hc[i]) * gh;
+  }
+  w2 += hgh.real();
+  std::vector<double2> hv(j + 1);
+  for (int i = 0; i <= j; ++i) hv[i] = make_double2(hc[i].real(), hc[i].imag());
+  HEOM_HIP_CHECK(hipMemcpyAsync(h1, hv.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
+  double2 scv = make_double2(0.0, 0.0);
+  if (std::isfinite(w2) && w2 > 1e-6 * ww) {
+    hnorm = std::sqrt(w2);
+    scv.x = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
+    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &scv, sizeof(double2), hipMemcpyHostToDevice, s));
+    HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s, sdev));
+  } else {  // cancellation: measure the norm directly
+    HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s));
+    HEOM_TRY(mdot<T>(vn, 0, 1, vn, n, 1, partial, nchunk, h2, s));
+    HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2, sizeof(double2), hipMemcpyDeviceToHost, s));
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    const double v = ((const double2 *)pin.p)[0].x;
+    if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
+    hnorm = std::sqrt(std::max(v, 0.0));
+    scv.x = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
+    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &scv, sizeof(double2), hipMemcpyHostToDevice, s));
+    HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, 1, s));
+  }
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack
+  return HEOM_OK;
+}
+
 template <typename T>
 heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x_is_zero, GmresStats &st,
                             hipStream_t s) {
+  if (deflate > 0) {
+    if (R != 1 || flexible || deflate + 1 > kRotateMax || deflate + 2 > m)
+      return fail(HEOM_ERR_ARG, "deflated restarting needs one right-hand side, a fixed preconditioner and "
+                                "1 <= deflate <= min(31, restart - 2)");
+    return solve_dr(b, x, tol, max_iter, x_is_zero, st, s);
+  }
   const int64_t nr = n * R;
   std::vector<double> bnorm, beta;
   HEOM_TRY(norms(b, bnorm, s));
@@ -161,7 +236,8 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
       if (P) HEOM_TRY(P(vj, zj, flexible));
       HEOM_TRY(A(zj, vn));
       ++st.applies;
-      // Classical Gram-Schmidt with selective reorthogonalisation (the test
+      // One right-hand side: Gram-matrix CGS2 (gram_step).  Several:
+      // classical Gram-Schmidt with selective reorthogonalisation (the test
       // of Daniel, Gragg, Kaufman and Stewart): one pass gives h = V^H w and
       // |w|^2 together, and |w - V h|^2 follows by Pythagoras.  When the
       // projection removed more than half of |w|^2 a second pass re-projects;
@@ -175,59 +251,9 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
         for (int r = 0; r < R; ++r) scv[r] = make_double2(active[r] && hn[r] > 1e-300 ? 1.0 / hn[r] : 0.0, 0.0);
       };
       if (R == 1) {
-        // Two-pass classical Gram-Schmidt with the Gram matrix: one pass over
-        // the basis gives a = V^H w, the new Gram column c = V^H v_j and
-        // |w|^2; the reorthogonalised coefficients follow from the measured
-        // Gram matrix G = V^H V as h = a + (a - G a) (the second projection
-        // of CGS2 without re-reading the basis), |w - V h|^2 from
-        // |w|^2 - 2 Re(h^H a) + h^H G h, and a second pass applies the
-        // update and the normalisation together.
-        HEOM_TRY(mdot2<T>(V, nr, j + 1, vn, vj, n, partial, nchunk, h1, s));
-        HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, sizeof(double2) * (2 * j + 3), hipMemcpyDeviceToHost, s));
-        HEOM_HIP_CHECK(hipStreamSynchronize(s));
-        const double2 *pp = (const double2 *)pin.p;
-        std::vector<cd> a(j + 1), hh(j + 1);
-        for (int i = 0; i <= j; ++i) {
-          a[i] = cd(pp[i].x, pp[i].y);
-          const cd c(pp[j + 1 + i].x, pp[j + 1 + i].y);
-          G[(size_t)j * (m + 1) + i] = c;                // G[i][j] (column j)
-          G[(size_t)i * (m + 1) + j] = std::conj(c);     // G[j][i]
-        }
-        const double ww = pp[2 * j + 2].x;
-        if (!std::isfinite(ww)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
-        for (int i = 0; i <= j; ++i) {
-          cd ga(0);
-          for (int q = 0; q <= j; ++q) ga += G[(size_t)q * (m + 1) + i] * a[q];
-          hh[i] = 2.0 * a[i] - ga;
-        }
-        double w2 = ww;
-        for (int i = 0; i <= j; ++i) w2 -= 2.0 * (std::conj(hh[i]) * a[i]).real();
-        cd hgh(0);
-        for (int i = 0; i <= j; ++i) {
-          cd gh(0);
-          for (int q = 0; q <= j; ++q) gh += G[(size_t)q * (m + 1) + i] * hh[q];
-          hgh += std::conj(hh[i]) * gh;
-        }
-        w2 += hgh.real();
-        for (int i = 0; i <= j; ++i) hv1[i] = make_double2(hh[i].real(), hh[i].imag());
-        HEOM_HIP_CHECK(hipMemcpyAsync(h1, hv1.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
-        if (std::isfinite(w2) && w2 > 1e-6 * ww) {
-          hn[0] = std::sqrt(w2);
-          scales();
-          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2), hipMemcpyHostToDevice, s));
-          HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s, sdev));
-        } else {  // cancellation: measure the norm directly
-          HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s));
-          HEOM_TRY(mdot<T>(vn, 0, 1, vn, n, 1, partial, nchunk, h2, s));
-          HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h2, sizeof(double2), hipMemcpyDeviceToHost, s));
-          HEOM_HIP_CHECK(hipStreamSynchronize(s));
-          const double v = ((const double2 *)pin.p)[0].x;
-          if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
-          hn[0] = std::sqrt(std::max(v, 0.0));
-          scales();
-          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2), hipMemcpyHostToDevice, s));
-          HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, 1, s));
-        }
+        std::vector<cd> hc;
+        HEOM_TRY(gram_step(j, hc, hn[0], s));
+        for (int i = 0; i <= j; ++i) hv1[i] = make_double2(hc[i].real(), hc[i].imag());
       } else {
         HEOM_TRY(mdot<T>(V, nr, j + 2, vn, n, R, partial, nchunk, h1, s));
         HEOM_HIP_CHECK(hipMemcpyAsync(pin.p, h1, hb, hipMemcpyDeviceToHost, s));

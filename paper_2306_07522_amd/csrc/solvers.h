@@ -3,6 +3,7 @@
 
 #include <functional>
 
+#include "blas.h"
 #include "device_common.h"
 #include "internal.h"
 
@@ -44,11 +45,15 @@ struct Gmres {
   std::function<heom_status(const void *, void *)> A;
   std::function<heom_status(const void *, void *, bool)> P;
   T2 *V = nullptr, *Z = nullptr, *w = nullptr, *t = nullptr;
-  double2 *partial = nullptr, *hdev = nullptr, *sdev = nullptr;
+  double2 *partial = nullptr, *hdev = nullptr, *sdev = nullptr, *qdev = nullptr;
   int nchunk = 1;
   // > 0: give up (not converged) when a restart cycle fails to shrink the
   // worst true residual below stall * its value one cycle earlier
   double stall = 0.0;
+  // > 0: deflated restarting (GMRES-DR, Morgan 2002) keeping this many
+  // harmonic Ritz vectors across restarts; one right-hand side, fixed
+  // preconditioner, deflate + 1 <= kRotateMax and deflate + 2 <= m
+  int deflate = 0;
   PinnedBuf pin;
   std::vector<cd> H, sn, g;
   std::vector<cd> G;  // Gram matrix of the current basis (single right-hand side)
@@ -57,6 +62,11 @@ struct Gmres {
   heom_status norms(const T2 *v, std::vector<double> &out, hipStream_t s);
   // x: initial guess (ignored when x_is_zero; then x must hold zeros)
   heom_status solve(const T2 *b, T2 *x, double tol, int max_iter, bool x_is_zero, GmresStats &st, hipStream_t s);
+  // one right-hand side: orthogonalise V_{j+1} against V_0..V_j (CGS2 with
+  // the Gram matrix G) and normalise it; h (j + 1 entries) and the norm
+  heom_status gram_step(int j, std::vector<cd> &h, double &hnorm, hipStream_t s);
+  // deflated restarting (deflated.cpp)
+  heom_status solve_dr(const T2 *b, T2 *x, double tol, int max_iter, bool x_is_zero, GmresStats &st, hipStream_t s);
 };
 
 // Multi-shift spectra (shifted.cpp): every frequency from one Krylov space.

@@ -1,0 +1,182 @@
+"""Host dense linear algebra of the Krylov solvers (csrc/dense.cpp) against
+numpy: the general complex eigen-solver (harmonic Ritz pairs of deflated
+restarting), the Hermitian Jacobi eigen-solver (eigenbasis of H for the block
+preconditioner), the pivoted LU solve and the column orthonormalisation.
+
+dense.cpp is plain C++ with no HIP dependency; the test builds it with g++
+together with a small C wrapper, so these checks run without a GPU."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2306_07522_amd", "csrc")
+
+WRAPPER = r"""
+#include <complex>
+#include <vector>
+#include "dense.h"
+using heom::cd;
+extern "C" {
+int t_eig(int n, const double *a, double *w, double *v) {
+  std::vector<cd> A(n * n), W, V;
+  for (int i = 0; i < n * n; ++i) A[i] = cd(a[2 * i], a[2 * i + 1]);
+  if (!heom::eig_general(n, A, W, V)) return 1;
+  for (int i = 0; i < n; ++i) { w[2 * i] = W[i].real(); w[2 * i + 1] = W[i].imag(); }
+  for (int i = 0; i < n * n; ++i) { v[2 * i] = V[i].real(); v[2 * i + 1] = V[i].imag(); }
+  return 0;
+}
+int t_eigh(int n, const double *a, double *e, double *u) {
+  std::vector<cd> A(n * n), U;
+  std::vector<double> E;
+  for (int i = 0; i < n * n; ++i) A[i] = cd(a[2 * i], a[2 * i + 1]);
+  if (!heom::eigh_jacobi(n, A, E, U)) return 1;
+  for (int i = 0; i < n; ++i) e[i] = E[i];
+  for (int i = 0; i < n * n; ++i) { u[2 * i] = U[i].real(); u[2 * i + 1] = U[i].imag(); }
+  return 0;
+}
+int t_solve(int n, const double *a, double *x) {
+  std::vector<cd> A(n * n), X(n);
+  for (int i = 0; i < n * n; ++i) A[i] = cd(a[2 * i], a[2 * i + 1]);
+  for (int i = 0; i < n; ++i) X[i] = cd(x[2 * i], x[2 * i + 1]);
+  if (!heom::lu_solve(n, A, X)) return 1;
+  for (int i = 0; i < n; ++i) { x[2 * i] = X[i].real(); x[2 * i + 1] = X[i].imag(); }
+  return 0;
+}
+int t_orth(int rows, int cols, double *p, double tol) {
+  std::vector<cd> P(rows * cols);
+  for (int i = 0; i < rows * cols; ++i) P[i] = cd(p[2 * i], p[2 * i + 1]);
+  const int k = heom::orthonormalise_columns(rows, cols, P, tol);
+  for (int i = 0; i < rows * cols; ++i) { p[2 * i] = P[i].real(); p[2 * i + 1] = P[i].imag(); }
+  return k;
+}
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def dense(tmp_path_factory):
+    d = tmp_path_factory.mktemp("dense")
+    src = d / "wrap.cpp"
+    src.write_text(WRAPPER)
+    so = d / "libdense_test.so"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, str(src),
+                    os.path.join(CSRC, "dense.cpp"), "-o", str(so)], check=True)
+    lib = C.CDLL(str(so))
+    dp = C.POINTER(C.c_double)
+    lib.t_eig.argtypes = [C.c_int, dp, dp, dp]
+    lib.t_eigh.argtypes = [C.c_int, dp, dp, dp]
+    lib.t_solve.argtypes = [C.c_int, dp, dp]
+    lib.t_orth.argtypes = [C.c_int, C.c_int, dp, C.c_double]
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _colmajor(A):
+    return np.ascontiguousarray(np.asfortranarray(A).ravel(order="F").view(np.float64))
+
+
+def _eig(lib, A):
+    n = A.shape[0]
+    a = _colmajor(A.astype(np.complex128))
+    w = np.zeros(2 * n)
+    v = np.zeros(2 * n * n)
+    assert lib.t_eig(n, _ptr(a), _ptr(w), _ptr(v)) == 0
+    return w.view(np.complex128), v.view(np.complex128).reshape(n, n, order="F")
+
+
+def _match(a, b):
+    """Largest distance after pairing every value of a with its nearest in b."""
+    b = list(b)
+    worst = 0.0
+    for x in a:
+        k = int(np.argmin([abs(x - y) for y in b]))
+        worst = max(worst, abs(x - b[k]))
+        b.pop(k)
+    return worst
+
+
+def _cases():
+    rng = np.random.default_rng(11)
+    out = []
+    for n in (1, 2, 3, 7, 30, 90):
+        out.append(("random", rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))))
+    H = np.triu(rng.standard_normal((40, 40)) + 1j * rng.standard_normal((40, 40)), -1)
+    out.append(("hessenberg", H))
+    T = np.triu(rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)))
+    out.append(("triangular", T))
+    Q, _ = np.linalg.qr(rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16)))
+    D = np.diag(np.repeat([1.0, -2.0 + 1j, 0.5j, 3.0], 4))
+    out.append(("repeated", Q @ D @ Q.conj().T))
+    # the shape that deflated restarting solves: Hessenberg plus a last-column update
+    Hm = np.triu(rng.standard_normal((25, 25)) + 1j * rng.standard_normal((25, 25)), -1)
+    f = np.linalg.solve(Hm.conj().T, np.eye(25)[:, -1])
+    out.append(("harmonic", Hm + 0.3 * np.outer(f, np.eye(25)[-1])))
+    return out
+
+
+@pytest.mark.parametrize("name,A", _cases(), ids=[c[0] + str(c[1].shape[0]) for c in _cases()])
+def test_eig_general_against_numpy(dense, name, A):
+    w, V = _eig(dense, A)
+    scale = max(1.0, np.abs(A).max())
+    assert _match(np.linalg.eigvals(A), w) <= 1e-8 * scale * A.shape[0]
+    if name != "repeated":  # eigenvectors of a repeated eigenvalue are a subspace; residuals still hold
+        res = np.linalg.norm(A @ V - V * w[None, :], axis=0)
+        assert res.max() <= 1e-9 * scale * A.shape[0]
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0)
+
+
+@pytest.mark.parametrize("n,degenerate", [(1, False), (2, False), (6, False), (16, False), (16, True), (20, True)])
+def test_eigh_jacobi_against_numpy(dense, n, degenerate):
+    rng = np.random.default_rng(n + 100 * degenerate)
+    if degenerate:  # spin-degenerate spectrum, as in the Anderson models
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+        ev = np.repeat(rng.standard_normal(n // 2), 2)
+        A = Q @ np.diag(ev) @ Q.conj().T
+    else:
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        A = A + A.conj().T
+    a = _colmajor(A)
+    e = np.zeros(n)
+    u = np.zeros(2 * n * n)
+    assert dense.t_eigh(n, _ptr(a), _ptr(e), _ptr(u)) == 0
+    U = u.view(np.complex128).reshape(n, n, order="F")
+    assert np.allclose(e, np.linalg.eigvalsh(A), atol=1e-12 * max(1.0, np.abs(A).max()))
+    assert np.abs(U.conj().T @ U - np.eye(n)).max() <= 1e-13
+    assert np.abs(U @ np.diag(e) @ U.conj().T - A).max() <= 1e-12 * max(1.0, np.abs(A).max())
+
+
+def test_lu_solve_against_numpy(dense):
+    rng = np.random.default_rng(5)
+    for n in (1, 4, 33):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        if n > 1:
+            A[0, 0] = 0.0  # needs a pivot
+        b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        x = np.ascontiguousarray(b.copy().view(np.float64))
+        assert dense.t_solve(n, _ptr(_colmajor(A)), _ptr(x)) == 0
+        assert np.allclose(x.view(np.complex128), np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
+    S = np.zeros((3, 3), complex)
+    x = np.zeros(6)
+    assert dense.t_solve(3, _ptr(_colmajor(S)), _ptr(x)) == 1
+
+
+def test_orthonormalise_columns(dense):
+    rng = np.random.default_rng(8)
+    P = rng.standard_normal((30, 6)) + 1j * rng.standard_normal((30, 6))
+    P[:, 3] = 2.0 * P[:, 0] - 1j * P[:, 1]          # dependent: dropped
+    p = _colmajor(P)
+    k = dense.t_orth(30, 6, _ptr(p), 1e-10)
+    assert k == 5
+    Q = p.view(np.complex128).reshape(30, 6, order="F")[:, :k]
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() <= 1e-13
+    # every original column lies in the span of Q
+    for c in range(6):
+        r = P[:, c] - Q @ (Q.conj().T @ P[:, c])
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(P[:, c])

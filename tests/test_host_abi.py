@@ -87,6 +87,34 @@ def test_argument_errors_are_reported():
         api.exponents_lorentz(1.0, 10.0, 0.0, -1.0, 3)                # negative temperature
 
 
+def test_solver_option_errors_are_reported():
+    """Options the solvers reject before touching device memory: deflated
+    restarting out of range or with the network, unknown preconditioners,
+    and heom_precondition with a preconditioner that is not a fixed map."""
+    import ctypes as C
+    api = _api()
+    from paper_2306_07522_amd import _lib as L
+    cfg = wl.spin_boson()
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], 0)
+    fake = C.c_void_p(256)     # never dereferenced: the options are checked first
+    rep = L.heom_solver_report()
+    for kw in (dict(deflate=32, restart=60), dict(deflate=29, restart=30), dict(deflate=-1),
+               dict(deflate=4, restart=30, precond="nn"), dict(precond=5)):
+        o = api.solver_opts(**kw)
+        st = api.lib().heom_steady(h.handle, fake, C.byref(o), C.byref(rep), None, 0, None)
+        assert st == 1, (kw, st)
+        assert b"deflate" in api.lib().heom_last_error() or b"preconditioner" in api.lib().heom_last_error()
+    o = api.solver_opts(deflate=4, restart=30)
+    fd = C.cast(fake, L.dp)
+    st = api.lib().heom_spectrum(h.handle, None, fake, 1, fd, fd, 1, fd, C.byref(o), C.byref(rep), None, 0, None)
+    assert st != 0
+    for p in (L.HEOM_PREC_NONE, L.HEOM_PREC_NN, 7):
+        st = api.lib().heom_precondition(h.handle, L.HEOM_FP64, p, fake, C.c_void_p(512), 1, None, 0, None)
+        assert st == 1 and b"precondition" in api.lib().heom_last_error()
+    with pytest.raises(TypeError):
+        api.solver_opts(deflation=4)
+
+
 @pytest.mark.parametrize("name", ["spin_boson", "siam", "charge_cavity_small", "random_mixed"])
 def test_same_ado_set_and_decay_as_oracle(name):
     if name == "spin_boson":

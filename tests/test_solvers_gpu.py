@@ -170,7 +170,7 @@ def test_dos_siam_vs_oracle(mode):
     assert np.abs(A - Ao).max() <= 1e-9 * np.abs(Ao).max(), (A, Ao)
 
 
-@pytest.mark.parametrize("mode", ["fp64", "shifted"])
+@pytest.mark.parametrize("mode", ["fp64", "shifted", "block"])
 def test_psd_cavity_vs_oracle(mode):
     torch, api = _torch(), _api()
     cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=2, m_max=2, n_max=1, lam=0.2, gamma=1.0, T=1.0, Gamma=0.5)
@@ -181,6 +181,8 @@ def test_psd_cavity_vs_oracle(mode):
     # state is its null vector) and <a> != 0 for this model
     om = np.linspace(0.25, 2.0, 8)
     extra = dict(precond="none", restart=60) if mode == "shifted" else {}
+    if mode == "block":
+        mode, extra = "fp64", dict(precond="block")
     S, rep = api.spectrum(he, None, x, cfg["aop"], om, kind="psd", tol=1e-12, rhs_chunk=5, mode=mode, **extra)
     assert rep["true_residual"] <= 1e-11, rep
     xs = osv.steady_state(oe.assemble(), oe.d)
@@ -202,4 +204,98 @@ def test_steady_pruned_hierarchy_vs_oracle():
     x, rep = api.steady_state(lm, tol=1e-12, restart=40, max_iter=4000)
     assert rep["status"] == 0, rep
     xs = to_blocks(osv.steady_state(om.assemble(), om.d), om.N, om.d)
+    assert rel_err(x.cpu().numpy()[perm], xs) <= 1e-9
+
+
+# ---------------------------------------------------------------- block preconditioner, deflated restarts
+def _block_reference(x, H, decay, delta, shifts):
+    """U ((U^H X U) / D) U^H per ADO and column, D = -(c_a - z) - i(E_i - E_j),
+    |D| < delta -> -delta; x: [N][d][d][R]."""
+    E, U = np.linalg.eigh(H)
+    Xt = np.einsum("ki,akjr,jl->ailr", U.conj(), x, U)
+    D = -(decay[:, None, None, None] - shifts[None, None, None, :]) - 1j * (E[None, :, None, None] - E[None, None, :, None])
+    D = np.where(np.abs(D) < delta, -delta, D)
+    return np.einsum("ik,aklr,jl->aijr", U, Xt / D, U.conj())
+
+
+def _block_cfgs():
+    return {
+        "weak_cavity": wl.charge_cavity(n_photon=3, n_bexp=2, n_fexp=2),
+        "two_orbital": wl.two_orbital_anderson(n_max=2),
+        "siam": wl.siam(n_max=2, n_exp=2),
+    }
+
+
+@pytest.mark.parametrize("name", ["weak_cavity", "two_orbital", "siam"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_preconditioner_matches_numpy(name, dtype):
+    """heom_precondition(HEOM_PREC_BLOCK) against the eigenbasis formula in
+    numpy, three columns with their own shifts (FP64 1e-12, FP32 1e-5)."""
+    torch, api = _torch(), _api()
+    cfg = _block_cfgs()[name]
+    lm = library_model(cfg, parity_op=cfg.get("parity_op"))
+    T = lm.tables()
+    _, _, lev = lm.ados()
+    tier1 = lev.sum(axis=1) == 1
+    delta = T["decay"][tier1].real.min()
+    R = 3
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((lm.N, lm.d, lm.d, R)) + 1j * rng.standard_normal((lm.N, lm.d, lm.d, R))
+    shifts = np.array([0.0, 0.7j, -1.3 + 0.2j])
+    if dtype == "c64":
+        x = x.astype(np.complex64).astype(np.complex128)
+    ref = _block_reference(x, cfg["H"], T["decay"], delta, shifts)
+    xt = torch.from_numpy(x.astype(np.complex64) if dtype == "c64" else x).cuda()
+    z = api.precondition(lm, xt, "block", shifts=torch.from_numpy(shifts).cuda(), n_rhs=R).cpu().numpy()
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert rel_err(z.astype(np.complex128), ref) <= tol
+
+
+def test_steady_block_preconditioner_weak_cavity():
+    """A weakly damped cavity (Gamma = lambda = 0.01): restarted GMRES without
+    a preconditioner stalls; with the block preconditioner it converges in
+    a few cycles, to the oracle's LU solution."""
+    torch, api = _torch(), _api()
+    cfg = wl.charge_cavity(n_photon=3, n_bexp=2, n_fexp=2)
+    om, lm = oracle_model(cfg), library_model(cfg, parity_op=cfg["parity_op"])
+    perm = oracle_to_library_perm(om, lm)
+    xs = to_blocks(osv.steady_state(om.assemble(), om.d), om.N, om.d)
+    x, rep = api.steady_state(lm, tol=1e-12, precond="block", restart=30, max_iter=600)
+    assert rep["status"] == 0 and rep["iterations"] <= 300, rep
+    assert rel_err(x.cpu().numpy()[perm], xs) <= 1e-9
+    _, rep0 = api.steady_state(lm, tol=1e-8, precond="none", restart=30, max_iter=600, allow_not_converged=True)
+    assert rep0["status"] == 4, rep0
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("precond", ["none", "block"])
+def test_steady_deflated_restarting_vs_oracle(mode, precond):
+    """GMRES-DR (deflated restarts) reaches the oracle's LU solution.  Without
+    a preconditioner, on a short restart length, it needs no more iterations
+    than plain restarts (with the block preconditioner the spectrum is
+    already clustered and keeping k of m vectors need not pay)."""
+    torch, api = _torch(), _api()
+    cfg = wl.siam(n_max=2, n_exp=2)
+    om, lm = oracle_model(cfg), library_model(cfg, parity_op=cfg["parity_op"])
+    perm = oracle_to_library_perm(om, lm)
+    xs = to_blocks(osv.steady_state(om.assemble(), om.d), om.N, om.d)
+    kw = dict(tol=1e-11, precond=precond, restart=10, max_iter=6000, mode=mode)
+    x, rep = api.steady_state(lm, deflate=4, **kw)
+    assert rep["status"] == 0, rep
+    assert rel_err(x.cpu().numpy()[perm], xs) <= 1e-8
+    _, rep0 = api.steady_state(lm, **kw)
+    assert rep0["status"] == 0, rep0
+    if mode == "fp64" and precond == "none":
+        assert rep["iterations"] <= rep0["iterations"], (rep, rep0)
+
+
+def test_steady_deflated_weak_cavity_vs_oracle():
+    """GMRES-DR with the block preconditioner on the weak cavity."""
+    torch, api = _torch(), _api()
+    cfg = wl.charge_cavity(n_photon=3, n_bexp=2, n_fexp=2)
+    om, lm = oracle_model(cfg), library_model(cfg, parity_op=cfg["parity_op"])
+    perm = oracle_to_library_perm(om, lm)
+    xs = to_blocks(osv.steady_state(om.assemble(), om.d), om.N, om.d)
+    x, rep = api.steady_state(lm, tol=1e-12, precond="block", restart=20, deflate=6, max_iter=600)
+    assert rep["status"] == 0, rep
     assert rel_err(x.cpu().numpy()[perm], xs) <= 1e-9
