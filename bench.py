@@ -227,8 +227,8 @@ def batch_benchmark(api, wl):
     """512 seeded uneven instances (spin-boson / Anderson, d in {2,4,8,16},
     tiers 2-6, 3-12 exponents): one batched apply against 512 single
     launches, the autotuned launch, and every stationary state in FP32 with
-    FP64 refinement to 1e-8 (no preconditioner, Jacobi for the instances
-    that miss it), hipGraph-replayed Arnoldi steps."""
+    FP64 refinement to 1e-8 (block preconditioner, no preconditioner for the
+    instances that miss it), hipGraph-replayed Arnoldi steps."""
     import torch
     cfgs = wl.batch_instances(512, seed=4242)
     hs = [api.Hierarchy(c["H"], c["baths"], c["m_max"], c["n_max"], parity_op=c.get("parity_op")) for c in cfgs]
@@ -249,7 +249,7 @@ def batch_benchmark(api, wl):
     nbytes = 2 * b.n * 8 + 8 * (sum(h.N for h in hs) + len(hs)) + 8 * edges + 8 * sum(h.N for h in hs)
     del x, y, xs, ys
     _progress(f"batch apply: {t_batch / reps * 1e3:.3f} ms vs {t_single / reps * 1e3:.3f} ms for 512 single launches")
-    (xb, rb), tb = _timed(lambda: b.steady_state(tol=1e-8, restart=30, max_iter=2400, mode="fp32_ir", precond="none",
+    (xb, rb), tb = _timed(lambda: b.steady_state(tol=1e-8, restart=30, max_iter=2400, mode="fp32_ir", precond="block",
                                                  fallback=1, use_graph=True, allow_not_converged=True))
     del xb
     conv = [r["status"] == 0 for r in rb]
@@ -261,10 +261,11 @@ def batch_benchmark(api, wl):
            "tuner": {"ms_default": round(tune["ms_default"], 4), "ms_best": round(tune["ms_best"], 4),
                      "grid": tune["grid"], "order": tune["order"]},
            "steady": {"seconds": round(tb, 3), "tol": 1e-8, "mode": "fp32_ir", "restart": 30, "max_iter": 2400,
+                      "precond": "block, then none for the instances that miss 1e-8",
                       "converged": int(sum(conv)),
                       "converged_anderson": int(sum(c for c, f in zip(conv, fam) if f == "anderson")),
                       "converged_spin_boson": int(sum(c for c, f in zip(conv, fam) if f == "spin_boson")),
-                      "fell_back_to_jacobi": int(sum(r["fell_back"] for r in rb)),
+                      "fell_back_to_none": int(sum(r["fell_back"] for r in rb)),
                       "max_iterations": int(max(r["iterations"] for r in rb))}}
     b.close()
     for h in hs:

@@ -426,8 +426,8 @@ heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev,
 /* Device workspace bytes for heom_batch_steady with these options. */
 heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opts *o, size_t *bytes);
 /* Stationary state of every instance (the bordered system of
- * heom_steady, Methods and "Package architecture"): restarted GMRES with the
- * Jacobi preconditioner on all instances at once, FP64 or FP32 with FP64
+ * heom_steady, Methods and "Package architecture"): restarted GMRES with a
+ * right preconditioner on all instances at once, FP64 or FP32 with FP64
  * iterative refinement (opts.mode), each instance to opts.tol in its true
  * residual.  Instances leave the active set when they converge.  use_graph
  * = 1 captures each Arnoldi step's device work (preconditioner, apply,
@@ -436,9 +436,11 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
  * if opts.use_x0).  r: n_inst reports (status, iterations, refinements,
  * true residual; seconds and applies are batch totals).  Returns
  * HEOM_ERR_NOT_CONVERGED if any instance misses the tolerance.
- * opts.precond: HEOM_PREC_JACOBI or HEOM_PREC_NONE; with opts.fallback = 1
- * the instances that miss the tolerance are solved again from zero with the
- * other choice, and their reports carry fell_back = 1 (iterations add up). */
+ * opts.precond: HEOM_PREC_NONE, HEOM_PREC_JACOBI or HEOM_PREC_BLOCK; with
+ * opts.fallback = 1 the instances that miss the tolerance are solved again
+ * from zero, with Jacobi after an unpreconditioned pass and without a
+ * preconditioner otherwise, and their reports carry fell_back = 1
+ * (iterations add up). */
 heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
                               int32_t use_graph, void *ws, size_t ws_bytes, void *stream);
 

@@ -43,6 +43,9 @@ struct BInst {
   const T2 *decay;
   const double2 *decay64;
   const double2 *hdiag64;
+  const double2 *ueig;  // [d][d] eigenvectors of H, row-major (block preconditioner)
+  const double *eval;   // [d] eigenvalues of H
+  double delta;         // block preconditioner regularisation
   int64_t off;  // first element of the instance in the batch vector
   int slots;
   int d;
@@ -175,6 +178,87 @@ __global__ void __launch_bounds__(256) batch_jacobi_kernel(const BInst<T> *__res
       const int64_t idx = I.off + a * cells + cell;
       const T2 v = r[idx];
       z[idx] = T2{(T)(((double)v.x * dg.x + (double)v.y * dg.y) * inv), (T)(((double)v.y * dg.x - (double)v.x * dg.y) * inv)};
+    }
+  }
+}
+
+// z = P^{-1} r per instance with the block preconditioner: per ADO the exact
+// inverse of -c_a - i[H, .] in the eigenbasis of H (see block_prec.hip), one
+// task of the tile at a time, four d x d products through LDS (d <= 16).
+template <typename T>
+__global__ void __launch_bounds__(256) batch_block_kernel(const BInst<T> *__restrict__ inst,
+                                                          const int4 *__restrict__ tiles, int n_tiles,
+                                                          const int *__restrict__ active,
+                                                          const typename Cplx<T>::t *__restrict__ r,
+                                                          typename Cplx<T>::t *__restrict__ z) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double2 Us[256], X[256], W[256];
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    if (active && !active[tl.x]) continue;  // uniform over the workgroup
+    const BInst<T> &I = inst[tl.x];
+    const int d = I.d, dd = d * d;
+    __syncthreads();  // the previous tile is done with the LDS
+    for (int e = threadIdx.x; e < dd; e += blockDim.x) Us[e] = I.ueig[e];
+    for (int64_t task = tl.y; task < tl.z; ++task) {
+      const int64_t a = I.tasks[task].x;
+      const int64_t base = I.off + a * dd;
+      __syncthreads();
+      for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+        const T2 v = r[base + e];
+        X[e] = make_double2((double)v.x, (double)v.y);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // W = U^H X
+        const int i = e / d, j = e % d;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double2 u = Us[k * d + i], x = X[k * d + j];
+          sx += u.x * x.x + u.y * x.y;
+          sy += u.x * x.y - u.y * x.x;
+        }
+        W[e] = make_double2(sx, sy);
+      }
+      __syncthreads();
+      const double2 c = I.decay64[a];
+      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // X = (W U) / D
+        const int i = e / d, j = e % d;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double2 w = W[i * d + k], u = Us[k * d + j];
+          sx += w.x * u.x - w.y * u.y;
+          sy += w.x * u.y + w.y * u.x;
+        }
+        double dx = -c.x, dy = -c.y - (I.eval[i] - I.eval[j]);
+        if (dx * dx + dy * dy < I.delta * I.delta) {
+          dx = -I.delta;
+          dy = 0.0;
+        }
+        const double inv = 1.0 / (dx * dx + dy * dy);
+        X[e] = make_double2((sx * dx + sy * dy) * inv, (sy * dx - sx * dy) * inv);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // W = U X
+        const int i = e / d, j = e % d;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double2 u = Us[i * d + k], x = X[k * d + j];
+          sx += u.x * x.x - u.y * x.y;
+          sy += u.x * x.y + u.y * x.x;
+        }
+        W[e] = make_double2(sx, sy);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // z = W U^H
+        const int i = e / d, j = e % d;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double2 w = W[i * d + k], u = Us[j * d + k];
+          sx += w.x * u.x + w.y * u.y;
+          sy += w.y * u.x - w.x * u.y;
+        }
+        z[base + e] = T2{(T)sx, (T)sy};
+      }
     }
   }
 }
@@ -446,6 +530,17 @@ static heom_status batch_apply_T(heom_batch &b, const void *x, void *y, int bord
 }
 
 template <typename T>
+static heom_status batch_block_T(heom_batch &b, const void *r, void *z, hipStream_t s) {
+  const int grid = b.grid > 0 ? std::min(b.grid, b.n_tiles) : b.n_tiles;
+  if (grid <= 0) return HEOM_OK;
+  const BInst<T> *I = std::is_same<T, double>::value ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
+  hipLaunchKernelGGL(batch_block_kernel<T>, dim3(grid), dim3(256), 0, s, I, b.tiles, b.n_tiles, b.active,
+                     (const typename Cplx<T>::t *)r, (typename Cplx<T>::t *)z);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
 static heom_status batch_jacobi_T(heom_batch &b, const void *r, void *z, int border, hipStream_t s) {
   const int grid = b.grid > 0 ? std::min(b.grid, b.n_tiles) : b.n_tiles;
   if (grid <= 0) return HEOM_OK;
@@ -541,7 +636,7 @@ struct BatchGmres {
   double2 *pin_h = nullptr;       // host pinned: step coefficients [(m + 1) S] and norms [S]
   PinnedBuf pin;
   bool use_graph = false;
-  bool jacobi = true;                  // false: no preconditioner (Z aliases V)
+  int prec = HEOM_PREC_JACOBI;         // HEOM_PREC_NONE: Z aliases V
   std::vector<hipGraphExec_t> graphs;  // one per Arnoldi step j
   hipStream_t cap = nullptr;
   ~BatchGmres() {
@@ -550,21 +645,21 @@ struct BatchGmres {
     if (cap) (void)hipStreamDestroy(cap);
   }
 
-  static size_t bytes(const heom_batch &b, int m, bool jac) {
+  static size_t bytes(const heom_batch &b, int m, bool jac) {  // jac: any preconditioner (Z kept)
     const size_t vec = (size_t)b.n * sizeof(T2);
     return (size_t)(m + 1) * vec + (jac ? (size_t)m * vec : 0) + vec + (size_t)(2 * m + 3) * b.n_chunks * sizeof(double2) +
            (size_t)(3 * m + 5) * b.S * sizeof(double2) + (size_t)b.S * (m + 1) * (m + 1) * sizeof(double2) +
            (size_t)b.S * sizeof(double) + 8 * 256;
   }
 
-  heom_status init(heom_batch &bb, WsArena &ws, int m_, bool graph, bool jac) {
+  heom_status init(heom_batch &bb, WsArena &ws, int m_, bool graph, int prec_) {
     b = &bb;
     m = m_;
     use_graph = graph;
-    jacobi = jac;
+    prec = prec_;
     const size_t vec = (size_t)b->n * sizeof(T2);
     V = (T2 *)ws.take((size_t)(m + 1) * vec);
-    Z = jacobi ? (T2 *)ws.take((size_t)m * vec) : V;
+    Z = prec != HEOM_PREC_NONE ? (T2 *)ws.take((size_t)m * vec) : V;
     w = (T2 *)ws.take(vec);
     partial = (double2 *)ws.take((size_t)(2 * m + 3) * b->n_chunks * sizeof(double2));
     // hdev: [0, (2m+3) S) reduced a, c, |w|^2;  then h [(m+1) S] and |w'|^2 [S]
@@ -592,7 +687,8 @@ struct BatchGmres {
     const int64_t n = b->n;
     T2 *vj = V + (size_t)j * n;
     T2 *zj = Z + (size_t)j * n;
-    if (jacobi) HEOM_TRY(batch_jacobi_T<T>(*b, vj, zj, border, s));
+    if (prec == HEOM_PREC_JACOBI) HEOM_TRY(batch_jacobi_T<T>(*b, vj, zj, border, s));
+    if (prec == HEOM_PREC_BLOCK) HEOM_TRY(batch_block_T<T>(*b, vj, zj, s));
     HEOM_TRY(batch_apply_T<T>(*b, zj, w, border, true, s));
     HEOM_TRY(seg_mdot2<T>(*b, V, n, j + 1, w, vj, partial, hdev, s));
     hipLaunchKernelGGL(batch_gram_kernel, dim3((b->S + 255) / 256), dim3(256), 0, s, gram, hdev, j, b->S, m + 1,
@@ -829,12 +925,14 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
     a.tasks = D.base.tasks; a.groups = D.base.groups; a.gedges = D.base.gedges;
     a.coef_op = D.coef_op; a.coef = D.coef64; a.ell_cnt = D.ell_cnt; a.ell_col = D.ell_col;
     a.ell_val = D.ell_val64; a.decay = D.decay64; a.decay64 = D.decay64; a.hdiag64 = D.hdiag;
+    a.ueig = D.ueig; a.eval = D.eval; a.delta = h.block_delta;
     a.off = b->off[s]; a.slots = h.ell.slots; a.d = h.d;
     i64[s] = a;
     BInst<float> f{};
     f.tasks = D.base.tasks; f.groups = D.base.groups; f.gedges = D.base.gedges;
     f.coef_op = D.coef_op; f.coef = D.coef32; f.ell_cnt = D.ell_cnt; f.ell_col = D.ell_col;
     f.ell_val = D.ell_val32; f.decay = D.decay32; f.decay64 = D.decay64; f.hdiag64 = D.hdiag;
+    f.ueig = D.ueig; f.eval = D.eval; f.delta = h.block_delta;
     f.off = b->off[s]; f.slots = h.ell.slots; f.d = h.d;
     i32[s] = f;
     cost[s] = (double)h.row_ptr.back() * h.d * h.d + (double)h.N * h.d * h.d;
@@ -1009,8 +1107,8 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
   if (!o) { heom_default_opts(&d); o = &d; }
   const size_t v64 = (size_t)b->n * 16, v32 = (size_t)b->n * 8;
   size_t need = v64 + 4096;  // right-hand side
-  // the Jacobi pass (first choice, or the fallback pass) keeps the Z basis
-  const bool jac = o->precond == HEOM_PREC_JACOBI || o->fallback;
+  // a preconditioned pass (first choice, or the fallback pass) keeps the Z basis
+  const bool jac = o->precond != HEOM_PREC_NONE || o->fallback;
   if (o->mode == HEOM_SOLVE_FP32_IR) need += v64 + 2 * v32 + BatchGmres<float>::bytes(*b, o->restart, jac);
   else need += BatchGmres<double>::bytes(*b, o->restart, jac);
   need += (size_t)b->S * sizeof(double) + 256;
@@ -1023,9 +1121,11 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
   HEOM_TRY(batch_check(b));
   if (!x_dev || !o || !ws) return fail(HEOM_ERR_ARG, "batch_steady: NULL argument");
   if (o->restart < 1 || o->restart > 1000 || o->max_iter < 1 || !(o->tol > 0)) return fail(HEOM_ERR_ARG, "batch_steady: bad options");
-  if (o->precond != HEOM_PREC_JACOBI && o->precond != HEOM_PREC_NONE)
-    return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: Jacobi or no preconditioning only");
-  const bool jac = o->precond == HEOM_PREC_JACOBI;
+  if (o->precond != HEOM_PREC_JACOBI && o->precond != HEOM_PREC_NONE && o->precond != HEOM_PREC_BLOCK)
+    return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: Jacobi, block or no preconditioning only");
+  const int prec1 = o->precond;
+  // the fallback pass: Jacobi after an unpreconditioned pass, none otherwise
+  const int prec2 = prec1 == HEOM_PREC_NONE ? HEOM_PREC_JACOBI : HEOM_PREC_NONE;
   if (o->mode != HEOM_SOLVE_FP64 && o->mode != HEOM_SOLVE_FP32_IR) return fail(HEOM_ERR_ARG, "batch_steady: mode");
   if (o->deflate != 0) return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: no deflated restarting");
   for (heom_hier *h : b->inst)
@@ -1045,13 +1145,13 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
   std::vector<char> conv(S, 0);
   int64_t applies = 0;
   // One pass solves the instances flagged in `want` (from zero unless
-  // from_x) with or without the Jacobi preconditioner.
-  auto run_pass = [&](bool jac_pass, std::vector<char> want, bool from_x) -> heom_status {
+  // from_x) with preconditioner prec_pass.
+  auto run_pass = [&](int prec_pass, std::vector<char> want, bool from_x) -> heom_status {
     WsArena arena2(ws, ws_bytes);
     arena2.take(sizeof(double2) * n);  // rhs
     if (o->mode == HEOM_SOLVE_FP64) {
       BatchGmres<double> gm;
-      HEOM_TRY(gm.init(*b, arena2, o->restart, use_graph != 0, jac_pass));
+      HEOM_TRY(gm.init(*b, arena2, o->restart, use_graph != 0, prec_pass));
       std::vector<int> it;
       std::vector<double> rs;
       std::vector<char> cv;
@@ -1065,7 +1165,7 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
     float2 *d32 = (float2 *)arena2.take(sizeof(float2) * n);
     if (!r64 || !r32 || !d32) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small");
     BatchGmres<float> gm;
-    HEOM_TRY(gm.init(*b, arena2, o->restart, use_graph != 0, jac_pass));
+    HEOM_TRY(gm.init(*b, arena2, o->restart, use_graph != 0, prec_pass));
     const std::vector<double> bn(S, 1.0);  // |e_0| = 1 for every instance
     std::vector<int> it0(S, 0);
     for (int ref = 0;; ++ref) {
@@ -1114,7 +1214,7 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
     return HEOM_OK;
   };
   if (!o->use_x0) HEOM_TRY(seg_zero<double>(x_dev, n, s));
-  HEOM_TRY(run_pass(jac, std::vector<char>(S, 1), o->use_x0 != 0));
+  HEOM_TRY(run_pass(prec1, std::vector<char>(S, 1), o->use_x0 != 0));
   std::vector<char> fell(S, 0);
   if (o->fallback) {
     // instances that missed the tolerance: again from zero with the other choice
@@ -1134,7 +1234,7 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
       HEOM_TRY((seg_scale<double, double>(*b, x_dev, kd, x_dev, s)));
       HEOM_HIP_CHECK(hipStreamSynchronize(s));
       fell = again;
-      HEOM_TRY(run_pass(!jac, again, false));
+      HEOM_TRY(run_pass(prec2, again, false));
     }
   }
   HEOM_HIP_CHECK(hipStreamSynchronize(s));
