@@ -158,14 +158,25 @@ def _train_network(api, d, hidden, models, snapshots, restart, subset, epochs, s
 
 
 def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snapshots, pair_restart,
-                      restart_none=None):
-    """Stationary state to a 1e-8 true residual: Jacobi GMRES vs FGMRES with
-    the network (which hands over to Jacobi if it stagnates)."""
+                      restart_none=None, deflated=None):
+    """Stationary state to a 1e-8 true residual: GMRES without a
+    preconditioner (plain restarts, and deflated restarts (m, k) when given),
+    Jacobi GMRES, and FGMRES with the network (which hands over to Jacobi if
+    it stagnates)."""
     h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
     (x_0, r0), t0 = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=restart_none or restart,
                                                      mode=mode, max_iter=20000, allow_not_converged=True))
     del x_0
     _progress(f"{cfg['name']} N={h.N} steady, GMRES without preconditioner: {r0['iterations']} iterations, {t0:.2f} s")
+    rec_dr = None
+    if deflated:
+        (x_d, rd), td = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=deflated[0],
+                                                         deflate=deflated[1], mode=mode, max_iter=20000,
+                                                         allow_not_converged=True))
+        del x_d
+        rec_dr = dict(_solve_record(rd, td), restart=deflated[0], deflate=deflated[1])
+        _progress(f"{cfg['name']} N={h.N} steady, GMRES-DR({deflated[0]}, {deflated[1]}) without preconditioner: "
+                  f"{rd['iterations']} iterations, {td:.2f} s")
     (x_p, rp), tp = _timed(lambda: api.steady_state(h, tol=1e-8, precond="jacobi", restart=restart, mode=mode,
                                                      max_iter=20000, allow_not_converged=True))
     del x_p
@@ -182,10 +193,12 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     net.close()
     _progress(f"{cfg['name']} N={h.N} steady, NN FGMRES: {rn['iterations']} iterations, {tn:.2f} s, "
               f"fell back {rn['fell_back']}")
-    best = min([t for t, r in ((t0, r0), (tp, rp)) if r["status"] == 0], default=None)
+    plain = [(t0, r0), (tp, rp)] + ([(rec_dr["seconds"], rd)] if rec_dr else [])
+    best = min([t for t, r in plain if r["status"] == 0], default=None)
     out = {"n_ado": h.N, "d": h.d, "restart": restart, "restart_none": restart_none or restart, "mode": mode,
            "nn_max_iter": cap,
            "plain_none": _solve_record(r0, t0), "plain_jacobi": _solve_record(rp, tp),
+           "plain_none_deflated": rec_dr, "best_plain_seconds": round(best, 4) if best else None,
            "nn_fgmres": _solve_record(rn, tn), "network": {"hidden": hidden, **info},
            "nn_speedup_vs_jacobi": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None,
            "nn_speedup_vs_best_plain": round(best / tn, 4) if best and tn > 0 and rn["status"] == 0 else None}
@@ -355,7 +368,7 @@ def solve_benchmarks(which):
         out.update(propagation_benchmarks(api, wl))
         train = [wl.perturbed_two_orbital(1000 + s, n_max=3) for s in range(3)]
         out["two_orbital_tier4_steady"] = steady_comparison(api, wl, wl.two_orbital_anderson(), train, 16, 256, 100,
-                                                            "fp64", (20, 60), 100, restart_none=60)
+                                                            "fp64", (20, 60), 100, restart_none=60, deflated=(20, 6))
         out["two_orbital_tier4_dos"] = dos_benchmark(api, wl, wl.two_orbital_anderson(), sample=0)
         out["batch_512_instances"] = batch_benchmark(api, wl)
     return out
