@@ -64,8 +64,9 @@ def parse():
     p.add_argument("--tiled", type=int, default=-1, help="-1: untiled apply; 0: default chunks; k: k chunks")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--solves", choices=["all", "siam", "none"], default="all",
-                   help="solve timings: all (two-orbital tier 4 and SIAM), siam only, or none")
+    p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "cavity", "batch"], default="all",
+                   help="solve timings: all legs, siam only, none, or one leg (the two-orbital stationary state "
+                        "with GMRES-DR, the cavity stationary state and PSD, the 512-instance batch) for profiling")
     p.add_argument("--calib", action="store_true",
                    help="also run one plain device copy of the ADO vector (HBM counter calibration)")
     return p.parse_args()
@@ -326,8 +327,19 @@ def propagation_benchmarks(api, wl):
                                 "cache_resident": True,
                                 "trace_rho0_end": float(torch.diagonal(traj[-1]).sum().real.item())}
     _progress(f"charge-cavity RK4: {n_steps} steps in {t:.2f} s")
-    # cavity power spectrum at its 1024 frequencies
-    he = h
+    h.close()
+    out.update(cavity_spectrum_benchmark(api, wl))
+    return out
+
+
+def cavity_spectrum_benchmark(api, wl):
+    """Stationary state of the charge-cavity model (3,165 ADOs of 20x20)
+    without a preconditioner and with the block preconditioner, and its power
+    spectrum at 1,024 frequencies."""
+    import numpy as np
+    out = {}
+    cfg = wl.charge_cavity()
+    he = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
     # weak couplings (lambda = Gamma = 0.01): restarted GMRES without a
     # preconditioner stalls near 1e-2 on this stationary state; the block
     # preconditioner (exact inverse of each ADO's own terms) converges in a
@@ -350,14 +362,32 @@ def propagation_benchmarks(api, wl):
                                 "converged": rep["status"] == 0, "finite": bool(np.all(np.isfinite(S))),
                                 "S_max": float(S.max()), "omega_at_S_max": float(om[int(np.argmax(S))])}
     _progress(f"charge-cavity PSD at {len(cfg['omegas'])} frequencies: {t:.2f} s")
-    h.close()
+    he.close()
     return out
+
+
+def deflated_steady_benchmark(api, wl):
+    """The two-orbital tier-4 stationary state with GMRES-DR(20, 6) alone."""
+    cfg = wl.two_orbital_anderson()
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    (x, r), t = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=20, deflate=6, max_iter=3000,
+                                                allow_not_converged=True))
+    del x
+    _progress(f"two-orbital steady, GMRES-DR(20, 6): {r['iterations']} iterations, {t:.2f} s")
+    h.close()
+    return {"two_orbital_tier4_steady_deflated": dict(_solve_record(r, t), restart=20, deflate=6)}
 
 
 def solve_benchmarks(which):
     import numpy as np
     from paper_2306_07522_amd import api, workloads as wl
     out = {}
+    if which == "two_orbital_dr":
+        return deflated_steady_benchmark(api, wl)
+    if which == "cavity":
+        return cavity_spectrum_benchmark(api, wl)
+    if which == "batch":
+        return {"batch_512_instances": batch_benchmark(api, wl)}
     siam_train = []
     for s in range(4):
         z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(4))
