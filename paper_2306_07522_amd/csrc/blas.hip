@@ -119,19 +119,32 @@ __global__ void __launch_bounds__(256) mdot2_kernel(const typename Cplx<T>::t *_
   if (blockIdx.y == 0 && threadIdx.x == 0) partial[(int64_t)(2 * k) * nchunk + chunk] = red[2 * NI][0];
 }
 
-// out[i * R + r] = sum over chunks of partial
-__global__ void reduce_partials_kernel(const double2 *__restrict__ partial, int k, int nchunk, int R,
-                                       double2 *__restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)k * R) return;
+// out[i * R + r] = sum over chunks of partial: one workgroup per output,
+// each thread sums a fixed strided subset of the chunks, then a fixed-order
+// tree in LDS (deterministic)
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double2 *__restrict__ partial, int k, int nchunk,
+                                                              int R, double2 *__restrict__ out) {
+  __shared__ double sx[256], sy[256];
+  const int64_t idx = blockIdx.x;
+  const int t = threadIdx.x;
   const int i = (int)(idx / R), r = (int)(idx % R);
-  double sx = 0, sy = 0;
-  for (int c = 0; c < nchunk; ++c) {
+  double ax = 0.0, ay = 0.0;
+  for (int c = t; c < nchunk; c += 256) {
     const double2 p = partial[((int64_t)i * nchunk + c) * R + r];
-    sx += p.x;
-    sy += p.y;
+    ax += p.x;
+    ay += p.y;
   }
-  out[idx] = make_double2(sx, sy);
+  sx[t] = ax;
+  sy[t] = ay;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      sx[t] += sx[t + h];
+      sy[t] += sy[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[idx] = make_double2(sx[0], sy[0]);
 }
 
 // w[e, r] -= sum_{i < k} V_i[e, r] * h[i * R + r]   (h is complex double)
@@ -361,8 +374,7 @@ heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, in
   hipLaunchKernelGGL((mdot_kernel<T, NI>), g, dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv, k,
                      (const typename Cplx<T>::t *)w, n, R, partial, nchunk);
   const int64_t kr = (int64_t)k * R;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((kr + 255) / 256)), dim3(256), 0, s, partial, k, nchunk, R,
-                     out);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)kr), dim3(256), 0, s, partial, k, nchunk, R, out);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -376,8 +388,7 @@ heom_status mdot2(const void *V, int64_t ldv, int k, const void *w, const void *
   hipLaunchKernelGGL((mdot2_kernel<T, NI>), g, dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv, k,
                      (const typename Cplx<T>::t *)w, (const typename Cplx<T>::t *)u, n, partial, nchunk);
   const int64_t kk = 2 * (int64_t)k + 1;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, partial, (int)kk,
-                     nchunk, 1, out);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)kk), dim3(256), 0, s, partial, (int)kk, nchunk, 1, out);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
