@@ -370,6 +370,21 @@ heom_status heom_nn_train(heom_nn *nn, const void *X_dev, const void *T_dev, int
  * heom_steady_residual: r = e_0 - B x (B as in heom_apply_steady_operator;
  * FP64 [N][d][d]).  heom_vector_axpby: y = alpha x + beta y over n complex
  * elements of the given precision (y is not read when beta = 0). */
+/* Electronic current from one fermionic lead into the system (Methods,
+ * "Electronic current", eq:last), in units e = hbar = 1:
+ *   I = i sum_{nu, h, sigma} (-1)^{delta_{nu,-}} Tr[d_sigma^{nu-bar} rho_{|{alpha,nu,h,sigma}}]
+ * over the first-level fermionic ADOs (m = 0, n = 1) of x_dev.  The lead is
+ * the set of fermionic bath records records[n_rec] (indices into the baths
+ * array given to heom_build_hierarchy, e.g. one record per spin of lead
+ * alpha).  h: even-parity hierarchy; x_dev: FP64 ADO vector (normally the
+ * stationary state of heom_steady).  out: host double[2], the complex
+ * current (real for a stationary state; 0 when n_max = 0).  Synchronises
+ * the stream; allocates and frees small device buffers for the term list.
+ * Errors: HEOM_ERR_ARG for a NULL argument, an odd-parity hierarchy, a bath
+ * index out of range, repeated, or of a bosonic bath. */
+heom_status heom_current(heom_hier *h, const void *x_dev, int32_t n_rec, const int32_t *records, double *out,
+                         void *stream);
+
 /* z = P^{-1} r for a fixed preconditioner precond (HEOM_PREC_JACOBI,
  * HEOM_PREC_SCALED or HEOM_PREC_BLOCK), the map the solvers apply on the
  * right.  r_dev, z_dev: device [N][d][d][n_rhs] complex vectors of the given

@@ -303,6 +303,22 @@ def axpby(x, alpha, y, beta, stream=None):
     return y
 
 
+def current(h, x, lead, stream=None):
+    """Electronic current (eq:last, e = hbar = 1) from the lead made of the
+    fermionic bath records `lead` (indices into the hierarchy's bath list)
+    into the system, read from the FP64 ADO vector x (complex)."""
+    import torch
+    if x.dtype != torch.complex128:
+        raise TypeError("the current is read from an FP64 (complex128) ADO vector")
+    if x.numel() != h.N * h.d * h.d:
+        raise ValueError("x has the wrong size for this hierarchy")
+    rec = np.ascontiguousarray(np.asarray(list(lead), dtype=np.int32))
+    out = np.zeros(2)
+    L.check(lib().heom_current(h.handle, _devptr(x), int(rec.size), rec.ctypes.data_as(L.i32p),
+                               out.ctypes.data_as(L.dp), _stream_ptr(stream)))
+    return complex(out[0], out[1])
+
+
 def precondition(h, r, precond="block", shifts=None, n_rhs=1, border=False, stream=None):
     """z = P^{-1} r for a fixed preconditioner ('jacobi', 'scaled', 'block');
     r: [N][d][d] or [N][d][d][n_rhs] complex device tensor; shifts: optional

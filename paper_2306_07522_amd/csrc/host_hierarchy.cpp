@@ -266,6 +266,7 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
   for (int bi = 0; bi < n_baths; ++bi) {
     const heom_bath &b = baths[bi];
     if (!b.op || b.n_exp < 0) return fail(HEOM_ERR_ARG, "bath " + std::to_string(bi) + ": bad operator/n_exp");
+    h->bath_kind.push_back(b.kind);
     auto O = read_mat(b.op, d);
     if (b.kind == HEOM_BOSON) {
       if (b.n_exp > 0 && (!b.u_type || !b.xi || !b.chi)) return fail(HEOM_ERR_ARG, "boson bath: missing arrays");
@@ -296,9 +297,9 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
       int base = (int)h->fexp.size();
       for (int k = 0; k < b.n_exp; ++k) {
         h->fexp.push_back({op_ann, +1, base + 2 * k + 1, cd(b.eta_p[2 * k], b.eta_p[2 * k + 1]),
-                           cd(b.gam_p[2 * k], b.gam_p[2 * k + 1]), base + k});
+                           cd(b.gam_p[2 * k], b.gam_p[2 * k + 1]), base + k, bi});
         h->fexp.push_back({op_ann, -1, base + 2 * k, cd(b.eta_m[2 * k], b.eta_m[2 * k + 1]),
-                           cd(b.gam_m[2 * k], b.gam_m[2 * k + 1]), base + b.n_exp + k});
+                           cd(b.gam_m[2 * k], b.gam_m[2 * k + 1]), base + b.n_exp + k, bi});
       }
     } else {
       return fail(HEOM_ERR_ARG, "bath kind must be HEOM_BOSON or HEOM_FERMION");

@@ -107,9 +107,11 @@ struct Hier {
   struct BosExp { int op, u; cd xi, chi; };
   // rank: position in the order eq:importance runs over (per bath: nu = +1
   // terms h = 1.., then nu = -1 terms)
-  struct FermExp { int op_ann, nu, partner; cd eta, gamma; int rank; };
+  // bath: index of the input bath record the exponent came from
+  struct FermExp { int op_ann, nu, partner; cd eta, gamma; int rank; int bath; };
   std::vector<BosExp> bexp;
   std::vector<FermExp> fexp;
+  std::vector<int> bath_kind;  // per input bath record: HEOM_BOSON or HEOM_FERMION
   std::vector<std::vector<cd>> ops;  // ops[0] = H
   // ADOs
   int64_t N = 0;

@@ -87,6 +87,23 @@ def test_argument_errors_are_reported():
         api.exponents_lorentz(1.0, 10.0, 0.0, -1.0, 3)                # negative temperature
 
 
+def test_current_argument_errors_are_reported():
+    """heom_current rejects leads it cannot read before touching the device."""
+    import ctypes as C
+    api = _api()
+    from paper_2306_07522_amd import _lib as L
+    cfg = wl.charge_cavity(n_photon=2, n_bexp=2, n_fexp=2, m_max=1, n_max=1)
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    ho = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=-1, parity_op=cfg["parity_op"])
+    fake = C.c_void_p(256)     # never dereferenced: the arguments are checked first
+    out = np.zeros(2)
+    for hh, lead in ((h, [0]), (h, [3]), (h, [-1]), (h, [1, 1]), (ho, [1])):
+        rec = np.asarray(lead, dtype=np.int32)
+        st = api.lib().heom_current(hh.handle, fake, rec.size, rec.ctypes.data_as(L.i32p), out.ctypes.data_as(L.dp),
+                                    None)
+        assert st == 1 and b"current" in api.lib().heom_last_error(), (lead, st)
+
+
 def test_solver_option_errors_are_reported():
     """Options the solvers reject before touching device memory: deflated
     restarting out of range or with the network, unknown preconditioners,
