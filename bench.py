@@ -64,7 +64,8 @@ def parse():
     p.add_argument("--tiled", type=int, default=-1, help="-1: untiled apply; 0: default chunks; k: k chunks")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "cavity", "batch"], default="all",
+    p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "cavity", "batch", "conductance"],
+                   default="all",
                    help="solve timings: all legs, siam only, none, or one leg (the two-orbital stationary state "
                         "with GMRES-DR, the cavity stationary state and PSD, the 512-instance batch) for profiling")
     p.add_argument("--calib", action="store_true",
@@ -367,6 +368,48 @@ def cavity_spectrum_benchmark(api, wl):
     return out
 
 
+def conductance_benchmark(api, wl):
+    """Differential conductance of the Anderson impurity of Example 1
+    (eps = -5, U = 10, Gamma = 1, W = 10, T = 0.5, 7 Pade terms per lead and
+    spin, tier 4) with importance pruning at 1e-7 (49,713 ADOs per bias
+    point): 21 bias points Phi in [0, 4] (mu_L = -mu_R = Phi / 2) solved as
+    one batch of stationary states, the current from lead L (eq:last) per
+    point, G = dI/dPhi by central differences; and the current at Phi = 2 of
+    the unpruned hierarchy (396,607 ADOs) for the pruning error."""
+    import numpy as np
+    import torch
+    phis = np.linspace(0.0, 4.0, 21)
+    t0 = time.perf_counter()
+    cfgs = [wl.siam(eps=-5.0, U=10.0, Gamma=1.0, W=10.0, T=0.5, mus=(p / 2, -p / 2), n_exp=7, n_max=4) for p in phis]
+    hs = [api.Hierarchy(c["H"], c["baths"], 0, 4, parity_op=c["parity_op"], importance_threshold=1e-7) for c in cfgs]
+    t_build = time.perf_counter() - t0
+    b = api.Batch(hs)
+    (x, reps), t = _timed(lambda: b.steady_state(tol=1e-9, restart=30, max_iter=3000, precond="jacobi", fallback=1,
+                                                 mode="fp64", allow_not_converged=True))
+    (cur, t_cur) = _timed(lambda: b.currents(x, [0, 1]))
+    I = np.array([c.real for c in cur])
+    G = np.gradient(I, phis)
+    _progress(f"conductance: {len(phis)} bias points x {hs[0].N} ADOs, stationary states in {t:.2f} s")
+    c = cfgs[10]
+    hf = api.Hierarchy(c["H"], c["baths"], 0, 4, parity_op=c["parity_op"])
+    (xf, rf), tf = _timed(lambda: api.steady_state(hf, tol=1e-9, restart=30, max_iter=3000, precond="jacobi"))
+    If = api.current(hf, xf, [0, 1]).real
+    _progress(f"conductance: unpruned hierarchy ({hf.N} ADOs) at Phi = 2 in {tf:.2f} s")
+    out = {"n_bias": len(phis), "phi": phis.round(3).tolist(), "n_ado_pruned": hs[0].N, "n_ado_full": hf.N,
+           "importance_threshold": 1e-7, "build_seconds": round(t_build, 3), "steady_seconds": round(t, 4),
+           "current_seconds": round(t_cur, 4), "converged": int(sum(r["status"] == 0 for r in reps)),
+           "max_iterations": int(max(r["iterations"] for r in reps)),
+           "current_L": I.round(8).tolist(), "conductance_dI_dPhi": G.round(8).tolist(),
+           "full_at_phi_2": {"current_L": round(If, 10), "steady_seconds": round(tf, 4),
+                             "iterations": rf["iterations"],
+                             "pruned_rel_diff": round(abs(I[10] - If) / abs(If), 6)}}
+    b.close()
+    for h in hs:
+        h.close()
+    hf.close()
+    return out
+
+
 def deflated_steady_benchmark(api, wl):
     """The two-orbital tier-4 stationary state with GMRES-DR(20, 6) alone."""
     cfg = wl.two_orbital_anderson()
@@ -389,6 +432,8 @@ def solve_benchmarks(which):
         return cavity_spectrum_benchmark(api, wl)
     if which == "batch":
         return {"batch_512_instances": batch_benchmark(api, wl)}
+    if which == "conductance":
+        return {"siam_example1_conductance": conductance_benchmark(api, wl)}
     siam_train = []
     for s in range(4):
         z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(4))
@@ -402,6 +447,7 @@ def solve_benchmarks(which):
                                                             "fp64", (20, 60), 100, restart_none=60, deflated=(20, 6))
         out["two_orbital_tier4_dos"] = dos_benchmark(api, wl, wl.two_orbital_anderson(), sample=0)
         out["batch_512_instances"] = batch_benchmark(api, wl)
+        out["siam_example1_conductance"] = conductance_benchmark(api, wl)
     return out
 
 

@@ -512,6 +512,12 @@ class Batch:
             out.append(v[a:b].view(h.N, h.d, h.d))
         return out
 
+    def currents(self, x, lead, stream=None):
+        """Electronic current (eq:last) from the lead `lead` (bath record
+        indices, the same in every instance) of every instance of the FP64
+        batch vector x."""
+        return [current(h, v, lead, stream=stream) for h, v in zip(self.members, self.split(x))]
+
     def apply(self, x, y=None, border=0, stream=None):
         import torch
         if y is None:

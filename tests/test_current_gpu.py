@@ -80,3 +80,24 @@ def test_interacting_current_is_conserved_on_the_gpu():
     assert rep["status"] == 0
     IL, IR = api.current(lm, x, [0, 1]), api.current(lm, x, [2, 3])
     assert IL.real > 0 and abs(IL + IR) <= 1e-9 * abs(IL), (IL, IR)
+
+
+def test_bias_sweep_in_one_batch_matches_landauer():
+    """A bias sweep (mu_L = -mu_R = Phi / 2) solved as one batch of stationary
+    states: every current against the Landauer integral at U = 0, and the
+    differential conductance dI/dPhi (central differences) against the same
+    differences of the Landauer currents."""
+    torch = _torch()
+    from paper_2306_07522_amd import api
+    phis = np.linspace(0.0, 3.0, 7)
+    cfgs = [wl.resonant_level(eps=0.5, mus=(p / 2, -p / 2), n_exp=3, T=0.5, n_max=2) for p in phis]
+    hs = [api.Hierarchy(c["H"], c["baths"], 0, 2, parity_op=c["parity_op"]) for c in cfgs]
+    b = api.Batch(hs)
+    x, reps = b.steady_state(tol=1e-12, restart=30, max_iter=3000, precond="block", fallback=1)
+    assert all(r["status"] == 0 for r in reps), reps
+    I = np.array([c.real for c in b.currents(x, [0])])
+    ref = np.array([ob.landauer_current(0.5, 2.0, 10.0, (p / 2, -p / 2), 0.5, 3) for p in phis])
+    assert np.abs(I - ref).max() <= 1e-9 * np.abs(ref).max(), (I, ref)
+    G, Gref = np.gradient(I, phis), np.gradient(ref, phis)
+    assert np.abs(G - Gref).max() <= 1e-8 * np.abs(Gref).max()
+    assert abs(I[0]) <= 1e-11 and np.all(np.diff(I) > 0)
