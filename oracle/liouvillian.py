@@ -93,14 +93,18 @@ def _pf(parity: int) -> int:
 class OracleHEOM:
     """Sparse HEOMLS for given H, baths, truncation and parity."""
 
-    def __init__(self, H, baths, m_max, n_max, parity=+1, ferm_perm=None, importance_threshold=0.0):
+    def __init__(self, H, baths, m_max, n_max, parity=+1, ferm_perm=None, importance_threshold=0.0, lindblad=()):
         """ferm_perm: optional relabelling of the fermionic exponents (new
         position i holds old exponent ferm_perm[i]); used to check that
         physical results do not depend on the exponent order.
         importance_threshold > 0: leave out the ADOs of eq:importance below
         it (levels m > 1 or n > 1); terms that reach a left-out ADO are
-        dropped like those beyond the tier cutoff."""
+        dropped like those beyond the tier cutoff.
+        lindblad: jump operators F; every ADO gets the Lindbladian of
+        eq:Lindbladian, F [.] F^dagger - 1/2 {F^dagger F, .}, beside its own
+        terms (the ADO space does not grow)."""
         self.H = np.asarray(H, dtype=np.complex128)
+        self.lindblad = [np.asarray(F, dtype=np.complex128) for F in lindblad]
         self.d = self.H.shape[0]
         self.bos, self.ferm = flatten_baths(baths)
         self.ferm_rank = ferm_importance_rank([len(r["eta_p"]) for r in baths if r["kind"] != "boson"])
@@ -180,6 +184,15 @@ class OracleHEOM:
         out.append((a, -1j, self._pre(Hk, self.H)))
         out.append((a, 1j, self._post(Hk, self.H)))
         out.append((a, -decay, None))
+        # eq:Lindbladian for every jump operator F
+        for k, F in enumerate(self.lindblad):
+            Fd = F.conj().T
+            key = ("L", k)
+            if key not in self._cache:
+                self._cache[key] = (spre(F) @ spost(Fd)).tocoo()
+            out.append((a, 1.0, self._cache[key]))
+            out.append((a, -0.5, self._pre(("LL", k), Fd @ F)))
+            out.append((a, -0.5, self._post(("LL", k), Fd @ F)))
         # -i sum_{q' not in q} A_{q'} rho_{j|[q', q]}
         if n < hier.Lf:
             for qp in range(len(self.ferm)):

@@ -1,0 +1,70 @@
+"""Pins of the oracle's Lindbladian (eq:Lindbladian), F [.] F^dagger -
+1/2 {F^dagger F, .} added to every ADO.
+
+* Two-level decay (F = sqrt(gamma) sigma_-, no baths): populations decay as
+  e^{-gamma t}, coherences as e^{-(i omega + gamma/2) t} (exact exponential of
+  the 4 x 4 matrix).
+* Damped oscillator in a truncated Fock space (F1 = sqrt(kappa (n+1)) a,
+  F2 = sqrt(kappa n) a^dagger): the stationary state is the thermal
+  distribution p_k ~ (n / (n + 1))^k, exactly also under truncation
+  (detailed balance between neighbouring levels).
+* With baths, the Lindbladian keeps the trace of rho_0 (the trace functional
+  stays a left null vector of M in the even sector), and it leaves the ADO
+  count alone.
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from oracle import exponents as ox
+from oracle import solvers as osv
+from oracle.liouvillian import OracleHEOM, from_blocks, to_blocks
+from paper_2306_07522_amd import workloads as wl
+
+
+def test_two_level_decay_closed_form():
+    w, g = 1.3, 0.4
+    H = np.diag([w / 2, -w / 2]).astype(complex)          # basis (e, g)
+    sm = np.array([[0, 0], [1, 0]], dtype=complex)         # sigma_-: e -> g
+    om = OracleHEOM(H, [], 0, 0, lindblad=[np.sqrt(g) * sm])
+    assert om.N == 1
+    M = om.assemble().toarray()
+    rho0 = np.array([[0.7, 0.2 - 0.1j], [0.2 + 0.1j, 0.3]])
+    for t in (0.5, 2.0):
+        rho = to_blocks(sla.expm(M * t) @ from_blocks(rho0[None]), 1, 2)[0]
+        assert abs(rho[0, 0] - 0.7 * np.exp(-g * t)) < 1e-13
+        assert abs(rho[1, 1] - (1 - 0.7 * np.exp(-g * t))) < 1e-13
+        assert abs(rho[0, 1] - (0.2 - 0.1j) * np.exp(-(1j * w + g / 2) * t)) < 1e-13
+
+
+def test_thermal_oscillator_stationary_state():
+    n_f, w, kappa, nbar = 9, 1.0, 0.05, 0.7
+    a = np.diag(np.sqrt(np.arange(1, n_f)), 1).astype(complex)
+    H = w * a.conj().T @ a
+    F = [np.sqrt(kappa * (nbar + 1)) * a, np.sqrt(kappa * nbar) * a.conj().T]
+    om = OracleHEOM(H, [], 0, 0, lindblad=F)
+    rho = to_blocks(osv.steady_state(om.assemble(), om.d), 1, n_f)[0]
+    p = (nbar / (nbar + 1)) ** np.arange(n_f)
+    p /= p.sum()
+    assert np.abs(rho - np.diag(p)).max() < 1e-12
+
+
+def test_lindblad_with_baths_keeps_trace_and_ado_count():
+    cfg = wl.spin_boson()
+    recs = ox.exponent_records(cfg["baths"])
+    sz = np.diag([1.0, -1.0]).astype(complex)
+    sm = np.array([[0, 0], [1, 0]], dtype=complex)
+    om0 = OracleHEOM(cfg["H"], recs, cfg["m_max"], 0)
+    om = OracleHEOM(cfg["H"], recs, cfg["m_max"], 0, lindblad=[0.3 * sm, 0.2 * sz])
+    assert om.N == om0.N
+    M = om.assemble()
+    d = om.d
+    trace_rows = [i + i * d for i in range(d)]           # column-stacked (i, i) of ADO 0
+    t = np.asarray(M[trace_rows, :].sum(axis=0)).ravel()
+    assert np.abs(t).max() < 1e-14
+    # and the Lindblad part is exactly what was added
+    D = (om.assemble() - om0.assemble()).toarray()[: d * d, : d * d]
+    L = np.zeros((4, 4), complex)
+    for F in (0.3 * sm, 0.2 * sz):
+        Fd = F.conj().T
+        L += np.kron(Fd.T, F) - 0.5 * np.kron(np.eye(2), Fd @ F) - 0.5 * np.kron((Fd @ F).T, np.eye(2))
+    assert np.abs(D - L).max() < 1e-15
