@@ -147,6 +147,19 @@ heom_status heom_build_hierarchy(int32_t d, const double *H, int32_t n_baths, co
 heom_status heom_build_hierarchy_pruned(int32_t d, const double *H, int32_t n_baths, const heom_bath *baths,
                                         int32_t m_max, int32_t n_max, int32_t parity, const double *parity_op,
                                         double importance_threshold, heom_hier **out);
+/* Lindbladian add-on (eq:Lindbladian and the construction paragraph around
+ * it): every ADO of h additionally evolves under
+ *   sum_k J(F_k)[X],  J(F)[X] = F X F^dagger - 1/2 {F^dagger F, X},
+ * which describes extra, Markovian environments without adding ADOs.  F:
+ * host, n_ops matrices of d x d complex (row-major, interleaved re/im),
+ * copied; rates go into the operators (F = sqrt(rate) L).  n_ops = 0 removes
+ * them.  With a parity operator given at build, each F must commute with
+ * it.  Every apply (heom_apply*, heom_propagate, heom_steady, heom_spectrum)
+ * includes the term; the preconditioners ignore it.  The device tables are
+ * uploaded again on the next use.  Errors: HEOM_ERR_ARG (NULL, non-finite,
+ * parity-odd F), HEOM_ERR_UNSUPPORTED (d > 32).  A hierarchy with a
+ * Lindbladian cannot join a batch. */
+heom_status heom_hierarchy_set_lindblad(heom_hier *h, int32_t n_ops, const double *F);
 void heom_free(heom_hier *h);
 heom_status heom_hierarchy_info(const heom_hier *h, heom_info *out);
 

@@ -98,6 +98,7 @@ SIGNATURES = {
     "heom_batch_info": (heom_status, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), i32p, i32p]),
     "heom_batch_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp]),
     "heom_batch_tune": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, dp, vp]),
+    "heom_hierarchy_set_lindblad": (heom_status, [vp, C.c_int32, dp]),
     "heom_current": (heom_status, [vp, vp, C.c_int32, i32p, dp, vp]),
     "heom_precondition": (heom_status, [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, C.c_int32, vp]),
     "heom_batch_workspace_size": (heom_status, [vp, C.POINTER(heom_solver_opts), C.POINTER(C.c_size_t)]),

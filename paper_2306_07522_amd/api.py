@@ -120,7 +120,7 @@ def _devptr(t):
 class Hierarchy:
     """Handle of heom_build_hierarchy: ADO list, neighbour tables, operators."""
 
-    def __init__(self, H, baths, m_max, n_max, parity=+1, parity_op=None, importance_threshold=0.0):
+    def __init__(self, H, baths, m_max, n_max, parity=+1, parity_op=None, importance_threshold=0.0, lindblad=()):
         lb = lib()
         H = _c128(H)
         d = H.shape[0]
@@ -149,6 +149,18 @@ class Hierarchy:
         self.Kb = info.n_bos_exp
         self.Kf = info.n_ferm_exp
         self.parity = parity
+        if len(lindblad):
+            self.set_lindblad(lindblad)
+
+    def set_lindblad(self, ops):
+        """Jump operators F_k (eq:Lindbladian): every ADO also evolves under
+        sum_k F_k X F_k^dagger - 1/2 {F_k^dagger F_k, X}; rates go into F_k."""
+        ops = [_c128(F) for F in ops]
+        if ops:
+            arr = np.ascontiguousarray(np.stack(ops)).view(np.float64)
+            L.check(self._lib.heom_hierarchy_set_lindblad(self._h, len(ops), arr.ctypes.data_as(L.dp)))
+        else:
+            L.check(self._lib.heom_hierarchy_set_lindblad(self._h, 0, None))
 
     @property
     def handle(self):

@@ -250,7 +250,7 @@ static heom_status launch_rk4_small_T(Hier &h, void *x, double dt, int64_t steps
   return HEOM_OK;
 }
 
-bool rk4_small_fits(const Hier &h) { return h.N * (int64_t)h.d * h.d <= 1024; }
+bool rk4_small_fits(const Hier &h) { return h.N * (int64_t)h.d * h.d <= 1024 && h.lind.empty(); }
 
 heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t steps, int64_t save_every,
                              int64_t step0, int64_t n_saves, void *traj, hipStream_t s) {
@@ -348,7 +348,8 @@ static heom_status run_plan(Hier &h, int precision, const ApplyArgs &a, const Pl
 
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s) {
   HEOM_TRY(check_apply(h, precision, a));
-  return run_plan(h, precision, a, h.dev.base, s);
+  HEOM_TRY(run_plan(h, precision, a, h.dev.base, s));
+  return launch_lindblad(h, precision, a, s);
 }
 
 heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n_chunks, hipStream_t s) {
@@ -362,7 +363,8 @@ heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n
     if (n_chunks < 1) n_chunks = 1;
   }
   HEOM_TRY(ensure_tiled_plan(h, n_chunks));
-  return run_plan(h, precision, a, h.dev.tiled, s);
+  HEOM_TRY(run_plan(h, precision, a, h.dev.tiled, s));
+  return launch_lindblad(h, precision, a, s);
 }
 
 }  // namespace heom

@@ -903,6 +903,12 @@ extern "C" {
 heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch **out) {
   if (!out || n_inst <= 0 || !inst) return fail(HEOM_ERR_ARG, "batch_create: bad arguments");
   *out = nullptr;
+  for (int s = 0; s < n_inst; ++s) {  // argument checks before any device work
+    if (!inst[s]) return fail(HEOM_ERR_ARG, "batch_create: NULL instance");
+    const Hier &h = *inst[s]->impl;
+    if (h.d > 16) return fail(HEOM_ERR_UNSUPPORTED, "batch_create: instances need d <= 16");
+    if (!h.lind.empty()) return fail(HEOM_ERR_UNSUPPORTED, "batch_create: instances with a Lindbladian are not batched");
+  }
   std::unique_ptr<heom_batch> b(new heom_batch());
   b->S = n_inst;
   b->inst.assign(inst, inst + n_inst);
@@ -915,9 +921,7 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
   std::vector<double> cost(n_inst);
   constexpr size_t kLdsMax = 64 * 1024;
   for (int s = 0; s < n_inst; ++s) {
-    if (!inst[s]) return fail(HEOM_ERR_ARG, "batch_create: NULL instance");
     Hier &h = *inst[s]->impl;
-    if (h.d > 16) return fail(HEOM_ERR_UNSUPPORTED, "batch_create: instances need d <= 16");
     HEOM_TRY(ensure_device(h));
     const DeviceTables &D = h.dev;
     b->off[s + 1] = b->off[s] + h.N * (int64_t)h.d * h.d;

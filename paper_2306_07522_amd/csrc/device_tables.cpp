@@ -32,7 +32,7 @@ void free_device(Hier &h) {
   (void)hipSetDevice(D.device);
   void *ptrs[] = {D.decay64, D.decay32, D.ell_cnt, D.ell_col, D.op_slots, D.ell_val64, D.ell_val32,
                   D.coef_op, D.coef64, D.coef32, D.hdiag, D.hdiag32, D.lev, D.c_meta, D.c_col, D.c_val64, D.c_val32,
-                  D.ueig, D.eval};
+                  D.ueig, D.eval, D.lind_f, D.lind_g};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_plan(D.base);
@@ -155,6 +155,22 @@ heom_status ensure_device(Hier &h) {
       if (f.gamma.real() > 0 && (dmin == 0.0 || f.gamma.real() < dmin)) dmin = f.gamma.real();
     h.block_delta = dmin > 0 ? dmin : 1.0;
   }
+  // Lindblad jump operators and G = sum_k F_k^dagger F_k
+  std::vector<double2> lf, lg;
+  if (!h.lind.empty()) {
+    const int d = h.d;
+    std::vector<cd> G((size_t)d * d, cd(0));
+    for (const auto &F : h.lind) {
+      for (int e = 0; e < d * d; ++e) lf.push_back(make_double2(F[e].real(), F[e].imag()));
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          cd acc(0);
+          for (int l = 0; l < d; ++l) acc += std::conj(F[(size_t)l * d + i]) * F[(size_t)l * d + j];
+          G[(size_t)i * d + j] += acc;
+        }
+    }
+    for (const cd &z : G) lg.push_back(make_double2(z.real(), z.imag()));
+  }
   std::vector<int32_t> meta(3 * L.n_ops);
   for (int o = 0; o < L.n_ops; ++o) { meta[3 * o] = L.c_off[o]; meta[3 * o + 1] = L.c_ns[o]; meta[3 * o + 2] = L.c_real[o]; }
   std::vector<double2> cv64(L.c_val.size());
@@ -205,6 +221,8 @@ heom_status ensure_device(Hier &h) {
       (st = upload(&D.lev, h.lev.data(), sizeof(int2) * N, tot)) ||
       (st = upload(&D.ueig, ue.data(), sizeof(double2) * ue.size(), tot)) ||
       (st = upload(&D.eval, Ev.data(), sizeof(double) * Ev.size(), tot)) ||
+      (!lf.empty() && (st = upload(&D.lind_f, lf.data(), sizeof(double2) * lf.size(), tot))) ||
+      (!lg.empty() && (st = upload(&D.lind_g, lg.data(), sizeof(double2) * lg.size(), tot))) ||
       (st = upload(&D.c_meta, meta.data(), sizeof(int32_t) * meta.size(), tot)) ||
       (st = upload(&D.c_col, L.c_col.data(), sizeof(int32_t) * L.c_col.size(), tot)) ||
       (st = upload(&D.c_val64, cv64.data(), sizeof(double2) * cv64.size(), tot)) ||

@@ -259,6 +259,7 @@ heom_status build_hier(int d, const double *Hp, int n_baths, const heom_bath *ba
   std::vector<cd> P;
   if (parity_op) {
     P = read_mat(parity_op, d);
+    h->parity_op = P;
     auto c = matmul(P, h->H, d), e = matmul(h->H, P, d);
     for (int i = 0; i < d * d; ++i) c[i] -= e[i];
     if (maxabs(c) > 1e-12 * std::max(1.0, maxabs(h->H))) return fail(HEOM_ERR_ARG, "H is not parity-even");

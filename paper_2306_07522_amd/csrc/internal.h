@@ -88,6 +88,8 @@ struct DeviceTables {
   float2 *hdiag32 = nullptr;
   double2 *ueig = nullptr;      // [d][d] row-major eigenvectors of H (H = U diag(E) U^H)
   double *eval = nullptr;       // [d] eigenvalues of H, ascending
+  double2 *lind_f = nullptr;    // [n_lind][d][d] Lindblad jump operators, row-major
+  double2 *lind_g = nullptr;    // [d][d] sum_k F_k^dagger F_k
   int32_t *c_meta = nullptr;    // [n_ops][3] (off, ns, real) of the compact ELL
   int32_t *c_col = nullptr;
   double2 *c_val64 = nullptr;
@@ -112,6 +114,9 @@ struct Hier {
   std::vector<BosExp> bexp;
   std::vector<FermExp> fexp;
   std::vector<int> bath_kind;  // per input bath record: HEOM_BOSON or HEOM_FERMION
+  std::vector<cd> parity_op;   // d*d row-major, empty when none was given
+  // Lindbladian add-on (eq:Lindbladian): jump operators, each d*d row-major
+  std::vector<std::vector<cd>> lind;
   std::vector<std::vector<cd>> ops;  // ops[0] = H
   // ADOs
   int64_t N = 0;
@@ -161,6 +166,9 @@ bool rk4_small_fits(const Hier &h);
 heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t steps, int64_t save_every,
                              int64_t step0, int64_t n_saves, void *traj, hipStream_t s);
 heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n_chunks, hipStream_t s);
+// y += sum_k J(F_k)[x (+ kc k)] on every ADO (after the apply proper); no-op without jump operators
+heom_status launch_lindblad(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
+constexpr int kLindbladMaxD = 32;
 
 }  // namespace heom
 

@@ -87,6 +87,28 @@ def test_argument_errors_are_reported():
         api.exponents_lorentz(1.0, 10.0, 0.0, -1.0, 3)                # negative temperature
 
 
+def test_lindblad_argument_errors_are_reported():
+    """heom_hierarchy_set_lindblad rejects parity-odd and non-finite jump
+    operators, and a hierarchy with a Lindbladian cannot join a batch (all
+    before any device work)."""
+    api = _api()
+    from paper_2306_07522_amd._lib import HeomError
+    cfg = wl.siam(n_max=1, n_exp=2)
+    h = api.Hierarchy(cfg["H"], cfg["baths"], 0, 1, parity_op=cfg["parity_op"])
+    d_up = cfg["dops"][0]
+    with pytest.raises(HeomError, match="parity-even"):
+        h.set_lindblad([d_up])                      # odd: mixes the parity sectors
+    bad = np.zeros((4, 4), complex)
+    bad[0, 0] = np.nan
+    with pytest.raises(HeomError, match="non-finite"):
+        h.set_lindblad([bad])
+    h.set_lindblad([0.3 * d_up.T @ d_up])           # dephasing of the up level: even
+    other = api.Hierarchy(cfg["H"], cfg["baths"], 0, 1, parity_op=cfg["parity_op"])
+    with pytest.raises(HeomError, match="Lindbladian"):
+        api.Batch([h, other])
+    h.set_lindblad([])                              # removed again
+
+
 def test_current_argument_errors_are_reported():
     """heom_current rejects leads it cannot read before touching the device."""
     import ctypes as C
