@@ -116,7 +116,7 @@ def charge_cavity(eps=-3.0, wc=1.0, g=0.5, n_photon=10, lam=0.01, gamma=0.1, T=0
     H = eps * nD + wc * A.T @ A + g * nD @ (A + A.T)
     baths = [drude_lorentz_bath(A + A.T, lam, gamma, T, n_bexp)]
     baths += [lorentz_lead(D, Gamma, W, mu, T, n_fexp) for mu in mus]
-    return dict(name="charge_cavity", d=2 * n_photon, H=H.astype(np.complex128), baths=baths,
+    return dict(name="charge_cavity", d=2 * n_photon, H=H.astype(np.complex128), baths=baths, wc=wc,
                 m_max=m_max, n_max=n_max, aop=A.astype(np.complex128), dops=[D],
                 parity_op=np.kron(fermion_parity(1), Ic), omegas=2.0 * np.arange(1, 1025) / 1024,
                 dt=0.01, t_final=200.0)
