@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "b5b3a7e19b077d1d", "bytes": 6_754_132_674},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "eea3e58cddcaf0db", "bytes": 6_753_627_138},
 }
 
 
