@@ -233,6 +233,13 @@ class OracleHEOM:
                 out.append((b, -1j * c, S))
         return out
 
+    def drive_superop(self, V):
+        """-i[V, .] on every ADO (block diagonal): the part of the first line
+        of eq:HEOM that a term f(t) V of a time-dependent H_s(t) adds."""
+        V = np.asarray(V, dtype=np.complex128)
+        blk = (-1j * (spre(V) - spost(V))).tocsr()
+        return sp.kron(sp.identity(self.N, format="csr"), blk, format="csr")
+
     def assemble(self, rows=None, shift=0.0):
         """CSR matrix of M + shift*I (column-stacked blocks, oracle order).
 

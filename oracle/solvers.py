@@ -41,6 +41,30 @@ def rk4(M, x0, dt, n_steps, save_every=0, d=None):
     return x, traj
 
 
+def rk4_driven(M0, drives, f, x0, t0, dt, n_steps):
+    """RK4 on dx/dt = M(t) x with a time-dependent system Hamiltonian
+    H_s(t) = H + sum_k f_k(t) V_k (the paper allows H_s(t) in the dynamics):
+    M(t) = M0 + sum_k f_k(t) D_k with D_k = -i[V_k, .] on every ADO (see
+    OracleHEOM.drive_superop).  f(t) returns the real coefficients f_k(t);
+    the stages use the times t, t + dt/2, t + dt/2, t + dt."""
+    x = np.array(x0, dtype=np.complex128)
+
+    def M(t):
+        c = f(t)
+        return M0 + sum(ck * Dk for ck, Dk in zip(c, drives))
+
+    t = t0
+    for _ in range(n_steps):
+        Ma, Mb, Mc = M(t), M(t + 0.5 * dt), M(t + dt)
+        k1 = Ma @ x
+        k2 = Mb @ (x + 0.5 * dt * k1)
+        k3 = Mb @ (x + 0.5 * dt * k2)
+        k4 = Mc @ (x + dt * k3)
+        x = x + (dt / 6.0) * (k1 + 2 * k2 + 2 * k3 + k4)
+        t += dt
+    return x
+
+
 def bordered_matrix(M, d):
     """Replace the row of element (0,0) of ADO 0 by the trace row."""
     M = sp.lil_matrix(M)
