@@ -235,6 +235,26 @@ heom_status heom_propagate(heom_hier *h, int32_t precision, void *x_dev, double 
                            int64_t save_every, void *rho0_traj_dev, int32_t graph_steps, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Time-dependent system Hamiltonian H_s(t) = H + sum_k f_k(t) V_k in RK4
+ * (the paper allows H_s(t) in the dynamics; "Package architecture").  As
+ * heom_propagate (same x_dev, save_every, traj_dev and workspace, whose size
+ * is heom_workspace_size(HEOM_OP_PROPAGATE)), starting at time t0; every
+ * RK4 stage adds -i sum_k f_k(t_stage) [V_k, X] to each ADO, with the stage
+ * times t, t + dt/2, t + dt/2, t + dt.  V: host, n_drive (1..8) Hermitian
+ * d x d complex matrices (row-major, interleaved), copied; with a parity
+ * operator given at build each V_k must commute with it.  f(t, coef, ctx)
+ * writes the n_drive real coefficients at time t; it is called on the host,
+ * four times per step, before the stage's kernels are enqueued.  Steps run
+ * eagerly (no graph; hierarchies of any size take the general kernels).
+ * Synchronises the stream before returning.  Errors: HEOM_ERR_ARG (bad
+ * arguments, non-Hermitian or parity-odd V, workspace too small),
+ * HEOM_ERR_NAN (a non-finite coefficient), HEOM_ERR_UNSUPPORTED (d > 32). */
+typedef void (*heom_drive_fn)(double t, double *coef, void *ctx);
+heom_status heom_propagate_driven(heom_hier *h, int32_t precision, void *x_dev, double t0, double dt,
+                                  int64_t n_steps, int64_t save_every, void *rho0_traj_dev, int32_t n_drive,
+                                  const double *V, heom_drive_fn f, void *ctx, void *ws, size_t ws_bytes,
+                                  void *stream);
+
 /* ------------------------------------------------------------------------
  * Linear solves (stationary state and spectra)
  * ---------------------------------------------------------------------- */

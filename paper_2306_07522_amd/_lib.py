@@ -8,6 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libheom.so")
 
 heom_status = C.c_int32
+heom_drive_fn = C.CFUNCTYPE(None, C.c_double, C.POINTER(C.c_double), C.c_void_p)
 vp = C.c_void_p
 dp = C.POINTER(C.c_double)
 i32p = C.POINTER(C.c_int32)
@@ -98,6 +99,8 @@ SIGNATURES = {
     "heom_batch_info": (heom_status, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), i32p, i32p]),
     "heom_batch_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp]),
     "heom_batch_tune": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, dp, vp]),
+    "heom_propagate_driven": (heom_status, [vp, C.c_int32, vp, C.c_double, C.c_double, C.c_int64, C.c_int64, vp,
+                                            C.c_int32, dp, heom_drive_fn, vp, vp, C.c_size_t, vp]),
     "heom_hierarchy_set_lindblad": (heom_status, [vp, C.c_int32, dp]),
     "heom_current": (heom_status, [vp, vp, C.c_int32, i32p, dp, vp]),
     "heom_precondition": (heom_status, [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, C.c_int32, vp]),

@@ -299,6 +299,34 @@ def propagate(h, x, dt, n_steps, save_every=0, graph_steps=0, stream=None, ws=No
     return traj
 
 
+def propagate_driven(h, x, dt, n_steps, drives, f, t0=0.0, save_every=0, stream=None, ws=None):
+    """RK4 in place with H_s(t) = H + sum_k f(t)[k] drives[k]; f is a Python
+    callable t -> sequence of len(drives) real coefficients.  Returns the
+    trajectory of ADO 0 when save_every > 0."""
+    import torch
+    prec = _precision_of(x)
+    V = [_c128(v) for v in drives]
+    arr = np.ascontiguousarray(np.stack(V)).view(np.float64)
+    traj = None
+    if save_every:
+        traj = torch.empty((n_steps // save_every, h.d, h.d), dtype=x.dtype, device=x.device)
+    if ws is None:
+        ws = _workspace(h, L.HEOM_OP_PROPAGATE, None)
+    nd = len(V)
+
+    def cb(t, out, _ctx):
+        c = f(t)
+        for i in range(nd):
+            out[i] = float(c[i])
+
+    fn = L.heom_drive_fn(cb)                      # kept alive for the duration of the call
+    L.check(lib().heom_propagate_driven(h.handle, prec, _devptr(x), float(t0), float(dt), int(n_steps),
+                                        int(save_every), _devptr(traj) if traj is not None else None, nd,
+                                        arr.ctypes.data_as(L.dp), fn, None, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream_ptr(stream)))
+    return traj
+
+
 def steady_residual(h, x, r=None, stream=None):
     """r = e_0 - B x on the device (B the stationary-state operator)."""
     import torch
