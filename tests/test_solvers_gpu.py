@@ -299,3 +299,49 @@ def test_steady_deflated_weak_cavity_vs_oracle():
     x, rep = api.steady_state(lm, tol=1e-12, precond="block", restart=20, deflate=6, max_iter=600)
     assert rep["status"] == 0, rep
     assert rel_err(x.cpu().numpy()[perm], xs) <= 1e-9
+
+
+# ---------------------------------------------------------------- full sizes, sampled oracle rows
+def _sampled_steady_residual(om, xo, per_tier, seed):
+    """b - B x on a seeded sample of block rows of the oracle's bordered
+    operator (every tier represented, ADO 0 included), B x from the oracle's
+    assembled rows applied to the library's solution (oracle order)."""
+    rng = np.random.default_rng(seed)
+    lev = np.array([len(j) + len(q) for j, q in om.hier.ados])
+    rows = [0]
+    for t in range(1, lev.max() + 1):
+        cand = np.nonzero(lev == t)[0]
+        rows += rng.choice(cand, min(per_tier, len(cand)), replace=False).tolist()
+    d = om.d
+    y = (om.assemble(rows=rows) @ from_blocks(xo)).reshape(len(rows), d, d).transpose(0, 2, 1)
+    y[0, 0, 0] = np.trace(xo[0])                      # the trace row of the bordered system
+    b = np.zeros_like(y)
+    b[0, 0, 0] = 1.0
+    return np.linalg.norm((b - y).ravel())
+
+
+def test_full_size_two_orbital_steady_state_on_sampled_oracle_rows():
+    """Two-orbital tier 4 (213,053 ADOs) with GMRES-DR(20, 6): the solution
+    satisfies the oracle's bordered equations on sampled rows."""
+    torch, api = _torch(), _api()
+    cfg = wl.two_orbital_anderson()
+    om, lm = oracle_model(cfg), library_model(cfg, parity_op=cfg["parity_op"])
+    perm = oracle_to_library_perm(om, lm)
+    x, rep = api.steady_state(lm, tol=1e-9, precond="none", restart=20, deflate=6, max_iter=3000)
+    assert rep["status"] == 0 and rep["true_residual"] <= 1e-9, rep
+    xo = x.cpu().numpy()[perm]
+    assert _sampled_steady_residual(om, xo, 80, 7) <= 2e-9
+    rho = xo[0]
+    assert abs(np.trace(rho) - 1.0) <= 1e-12 and np.abs(rho - rho.conj().T).max() <= 1e-9
+
+
+def test_full_size_cavity_steady_state_on_sampled_oracle_rows():
+    """Charge cavity (3,165 ADOs of 20 x 20) with the block preconditioner."""
+    torch, api = _torch(), _api()
+    cfg = wl.charge_cavity()
+    om, lm = oracle_model(cfg), library_model(cfg, parity_op=cfg["parity_op"])
+    perm = oracle_to_library_perm(om, lm)
+    x, rep = api.steady_state(lm, tol=1e-10, precond="block", restart=60, max_iter=3000)
+    assert rep["status"] == 0, rep
+    xo = x.cpu().numpy()[perm]
+    assert _sampled_steady_residual(om, xo, 60, 11) <= 2e-10
