@@ -224,3 +224,38 @@ def test_apply_pruned_hierarchy(name, th, parity):
     full = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=parity)
     assert lm.N == om.N < full.N
     _parity_check(cfg, parity=parity, seeds=(0, 1), om=om, lm=lm)
+
+
+@pytest.mark.parametrize("name,R", [("cavity", 13), ("two_orbital", 20), ("cavity", 2), ("random_d2", 300)])
+def test_apply_multi_rhs_column_counts(name, R):
+    """Several right-hand sides at column counts that do not divide the
+    workgroup (d = 20 with 13 and 2 columns, d = 16 with 20, d = 2 with 300),
+    FP64 and FP32, with per-column shifts and through the tiled plan."""
+    torch = _torch()
+    if name == "cavity":
+        cfg = wl.charge_cavity(n_photon=10, n_bexp=2, n_fexp=2, m_max=1, n_max=1)
+    elif name == "two_orbital":
+        cfg = wl.two_orbital_anderson(n_max=2)
+    else:
+        cfg = _random_cfg(5, 2, 2, 2, 2, 2)
+    om, lm = oracle_model(cfg), library_model(cfg)
+    perm = oracle_to_library_perm(om, lm)
+    rng = np.random.default_rng(R)
+    shifts = rng.standard_normal(R) + 1j * rng.standard_normal(R)
+    xo = wl.random_vector(rng, om.N, om.d, n_rhs=R)
+    xl = np.empty_like(xo)
+    xl[perm] = xo
+    M = om.assemble()
+    yo = np.stack([to_blocks(M @ from_blocks(xo[..., r]) + shifts[r] * from_blocks(xo[..., r]), om.N, om.d)
+                   for r in range(R)], axis=-1)
+    y = lm.apply(torch.from_numpy(xl).cuda(), shift=torch.from_numpy(shifts).cuda(), n_rhs=R).cpu().numpy()
+    assert rel_err(y[perm], yo) <= FP64_TOL
+    x32 = xl.astype(np.complex64)
+    xo32 = x32.astype(np.complex128)[perm]
+    yo32 = np.stack([to_blocks(M @ from_blocks(xo32[..., r]) + shifts[r] * from_blocks(xo32[..., r]), om.N, om.d)
+                     for r in range(R)], axis=-1)
+    y32 = lm.apply(torch.from_numpy(x32).cuda(), shift=torch.from_numpy(shifts.astype(np.complex64)).cuda(),
+                   n_rhs=R).cpu().numpy()
+    assert rel_err(y32[perm].astype(np.complex128), yo32) <= FP32_TOL
+    yt = lm.apply(torch.from_numpy(xl).cuda(), shift=torch.from_numpy(shifts).cuda(), n_rhs=R, tiled=3).cpu().numpy()
+    assert rel_err(yt[perm], yo) <= FP64_TOL
