@@ -46,10 +46,11 @@ MEASURED_TRAFFIC = {
 
 
 def _apply_source_sha():
-    """Hash of the apply kernels' sources (the launch code and the per-wave task)."""
+    """Hash of the apply kernels' sources (the launch code, the per-wave task,
+    and the table builder that sets the task order)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("apply.hip", "apply_wave.h"):
+    for name in ("apply.hip", "apply_wave.h", "device_tables.cpp"):
         with open(os.path.join(ROOT, "paper_2306_07522_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
