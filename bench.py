@@ -171,7 +171,7 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
                                                      mode=mode, max_iter=20000, allow_not_converged=True))
     del x_0
     _progress(f"{cfg['name']} N={h.N} steady, GMRES without preconditioner: {r0['iterations']} iterations, {t0:.2f} s")
-    rec_dr = None
+    rec_dr, rec_dr32 = None, None
     if deflated:
         (x_d, rd), td = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=deflated[0],
                                                          deflate=deflated[1], mode=mode, max_iter=20000,
@@ -180,6 +180,14 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
         rec_dr = dict(_solve_record(rd, td), restart=deflated[0], deflate=deflated[1])
         _progress(f"{cfg['name']} N={h.N} steady, GMRES-DR({deflated[0]}, {deflated[1]}) without preconditioner: "
                   f"{rd['iterations']} iterations, {td:.2f} s")
+        # the same in FP32 with FP64 iterative refinement to the 1e-8 true residual
+        (x_d, rd32), td32 = _timed(lambda: api.steady_state(h, tol=1e-8, precond="none", restart=deflated[0],
+                                                             deflate=deflated[1], mode="fp32_ir", max_iter=20000,
+                                                             allow_not_converged=True))
+        del x_d
+        rec_dr32 = dict(_solve_record(rd32, td32), restart=deflated[0], deflate=deflated[1], mode="fp32_ir")
+        _progress(f"{cfg['name']} N={h.N} steady, GMRES-DR({deflated[0]}, {deflated[1]}) FP32 + FP64 refinement: "
+                  f"{rd32['iterations']} iterations, {td32:.2f} s")
     (x_p, rp), tp = _timed(lambda: api.steady_state(h, tol=1e-8, precond="jacobi", restart=restart, mode=mode,
                                                      max_iter=20000, allow_not_converged=True))
     del x_p
@@ -196,12 +204,13 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
     net.close()
     _progress(f"{cfg['name']} N={h.N} steady, NN FGMRES: {rn['iterations']} iterations, {tn:.2f} s, "
               f"fell back {rn['fell_back']}")
-    plain = [(t0, r0), (tp, rp)] + ([(rec_dr["seconds"], rd)] if rec_dr else [])
+    plain = [(t0, r0), (tp, rp)] + ([(rec_dr["seconds"], rd), (rec_dr32["seconds"], rd32)] if rec_dr else [])
     best = min([t for t, r in plain if r["status"] == 0], default=None)
     out = {"n_ado": h.N, "d": h.d, "restart": restart, "restart_none": restart_none or restart, "mode": mode,
            "nn_max_iter": cap,
            "plain_none": _solve_record(r0, t0), "plain_jacobi": _solve_record(rp, tp),
-           "plain_none_deflated": rec_dr, "best_plain_seconds": round(best, 4) if best else None,
+           "plain_none_deflated": rec_dr, "plain_none_deflated_fp32_ir": rec_dr32,
+           "best_plain_seconds": round(best, 4) if best else None,
            "nn_fgmres": _solve_record(rn, tn), "network": {"hidden": hidden, **info},
            "nn_speedup_vs_jacobi": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None,
            "nn_speedup_vs_best_plain": round(best / tn, 4) if best and tn > 0 and rn["status"] == 0 else None}
