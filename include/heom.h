@@ -300,14 +300,20 @@ typedef struct {
                              its residual is <= 0.1, else from zero; the
                              report sums both attempts                     */
   int32_t use_x0;         /* 1: x_dev holds the initial guess                 */
-  int32_t deflate;        /* heom_steady only: 0 = plain restarts; k > 0 =
-                             deflated restarting (GMRES-DR, Morgan 2002):
-                             each restart keeps the k harmonic Ritz vectors
-                             of smallest harmonic Ritz value and the
-                             residual, so slow modes of the operator stay
-                             in the Krylov space.  1 <= k <= 31,
+  int32_t deflate;        /* 0 = plain restarts; k > 0 = deflated restarts,
+                             so that slow modes of the operator stay in
+                             the Krylov space.  heom_steady: GMRES-DR
+                             (Morgan 2002), each restart keeps the k
+                             harmonic Ritz vectors of smallest harmonic
+                             Ritz value and the residual.  heom_spectrum
+                             in HEOM_SOLVE_SHIFTED mode: thick
+                             (Krylov-Schur) restarts of the multi-shift
+                             FOM, each full cycle keeps the Schur vectors
+                             of the k Ritz values of M nearest the negated
+                             unconverged shifts -i(+-omega) and the common
+                             residual direction.  1 <= k <= 31,
                              k <= restart - 2, precond not HEOM_PREC_NN;
-                             other entry points reject k != 0            */
+                             other entry points and modes reject k != 0 */
 } heom_solver_opts;
 
 typedef struct {

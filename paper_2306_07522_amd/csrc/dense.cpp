@@ -48,16 +48,9 @@ void rot_cols(std::vector<cd> &A, int lda, int i, int r0, int r1, const Rot &g) 
 
 }  // namespace
 
-bool eig_general(int n, const std::vector<cd> &A, std::vector<cd> &w, std::vector<cd> &vecs) {
-  w.assign(n, cd(0));
-  vecs.assign((size_t)n * n, cd(0));
-  if (n <= 0) return true;
-  std::vector<cd> H(A.begin(), A.begin() + (size_t)n * n);
-  std::vector<cd> Z((size_t)n * n, cd(0));
-  for (int i = 0; i < n; ++i) Z[i + (size_t)i * n] = 1.0;
+void hessenberg_reduce(int n, std::vector<cd> &H, std::vector<cd> &Z) {
   auto h = [&](int i, int j) -> cd & { return H[i + (size_t)j * n]; };
-
-  // Householder reduction to upper Hessenberg form: H <- U^H H U, Z <- Z U
+  // Householder reflections I - 2 v v^H on rows/columns j+1..n-1
   std::vector<cd> v(n);
   for (int j = 0; j + 2 < n; ++j) {
     double xn = 0.0;
@@ -95,6 +88,15 @@ bool eig_general(int n, const std::vector<cd> &A, std::vector<cd> &w, std::vecto
     }
     for (int i = j + 2; i < n; ++i) h(i, j) = 0.0;
   }
+}
+
+bool schur_complex(int n, const std::vector<cd> &A, std::vector<cd> &H, std::vector<cd> &Z) {
+  H.assign(A.begin(), A.begin() + (size_t)n * n);
+  Z.assign((size_t)n * n, cd(0));
+  for (int i = 0; i < n; ++i) Z[i + (size_t)i * n] = 1.0;
+  if (n <= 1) return true;
+  auto h = [&](int i, int j) -> cd & { return H[i + (size_t)j * n]; };
+  hessenberg_reduce(n, H, Z);
 
   // implicitly shifted QR on the active window [lo, hi]
   double anorm = 0.0;
@@ -140,6 +142,46 @@ bool eig_general(int n, const std::vector<cd> &A, std::vector<cd> &w, std::vecto
       rot_cols(Z, n, k, 0, n, g);
     }
   }
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 1; i < n; ++i) h(i, j) = 0.0;
+  return true;
+}
+
+void schur_reorder(int n, std::vector<cd> &T, std::vector<cd> &Z, const std::vector<char> &sel) {
+  auto t = [&](int i, int j) -> cd & { return T[i + (size_t)j * n]; };
+  std::vector<char> flag(sel.begin(), sel.begin() + n);
+  int next = 0;  // first position not yet holding a selected eigenvalue
+  for (int i = 0; i < n; ++i) {
+    if (!flag[i]) continue;
+    // bubble the eigenvalue at i up to position next
+    for (int q = i - 1; q >= next; --q) {
+      // swap the diagonal entries a = T(q,q), b = T(q+1,q+1): the plane
+      // rotation that maps the eigenvector (t_q,q+1, b - a) of the 2 x 2
+      // block for b onto e_1 makes T(q,q) = b and T(q+1,q) = 0
+      const cd a = t(q, q), b = t(q + 1, q + 1);
+      const Rot g = make_rot(t(q, q + 1), b - a);
+      rot_rows(T, n, q, q, n, g);
+      rot_cols(T, n, q, 0, q + 2, g);
+      rot_cols(Z, n, q, 0, n, g);
+      t(q + 1, q) = 0.0;
+      t(q, q) = b;
+      t(q + 1, q + 1) = a;
+      std::swap(flag[q], flag[q + 1]);
+    }
+    ++next;
+  }
+}
+
+bool eig_general(int n, const std::vector<cd> &A, std::vector<cd> &w, std::vector<cd> &vecs) {
+  w.assign(n, cd(0));
+  vecs.assign((size_t)n * n, cd(0));
+  if (n <= 0) return true;
+  std::vector<cd> H, Z;
+  if (!schur_complex(n, A, H, Z)) return false;
+  auto h = [&](int i, int j) -> cd & { return H[i + (size_t)j * n]; };
+  double anorm = 0.0;
+  for (const cd &z : A) anorm = std::max(anorm, std::abs(z));
+  const double eps = std::numeric_limits<double>::epsilon();
 
   for (int i = 0; i < n; ++i) w[i] = h(i, i);
   // eigenvectors of the triangular T, then through Z

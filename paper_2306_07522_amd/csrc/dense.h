@@ -18,6 +18,21 @@ using cd = std::complex<double>;
 // iteration did not converge.
 bool eig_general(int n, const std::vector<cd> &A, std::vector<cd> &w, std::vector<cd> &vecs);
 
+// Unitary reduction to upper Hessenberg form by Householder reflections:
+// H (n x n, in place) <- Q^H H Q and Z <- Z Q.
+void hessenberg_reduce(int n, std::vector<cd> &H, std::vector<cd> &Z);
+
+// Complex Schur form A = Z T Z^H (T upper triangular with the eigenvalues on
+// its diagonal, Z unitary): Hessenberg reduction, then the shifted QR
+// iteration.  Returns false if the QR iteration did not converge.
+bool schur_complex(int n, const std::vector<cd> &A, std::vector<cd> &T, std::vector<cd> &Z);
+
+// Reorder a Schur form (T, Z) in place so that the diagonal entries flagged
+// in sel[0..n) come first, in their present order, by unitary swaps of
+// neighbouring diagonal entries; Z T Z^H is unchanged and the leading k
+// columns of Z then span the invariant subspace of the k flagged eigenvalues.
+void schur_reorder(int n, std::vector<cd> &T, std::vector<cd> &Z, const std::vector<char> &sel);
+
 // Eigen-decomposition of a Hermitian n x n matrix A = U diag(E) U^H by
 // cyclic complex Jacobi rotations (orthonormal U also for degenerate
 // eigenvalues); E ascending.  Returns false if the sweeps did not converge.

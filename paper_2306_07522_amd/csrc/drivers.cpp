@@ -441,7 +441,8 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
   if (!even || !x_ss_dev || !op || !omega || !out_host || n_omega < 0) return fail(HEOM_ERR_ARG, "spectrum: NULL argument");
   HEOM_TRY(check_opts(o));
   if (kind != 0 && kind != 1) return fail(HEOM_ERR_ARG, "spectrum: kind must be 0 (DOS) or 1 (PSD)");
-  if (o->deflate != 0) return fail(HEOM_ERR_UNSUPPORTED, "spectrum: deflated restarting is for the stationary state");
+  if (o->deflate != 0 && o->mode != HEOM_SOLVE_SHIFTED)
+    return fail(HEOM_ERR_UNSUPPORTED, "spectrum: thick restarts are for the multi-shift mode only");
   if (kind == 0 && !odd) return fail(HEOM_ERR_ARG, "spectrum: the density of states needs the odd-parity hierarchy");
   Hier &he = *even->impl;
   Hier &hs = kind == 0 ? *odd->impl : he;

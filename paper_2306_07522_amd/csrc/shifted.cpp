@@ -10,6 +10,16 @@
 // so the next cycle restarts every shift from the same vector with its own
 // scalar weight (restarted FOM for shifted systems, Simoncini 2003).
 //
+// Thick restarts (deflate = k > 0) keep, besides that vector, the Schur
+// vectors V_m Z_k of the k Ritz values of M nearest the negated shifts that
+// are still active (the eigenvalues that stall those shifts).  With
+// H_m Z_k = Z_k T_k (reordered complex Schur form of the projected matrix)
+// the kept space satisfies the shift-invariant relation
+//   M (V_m Z_k) = (V_m Z_k) T_k + v_{m+1} (h_{m+1,m} e_m^T Z_k),
+// so Arnoldi continues from v_{m+1}, every shift's residual stays parallel to
+// the last basis vector, and each cycle solves (H + sigma_k) y = gamma_k e_k
+// with the full projected matrix H (Krylov-Schur restarting, Stewart 2001).
+//
 // The spectrum only needs the trace readout Tr[O x_k,0] of ADO 0, which is
 // linear in x_k.  Each Arnoldi vector v_j therefore contributes the scalar
 // Tr[O v_j,0] once, and no solution vector is ever stored: the memory is the
@@ -22,6 +32,7 @@
 #include <cstring>
 
 #include "blas.h"
+#include "dense.h"
 #include "internal.h"
 #include "solvers.h"
 
@@ -35,15 +46,14 @@ struct ShiftSystem {
   int col_r = 0;          // readout Tr[ops[col_r] x_0]
 };
 
-// Solve (H + sigma I) y = g0 e_1 for the upper-Hessenberg k x k matrix H
+// Solve (H + sigma I) y = rhs for the upper-Hessenberg k x k matrix H
 // (column-major, leading dimension ld) by Gaussian elimination with partial
 // pivoting between neighbouring rows.  Returns false when singular.
-bool hessenberg_solve(const std::vector<cd> &H, int ld, int k, cd sigma, cd g0, std::vector<cd> &y) {
-  std::vector<cd> A((size_t)k * k), rhs(k, cd(0));
+bool hessenberg_solve(const std::vector<cd> &H, int ld, int k, cd sigma, std::vector<cd> rhs, std::vector<cd> &y) {
+  std::vector<cd> A((size_t)k * k);
   for (int c = 0; c < k; ++c)
     for (int r = 0; r < k; ++r) A[(size_t)c * k + r] = (r <= c + 1) ? H[(size_t)c * ld + r] : cd(0);
   for (int i = 0; i < k; ++i) A[(size_t)i * k + i] += sigma;
-  rhs[0] = g0;
   for (int i = 0; i + 1 < k; ++i) {
     // rows i and i+1 only (Hessenberg)
     if (std::abs(A[(size_t)i * k + i + 1]) > std::abs(A[(size_t)i * k + i])) {
@@ -80,7 +90,8 @@ size_t shifted_bytes(const Hier &h, const heom_solver_opts &o) {
   const int nprobe = 3;
   int64_t nch = std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
   return (size_t)(m + 1) * vec + (size_t)(nprobe + 2) * vec + (size_t)(2 * m + 3) * nch * sizeof(double2) +
-         4 * (size_t)(m + 3) * sizeof(double2) + 2 * (size_t)h.d * h.d * 16 + 16 * 1024;
+         4 * (size_t)(m + 3) * sizeof(double2) + 2 * (size_t)h.d * h.d * 16 +
+         (size_t)m * kRotateMax * sizeof(double2) + 16 * 1024;
 }
 
 // One right-hand side, all shifts: readout[k] = Tr[ops[col_r] x_k,0].
@@ -104,7 +115,10 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
   double2 *partial = (double2 *)ws.take((size_t)(2 * m + 3) * nch * sizeof(double2));
   double2 *hdev = (double2 *)ws.take(2 * (size_t)(m + 3) * sizeof(double2));
   double2 *sdev = (double2 *)ws.take(2 * sizeof(double2));
-  if (!V || !b || !r || !partial || !hdev || !sdev) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
+  const int kdef = o.deflate;  // 0: plain restarts from the residual direction
+  double2 *zdev = kdef > 0 ? (double2 *)ws.take((size_t)m * kRotateMax * sizeof(double2)) : nullptr;
+  if (!V || !b || !r || !partial || !hdev || !sdev || (kdef > 0 && !zdev))
+    return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
   for (double2 *p : xp)
     if (!p) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
   PinnedBuf pin;
@@ -153,12 +167,75 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
   int iters = 0, cycles = 0;
   int64_t applies = 0;
   double worst_est = 1.0;
-  while (true) {
-    // Arnoldi on M (no shift)
+  int p = 0;  // basis columns kept by a thick restart; column p is the residual direction
+  // Krylov-Schur restart after a full cycle of kk columns: Schur form of the
+  // projected matrix, the kdef Ritz values nearest the negated active shifts
+  // moved to the front, V_k <- V_kk Z_k, v_kk moved to column kdef; the
+  // projected matrix, the readout weights t and the Gram matrix G follow Z.
+  auto thick_restart = [&](int kk, cd hlast) -> heom_status {
+    std::vector<cd> Hk((size_t)kk * kk), T, Z;
+    for (int c = 0; c < kk; ++c)
+      for (int i = 0; i < kk; ++i) Hk[(size_t)c * kk + i] = H[(size_t)c * (m + 1) + i];
+    if (!schur_complex(kk, Hk, T, Z)) {  // no Schur form: restart plainly
+      HEOM_HIP_CHECK(hipMemcpyAsync(V, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
+      p = 0;
+      return HEOM_OK;
+    }
+    std::vector<double> dist(kk, HUGE_VAL);
+    for (int i = 0; i < kk; ++i) {
+      const cd th = T[(size_t)i * kk + i];
+      for (int k = 0; k < K; ++k)
+        if (active[k]) dist[i] = std::min(dist[i], std::abs(th + sys.sigma[k]));
+    }
+    std::vector<int> order(kk);
+    for (int i = 0; i < kk; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return dist[a] < dist[b]; });
+    std::vector<char> sel(kk, 0);
+    for (int i = 0; i < kdef; ++i) sel[order[i]] = 1;
+    schur_reorder(kk, T, Z, sel);
+    // V[:, 0..kdef) <- V[:, 0..kk) Z[:, 0..kdef), then v_kk to column kdef
+    std::vector<double2> zh((size_t)kk * kdef);
+    for (int c = 0; c < kdef; ++c)
+      for (int i = 0; i < kk; ++i) {
+        const cd z = Z[(size_t)c * kk + i];
+        zh[(size_t)c * kk + i] = make_double2(z.real(), z.imag());
+      }
+    HEOM_HIP_CHECK(hipMemcpyAsync(zdev, zh.data(), sizeof(double2) * zh.size(), hipMemcpyHostToDevice, s));
+    HEOM_TRY(basis_rotate<double>(V, n, kk, zdev, kdef, n, s));
+    HEOM_HIP_CHECK(hipMemcpyAsync(V + (size_t)kdef * n, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
+    // projected matrix: T_k on top, h_{kk,kk-1} e_{kk-1}^T Z_k below it
+    std::vector<cd> tn(kdef), Gn((size_t)kdef * kdef);
+    for (int c = 0; c < kdef; ++c) {
+      cd a(0);
+      for (int i = 0; i < kk; ++i) a += t[i] * Z[(size_t)c * kk + i];
+      tn[c] = a;
+      for (int e = 0; e < kdef; ++e) {  // (Z^H G Z)(e, c)
+        cd g(0);
+        for (int i = 0; i < kk; ++i) {
+          cd gz(0);
+          for (int q = 0; q < kk; ++q) gz += G[(size_t)q * (m + 1) + i] * Z[(size_t)c * kk + q];
+          g += std::conj(Z[(size_t)e * kk + i]) * gz;
+        }
+        Gn[(size_t)c * kdef + e] = g;
+      }
+    }
     std::fill(H.begin(), H.end(), cd(0));
-    int kk = 0;
+    for (int c = 0; c < kdef; ++c) {
+      for (int i = 0; i <= c; ++i) H[(size_t)c * (m + 1) + i] = T[(size_t)c * kk + i];
+      H[(size_t)c * (m + 1) + kdef] = hlast * Z[(size_t)c * kk + kk - 1];
+      t[c] = tn[c];
+      for (int e = 0; e < kdef; ++e) G[(size_t)c * (m + 1) + e] = Gn[(size_t)c * kdef + e];
+    }
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    p = kdef;
+    return HEOM_OK;
+  };
+  while (true) {
+    // Arnoldi on M (no shift), continued from column p
+    std::fill(H.begin() + (size_t)p * (m + 1), H.end(), cd(0));
+    int kk = p;
     bool breakdown = false;
-    for (int j = 0; j < m; ++j) {
+    for (int j = p; j < m; ++j) {
       double2 *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
       HEOM_TRY(readv(vj, t[j]));
       ApplyArgs a;
@@ -222,39 +299,86 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
       if (breakdown || iters >= o.max_iter) break;
     }
     ++cycles;
-    // per shift: (H + sigma) y = gamma e_1, readout += t . y, new residual weight
+    // per shift: (H + sigma) y = gamma e_p, readout += t . y, new residual
+    // weight.  After a thick restart H is no longer Hessenberg (row p holds
+    // h_{m+1,m} e_m^T Z_k); one unitary reduction H = Q Hh Q^H per cycle
+    // turns every shift's system into a Hessenberg one with right-hand side
+    // gamma Q^H e_p, and the readout and last-component weights into t^T Q
+    // and e_kk^T Q.
     const cd hlast = H[(size_t)(kk - 1) * (m + 1) + kk];
-    std::vector<cd> y;
+    const bool hess = p <= 1;
+    std::vector<cd> Hh, Q, qp(kk), tq(kk), ql(kk);
+    if (hess) {
+      for (int j = 0; j < kk; ++j) {
+        qp[j] = j == p ? cd(1) : cd(0);
+        tq[j] = t[j];
+        ql[j] = j == kk - 1 ? cd(1) : cd(0);
+      }
+    } else {
+      Hh.resize((size_t)kk * kk);
+      Q.assign((size_t)kk * kk, cd(0));
+      for (int c = 0; c < kk; ++c) {
+        Q[(size_t)c * kk + c] = 1.0;
+        for (int i = 0; i < kk; ++i) Hh[(size_t)c * kk + i] = H[(size_t)c * (m + 1) + i];
+      }
+      hessenberg_reduce(kk, Hh, Q);
+      for (int j = 0; j < kk; ++j) {
+        qp[j] = std::conj(Q[(size_t)j * kk + p]);
+        ql[j] = Q[(size_t)j * kk + kk - 1];
+        cd a(0);
+        for (int i = 0; i < kk; ++i) a += t[i] * Q[(size_t)j * kk + i];
+        tq[j] = a;
+      }
+    }
+    std::vector<cd> y, rhs(kk);
     bool any = false;
     worst_est = 0;
     std::vector<std::vector<cd>> yprobe(nprobe);
     for (int k = 0; k < K; ++k) {
       if (!active[k]) continue;
-      if (!hessenberg_solve(H, m + 1, kk, sys.sigma[k], gamma[k], y))
+      for (int j = 0; j < kk; ++j) rhs[j] = gamma[k] * qp[j];
+      if (!(hess ? hessenberg_solve(H, m + 1, kk, sys.sigma[k], rhs, y) : hessenberg_solve(Hh, kk, kk, sys.sigma[k], rhs, y)))
         return fail(HEOM_ERR_SINGULAR, "spectrum: singular projected shifted system");
-      cd acc(0);
-      for (int j = 0; j < kk; ++j) acc += y[j] * t[j];
+      cd acc(0), last(0);
+      for (int j = 0; j < kk; ++j) {
+        acc += y[j] * tq[j];
+        last += y[j] * ql[j];
+      }
       readout[k] += acc;
-      for (int p = 0; p < nprobe; ++p)
-        if (probe_k[p] == k) yprobe[p] = y;
-      gamma[k] = breakdown ? cd(0) : -hlast * y[kk - 1];
+      for (int q = 0; q < nprobe; ++q)
+        if (probe_k[q] == k) {
+          yprobe[q] = y;
+          if (!hess) {  // coefficients in the basis V: Q y
+            for (int i = 0; i < kk; ++i) {
+              cd v(0);
+              for (int j = 0; j < kk; ++j) v += Q[(size_t)j * kk + i] * y[j];
+              yprobe[q][i] = v;
+            }
+          }
+        }
+      gamma[k] = breakdown ? cd(0) : -hlast * last;
       const double est = std::abs(gamma[k]) / bnorm;
       if (est <= o.tol) active[k] = 0;
       else any = true;
       worst_est = std::max(worst_est, est);
     }
     // probes: x_p += V y_p
-    for (int p = 0; p < nprobe; ++p) {
-      if (yprobe[p].empty()) continue;
+    for (int q = 0; q < nprobe; ++q) {
+      if (yprobe[q].empty()) continue;
       std::vector<double2> yh(kk);
-      for (int j = 0; j < kk; ++j) yh[j] = make_double2(yprobe[p][j].real(), yprobe[p][j].imag());
+      for (int j = 0; j < kk; ++j) yh[j] = make_double2(yprobe[q][j].real(), yprobe[q][j].imag());
       HEOM_HIP_CHECK(hipMemcpyAsync(hdev, yh.data(), sizeof(double2) * kk, hipMemcpyHostToDevice, s));
-      HEOM_TRY(basis_update<double>(V, n, kk, hdev, xp[p], n, 1, 1.0, s));
+      HEOM_TRY(basis_update<double>(V, n, kk, hdev, xp[q], n, 1, 1.0, s));
       HEOM_HIP_CHECK(hipStreamSynchronize(s));
     }
     if (!any || breakdown || iters >= o.max_iter) break;
-    // restart from the common residual direction v_{kk}
-    HEOM_HIP_CHECK(hipMemcpyAsync(V, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
+    if (kdef > 0 && kk == m) {
+      HEOM_TRY(thick_restart(kk, hlast));
+    } else {
+      // restart from the common residual direction v_{kk}
+      HEOM_HIP_CHECK(hipMemcpyAsync(V, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
+      p = 0;
+    }
   }
   // true residuals of the probes with the plain apply
   double worst_true = 0;

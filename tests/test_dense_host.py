@@ -1,6 +1,7 @@
 """Host dense linear algebra of the Krylov solvers (csrc/dense.cpp) against
 numpy: the general complex eigen-solver (harmonic Ritz pairs of deflated
-restarting), the Hermitian Jacobi eigen-solver (eigenbasis of H for the block
+restarting), the complex Schur form with reordering (thick restarts of the
+multi-shift solver), the Hermitian Jacobi eigen-solver (eigenbasis of H for the block
 preconditioner), the pivoted LU solve and the column orthonormalisation.
 
 dense.cpp is plain C++ with no HIP dependency; the test builds it with g++
@@ -46,6 +47,28 @@ int t_solve(int n, const double *a, double *x) {
   for (int i = 0; i < n; ++i) { x[2 * i] = X[i].real(); x[2 * i + 1] = X[i].imag(); }
   return 0;
 }
+int t_schur(int n, const double *a, const char *sel, double *t, double *z, int reorder) {
+  std::vector<cd> A(n * n), T, Z;
+  for (int i = 0; i < n * n; ++i) A[i] = cd(a[2 * i], a[2 * i + 1]);
+  if (!heom::schur_complex(n, A, T, Z)) return 1;
+  if (reorder) heom::schur_reorder(n, T, Z, std::vector<char>(sel, sel + n));
+  for (int i = 0; i < n * n; ++i) {
+    t[2 * i] = T[i].real(); t[2 * i + 1] = T[i].imag();
+    z[2 * i] = Z[i].real(); z[2 * i + 1] = Z[i].imag();
+  }
+  return 0;
+}
+int t_hess(int n, double *a, double *z) {
+  std::vector<cd> H(n * n), Z(n * n, cd(0));
+  for (int i = 0; i < n * n; ++i) H[i] = cd(a[2 * i], a[2 * i + 1]);
+  for (int i = 0; i < n; ++i) Z[i + i * n] = 1.0;
+  heom::hessenberg_reduce(n, H, Z);
+  for (int i = 0; i < n * n; ++i) {
+    a[2 * i] = H[i].real(); a[2 * i + 1] = H[i].imag();
+    z[2 * i] = Z[i].real(); z[2 * i + 1] = Z[i].imag();
+  }
+  return 0;
+}
 int t_orth(int rows, int cols, double *p, double tol) {
   std::vector<cd> P(rows * cols);
   for (int i = 0; i < rows * cols; ++i) P[i] = cd(p[2 * i], p[2 * i + 1]);
@@ -71,6 +94,8 @@ def dense(tmp_path_factory):
     lib.t_eigh.argtypes = [C.c_int, dp, dp, dp]
     lib.t_solve.argtypes = [C.c_int, dp, dp]
     lib.t_orth.argtypes = [C.c_int, C.c_int, dp, C.c_double]
+    lib.t_schur.argtypes = [C.c_int, dp, C.c_char_p, dp, dp, C.c_int]
+    lib.t_hess.argtypes = [C.c_int, dp, dp]
     return lib
 
 
@@ -180,3 +205,82 @@ def test_orthonormalise_columns(dense):
     for c in range(6):
         r = P[:, c] - Q @ (Q.conj().T @ P[:, c])
         assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(P[:, c])
+
+
+def _schur(lib, A, sel=None):
+    n = A.shape[0]
+    a = _colmajor(A.astype(np.complex128))
+    t = np.zeros(2 * n * n)
+    z = np.zeros(2 * n * n)
+    flags = bytes(bytearray([1 if (sel is not None and sel[i]) else 0 for i in range(n)]))
+    assert lib.t_schur(n, _ptr(a), flags, _ptr(t), _ptr(z), int(sel is not None)) == 0
+    return (t.view(np.complex128).reshape(n, n, order="F"), z.view(np.complex128).reshape(n, n, order="F"))
+
+
+@pytest.mark.parametrize("name,A", _cases(), ids=[c[0] + str(c[1].shape[0]) for c in _cases()])
+def test_schur_complex(dense, name, A):
+    """A = Z T Z^H with Z unitary and T upper triangular; diag(T) are the
+    eigenvalues."""
+    n = A.shape[0]
+    T, Z = _schur(dense, A)
+    scale = max(1.0, np.abs(A).max())
+    assert np.abs(np.tril(T, -1)).max(initial=0.0) == 0.0
+    assert np.abs(Z.conj().T @ Z - np.eye(n)).max() <= 1e-13 * n
+    assert np.abs(Z @ T @ Z.conj().T - A).max() <= 1e-13 * scale * n
+    assert _match(np.linalg.eigvals(A), np.diag(T)) <= 1e-8 * scale * n
+
+
+@pytest.mark.parametrize("n,pick", [(2, [1]), (6, [5, 2]), (20, [19, 3, 11, 7]), (30, list(range(0, 30, 3)))])
+def test_schur_reorder_moves_selected_eigenvalues_first(dense, n, pick):
+    """After reordering, the flagged eigenvalues lead the diagonal in their
+    original order, the form is still a Schur form of A, and the leading
+    columns of Z span an invariant subspace: A Z_k = Z_k T_k."""
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    T0, _ = _schur(dense, A)
+    sel = np.zeros(n, bool)
+    sel[pick] = True
+    T, Z = _schur(dense, A, sel)
+    k = len(pick)
+    want = np.diag(T0)[np.sort(pick)]
+    assert np.abs(np.diag(T)[:k] - want).max() <= 1e-12 * np.abs(A).max()
+    assert _match(np.diag(T)[k:], np.diag(T0)[~sel]) <= 1e-10 * np.abs(A).max()
+    assert np.abs(np.tril(T, -1)).max(initial=0.0) == 0.0
+    assert np.abs(Z.conj().T @ Z - np.eye(n)).max() <= 1e-13 * n
+    assert np.abs(Z @ T @ Z.conj().T - A).max() <= 1e-12 * np.abs(A).max() * n
+    Zk = Z[:, :k]
+    assert np.abs(A @ Zk - Zk @ T[:k, :k]).max() <= 1e-12 * np.abs(A).max() * n
+
+
+def test_schur_reorder_with_equal_eigenvalues(dense):
+    """Swapping equal diagonal entries is a no-op rotation, not a division by
+    zero."""
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8)))
+    A = Q @ np.diag([1.0, 1.0, 2.0, 2.0, 1.0, 3.0, 3.0, 2.0]).astype(complex) @ Q.conj().T
+    sel = np.zeros(8, bool)
+    sel[[4, 6, 7]] = True
+    T, Z = _schur(dense, A, sel)
+    assert np.all(np.isfinite(T)) and np.all(np.isfinite(Z))
+    assert np.abs(Z @ T @ Z.conj().T - A).max() <= 1e-12 * 8
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 9, 25])
+def test_hessenberg_reduce(dense, n):
+    """H <- Q^H H Q is upper Hessenberg, Q unitary, and the similarity holds;
+    an already Hessenberg input keeps its moduli (only phases change)."""
+    rng = np.random.default_rng(40 + n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    a = _colmajor(A)
+    z = np.zeros(2 * n * n)
+    dense.t_hess(n, _ptr(a), _ptr(z))
+    H = a.view(np.complex128).reshape(n, n, order="F")
+    Q = z.view(np.complex128).reshape(n, n, order="F")
+    assert np.abs(np.tril(H, -2)).max(initial=0.0) == 0.0
+    assert np.abs(Q.conj().T @ Q - np.eye(n)).max() <= 1e-13 * n
+    assert np.abs(Q @ H @ Q.conj().T - A).max() <= 1e-13 * n * np.abs(A).max()
+    Hh = np.triu(A, -1)
+    a = _colmajor(Hh)
+    dense.t_hess(n, _ptr(a), _ptr(z))
+    H2 = a.view(np.complex128).reshape(n, n, order="F")
+    assert np.allclose(np.abs(H2), np.abs(Hh), atol=1e-13 * n)

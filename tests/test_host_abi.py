@@ -146,7 +146,10 @@ def test_solver_option_errors_are_reported():
     o = api.solver_opts(deflate=4, restart=30)
     fd = C.cast(fake, L.dp)
     st = api.lib().heom_spectrum(h.handle, None, fake, 1, fd, fd, 1, fd, C.byref(o), C.byref(rep), None, 0, None)
-    assert st != 0
+    assert st != 0 and b"multi-shift" in api.lib().heom_last_error()   # thick restarts: multi-shift mode only
+    o = api.solver_opts(deflate=29, restart=30, mode="shifted", precond="none")
+    st = api.lib().heom_spectrum(h.handle, None, fake, 1, fd, fd, 1, fd, C.byref(o), C.byref(rep), None, 0, None)
+    assert st == 1 and b"deflate" in api.lib().heom_last_error()
     for p in (L.HEOM_PREC_NONE, L.HEOM_PREC_NN, 7):
         st = api.lib().heom_precondition(h.handle, L.HEOM_FP64, p, fake, C.c_void_p(512), 1, None, 0, None)
         assert st == 1 and b"precondition" in api.lib().heom_last_error()
