@@ -5,6 +5,17 @@
 
 namespace heom {
 
+// Number of chunks of the multi-dot partial sums for n elements and R
+// right-hand sides (one right-hand side: about 1,024 elements per chunk, at
+// most 8,192 chunks, so that the one-workgroup-per-chunk kernel has many
+// workgroups per compute unit)
+inline int dot_chunks(int64_t n, int R) {
+  int64_t c = R == 1 ? n / 1024 : (n * R) / (256 * 64);
+  if (c < 1) c = 1;
+  const int64_t cap = R == 1 ? 8192 : 1024;
+  if (c > cap) c = cap;
+  return (int)c;
+}
 // out[i * R + r] = conj(V_i) . w per right-hand side (partial: k * nchunk * R scratch)
 template <typename T>
 heom_status mdot(const void *V, int64_t ldv, int k, const void *w, int64_t n, int R, double2 *partial, int nchunk,
@@ -20,11 +31,23 @@ heom_status mdot2(const void *V, int64_t ldv, int k, const void *w, const void *
 template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
                          hipStream_t s, const double2 *post = nullptr);
+// X.p[p] += sum_{i < n_in} V_i Y[i + p * n_in] for p < n_acc <= kAccumMax
+// (Y: device, column-major, complex double), one read of the basis
+constexpr int kAccumMax = 4;
+struct AccumOut {
+  void *p[kAccumMax];
+};
+template <typename T>
+heom_status basis_accum(const void *V, int64_t ldv, int n_in, const double2 *Y, int n_acc, const AccumOut &X, int64_t n,
+                        hipStream_t s);
 // In-place change of basis: V_c <- sum_{i < n_in} V_i Q[i + c * n_in] for
-// c < n_out <= kRotateMax (Q: device, column-major, complex double)
+// c < n_out <= kRotateMax (Q: device, column-major, complex double); with
+// n_acc > 0 also X->p[p] += sum_i V_i Y[i + p * n_in] (p < n_acc) from the
+// same read of the basis
 constexpr int kRotateMax = 32;
 template <typename T>
-heom_status basis_rotate(void *V, int64_t ldv, int n_in, const double2 *Q, int n_out, int64_t n, hipStream_t s);
+heom_status basis_rotate(void *V, int64_t ldv, int n_in, const double2 *Q, int n_out, int64_t n, hipStream_t s,
+                         const double2 *Y = nullptr, int n_acc = 0, const AccumOut *X = nullptr);
 template <typename T>
 heom_status scale_vec(const void *w, const double2 *sc, void *out, int64_t n, int R, hipStream_t s);
 template <typename TX, typename TY>

@@ -119,6 +119,134 @@ __global__ void __launch_bounds__(256) mdot2_kernel(const typename Cplx<T>::t *_
   if (blockIdx.y == 0 && threadIdx.x == 0) partial[(int64_t)(2 * k) * nchunk + chunk] = red[2 * NI][0];
 }
 
+// The same two-vector multi-dot for k <= kWaveDotMaxK: w and u are read once
+// whatever k is.  One workgroup per chunk; each wave walks sub-blocks of
+// 64 * P elements of the chunk, holding w and u there in registers, and
+// takes the basis vectors four at a time.  The 16 per-lane values of four
+// vectors (Re and Im of conj(V_q).w and conj(V_q).u) are summed over the wave
+// by recursive halving: after exchanges at lane distances 32, 16, 8, 4 each
+// lane holds one of the 16 values summed over half, a quarter, ... of the
+// wave, and two more exchanges (2, 1) finish the sum, so lane l ends with
+// value ((l >> 2) & 15).  Each lane accumulates its value of group g in
+// acc[g] over the sub-blocks; |w|^2 stays lane-local until the end.  The
+// four waves then combine through LDS in a fixed order (deterministic).
+constexpr int kWaveDotMaxK = 64;
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256) mdot2_wave_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv,
+                                                         int k, const typename Cplx<T>::t *__restrict__ w,
+                                                         const typename Cplx<T>::t *__restrict__ u, int64_t n,
+                                                         double2 *__restrict__ partial, int nchunk) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int G = kWaveDotMaxK / 4;
+  __shared__ double red[4][G][16];
+  __shared__ double redw[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunk = blockIdx.x;
+  const int64_t e0 = n * chunk / nchunk, e1 = n * (chunk + 1) / nchunk;
+  const int ng = (k + 3) / 4;
+  double acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = 0.0;
+  double ww = 0.0;
+  for (int64_t base = e0 + (int64_t)wave * 64 * P; base < e1; base += (int64_t)4 * 64 * P) {
+    double wx[P], wy[P], ux[P], uy[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t e = base + lane + 64 * p;
+      wx[p] = wy[p] = ux[p] = uy[p] = 0.0;
+      if (e < e1) {
+        const T2 bw = w[e], bu = u[e];
+        wx[p] = bw.x; wy[p] = bw.y; ux[p] = bu.x; uy[p] = bu.y;
+        ww += wx[p] * wx[p] + wy[p] * wy[p];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g >= ng) break;
+      double v[16];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = 4 * g + c;
+        double dx = 0.0, dy = 0.0, fx = 0.0, fy = 0.0;
+        if (q < k) {
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const int64_t e = base + lane + 64 * p;
+            if (e < e1) {
+              const T2 a = V[(int64_t)q * ldv + e];
+              const double ax = a.x, ay = a.y;
+              dx += ax * wx[p] + ay * wy[p];
+              dy += ax * wy[p] - ay * wx[p];
+              fx += ax * ux[p] + ay * uy[p];
+              fy += ax * uy[p] - ay * ux[p];
+            }
+          }
+        }
+        v[4 * c] = dx; v[4 * c + 1] = dy; v[4 * c + 2] = fx; v[4 * c + 3] = fy;
+      }
+      // recursive halving: at distance 32 the lanes with bit 5 set keep
+      // values 8..15, the others 0..7, and each adds its partner's copy
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const bool hi = lane & 32;
+        const double send = hi ? v[r] : v[8 + r];
+        const double keep = hi ? v[8 + r] : v[r];
+        v[r] = keep + __shfl_xor(send, 32);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool hi = lane & 16;
+        const double send = hi ? v[r] : v[4 + r];
+        const double keep = hi ? v[4 + r] : v[r];
+        v[r] = keep + __shfl_xor(send, 16);
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const bool hi = lane & 8;
+        const double send = hi ? v[r] : v[2 + r];
+        const double keep = hi ? v[2 + r] : v[r];
+        v[r] = keep + __shfl_xor(send, 8);
+      }
+      {
+        const bool hi = lane & 4;
+        const double send = hi ? v[0] : v[1];
+        const double keep = hi ? v[1] : v[0];
+        v[0] = keep + __shfl_xor(send, 4);
+      }
+      v[0] += __shfl_xor(v[0], 2);
+      v[0] += __shfl_xor(v[0], 1);
+      acc[g] += v[0];
+    }
+  }
+  // lane l holds value j = 8 b5 + 4 b4 + 2 b3 + b2 of every group (bits of l)
+  const int j = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+  if ((lane & 3) == 0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (g < ng) red[wave][g][j] = acc[g];
+  }
+  redw[wave][lane] = ww;
+  __syncthreads();
+  // value j of group g: vector q = 4g + j / 4, component j % 4 (Re, Im of
+  // the w product, then of the u product)
+  for (int q = threadIdx.x; q < k; q += 256) {
+    const int g = q >> 2, c = q & 3;
+    double t[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      t[i] = ((red[0][g][4 * c + i] + red[1][g][4 * c + i]) + red[2][g][4 * c + i]) + red[3][g][4 * c + i];
+    partial[(int64_t)q * nchunk + chunk] = make_double2(t[0], t[1]);
+    partial[(int64_t)(k + q) * nchunk + chunk] = make_double2(t[2], t[3]);
+  }
+  if (wave == 0) {
+    double sw = ((redw[0][lane] + redw[1][lane]) + redw[2][lane]) + redw[3][lane];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
+    if (lane == 0) partial[(int64_t)(2 * k) * nchunk + chunk] = make_double2(sw, 0.0);
+  }
+}
+
 // out[i * R + r] = sum over chunks of partial: one workgroup per output,
 // each thread sums a fixed strided subset of the chunks, then a fixed-order
 // tree in LDS (deterministic)
@@ -177,34 +305,92 @@ __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T
 }
 
 // V_c <- sum_i V_i Q[i, c] for c < n_out (Q column-major, n_in x n_out,
-// n_out <= kRotateMax), in place: each thread reads all n_in entries of its
-// element before it writes any, and no other thread touches that element.
-template <typename T>
+// n_out <= MAXC <= kRotateMax), in place: each thread reads all n_in entries
+// of its element before it writes any, and no other thread touches that
+// element.  Optionally, from the same read, X_p += sum_i V_i Y[i + p n_in]
+// for p < n_acc (outputs outside V).  MAXC sizes the register accumulators.
+template <typename T, int MAXC>
 __global__ void __launch_bounds__(256) basis_rotate_kernel(typename Cplx<T>::t *V, int64_t ldv, int n_in,
-                                                           const double2 *__restrict__ Q, int n_out, int64_t n) {
+                                                           const double2 *__restrict__ Q, int n_out,
+                                                           const double2 *__restrict__ Y, int n_acc, AccumOut X,
+                                                           int64_t n) {
   using T2 = typename Cplx<T>::t;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    double ax[kRotateMax], ay[kRotateMax];
+    double ax[MAXC], ay[MAXC], bx[kAccumMax], by[kAccumMax];
 #pragma unroll
-    for (int c = 0; c < kRotateMax; ++c) {
+    for (int c = 0; c < MAXC; ++c) {
       ax[c] = 0.0;
       ay[c] = 0.0;
     }
+#pragma unroll
+    for (int p = 0; p < kAccumMax; ++p) bx[p] = by[p] = 0.0;
     for (int i = 0; i < n_in; ++i) {
       const T2 v = V[i * ldv + e];
       const double vx = v.x, vy = v.y;
 #pragma unroll
-      for (int c = 0; c < kRotateMax; ++c) {
+      for (int c = 0; c < MAXC; ++c) {
         if (c < n_out) {
           const double2 q = Q[(int64_t)c * n_in + i];
           ax[c] += vx * q.x - vy * q.y;
           ay[c] += vx * q.y + vy * q.x;
         }
       }
+#pragma unroll
+      for (int p = 0; p < kAccumMax; ++p) {
+        if (p < n_acc) {
+          const double2 q = Y[(int64_t)p * n_in + i];
+          bx[p] += vx * q.x - vy * q.y;
+          by[p] += vx * q.y + vy * q.x;
+        }
+      }
     }
 #pragma unroll
-    for (int c = 0; c < kRotateMax; ++c)
+    for (int c = 0; c < MAXC; ++c)
       if (c < n_out) V[c * ldv + e] = T2{(T)ax[c], (T)ay[c]};
+#pragma unroll
+    for (int p = 0; p < kAccumMax; ++p)
+      if (p < n_acc) {
+        T2 *xo = (T2 *)X.p[p];
+        T2 o = xo[e];
+        o.x = (T)((double)o.x + bx[p]);
+        o.y = (T)((double)o.y + by[p]);
+        xo[e] = o;
+      }
+  }
+}
+
+// X_p += sum_{i < n_in} V_i Y[i + p * n_in] for p < n_acc <= kAccumMax
+// (Y: device, column-major, complex double): several combinations of the
+// basis from one read of it.
+template <typename T>
+__global__ void __launch_bounds__(256) basis_accum_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv,
+                                                          int n_in, const double2 *__restrict__ Y, int n_acc,
+                                                          AccumOut X, int64_t n) {
+  using T2 = typename Cplx<T>::t;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double ax[kAccumMax], ay[kAccumMax];
+#pragma unroll
+    for (int p = 0; p < kAccumMax; ++p) ax[p] = ay[p] = 0.0;
+    for (int i = 0; i < n_in; ++i) {
+      const T2 v = V[i * ldv + e];
+      const double vx = v.x, vy = v.y;
+#pragma unroll
+      for (int p = 0; p < kAccumMax; ++p)
+        if (p < n_acc) {
+          const double2 q = Y[(int64_t)p * n_in + i];
+          ax[p] += vx * q.x - vy * q.y;
+          ay[p] += vx * q.y + vy * q.x;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kAccumMax; ++p)
+      if (p < n_acc) {
+        T2 *xo = (T2 *)X.p[p];
+        T2 o = xo[e];
+        o.x = (T)((double)o.x + ax[p]);
+        o.y = (T)((double)o.y + ay[p]);
+        xo[e] = o;
+      }
   }
 }
 
@@ -383,10 +569,15 @@ template <typename T>
 heom_status mdot2(const void *V, int64_t ldv, int k, const void *w, const void *u, int64_t n, double2 *partial,
                   int nchunk, double2 *out, hipStream_t s) {
   if (k <= 0) return HEOM_OK;
-  constexpr int NI = 4;
-  dim3 g(nchunk, (k + NI - 1) / NI);
-  hipLaunchKernelGGL((mdot2_kernel<T, NI>), g, dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv, k,
-                     (const typename Cplx<T>::t *)w, (const typename Cplx<T>::t *)u, n, partial, nchunk);
+  if (k <= kWaveDotMaxK) {
+    hipLaunchKernelGGL((mdot2_wave_kernel<T, 4>), dim3(nchunk), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
+                       k, (const typename Cplx<T>::t *)w, (const typename Cplx<T>::t *)u, n, partial, nchunk);
+  } else {
+    constexpr int NI = 4;
+    dim3 g(nchunk, (k + NI - 1) / NI);
+    hipLaunchKernelGGL((mdot2_kernel<T, NI>), g, dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv, k,
+                       (const typename Cplx<T>::t *)w, (const typename Cplx<T>::t *)u, n, partial, nchunk);
+  }
   const int64_t kk = 2 * (int64_t)k + 1;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)kk), dim3(256), 0, s, partial, (int)kk, nchunk, 1, out);
   HEOM_HIP_CHECK(hipGetLastError());
@@ -404,10 +595,33 @@ heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, vo
 }
 
 template <typename T>
-heom_status basis_rotate(void *V, int64_t ldv, int n_in, const double2 *Q, int n_out, int64_t n, hipStream_t s) {
+heom_status basis_rotate(void *V, int64_t ldv, int n_in, const double2 *Q, int n_out, int64_t n, hipStream_t s,
+                         const double2 *Y, int n_acc, const AccumOut *X) {
   if (n_out < 1 || n_out > kRotateMax || n_in < n_out) return fail(HEOM_ERR_ARG, "basis_rotate: bad column counts");
-  hipLaunchKernelGGL(basis_rotate_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, (typename Cplx<T>::t *)V, ldv, n_in, Q,
-                     n_out, n);
+  if (n_acc < 0 || n_acc > kAccumMax || (n_acc > 0 && (!Y || !X))) return fail(HEOM_ERR_ARG, "basis_rotate: bad outputs");
+  AccumOut xo{};
+  for (int p = 0; p < n_acc; ++p) {
+    if (!X->p[p]) return fail(HEOM_ERR_ARG, "basis_rotate: NULL output");
+    xo.p[p] = X->p[p];
+  }
+  if (n_out <= 8)
+    hipLaunchKernelGGL((basis_rotate_kernel<T, 8>), dim3(grid_for(n)), dim3(256), 0, s, (typename Cplx<T>::t *)V, ldv,
+                       n_in, Q, n_out, Y, n_acc, xo, n);
+  else
+    hipLaunchKernelGGL((basis_rotate_kernel<T, kRotateMax>), dim3(grid_for(n)), dim3(256), 0, s,
+                       (typename Cplx<T>::t *)V, ldv, n_in, Q, n_out, Y, n_acc, xo, n);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
+heom_status basis_accum(const void *V, int64_t ldv, int n_in, const double2 *Y, int n_acc, const AccumOut &X, int64_t n,
+                        hipStream_t s) {
+  if (n_acc < 1 || n_acc > kAccumMax || n_in < 1) return fail(HEOM_ERR_ARG, "basis_accum: bad column counts");
+  for (int p = 0; p < n_acc; ++p)
+    if (!X.p[p]) return fail(HEOM_ERR_ARG, "basis_accum: NULL output");
+  hipLaunchKernelGGL(basis_accum_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
+                     n_in, Y, n_acc, X, n);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -488,7 +702,10 @@ heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const
   template heom_status basis_update<T>(const void *, int64_t, int, const double2 *, void *, int64_t, int, double,  \
                                        hipStream_t, const double2 *);                                              \
   template heom_status scale_vec<T>(const void *, const double2 *, void *, int64_t, int, hipStream_t);             \
-  template heom_status basis_rotate<T>(void *, int64_t, int, const double2 *, int, int64_t, hipStream_t);            \
+  template heom_status basis_rotate<T>(void *, int64_t, int, const double2 *, int, int64_t, hipStream_t,             \
+                                       const double2 *, int, const AccumOut *);                                    \
+  template heom_status basis_accum<T>(const void *, int64_t, int, const double2 *, int, const AccumOut &, int64_t,  \
+                                      hipStream_t);                                                               \
   template heom_status jacobi<T>(const void *, void *, const Hier &, int, const double2 *, int, hipStream_t, int);  \
   template heom_status rk4_combine<T>(void *, const void *, const void *, const void *, const void *, double,      \
                                       int64_t, hipStream_t);                                                       \

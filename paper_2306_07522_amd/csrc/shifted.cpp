@@ -30,6 +30,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "blas.h"
 #include "dense.h"
@@ -40,46 +41,82 @@ namespace heom {
 
 namespace {
 
+constexpr int kMaxShiftThreads = 8;  // host threads for the per-shift projected solves
+
 struct ShiftSystem {
   std::vector<cd> sigma;  // per frequency
   int col_b = 0;          // right-hand side = ops[col_b] . x_ss
   int col_r = 0;          // readout Tr[ops[col_r] x_0]
 };
 
-// Solve (H + sigma I) y = rhs for the upper-Hessenberg k x k matrix H
+// Solves (H + sigma I) y = rhs for the upper-Hessenberg k x k matrix H
 // (column-major, leading dimension ld) by Gaussian elimination with partial
-// pivoting between neighbouring rows.  Returns false when singular.
-bool hessenberg_solve(const std::vector<cd> &H, int ld, int k, cd sigma, std::vector<cd> rhs, std::vector<cd> &y) {
-  std::vector<cd> A((size_t)k * k);
-  for (int c = 0; c < k; ++c)
-    for (int r = 0; r < k; ++r) A[(size_t)c * k + r] = (r <= c + 1) ? H[(size_t)c * ld + r] : cd(0);
-  for (int i = 0; i < k; ++i) A[(size_t)i * k + i] += sigma;
-  for (int i = 0; i + 1 < k; ++i) {
-    // rows i and i+1 only (Hessenberg)
-    if (std::abs(A[(size_t)i * k + i + 1]) > std::abs(A[(size_t)i * k + i])) {
-      for (int c = i; c < k; ++c) std::swap(A[(size_t)c * k + i], A[(size_t)c * k + i + 1]);
-      std::swap(rhs[i], rhs[i + 1]);
+// pivoting between neighbouring rows, in plain real arithmetic (the
+// projected entries are finite and moderate, so the special-case handling
+// of library complex products and quotients is not needed); the buffers are
+// kept between calls.  Returns false when singular or not finite.
+struct HessSolver {
+  std::vector<double> ar, ai, br, bi;
+  bool solve(const std::vector<cd> &H, int ld, int k, cd sigma, const std::vector<cd> &rhs, std::vector<cd> &y) {
+    ar.resize((size_t)k * k);
+    ai.resize((size_t)k * k);
+    br.resize(k);
+    bi.resize(k);
+    for (int c = 0; c < k; ++c)
+      for (int r = 0; r <= std::min(c + 1, k - 1); ++r) {  // rows below c + 1 are never read
+        const cd v = H[(size_t)c * ld + r];
+        ar[(size_t)c * k + r] = v.real();
+        ai[(size_t)c * k + r] = v.imag();
+      }
+    for (int i = 0; i < k; ++i) {
+      ar[(size_t)i * k + i] += sigma.real();
+      ai[(size_t)i * k + i] += sigma.imag();
+      br[i] = rhs[i].real();
+      bi[i] = rhs[i].imag();
     }
-    const cd p = A[(size_t)i * k + i];
-    if (p == cd(0)) return false;
-    const cd f = A[(size_t)i * k + i + 1] / p;
-    if (f != cd(0)) {
-      for (int c = i; c < k; ++c) A[(size_t)c * k + i + 1] -= f * A[(size_t)c * k + i];
-      rhs[i + 1] -= f * rhs[i];
+    for (int i = 0; i + 1 < k; ++i) {
+      // rows i and i+1 only (Hessenberg); pivot on the larger modulus
+      const size_t d0 = (size_t)i * k + i, d1 = d0 + 1;
+      if (ar[d1] * ar[d1] + ai[d1] * ai[d1] > ar[d0] * ar[d0] + ai[d0] * ai[d0]) {
+        for (int c = i; c < k; ++c) {
+          std::swap(ar[(size_t)c * k + i], ar[(size_t)c * k + i + 1]);
+          std::swap(ai[(size_t)c * k + i], ai[(size_t)c * k + i + 1]);
+        }
+        std::swap(br[i], br[i + 1]);
+        std::swap(bi[i], bi[i + 1]);
+      }
+      const double pr = ar[d0], pi = ai[d0], pn = pr * pr + pi * pi;
+      if (pn == 0.0) return false;
+      // f = A[i+1][i] / p
+      const double fr = (ar[d1] * pr + ai[d1] * pi) / pn, fi = (ai[d1] * pr - ar[d1] * pi) / pn;
+      if (fr != 0.0 || fi != 0.0) {
+        for (int c = i; c < k; ++c) {
+          const size_t u = (size_t)c * k + i;
+          ar[u + 1] -= fr * ar[u] - fi * ai[u];
+          ai[u + 1] -= fr * ai[u] + fi * ar[u];
+        }
+        br[i + 1] -= fr * br[i] - fi * bi[i];
+        bi[i + 1] -= fr * bi[i] + fi * br[i];
+      }
     }
+    y.resize(k);
+    for (int i = k - 1; i >= 0; --i) {
+      double sr = br[i], si = bi[i];
+      for (int c = i + 1; c < k; ++c) {
+        const size_t u = (size_t)c * k + i;
+        sr -= ar[u] * y[c].real() - ai[u] * y[c].imag();
+        si -= ar[u] * y[c].imag() + ai[u] * y[c].real();
+      }
+      const size_t dd = (size_t)i * k + i;
+      const double pr = ar[dd], pi = ai[dd], pn = pr * pr + pi * pi;
+      if (pn == 0.0) return false;
+      const double yr = (sr * pr + si * pi) / pn, yi = (si * pr - sr * pi) / pn;
+      if (!std::isfinite(yr) || !std::isfinite(yi)) return false;
+      y[i] = cd(yr, yi);
+    }
+    return true;
   }
-  y.assign(k, cd(0));
-  for (int i = k - 1; i >= 0; --i) {
-    cd acc = rhs[i];
-    for (int c = i + 1; c < k; ++c) acc -= A[(size_t)c * k + i] * y[c];
-    const cd p = A[(size_t)i * k + i];
-    if (p == cd(0)) return false;
-    y[i] = acc / p;
-  }
-  for (const cd &v : y)
-    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return false;
-  return true;
-}
+};
 
 }  // namespace
 
@@ -88,10 +125,10 @@ size_t shifted_bytes(const Hier &h, const heom_solver_opts &o) {
   const size_t vec = (size_t)n * 16;
   const int m = o.restart;
   const int nprobe = 3;
-  int64_t nch = std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
+  const int64_t nch = dot_chunks(n, 1);
   return (size_t)(m + 1) * vec + (size_t)(nprobe + 2) * vec + (size_t)(2 * m + 3) * nch * sizeof(double2) +
          4 * (size_t)(m + 3) * sizeof(double2) + 2 * (size_t)h.d * h.d * 16 +
-         (size_t)m * kRotateMax * sizeof(double2) + 16 * 1024;
+         (size_t)m * (kRotateMax + kAccumMax) * sizeof(double2) + 16 * 1024;
 }
 
 // One right-hand side, all shifts: readout[k] = Tr[ops[col_r] x_k,0].
@@ -111,13 +148,14 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
   const int nprobe = std::min(3, K);
   std::vector<double2 *> xp(nprobe);
   for (int p = 0; p < nprobe; ++p) xp[p] = (double2 *)ws.take(vec);
-  const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(n / (256 * 64), 1024));
+  const int nch = dot_chunks(n, 1);
   double2 *partial = (double2 *)ws.take((size_t)(2 * m + 3) * nch * sizeof(double2));
   double2 *hdev = (double2 *)ws.take(2 * (size_t)(m + 3) * sizeof(double2));
   double2 *sdev = (double2 *)ws.take(2 * sizeof(double2));
   const int kdef = o.deflate;  // 0: plain restarts from the residual direction
   double2 *zdev = kdef > 0 ? (double2 *)ws.take((size_t)m * kRotateMax * sizeof(double2)) : nullptr;
-  if (!V || !b || !r || !partial || !hdev || !sdev || (kdef > 0 && !zdev))
+  double2 *ydev = (double2 *)ws.take((size_t)m * kAccumMax * sizeof(double2));
+  if (!V || !b || !r || !partial || !hdev || !sdev || !ydev || (kdef > 0 && !zdev))
     return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
   for (double2 *p : xp)
     if (!p) return fail(HEOM_ERR_ARG, "spectrum: workspace too small");
@@ -172,12 +210,15 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
   // projected matrix, the kdef Ritz values nearest the negated active shifts
   // moved to the front, V_k <- V_kk Z_k, v_kk moved to column kdef; the
   // projected matrix, the readout weights t and the Gram matrix G follow Z.
-  auto thick_restart = [&](int kk, cd hlast) -> heom_status {
+  // The probe updates (nact columns of ydev into outs) ride on the basis read.
+  auto thick_restart = [&](int kk, cd hlast, int nact, const AccumOut &outs) -> heom_status {
     std::vector<cd> Hk((size_t)kk * kk), T, Z;
     for (int c = 0; c < kk; ++c)
       for (int i = 0; i < kk; ++i) Hk[(size_t)c * kk + i] = H[(size_t)c * (m + 1) + i];
-    if (!schur_complex(kk, Hk, T, Z)) {  // no Schur form: restart plainly
+    if (!schur_complex(kk, Hk, T, Z)) {  // no Schur form: probes, then restart plainly
+      if (nact > 0) HEOM_TRY(basis_accum<double>(V, n, kk, ydev, nact, outs, n, s));
       HEOM_HIP_CHECK(hipMemcpyAsync(V, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
       p = 0;
       return HEOM_OK;
     }
@@ -201,7 +242,7 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
         zh[(size_t)c * kk + i] = make_double2(z.real(), z.imag());
       }
     HEOM_HIP_CHECK(hipMemcpyAsync(zdev, zh.data(), sizeof(double2) * zh.size(), hipMemcpyHostToDevice, s));
-    HEOM_TRY(basis_rotate<double>(V, n, kk, zdev, kdef, n, s));
+    HEOM_TRY(basis_rotate<double>(V, n, kk, zdev, kdef, n, s, ydev, nact, &outs));
     HEOM_HIP_CHECK(hipMemcpyAsync(V + (size_t)kdef * n, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
     // projected matrix: T_k on top, h_{kk,kk-1} e_{kk-1}^T Z_k below it
     std::vector<cd> tn(kdef), Gn((size_t)kdef * kdef);
@@ -330,51 +371,97 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
         tq[j] = a;
       }
     }
-    std::vector<cd> y, rhs(kk);
-    bool any = false;
-    worst_est = 0;
+    // the shifts are independent: contiguous ranges on a few host threads
     std::vector<std::vector<cd>> yprobe(nprobe);
-    for (int k = 0; k < K; ++k) {
-      if (!active[k]) continue;
-      for (int j = 0; j < kk; ++j) rhs[j] = gamma[k] * qp[j];
-      if (!(hess ? hessenberg_solve(H, m + 1, kk, sys.sigma[k], rhs, y) : hessenberg_solve(Hh, kk, kk, sys.sigma[k], rhs, y)))
-        return fail(HEOM_ERR_SINGULAR, "spectrum: singular projected shifted system");
-      cd acc(0), last(0);
-      for (int j = 0; j < kk; ++j) {
-        acc += y[j] * tq[j];
-        last += y[j] * ql[j];
-      }
-      readout[k] += acc;
-      for (int q = 0; q < nprobe; ++q)
-        if (probe_k[q] == k) {
-          yprobe[q] = y;
-          if (!hess) {  // coefficients in the basis V: Q y
-            for (int i = 0; i < kk; ++i) {
-              cd v(0);
-              for (int j = 0; j < kk; ++j) v += Q[(size_t)j * kk + i] * y[j];
-              yprobe[q][i] = v;
+    auto run_shifts = [&](int k0, int k1, bool &any_l, double &worst_l, bool &singular_l) {
+      HessSolver hs;
+      std::vector<cd> y, rhs(kk);
+      for (int k = k0; k < k1; ++k) {
+        if (!active[k]) continue;
+        const double gr = gamma[k].real(), gi = gamma[k].imag();
+        for (int j = 0; j < kk; ++j)
+          rhs[j] = cd(gr * qp[j].real() - gi * qp[j].imag(), gr * qp[j].imag() + gi * qp[j].real());
+        if (!(hess ? hs.solve(H, m + 1, kk, sys.sigma[k], rhs, y) : hs.solve(Hh, kk, kk, sys.sigma[k], rhs, y))) {
+          singular_l = true;
+          return;
+        }
+        double axr = 0, axi = 0, lr = 0, li = 0;
+        for (int j = 0; j < kk; ++j) {
+          const double yr = y[j].real(), yi = y[j].imag();
+          axr += yr * tq[j].real() - yi * tq[j].imag();
+          axi += yr * tq[j].imag() + yi * tq[j].real();
+          lr += yr * ql[j].real() - yi * ql[j].imag();
+          li += yr * ql[j].imag() + yi * ql[j].real();
+        }
+        readout[k] += cd(axr, axi);
+        for (int q = 0; q < nprobe; ++q)
+          if (probe_k[q] == k) {
+            yprobe[q] = y;
+            if (!hess) {  // coefficients in the basis V: Q y
+              for (int i = 0; i < kk; ++i) {
+                cd v(0);
+                for (int j = 0; j < kk; ++j) v += Q[(size_t)j * kk + i] * y[j];
+                yprobe[q][i] = v;
+              }
             }
           }
+        const double hr = hlast.real(), hi = hlast.imag();
+        gamma[k] = breakdown ? cd(0) : cd(-(hr * lr - hi * li), -(hr * li + hi * lr));
+        const double est = std::abs(gamma[k]) / bnorm;
+        if (est <= o.tol) active[k] = 0;
+        else any_l = true;
+        worst_l = std::max(worst_l, est);
+      }
+    };
+    bool any = false, singular = false;
+    worst_est = 0;
+    {
+      const int nth = (int)std::min<int64_t>(kMaxShiftThreads, std::max<int64_t>(1, (int64_t)K * kk * kk / 100000));
+      std::vector<char> any_t(nth, 0), sing_t(nth, 0);
+      std::vector<double> worst_t(nth, 0.0);
+      auto body = [&](int t) {
+        bool a = false, sg = false;
+        double w = 0.0;
+        run_shifts((int)((int64_t)K * t / nth), (int)((int64_t)K * (t + 1) / nth), a, w, sg);
+        any_t[t] = a;
+        sing_t[t] = sg;
+        worst_t[t] = w;
+      };
+      std::vector<std::thread> pool;
+      for (int t = 1; t < nth; ++t) {
+        try {
+          pool.emplace_back(body, t);
+        } catch (...) {  // no thread available: this range runs here
+          body(t);
         }
-      gamma[k] = breakdown ? cd(0) : -hlast * last;
-      const double est = std::abs(gamma[k]) / bnorm;
-      if (est <= o.tol) active[k] = 0;
-      else any = true;
-      worst_est = std::max(worst_est, est);
+      }
+      body(0);
+      for (auto &th : pool) th.join();
+      for (int t = 0; t < nth; ++t) {
+        any = any || any_t[t];
+        singular = singular || sing_t[t];
+        worst_est = std::max(worst_est, worst_t[t]);
+      }
     }
-    // probes: x_p += V y_p
+    if (singular) return fail(HEOM_ERR_SINGULAR, "spectrum: singular projected shifted system");
+    // probes: x_p += V y_p, all from one read of the basis (at a thick
+    // restart, from the read that forms the new basis)
+    AccumOut outs{};
+    std::vector<double2> yh;
+    int nact = 0;
     for (int q = 0; q < nprobe; ++q) {
       if (yprobe[q].empty()) continue;
-      std::vector<double2> yh(kk);
-      for (int j = 0; j < kk; ++j) yh[j] = make_double2(yprobe[q][j].real(), yprobe[q][j].imag());
-      HEOM_HIP_CHECK(hipMemcpyAsync(hdev, yh.data(), sizeof(double2) * kk, hipMemcpyHostToDevice, s));
-      HEOM_TRY(basis_update<double>(V, n, kk, hdev, xp[q], n, 1, 1.0, s));
-      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      for (int j = 0; j < kk; ++j) yh.push_back(make_double2(yprobe[q][j].real(), yprobe[q][j].imag()));
+      outs.p[nact++] = xp[q];
     }
-    if (!any || breakdown || iters >= o.max_iter) break;
-    if (kdef > 0 && kk == m) {
-      HEOM_TRY(thick_restart(kk, hlast));
+    if (nact > 0) HEOM_HIP_CHECK(hipMemcpyAsync(ydev, yh.data(), sizeof(double2) * yh.size(), hipMemcpyHostToDevice, s));
+    const bool more = any && !breakdown && iters < o.max_iter;
+    if (more && kdef > 0 && kk == m) {
+      HEOM_TRY(thick_restart(kk, hlast, nact, outs));
     } else {
+      if (nact > 0) HEOM_TRY(basis_accum<double>(V, n, kk, ydev, nact, outs, n, s));
+      HEOM_HIP_CHECK(hipStreamSynchronize(s));
+      if (!more) break;
       // restart from the common residual direction v_{kk}
       HEOM_HIP_CHECK(hipMemcpyAsync(V, V + (size_t)kk * n, vec, hipMemcpyDeviceToDevice, s));
       p = 0;

@@ -43,13 +43,6 @@ heom_status PinnedBuf::ensure(size_t bytes) {
   return HEOM_OK;
 }
 
-static int dot_chunks(int64_t n, int R) {
-  int64_t c = (n * R) / (256 * 64);
-  if (c < 1) c = 1;
-  if (c > 1024) c = 1024;
-  return (int)c;
-}
-
 size_t gmres_bytes(int64_t n, int R, int m, bool flexible, size_t w) {
   const size_t vec = (size_t)n * R * w;
   size_t b = (size_t)(m + 1) * vec + 2 * vec + 1024;
