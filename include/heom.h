@@ -291,7 +291,8 @@ typedef struct {
                              HEOM_SOLVE_SHIFTED                               */
   double inner_tol;       /* FP32 inner tolerance for IR (default 1e-5)       */
   int32_t max_refine;     /* IR outer steps (default 20)                      */
-  int32_t rhs_chunk;      /* spectra: right-hand sides per multi-RHS solve    */
+  int32_t rhs_chunk;      /* spectra: frequencies per multi-RHS solve; 0 =
+                             automatic (heom_spectrum_chunk)               */
   const heom_nn *nn;      /* learned preconditioner for HEOM_PREC_NN          */
   int32_t fallback;       /* 1: on NN failure (NaN, max_iter, or an FP64
                              restart cycle that cuts the true residual by
@@ -328,8 +329,14 @@ typedef struct {
 } heom_solver_report;
 
 /* Defaults: restart 30, max_iter 3000, tol 1e-8, Jacobi, FP64, inner_tol
- * 1e-5, max_refine 20, rhs_chunk 64, fallback on. */
+ * 1e-5, max_refine 20, rhs_chunk 0 (automatic), fallback on. */
 void heom_default_opts(heom_solver_opts *o);
+/* Frequencies per multi-RHS solve that heom_spectrum uses with options o on
+ * hierarchy h (the odd one for a density of states): o->rhs_chunk when
+ * positive, else 1 for hierarchies of at least 2^18 elements per column
+ * (N d^2) and 16 below.  Size the workspace with n_rhs = this value for a
+ * power spectrum and twice it for a density of states.  0 for a NULL h. */
+int32_t heom_spectrum_chunk(const heom_hier *h, const heom_solver_opts *o);
 /* Device workspace (bytes) that `op` needs with options o (NULL = defaults).
  * n_rhs: for HEOM_OP_SPECTRUM the number of columns of one chunk, i.e.
  * rhs_chunk for a power spectrum and 2 rhs_chunk for a density of states;

@@ -72,6 +72,7 @@ SIGNATURES = {
     "heom_apply_steady_operator": (heom_status, [vp, C.c_int32, vp, vp, vp]),
     "heom_apply_tiled": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
     "heom_default_opts": (None, [C.POINTER(heom_solver_opts)]),
+    "heom_spectrum_chunk": (C.c_int32, [vp, C.POINTER(heom_solver_opts)]),
     "heom_workspace_size": (heom_status, [vp, C.c_int32, C.POINTER(heom_solver_opts), C.c_int64,
                                           C.POINTER(C.c_size_t)]),
     "heom_propagate": (heom_status, [vp, C.c_int32, vp, C.c_double, C.c_int64, C.c_int64, vp, C.c_int32, vp,

@@ -421,8 +421,10 @@ def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, allow_not_con
     om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
     out = np.zeros(len(om))
     k = 0 if kind == "dos" else 1
-    cols = max(1, min(o.rhs_chunk, len(om))) * (2 if k == 0 else 1)
-    ws = _workspace(odd if k == 0 else even, L.HEOM_OP_SPECTRUM, o, cols)
+    hs = odd if k == 0 else even
+    chunk = lib().heom_spectrum_chunk(hs.handle, C.byref(o))
+    cols = max(1, min(chunk, len(om))) * (2 if k == 0 else 1)
+    ws = _workspace(hs, L.HEOM_OP_SPECTRUM, o, cols)
     opm = _c128(op)
     rep = L.heom_solver_report()
     st = lib().heom_spectrum(even.handle, odd.handle if odd is not None else None, _devptr(x_ss), k, _dptr(opm),

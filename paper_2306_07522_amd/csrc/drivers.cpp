@@ -211,10 +211,25 @@ void heom_default_opts(heom_solver_opts *o) {
   o->mode = HEOM_SOLVE_FP64;
   o->inner_tol = 1e-5;
   o->max_refine = 20;
-  o->rhs_chunk = 64;
+  o->rhs_chunk = 0;  // automatic (heom_spectrum_chunk)
   o->nn = nullptr;
   o->fallback = 1;
   o->use_x0 = 0;
+}
+
+// Frequencies per multi-RHS spectrum solve when rhs_chunk is 0: one for
+// hierarchies of at least 2^18 elements per column (the one-column path
+// works on whole blocks per wave and needs no column to wait for the slowest
+// one), 16 below (launch latency dominates small systems).
+static int auto_spectrum_chunk(const Hier &h) {
+  const int64_t n = h.N * (int64_t)h.d * h.d;
+  return n >= (int64_t(1) << 18) ? 1 : 16;
+}
+
+int32_t heom_spectrum_chunk(const heom_hier *hw, const heom_solver_opts *o) {
+  if (!hw) return 0;
+  if (o && o->rhs_chunk > 0) return o->rhs_chunk;
+  return auto_spectrum_chunk(*hw->impl);
 }
 
 heom_status heom_workspace_size(const heom_hier *hw, int32_t op, const heom_solver_opts *o, int64_t n_rhs,
@@ -456,7 +471,8 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
   const int d = hs.d;
   const int64_t n = hs.N * (int64_t)d * d;
   const int per = kind == 0 ? 2 : 1;
-  const int nw_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(o->rhs_chunk > 0 ? o->rhs_chunk : 64, n_omega));
+  const int nw_chunk =
+      (int)std::max<int64_t>(1, std::min<int64_t>(o->rhs_chunk > 0 ? o->rhs_chunk : auto_spectrum_chunk(hs), n_omega));
   const int Rmax = per * nw_chunk;
   WsArena arena(ws, ws_bytes);
   double2 *opsd = (double2 *)arena.take(2 * (size_t)d * d * sizeof(double2));

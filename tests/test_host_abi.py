@@ -277,3 +277,27 @@ def test_library_pruned_ados_match_oracle():
             m |= 1 << k
         ora_sets.add(m)
     assert lib_sets == ora_sets
+
+
+def test_spectrum_chunk_rule():
+    """rhs_chunk 0 (the default) lets the library choose the frequencies per
+    spectrum solve: one for hierarchies of at least 2^18 elements per column,
+    16 below; a positive rhs_chunk is used as given."""
+    import ctypes as C
+    api = _api()
+    lib = api.lib()
+    assert api.solver_opts().rhs_chunk == 0
+    small = wl.spin_boson()
+    hs = api.Hierarchy(small["H"], small["baths"], small["m_max"], small["n_max"])
+    cav = wl.charge_cavity()
+    hc = api.Hierarchy(cav["H"], cav["baths"], cav["m_max"], cav["n_max"], parity_op=cav["parity_op"])
+    assert hc.N * hc.d * hc.d >= 1 << 18 > hs.N * hs.d * hs.d
+    o = api.solver_opts()
+    assert lib.heom_spectrum_chunk(hs.handle, C.byref(o)) == 16
+    assert lib.heom_spectrum_chunk(hc.handle, C.byref(o)) == 1
+    assert lib.heom_spectrum_chunk(hc.handle, None) == 1
+    o8 = api.solver_opts(rhs_chunk=8)
+    assert lib.heom_spectrum_chunk(hc.handle, C.byref(o8)) == 8
+    assert lib.heom_spectrum_chunk(None, C.byref(o8)) == 0
+    hs.close()
+    hc.close()
