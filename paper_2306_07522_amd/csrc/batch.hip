@@ -383,13 +383,21 @@ __global__ void __launch_bounds__(256) seg_mdot2_kernel(const typename Cplx<T>::
 // and form the twice-projected coefficients h = a + (a - G a), a = V^H w
 // (CGS2's second projection from the measured Gram matrix G = V^H V).
 // red: [(2k + 1)][S] reduced a, c, |w|^2; G: [S][ldg][ldg] column-major.
+// Also |w - V h|^2 = |w|^2 - 2 Re(h^H a) + h^H G h without another read:
+// form[s] = (that value, 1 when it cancels), post[s].x = its inverse square
+// root (0 when it cancels: the update then keeps w - V h for an explicit
+// norm), flag[s] = 1 for those instances.
 __global__ void batch_gram_kernel(double2 *__restrict__ G, const double2 *__restrict__ red, int j, int S, int ldg,
-                                  const int *__restrict__ active, double2 *__restrict__ hout) {
+                                  const int *__restrict__ active, double2 *__restrict__ hout,
+                                  double2 *__restrict__ form, double2 *__restrict__ post, int *__restrict__ flag) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const int k = j + 1;
   if (active && !active[s]) {
     for (int i = 0; i < k; ++i) hout[(int64_t)i * S + s] = make_double2(0.0, 0.0);
+    form[s] = make_double2(0.0, 0.0);
+    post[s] = make_double2(0.0, 0.0);
+    flag[s] = 0;
     return;
   }
   double2 *Gs = G + (size_t)s * ldg * ldg;
@@ -408,19 +416,43 @@ __global__ void batch_gram_kernel(double2 *__restrict__ G, const double2 *__rest
     const double2 a = red[(int64_t)i * S + s];
     hout[(int64_t)i * S + s] = make_double2(2.0 * a.x - gx, 2.0 * a.y - gy);
   }
+  const double ww = red[(int64_t)(2 * k) * S + s].x;
+  double hn2 = ww;
+  for (int i = 0; i < k; ++i) {
+    const double2 h = hout[(int64_t)i * S + s], a = red[(int64_t)i * S + s];
+    hn2 -= 2.0 * (h.x * a.x + h.y * a.y);
+    double gx = 0.0, gy = 0.0;  // (G h)_i
+    for (int q = 0; q < k; ++q) {
+      const double2 g = Gs[(size_t)q * ldg + i], hq = hout[(int64_t)q * S + s];
+      gx += g.x * hq.x - g.y * hq.y;
+      gy += g.x * hq.y + g.y * hq.x;
+    }
+    hn2 += h.x * gx + h.y * gy;
+  }
+  const bool fused = isfinite(hn2) && hn2 > 1e-6 * ww;
+  form[s] = make_double2(hn2, fused ? 0.0 : 1.0);
+  post[s] = make_double2(fused ? 1.0 / sqrt(hn2) : 0.0, 0.0);
+  flag[s] = fused ? 0 : 1;
 }
 
-// w += sign * sum_{i < k} V_i h[i * S + seg]
+// w += sign * sum_{i < k} V_i h[i * S + seg]; with post, instances whose
+// post[seg].x > 0 write the result times post[seg].x to vnext instead
+// (fused normalisation; w is left as it was)
 template <typename T>
 __global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
                                                          const double2 *__restrict__ h, int S,
                                                          typename Cplx<T>::t *__restrict__ w,
                                                          const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg,
-                                                         const int *__restrict__ active, double sign) {
+                                                         const int *__restrict__ active, double sign,
+                                                         const double2 *__restrict__ post,
+                                                         typename Cplx<T>::t *__restrict__ vnext) {
   using T2 = typename Cplx<T>::t;
   const int c = blockIdx.x;
   const int s = ch_seg[c];
   if (active && !active[s]) return;
+  const double sc = post ? post[s].x : 0.0;
+  T2 *dst = sc > 0.0 ? vnext : w;
+  const double f = sc > 0.0 ? sc : 1.0;
   for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
     double ax = w[e].x, ay = w[e].y;
     for (int i = 0; i < k; ++i) {
@@ -430,17 +462,20 @@ __global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>:
       ax += sign * ((double)v.x * hh.x - (double)v.y * hh.y);
       ay += sign * ((double)v.x * hh.y + (double)v.y * hh.x);
     }
-    w[e] = T2{(T)ax, (T)ay};
+    dst[e] = T2{(T)(f * ax), (T)(f * ay)};
   }
 }
 
-// out = sc[seg] * in  (real per-instance scale; types may differ)
+// out = sc[seg] * in  (real per-instance scale; types may differ); with a
+// mask, only the instances whose mask entry is set
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) seg_scale_kernel(const typename Cplx<TI>::t *__restrict__ in,
                                                         const double *__restrict__ sc,
                                                         typename Cplx<TO>::t *__restrict__ out,
-                                                        const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg) {
+                                                        const int64_t *__restrict__ ch_e, const int *__restrict__ ch_seg,
+                                                        const int *__restrict__ mask) {
   const int c = blockIdx.x;
+  if (mask && !mask[ch_seg[c]]) return;
   const double f = sc[ch_seg[c]];
   for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256)
     out[e] = typename Cplx<TO>::t{(TO)(f * (double)in[e].x), (TO)(f * (double)in[e].y)};
@@ -554,12 +589,12 @@ static heom_status batch_jacobi_T(heom_batch &b, const void *r, void *z, int bor
 // out[i * S + s] = conj(V_i) . w per instance, i < k
 template <typename T>
 static heom_status seg_mdot(heom_batch &b, const void *V, int64_t ldv, int k, const void *w, double2 *partial,
-                            double2 *out, hipStream_t s) {
+                            double2 *out, hipStream_t s, const int *mask = nullptr) {  // mask: instead of active
   using T2 = typename Cplx<T>::t;
   constexpr int NI = 4;
   dim3 grid(b.n_chunks, (k + NI - 1) / NI);
   hipLaunchKernelGGL((seg_mdot_kernel<T, NI>), grid, dim3(256), 0, s, (const T2 *)V, ldv, k, (const T2 *)w, b.ch_e,
-                     b.ch_seg, b.n_chunks, b.active, partial);
+                     b.ch_seg, b.n_chunks, mask ? mask : b.active, partial);
   HEOM_HIP_CHECK(hipGetLastError());
   const int64_t tot = (int64_t)k * b.S;
   hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, k, b.n_chunks,
@@ -587,18 +622,19 @@ static heom_status seg_mdot2(heom_batch &b, const void *V, int64_t ldv, int k, c
 
 template <typename T>
 static heom_status seg_update(heom_batch &b, const void *V, int64_t ldv, int k, const double2 *h, void *w,
-                              double sign, hipStream_t s) {
+                              double sign, hipStream_t s, const double2 *post = nullptr, void *vnext = nullptr) {
   using T2 = typename Cplx<T>::t;
   hipLaunchKernelGGL(seg_update_kernel<T>, dim3(b.n_chunks), dim3(256), 0, s, (const T2 *)V, ldv, k, h, b.S, (T2 *)w,
-                     b.ch_e, b.ch_seg, b.active, sign);
+                     b.ch_e, b.ch_seg, b.active, sign, post, (T2 *)vnext);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
 
 template <typename TI, typename TO>
-static heom_status seg_scale(heom_batch &b, const void *in, const double *sc, void *out, hipStream_t s) {
+static heom_status seg_scale(heom_batch &b, const void *in, const double *sc, void *out, hipStream_t s,
+                             const int *mask = nullptr) {
   hipLaunchKernelGGL((seg_scale_kernel<TI, TO>), dim3(b.n_chunks), dim3(256), 0, s,
-                     (const typename Cplx<TI>::t *)in, sc, (typename Cplx<TO>::t *)out, b.ch_e, b.ch_seg);
+                     (const typename Cplx<TI>::t *)in, sc, (typename Cplx<TO>::t *)out, b.ch_e, b.ch_seg, mask);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -632,6 +668,7 @@ struct BatchGmres {
   T2 *V = nullptr, *Z = nullptr, *w = nullptr;
   double2 *partial = nullptr, *hdev = nullptr, *gram = nullptr;
   double *sdev = nullptr;
+  int *flag = nullptr;            // [S] 1: the Gram formula cancelled, explicit norm
   double *pin_sc = nullptr;       // host pinned [S]
   double2 *pin_h = nullptr;       // host pinned: step coefficients [(m + 1) S] and norms [S]
   PinnedBuf pin;
@@ -648,8 +685,8 @@ struct BatchGmres {
   static size_t bytes(const heom_batch &b, int m, bool jac) {  // jac: any preconditioner (Z kept)
     const size_t vec = (size_t)b.n * sizeof(T2);
     return (size_t)(m + 1) * vec + (jac ? (size_t)m * vec : 0) + vec + (size_t)(2 * m + 3) * b.n_chunks * sizeof(double2) +
-           (size_t)(3 * m + 5) * b.S * sizeof(double2) + (size_t)b.S * (m + 1) * (m + 1) * sizeof(double2) +
-           (size_t)b.S * sizeof(double) + 8 * 256;
+           (size_t)(3 * m + 7) * b.S * sizeof(double2) + (size_t)b.S * (m + 1) * (m + 1) * sizeof(double2) +
+           (size_t)b.S * sizeof(double) + (size_t)b.S * sizeof(int) + 9 * 256;
   }
 
   heom_status init(heom_batch &bb, WsArena &ws, int m_, bool graph, int prec_) {
@@ -662,27 +699,36 @@ struct BatchGmres {
     Z = prec != HEOM_PREC_NONE ? (T2 *)ws.take((size_t)m * vec) : V;
     w = (T2 *)ws.take(vec);
     partial = (double2 *)ws.take((size_t)(2 * m + 3) * b->n_chunks * sizeof(double2));
-    // hdev: [0, (2m+3) S) reduced a, c, |w|^2;  then h [(m+1) S] and |w'|^2 [S]
-    hdev = (double2 *)ws.take((size_t)(3 * m + 5) * b->S * sizeof(double2));
+    // hdev: [0, (2m+3) S) reduced a, c, |w|^2;  then h [(m+1) S], the
+    // explicit |w'|^2 [S], the Gram-formula |w'|^2 and its flag [S], and the
+    // fused normalisation scale [S]
+    hdev = (double2 *)ws.take((size_t)(3 * m + 7) * b->S * sizeof(double2));
     gram = (double2 *)ws.take((size_t)b->S * (m + 1) * (m + 1) * sizeof(double2));
     sdev = (double *)ws.take((size_t)b->S * sizeof(double));
-    if (!V || !Z || !w || !partial || !hdev || !gram || !sdev) return fail(HEOM_ERR_ARG, "batch: workspace too small");
-    HEOM_TRY(pin.ensure((size_t)(m + 2) * b->S * sizeof(double2) + (size_t)(m + 1) * b->S * sizeof(double2) +
+    flag = (int *)ws.take((size_t)b->S * sizeof(int));
+    if (!V || !Z || !w || !partial || !hdev || !gram || !sdev || !flag)
+      return fail(HEOM_ERR_ARG, "batch: workspace too small");
+    HEOM_TRY(pin.ensure((size_t)(m + 3) * b->S * sizeof(double2) + (size_t)(m + 1) * b->S * sizeof(double2) +
                         (size_t)b->S * sizeof(double)));
     pin_h = (double2 *)pin.p;
-    pin_sc = (double *)(pin_h + (size_t)(2 * m + 3) * b->S);
+    pin_sc = (double *)(pin_h + (size_t)(2 * m + 4) * b->S);
     graphs.assign(m, nullptr);
     if (use_graph) HEOM_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     return HEOM_OK;
   }
 
   double2 *h_out() const { return hdev + (size_t)(2 * m + 3) * b->S; }   // [(m+1)][S] coefficients
-  double2 *n_out() const { return h_out() + (size_t)(m + 1) * b->S; }    // [S] |w'|^2
+  double2 *n_out() const { return h_out() + (size_t)(m + 1) * b->S; }    // [S] |w'|^2 (explicit, flagged only)
+  double2 *f_out() const { return n_out() + b->S; }                      // [S] (formula |w'|^2, flag)
+  double2 *post() const { return f_out() + b->S; }                       // [S] fused scale
 
   // Device work of Arnoldi step j: z_j = P v_j, w = B z_j, then CGS2 in two
   // passes over the basis: one two-vector multi-dot (a = V^H w, the Gram
-  // column V^H v_j, |w|^2), the per-instance Gram correction, one update;
-  // then |w|^2 and the copy of the coefficients to the host.
+  // column V^H v_j, |w|^2), the per-instance Gram correction with the norm
+  // |w - V h| from the Gram matrix, one update that writes v_{j+1} already
+  // normalised; only instances whose norm formula cancelled keep w - V h in
+  // w and get an explicit |w|^2; then the copy of the coefficients to the
+  // host.
   heom_status step_device(int j, int border, hipStream_t s) {
     const int64_t n = b->n;
     T2 *vj = V + (size_t)j * n;
@@ -692,11 +738,11 @@ struct BatchGmres {
     HEOM_TRY(batch_apply_T<T>(*b, zj, w, border, true, s));
     HEOM_TRY(seg_mdot2<T>(*b, V, n, j + 1, w, vj, partial, hdev, s));
     hipLaunchKernelGGL(batch_gram_kernel, dim3((b->S + 255) / 256), dim3(256), 0, s, gram, hdev, j, b->S, m + 1,
-                       b->active, h_out());
+                       b->active, h_out(), f_out(), post(), flag);
     HEOM_HIP_CHECK(hipGetLastError());
-    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h_out(), w, -1.0, s));
-    HEOM_TRY(seg_mdot<T>(*b, w, 0, 1, w, partial, n_out(), s));
-    HEOM_HIP_CHECK(hipMemcpyAsync(pin_h, h_out(), sizeof(double2) * (m + 2) * b->S, hipMemcpyDeviceToHost, s));
+    HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h_out(), w, -1.0, s, post(), V + (size_t)(j + 1) * n));
+    HEOM_TRY(seg_mdot<T>(*b, w, 0, 1, w, partial, n_out(), s, flag));
+    HEOM_HIP_CHECK(hipMemcpyAsync(pin_h, h_out(), sizeof(double2) * (m + 3) * b->S, hipMemcpyDeviceToHost, s));
     return HEOM_OK;
   }
 
@@ -803,15 +849,16 @@ struct BatchGmres {
         ++applies;
         ++it_total;
         HEOM_HIP_CHECK(hipStreamSynchronize(s));
-        const double2 *hp1 = pin_h, *hnrm = pin_h + (size_t)(m + 1) * S;
-        bool more = false;
+        const double2 *hp1 = pin_h, *hnrm = pin_h + (size_t)(m + 1) * S, *hform = hnrm + S;
+        bool more = false, stopped = false, explicit_norm = false;
         for (int q = 0; q < S; ++q) {
           pin_sc[q] = 0.0;
           if (!ext[q]) continue;
           ++iters[q];
           cd *Hc = &H[((size_t)q * (m + 1)) * m];
           for (int i = 0; i <= j; ++i) Hc[(size_t)j * (m + 1) + i] = cd(hp1[(size_t)i * S + q].x, hp1[(size_t)i * S + q].y);
-          const double hn = std::sqrt(std::max(hnrm[q].x, 0.0));
+          const bool flagged = hform[q].y != 0.0;  // v_{j+1} not yet written: scale w below
+          const double hn = std::sqrt(std::max(flagged ? hnrm[q].x : hform[q].x, 0.0));
           if (!std::isfinite(hn)) return fail(HEOM_ERR_NAN, "batch: non-finite Arnoldi norm");
           Hc[(size_t)j * (m + 1) + j + 1] = hn;
           cd *col = &Hc[(size_t)j * (m + 1)];
@@ -843,15 +890,23 @@ struct BatchGmres {
           gr[j] = c * gr[j];
           kcol[q] = j + 1;
           const double rel = bnorm[q] > 0 ? std::abs(gr[j + 1]) / bnorm[q] : 0.0;
-          if (rel <= tol * 0.5 || hn <= 1e-300 || iters[q] >= max_iter) ext[q] = 0;
-          else pin_sc[q] = 1.0 / hn;
+          if (rel <= tol * 0.5 || hn <= 1e-300 || iters[q] >= max_iter) {
+            ext[q] = 0;
+            stopped = true;
+          } else if (flagged) {
+            pin_sc[q] = 1.0 / hn;
+            explicit_norm = true;
+          }
           more = more || ext[q];
         }
         if (!more) { ++j; break; }
-        // V_{j+1} = w / hn for the instances still extending; others stop here
-        HEOM_TRY(set_active(ext, s));
-        HEOM_HIP_CHECK(hipMemcpyAsync(sdev, pin_sc, sizeof(double) * S, hipMemcpyHostToDevice, s));
-        HEOM_TRY((seg_scale<T, T>(*b, w, sdev, V + (size_t)(j + 1) * n, s)));
+        // instances that stop leave the active set; v_{j+1} = w / hn for the
+        // flagged instances still extending (the others have it already)
+        if (stopped) HEOM_TRY(set_active(ext, s));
+        if (explicit_norm) {
+          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, pin_sc, sizeof(double) * S, hipMemcpyHostToDevice, s));
+          HEOM_TRY((seg_scale<T, T>(*b, w, sdev, V + (size_t)(j + 1) * n, s, flag)));
+        }
       }
       // x += Z y per instance
       int kmax = 0;
