@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(256) seg_mdot2_kernel(const typename Cplx<T>::
   if (blockIdx.y == 0 && threadIdx.x == 0) partial[(int64_t)(2 * k) * n_chunks + c] = red[2 * NI][0];
 }
 
-// Per instance (one thread each): record the new Gram column c = V^H v_j
+// Per instance (one wave each): record the new Gram column c = V^H v_j
 // and form the twice-projected coefficients h = a + (a - G a), a = V^H w
 // (CGS2's second projection from the measured Gram matrix G = V^H V).
 // red: [(2k + 1)][S] reduced a, c, |w|^2; G: [S][ldg][ldg] column-major.
@@ -387,27 +387,32 @@ __global__ void __launch_bounds__(256) seg_mdot2_kernel(const typename Cplx<T>::
 // form[s] = (that value, 1 when it cancels), post[s].x = its inverse square
 // root (0 when it cancels: the update then keeps w - V h for an explicit
 // norm), flag[s] = 1 for those instances.
-__global__ void batch_gram_kernel(double2 *__restrict__ G, const double2 *__restrict__ red, int j, int S, int ldg,
-                                  const int *__restrict__ active, double2 *__restrict__ hout,
-                                  double2 *__restrict__ form, double2 *__restrict__ post, int *__restrict__ flag) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
+__global__ void __launch_bounds__(64) batch_gram_kernel(double2 *__restrict__ G, const double2 *__restrict__ red,
+                                                        int j, int S, int ldg, const int *__restrict__ active,
+                                                        double2 *__restrict__ hout, double2 *__restrict__ form,
+                                                        double2 *__restrict__ post, int *__restrict__ flag) {
+  // one wave per instance; lane l handles basis indices l, l + 64, ...
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x;
   const int k = j + 1;
   if (active && !active[s]) {
-    for (int i = 0; i < k; ++i) hout[(int64_t)i * S + s] = make_double2(0.0, 0.0);
-    form[s] = make_double2(0.0, 0.0);
-    post[s] = make_double2(0.0, 0.0);
-    flag[s] = 0;
+    for (int i = lane; i < k; i += 64) hout[(int64_t)i * S + s] = make_double2(0.0, 0.0);
+    if (lane == 0) {
+      form[s] = make_double2(0.0, 0.0);
+      post[s] = make_double2(0.0, 0.0);
+      flag[s] = 0;
+    }
     return;
   }
   double2 *Gs = G + (size_t)s * ldg * ldg;
-  for (int i = 0; i < k; ++i) {
+  for (int i = lane; i < k; i += 64) {
     const double2 c = red[(int64_t)(k + i) * S + s];
     Gs[(size_t)j * ldg + i] = c;
     Gs[(size_t)i * ldg + j] = make_double2(c.x, -c.y);
   }
-  for (int i = 0; i < k; ++i) {
-    double gx = 0.0, gy = 0.0;
+  __syncthreads();
+  for (int i = lane; i < k; i += 64) {
+    double gx = 0.0, gy = 0.0;  // (G a)_i
     for (int q = 0; q < k; ++q) {
       const double2 g = Gs[(size_t)q * ldg + i], a = red[(int64_t)q * S + s];
       gx += g.x * a.x - g.y * a.y;
@@ -416,23 +421,29 @@ __global__ void batch_gram_kernel(double2 *__restrict__ G, const double2 *__rest
     const double2 a = red[(int64_t)i * S + s];
     hout[(int64_t)i * S + s] = make_double2(2.0 * a.x - gx, 2.0 * a.y - gy);
   }
-  const double ww = red[(int64_t)(2 * k) * S + s].x;
-  double hn2 = ww;
-  for (int i = 0; i < k; ++i) {
+  __syncthreads();
+  // |w - V h|^2 = |w|^2 - 2 Re(h^H a) + h^H G h
+  double part = 0.0;
+  for (int i = lane; i < k; i += 64) {
     const double2 h = hout[(int64_t)i * S + s], a = red[(int64_t)i * S + s];
-    hn2 -= 2.0 * (h.x * a.x + h.y * a.y);
     double gx = 0.0, gy = 0.0;  // (G h)_i
     for (int q = 0; q < k; ++q) {
       const double2 g = Gs[(size_t)q * ldg + i], hq = hout[(int64_t)q * S + s];
       gx += g.x * hq.x - g.y * hq.y;
       gy += g.x * hq.y + g.y * hq.x;
     }
-    hn2 += h.x * gx + h.y * gy;
+    part += (h.x * gx + h.y * gy) - 2.0 * (h.x * a.x + h.y * a.y);
   }
-  const bool fused = isfinite(hn2) && hn2 > 1e-6 * ww;
-  form[s] = make_double2(hn2, fused ? 0.0 : 1.0);
-  post[s] = make_double2(fused ? 1.0 / sqrt(hn2) : 0.0, 0.0);
-  flag[s] = fused ? 0 : 1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+  if (lane == 0) {
+    const double ww = red[(int64_t)(2 * k) * S + s].x;
+    const double hn2 = ww + part;
+    const bool fused = isfinite(hn2) && hn2 > 1e-6 * ww;
+    form[s] = make_double2(hn2, fused ? 0.0 : 1.0);
+    post[s] = make_double2(fused ? 1.0 / sqrt(hn2) : 0.0, 0.0);
+    flag[s] = fused ? 0 : 1;
+  }
 }
 
 // w += sign * sum_{i < k} V_i h[i * S + seg]; with post, instances whose
@@ -737,8 +748,8 @@ struct BatchGmres {
     if (prec == HEOM_PREC_BLOCK) HEOM_TRY(batch_block_T<T>(*b, vj, zj, s));
     HEOM_TRY(batch_apply_T<T>(*b, zj, w, border, true, s));
     HEOM_TRY(seg_mdot2<T>(*b, V, n, j + 1, w, vj, partial, hdev, s));
-    hipLaunchKernelGGL(batch_gram_kernel, dim3((b->S + 255) / 256), dim3(256), 0, s, gram, hdev, j, b->S, m + 1,
-                       b->active, h_out(), f_out(), post(), flag);
+    hipLaunchKernelGGL(batch_gram_kernel, dim3(b->S), dim3(64), 0, s, gram, hdev, j, b->S, m + 1, b->active, h_out(),
+                       f_out(), post(), flag);
     HEOM_HIP_CHECK(hipGetLastError());
     HEOM_TRY(seg_update<T>(*b, V, n, j + 1, h_out(), w, -1.0, s, post(), V + (size_t)(j + 1) * n));
     HEOM_TRY(seg_mdot<T>(*b, w, 0, 1, w, partial, n_out(), s, flag));
