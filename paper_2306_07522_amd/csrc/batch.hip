@@ -618,6 +618,10 @@ template <typename T>
 static heom_status seg_mdot2(heom_batch &b, const void *V, int64_t ldv, int k, const void *w, const void *u,
                              double2 *partial, double2 *out, hipStream_t s) {
   using T2 = typename Cplx<T>::t;
+  // (the one-read wave variant of the single-hierarchy solver was measured
+  // here and is slower: the per-instance chunks are mostly small, and one
+  // workgroup walking all groups of four basis vectors serially loses to a
+  // workgroup per group)
   constexpr int NI = 4;
   dim3 grid(b.n_chunks, (k + NI - 1) / NI);
   hipLaunchKernelGGL((seg_mdot2_kernel<T, NI>), grid, dim3(256), 0, s, (const T2 *)V, ldv, k, (const T2 *)w,
