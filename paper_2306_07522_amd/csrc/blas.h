@@ -61,6 +61,9 @@ heom_status block_prec(const void *r, void *z, const Hier &h, int R, const doubl
 template <typename T>
 heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *shifts, int border, hipStream_t s,
                    int modulus = 0);
+// u = x + c k (RK4 stage input, formed once before the apply)
+template <typename T>
+heom_status stage_input(const void *x, const void *k, double c, void *u, int64_t total, hipStream_t s);
 template <typename T>
 heom_status rk4_combine(void *x, const void *k1, const void *k2, const void *k3, const void *k4, double dt,
                         int64_t total, hipStream_t s);

@@ -360,6 +360,21 @@ __global__ void rk4_combine_kernel(typename Cplx<T>::t *__restrict__ x, const ty
   }
 }
 
+// RK4 stage input u = x + c k, with the same fused multiply-add (in T) that
+// the apply uses when it forms the stage input while gathering
+template <typename T>
+__global__ void stage_input_kernel(const typename Cplx<T>::t *__restrict__ x, const typename Cplx<T>::t *__restrict__ k,
+                                   T c, typename Cplx<T>::t *__restrict__ u, int64_t total) {
+  using T2 = typename Cplx<T>::t;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const T2 q = k[idx];
+    T2 v = x[idx];
+    v.x = fma(c, q.x, v.x);
+    v.y = fma(c, q.y, v.y);
+    u[idx] = v;
+  }
+}
+
 // save ADO 0 into the trajectory slot counter[0] and advance the counter
 template <typename T>
 __global__ void save_rho0_kernel(const typename Cplx<T>::t *__restrict__ x, typename Cplx<T>::t *__restrict__ traj,
@@ -539,6 +554,14 @@ heom_status jacobi(const void *r, void *z, const Hier &h, int R, const double2 *
 }
 
 template <typename T>
+heom_status stage_input(const void *x, const void *k, double c, void *u, int64_t total, hipStream_t s) {
+  hipLaunchKernelGGL(stage_input_kernel<T>, dim3(grid_for(total)), dim3(256), 0, s, (const typename Cplx<T>::t *)x,
+                     (const typename Cplx<T>::t *)k, (T)c, (typename Cplx<T>::t *)u, total);
+  HEOM_HIP_CHECK(hipGetLastError());
+  return HEOM_OK;
+}
+
+template <typename T>
 heom_status rk4_combine(void *x, const void *k1, const void *k2, const void *k3, const void *k4, double dt, int64_t total,
                         hipStream_t s) {
   using T2 = typename Cplx<T>::t;
@@ -596,6 +619,7 @@ heom_status trace_readout(const void *x, const double2 *ops, int d, int R, const
   template heom_status rk4_combine<T>(void *, const void *, const void *, const void *, const void *, double,      \
                                       int64_t, hipStream_t);                                                       \
   template heom_status save_rho0<T>(const void *, void *, int, int *, int64_t, hipStream_t);                       \
+  template heom_status stage_input<T>(const void *, const void *, double, void *, int64_t, hipStream_t);           \
   template heom_status left_multiply<T>(const double2 *, const double2 *, int, int64_t, int, const int *, void *, \
                                         hipStream_t);                                                              \
   template heom_status trace_readout<T>(const void *, const double2 *, int, int, const int *, double, double *,    \

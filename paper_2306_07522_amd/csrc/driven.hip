@@ -125,8 +125,10 @@ extern "C" heom_status heom_propagate_driven(heom_hier *hw, int32_t precision, v
   WsArena arena(ws, ws_bytes);
   void *k[4];
   for (int i = 0; i < 4; ++i) k[i] = arena.take((size_t)n * w);
+  void *u = arena.take((size_t)n * w);  // stage input x + c k, formed once per stage
   int *counter = (int *)arena.take(256);
-  if (!k[0] || !k[1] || !k[2] || !k[3] || !counter) return fail(HEOM_ERR_ARG, "propagate_driven: workspace too small");
+  if (!k[0] || !k[1] || !k[2] || !k[3] || !u || !counter)
+    return fail(HEOM_ERR_ARG, "propagate_driven: workspace too small");
   double2 *Vdev = nullptr;
   if (hipMalloc(&Vdev, sizeof(double2) * Vd.size()) != hipSuccess) return fail(HEOM_ERR_ALLOC, "propagate_driven: allocation");
   struct Free {
@@ -152,9 +154,10 @@ extern "C" heom_status heom_propagate_driven(heom_hier *hw, int32_t precision, v
       a.n_rhs = 1;
       a.x = x_dev;
       a.y = k[st];
-      if (st > 0) {
-        a.k = k[st - 1];
-        a.kc = cs[st - 1];
+      if (st > 0) {  // one pass forms x + c k for both the apply and the drive term
+        if (precision == HEOM_FP64) HEOM_TRY(stage_input<double>(x_dev, k[st - 1], cs[st - 1], u, n, s));
+        else HEOM_TRY(stage_input<float>(x_dev, k[st - 1], cs[st - 1], u, n, s));
+        a.x = u;
       }
       DriveCoef cf;
       HEOM_TRY(coef(ts[st], cf));

@@ -238,7 +238,7 @@ heom_status heom_workspace_size(const heom_hier *hw, int32_t op, const heom_solv
   const Hier &h = *hw->impl;
   const int64_t n = h.N * (int64_t)h.d * h.d;
   if (op == HEOM_OP_PROPAGATE) {
-    *bytes = 4 * (size_t)n * 16 + 4096;  // k1..k4 at FP64 size (enough for FP32 too)
+    *bytes = 5 * (size_t)n * 16 + 4096;  // k1..k4 and the stage input at FP64 size (enough for FP32 too)
     return HEOM_OK;
   }
   heom_solver_opts d;
@@ -307,8 +307,9 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
   WsArena arena(ws, ws_bytes);
   void *k[4];
   for (int i = 0; i < 4; ++i) k[i] = arena.take((size_t)n * w);
+  void *u = arena.take((size_t)n * w);  // stage input x + c k, formed once per stage
   int *counter = (int *)arena.take(256);
-  if (!k[0] || !k[1] || !k[2] || !k[3] || !counter) return fail(HEOM_ERR_ARG, "propagate: workspace too small");
+  if (!k[0] || !k[1] || !k[2] || !k[3] || !u || !counter) return fail(HEOM_ERR_ARG, "propagate: workspace too small");
   HEOM_TRY(fill_int(counter, 0, 1, s));
   const int64_t n_saves = save_every > 0 ? n_steps / save_every : 0;
   auto step = [&](int64_t idx) -> heom_status {
@@ -319,8 +320,11 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
     HEOM_TRY(launch_apply(h, precision, a, s));
     const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
     for (int st = 1; st < 4; ++st) {
-      a.k = k[st - 1];
-      a.kc = cs[st - 1];
+      // one pass forms x + c k; the apply then gathers one block per
+      // neighbour instead of two
+      if (precision == HEOM_FP64) HEOM_TRY(stage_input<double>(x_dev, k[st - 1], cs[st - 1], u, n, s));
+      else HEOM_TRY(stage_input<float>(x_dev, k[st - 1], cs[st - 1], u, n, s));
+      a.x = u;
       a.y = k[st];
       HEOM_TRY(launch_apply(h, precision, a, s));
     }
