@@ -66,7 +66,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "two_orbital_dos", "cavity", "batch",
-                                             "conductance"],
+                                             "conductance", "propagation"],
                    default="all",
                    help="solve timings: all legs, siam only, none, or one leg (the two-orbital stationary state "
                         "with GMRES-DR, the cavity stationary state and PSD, the 512-instance batch) for profiling")
@@ -313,9 +313,10 @@ def batch_benchmark(api, wl):
 
 def propagation_benchmarks(api, wl):
     """RK4 on the paper's workloads: the spin-boson model (35 ADOs, 2,000
-    steps of dt = 0.01, eager launches and hipGraph-captured steps) and the
+    steps of dt = 0.01, eager launches and hipGraph-captured steps), the
     charge-cavity model (3,165 ADOs of 20x20, t = 0 -> 200 with dt = 0.01,
-    20,000 steps), both FP64, rho_0 saved every step."""
+    20,000 steps) and 40 steps of the two-orbital tier-4 hierarchy, all
+    FP64."""
     import numpy as np
     import torch
     out = {}
@@ -344,7 +345,8 @@ def propagation_benchmarks(api, wl):
     n_steps, dt = 20000, 0.01
     api.propagate(h, x.clone(), dt, 50, graph_steps=50)
     traj, t = _timed(lambda: api.propagate(h, x, dt, n_steps, save_every=100, graph_steps=100))
-    step_bytes = 4 * algorithmic_bytes(h, 16) + 6 * h.N * h.d * h.d * 16
+    # four applies, three stage inputs x + c k (read 2, write 1) and the combine (read 5, write 1)
+    step_bytes = 4 * algorithmic_bytes(h, 16) + 15 * h.N * h.d * h.d * 16
     out["charge_cavity_rk4"] = {"n_ado": h.N, "d": h.d, "steps": n_steps, "dt": dt, "seconds": round(t, 3),
                                 "us_per_step": round(t / n_steps * 1e6, 3),
                                 "gbs_algorithmic": round(step_bytes * n_steps / t / 1e9, 2),
@@ -352,6 +354,22 @@ def propagation_benchmarks(api, wl):
                                 "trace_rho0_end": float(torch.diagonal(traj[-1]).sum().real.item())}
     _progress(f"charge-cavity RK4: {n_steps} steps in {t:.2f} s")
     h.close()
+    # the largest workload: 40 FP64 RK4 steps of the two-orbital tier-4 hierarchy
+    cfg = wl.two_orbital_anderson()
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    x = torch.zeros((h.N, h.d, h.d), dtype=torch.complex128, device="cuda")
+    x[0] = torch.eye(h.d, dtype=torch.complex128, device="cuda") / h.d
+    n_steps, dt = 40, 0.01
+    api.propagate(h, x.clone(), dt, 4)
+    traj, t = _timed(lambda: api.propagate(h, x, dt, n_steps, save_every=n_steps))
+    step_bytes = 4 * algorithmic_bytes(h, 16) + 15 * h.N * h.d * h.d * 16
+    out["two_orbital_tier4_rk4"] = {"n_ado": h.N, "d": h.d, "steps": n_steps, "dt": dt, "seconds": round(t, 3),
+                                    "ms_per_step": round(t / n_steps * 1e3, 3),
+                                    "gbs_algorithmic": round(step_bytes * n_steps / t / 1e9, 2),
+                                    "trace_rho0_end": float(torch.diagonal(traj[-1]).sum().real.item())}
+    _progress(f"two-orbital tier-4 RK4: {t / n_steps * 1e3:.2f} ms per step")
+    h.close()
+    del x, traj
     out.update(cavity_spectrum_benchmark(api, wl))
     return out
 
@@ -505,6 +523,8 @@ def solve_benchmarks(which):
         return {"batch_512_instances": batch_benchmark(api, wl)}
     if which == "conductance":
         return {"siam_example1_conductance": conductance_benchmark(api, wl)}
+    if which == "propagation":
+        return propagation_benchmarks(api, wl)
     if which == "two_orbital_dos":
         return {"two_orbital_tier4_dos": dos_benchmark(api, wl, wl.two_orbital_anderson(), sample=0)}
     siam_train = []
