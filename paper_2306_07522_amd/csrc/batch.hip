@@ -25,6 +25,7 @@
 #include "blas.h"
 #include "device_common.h"
 #include "internal.h"
+#include "tile_product.h"
 #include "solvers.h"
 
 namespace heom {
@@ -183,82 +184,67 @@ __global__ void __launch_bounds__(256) batch_jacobi_kernel(const BInst<T> *__res
 }
 
 // z = P^{-1} r per instance with the block preconditioner: per ADO the exact
-// inverse of -c_a - i[H, .] in the eigenbasis of H (see block_prec.hip), one
-// task of the tile at a time, four d x d products through LDS (d <= 16).
+// inverse of -c_a - i[H, .] in the eigenbasis of H (see block_prec.hip), four
+// d x d products through LDS (d <= 16), one task per wave at a time.
 template <typename T>
 __global__ void __launch_bounds__(256) batch_block_kernel(const BInst<T> *__restrict__ inst,
                                                           const int4 *__restrict__ tiles, int n_tiles,
                                                           const int *__restrict__ active,
                                                           const typename Cplx<T>::t *__restrict__ r,
                                                           typename Cplx<T>::t *__restrict__ z) {
+  // the eigenbasis U of the tile's instance is shared; each wave takes every
+  // fourth task of the tile with its own X and W and 2 x 2 product tiles
+  // (d <= 16: at most 64 tiles, one per lane)
   using T2 = typename Cplx<T>::t;
-  __shared__ double2 Us[256], X[256], W[256];
+  __shared__ double2 Us[256], Xs[4][256], Ws[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double2 *X = Xs[wave], *W = Ws[wave];
   for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int4 tl = tiles[t];
     if (active && !active[tl.x]) continue;  // uniform over the workgroup
     const BInst<T> &I = inst[tl.x];
     const int d = I.d, dd = d * d;
-    __syncthreads();  // the previous tile is done with the LDS
+    __syncthreads();  // every wave is done with the previous tile's U
     for (int e = threadIdx.x; e < dd; e += blockDim.x) Us[e] = I.ueig[e];
-    for (int64_t task = tl.y; task < tl.z; ++task) {
+    __syncthreads();
+    for (int64_t task = tl.y + wave; task < tl.z; task += 4) {
       const int64_t a = I.tasks[task].x;
       const int64_t base = I.off + a * dd;
-      __syncthreads();
-      for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+      for (int e = lane; e < dd; e += 64) {
         const T2 v = r[base + e];
         X[e] = make_double2((double)v.x, (double)v.y);
       }
-      __syncthreads();
-      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // W = U^H X
-        const int i = e / d, j = e % d;
-        double sx = 0.0, sy = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double2 u = Us[k * d + i], x = X[k * d + j];
-          sx += u.x * x.x + u.y * x.y;
-          sy += u.x * x.y - u.y * x.x;
-        }
-        W[e] = make_double2(sx, sy);
-      }
-      __syncthreads();
+      wave_sync();
+      // W = U^H X
+      tile_product(
+          d, lane, [&](int i, int k) { const double2 u = Us[k * d + i]; return make_double2(u.x, -u.y); },
+          [&](int k, int j) { return X[k * d + j]; }, [&](int i, int j, double2 v) { W[i * d + j] = v; });
+      wave_sync();
+      // X = (W U) / D
       const double2 c = I.decay64[a];
-      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // X = (W U) / D
-        const int i = e / d, j = e % d;
-        double sx = 0.0, sy = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double2 w = W[i * d + k], u = Us[k * d + j];
-          sx += w.x * u.x - w.y * u.y;
-          sy += w.x * u.y + w.y * u.x;
-        }
-        double dx = -c.x, dy = -c.y - (I.eval[i] - I.eval[j]);
-        if (dx * dx + dy * dy < I.delta * I.delta) {
-          dx = -I.delta;
-          dy = 0.0;
-        }
-        const double inv = 1.0 / (dx * dx + dy * dy);
-        X[e] = make_double2((sx * dx + sy * dy) * inv, (sy * dx - sx * dy) * inv);
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // W = U X
-        const int i = e / d, j = e % d;
-        double sx = 0.0, sy = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double2 u = Us[i * d + k], x = X[k * d + j];
-          sx += u.x * x.x - u.y * x.y;
-          sy += u.x * x.y + u.y * x.x;
-        }
-        W[e] = make_double2(sx, sy);
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < dd; e += blockDim.x) {  // z = W U^H
-        const int i = e / d, j = e % d;
-        double sx = 0.0, sy = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double2 w = W[i * d + k], u = Us[j * d + k];
-          sx += w.x * u.x + w.y * u.y;
-          sy += w.y * u.x - w.x * u.y;
-        }
-        z[base + e] = T2{(T)sx, (T)sy};
-      }
+      tile_product(
+          d, lane, [&](int i, int k) { return W[i * d + k]; }, [&](int k, int j) { return Us[k * d + j]; },
+          [&](int i, int j, double2 v) {
+            double dx = -c.x, dy = -c.y - (I.eval[i] - I.eval[j]);
+            if (dx * dx + dy * dy < I.delta * I.delta) {
+              dx = -I.delta;
+              dy = 0.0;
+            }
+            const double inv = 1.0 / (dx * dx + dy * dy);
+            X[i * d + j] = make_double2((v.x * dx + v.y * dy) * inv, (v.y * dx - v.x * dy) * inv);
+          });
+      wave_sync();
+      // W = U X
+      tile_product(
+          d, lane, [&](int i, int k) { return Us[i * d + k]; }, [&](int k, int j) { return X[k * d + j]; },
+          [&](int i, int j, double2 v) { W[i * d + j] = v; });
+      wave_sync();
+      // z = W U^H
+      tile_product(
+          d, lane, [&](int i, int k) { return W[i * d + k]; },
+          [&](int k, int j) { const double2 u = Us[j * d + k]; return make_double2(u.x, -u.y); },
+          [&](int i, int j, double2 v) { z[base + i * d + j] = T2{(T)v.x, (T)v.y}; });
+      wave_sync();  // X and W are rewritten by the next task
     }
   }
 }

@@ -17,34 +17,11 @@
 // products are bound by LDS reads, two per multiply-add without tiling).
 #include "blas.h"
 #include "device_common.h"
+#include "tile_product.h"
 
 namespace heom {
 
 constexpr int kBlockPrecMaxD = 32;
-
-// C(i, j) = sum_k A(i, k) B(k, j) over 2 x 2 tiles, ceil(d/2)^2 <= 256 tiles,
-// one per thread; out(i, j, value) stores an element (only in-range ones).
-// a(i, k) and b(k, j) are only called with in-range indices.
-template <class FA, class FB, class FO>
-__device__ __forceinline__ void tile_product(int d, FA a, FB b, FO out) {
-  const int h = (d + 1) >> 1;
-  const int t = threadIdx.x;
-  if (t >= h * h) return;
-  const int i0 = 2 * (t / h), j0 = 2 * (t % h);
-  const int i1 = i0 + 1 < d ? i0 + 1 : i0, j1 = j0 + 1 < d ? j0 + 1 : j0;
-  double c00x = 0, c00y = 0, c01x = 0, c01y = 0, c10x = 0, c10y = 0, c11x = 0, c11y = 0;
-  for (int k = 0; k < d; ++k) {
-    const double2 a0 = a(i0, k), a1 = a(i1, k), b0 = b(k, j0), b1 = b(k, j1);
-    c00x += a0.x * b0.x - a0.y * b0.y; c00y += a0.x * b0.y + a0.y * b0.x;
-    c01x += a0.x * b1.x - a0.y * b1.y; c01y += a0.x * b1.y + a0.y * b1.x;
-    c10x += a1.x * b0.x - a1.y * b0.y; c10y += a1.x * b0.y + a1.y * b0.x;
-    c11x += a1.x * b1.x - a1.y * b1.y; c11y += a1.x * b1.y + a1.y * b1.x;
-  }
-  out(i0, j0, make_double2(c00x, c00y));
-  if (j1 != j0) out(i0, j1, make_double2(c01x, c01y));
-  if (i1 != i0) out(i1, j0, make_double2(c10x, c10y));
-  if (i1 != i0 && j1 != j0) out(i1, j1, make_double2(c11x, c11y));
-}
 
 template <typename T>
 __global__ void __launch_bounds__(256) block_prec_kernel(const typename Cplx<T>::t *__restrict__ r,
@@ -72,14 +49,14 @@ __global__ void __launch_bounds__(256) block_prec_kernel(const typename Cplx<T>:
     __syncthreads();
     // W = U^H X
     tile_product(
-        d, [&](int i, int k) { const double2 u = Us[k * d + i]; return make_double2(u.x, -u.y); },
+        d, (int)threadIdx.x, [&](int i, int k) { const double2 u = Us[k * d + i]; return make_double2(u.x, -u.y); },
         [&](int k, int j) { return X[k * d + j]; }, [&](int i, int j, double2 v) { W[i * d + j] = v; });
     __syncthreads();
     // X = (W U) / D_a
     const double2 c = decay[a];
     const double2 sh = shifts ? shifts[rr] : make_double2(0.0, 0.0);
     tile_product(
-        d, [&](int i, int k) { return W[i * d + k]; }, [&](int k, int j) { return Us[k * d + j]; },
+        d, (int)threadIdx.x, [&](int i, int k) { return W[i * d + k]; }, [&](int k, int j) { return Us[k * d + j]; },
         [&](int i, int j, double2 v) {
           double dx = -(c.x - sh.x), dy = -(c.y - sh.y) - (E[i] - E[j]);
           if (dx * dx + dy * dy < delta * delta) {
@@ -92,12 +69,12 @@ __global__ void __launch_bounds__(256) block_prec_kernel(const typename Cplx<T>:
     __syncthreads();
     // W = U X
     tile_product(
-        d, [&](int i, int k) { return Us[i * d + k]; }, [&](int k, int j) { return X[k * d + j]; },
+        d, (int)threadIdx.x, [&](int i, int k) { return Us[i * d + k]; }, [&](int k, int j) { return X[k * d + j]; },
         [&](int i, int j, double2 v) { W[i * d + j] = v; });
     __syncthreads();
     // z = W U^H
     tile_product(
-        d, [&](int i, int k) { return W[i * d + k]; },
+        d, (int)threadIdx.x, [&](int i, int k) { return W[i * d + k]; },
         [&](int k, int j) { const double2 u = Us[j * d + k]; return make_double2(u.x, -u.y); },
         [&](int i, int j, double2 v) { z[(base + i * d + j) * R + rr] = T2{(T)v.x, (T)v.y}; });
   }
