@@ -176,6 +176,33 @@ def test_batch_steady_matches_oracle_direct_solve():
         assert np.abs(xs - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
+def test_batch_instances_that_exhaust_their_krylov_space():
+    """Tiny spin-boson instances (tier 1: 16 elements; tier 2: 40) next to a
+    larger one, with restart 30. The tiny ones exhaust their Krylov space
+    within one cycle. There the Gram-matrix formula for |w - V h| cancels,
+    and the batched solver switches those instances to an explicit norm while
+    the others keep the fused normalisation. Every instance must match the
+    oracle's direct solve."""
+    torch = _torch()
+    base = wl.spin_boson()
+    cfgs = []
+    for m_max, eps in ((1, 0.5), (2, 0.3), (1, -0.2), (4, 0.5)):
+        c = dict(base)
+        c["H"] = eps * np.diag([1.0, -1.0]).astype(complex) + 0.5 * np.array([[0, 1], [1, 0]], complex)
+        c["m_max"] = m_max
+        cfgs.append(c)
+    hs, b = _build(cfgs)
+    assert min(h.N * h.d * h.d for h in hs) == 16 and max(h.N * h.d * h.d for h in hs) > 30
+    x, reps = b.steady_state(tol=1e-12, restart=30, max_iter=3000, precond="none", fallback=0)
+    assert all(r["status"] == 0 for r in reps), reps
+    for s, (c, h) in enumerate(zip(cfgs, hs)):
+        om = oracle_model(c)
+        perm = oracle_to_library_perm(om, h)
+        ref = to_blocks(oracle_steady(om.assemble(), om.d), om.N, om.d)
+        xs = x[b.offsets[s]: b.offsets[s + 1]].cpu().numpy().reshape(h.N, h.d, h.d)[perm]
+        assert np.abs(xs - ref).max() <= 1e-10 * np.abs(ref).max(), (s, np.abs(xs - ref).max())
+
+
 def test_batch_graph_replay_equals_eager():
     torch = _torch()
     cfgs = [c for c, _ in _pick_converging(16)]
