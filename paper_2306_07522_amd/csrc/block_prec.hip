@@ -32,10 +32,13 @@ __global__ void __launch_bounds__(256) block_prec_kernel(const typename Cplx<T>:
   using T2 = typename Cplx<T>::t;
   extern __shared__ double2 lds[];
   const int dd = d * d;
+  // LDS rows padded to d + 1 entries: with d entries (320 B for d = 20) the
+  // rows two apart that a tile's lanes read fall on the same banks
+  const int p = d + 1, pd = d * p;
   double2 *Us = lds;           // U, row-major
-  double2 *X = lds + dd;       // working block
-  double2 *W = lds + 2 * dd;   // second working block
-  for (int e = threadIdx.x; e < dd; e += blockDim.x) Us[e] = U[e];
+  double2 *X = lds + pd;       // working block
+  double2 *W = lds + 2 * pd;   // second working block
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) Us[(e / d) * p + e % d] = U[e];
   const int64_t tasks = N * R;
   for (int64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
     const int64_t a = task / R;
@@ -44,19 +47,19 @@ __global__ void __launch_bounds__(256) block_prec_kernel(const typename Cplx<T>:
     __syncthreads();  // U staged; the previous task is done with X and W
     for (int e = threadIdx.x; e < dd; e += blockDim.x) {
       const T2 v = r[(base + e) * R + rr];
-      X[e] = make_double2((double)v.x, (double)v.y);
+      X[(e / d) * p + e % d] = make_double2((double)v.x, (double)v.y);
     }
     __syncthreads();
     // W = U^H X
     tile_product(
-        d, (int)threadIdx.x, [&](int i, int k) { const double2 u = Us[k * d + i]; return make_double2(u.x, -u.y); },
-        [&](int k, int j) { return X[k * d + j]; }, [&](int i, int j, double2 v) { W[i * d + j] = v; });
+        d, (int)threadIdx.x, [&](int i, int k) { const double2 u = Us[k * p + i]; return make_double2(u.x, -u.y); },
+        [&](int k, int j) { return X[k * p + j]; }, [&](int i, int j, double2 v) { W[i * p + j] = v; });
     __syncthreads();
     // X = (W U) / D_a
     const double2 c = decay[a];
     const double2 sh = shifts ? shifts[rr] : make_double2(0.0, 0.0);
     tile_product(
-        d, (int)threadIdx.x, [&](int i, int k) { return W[i * d + k]; }, [&](int k, int j) { return Us[k * d + j]; },
+        d, (int)threadIdx.x, [&](int i, int k) { return W[i * p + k]; }, [&](int k, int j) { return Us[k * p + j]; },
         [&](int i, int j, double2 v) {
           double dx = -(c.x - sh.x), dy = -(c.y - sh.y) - (E[i] - E[j]);
           if (dx * dx + dy * dy < delta * delta) {
@@ -64,18 +67,18 @@ __global__ void __launch_bounds__(256) block_prec_kernel(const typename Cplx<T>:
             dy = 0.0;
           }
           const double inv = 1.0 / (dx * dx + dy * dy);
-          X[i * d + j] = make_double2((v.x * dx + v.y * dy) * inv, (v.y * dx - v.x * dy) * inv);
+          X[i * p + j] = make_double2((v.x * dx + v.y * dy) * inv, (v.y * dx - v.x * dy) * inv);
         });
     __syncthreads();
     // W = U X
     tile_product(
-        d, (int)threadIdx.x, [&](int i, int k) { return Us[i * d + k]; }, [&](int k, int j) { return X[k * d + j]; },
-        [&](int i, int j, double2 v) { W[i * d + j] = v; });
+        d, (int)threadIdx.x, [&](int i, int k) { return Us[i * p + k]; }, [&](int k, int j) { return X[k * p + j]; },
+        [&](int i, int j, double2 v) { W[i * p + j] = v; });
     __syncthreads();
     // z = W U^H
     tile_product(
-        d, (int)threadIdx.x, [&](int i, int k) { return W[i * d + k]; },
-        [&](int k, int j) { const double2 u = Us[j * d + k]; return make_double2(u.x, -u.y); },
+        d, (int)threadIdx.x, [&](int i, int k) { return W[i * p + k]; },
+        [&](int k, int j) { const double2 u = Us[j * p + k]; return make_double2(u.x, -u.y); },
         [&](int i, int j, double2 v) { z[(base + i * d + j) * R + rr] = T2{(T)v.x, (T)v.y}; });
   }
 }
@@ -86,7 +89,7 @@ heom_status block_prec(const void *r, void *z, const Hier &h, int R, const doubl
   if (!h.dev.ueig || !h.dev.eval) return fail(HEOM_ERR_ARG, "block preconditioner: device tables missing");
   const int64_t tasks = h.N * (int64_t)R;
   const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(tasks, 1), 8192);
-  const size_t lds = sizeof(double2) * 3 * h.d * h.d;
+  const size_t lds = sizeof(double2) * 3 * h.d * (h.d + 1);
   // one thread per 2 x 2 tile, whole waves: 128 threads for d = 20, 256 for d = 32
   const int tiles = ((h.d + 1) / 2) * ((h.d + 1) / 2);
   const unsigned threads = (unsigned)std::min(256, (tiles + 63) / 64 * 64);
