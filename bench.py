@@ -578,7 +578,8 @@ def cpu_baseline(seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
+        print(f"bench.py: the HEOM library runs on one GPU; --gpus {args.gpus} is not supported (use --gpus 1)",
+              file=sys.stderr)
         sys.exit(2)
     r = gpu_apply_bench(args)
     h = r["h"]
