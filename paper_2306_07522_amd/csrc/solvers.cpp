@@ -74,6 +74,7 @@ heom_status Gmres<T>::init(WsArena &ws, int64_t n_, int R_, int m_, bool flexibl
   if (!V || !w || !t || (flexible && !Z) || !partial || !hdev || !sdev || !qdev)
     return fail(HEOM_ERR_ARG, "solver workspace too small (see heom_workspace_size)");
   HEOM_TRY(pin.ensure(std::max((size_t)2 * (m + 2) * R, (size_t)(m + 1) * kRotateMax) * sizeof(double2)));
+  HEOM_TRY(pin_up.ensure((size_t)(m + 3) * sizeof(double2)));
   H.assign((size_t)R * (m + 1) * m, cd(0));
   G.assign((size_t)(m + 1) * (m + 1), cd(0));
   cs.assign((size_t)R * m, 0.0);
@@ -135,14 +136,18 @@ heom_status Gmres<T>::gram_step(int j, std::vector<cd> &hc, double &hnorm, hipSt
     hgh += std::conj(hc[i]) * gh;
   }
   w2 += hgh.real();
-  std::vector<double2> hv(j + 1);
+  // uploads from the solver's own pinned staging: the host writes it again
+  // only after the next step's read-back synchronisation, which these copies
+  // precede on the stream, so no wait is needed here
+  double2 *hv = (double2 *)pin_up.p;
+  double2 *scv = hv + (m + 2);
   for (int i = 0; i <= j; ++i) hv[i] = make_double2(hc[i].real(), hc[i].imag());
-  HEOM_HIP_CHECK(hipMemcpyAsync(h1, hv.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
-  double2 scv = make_double2(0.0, 0.0);
+  HEOM_HIP_CHECK(hipMemcpyAsync(h1, hv, sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
+  *scv = make_double2(0.0, 0.0);
   if (std::isfinite(w2) && w2 > 1e-6 * ww) {
     hnorm = std::sqrt(w2);
-    scv.x = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
-    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &scv, sizeof(double2), hipMemcpyHostToDevice, s));
+    scv->x = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
+    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv, sizeof(double2), hipMemcpyHostToDevice, s));
     HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s, sdev));
   } else {  // cancellation: measure the norm directly
     HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, 1, -1.0, s));
@@ -152,11 +157,10 @@ heom_status Gmres<T>::gram_step(int j, std::vector<cd> &hc, double &hnorm, hipSt
     const double v = ((const double2 *)pin.p)[0].x;
     if (!std::isfinite(v)) return fail(HEOM_ERR_NAN, "non-finite Arnoldi norm");
     hnorm = std::sqrt(std::max(v, 0.0));
-    scv.x = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
-    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, &scv, sizeof(double2), hipMemcpyHostToDevice, s));
+    scv->x = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
+    HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv, sizeof(double2), hipMemcpyHostToDevice, s));
     HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, 1, s));
   }
-  HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack
   return HEOM_OK;
 }
 
@@ -304,7 +308,9 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
           }
         }
       }
-      HEOM_HIP_CHECK(hipStreamSynchronize(s));  // scv lives on the host stack
+      // several right-hand sides: the scales above live on the host stack
+      // (one right-hand side uploads from gram_step's pinned staging)
+      if (R > 1) HEOM_HIP_CHECK(hipStreamSynchronize(s));
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
         cd *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m

@@ -55,6 +55,9 @@ struct Gmres {
   // preconditioner, deflate + 1 <= kRotateMax and deflate + 2 <= m
   int deflate = 0;
   PinnedBuf pin;
+  // upload staging of gram_step (coefficients, then the scale at slot m + 2):
+  // pinned and owned here, so the step need not wait for its copies
+  PinnedBuf pin_up;
   std::vector<cd> H, sn, g;
   std::vector<cd> G;  // Gram matrix of the current basis (single right-hand side)
   std::vector<double> cs;
