@@ -1176,7 +1176,7 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
   return HEOM_OK;
 }
 
-heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
+static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
                               int32_t use_graph, void *ws, size_t ws_bytes, void *stream) {
   HEOM_TRY(batch_check(b));
   if (!x_dev || !o || !ws) return fail(HEOM_ERR_ARG, "batch_steady: NULL argument");
@@ -1316,6 +1316,11 @@ heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts
     }
   }
   return ok ? HEOM_OK : fail(HEOM_ERR_NOT_CONVERGED, "batch_steady: some instances did not reach the tolerance");
+}
+
+heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
+                              int32_t use_graph, void *ws, size_t ws_bytes, void *stream) {
+  return guarded([&] { return heom_batch_steady_body(b, x_dev, o, r, use_graph, ws, ws_bytes, stream); });
 }
 
 }  // extern "C"

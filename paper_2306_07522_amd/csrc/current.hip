@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) current_kernel(const double2 *__restrict_
 
 using namespace heom;
 
-extern "C" heom_status heom_current(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
+static heom_status heom_current_body(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
                                     double *out, void *stream) {
   if (!hw || !x_dev || !records || !out || n_rec < 1) return fail(HEOM_ERR_ARG, "current: NULL argument");
   Hier &h = *hw->impl;
@@ -108,4 +108,9 @@ extern "C" heom_status heom_current(heom_hier *hw, const void *x_dev, int32_t n_
   if (d_ops) (void)hipFree(d_ops);
   if (d_out) (void)hipFree(d_out);
   return st;
+}
+
+extern "C" heom_status heom_current(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
+                                    double *out, void *stream) {
+  return guarded([&] { return heom_current_body(hw, x_dev, n_rec, records, out, stream); });
 }

@@ -81,7 +81,7 @@ static heom_status launch_drive(const Hier &h, int precision, const ApplyArgs &a
 
 using namespace heom;
 
-extern "C" heom_status heom_propagate_driven(heom_hier *hw, int32_t precision, void *x_dev, double t0, double dt,
+static heom_status heom_propagate_driven_body(heom_hier *hw, int32_t precision, void *x_dev, double t0, double dt,
                                              int64_t n_steps, int64_t save_every, void *traj_dev, int32_t n_drive,
                                              const double *V_host, heom_drive_fn f, void *ctx, void *ws,
                                              size_t ws_bytes, void *stream) {
@@ -174,4 +174,11 @@ extern "C" heom_status heom_propagate_driven(heom_hier *hw, int32_t precision, v
   }
   HEOM_HIP_CHECK(hipStreamSynchronize(s));  // the drive operators are freed on return
   return HEOM_OK;
+}
+
+extern "C" heom_status heom_propagate_driven(heom_hier *hw, int32_t precision, void *x_dev, double t0, double dt,
+                                             int64_t n_steps, int64_t save_every, void *traj_dev, int32_t n_drive,
+                                             const double *V_host, heom_drive_fn f, void *ctx, void *ws,
+                                             size_t ws_bytes, void *stream) {
+  return guarded([&] { return heom_propagate_driven_body(hw, precision, x_dev, t0, dt, n_steps, save_every, traj_dev, n_drive, V_host, f, ctx, ws, ws_bytes, stream); });
 }

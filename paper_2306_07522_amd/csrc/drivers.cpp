@@ -260,7 +260,7 @@ heom_status heom_workspace_size(const heom_hier *hw, int32_t op, const heom_solv
   return fail(HEOM_ERR_ARG, "unknown workspace op");
 }
 
-heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double dt, int64_t n_steps,
+static heom_status heom_propagate_body(heom_hier *hw, int32_t precision, void *x_dev, double dt, int64_t n_steps,
                            int64_t save_every, void *traj_dev, int32_t graph_steps, void *ws, size_t ws_bytes,
                            void *stream) {
   if (!hw || !x_dev || n_steps < 0 || !(std::isfinite(dt))) return fail(HEOM_ERR_ARG, "propagate: bad arguments");
@@ -366,6 +366,12 @@ heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double
   return HEOM_OK;
 }
 
+heom_status heom_propagate(heom_hier *hw, int32_t precision, void *x_dev, double dt, int64_t n_steps,
+                           int64_t save_every, void *traj_dev, int32_t graph_steps, void *ws, size_t ws_bytes,
+                           void *stream) {
+  return guarded([&] { return heom_propagate_body(hw, precision, x_dev, dt, n_steps, save_every, traj_dev, graph_steps, ws, ws_bytes, stream); });
+}
+
 heom_status heom_steady_residual(heom_hier *hw, const void *x_dev, void *r_dev, void *stream) {
   if (!hw || !x_dev || !r_dev || x_dev == r_dev) return fail(HEOM_ERR_ARG, "steady_residual: bad arguments");
   Hier &h = *hw->impl;
@@ -389,7 +395,7 @@ heom_status heom_vector_axpby(int32_t precision, const void *x_dev, double alpha
   return fail(HEOM_ERR_ARG, "bad precision");
 }
 
-heom_status heom_precondition(heom_hier *hw, int32_t precision, int32_t precond, const void *r_dev, void *z_dev,
+static heom_status heom_precondition_body(heom_hier *hw, int32_t precision, int32_t precond, const void *r_dev, void *z_dev,
                               int32_t n_rhs, const void *shifts_dev, int32_t border, void *stream) {
   if (!hw || !r_dev || !z_dev) return fail(HEOM_ERR_ARG, "precondition: NULL argument");
   if (r_dev == z_dev) return fail(HEOM_ERR_ARG, "precondition: r and z must not alias");
@@ -410,7 +416,12 @@ heom_status heom_precondition(heom_hier *hw, int32_t precision, int32_t precond,
               : jacobi<float>(r_dev, z_dev, h, n_rhs, sh, border, s, mod);
 }
 
-heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, heom_solver_report *r, void *ws,
+heom_status heom_precondition(heom_hier *hw, int32_t precision, int32_t precond, const void *r_dev, void *z_dev,
+                              int32_t n_rhs, const void *shifts_dev, int32_t border, void *stream) {
+  return guarded([&] { return heom_precondition_body(hw, precision, precond, r_dev, z_dev, n_rhs, shifts_dev, border, stream); });
+}
+
+static heom_status heom_steady_body(heom_hier *hw, void *x_dev, const heom_solver_opts *o, heom_solver_report *r, void *ws,
                         size_t ws_bytes, void *stream) {
   if (!hw || !x_dev) return fail(HEOM_ERR_ARG, "steady: NULL argument");
   HEOM_TRY(check_opts(o));
@@ -454,7 +465,12 @@ heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, h
   return st;
 }
 
-heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev, int32_t kind, const double *op,
+heom_status heom_steady(heom_hier *hw, void *x_dev, const heom_solver_opts *o, heom_solver_report *r, void *ws,
+                        size_t ws_bytes, void *stream) {
+  return guarded([&] { return heom_steady_body(hw, x_dev, o, r, ws, ws_bytes, stream); });
+}
+
+static heom_status heom_spectrum_body(heom_hier *even, heom_hier *odd, const void *x_ss_dev, int32_t kind, const double *op,
                           const double *omega, int64_t n_omega, double *out_host, const heom_solver_opts *o,
                           heom_solver_report *r, void *ws, size_t ws_bytes, void *stream) {
   if (!even || !x_ss_dev || !op || !omega || !out_host || n_omega < 0) return fail(HEOM_ERR_ARG, "spectrum: NULL argument");
@@ -539,6 +555,12 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
     for (int q = 0; q < nw; ++q) out_host[w0 + q] = kind == 0 ? outh[q] + outh[nw + q] : outh[q];
   }
   return worst == HEOM_OK ? HEOM_OK : fail(worst, "spectrum: some frequencies did not converge");
+}
+
+heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev, int32_t kind, const double *op,
+                          const double *omega, int64_t n_omega, double *out_host, const heom_solver_opts *o,
+                          heom_solver_report *r, void *ws, size_t ws_bytes, void *stream) {
+  return guarded([&] { return heom_spectrum_body(even, odd, x_ss_dev, kind, op, omega, n_omega, out_host, o, r, ws, ws_bytes, stream); });
 }
 
 }  // extern "C"

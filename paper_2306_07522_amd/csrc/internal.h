@@ -6,6 +6,8 @@
 #include <complex>
 #include <cstdint>
 #include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -18,6 +20,22 @@ using cd = std::complex<double>;
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
 heom_status fail(heom_status s, const std::string &msg);
+
+// Runs the body of a C entry point so that no C++ exception crosses the C
+// boundary: host allocation failures become HEOM_ERR_ALLOC, anything else
+// HEOM_ERR_ARG with its message.
+template <class F>
+heom_status guarded(F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail(HEOM_ERR_ALLOC, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(HEOM_ERR_ARG, e.what());
+  } catch (...) {
+    return fail(HEOM_ERR_ARG, "unexpected host error");
+  }
+}
 
 #define HEOM_HIP_CHECK(expr)                                                         \
   do {                                                                               \

@@ -117,7 +117,7 @@ heom_status launch_lindblad(Hier &h, int precision, const ApplyArgs &a, hipStrea
 
 using namespace heom;
 
-extern "C" heom_status heom_hierarchy_set_lindblad(heom_hier *hw, int32_t n_ops, const double *F) {
+static heom_status heom_hierarchy_set_lindblad_body(heom_hier *hw, int32_t n_ops, const double *F) {
   if (!hw || n_ops < 0 || (n_ops > 0 && !F)) return fail(HEOM_ERR_ARG, "set_lindblad: NULL argument");
   Hier &h = *hw->impl;
   const int d = h.d;
@@ -150,4 +150,8 @@ extern "C" heom_status heom_hierarchy_set_lindblad(heom_hier *hw, int32_t n_ops,
   free_device(h);  // tables are uploaded again, with the jump operators, on the next use
   h.lind = std::move(ops);
   return HEOM_OK;
+}
+
+extern "C" heom_status heom_hierarchy_set_lindblad(heom_hier *hw, int32_t n_ops, const double *F) {
+  return guarded([&] { return heom_hierarchy_set_lindblad_body(hw, n_ops, F); });
 }

@@ -419,10 +419,15 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
       const int nth = (int)std::min<int64_t>(kMaxShiftThreads, std::max<int64_t>(1, (int64_t)K * kk * kk / 100000));
       std::vector<char> any_t(nth, 0), sing_t(nth, 0);
       std::vector<double> worst_t(nth, 0.0);
+      std::vector<char> fail_t(nth, 0);
       auto body = [&](int t) {
         bool a = false, sg = false;
         double w = 0.0;
-        run_shifts((int)((int64_t)K * t / nth), (int)((int64_t)K * (t + 1) / nth), a, w, sg);
+        try {  // nothing may escape a worker thread (that would end the process)
+          run_shifts((int)((int64_t)K * t / nth), (int)((int64_t)K * (t + 1) / nth), a, w, sg);
+        } catch (...) {
+          fail_t[t] = 1;
+        }
         any_t[t] = a;
         sing_t[t] = sg;
         worst_t[t] = w;
@@ -438,6 +443,7 @@ static heom_status shifted_fom(Hier &h, const double2 *x_ss, const double2 *opsd
       body(0);
       for (auto &th : pool) th.join();
       for (int t = 0; t < nth; ++t) {
+        if (fail_t[t]) return fail(HEOM_ERR_ALLOC, "spectrum: host memory for the projected solves");
         any = any || any_t[t];
         singular = singular || sing_t[t];
         worst_est = std::max(worst_est, worst_t[t]);
