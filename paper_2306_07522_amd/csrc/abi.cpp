@@ -175,7 +175,7 @@ heom_status heom_hierarchy_tables(const heom_hier *hw, double *decay, int64_t *r
   return HEOM_OK;
 }
 
-heom_status heom_apply(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+static heom_status heom_apply_body(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
                        const double *shift, void *stream) {
   if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");
   if (x_dev == y_dev) return fail(HEOM_ERR_ARG, "apply: x and y must not alias");
@@ -187,7 +187,12 @@ heom_status heom_apply(heom_hier *hw, int32_t precision, const void *x_dev, void
   return launch_apply(*hw->impl, precision, a, (hipStream_t)stream);
 }
 
-heom_status heom_apply_shifted(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+heom_status heom_apply(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                       const double *shift, void *stream) {
+  return guarded([&] { return heom_apply_body(hw, precision, x_dev, y_dev, n_rhs, shift, stream); });
+}
+
+static heom_status heom_apply_shifted_body(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
                                const void *shifts_dev, void *stream) {
   if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");
   if (x_dev == y_dev) return fail(HEOM_ERR_ARG, "apply: x and y must not alias");
@@ -200,7 +205,12 @@ heom_status heom_apply_shifted(heom_hier *hw, int32_t precision, const void *x_d
   return launch_apply(*hw->impl, precision, a, (hipStream_t)stream);
 }
 
-heom_status heom_apply_steady_operator(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev,
+heom_status heom_apply_shifted(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                               const void *shifts_dev, void *stream) {
+  return guarded([&] { return heom_apply_shifted_body(hw, precision, x_dev, y_dev, n_rhs, shifts_dev, stream); });
+}
+
+static heom_status heom_apply_steady_operator_body(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev,
                                        void *stream) {
   if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");
   if (x_dev == y_dev) return fail(HEOM_ERR_ARG, "apply: x and y must not alias");
@@ -212,7 +222,12 @@ heom_status heom_apply_steady_operator(heom_hier *hw, int32_t precision, const v
   return launch_apply(*hw->impl, precision, a, (hipStream_t)stream);
 }
 
-heom_status heom_apply_tiled(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+heom_status heom_apply_steady_operator(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev,
+                                       void *stream) {
+  return guarded([&] { return heom_apply_steady_operator_body(hw, precision, x_dev, y_dev, stream); });
+}
+
+static heom_status heom_apply_tiled_body(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
                              const double *shift, int32_t n_chunks, void *stream) {
   if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");
   Hier &h = *hw->impl;
@@ -223,6 +238,11 @@ heom_status heom_apply_tiled(heom_hier *hw, int32_t precision, const void *x_dev
   a.n_rhs = n_rhs;
   a.shift0 = shift ? cd(shift[0], shift[1]) : cd(0.0);
   return launch_apply_tiled(h, precision, a, n_chunks, (hipStream_t)stream);
+}
+
+heom_status heom_apply_tiled(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                             const double *shift, int32_t n_chunks, void *stream) {
+  return guarded([&] { return heom_apply_tiled_body(hw, precision, x_dev, y_dev, n_rhs, shift, n_chunks, stream); });
 }
 
 }  // extern "C"

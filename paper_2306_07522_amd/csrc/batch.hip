@@ -956,7 +956,7 @@ static heom_status batch_check(const heom_batch *b) {
 // ----------------------------------------------------------------- ABI
 extern "C" {
 
-heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch **out) {
+static heom_status heom_batch_create_body(int32_t n_inst, heom_hier *const *inst, heom_batch **out) {
   if (!out || n_inst <= 0 || !inst) return fail(HEOM_ERR_ARG, "batch_create: bad arguments");
   *out = nullptr;
   for (int s = 0; s < n_inst; ++s) {  // argument checks before any device work
@@ -1088,6 +1088,10 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
   return HEOM_OK;
 }
 
+heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch **out) {
+  return guarded([&] { return heom_batch_create_body(n_inst, inst, out); });
+}
+
 void heom_batch_free(heom_batch *b) { delete b; }
 
 heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_tiles, int32_t *grid, int32_t *order) {
@@ -1099,7 +1103,7 @@ heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_ti
   return HEOM_OK;
 }
 
-heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t border,
+static heom_status heom_batch_apply_body(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t border,
                              void *stream) {
   HEOM_TRY(batch_check(b));
   if (!x_dev || !y_dev) return fail(HEOM_ERR_ARG, "batch_apply: NULL vector");
@@ -1109,7 +1113,12 @@ heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev
   return fail(HEOM_ERR_ARG, "batch_apply: precision must be FP64 or FP32");
 }
 
-heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
+heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t border,
+                             void *stream) {
+  return guarded([&] { return heom_batch_apply_body(b, precision, x_dev, y_dev, border, stream); });
+}
+
+static heom_status heom_batch_tune_body(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
                             double *ms_default, double *ms_best, void *stream) {
   HEOM_TRY(batch_check(b));
   if (!x_dev || !y_dev || reps < 1) return fail(HEOM_ERR_ARG, "batch_tune: bad arguments");
@@ -1159,6 +1168,11 @@ heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev,
   if (ms_default) *ms_default = def;
   if (ms_best) *ms_best = best;
   return HEOM_OK;
+}
+
+heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
+                            double *ms_default, double *ms_best, void *stream) {
+  return guarded([&] { return heom_batch_tune_body(b, precision, x_dev, y_dev, reps, ms_default, ms_best, stream); });
 }
 
 heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opts *o, size_t *bytes) {

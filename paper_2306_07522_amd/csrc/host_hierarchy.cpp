@@ -104,7 +104,7 @@ static heom_status dist_params(int fermi, int method, int n, std::vector<double>
 
 using namespace heom;
 
-extern "C" heom_status heom_pade_params(int32_t kind, int32_t method, int32_t n, double *kappa, double *zeta) {
+static heom_status heom_pade_params_body(int32_t kind, int32_t method, int32_t n, double *kappa, double *zeta) {
   if (n < 0 || n > 64 || (n > 0 && (!kappa || !zeta))) return fail(HEOM_ERR_ARG, "pade_params: bad n or pointers");
   if (kind != HEOM_FERMION && kind != HEOM_BOSON) return fail(HEOM_ERR_ARG, "pade_params: bad kind");
   std::vector<double> k, z;
@@ -113,7 +113,11 @@ extern "C" heom_status heom_pade_params(int32_t kind, int32_t method, int32_t n,
   return HEOM_OK;
 }
 
-extern "C" heom_status heom_exponents_lorentz(double Gamma, double W, double mu, double T, int32_t n_exp,
+extern "C" heom_status heom_pade_params(int32_t kind, int32_t method, int32_t n, double *kappa, double *zeta) {
+  return guarded([&] { return heom_pade_params_body(kind, method, n, kappa, zeta); });
+}
+
+static heom_status heom_exponents_lorentz_body(double Gamma, double W, double mu, double T, int32_t n_exp,
                                               int32_t method, double *eta_p, double *gam_p, double *eta_m,
                                               double *gam_m) {
   if (n_exp < 1 || n_exp > 65 || T <= 0 || W <= 0 || !eta_p || !gam_p || !eta_m || !gam_m)
@@ -143,7 +147,13 @@ extern "C" heom_status heom_exponents_lorentz(double Gamma, double W, double mu,
   return HEOM_OK;
 }
 
-extern "C" heom_status heom_exponents_drude_lorentz(double lam, double gamma, double T, int32_t n_exp,
+extern "C" heom_status heom_exponents_lorentz(double Gamma, double W, double mu, double T, int32_t n_exp,
+                                              int32_t method, double *eta_p, double *gam_p, double *eta_m,
+                                              double *gam_m) {
+  return guarded([&] { return heom_exponents_lorentz_body(Gamma, W, mu, T, n_exp, method, eta_p, gam_p, eta_m, gam_m); });
+}
+
+static heom_status heom_exponents_drude_lorentz_body(double lam, double gamma, double T, int32_t n_exp,
                                                     int32_t method, double *xi, double *chi) {
   if (n_exp < 1 || n_exp > 65 || T <= 0 || gamma <= 0 || !xi || !chi)
     return fail(HEOM_ERR_ARG, "exponents_drude_lorentz: bad arguments");
@@ -163,6 +173,11 @@ extern "C" heom_status heom_exponents_drude_lorentz(double lam, double gamma, do
     chi[2 * l + 1] = 0.0;
   }
   return HEOM_OK;
+}
+
+extern "C" heom_status heom_exponents_drude_lorentz(double lam, double gamma, double T, int32_t n_exp,
+                                                    int32_t method, double *xi, double *chi) {
+  return guarded([&] { return heom_exponents_drude_lorentz_body(lam, gamma, T, n_exp, method, xi, chi); });
 }
 
 namespace heom {

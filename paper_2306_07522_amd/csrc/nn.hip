@@ -474,7 +474,7 @@ using namespace heom;
 
 extern "C" {
 
-heom_status heom_nn_create(int32_t d, int32_t hidden, uint64_t seed, heom_nn **out) {
+static heom_status heom_nn_create_body(int32_t d, int32_t hidden, uint64_t seed, heom_nn **out) {
   if (!out || d < 1 || d > 32 || hidden < 32 || hidden > 256 || hidden % 32)
     return fail(HEOM_ERR_ARG, "nn_create: d in [1, 32], hidden a multiple of 32 in [32, 256]");
   *out = nullptr;
@@ -527,6 +527,10 @@ heom_status heom_nn_create(int32_t d, int32_t hidden, uint64_t seed, heom_nn **o
   return HEOM_OK;
 }
 
+heom_status heom_nn_create(int32_t d, int32_t hidden, uint64_t seed, heom_nn **out) {
+  return guarded([&] { return heom_nn_create_body(d, hidden, seed, out); });
+}
+
 void heom_nn_free(heom_nn *n) {
   if (!n) return;
   for (int l = 0; l < 3; ++l) {
@@ -573,7 +577,7 @@ heom_status heom_nn_set_params(heom_nn *n, const float *host) {
   return HEOM_OK;
 }
 
-heom_status heom_nn_save(const heom_nn *n, const char *path) {
+static heom_status heom_nn_save_body(const heom_nn *n, const char *path) {
   if (!n || !path) return fail(HEOM_ERR_ARG, "NULL argument");
   std::vector<float> p(param_count(*n));
   HEOM_TRY(heom_nn_get_params(n, p.data()));
@@ -585,7 +589,11 @@ heom_status heom_nn_save(const heom_nn *n, const char *path) {
   return ok ? HEOM_OK : fail(HEOM_ERR_ARG, "write failed");
 }
 
-heom_status heom_nn_load(const char *path, heom_nn **out) {
+heom_status heom_nn_save(const heom_nn *n, const char *path) {
+  return guarded([&] { return heom_nn_save_body(n, path); });
+}
+
+static heom_status heom_nn_load_body(const char *path, heom_nn **out) {
   if (!path || !out) return fail(HEOM_ERR_ARG, "NULL argument");
   FILE *f = std::fopen(path, "rb");
   if (!f) return fail(HEOM_ERR_ARG, std::string("cannot open ") + path);
@@ -607,7 +615,11 @@ heom_status heom_nn_load(const char *path, heom_nn **out) {
   return HEOM_OK;
 }
 
-heom_status heom_nn_pairs(heom_hier *hw, const heom_nn *n, const void *r_dev, const void *e_dev, int32_t border,
+heom_status heom_nn_load(const char *path, heom_nn **out) {
+  return guarded([&] { return heom_nn_load_body(path, out); });
+}
+
+static heom_status heom_nn_pairs_body(heom_hier *hw, const heom_nn *n, const void *r_dev, const void *e_dev, int32_t border,
                           void *X_dev, void *T_dev, void *stream) {
   if (!hw || !n || !r_dev || !X_dev || (e_dev && !T_dev)) return fail(HEOM_ERR_ARG, "nn_pairs: NULL argument");
   Hier &h = *hw->impl;
@@ -627,7 +639,12 @@ heom_status heom_nn_pairs(heom_hier *hw, const heom_nn *n, const void *r_dev, co
   return HEOM_OK;
 }
 
-heom_status heom_nn_forward(const heom_nn *n, const void *X_dev, int64_t rows, void *O_dev, void *stream) {
+heom_status heom_nn_pairs(heom_hier *hw, const heom_nn *n, const void *r_dev, const void *e_dev, int32_t border,
+                          void *X_dev, void *T_dev, void *stream) {
+  return guarded([&] { return heom_nn_pairs_body(hw, n, r_dev, e_dev, border, X_dev, T_dev, stream); });
+}
+
+static heom_status heom_nn_forward_body(const heom_nn *n, const void *X_dev, int64_t rows, void *O_dev, void *stream) {
   if (!n || !X_dev || !O_dev || rows < 0 || rows > 0x7fffffffLL) return fail(HEOM_ERR_ARG, "nn_forward: bad arguments");
   DevScratch ds;
   FwdBuffers f;
@@ -641,7 +658,11 @@ heom_status heom_nn_forward(const heom_nn *n, const void *X_dev, int64_t rows, v
   return HEOM_OK;
 }
 
-heom_status heom_nn_gradients(const heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, float *grads_host,
+heom_status heom_nn_forward(const heom_nn *n, const void *X_dev, int64_t rows, void *O_dev, void *stream) {
+  return guarded([&] { return heom_nn_forward_body(n, X_dev, rows, O_dev, stream); });
+}
+
+static heom_status heom_nn_gradients_body(const heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, float *grads_host,
                               float *loss_host, void *stream) {
   if (!n || !X_dev || !T_dev || rows <= 0 || rows > 0x7fffffffLL) return fail(HEOM_ERR_ARG, "nn_gradients: bad arguments");
   hipStream_t s = (hipStream_t)stream;
@@ -669,7 +690,12 @@ heom_status heom_nn_gradients(const heom_nn *n, const void *X_dev, const void *T
   return HEOM_OK;
 }
 
-heom_status heom_nn_train(heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset, int32_t epochs,
+heom_status heom_nn_gradients(const heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, float *grads_host,
+                              float *loss_host, void *stream) {
+  return guarded([&] { return heom_nn_gradients_body(n, X_dev, T_dev, rows, grads_host, loss_host, stream); });
+}
+
+static heom_status heom_nn_train_body(heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset, int32_t epochs,
                           int32_t batch, double lr, uint64_t seed, float *loss_per_epoch, void *stream) {
   if (!n || !X_dev || !T_dev || rows <= 0 || epochs < 0 || batch <= 0 || !(lr > 0))
     return fail(HEOM_ERR_ARG, "nn_train: bad arguments");
@@ -729,6 +755,11 @@ heom_status heom_nn_train(heom_nn *n, const void *X_dev, const void *T_dev, int6
   }
   HEOM_HIP_CHECK(hipStreamSynchronize(s));
   return HEOM_OK;
+}
+
+heom_status heom_nn_train(heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset, int32_t epochs,
+                          int32_t batch, double lr, uint64_t seed, float *loss_per_epoch, void *stream) {
+  return guarded([&] { return heom_nn_train_body(n, X_dev, T_dev, rows, subset, epochs, batch, lr, seed, loss_per_epoch, stream); });
 }
 
 }  // extern "C"
