@@ -74,7 +74,7 @@ heom_status Gmres<T>::init(WsArena &ws, int64_t n_, int R_, int m_, bool flexibl
   if (!V || !w || !t || (flexible && !Z) || !partial || !hdev || !sdev || !qdev)
     return fail(HEOM_ERR_ARG, "solver workspace too small (see heom_workspace_size)");
   HEOM_TRY(pin.ensure(std::max((size_t)2 * (m + 2) * R, (size_t)(m + 1) * kRotateMax) * sizeof(double2)));
-  HEOM_TRY(pin_up.ensure((size_t)(m + 3) * sizeof(double2)));
+  HEOM_TRY(pin_up.ensure((size_t)(m + 3 + R) * sizeof(double2)));
   H.assign((size_t)R * (m + 1) * m, cd(0));
   G.assign((size_t)(m + 1) * (m + 1), cd(0));
   cs.assign((size_t)R * m, 0.0);
@@ -243,7 +243,10 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
       const size_t hb = sizeof(double2) * (size_t)(j + 2) * R;
       std::vector<double2> hv1((size_t)(j + 2) * R), hv2((size_t)(j + 2) * R, make_double2(0.0, 0.0));
       std::vector<double> hn(R, 0.0);
-      std::vector<double2> scv(R, make_double2(0.0, 0.0));
+      // per-RHS scales, uploaded from the solver's pinned staging (slots
+      // m + 3 ...): the host rewrites them only after the next iteration's
+      // read-back synchronisation
+      double2 *scv = (double2 *)pin_up.p + (m + 3);
       auto scales = [&]() {
         for (int r = 0; r < R; ++r) scv[r] = make_double2(active[r] && hn[r] > 1e-300 ? 1.0 / hn[r] : 0.0, 0.0);
       };
@@ -272,7 +275,7 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
         }
         if (!reorth) {
           scales();
-          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+          HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv, sizeof(double2) * R, hipMemcpyHostToDevice, s));
           HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s, sdev));
         } else {
           HEOM_TRY(basis_update<T>(V, nr, j + 1, h1, vn, n, R, -1.0, s));
@@ -290,7 +293,7 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
           }
           if (!explicit_norm) {
             scales();
-            HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+            HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv, sizeof(double2) * R, hipMemcpyHostToDevice, s));
             HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s, sdev));
           } else {
             HEOM_TRY(basis_update<T>(V, nr, j + 1, h2, vn, n, R, -1.0, s));
@@ -303,14 +306,11 @@ heom_status Gmres<T>::solve(const T2 *b, T2 *x, double tol, int max_iter, bool x
               hn[r] = std::sqrt(std::max(v, 0.0));
             }
             scales();
-            HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv.data(), sizeof(double2) * R, hipMemcpyHostToDevice, s));
+            HEOM_HIP_CHECK(hipMemcpyAsync(sdev, scv, sizeof(double2) * R, hipMemcpyHostToDevice, s));
             HEOM_TRY(scale_vec<T>(vn, sdev, vn, n, R, s));
           }
         }
       }
-      // several right-hand sides: the scales above live on the host stack
-      // (one right-hand side uploads from gram_step's pinned staging)
-      if (R > 1) HEOM_HIP_CHECK(hipStreamSynchronize(s));
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
         cd *Hc = &H[((size_t)r * (m + 1)) * m];  // column-major (m+1) x m
