@@ -414,7 +414,13 @@ def collect_pairs(h, net, snapshots=(10, 30, 60), x_star=None, restart=60, tol=1
 
 def spectrum(even, odd, x_ss, op, omegas, kind="dos", stream=None, allow_not_converged=False, **opts):
     """Density of states (kind 'dos', odd-parity `odd`) or power spectral
-    density (kind 'psd') of operator `op` at the given frequencies.  With
+    density (kind 'psd') of operator `op` at the given frequencies.
+
+    opts are solver options (solver_opts).  mode='shifted' with
+    precond='none' serves every frequency from one Krylov space (multi-shift
+    FOM; deflate=k > 0 adds thick restarts keeping k Schur vectors); the other
+    modes solve per frequency, rhs_chunk frequencies per multi-RHS solve
+    (0, the default, lets the library choose from the hierarchy size).  With
     allow_not_converged the values are returned when some frequency misses
     the tolerance (report status 4)."""
     o = solver_opts(**opts)
