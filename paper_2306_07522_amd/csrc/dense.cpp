@@ -339,4 +339,64 @@ int orthonormalise_columns(int rows, int cols, std::vector<cd> &P, double drop_t
   return kept;
 }
 
+bool HessSolver::solve(const std::vector<cd> &H, int ld, int k, cd sigma, const std::vector<cd> &rhs, std::vector<cd> &y) {
+  ar.resize((size_t)k * k);
+  ai.resize((size_t)k * k);
+  br.resize(k);
+  bi.resize(k);
+  for (int c = 0; c < k; ++c)
+    for (int r = 0; r <= std::min(c + 1, k - 1); ++r) {  // rows below c + 1 are never read
+      const cd v = H[(size_t)c * ld + r];
+      ar[(size_t)c * k + r] = v.real();
+      ai[(size_t)c * k + r] = v.imag();
+    }
+  for (int i = 0; i < k; ++i) {
+    ar[(size_t)i * k + i] += sigma.real();
+    ai[(size_t)i * k + i] += sigma.imag();
+    br[i] = rhs[i].real();
+    bi[i] = rhs[i].imag();
+  }
+  for (int i = 0; i + 1 < k; ++i) {
+    // rows i and i+1 only (Hessenberg); pivot on the larger modulus
+    const size_t d0 = (size_t)i * k + i, d1 = d0 + 1;
+    if (ar[d1] * ar[d1] + ai[d1] * ai[d1] > ar[d0] * ar[d0] + ai[d0] * ai[d0]) {
+      for (int c = i; c < k; ++c) {
+        std::swap(ar[(size_t)c * k + i], ar[(size_t)c * k + i + 1]);
+        std::swap(ai[(size_t)c * k + i], ai[(size_t)c * k + i + 1]);
+      }
+      std::swap(br[i], br[i + 1]);
+      std::swap(bi[i], bi[i + 1]);
+    }
+    const double pr = ar[d0], pi = ai[d0], pn = pr * pr + pi * pi;
+    if (pn == 0.0) return false;
+    // f = A[i+1][i] / p
+    const double fr = (ar[d1] * pr + ai[d1] * pi) / pn, fi = (ai[d1] * pr - ar[d1] * pi) / pn;
+    if (fr != 0.0 || fi != 0.0) {
+      for (int c = i; c < k; ++c) {
+        const size_t u = (size_t)c * k + i;
+        ar[u + 1] -= fr * ar[u] - fi * ai[u];
+        ai[u + 1] -= fr * ai[u] + fi * ar[u];
+      }
+      br[i + 1] -= fr * br[i] - fi * bi[i];
+      bi[i + 1] -= fr * bi[i] + fi * br[i];
+    }
+  }
+  y.resize(k);
+  for (int i = k - 1; i >= 0; --i) {
+    double sr = br[i], si = bi[i];
+    for (int c = i + 1; c < k; ++c) {
+      const size_t u = (size_t)c * k + i;
+      sr -= ar[u] * y[c].real() - ai[u] * y[c].imag();
+      si -= ar[u] * y[c].imag() + ai[u] * y[c].real();
+    }
+    const size_t dd = (size_t)i * k + i;
+    const double pr = ar[dd], pi = ai[dd], pn = pr * pr + pi * pi;
+    if (pn == 0.0) return false;
+    const double yr = (sr * pr + si * pi) / pn, yi = (si * pr - sr * pi) / pn;
+    if (!std::isfinite(yr) || !std::isfinite(yi)) return false;
+    y[i] = cd(yr, yi);
+  }
+  return true;
+}
+
 }  // namespace heom

@@ -33,6 +33,18 @@ bool schur_complex(int n, const std::vector<cd> &A, std::vector<cd> &T, std::vec
 // columns of Z then span the invariant subspace of the k flagged eigenvalues.
 void schur_reorder(int n, std::vector<cd> &T, std::vector<cd> &Z, const std::vector<char> &sel);
 
+// Solves (H + sigma I) y = rhs for an upper-Hessenberg k x k matrix H
+// (column-major, leading dimension ld; entries below the subdiagonal are not
+// read) by Gaussian elimination with partial pivoting between neighbouring
+// rows, in plain real arithmetic (the projected entries of the Krylov
+// solvers are finite and moderate, so the special-case handling of library
+// complex products and quotients is not needed); the buffers are kept
+// between calls.  Returns false when singular or not finite.
+struct HessSolver {
+  std::vector<double> ar, ai, br, bi;
+  bool solve(const std::vector<cd> &H, int ld, int k, cd sigma, const std::vector<cd> &rhs, std::vector<cd> &y);
+};
+
 // Eigen-decomposition of a Hermitian n x n matrix A = U diag(E) U^H by
 // cyclic complex Jacobi rotations (orthonormal U also for degenerate
 // eigenvalues); E ascending.  Returns false if the sweeps did not converge.

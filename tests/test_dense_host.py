@@ -1,7 +1,8 @@
 """Host dense linear algebra of the Krylov solvers (csrc/dense.cpp) against
 numpy: the general complex eigen-solver (harmonic Ritz pairs of deflated
-restarting), the complex Schur form with reordering (thick restarts of the
-multi-shift solver), the Hermitian Jacobi eigen-solver (eigenbasis of H for the block
+restarting), the complex Schur form with reordering and the shifted
+Hessenberg solves (thick restarts of the multi-shift solver), the Hermitian
+Jacobi eigen-solver (eigenbasis of H for the block
 preconditioner), the pivoted LU solve and the column orthonormalisation.
 
 dense.cpp is plain C++ with no HIP dependency; the test builds it with g++
@@ -69,6 +70,15 @@ int t_hess(int n, double *a, double *z) {
   }
   return 0;
 }
+int t_hsolve(int k, const double *h, double sr, double si, const double *rhs, double *y) {
+  std::vector<cd> H(k * k), R(k), Y;
+  for (int i = 0; i < k * k; ++i) H[i] = cd(h[2 * i], h[2 * i + 1]);
+  for (int i = 0; i < k; ++i) R[i] = cd(rhs[2 * i], rhs[2 * i + 1]);
+  heom::HessSolver hs;
+  if (!hs.solve(H, k, k, cd(sr, si), R, Y)) return 1;
+  for (int i = 0; i < k; ++i) { y[2 * i] = Y[i].real(); y[2 * i + 1] = Y[i].imag(); }
+  return 0;
+}
 int t_orth(int rows, int cols, double *p, double tol) {
   std::vector<cd> P(rows * cols);
   for (int i = 0; i < rows * cols; ++i) P[i] = cd(p[2 * i], p[2 * i + 1]);
@@ -96,6 +106,7 @@ def dense(tmp_path_factory):
     lib.t_orth.argtypes = [C.c_int, C.c_int, dp, C.c_double]
     lib.t_schur.argtypes = [C.c_int, dp, C.c_char_p, dp, dp, C.c_int]
     lib.t_hess.argtypes = [C.c_int, dp, dp]
+    lib.t_hsolve.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp, dp]
     return lib
 
 
@@ -284,3 +295,33 @@ def test_hessenberg_reduce(dense, n):
     dense.t_hess(n, _ptr(a), _ptr(z))
     H2 = a.view(np.complex128).reshape(n, n, order="F")
     assert np.allclose(np.abs(H2), np.abs(Hh), atol=1e-13 * n)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 20, 40])
+def test_shifted_hessenberg_solve(dense, k):
+    """(H + sigma I) y = rhs for upper-Hessenberg H at several complex shifts
+    (the per-frequency projected systems of the multi-shift solver), against
+    numpy; entries below the subdiagonal are ignored; a zero pivot is
+    reported."""
+    rng = np.random.default_rng(70 + k)
+    H = np.triu(rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)), -1)
+    Hfull = H + np.tril(rng.standard_normal((k, k)), -2)   # junk below the subdiagonal: must not be read
+    rhs = rng.standard_normal(k) + 1j * rng.standard_normal(k)
+    for sigma in (0.0, 0.7j, -1.3 + 2.0j, 1e-3):
+        y = np.zeros(2 * k)
+        st = dense.t_hsolve(k, _ptr(_colmajor(Hfull)), sigma.real if isinstance(sigma, complex) else sigma,
+                            sigma.imag if isinstance(sigma, complex) else 0.0,
+                            _ptr(np.ascontiguousarray(rhs.view(np.float64))), _ptr(y))
+        assert st == 0
+        ref = np.linalg.solve(H + sigma * np.eye(k), rhs)
+        assert np.abs(y.view(np.complex128) - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+    # neighbouring-row pivoting: a zero diagonal entry with a nonzero subdiagonal one
+    if k >= 2:
+        Hp = H.copy()
+        Hp[0, 0] = 0.0
+        y = np.zeros(2 * k)
+        assert dense.t_hsolve(k, _ptr(_colmajor(Hp)), 0.0, 0.0, _ptr(np.ascontiguousarray(rhs.view(np.float64))), _ptr(y)) == 0
+        assert np.allclose(y.view(np.complex128), np.linalg.solve(Hp, rhs), rtol=1e-9, atol=1e-11)
+    Z = np.zeros((k, k), complex)
+    y = np.zeros(2 * k)
+    assert dense.t_hsolve(k, _ptr(_colmajor(Z)), 0.0, 0.0, _ptr(np.ascontiguousarray(rhs.view(np.float64))), _ptr(y)) == 1
