@@ -118,6 +118,33 @@ def gpu_apply_bench(args):
                 bytes=nbytes)
 
 
+def other_precision_apply(h, precision, tiled_arg, steps=20, warmup=3):
+    """Average kernel time (HIP events on the launch stream) and algorithmic
+    GB/s of the same apply in the given precision."""
+    import torch
+    dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    w = 16 if precision == "fp64" else 8
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn((h.N, h.d, h.d), dtype=dtype, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    tiled = None if tiled_arg < 0 else tiled_arg
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        h.apply(x, y, tiled=tiled, stream=stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        h.apply(x, y, tiled=tiled, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    nbytes = algorithmic_bytes(h, w)
+    del x, y
+    return {"precision": precision, "kernel_ms_avg": round(ms, 4), "bytes_per_step": nbytes,
+            "gbs_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 2),
+            "frac_of_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def _progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -610,6 +637,12 @@ def main():
         "kernel_ms": {"avg": round(r["avg_kernel_ms"], 4), "median": round(r["median_kernel_ms"], 4)},
         "bytes_per_step": r["bytes"],
     }
+    # the same apply in the other precision (the FP32 inner solves use it),
+    # for reference beside the headline figure
+    out["apply_other_precision"] = other_precision_apply(r["h"], "fp32" if args.precision == "fp64" else "fp64",
+                                                         args.tiled)
+    _progress(f"apply in {out['apply_other_precision']['precision']}: "
+              f"{out['apply_other_precision']['kernel_ms_avg']:.3f} ms average kernel time")
     if not args.no_cpu:
         _progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
