@@ -57,22 +57,58 @@ struct WaveShape {
   static __device__ __forceinline__ int col(int lane, int s) { return UJ ? lane % D : (lane + 64 * s) % D; }
 };
 
+// Element of the d x d block that lane `lane` holds in slot s: lane + 64 s,
+// or, for FP32 blocks that fill whole waves with an even number of elements
+// per lane, pairs of neighbouring elements 2 lane + (s & 1) + 128 (s >> 1),
+// so that a lane's two elements are one 16-byte access like an FP64 element.
+template <typename T, int D>
+struct LaneMap {
+  using W = WaveShape<D>;
+  static constexpr bool PAIR = sizeof(T) == 4 && W::EPL % 2 == 0 && W::FULL;
+  static __device__ __forceinline__ int elem(int lane, int s) {
+    return PAIR ? 2 * lane + (s & 1) + 128 * (s >> 1) : lane + 64 * s;
+  }
+  static __device__ __forceinline__ bool on(int lane, int s) { return PAIR ? true : W::on(lane, s); }
+  static __device__ __forceinline__ int col(int lane, int s) { return PAIR ? elem(lane, s) % D : W::col(lane, s); }
+};
+
 template <typename T, int D, bool FUSE>
 __device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, int lane,
                                            typename Cplx<T>::t (&v)[WaveShape<D>::EPL]) {
   using W = WaveShape<D>;
+  using M = LaneMap<T, D>;
   constexpr int DD = D * D;
   const typename Cplx<T>::t *xb = P.x + b * DD;
+  if constexpr (M::PAIR) {
 #pragma unroll
-  for (int s = 0; s < W::EPL; ++s) v[s] = W::on(lane, s) ? xb[lane + 64 * s] : typename Cplx<T>::t{0, 0};
-  if (FUSE) {
-    const typename Cplx<T>::t *kb = P.kvec + b * DD;
+    for (int s = 0; s < W::EPL; s += 2) {
+      const float4 q = *reinterpret_cast<const float4 *>(xb + M::elem(lane, s));
+      v[s] = typename Cplx<T>::t{q.x, q.y};
+      v[s + 1] = typename Cplx<T>::t{q.z, q.w};
+    }
+    if (FUSE) {
+      const typename Cplx<T>::t *kb = P.kvec + b * DD;
 #pragma unroll
-    for (int s = 0; s < W::EPL; ++s) {
-      if (!W::on(lane, s)) continue;
-      const typename Cplx<T>::t q = kb[lane + 64 * s];
-      v[s].x = fma(P.kc, q.x, v[s].x);
-      v[s].y = fma(P.kc, q.y, v[s].y);
+      for (int s = 0; s < W::EPL; s += 2) {
+        const float4 q = *reinterpret_cast<const float4 *>(kb + M::elem(lane, s));
+        v[s].x = fma(P.kc, q.x, v[s].x);
+        v[s].y = fma(P.kc, q.y, v[s].y);
+        v[s + 1].x = fma(P.kc, q.z, v[s + 1].x);
+        v[s + 1].y = fma(P.kc, q.w, v[s + 1].y);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < W::EPL; ++s) v[s] = W::on(lane, s) ? xb[lane + 64 * s] : typename Cplx<T>::t{0, 0};
+    if (FUSE) {
+      const typename Cplx<T>::t *kb = P.kvec + b * DD;
+#pragma unroll
+      for (int s = 0; s < W::EPL; ++s) {
+        if (!W::on(lane, s)) continue;
+        const typename Cplx<T>::t q = kb[lane + 64 * s];
+        v[s].x = fma(P.kc, q.x, v[s].x);
+        v[s].y = fma(P.kc, q.y, v[s].y);
+      }
     }
   }
 }
@@ -97,7 +133,8 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
   const int64_t abase = a * DD;
   T2 acc[EPL];
 #pragma unroll
-  for (int s = 0; s < EPL; ++s) acc[s] = (flags & TASK_ACC) && W::on(lane, s) ? P.y[abase + lane + 64 * s] : T2{0, 0};
+  for (int s = 0; s < EPL; ++s)
+    acc[s] = (flags & TASK_ACC) && LaneMap<T, D>::on(lane, s) ? P.y[abase + LaneMap<T, D>::elem(lane, s)] : T2{0, 0};
   T2 trace{0, 0};
   int g = tk.y;
   if (g < tk.z) {
@@ -146,7 +183,7 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
         const T2 c = csub(P.decay[a], z);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
-          const T2 dh = csub(thd[(lane + 64 * s) / D], thd[W::col(lane, s)]);
+          const T2 dh = csub(thd[LaneMap<T, D>::elem(lane, s) / D], thd[LaneMap<T, D>::col(lane, s)]);
           const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
           acc[s] = csub(acc[s], cmul(f, u[s]));
         }
@@ -158,7 +195,7 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
       if (ns > 0 || need_trace) {
 #pragma unroll
         for (int s = 0; s < EPL; ++s)
-          if (W::on(lane, s)) buf[lane + 64 * s] = u[s];
+          if (LaneMap<T, D>::on(lane, s)) buf[LaneMap<T, D>::elem(lane, s)] = u[s];
         wave_sync();
         if (need_trace && lane == 0)
           for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
@@ -166,9 +203,9 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
           const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
 #pragma unroll
           for (int s = 0; s < EPL; ++s) {
-            if (!W::on(lane, s)) continue;
-            const int i = (lane + 64 * s) / D;
-            const int j = W::col(lane, s);
+            if (!LaneMap<T, D>::on(lane, s)) continue;
+            const int i = LaneMap<T, D>::elem(lane, s) / D;
+            const int j = LaneMap<T, D>::col(lane, s);
             const int rbase = off + (D + j) * ns;
             const int lbase = off + i * ns;
             T2 L{0, 0}, Rv{0, 0};
@@ -199,10 +236,10 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
   }
 #pragma unroll
   for (int s = 0; s < EPL; ++s) {
-    if (!W::on(lane, s)) continue;
+    if (!LaneMap<T, D>::on(lane, s)) continue;
     T2 v = acc[s];
-    if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;
-    P.y[abase + lane + 64 * s] = v;
+    if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;  // element 0 in both maps
+    P.y[abase + LaneMap<T, D>::elem(lane, s)] = v;
   }
 }
 
