@@ -25,7 +25,11 @@
  *    on error the outputs are unspecified and heom_last_error() returns a
  *    thread-local message.
  *  - A handle is immutable after build and may be used from several
- *    streams at once provided each call has its own workspace.
+ *    host threads and streams at once provided each call has its own
+ *    workspace.  Its device tables are uploaded by the first call that
+ *    needs them, once, under a lock held by the handle.  The exceptions are
+ *    heom_hierarchy_set_lindblad and heom_free, which change or release the
+ *    handle and must not overlap any other call on it.
  */
 #ifndef HEOM_H
 #define HEOM_H
@@ -211,6 +215,23 @@ heom_status heom_apply_shifted(heom_hier *h, int32_t precision, const void *x_de
  * side. */
 heom_status heom_apply_steady_operator(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev,
                                        void *stream);
+
+/* Launch plans of the apply (eq:HEOM's terms are the same in every plan;
+ * only the order of the floating-point additions differs).
+ *  HEOM_PLAN_AUTO  the fastest plan built for the hierarchy (the default of
+ *                  every other entry point);
+ *  HEOM_PLAN_PULL  one launch: every ADO gathers all its neighbour blocks;
+ *  HEOM_PLAN_SLAB  two launches over label slabs of the top two fermionic
+ *                  tiers: each top-tier ADO is read once per launch for its
+ *                  own row and for the up-terms of its parents (built for
+ *                  purely fermionic hierarchies without pruning, n_max >= 3;
+ *                  HEOM_ERR_UNSUPPORTED otherwise). */
+enum { HEOM_PLAN_AUTO = 0, HEOM_PLAN_PULL = 1, HEOM_PLAN_SLAB = 2 };
+
+/* heom_apply with an explicit launch plan (HEOM_PLAN_*); same arguments,
+ * same result up to rounding order. */
+heom_status heom_apply_plan(heom_hier *h, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                            const double *shift, int32_t plan, void *stream);
 
 /* Apply with the top tier split into `n_chunks` column blocks (one launch
  * per block plus one for the lower tiers) so that each block's neighbour

@@ -71,6 +71,7 @@ SIGNATURES = {
     "heom_apply_shifted": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp, vp]),
     "heom_apply_steady_operator": (heom_status, [vp, C.c_int32, vp, vp, vp]),
     "heom_apply_tiled": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
+    "heom_apply_plan": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
     "heom_default_opts": (None, [C.POINTER(heom_solver_opts)]),
     "heom_spectrum_chunk": (C.c_int32, [vp, C.POINTER(heom_solver_opts)]),
     "heom_workspace_size": (heom_status, [vp, C.c_int32, C.POINTER(heom_solver_opts), C.c_int64,

@@ -208,9 +208,10 @@ class Hierarchy:
         return dict(decay=dec, row_ptr=rp, col=col[:E], kind=kind[:E], exp=expo[:E], mult=mult[:E])
 
     # ------------------------------------------------------------ device work
-    def apply(self, x, y=None, shift=None, n_rhs=1, stream=None, tiled=None):
+    def apply(self, x, y=None, shift=None, n_rhs=1, stream=None, tiled=None, plan=None):
         """y = (M + shift) x on the GPU.  x: [N][d][d] or [N][d][d][R] tensor.
-        shift: complex scalar, or a device tensor of R shifts (per column)."""
+        shift: complex scalar, or a device tensor of R shifts (per column).
+        plan: None (library default), "pull" or "slab" (heom_apply_plan)."""
         import torch
         if y is None:
             y = torch.empty_like(x)
@@ -228,7 +229,11 @@ class Hierarchy:
         sh = None
         if shift is not None:
             sh = np.array([complex(shift).real, complex(shift).imag])
-        if tiled is not None:
+        if plan is not None:
+            code = {"auto": 0, "pull": 1, "slab": 2}[plan]
+            L.check(self._lib.heom_apply_plan(self._h, prec, _devptr(x), _devptr(y), n_rhs,
+                                              _dptr(sh) if sh is not None else None, code, s))
+        elif tiled is not None:
             L.check(self._lib.heom_apply_tiled(self._h, prec, _devptr(x), _devptr(y), n_rhs,
                                                _dptr(sh) if sh is not None else None, int(tiled), s))
         else:

@@ -192,6 +192,23 @@ heom_status heom_apply(heom_hier *hw, int32_t precision, const void *x_dev, void
   return guarded([&] { return heom_apply_body(hw, precision, x_dev, y_dev, n_rhs, shift, stream); });
 }
 
+static heom_status heom_apply_plan_body(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev,
+                                        int32_t n_rhs, const double *shift, int32_t plan, void *stream) {
+  if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");
+  if (x_dev == y_dev) return fail(HEOM_ERR_ARG, "apply: x and y must not alias");
+  ApplyArgs a;
+  a.x = x_dev;
+  a.y = y_dev;
+  a.n_rhs = n_rhs;
+  a.shift0 = shift ? cd(shift[0], shift[1]) : cd(0.0);
+  return launch_apply_plan(*hw->impl, precision, a, plan, (hipStream_t)stream);
+}
+
+heom_status heom_apply_plan(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
+                            const double *shift, int32_t plan, void *stream) {
+  return guarded([&] { return heom_apply_plan_body(hw, precision, x_dev, y_dev, n_rhs, shift, plan, stream); });
+}
+
 static heom_status heom_apply_shifted_body(heom_hier *hw, int32_t precision, const void *x_dev, void *y_dev, int32_t n_rhs,
                                const void *shifts_dev, void *stream) {
   if (!hw) return fail(HEOM_ERR_ARG, "NULL handle");

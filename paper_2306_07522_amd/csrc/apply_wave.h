@@ -28,6 +28,10 @@ struct ApplyParams {
   const T2 *hdiag;
   int tpw;  // tasks per wave
   int xchunk;  // XCD remap super-chunk in blocks (multiple of 8; 0 = off)
+  // XCD runs (xsplit = 1): workgroup b serves XCD k = b % 8 and takes tasks
+  // xlo[k] + 4 (b / 8) + wave while below xhi[k]
+  int xsplit;
+  int64_t xlo[8], xhi[8];
   const int32_t *coef_op;
   const T2 *coef;
   const T2 *x;

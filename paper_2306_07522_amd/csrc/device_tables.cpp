@@ -36,9 +36,11 @@ void free_device(Hier &h) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_plan(D.base);
-  free_plan(D.tiled);
+  free_plan(D.slab);
+  for (auto &kv : D.tiled) free_plan(kv.second);
   (void)hipSetDevice(cur);
   D = DeviceTables();
+  h.dev_ready.store(-1, std::memory_order_release);
 }
 
 // One task's edges -> groups.  Edges that share an operator and an
@@ -98,12 +100,12 @@ struct PlanBuilder {
   }
 };
 
-heom_status ensure_device(Hier &h) {
-  int dev = 0;
-  HEOM_HIP_CHECK(hipGetDevice(&dev));
+static heom_status build_slab_plan(Hier &h, Plan &out, size_t &tot);
+
+// Upload of every table and launch plan to device `dev`; runs once per
+// handle, under h.dev_mu.
+static heom_status upload_tables(Hier &h, int dev) {
   DeviceTables &D = h.dev;
-  if (D.device == dev) return HEOM_OK;
-  if (D.device >= 0) return fail(HEOM_ERR_ARG, "hierarchy tables live on another device");
   D.device = dev;
   size_t tot = 0;
   const int64_t N = h.N;
@@ -227,12 +229,175 @@ heom_status ensure_device(Hier &h) {
       (st = upload(&D.c_col, L.c_col.data(), sizeof(int32_t) * L.c_col.size(), tot)) ||
       (st = upload(&D.c_val64, cv64.data(), sizeof(double2) * cv64.size(), tot)) ||
       (st = upload(&D.c_val32, cv32.data(), sizeof(float2) * cv32.size(), tot)) ||
-      (st = pb.upload_to(D.base, tot))) {
+      (st = pb.upload_to(D.base, tot)) ||
+      (st = build_slab_plan(h, D.slab, tot))) {
     free_device(h);
     return st;
   }
   D.base.task_off = {0, (int64_t)pb.tasks.size()};
   D.bytes = tot;
+  return HEOM_OK;
+}
+
+heom_status ensure_device(Hier &h) {
+  int dev = 0;
+  HEOM_HIP_CHECK(hipGetDevice(&dev));
+  if (h.dev_ready.load(std::memory_order_acquire) == dev) return HEOM_OK;
+  std::lock_guard<std::mutex> lock(h.dev_mu);
+  const int ready = h.dev_ready.load(std::memory_order_relaxed);
+  if (ready == dev) return HEOM_OK;
+  if (ready >= 0) return fail(HEOM_ERR_ARG, "hierarchy tables live on another device");
+  HEOM_TRY(upload_tables(h, dev));
+  h.dev_ready.store(dev, std::memory_order_release);
+  return HEOM_OK;
+}
+
+// ---------------------------------------------------------------- slab plan
+// For a purely fermionic hierarchy cut at tier L = n_max, every top-tier ADO
+// c (an L-subset of exponent labels) feeds the up-terms of its L parents
+// c \ {u} (eq:HEOM, the C-type terms).  The single-launch plan has every
+// parent gather its children, so each child block is fetched once for its
+// own row and once per parent; the parents' child sets overlap like an
+// expander graph, and the cache sees little of that reuse.
+//
+// The slab plan splits each tier-(L-1) parent P's up-terms by the position
+// the added label u takes in the child:
+//  * prefix part, u above the second largest label of P: the child then
+//    shares its L - 2 smallest labels (its prefix core) with P minus max(P);
+//  * suffix part, every other u: for L = 4 the child shares its L - 2
+//    largest labels (its suffix core) with P minus min(P).
+// A slab is the set of parents and children with one core.  Launch A runs
+// the tiers below L - 1 in full and then, slab by slab, the prefix parts of
+// the slab's parents (written to y) followed by the full rows of its
+// children (self and down terms).  Launch B runs, slab by slab, the rest of
+// each parent's row (self, down terms, suffix part) and adds it to y.  A
+// slab's children are read by the slab's parents and children close
+// together in time; each XCD walks a contiguous run of slabs, so those
+// re-reads stay in its L2 and a top-tier block leaves HBM about once per
+// launch instead of once per parent.
+static bool slab_applicable(const Hier &h) {
+  const int L = h.Lf;
+  return h.Kb == 0 && h.importance_threshold <= 0.0 && L >= 3 && (int)h.tier_off.size() == L + 2 &&
+         h.tier_off[L + 1] > h.tier_off[L];
+}
+
+// Cuts tasks [0, n) with costs c into 8 contiguous runs of similar cost,
+// at unit boundaries (unit_start[t] = true where a slab begins).
+static std::vector<int64_t> xcd_split(const std::vector<int64_t> &cost, const std::vector<char> &unit_start) {
+  const int64_t n = (int64_t)cost.size();
+  std::vector<int64_t> pre(n + 1, 0);
+  for (int64_t t = 0; t < n; ++t) pre[t + 1] = pre[t] + cost[t];
+  std::vector<int64_t> off(9, 0);
+  off[8] = n;
+  int64_t t = 0;
+  for (int k = 1; k < 8; ++k) {
+    const double target = (double)pre[n] * k / 8.0;
+    t = std::max(t, off[k - 1]);
+    while (t < n && (double)pre[t + 1] <= target) ++t;  // pre[t] <= target < pre[t + 1]
+    // nearest unit boundary at or around t
+    int64_t lo = t, hi = t;
+    while (lo > off[k - 1] && !unit_start[lo]) --lo;
+    while (hi < n && !unit_start[hi]) ++hi;
+    off[k] = (target - (double)pre[lo] <= (double)pre[hi] - target) ? lo : hi;
+    if (off[k] < off[k - 1]) off[k] = off[k - 1];
+  }
+  return off;
+}
+
+static heom_status build_slab_plan(Hier &h, Plan &out, size_t &tot) {
+  if (!slab_applicable(h)) return HEOM_OK;
+  const int L = h.Lf;
+  const int64_t v0 = h.tier_off[L - 1], c0 = h.tier_off[L], c1 = h.tier_off[L + 1];
+  const int64_t k0 = h.tier_off[L - 2];
+  const int64_t n_core = v0 - k0;
+  auto top_bit = [](uint64_t m) { return 63 - __builtin_clzll(m); };
+  auto low_bit = [](uint64_t m) { return __builtin_ctzll(m); };
+  auto core_of = [&](uint64_t m) -> int64_t {
+    const int64_t a = lookup_ado(h, m, 0);
+    return (a >= k0 && a < v0) ? a - k0 : -1;
+  };
+  std::vector<std::vector<int64_t>> pv(n_core), pc(n_core), sv(n_core);
+  for (int64_t P = v0; P < c0; ++P) {
+    const uint64_t m = h.fmask[P];
+    const int64_t kp = core_of(m & ~(1ull << top_bit(m))), ks = core_of(m & ~(1ull << low_bit(m)));
+    if (kp < 0 || ks < 0) return fail(HEOM_ERR_ARG, "slab plan: missing core ADO");
+    pv[kp].push_back(P);
+    sv[ks].push_back(P);
+  }
+  for (int64_t c = c0; c < c1; ++c) {
+    uint64_t m = h.fmask[c];
+    m &= ~(1ull << top_bit(m));
+    m &= ~(1ull << top_bit(m));
+    const int64_t kp = core_of(m);
+    if (kp < 0) return fail(HEOM_ERR_ARG, "slab plan: missing core ADO");
+    pc[kp].push_back(c);
+  }
+  // up edge e of parent P belongs to the prefix part when its added label
+  // lies above the second largest label of P
+  auto prefix_part = [&](int64_t P, int64_t e) {
+    const uint64_t m = h.fmask[P];
+    const int64_t c = h.ecol[e];
+    if (c < c0) return false;  // down edge
+    const int u = low_bit(h.fmask[c] & ~m);
+    const int second = top_bit(m & ~(1ull << top_bit(m)));
+    return u > second;
+  };
+  PlanBuilder pb(h);
+  std::vector<int64_t> es, cost;
+  std::vector<char> ustart;
+  int64_t n_edges = 0, n_self = 0;
+  auto add = [&](int64_t a, bool self, bool acc, bool first) {
+    pb.add_task(a, es, self, acc);
+    cost.push_back(1 + (int64_t)es.size());
+    ustart.push_back(first);
+    n_edges += (int64_t)es.size();
+    n_self += self;
+  };
+  // launch A
+  for (int64_t a = 0; a < v0; ++a) {
+    es.clear();
+    for (int64_t e = h.row_ptr[a]; e < h.row_ptr[a + 1]; ++e) es.push_back(e);
+    add(a, true, false, true);
+  }
+  for (int64_t k = 0; k < n_core; ++k) {
+    bool first = true;
+    for (int64_t P : pv[k]) {
+      es.clear();
+      for (int64_t e = h.row_ptr[P]; e < h.row_ptr[P + 1]; ++e)
+        if (prefix_part(P, e)) es.push_back(e);
+      add(P, false, false, first);
+      first = false;
+    }
+    for (int64_t c : pc[k]) {
+      es.clear();
+      for (int64_t e = h.row_ptr[c]; e < h.row_ptr[c + 1]; ++e) es.push_back(e);
+      add(c, true, false, first);
+      first = false;
+    }
+  }
+  const int64_t nA = (int64_t)pb.tasks.size();
+  std::vector<int64_t> costA(cost.begin(), cost.end());
+  std::vector<char> ustartA(ustart.begin(), ustart.end());
+  cost.clear();
+  ustart.clear();
+  // launch B
+  for (int64_t k = 0; k < n_core; ++k) {
+    bool first = true;
+    for (int64_t P : sv[k]) {
+      es.clear();
+      for (int64_t e = h.row_ptr[P]; e < h.row_ptr[P + 1]; ++e)
+        if (!prefix_part(P, e)) es.push_back(e);
+      add(P, true, true, first);
+      first = false;
+    }
+  }
+  const int64_t nB = (int64_t)pb.tasks.size() - nA;
+  // every ADO's row exactly once: one self group per ADO, every edge once
+  if (nB != c0 - v0 || nA != c1 - (c0 - v0) || n_self != h.N || n_edges != h.row_ptr[h.N])
+    return fail(HEOM_ERR_ARG, "slab plan: rows not covered exactly once");
+  HEOM_TRY(pb.upload_to(out, tot));
+  out.task_off = {0, nA, nA + nB};
+  out.xcd_off = {xcd_split(costA, ustartA), xcd_split(cost, ustart)};
   return HEOM_OK;
 }
 
@@ -242,14 +407,19 @@ heom_status ensure_device(Hier &h) {
 // of chunk k in full and adds, to every non-leaf row, the terms whose
 // neighbour lies in chunk k.  Each launch therefore streams one chunk of
 // leaf blocks once and re-reads it from cache.
-heom_status ensure_tiled_plan(Hier &h, int n_chunks) {
+heom_status ensure_tiled_plan(Hier &h, int n_chunks, const Plan **out) {
+  HEOM_TRY(ensure_device(h));
+  std::lock_guard<std::mutex> lock(h.dev_mu);
   DeviceTables &D = h.dev;
   const int64_t N = h.N;
   const int64_t leaf0 = h.tier_off[h.tier_off.size() - 2];
   const int64_t nleaf = N - leaf0;
   n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(n_chunks, std::max<int64_t>(nleaf, 1)));
-  if (D.tiled.tasks && D.tiled.n_chunks == n_chunks) return HEOM_OK;
-  free_plan(D.tiled);
+  auto it = D.tiled.find(n_chunks);
+  if (it != D.tiled.end()) {
+    *out = &it->second;
+    return HEOM_OK;
+  }
   PlanBuilder pb(h);
   std::vector<int64_t> task_off{0};
   std::vector<int64_t> es;
@@ -276,9 +446,17 @@ heom_status ensure_tiled_plan(Hier &h, int n_chunks) {
     task_off.push_back((int64_t)pb.tasks.size());
   }
   size_t tot = 0;
-  HEOM_TRY(pb.upload_to(D.tiled, tot));
-  D.tiled.task_off = task_off;
-  D.tiled.n_chunks = n_chunks;
+  Plan pl;
+  heom_status st = pb.upload_to(pl, tot);
+  if (st != HEOM_OK) {
+    free_plan(pl);
+    return st;
+  }
+  pl.task_off = task_off;
+  pl.n_chunks = n_chunks;
+  Plan &slot = D.tiled[n_chunks];
+  slot = pl;
+  *out = &slot;
   return HEOM_OK;
 }
 

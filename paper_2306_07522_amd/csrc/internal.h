@@ -3,9 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <complex>
 #include <cstdint>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -79,12 +82,17 @@ struct OpEll {
 // A group shares one operator and one coefficient pair (cl, cr); its edges
 // carry a small integer weight, so the group contributes
 //   cl * O u + cr * u O,   u = sum_e w_e x_{b_e}.
+//
+// A launch may also carry an XCD split: xcd_off[l][k] .. xcd_off[l][k + 1]
+// is the contiguous run of launch l's tasks that XCD k walks (workgroup b
+// runs on XCD b % 8), cut so that the runs cost about the same.
 struct Plan {
   int n_chunks = -1;             // -1: untiled single launch
   int4 *tasks = nullptr;         // {a, g0, g1, flags}
   int4 *groups = nullptr;        // {e0, e1, coef_id, self}
   int2 *gedges = nullptr;        // {b, w}
   std::vector<int64_t> task_off; // [n_launch + 1]
+  std::vector<std::vector<int64_t>> xcd_off;  // empty, or [n_launch][9] (relative to task_off[l])
   size_t bytes = 0;
 };
 
@@ -112,8 +120,9 @@ struct DeviceTables {
   int32_t *c_col = nullptr;
   double2 *c_val64 = nullptr;
   float2 *c_val32 = nullptr;
-  Plan base;                    // untiled
-  Plan tiled;                   // top tier split into chunks
+  Plan base;                    // untiled, one launch: every ADO gathers all its neighbours
+  Plan slab;                    // two launches over label slabs (empty when not applicable)
+  std::map<int, Plan> tiled;    // top tier split into chunks, by chunk count
   size_t bytes = 0;
 };
 
@@ -150,6 +159,10 @@ struct Hier {
   int coef_H = 0;
   OpEll ell;
   int64_t n_leaf = 0;
+  // device upload: done once, on first use, under dev_mu; dev_ready holds the
+  // device id once every table and plan is in place (-1 before)
+  std::mutex dev_mu;
+  std::atomic<int> dev_ready{-1};
   // bosonic code for dictionary lookups
   std::vector<uint64_t> bos_pow;
   std::vector<std::pair<uint64_t, uint64_t>> keys;  // sorted (fmask, bos code)
@@ -164,7 +177,8 @@ int64_t lookup_ado(const Hier &h, uint64_t fmask, uint64_t bcode);
 
 // device upload / kernels (device.hip)
 heom_status ensure_device(Hier &h);
-heom_status ensure_tiled_plan(Hier &h, int n_chunks);
+// the tiled plan of n_chunks chunks (built on first request, kept until heom_free)
+heom_status ensure_tiled_plan(Hier &h, int n_chunks, const Plan **out);
 void free_device(Hier &h);
 void free_plan(Plan &p);
 
@@ -179,6 +193,8 @@ struct ApplyArgs {
   int border = 0;               // 1: replace y[0][0][0] by Tr rho_0 (steady-state row)
 };
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
+// as launch_apply with an explicit plan (HEOM_PLAN_*)
+heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int plan, hipStream_t s);
 // whole RK4 steps in one workgroup for hierarchies of at most 1024 elements
 bool rk4_small_fits(const Hier &h);
 heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t steps, int64_t save_every,

@@ -22,7 +22,7 @@ def _torch():
     return torch
 
 
-def _parity_check(cfg, parity=+1, seeds=(0,), shift=None, tiled=None, fp32=True, om=None, lm=None):
+def _parity_check(cfg, parity=+1, seeds=(0,), shift=None, tiled=None, fp32=True, om=None, lm=None, plan=None):
     torch = _torch()
     om = om or oracle_model(cfg, parity=parity)
     lm = lm or library_model(cfg, parity=parity)
@@ -36,14 +36,14 @@ def _parity_check(cfg, parity=+1, seeds=(0,), shift=None, tiled=None, fp32=True,
         xl[perm] = xo
         yo = to_blocks(M @ from_blocks(xo), om.N, om.d)
         x_dev = torch.from_numpy(xl).cuda()
-        y = lm.apply(x_dev, shift=shift, tiled=tiled).cpu().numpy()
+        y = lm.apply(x_dev, shift=shift, tiled=tiled, plan=plan).cpu().numpy()
         e64 = rel_err(y[perm], yo)
         assert e64 <= FP64_TOL, (cfg.get("name"), seed, e64)
         errs.setdefault("fp64", []).append(e64)
         if fp32:
             x32 = xl.astype(np.complex64)
             yo32 = to_blocks(M @ from_blocks(x32.astype(np.complex128)[perm]), om.N, om.d)
-            y32 = lm.apply(torch.from_numpy(x32).cuda(), shift=shift, tiled=tiled).cpu().numpy()
+            y32 = lm.apply(torch.from_numpy(x32).cuda(), shift=shift, tiled=tiled, plan=plan).cpu().numpy()
             e32 = rel_err(y32[perm].astype(np.complex128), yo32)
             assert e32 <= FP32_TOL, (cfg.get("name"), seed, e32)
             errs.setdefault("fp32", []).append(e32)
@@ -136,7 +136,52 @@ def test_apply_multi_rhs_per_column_shifts():
         assert rel_err(yt[perm][..., r], yo) <= FP64_TOL
 
 
-def _row_sampled(precision, tiled):
+def _fermionic_cfg(seed, d, n_baths, nf, n_max):
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    baths = wl.random_raw_baths(rng, d, n_bos_baths=0, n_ferm_baths=n_baths, n_ferm_exp=nf)
+    return dict(name=f"fermionic_d{d}_L{n_max}", H=H + H.conj().T, baths=baths, m_max=0, n_max=n_max)
+
+
+@pytest.mark.parametrize("d,n_baths,nf,n_max", [
+    (8, 2, 2, 4),     # K = 8, L = 4: every position of the added label owned by a slab
+    (16, 2, 2, 4),
+    (4, 3, 2, 3),     # L = 3: the suffix part is the smallest position only
+    (8, 2, 2, 5),     # L = 5: the middle position falls to the second launch's plain gathers
+    (8, 1, 4, 3),     # one bath record, K = 8
+])
+@pytest.mark.parametrize("parity", [+1, -1])
+@pytest.mark.parametrize("plan", ["slab", "pull"])
+def test_apply_plans_fermionic(d, n_baths, nf, n_max, parity, plan):
+    """Both launch plans of a purely fermionic hierarchy against the oracle
+    (the slab plan splits each tier-(L-1) row over two launches)."""
+    cfg = _fermionic_cfg(300 + d + n_max, d, n_baths, nf, n_max)
+    errs = _parity_check(cfg, parity=parity, seeds=(0,), shift=0.25 + 0.5j, plan=plan)
+    print(plan, d, n_max, errs)
+
+
+def test_apply_slab_plan_workloads():
+    """The Anderson impurity (tier 3, 40 exponents) and the two-orbital model
+    at tier 3 (48 exponents) through the slab plan, both parities."""
+    for cfg in (wl.siam(), wl.two_orbital_anderson(n_max=3)):
+        for p in (+1, -1):
+            _parity_check(cfg, parity=p, seeds=(5,), plan="slab")
+
+
+def test_apply_slab_plan_unsupported():
+    """A hierarchy with a bosonic bath has no slab plan: an explicit request
+    fails with HEOM_ERR_UNSUPPORTED, the default plan still runs."""
+    torch = _torch()
+    from paper_2306_07522_amd import _lib
+    cfg = _random_cfg(12, 4, 2, 2, 2, 3)
+    lm = library_model(cfg)
+    x = torch.from_numpy(wl.random_vector(np.random.default_rng(0), lm.N, 4)).cuda()
+    with pytest.raises(_lib.HeomError, match="slab plan"):
+        lm.apply(x, plan="slab")
+    _parity_check(cfg, seeds=(0,), plan="auto", fp32=False)
+
+
+def _row_sampled(precision, tiled, plan=None):
     """Two-orbital Anderson model at its full size (213,053 ADOs, d = 16):
     the oracle assembles only a seeded sample of block rows (every tier
     represented) and the GPU output is compared on those rows."""
@@ -157,19 +202,20 @@ def _row_sampled(precision, tiled):
     if precision == "fp32":
         x = x.astype(np.complex64)
     xd = torch.from_numpy(x).cuda()
-    y = lm.apply(xd, tiled=tiled).cpu().numpy().astype(np.complex128)
+    y = lm.apply(xd, tiled=tiled, plan=plan).cpu().numpy().astype(np.complex128)
     del xd
     xo = x.astype(np.complex128)[perm]                  # oracle order
     Msub = om.assemble(rows=rows)
     yo = (Msub @ from_blocks(xo)).reshape(len(rows), 16, 16).transpose(0, 2, 1)
     err = rel_err(y[perm[rows]], yo)
-    print("row-sampled", precision, tiled, err, len(rows))
+    print("row-sampled", precision, tiled, plan, err, len(rows))
     assert err <= (FP64_TOL if precision == "fp64" else FP32_TOL)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_apply_two_orbital_row_sampled(precision):
-    _row_sampled(precision, tiled=None)
+@pytest.mark.parametrize("plan", ["slab", "pull"])
+def test_apply_two_orbital_row_sampled(precision, plan):
+    _row_sampled(precision, tiled=None, plan=plan)
 
 
 def test_apply_two_orbital_row_sampled_tiled():
