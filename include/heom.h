@@ -218,15 +218,35 @@ heom_status heom_apply_steady_operator(heom_hier *h, int32_t precision, const vo
 
 /* Launch plans of the apply (eq:HEOM's terms are the same in every plan;
  * only the order of the floating-point additions differs).
- *  HEOM_PLAN_AUTO  the fastest plan built for the hierarchy (the default of
- *                  every other entry point);
+ *  HEOM_PLAN_AUTO  the default of every other entry point (the pull plan);
  *  HEOM_PLAN_PULL  one launch: every ADO gathers all its neighbour blocks;
- *  HEOM_PLAN_SLAB  two launches over label slabs of the top two fermionic
- *                  tiers: each top-tier ADO is read once per launch for its
- *                  own row and for the up-terms of its parents (built for
- *                  purely fermionic hierarchies without pruning, n_max >= 3;
- *                  HEOM_ERR_UNSUPPORTED otherwise). */
+ *  HEOM_PLAN_SLAB  three launches: the lower tiers and the top tier's own
+ *                  rows, then two launches over label slabs of the top two
+ *                  fermionic tiers in which the parents' up-terms are summed
+ *                  while each top-tier block passes through LDS once per
+ *                  launch.  Fewer bytes from memory, but slower than the pull
+ *                  plan where measured (two-orbital model, d = 16).  Built for
+ *                  purely fermionic hierarchies without pruning, n_max >= 3,
+ *                  d = 8 or 16, one right-hand side; HEOM_ERR_UNSUPPORTED
+ *                  otherwise. */
 enum { HEOM_PLAN_AUTO = 0, HEOM_PLAN_PULL = 1, HEOM_PLAN_SLAB = 2 };
+
+/* Layout of the slab plan, computed on the host without touching the
+ * device (the plan itself is uploaded with the other tables on first use):
+ * per launch (0 = A, 1 = B) the workgroup count (empty XCD slots included),
+ * the child entries (a child counts once per workgroup that reads it), the
+ * most parents one workgroup holds, and the estimated cost per XCD in block
+ * reads.  built = 0 when the hierarchy has no slab plan.  The build checks
+ * that every ADO's row (self term and every neighbour term) is scheduled
+ * exactly once and fails with HEOM_ERR_ARG otherwise. */
+typedef struct {
+  int32_t built;
+  int32_t max_vertices[2];
+  int64_t children, parents;
+  int64_t jobs[2], entries[2], cost[2];
+  int64_t xcd_cost[2][8];
+} heom_slab_stats;
+heom_status heom_slab_plan_stats(const heom_hier *h, heom_slab_stats *out);
 
 /* heom_apply with an explicit launch plan (HEOM_PLAN_*); same arguments,
  * same result up to rounding order. */

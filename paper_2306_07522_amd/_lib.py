@@ -36,6 +36,12 @@ class heom_info(C.Structure):
                 ("tier_offset", C.c_int64 * 34), ("table_bytes", C.c_int64), ("vector_bytes_fp64", C.c_int64)]
 
 
+class heom_slab_stats(C.Structure):
+    _fields_ = [("built", C.c_int32), ("max_vertices", C.c_int32 * 2), ("children", C.c_int64),
+                ("parents", C.c_int64), ("jobs", C.c_int64 * 2), ("entries", C.c_int64 * 2),
+                ("cost", C.c_int64 * 2), ("xcd_cost", (C.c_int64 * 8) * 2)]
+
+
 class heom_solver_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("precond", C.c_int32),
                 ("mode", C.c_int32), ("inner_tol", C.c_double), ("max_refine", C.c_int32),
@@ -72,6 +78,7 @@ SIGNATURES = {
     "heom_apply_steady_operator": (heom_status, [vp, C.c_int32, vp, vp, vp]),
     "heom_apply_tiled": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
     "heom_apply_plan": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, C.c_int32, vp]),
+    "heom_slab_plan_stats": (heom_status, [vp, C.POINTER(heom_slab_stats)]),
     "heom_default_opts": (None, [C.POINTER(heom_solver_opts)]),
     "heom_spectrum_chunk": (C.c_int32, [vp, C.POINTER(heom_solver_opts)]),
     "heom_workspace_size": (heom_status, [vp, C.c_int32, C.POINTER(heom_solver_opts), C.c_int64,

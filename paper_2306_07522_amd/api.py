@@ -207,6 +207,17 @@ class Hierarchy:
                                                 *[a.ctypes.data_as(L.i32p) for a in (col, kind, expo, mult)]))
         return dict(decay=dec, row_ptr=rp, col=col[:E], kind=kind[:E], exp=expo[:E], mult=mult[:E])
 
+    def slab_plan_stats(self):
+        """Host-side layout of the slab launch plan (heom_slab_plan_stats), or
+        None when the hierarchy has no slab plan."""
+        st = L.heom_slab_stats()
+        L.check(self._lib.heom_slab_plan_stats(self._h, C.byref(st)))
+        if not st.built:
+            return None
+        return dict(children=st.children, parents=st.parents, jobs=list(st.jobs), entries=list(st.entries),
+                    max_vertices=list(st.max_vertices), cost=list(st.cost),
+                    xcd_cost=[list(st.xcd_cost[l]) for l in range(2)])
+
     # ------------------------------------------------------------ device work
     def apply(self, x, y=None, shift=None, n_rhs=1, stream=None, tiled=None, plan=None):
         """y = (M + shift) x on the GPU.  x: [N][d][d] or [N][d][d][R] tensor.

@@ -52,12 +52,6 @@ apply_wave_kernel(ApplyParams<T> P) {
   // the task index is uniform across the wave: keep every table lookup scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T2 *buf = sbuf + wave * DD;
-  if (P.xsplit) {
-    const int k = blockIdx.x & 7;
-    const int64_t task = P.xlo[k] + 4 * (int64_t)(blockIdx.x >> 3) + wave;
-    if (task < P.xhi[k]) wave_task<T, D, FUSE>(P, task, lane, buf, tval, tcol, thd);
-    return;
-  }
   int64_t blk = blockIdx.x;
   if (P.xchunk > 0 && (int64_t)(blockIdx.x / P.xchunk + 1) * P.xchunk <= (int64_t)gridDim.x) {
     // XCD-aware remap inside super-chunks of xchunk blocks: block b runs on
@@ -267,8 +261,7 @@ heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t
 }
 
 template <typename T>
-static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1,
-                           const std::vector<int64_t> *xoff, hipStream_t s) {
+static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1, hipStream_t s) {
   using T2 = typename Cplx<T>::t;
   DeviceTables &D = h.dev;
   const int64_t n_tasks = t1 - t0;
@@ -307,20 +300,7 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   if (a.n_rhs == 1 && (d == 8 || d == 16 || d == 20) && smem <= 48 * 1024) {
     P.tpw = 1;
     P.xchunk = 64;
-    int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
-    if (xoff) {
-      if (xoff->size() != 9 || (*xoff)[0] != 0 || (*xoff)[8] != n_tasks)
-        return fail(HEOM_ERR_ARG, "apply: malformed XCD split");
-      int64_t most = 0;
-      P.xsplit = 1;
-      for (int k = 0; k < 8; ++k) {
-        P.xlo[k] = (*xoff)[k];
-        P.xhi[k] = (*xoff)[k + 1];
-        if (P.xhi[k] < P.xlo[k]) return fail(HEOM_ERR_ARG, "apply: malformed XCD split");
-        most = std::max(most, (P.xhi[k] - P.xlo[k] + 3) / 4);
-      }
-      grid = 8 * most;
-    }
+    const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
     if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
     dim3 g((unsigned)grid), b(256);
     if (d == 8) {
@@ -350,6 +330,12 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   return HEOM_OK;
 }
 
+heom_status launch_plan_range(Hier &h, int precision, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1,
+                              hipStream_t s) {
+  if (precision == HEOM_FP64) return launch_T<double>(h, a, pl, t0, t1, s);
+  return launch_T<float>(h, a, pl, t0, t1, s);
+}
+
 static heom_status check_apply(Hier &h, int precision, const ApplyArgs &a) {
   if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_ERR_ARG, "precision must be FP64 or FP32");
   if (!a.x || !a.y) return fail(HEOM_ERR_ARG, "apply: NULL vector");
@@ -360,33 +346,33 @@ static heom_status check_apply(Hier &h, int precision, const ApplyArgs &a) {
 
 static heom_status run_plan(Hier &h, int precision, const ApplyArgs &a, const Plan &pl, hipStream_t s) {
   for (size_t l = 0; l + 1 < pl.task_off.size(); ++l) {
-    const std::vector<int64_t> *xoff = l < pl.xcd_off.size() ? &pl.xcd_off[l] : nullptr;
-    if (precision == HEOM_FP64) HEOM_TRY(launch_T<double>(h, a, pl, pl.task_off[l], pl.task_off[l + 1], xoff, s));
-    else HEOM_TRY(launch_T<float>(h, a, pl, pl.task_off[l], pl.task_off[l + 1], xoff, s));
+    if (precision == HEOM_FP64) HEOM_TRY(launch_T<double>(h, a, pl, pl.task_off[l], pl.task_off[l + 1], s));
+    else HEOM_TRY(launch_T<float>(h, a, pl, pl.task_off[l], pl.task_off[l + 1], s));
   }
   return HEOM_OK;
 }
 
 heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int plan, hipStream_t s) {
   HEOM_TRY(check_apply(h, precision, a));
-  const Plan *pl = &h.dev.base;
-  const bool have_slab = h.dev.slab.tasks != nullptr;
+  const bool have_slab = h.dev.slab.built;
+  bool slab = false;
   switch (plan) {
-    case HEOM_PLAN_AUTO:
-      // the slab plan is measured for the one-column wave kernel
-      if (have_slab && a.n_rhs == 1) pl = &h.dev.slab;
+    case HEOM_PLAN_AUTO:  // the pull plan: measured faster than the slab plan on the two-orbital model
       break;
     case HEOM_PLAN_PULL:
       break;
     case HEOM_PLAN_SLAB:
-      if (!have_slab)
-        return fail(HEOM_ERR_UNSUPPORTED, "apply: the slab plan needs a purely fermionic, unpruned hierarchy with n_max >= 3");
-      pl = &h.dev.slab;
+      if (!have_slab || a.n_rhs != 1)
+        return fail(HEOM_ERR_UNSUPPORTED,
+                    "apply: the slab plan needs one right-hand side and a purely fermionic, unpruned hierarchy "
+                    "with n_max >= 3 and d = 8 or 16");
+      slab = true;
       break;
     default:
       return fail(HEOM_ERR_ARG, "apply: unknown plan");
   }
-  HEOM_TRY(run_plan(h, precision, a, *pl, s));
+  if (slab) HEOM_TRY(launch_apply_slab(h, precision, a, s));
+  else HEOM_TRY(run_plan(h, precision, a, h.dev.base, s));
   return launch_lindblad(h, precision, a, s);
 }
 

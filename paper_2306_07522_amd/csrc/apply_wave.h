@@ -28,10 +28,6 @@ struct ApplyParams {
   const T2 *hdiag;
   int tpw;  // tasks per wave
   int xchunk;  // XCD remap super-chunk in blocks (multiple of 8; 0 = off)
-  // XCD runs (xsplit = 1): workgroup b serves XCD k = b % 8 and takes tasks
-  // xlo[k] + 4 (b / 8) + wave while below xhi[k]
-  int xsplit;
-  int64_t xlo[8], xhi[8];
   const int32_t *coef_op;
   const T2 *coef;
   const T2 *x;
@@ -117,16 +113,98 @@ __device__ __forceinline__ void load_block(const ApplyParams<T> &P, int64_t b, i
   }
 }
 
-// One output ADO (task) of the wave formulation, computed by one wavefront:
-// the task's groups stream their neighbour blocks (the next group's first
-// block prefetched while the current one is finished, multi-edge groups two
-// blocks at a time), each group sum is staged in the wave's LDS slice `buf`,
-// and the operator products gather from it through the compact tables
-// (tval, tcol) and the H diagonal (thd) held in LDS.
-template <typename T, int D, bool FUSE>
-__device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
-                                          const typename Cplx<T>::t *tval, const int *tcol,
-                                          const typename Cplx<T>::t *thd) {
+// acc += w (cl O X + cr X O) for the coefficient pair and operator of
+// coefficient entry cid, with X a d x d block staged in LDS (row-major) and
+// acc in the lane layout of LaneMap.  O gathers through the compact tables.
+template <typename T, int D>
+__device__ __forceinline__ void op_terms(const ApplyParams<T> &P, int cid, T w, int lane,
+                                         const typename Cplx<T>::t *X, const typename Cplx<T>::t *tval,
+                                         const int *tcol, typename Cplx<T>::t (&acc)[WaveShape<D>::EPL]) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int EPL = WaveShape<D>::EPL;
+  const int op = P.coef_op[cid];
+  const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
+  if (ns <= 0) return;
+  T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
+  cl.x *= w; cl.y *= w; cr.x *= w; cr.y *= w;
+#pragma unroll
+  for (int s = 0; s < EPL; ++s) {
+    if (!LaneMap<T, D>::on(lane, s)) continue;
+    const int i = LaneMap<T, D>::elem(lane, s) / D;
+    const int j = LaneMap<T, D>::col(lane, s);
+    const int rbase = off + (D + j) * ns;
+    const int lbase = off + i * ns;
+    T2 L{0, 0}, Rv{0, 0};
+    if (isreal) {
+#pragma unroll 1
+      for (int t = 0; t < ns; ++t) {
+        const T vl = tval[lbase + t].x, vr = tval[rbase + t].x;
+        const T2 bl = X[tcol[lbase + t] * D + j];
+        const T2 br = X[i * D + tcol[rbase + t]];
+        L.x = fma(vl, bl.x, L.x); L.y = fma(vl, bl.y, L.y);
+        Rv.x = fma(vr, br.x, Rv.x); Rv.y = fma(vr, br.y, Rv.y);
+      }
+    } else {
+#pragma unroll 1
+      for (int t = 0; t < ns; ++t) {
+        L = cfma(tval[lbase + t], X[tcol[lbase + t] * D + j], L);
+        Rv = cfma(X[i * D + tcol[rbase + t]], tval[rbase + t], Rv);
+      }
+    }
+    acc[s] = cfma(cl, L, acc[s]);
+    acc[s] = cfma(cr, Rv, acc[s]);
+  }
+}
+
+// One group's terms, with the group sum u (in the lane layout) in hand: the
+// decay and the diagonal of H for the self group, then cl O u + cr u O
+// through the wave's LDS slice (and the trace of ADO 0 for the bordered
+// operator).
+template <typename T, int D>
+__device__ __forceinline__ void group_terms(const ApplyParams<T> &P, const int4 &gr, int64_t a, int lane,
+                                            const typename Cplx<T>::t (&u)[WaveShape<D>::EPL],
+                                            typename Cplx<T>::t *buf, const typename Cplx<T>::t *tval,
+                                            const int *tcol, const typename Cplx<T>::t *thd,
+                                            typename Cplx<T>::t (&acc)[WaveShape<D>::EPL],
+                                            typename Cplx<T>::t &trace) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int EPL = WaveShape<D>::EPL;
+  if (gr.w) {
+    // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
+    const T2 z = P.shifts ? P.shifts[0] : P.shift0;
+    const T2 c = csub(P.decay[a], z);
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+      const T2 dh = csub(thd[LaneMap<T, D>::elem(lane, s) / D], thd[LaneMap<T, D>::col(lane, s)]);
+      const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
+      acc[s] = csub(acc[s], cmul(f, u[s]));
+    }
+  }
+  const int cid = gr.z;
+  const int op = P.coef_op[cid];
+  const int ns = P.c_meta[3 * op + 1];
+  const bool need_trace = gr.w && P.border && a == 0;
+  if (ns > 0 || need_trace) {
+#pragma unroll
+    for (int s = 0; s < EPL; ++s)
+      if (LaneMap<T, D>::on(lane, s)) buf[LaneMap<T, D>::elem(lane, s)] = u[s];
+    wave_sync();
+    if (need_trace && lane == 0)
+      for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
+    op_terms<T, D>(P, cid, (T)1, lane, buf, tval, tcol, acc);
+    wave_sync();
+  }
+}
+
+// The groups of one task added to acc, then acc written to the task's output
+// ADO (see wave_task).
+// PAIRS = false streams multi-edge groups one block at a time (fewer
+// registers; for callers that hold other blocks in registers meanwhile).
+template <typename T, int D, bool FUSE, bool PAIRS = true>
+__device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
+                                              const typename Cplx<T>::t *tval, const int *tcol,
+                                              const typename Cplx<T>::t *thd,
+                                              typename Cplx<T>::t (&acc)[WaveShape<D>::EPL]) {
   using T2 = typename Cplx<T>::t;
   using W = WaveShape<D>;
   constexpr int DD = D * D;
@@ -135,10 +213,6 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
   const int64_t a = tk.x;
   const int flags = tk.w;
   const int64_t abase = a * DD;
-  T2 acc[EPL];
-#pragma unroll
-  for (int s = 0; s < EPL; ++s)
-    acc[s] = (flags & TASK_ACC) && LaneMap<T, D>::on(lane, s) ? P.y[abase + LaneMap<T, D>::elem(lane, s)] : T2{0, 0};
   T2 trace{0, 0};
   int g = tk.y;
   if (g < tk.z) {
@@ -158,7 +232,7 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
         load_block<T, D, FUSE>(P, P.gedges[grn.x].x, lane, vnext);
       }
       int e = gr.x + 1;
-      for (; e + 1 < gr.y; e += 2) {
+      for (; PAIRS && e + 1 < gr.y; e += 2) {
         const int2 e0 = P.gedges[e], e1 = P.gedges[e + 1];
         T2 v0[EPL], v1[EPL];
         load_block<T, D, FUSE>(P, e0.x, lane, v0);
@@ -170,7 +244,7 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
           u[s].y = fma(w0, v0[s].y, fma(w1, v1[s].y, u[s].y));
         }
       }
-      if (e < gr.y) {
+      for (; e < gr.y; ++e) {
         const int2 e0 = P.gedges[e];
         T2 v0[EPL];
         load_block<T, D, FUSE>(P, e0.x, lane, v0);
@@ -181,60 +255,7 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
           u[s].y = fma(w0, v0[s].y, u[s].y);
         }
       }
-      if (gr.w) {
-        // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
-        const T2 z = P.shifts ? P.shifts[0] : P.shift0;
-        const T2 c = csub(P.decay[a], z);
-#pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-          const T2 dh = csub(thd[LaneMap<T, D>::elem(lane, s) / D], thd[LaneMap<T, D>::col(lane, s)]);
-          const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
-          acc[s] = csub(acc[s], cmul(f, u[s]));
-        }
-      }
-      const int cid = gr.z;
-      const int op = P.coef_op[cid];
-      const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
-      const bool need_trace = gr.w && P.border && a == 0;
-      if (ns > 0 || need_trace) {
-#pragma unroll
-        for (int s = 0; s < EPL; ++s)
-          if (LaneMap<T, D>::on(lane, s)) buf[LaneMap<T, D>::elem(lane, s)] = u[s];
-        wave_sync();
-        if (need_trace && lane == 0)
-          for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
-        if (ns > 0) {
-          const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
-#pragma unroll
-          for (int s = 0; s < EPL; ++s) {
-            if (!LaneMap<T, D>::on(lane, s)) continue;
-            const int i = LaneMap<T, D>::elem(lane, s) / D;
-            const int j = LaneMap<T, D>::col(lane, s);
-            const int rbase = off + (D + j) * ns;
-            const int lbase = off + i * ns;
-            T2 L{0, 0}, Rv{0, 0};
-            if (isreal) {
-#pragma unroll 1
-              for (int t = 0; t < ns; ++t) {
-                const T vl = tval[lbase + t].x, vr = tval[rbase + t].x;
-                const T2 bl = buf[tcol[lbase + t] * D + j];
-                const T2 br = buf[i * D + tcol[rbase + t]];
-                L.x = fma(vl, bl.x, L.x); L.y = fma(vl, bl.y, L.y);
-                Rv.x = fma(vr, br.x, Rv.x); Rv.y = fma(vr, br.y, Rv.y);
-              }
-            } else {
-#pragma unroll 1
-              for (int t = 0; t < ns; ++t) {
-                L = cfma(tval[lbase + t], buf[tcol[lbase + t] * D + j], L);
-                Rv = cfma(buf[i * D + tcol[rbase + t]], tval[rbase + t], Rv);
-              }
-            }
-            acc[s] = cfma(cl, L, acc[s]);
-            acc[s] = cfma(cr, Rv, acc[s]);
-          }
-        }
-        wave_sync();
-      }
+      group_terms<T, D>(P, gr, a, lane, u, buf, tval, tcol, thd, acc, trace);
       gr = grn;
     }
   }
@@ -245,6 +266,29 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
     if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;  // element 0 in both maps
     P.y[abase + LaneMap<T, D>::elem(lane, s)] = v;
   }
+}
+
+// One output ADO (task) of the wave formulation, computed by one wavefront:
+// the task's groups stream their neighbour blocks (the next group's first
+// block prefetched while the current one is finished, multi-edge groups two
+// blocks at a time), each group sum is staged in the wave's LDS slice `buf`,
+// and the operator products gather from it through the compact tables
+// (tval, tcol) and the H diagonal (thd) held in LDS.  A task flagged
+// TASK_ACC adds to the output instead of overwriting it.
+template <typename T, int D, bool FUSE, bool PAIRS = true>
+__device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
+                                          const typename Cplx<T>::t *tval, const int *tcol,
+                                          const typename Cplx<T>::t *thd) {
+  using T2 = typename Cplx<T>::t;
+  constexpr int DD = D * D;
+  constexpr int EPL = WaveShape<D>::EPL;
+  const int4 tk = P.tasks[task];
+  const int64_t abase = (int64_t)tk.x * DD;
+  T2 acc[EPL];
+#pragma unroll
+  for (int s = 0; s < EPL; ++s)
+    acc[s] = (tk.w & TASK_ACC) && LaneMap<T, D>::on(lane, s) ? P.y[abase + LaneMap<T, D>::elem(lane, s)] : T2{0, 0};
+  wave_task_add<T, D, FUSE, PAIRS>(P, task, lane, buf, tval, tcol, thd, acc);
 }
 
 }  // namespace heom

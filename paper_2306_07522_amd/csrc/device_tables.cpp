@@ -1,6 +1,7 @@
 // Upload of the hierarchy tables to the device, and the apply launch plans.
 #include <algorithm>
 #include <cmath>
+#include <map>
 
 #include "dense.h"
 #include "internal.h"
@@ -36,7 +37,7 @@ void free_device(Hier &h) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_plan(D.base);
-  free_plan(D.slab);
+  free_slab_plan(D.slab);
   for (auto &kv : D.tiled) free_plan(kv.second);
   (void)hipSetDevice(cur);
   D = DeviceTables();
@@ -100,7 +101,7 @@ struct PlanBuilder {
   }
 };
 
-static heom_status build_slab_plan(Hier &h, Plan &out, size_t &tot);
+static heom_status build_slab_plan(const Hier &h, SlabPlan *out, size_t &tot, heom_slab_stats *stats);
 
 // Upload of every table and launch plan to device `dev`; runs once per
 // handle, under h.dev_mu.
@@ -230,7 +231,7 @@ static heom_status upload_tables(Hier &h, int dev) {
       (st = upload(&D.c_val64, cv64.data(), sizeof(double2) * cv64.size(), tot)) ||
       (st = upload(&D.c_val32, cv32.data(), sizeof(float2) * cv32.size(), tot)) ||
       (st = pb.upload_to(D.base, tot)) ||
-      (st = build_slab_plan(h, D.slab, tot))) {
+      (st = build_slab_plan(h, &D.slab, tot, nullptr))) {
     free_device(h);
     return st;
   }
@@ -254,57 +255,155 @@ heom_status ensure_device(Hier &h) {
 
 // ---------------------------------------------------------------- slab plan
 // For a purely fermionic hierarchy cut at tier L = n_max, every top-tier ADO
-// c (an L-subset of exponent labels) feeds the up-terms of its L parents
-// c \ {u} (eq:HEOM, the C-type terms).  The single-launch plan has every
-// parent gather its children, so each child block is fetched once for its
-// own row and once per parent; the parents' child sets overlap like an
-// expander graph, and the cache sees little of that reuse.
+// c (an L-subset of exponent labels) feeds the up-terms (the C-type terms of
+// eq:HEOM) of its L parents c \ {u}.  In the single-launch plan every parent
+// gathers its children, so a child block leaves memory once for its own row
+// and once per parent, and the parents' child sets overlap like an expander
+// graph, so the caches see little of that reuse.
 //
 // The slab plan splits each tier-(L-1) parent P's up-terms by the position
 // the added label u takes in the child:
-//  * prefix part, u above the second largest label of P: the child then
-//    shares its L - 2 smallest labels (its prefix core) with P minus max(P);
-//  * suffix part, every other u: for L = 4 the child shares its L - 2
-//    largest labels (its suffix core) with P minus min(P).
-// A slab is the set of parents and children with one core.  Launch A runs
-// the tiers below L - 1 in full and then, slab by slab, the prefix parts of
-// the slab's parents (written to y) followed by the full rows of its
-// children (self and down terms).  Launch B runs, slab by slab, the rest of
-// each parent's row (self, down terms, suffix part) and adds it to y.  A
-// slab's children are read by the slab's parents and children close
-// together in time; each XCD walks a contiguous run of slabs, so those
-// re-reads stay in its L2 and a top-tier block leaves HBM about once per
-// launch instead of once per parent.
+//  * prefix part, u above the second largest label of P: the child then has
+//    the same L - 2 smallest labels (its prefix core) as P minus max(P);
+//  * suffix part, u below the second smallest label of P: the child has the
+//    same L - 2 largest labels (its suffix core) as P minus min(P);
+//  * for L >= 5 the positions in between stay with plain gathers.
+// A slab is one core with its parents (core + one label beyond it) and its
+// children (core + two labels beyond it), so a child is a pair of the slab's
+// parents and feeds exactly those two.  Launch A runs the prefix slabs: per
+// slab workgroup, the children arrive in sub-rounds of a round-robin pairing
+// of the parents (no parent twice in a sub-round), are read once into LDS,
+// add their terms to both parents' register accumulators from there, and
+// have their own rows (self and down terms) computed; at the end the
+// parents' prefix parts are written to y.  Launch A also runs the tiers
+// below L - 1.  Launch B runs the suffix slabs the same way and finishes each
+// parent's row (self, down terms, the rest of its up-terms) on top of y.  A
+// top-tier block thus leaves memory once per launch.
 static bool slab_applicable(const Hier &h) {
   const int L = h.Lf;
+  // LDS of a slab workgroup in FP64: staging, two sub-round buffers, operator tables
+  const size_t lds = (size_t)2 * kSlabSub * h.d * h.d * 16 + h.ell.c_col.size() * 20 + h.coefs.size() * 48 + 32 + h.d * 16;
   return h.Kb == 0 && h.importance_threshold <= 0.0 && L >= 3 && (int)h.tier_off.size() == L + 2 &&
-         h.tier_off[L + 1] > h.tier_off[L];
+         h.tier_off[L + 1] > h.tier_off[L] && (h.d == 8 || h.d == 16) && lds <= 160 * 1024;
 }
 
-// Cuts tasks [0, n) with costs c into 8 contiguous runs of similar cost,
-// at unit boundaries (unit_start[t] = true where a slab begins).
-static std::vector<int64_t> xcd_split(const std::vector<int64_t> &cost, const std::vector<char> &unit_start) {
-  const int64_t n = (int64_t)cost.size();
-  std::vector<int64_t> pre(n + 1, 0);
-  for (int64_t t = 0; t < n; ++t) pre[t + 1] = pre[t] + cost[t];
-  std::vector<int64_t> off(9, 0);
-  off[8] = n;
-  int64_t t = 0;
-  for (int k = 1; k < 8; ++k) {
-    const double target = (double)pre[n] * k / 8.0;
-    t = std::max(t, off[k - 1]);
-    while (t < n && (double)pre[t + 1] <= target) ++t;  // pre[t] <= target < pre[t + 1]
-    // nearest unit boundary at or around t
-    int64_t lo = t, hi = t;
-    while (lo > off[k - 1] && !unit_start[lo]) --lo;
-    while (hi < n && !unit_start[hi]) ++hi;
-    off[k] = (target - (double)pre[lo] <= (double)pre[hi] - target) ? lo : hi;
-    if (off[k] < off[k - 1]) off[k] = off[k - 1];
+// Round-robin pairing of n items (circle method): rounds of disjoint pairs
+// covering every pair once.
+static std::vector<std::vector<std::pair<int, int>>> round_robin(int n) {
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  const int m = n + (n & 1);  // a dummy item when n is odd
+  for (int r = 0; r + 1 < m; ++r) {
+    std::vector<std::pair<int, int>> pr;
+    auto push = [&](int a, int b) {
+      if (a < n && b < n) pr.push_back({std::min(a, b), std::max(a, b)});
+    };
+    push(r, m - 1);
+    for (int k = 1; k < m / 2; ++k) push((r + k) % (m - 1), (r - k + (m - 1)) % (m - 1));
+    rounds.push_back(pr);
   }
-  return off;
+  return rounds;
 }
 
-static heom_status build_slab_plan(Hier &h, Plan &out, size_t &tot) {
+struct SlabJob {
+  std::vector<int2> vert;                 // {ADO, finalize task}
+  std::vector<std::vector<int4>> subs;    // sub-rounds of entries
+  int64_t cost = 0;
+  int64_t group = 0;                      // jobs sharing a group read the same parents
+  int64_t slab = 0, slab_cost = 0;        // parts of one slab share the children between them
+};
+
+struct PassHost {
+  std::vector<int4> jt;
+  std::vector<int32_t> sub;
+  std::vector<int4> ent;
+  std::vector<int2> vert;
+  std::vector<int64_t> load;
+  int max_vert = 0;
+};
+
+static heom_status layout_pass(std::vector<SlabJob> &jobs, PassHost &H) {
+  // XCD assignment: groups (by cost) onto the 8 XCDs, least loaded first;
+  // each XCD then runs its jobs costliest first.  Workgroup b runs on XCD
+  // b % 8, so job i of XCD k sits at position 8 i + k.
+  std::map<int64_t, int64_t> gcost;
+  for (auto &j : jobs) gcost[j.group] += j.cost;
+  std::vector<std::pair<int64_t, int64_t>> gl(gcost.begin(), gcost.end());
+  std::stable_sort(gl.begin(), gl.end(), [](auto &a, auto &b) { return a.second > b.second; });
+  std::map<int64_t, int> gx;
+  std::vector<int64_t> load(8, 0);
+  for (auto &g : gl) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    gx[g.first] = k;
+    load[k] += g.second;
+  }
+  std::vector<std::vector<int>> lists(8);
+  for (int i = 0; i < (int)jobs.size(); ++i) lists[gx[jobs[i].group]].push_back(i);
+  size_t most = 0;
+  for (auto &l : lists) {
+    // costliest slabs first; the parts of one slab next to each other, so
+    // that the children they share are still in L2 for the second part
+    std::stable_sort(l.begin(), l.end(), [&](int a, int b) {
+      if (jobs[a].slab_cost != jobs[b].slab_cost) return jobs[a].slab_cost > jobs[b].slab_cost;
+      if (jobs[a].group != jobs[b].group) return jobs[a].group < jobs[b].group;
+      return jobs[a].slab < jobs[b].slab;
+    });
+    most = std::max(most, l.size());
+  }
+  std::vector<int4> &jt = H.jt;
+  std::vector<int32_t> &sub = H.sub;
+  std::vector<int4> &ent = H.ent;
+  std::vector<int2> &vert = H.vert;
+  jt.assign(8 * most, make_int4(0, 0, 0, 0));
+  for (size_t i = 0; i < most; ++i)
+    for (int k = 0; k < 8; ++k) {
+      if (i >= lists[k].size()) continue;
+      SlabJob &J = jobs[lists[k][i]];
+      if (J.vert.empty() && J.subs.empty()) continue;
+      int4 &o = jt[8 * i + k];
+      if (J.subs.empty() && !J.vert.empty() && J.vert[0].x < 0) {  // plain job
+        o = make_int4(J.vert[0].y, -(int)J.vert.size(), 0, 0);
+        continue;
+      }
+      o.x = (int)vert.size();
+      o.y = (int)J.vert.size();
+      o.z = (int)sub.size();
+      o.w = (int)J.subs.size();
+      H.max_vert = std::max(H.max_vert, (int)J.vert.size());
+      for (auto &v : J.vert) vert.push_back(v);
+      for (auto &sr : J.subs) {
+        sub.push_back((int)ent.size());
+        for (auto &e : sr) ent.push_back(e);
+      }
+      sub.push_back((int)ent.size());
+    }
+  if (ent.size() > 0x7fffffffull) return fail(HEOM_ERR_UNSUPPORTED, "slab plan too large");
+  H.load = load;
+  return HEOM_OK;
+}
+
+static heom_status upload_pass(const PassHost &H, SlabPass &P, size_t &tot) {
+  HEOM_TRY(upload(&P.jobs, H.jt.data(), sizeof(int4) * H.jt.size(), tot));
+  HEOM_TRY(upload(&P.sub, H.sub.data(), sizeof(int32_t) * H.sub.size(), tot));
+  HEOM_TRY(upload(&P.ent, H.ent.data(), sizeof(int4) * H.ent.size(), tot));
+  HEOM_TRY(upload(&P.vert, H.vert.data(), sizeof(int2) * H.vert.size(), tot));
+  P.n_jobs = (int64_t)H.jt.size();
+  P.cost = H.load;
+  return HEOM_OK;
+}
+
+void free_slab_plan(SlabPlan &p) {
+  free_plan(p.tasks);
+  for (auto &q : p.pass) {
+    for (void *ptr : {(void *)q.jobs, (void *)q.sub, (void *)q.ent, (void *)q.vert})
+      if (ptr) (void)hipFree(ptr);
+    q = SlabPass();
+  }
+  p.built = false;
+}
+
+// Host side of the slab plan: companion tasks and the job layout of both
+// launches, with the coverage checks.  Uploaded when `out` is given.
+static heom_status build_slab_plan(const Hier &h, SlabPlan *out, size_t &tot, heom_slab_stats *stats) {
   if (!slab_applicable(h)) return HEOM_OK;
   const int L = h.Lf;
   const int64_t v0 = h.tier_off[L - 1], c0 = h.tier_off[L], c1 = h.tier_off[L + 1];
@@ -316,7 +415,8 @@ static heom_status build_slab_plan(Hier &h, Plan &out, size_t &tot) {
     const int64_t a = lookup_ado(h, m, 0);
     return (a >= k0 && a < v0) ? a - k0 : -1;
   };
-  std::vector<std::vector<int64_t>> pv(n_core), pc(n_core), sv(n_core);
+  // vertices of each slab, in ascending order of their extra label
+  std::vector<std::vector<int64_t>> pv(n_core), sv(n_core);
   for (int64_t P = v0; P < c0; ++P) {
     const uint64_t m = h.fmask[P];
     const int64_t kp = core_of(m & ~(1ull << top_bit(m))), ks = core_of(m & ~(1ull << low_bit(m)));
@@ -324,82 +424,202 @@ static heom_status build_slab_plan(Hier &h, Plan &out, size_t &tot) {
     pv[kp].push_back(P);
     sv[ks].push_back(P);
   }
-  for (int64_t c = c0; c < c1; ++c) {
-    uint64_t m = h.fmask[c];
-    m &= ~(1ull << top_bit(m));
-    m &= ~(1ull << top_bit(m));
-    const int64_t kp = core_of(m);
-    if (kp < 0) return fail(HEOM_ERR_ARG, "slab plan: missing core ADO");
-    pc[kp].push_back(c);
-  }
-  // up edge e of parent P belongs to the prefix part when its added label
-  // lies above the second largest label of P
-  auto prefix_part = [&](int64_t P, int64_t e) {
-    const uint64_t m = h.fmask[P];
+  // edge of row P that reaches ADO c
+  auto edge_to = [&](int64_t P, int64_t c) -> int64_t {
+    for (int64_t e = h.row_ptr[P]; e < h.row_ptr[P + 1]; ++e)
+      if (h.ecol[e] == c) return e;
+    return -1;
+  };
+  auto part_of = [&](int64_t P, int64_t e) -> int {  // 0 prefix, 1 suffix, 2 plain gather, -1 not an up edge
     const int64_t c = h.ecol[e];
-    if (c < c0) return false;  // down edge
+    if (c < c0) return -1;
+    const uint64_t m = h.fmask[P];
     const int u = low_bit(h.fmask[c] & ~m);
-    const int second = top_bit(m & ~(1ull << top_bit(m)));
-    return u > second;
+    const int second_top = top_bit(m & ~(1ull << top_bit(m)));
+    const int second_low = low_bit(m & ~(1ull << low_bit(m)));
+    if (u > second_top) return 0;
+    if (u < second_low) return 1;
+    return 2;
   };
   PlanBuilder pb(h);
-  std::vector<int64_t> es, cost;
-  std::vector<char> ustart;
-  int64_t n_edges = 0, n_self = 0;
-  auto add = [&](int64_t a, bool self, bool acc, bool first) {
+  std::vector<int64_t> es;
+  int64_t n_cov = 0, n_self = 0;  // coverage check: every edge and every self term exactly once
+  int64_t n_own = 0, n_vert[2] = {0, 0};  // every child row scheduled once, every parent once per launch
+  auto task_row = [&](int64_t a, bool self, bool acc) {
     pb.add_task(a, es, self, acc);
-    cost.push_back(1 + (int64_t)es.size());
-    ustart.push_back(first);
-    n_edges += (int64_t)es.size();
+    n_cov += (int64_t)es.size();
     n_self += self;
+    return (int)pb.tasks.size() - 1;
   };
-  // launch A
+  // companion tasks, in launch order.  The rows launch (the ordinary wave
+  // kernel) runs the tiers below L - 1 and the children's own rows (self and
+  // down terms), the latter in windows of their largest label: three of a
+  // child's four parents hold that label too, so the window's parents are
+  // re-read from cache.
   for (int64_t a = 0; a < v0; ++a) {
     es.clear();
     for (int64_t e = h.row_ptr[a]; e < h.row_ptr[a + 1]; ++e) es.push_back(e);
-    add(a, true, false, true);
+    task_row(a, true, false);
   }
+  {
+    std::vector<std::pair<int64_t, int64_t>> order;
+    order.reserve(c1 - c0);
+    for (int64_t c = c0; c < c1; ++c) order.push_back({top_bit(h.fmask[c]), c});
+    std::stable_sort(order.begin(), order.end());
+    for (auto &oc : order) {
+      es.clear();
+      for (int64_t e = h.row_ptr[oc.second]; e < h.row_ptr[oc.second + 1]; ++e) es.push_back(e);
+      task_row(oc.second, true, false);
+      ++n_own;
+    }
+  }
+  const int64_t n_rows = (int64_t)pb.tasks.size();
+  // companion tasks finishing the parents' rows (launch B)
+  std::vector<int> fin_task(c0 - v0, -1);
+  for (int64_t P = v0; P < c0; ++P) {
+    es.clear();
+    for (int64_t e = h.row_ptr[P]; e < h.row_ptr[P + 1]; ++e) {
+      const int pt = part_of(P, e);
+      if (pt == -1 || pt == 2) es.push_back(e);
+    }
+    fin_task[P - v0] = task_row(P, true, true);
+  }
+  std::vector<SlabJob> jobsA, jobsB;
+  int64_t costA = 0, costB = 0;
+  // one slab -> jobs.  side_part: which part of the parents' up-terms this
+  // launch owns (0 prefix, 1 suffix).
+  auto slab_jobs = [&](const std::vector<int64_t> &V, uint64_t core, int side_part, int64_t group, int64_t slab_id,
+                       std::vector<SlabJob> &out_jobs, int64_t max_cost) -> heom_status {
+    const int m = (int)V.size();
+    if (m == 0) return HEOM_OK;
+    const size_t first_job = out_jobs.size();
+    std::vector<int> extra(m);
+    for (int t = 0; t < m; ++t) extra[t] = low_bit(h.fmask[V[t]] & ~core);
+    auto rounds = round_robin(m);
+    // cost of the whole slab decides the split into vertex ranges
+    const int64_t n_pairs = (int64_t)m * (m - 1) / 2;
+    const int64_t whole = n_pairs + (int64_t)m * (side_part == 0 ? 1 : 8);
+    int G = (int)std::max<int64_t>(1, (whole + max_cost - 1) / std::max<int64_t>(max_cost, 1));
+    G = std::max(G, (m + kSlabWaves * kSlabVmax - 1) / (kSlabWaves * kSlabVmax));
+    G = std::min(G, std::max(1, m / 4));
+    // split points: equal numbers of vertices
+    std::vector<int> cut(G + 1, m);
+    cut[0] = 0;
+    {
+      std::vector<int64_t> wsum(m + 1, 0);
+      for (int t = 0; t < m; ++t) wsum[t + 1] = wsum[t] + 1;
+      for (int g = 1; g < G; ++g) {
+        int t = cut[g - 1] + 1;
+        while (t < m && wsum[t] * G < wsum[m] * g) ++t;
+        cut[g] = std::min(t, m - (G - g));
+      }
+    }
+    for (int g = 0; g < G; ++g) {
+      const int lo = cut[g], hi = cut[g + 1];
+      if (hi - lo > kSlabWaves * kSlabVmax) return fail(HEOM_ERR_ARG, "slab plan: too many vertices in one job");
+      SlabJob J;
+      J.group = group;
+      for (int t = lo; t < hi; ++t) J.vert.push_back(make_int2((int)V[t], side_part == 1 ? fin_task[V[t] - v0] : -1));
+      for (auto &rd : rounds) {
+        std::vector<int4> cur;
+        for (auto &pr : rd) {
+          const int a = pr.first, b = pr.second;
+          const bool ma = a >= lo && a < hi, mb = b >= lo && b < hi;
+          if (!ma && !mb) continue;
+          const uint64_t cm = core | (1ull << extra[a]) | (1ull << extra[b]);
+          const int64_t c = lookup_ado(h, cm, 0);
+          if (c < c0 || c >= c1) return fail(HEOM_ERR_ARG, "slab plan: missing child ADO");
+          // a side is this job's when its vertex is and its edge belongs to
+          // this launch's part (for L = 3 a suffix-slab pair feeds only its
+          // upper vertex: the lower one takes that child in its prefix part)
+          auto side = [&](int t, bool mine) -> int {
+            if (!mine) return 127 << 24;
+            const int64_t e = edge_to(V[t], c);
+            if (e < 0) return -1;
+            if (part_of(V[t], e) != side_part) return 127 << 24;
+            const int cid = (int)((uint32_t)h.einfo[e] >> 8);
+            const int mult = (int)(int8_t)(h.einfo[e] & 0xff);
+            if (cid >= (1 << 23) || (mult != 1 && mult != -1)) return -1;
+            n_cov += 1;
+            return ((t - lo) << 24) | (mult < 0 ? (1 << 23) : 0) | cid;
+          };
+          const int sa = side(a, ma), sb = side(b, mb);
+          if (sa < 0 || sb < 0) return fail(HEOM_ERR_ARG, "slab plan: inconsistent edge");
+          if (sa == (127 << 24) && sb == (127 << 24)) continue;
+          cur.push_back(make_int4((int)c, -1, sa, sb));
+          J.cost += 1;
+          if ((int)cur.size() == kSlabSub) {
+            J.subs.push_back(cur);
+            cur.clear();
+          }
+        }
+        if (!cur.empty()) J.subs.push_back(cur);
+      }
+      J.cost += (int64_t)J.vert.size() * (side_part == 0 ? 1 : 8);
+      n_vert[side_part] += (int64_t)J.vert.size();
+      J.slab = slab_id;
+      out_jobs.push_back(std::move(J));
+    }
+    int64_t sc = 0;
+    for (size_t q = first_job; q < out_jobs.size(); ++q) sc += out_jobs[q].cost;
+    for (size_t q = first_job; q < out_jobs.size(); ++q) out_jobs[q].slab_cost = sc;
+    return HEOM_OK;
+  };
+  // target job cost: about two jobs per compute unit
+  const int64_t n_pair_total = c1 - c0;
+  const int64_t maxA = std::max<int64_t>(64, (n_pair_total + (c0 - v0)) / 512);
+  const int64_t maxB = std::max<int64_t>(64, (n_pair_total * 1 + (c0 - v0) * 8) / 512);
   for (int64_t k = 0; k < n_core; ++k) {
-    bool first = true;
-    for (int64_t P : pv[k]) {
-      es.clear();
-      for (int64_t e = h.row_ptr[P]; e < h.row_ptr[P + 1]; ++e)
-        if (prefix_part(P, e)) es.push_back(e);
-      add(P, false, false, first);
-      first = false;
-    }
-    for (int64_t c : pc[k]) {
-      es.clear();
-      for (int64_t e = h.row_ptr[c]; e < h.row_ptr[c + 1]; ++e) es.push_back(e);
-      add(c, true, false, first);
-      first = false;
-    }
+    const uint64_t core = h.fmask[k0 + k];
+    // jobs that read the same non-local parents share a group: the core minus its smallest label
+    const int64_t group = (int64_t)(core & ~(core ? (1ull << low_bit(core)) : 0ull));
+    HEOM_TRY(slab_jobs(pv[k], core, 0, group, k, jobsA, maxA));
+    HEOM_TRY(slab_jobs(sv[k], core, 1, group, k, jobsB, maxB));
   }
-  const int64_t nA = (int64_t)pb.tasks.size();
-  std::vector<int64_t> costA(cost.begin(), cost.end());
-  std::vector<char> ustartA(ustart.begin(), ustart.end());
-  cost.clear();
-  ustart.clear();
-  // launch B
-  for (int64_t k = 0; k < n_core; ++k) {
-    bool first = true;
-    for (int64_t P : sv[k]) {
-      es.clear();
-      for (int64_t e = h.row_ptr[P]; e < h.row_ptr[P + 1]; ++e)
-        if (!prefix_part(P, e)) es.push_back(e);
-      add(P, true, true, first);
-      first = false;
-    }
-  }
-  const int64_t nB = (int64_t)pb.tasks.size() - nA;
-  // every ADO's row exactly once: one self group per ADO, every edge once
-  if (nB != c0 - v0 || nA != c1 - (c0 - v0) || n_self != h.N || n_edges != h.row_ptr[h.N])
+  for (auto &j : jobsA) costA += j.cost;
+  for (auto &j : jobsB) costB += j.cost;
+  if (n_self != h.N || n_cov != h.row_ptr[h.N] || n_own != c1 - c0 || n_vert[0] != c0 - v0 || n_vert[1] != c0 - v0)
     return fail(HEOM_ERR_ARG, "slab plan: rows not covered exactly once");
-  HEOM_TRY(pb.upload_to(out, tot));
-  out.task_off = {0, nA, nA + nB};
-  out.xcd_off = {xcd_split(costA, ustartA), xcd_split(cost, ustart)};
+  PassHost HA, HB;
+  HEOM_TRY(layout_pass(jobsA, HA));
+  HEOM_TRY(layout_pass(jobsB, HB));
+  if (stats) {
+    stats->built = 1;
+    stats->children = c1 - c0;
+    stats->parents = c0 - v0;
+    const PassHost *hp[2] = {&HA, &HB};
+    for (int l = 0; l < 2; ++l) {
+      stats->jobs[l] = (int64_t)hp[l]->jt.size();
+      stats->entries[l] = (int64_t)hp[l]->ent.size();
+      stats->max_vertices[l] = hp[l]->max_vert;
+      for (int k = 0; k < 8; ++k) stats->xcd_cost[l][k] = hp[l]->load[k];
+    }
+    stats->cost[0] = costA;
+    stats->cost[1] = costB;
+  }
+  if (!out) return HEOM_OK;
+  HEOM_TRY(pb.upload_to(out->tasks, tot));
+  out->tasks.task_off = {0, (int64_t)pb.tasks.size()};
+  out->n_rows = n_rows;
+  HEOM_TRY(upload_pass(HA, out->pass[0], tot));
+  HEOM_TRY(upload_pass(HB, out->pass[1], tot));
+  out->built = true;
   return HEOM_OK;
 }
+
+}  // namespace heom
+
+extern "C" heom_status heom_slab_plan_stats(const heom_hier *hw, heom_slab_stats *out) {
+  using namespace heom;
+  return guarded([&]() -> heom_status {
+    if (!hw || !out) return fail(HEOM_ERR_ARG, "slab_plan_stats: NULL argument");
+    *out = heom_slab_stats{};
+    size_t tot = 0;
+    return build_slab_plan(*hw->impl, nullptr, tot, out);
+  });
+}
+
+namespace heom {
 
 // Tiled plan.  The leaf ADOs (no higher-tier neighbour: the last tier) are
 // split into n_chunks contiguous column blocks.  Launch 0 computes every

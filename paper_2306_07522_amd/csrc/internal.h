@@ -82,18 +82,45 @@ struct OpEll {
 // A group shares one operator and one coefficient pair (cl, cr); its edges
 // carry a small integer weight, so the group contributes
 //   cl * O u + cr * u O,   u = sum_e w_e x_{b_e}.
-//
-// A launch may also carry an XCD split: xcd_off[l][k] .. xcd_off[l][k + 1]
-// is the contiguous run of launch l's tasks that XCD k walks (workgroup b
-// runs on XCD b % 8), cut so that the runs cost about the same.
 struct Plan {
   int n_chunks = -1;             // -1: untiled single launch
   int4 *tasks = nullptr;         // {a, g0, g1, flags}
   int4 *groups = nullptr;        // {e0, e1, coef_id, self}
   int2 *gedges = nullptr;        // {b, w}
   std::vector<int64_t> task_off; // [n_launch + 1]
-  std::vector<std::vector<int64_t>> xcd_off;  // empty, or [n_launch][9] (relative to task_off[l])
   size_t bytes = 0;
+};
+
+// Slab passes of the apply (built in device_tables.cpp, run by
+// apply_slab.hip).  A job is one workgroup's share of a label slab: the
+// slab's parents (vertices) whose up-term accumulators the workgroup keeps in
+// registers, and the slab's children, fed to it in sub-rounds (disjoint pairs
+// of vertices, so no two children of a sub-round touch the same vertex) that
+// are staged once in LDS and serve both of their parents from there.
+//   jobs: {vert_off, n_vert, sub_off, n_sub}; n_vert < 0 marks a plain job
+//         running companion tasks [vert_off, vert_off - n_vert) one per wave;
+//   sub:  entry boundaries, sub[sub_off + s] .. sub[sub_off + s + 1];
+//   ent:  {child ADO, companion task of the child's own row or -1,
+//          side A, side B}, a side packing the coefficient entry (bits
+//          0..22), a negative reorder sign (bit 23) and the job-local vertex
+//          slot (bits 24..30; 127 = not this job's vertex);
+//   vert: {ADO, companion task finishing the vertex's row or -1}.
+struct SlabPass {
+  int4 *jobs = nullptr;
+  int32_t *sub = nullptr;
+  int4 *ent = nullptr;
+  int2 *vert = nullptr;
+  int64_t n_jobs = 0;
+  std::vector<int64_t> cost;    // per XCD, for the record
+};
+constexpr int kSlabWaves = 8;   // waves per slab workgroup
+constexpr int kSlabSub = 16;    // children per sub-round
+constexpr int kSlabVmax = 4;    // vertex accumulators per wave
+struct SlabPlan {
+  Plan tasks;                   // companion tasks, groups and edges
+  int64_t n_rows = 0;           // companion tasks [0, n_rows): the rows launch
+  SlabPass pass[2];
+  bool built = false;
 };
 
 // Device copies of the tables, one set per precision for the values.
@@ -121,7 +148,7 @@ struct DeviceTables {
   double2 *c_val64 = nullptr;
   float2 *c_val32 = nullptr;
   Plan base;                    // untiled, one launch: every ADO gathers all its neighbours
-  Plan slab;                    // two launches over label slabs (empty when not applicable)
+  SlabPlan slab;                // two launches over label slabs (built = false when not applicable)
   std::map<int, Plan> tiled;    // top tier split into chunks, by chunk count
   size_t bytes = 0;
 };
@@ -195,6 +222,12 @@ struct ApplyArgs {
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
 // as launch_apply with an explicit plan (HEOM_PLAN_*)
 heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int plan, hipStream_t s);
+// the three slab launches (apply_slab.hip)
+heom_status launch_apply_slab(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
+// the wave kernel over tasks [t0, t1) of a plan (apply.hip)
+heom_status launch_plan_range(Hier &h, int precision, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1,
+                              hipStream_t s);
+void free_slab_plan(SlabPlan &p);
 // whole RK4 steps in one workgroup for hierarchies of at most 1024 elements
 bool rk4_small_fits(const Hier &h);
 heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t steps, int64_t save_every,

@@ -301,3 +301,50 @@ def test_spectrum_chunk_rule():
     assert lib.heom_spectrum_chunk(None, C.byref(o8)) == 0
     hs.close()
     hc.close()
+
+
+def _fermionic_model(seed, d, n_baths, nf, n_max, dense=True):
+    rng = np.random.default_rng(seed)
+    H = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    baths = wl.random_raw_baths(rng, d, n_bos_baths=0, n_ferm_baths=n_baths, n_ferm_exp=nf, dense_ops=dense)
+    return dict(H=H + H.conj().T, baths=baths, m_max=0, n_max=n_max)
+
+
+@pytest.mark.parametrize("d,n_baths,nf,n_max,dense", [
+    (8, 2, 2, 4, True), (16, 2, 2, 4, False), (8, 3, 2, 3, True), (8, 2, 2, 5, True), (8, 1, 4, 3, True),
+])
+def test_slab_plan_layout(d, n_baths, nf, n_max, dense):
+    """The slab plan of purely fermionic hierarchies, built on the host: the
+    build itself checks that every row's self term and every neighbour term
+    is scheduled exactly once (it fails otherwise); here also that every
+    top-tier ADO is read in launch A, that no job holds more parents than the
+    register accumulators, and that both launches are spread over 8 XCDs."""
+    cfg = _fermionic_model(300 + d + n_max, d, n_baths, nf, n_max, dense)
+    lm = library_model(cfg)
+    st = lm.slab_plan_stats()
+    assert st is not None
+    info = lm.info
+    t = list(info.tier_offset)
+    assert st["children"] == t[n_max + 1] - t[n_max] and st["parents"] == t[n_max] - t[n_max - 1]
+    assert st["entries"][0] >= st["children"]
+    assert max(st["max_vertices"]) <= 32
+    assert st["jobs"][0] % 8 == 0 and st["jobs"][1] % 8 == 0
+
+
+def test_slab_plan_two_orbital_tier4():
+    """The two-orbital model at tier 4 (213,053 ADOs): launch A reads each
+    top-tier ADO at most about 1.35 times (splitting a large slab over several
+    workgroups duplicates the children they share), the XCD loads are within
+    15 % of each other, and no plan exists for a model with a bosonic bath or
+    with pruning."""
+    cfg = wl.two_orbital_anderson()
+    lm = library_model(cfg, parity_op=cfg["parity_op"])
+    st = lm.slab_plan_stats()
+    assert st["children"] == 194580 and st["parents"] == 17296
+    assert st["children"] <= st["entries"][0] <= 1.35 * st["children"]
+    assert st["entries"][1] <= 1.35 * st["children"]
+    for l in range(2):
+        c = st["xcd_cost"][l]
+        assert max(c) <= 1.15 * min(c), (l, c)
+    cav = library_model(wl.charge_cavity(n_photon=3, n_bexp=2, n_fexp=2, m_max=1, n_max=2))
+    assert cav.slab_plan_stats() is None
