@@ -66,8 +66,8 @@ def parse():
     p.add_argument("--tiled", type=int, default=-1, help="-1: untiled apply; 0: default chunks; k: k chunks")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "two_orbital_dos", "cavity", "batch",
-                                             "conductance", "propagation"],
+    p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "two_orbital_dos", "two_orbital_nn",
+                                             "cavity", "batch", "conductance", "propagation"],
                    default="all",
                    help="solve timings: all legs, siam only, none, or one leg (the two-orbital stationary state "
                         "with GMRES-DR, the cavity stationary state and PSD, the 512-instance batch) for profiling")
@@ -164,33 +164,56 @@ def _solve_record(rep, wall):
             "true_residual": rep["true_residual"], "converged": rep["status"] == 0, "fell_back": bool(rep["fell_back"])}
 
 
-def _train_network(api, d, hidden, models, snapshots, restart, subset, epochs, seed=0):
-    """Pairs from plain GMRES on each model (collect_pairs), then GPU training."""
+def _protocol_pairs(api, net, models, snapshots, restart, rows_per_snapshot, seed):
+    """(X, T, W) device tensors: for every model the stationary state x* (FP64
+    GMRES-DR, 1e-10), then plain GMRES iterates x_k after k iterations for
+    each snapshot k, giving (residual, error) pairs per ADO block
+    (heom_nn_pairs); rows_per_snapshot seeded blocks of each snapshot are
+    kept (all when 0)."""
     import torch
-    net = api.Network(d=d, hidden=hidden, seed=seed)
-    t0 = time.perf_counter()
-    Xs, Ts = [], []
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    Xs, Ts, Ws = [], [], []
     for cfg in models:
         hp = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
-        for X, T in api.collect_pairs(hp, net, snapshots=snapshots, restart=restart):
+        x_star, _ = api.steady_state(hp, tol=1e-10, precond="none", restart=20, deflate=6, max_iter=20000)
+        for X, T, W in api.collect_pairs(hp, net, snapshots=snapshots, x_star=x_star, restart=restart):
+            if rows_per_snapshot and rows_per_snapshot < X.shape[0]:
+                idx = torch.randperm(X.shape[0], generator=g, device="cuda")[:rows_per_snapshot]
+                X, T, W = X[idx], T[idx], W[idx]
             Xs.append(X)
             Ts.append(T)
+            Ws.append(W)
+        del x_star
         hp.close()
-        _progress(f"pairs from one perturbed {cfg['name']} model ({time.perf_counter() - t0:.1f} s so far)")
-    X, T = torch.cat(Xs), torch.cat(Ts)
-    torch.cuda.synchronize()
+    return torch.cat(Xs), torch.cat(Ts), torch.cat(Ws)
+
+
+def nn_protocol(api, d, hidden, train_models, eval_models, snapshots, restart, rows_per_snapshot, epochs, seed=0):
+    """The learned preconditioner's protocol: pairs from plain GMRES on the
+    training models (seeded perturbations), GPU training, and the weighted
+    loss on pairs from held-out models before (untrained network) and after
+    training."""
+    net = api.Network(d=d, hidden=hidden, seed=seed)
+    t0 = time.perf_counter()
+    X, T, W = _protocol_pairs(api, net, train_models, snapshots, restart, rows_per_snapshot, seed + 11)
     t_pairs = time.perf_counter() - t0
-    losses, t_train = _timed(lambda: net.train(X, T, epochs=epochs, batch=4096, lr=1e-3, seed=seed + 1,
-                                               subset=min(subset, X.shape[0])))
-    info = {"pair_rows": int(X.shape[0]), "train_rows": int(min(subset, X.shape[0])), "epochs": epochs,
+    _progress(f"network pairs: {X.shape[0]} rows from {len(train_models)} models in {t_pairs:.1f} s")
+    Xe, Te, We = _protocol_pairs(api, net, eval_models, snapshots, restart, rows_per_snapshot, seed + 12)
+    _, held_first = net.gradients(Xe, Te, We)
+    losses, t_train = _timed(lambda: net.train(X, T, W, epochs=epochs, batch=1024, lr=1e-3, seed=seed + 1))
+    _, held_last = net.gradients(Xe, Te, We)
+    _progress(f"network trained in {t_train:.1f} s: held-out loss {held_first:.4g} -> {held_last:.4g}")
+    info = {"train_models": len(train_models), "held_out_models": len(eval_models), "pair_rows": int(X.shape[0]),
+            "held_out_rows": int(Xe.shape[0]), "snapshots": list(snapshots), "epochs": epochs,
             "pairs_seconds": round(t_pairs, 3), "train_seconds": round(t_train, 3),
-            "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
-    del X, T, Xs, Ts
+            "train_loss_first": float(losses[0]), "train_loss_last": float(losses[-1]),
+            "held_out_loss_first": float(held_first), "held_out_loss_last": float(held_last),
+            "held_out_loss_ratio": round(float(held_first / held_last), 3) if held_last > 0 else None}
+    del X, T, W, Xe, Te, We
     return net, info
 
 
-def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snapshots, pair_restart,
-                      restart_none=None, deflated=None):
+def steady_comparison(api, wl, cfg, net, info, hidden, restart, mode, restart_none=None, deflated=None):
     """Stationary state to a 1e-8 true residual: GMRES without a
     preconditioner (plain restarts, and deflated restarts (m, k) when given),
     Jacobi GMRES, and FGMRES with the network (which hands over to Jacobi if
@@ -221,16 +244,12 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
                                                      max_iter=20000, allow_not_converged=True))
     del x_p
     _progress(f"{cfg['name']} N={h.N} steady, Jacobi GMRES: {rp['iterations']} iterations, {tp:.2f} s")
-    net, info = _train_network(api, d, hidden, train_models, snapshots, pair_restart, 20000, 10)
-    _progress(f"{cfg['name']} network: {info['pair_rows']} pair rows in {info['pairs_seconds']:.1f} s, "
-              f"trained in {info['train_seconds']:.1f} s")
     # the network gets as many iterations as Jacobi needed; past that it hands
     # over to Jacobi (from its iterate, with the same budget again)
     cap = max(rp["iterations"], restart)
     (x_n, rn), tn = _timed(lambda: api.steady_state(h, tol=1e-8, precond="nn", nn=net, restart=restart, mode=mode,
                                                      max_iter=cap, allow_not_converged=True))
     del x_n
-    net.close()
     _progress(f"{cfg['name']} N={h.N} steady, NN FGMRES: {rn['iterations']} iterations, {tn:.2f} s, "
               f"fell back {rn['fell_back']}")
     plain = [(t0, r0), (tp, rp)] + ([(rec_dr["seconds"], rd), (rec_dr32["seconds"], rd32)] if rec_dr else [])
@@ -244,6 +263,32 @@ def steady_comparison(api, wl, cfg, train_models, d, hidden, restart, mode, snap
            "nn_speedup_vs_jacobi": round(tp / tn, 4) if tn > 0 and rn["status"] == 0 and rp["status"] == 0 else None,
            "nn_speedup_vs_best_plain": round(best / tn, 4) if best and tn > 0 and rn["status"] == 0 else None}
     h.close()
+    return out
+
+
+def nn_dos_sample(api, cfg, net, n_sample=1, restart=60, max_iter=1500):
+    """Density of states on an evenly spaced sample of the model's frequency
+    grid, per frequency (two shifted solves each, 1e-8): FGMRES with the
+    network (handing over to Jacobi GMRES on stagnation) against Jacobi
+    GMRES; seconds and iterations per frequency and the time this rate
+    would take on the full grid."""
+    import numpy as np
+    he = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=+1, parity_op=cfg["parity_op"])
+    ho = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=-1, parity_op=cfg["parity_op"])
+    x, _ = api.steady_state(he, tol=1e-10, precond="none", restart=20, deflate=6, max_iter=20000)
+    om = cfg["omegas"]
+    idx = np.linspace(0, len(om) - 1, n_sample + 2).astype(int)[1:-1]
+    out = {"n_omega_grid": len(om), "omegas": [float(w) for w in om[idx]]}
+    for name, kw in (("jacobi_gmres", dict(precond="jacobi")), ("nn_fgmres", dict(precond="nn", nn=net))):
+        (A, rep), t = _timed(lambda: api.spectrum(he, ho, x, cfg["dops"][0], om[idx], kind="dos", tol=1e-8,
+                                                  rhs_chunk=1, restart=restart, max_iter=max_iter,
+                                                  allow_not_converged=True, **kw))
+        out[name] = dict(_solve_record(rep, t), seconds_per_omega=round(t / len(idx), 4),
+                         full_grid_seconds_at_this_rate=round(t / len(idx) * len(om), 1),
+                         dos=[float(a) for a in A])
+        _progress(f"{cfg['name']} DOS sample of {len(idx)} frequencies, {name}: {rep['iterations']} iterations, {t:.2f} s")
+    he.close()
+    ho.close()
     return out
 
 
@@ -539,6 +584,22 @@ def deflated_steady_benchmark(api, wl):
     return {"two_orbital_tier4_steady_deflated": dict(_solve_record(r, t), restart=20, deflate=6)}
 
 
+def two_orbital_nn(api, wl):
+    """The two-orbital protocol: 40 seeded perturbations (1000..1039) give
+    2 x 10^4 pairs (250 blocks of each of two GMRES snapshots); the held-out
+    set is 5 other seeds (2000..2004) and the nominal model.  Then the
+    stationary state and a sample of the density of states, network against
+    the plain solvers."""
+    net, info = nn_protocol(api, 16, 256, [wl.perturbed_two_orbital(1000 + s) for s in range(40)],
+                            [wl.perturbed_two_orbital(2000 + s) for s in range(5)] + [wl.two_orbital_anderson()],
+                            (20, 60), 20, 250, 100)
+    out = {"two_orbital_tier4_steady": steady_comparison(api, wl, wl.two_orbital_anderson(), net, info, 256, 100,
+                                                         "fp64", restart_none=60, deflated=(20, 6)),
+           "two_orbital_tier4_dos_nn_sample": nn_dos_sample(api, wl.two_orbital_anderson(), net)}
+    net.close()
+    return out
+
+
 def solve_benchmarks(which):
     import numpy as np
     from paper_2306_07522_amd import api, workloads as wl
@@ -555,17 +616,20 @@ def solve_benchmarks(which):
         return propagation_benchmarks(api, wl)
     if which == "two_orbital_dos":
         return {"two_orbital_tier4_dos": dos_benchmark(api, wl, wl.two_orbital_anderson(), sample=0)}
-    siam_train = []
-    for s in range(4):
-        z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(4))
-        siam_train.append(wl.siam(eps=-5.0 * z[0], U=10.0 * z[1], Gamma=2.0 * z[2], mus=(z[3], -z[3])))
-    out["siam_tier3_steady"] = steady_comparison(api, wl, wl.siam(), siam_train, 4, 128, 30, "fp64", (10, 30, 60), 30)
+    if which == "two_orbital_nn":
+        return two_orbital_nn(api, wl)
+    def siam_pert(seed):
+        z = np.exp(0.1 * np.random.default_rng(seed).standard_normal(4))
+        return wl.siam(eps=-5.0 * z[0], U=10.0 * z[1], Gamma=2.0 * z[2], mus=(z[3], -z[3]))
+
+    net, info = nn_protocol(api, 4, 256, [siam_pert(1000 + s) for s in range(8)],
+                            [siam_pert(2000 + s) for s in range(3)] + [wl.siam()], (10, 30, 60), 30, 2500, 80)
+    out["siam_tier3_steady"] = steady_comparison(api, wl, wl.siam(), net, info, 256, 30, "fp64")
+    net.close()
     out["siam_tier3_dos"] = dos_benchmark(api, wl, wl.siam())
     if which == "all":
         out.update(propagation_benchmarks(api, wl))
-        train = [wl.perturbed_two_orbital(1000 + s, n_max=3) for s in range(3)]
-        out["two_orbital_tier4_steady"] = steady_comparison(api, wl, wl.two_orbital_anderson(), train, 16, 256, 100,
-                                                            "fp64", (20, 60), 100, restart_none=60, deflated=(20, 6))
+        out.update(two_orbital_nn(api, wl))
         out["two_orbital_tier4_dos"] = dos_benchmark(api, wl, wl.two_orbital_anderson(), sample=0)
         out["batch_512_instances"] = batch_benchmark(api, wl)
         out["siam_example1_conductance"] = conductance_benchmark(api, wl)

@@ -410,17 +410,21 @@ heom_status heom_spectrum(heom_hier *even, heom_hier *odd, const void *x_ss_dev,
 /* ------------------------------------------------------------------------
  * Learned block preconditioner
  * ------------------------------------------------------------------------
- * A multilayer perceptron g: features -> 2 d^2 applied to every ADO block.
- * With jr = J r (J the Jacobi preconditioner of the system: the diagonal of
- * M + shift, the bordered row counting as 1, zeros as 1) and nu_a = |jr_a|,
- * the features of block a are [Re jr_a / nu_a, Im jr_a / nu_a, n_a / n_max,
- * m_a / m_max, Re c_a / cs, Im c_a / cs] (cs = max |c_a|), padded with
- * zeros to k1 = a multiple of 32, and the preconditioned block is
- * z_a = jr_a + nu_a (g_re + i g_im).  Layers: k1 -> hidden -> hidden ->
- * o_pad (= 2 d^2 rounded up to 32) with ReLU; BF16 operands, FP32
- * accumulation, FP32 master weights.  Parameters are laid out as
- * [W1 (hidden x k1), b1, W2 (hidden x hidden), b2, W3 (o_pad x hidden), b3],
- * row-major FP32.  Networks live on the device current at creation. */
+ * A multilayer perceptron g: features -> 2 d^2 applied to every ADO block
+ * of a residual r (not a passage of the paper: the learned part of this
+ * library).  With nu_a = |r_a| the features of block a of right-hand side
+ * j are [Re r_a / nu_a, Im r_a / nu_a, n_a / n_max, m_a / m_max,
+ * Re c_a / cs, Im c_a / cs, Re z_j / cs, Im z_j / cs] (c_a the ADO's decay,
+ * z_j the shift of the system, cs = max |c_a|; a zero block has zero block
+ * features), padded with zeros to k1 = a multiple of 32, and the
+ * preconditioned block is z_a = r_a + nu_a (g_re + i g_im): the untrained
+ * (zero) network is the identity, the better plain map of the large
+ * fermionic models, and a zero residual block stays zero.  Layers:
+ * k1 -> hidden -> hidden -> o_pad (= 2 d^2 rounded up to 32) with ReLU; BF16
+ * operands, FP32 accumulation, FP32 master weights.  Parameters are laid
+ * out as [W1 (hidden x k1), b1, W2 (hidden x hidden), b2, W3 (o_pad x
+ * hidden), b3], row-major FP32.  Networks live on the device current at
+ * creation. */
 
 /* Seeded He-uniform initialisation (last layer scaled by 0.05). */
 heom_status heom_nn_create(int32_t d, int32_t hidden, uint64_t seed, heom_nn **out);
@@ -432,26 +436,31 @@ heom_status heom_nn_save(const heom_nn *nn, const char *path);
 heom_status heom_nn_load(const char *path, heom_nn **out);
 
 /* Training pairs from a residual r (FP64 [N][d][d], device) and the error
- * e = x* - x it leaves (FP64, device, or NULL for features only) of the
- * system heom_steady solves (border = 1) or of M (border = 0): writes the
- * BF16 features X [N][k1] and the FP32 targets T [N][o_pad] =
- * (e_a - jr_a) / nu_a (padding zero). */
+ * e = x* - x it leaves (FP64, device, or NULL for features only): writes
+ * the BF16 features X [N][k1], the FP32 targets T [N][o_pad] =
+ * (e_a - r_a) / nu_a (zero for a zero block and in the padding) and, when
+ * W_dev is not NULL, the FP32 row weights W [N] = nu_a^2 / mean_b nu_b^2,
+ * so that the weighted loss below measures the error of the correction
+ * nu_a g_a against e_a - r_a itself, relative to the pair set's mean.
+ * border is kept for the call's form and has no effect. */
 heom_status heom_nn_pairs(heom_hier *h, const heom_nn *nn, const void *r_dev, const void *e_dev, int32_t border,
-                          void *X_dev, void *T_dev, void *stream);
+                          void *X_dev, void *T_dev, void *W_dev, void *stream);
 /* O [rows][o_pad] FP32 = g(X) for BF16 features X [rows][k1]. */
 heom_status heom_nn_forward(const heom_nn *nn, const void *X_dev, int64_t rows, void *O_dev, void *stream);
-/* Gradients of sum (g(X) - T)^2 / (2 rows) in the parameter layout above
- * (host, n_params floats) and the loss (host, 1 float). */
-heom_status heom_nn_gradients(const heom_nn *nn, const void *X_dev, const void *T_dev, int64_t rows,
+/* Gradients of sum_rows w (g(X) - T)^2 / (2 rows) in the parameter layout
+ * above (host, n_params floats) and the loss (host, 1 float); W_dev: FP32
+ * row weights [rows], or NULL for all ones. */
+heom_status heom_nn_gradients(const heom_nn *nn, const void *X_dev, const void *T_dev, const void *W_dev, int64_t rows,
                               float *grads_host, float *loss_host, void *stream);
-/* Adam (beta 0.9 / 0.999, eps 1e-8) over shuffled mini-batches of `batch`
- * rows for `epochs` passes over the training set: all `rows` pairs, or a
- * fixed seeded subset of `subset` of them when 0 < subset < rows.
+/* Adam (beta 0.9 / 0.999, eps 1e-8) on the weighted loss above over
+ * shuffled mini-batches of `batch` rows for `epochs` passes over the
+ * training set: all `rows` pairs, or a fixed seeded subset of `subset` of
+ * them when 0 < subset < rows.  W_dev may be NULL (all ones).
  * loss_per_epoch (host, epochs floats, may be NULL) receives the mean
  * mini-batch loss.  Allocates its own scratch. */
-heom_status heom_nn_train(heom_nn *nn, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset,
-                          int32_t epochs, int32_t batch, double lr, uint64_t seed, float *loss_per_epoch,
-                          void *stream);
+heom_status heom_nn_train(heom_nn *nn, const void *X_dev, const void *T_dev, const void *W_dev, int64_t rows,
+                          int64_t subset, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                          float *loss_per_epoch, void *stream);
 
 /* Vector helpers for building training pairs on the device.
  * heom_steady_residual: r = e_0 - B x (B as in heom_apply_steady_operator;

@@ -1,7 +1,8 @@
 """Learned block preconditioner's network -- oracle (test infrastructure only).
 
 A multilayer perceptron X -> relu(X W1^T + b1) -> relu(. W2^T + b2) ->
-. W3^T + b3 with loss L = sum (O - T)^2 / (2 rows), written out with numpy:
+. W3^T + b3 with the row-weighted loss L = sum_rows w (O - T)^2 / (2 rows)
+(w = 1 when no weights are given), written out with numpy:
 
 * ``forward64`` / ``grads64``: FP64, the mathematical definition (checked
   against central finite differences in the tests);
@@ -60,15 +61,19 @@ def forward64(layers, X):
     return A2 @ W3.T + b3, (Z1, A1, Z2, A2)
 
 
-def loss64(layers, X, T):
+def _w(W, rows):
+    return np.ones(rows) if W is None else np.asarray(W, dtype=np.float64)
+
+
+def loss64(layers, X, T, W=None):
     O, _ = forward64(layers, X)
-    return 0.5 * np.sum((O - T) ** 2) / X.shape[0]
+    return 0.5 * np.sum(_w(W, X.shape[0])[:, None] * (O - T) ** 2) / X.shape[0]
 
 
-def grads64(layers, X, T):
+def grads64(layers, X, T, W=None):
     (W1, b1), (W2, b2), (W3, b3) = layers
     O, (Z1, A1, Z2, A2) = forward64(layers, X)
-    dO = (O - T) / X.shape[0]
+    dO = _w(W, X.shape[0])[:, None] * (O - T) / X.shape[0]
     gW3, gb3 = dO.T @ A2, dO.sum(0)
     dZ2 = (dO @ W3) * (Z2 > 0)
     gW2, gb2 = dZ2.T @ A1, dZ2.sum(0)
@@ -90,11 +95,12 @@ def forward_bf16(layers, X):
     return O, (Z1, A1, Z2, A2)
 
 
-def grads_bf16(layers, X, T):
+def grads_bf16(layers, X, T, W=None):
     Wb = [bf16(W) for W, _ in layers]
     O, (Z1, A1, Z2, A2) = forward_bf16(layers, X)
     rows = X.shape[0]
-    dO = bf16((O - T.astype(np.float32)) * np.float32(1.0 / rows))
+    w32 = np.float32(_w(W, rows))[:, None]
+    dO = bf16((O - T.astype(np.float32)) * np.float32(1.0 / rows) * w32)
     f64 = lambda a: a.astype(np.float64)
     gW3 = f64(dO).T @ f64(A2)
     gb3 = f64(dO).sum(0)
@@ -104,30 +110,56 @@ def grads_bf16(layers, X, T):
     dZ1 = bf16(np.where(Z1 > 0, (f64(dZ2) @ f64(Wb[1])).astype(np.float32), 0))
     gW1 = f64(dZ1).T @ f64(X)
     gb1 = f64(dZ1).sum(0)
-    loss = 0.5 * float(np.sum((f64(O) - f64(T)) ** 2)) / rows
+    loss = 0.5 * float(np.sum(f64(w32) * (f64(O) - f64(T)) ** 2)) / rows
     return [(gW1, gb1), (gW2, gb2), (gW3, gb3)], loss
 
 
 # ----------------------------------------------------------------- features
-def features(r_blocks, diag_blocks, level_n, level_m, decay, n_max, m_max, k1, border=False):
-    """Features of every block of r (shape [N][d][d], complex): Jacobi
-    scaling jr = r / diag (diagonal of the system; the bordered element and
-    exact zeros count as 1), nu = |jr_a|, then [Re jr/nu, Im jr/nu, n/n_max,
-    m/m_max, Re c/cs, Im c/cs] padded to k1.  Returns (X float64, nu, jr)."""
-    diag = np.array(diag_blocks, dtype=np.complex128, copy=True)
-    if border:
-        diag[0, 0, 0] = 1.0
-    diag[diag == 0] = 1.0
-    jr = r_blocks / diag
-    N, d, _ = jr.shape
-    nu = np.sqrt(np.sum(np.abs(jr) ** 2, axis=(1, 2)))
-    nu[~(nu > 1e-300)] = 1.0
+def features(r_blocks, level_n, level_m, decay, n_max, m_max, k1, shift=0.0):
+    """Features of every block of the residual r (shape [N][d][d], complex):
+    nu_a = |r_a|_2, then [Re r_a/nu_a, Im r_a/nu_a, n_a/n_max, m_a/m_max,
+    Re c_a/cs, Im c_a/cs, Re z/cs, Im z/cs] padded to k1, with cs = max |c_a|
+    and z the shift of the system; a zero block has zero block features.
+    Returns (X float64, nu)."""
+    r = np.asarray(r_blocks, dtype=np.complex128)
+    N, d, _ = r.shape
+    nu = np.sqrt(np.sum(np.abs(r) ** 2, axis=(1, 2)))
+    inv = np.where(nu > 1e-300, 1.0 / np.where(nu > 1e-300, nu, 1.0), 0.0)
     cs = np.max(np.abs(decay))
     X = np.zeros((N, k1))
-    X[:, : d * d] = (jr.real / nu[:, None, None]).reshape(N, -1)
-    X[:, d * d: 2 * d * d] = (jr.imag / nu[:, None, None]).reshape(N, -1)
+    X[:, : d * d] = (r.real * inv[:, None, None]).reshape(N, -1)
+    X[:, d * d: 2 * d * d] = (r.imag * inv[:, None, None]).reshape(N, -1)
     X[:, 2 * d * d] = level_n / max(n_max, 1)
     X[:, 2 * d * d + 1] = level_m / max(m_max, 1)
     X[:, 2 * d * d + 2] = decay.real / cs
     X[:, 2 * d * d + 3] = decay.imag / cs
-    return X, nu, jr
+    X[:, 2 * d * d + 4] = complex(shift).real / cs
+    X[:, 2 * d * d + 5] = complex(shift).imag / cs
+    return X, nu
+
+
+def targets(r_blocks, e_blocks):
+    """Training targets (e_a - r_a)/nu_a (zero for a zero block) and row
+    weights nu_a^2 / mean_b nu_b^2 of residual blocks r and error blocks e;
+    targets as [Re, Im] rows of length 2 d^2."""
+    r = np.asarray(r_blocks, dtype=np.complex128)
+    e = np.asarray(e_blocks, dtype=np.complex128)
+    N, d, _ = r.shape
+    nu = np.sqrt(np.sum(np.abs(r) ** 2, axis=(1, 2)))
+    inv = np.where(nu > 1e-300, 1.0 / np.where(nu > 1e-300, nu, 1.0), 0.0)
+    t = (e - r) * inv[:, None, None]
+    T = np.concatenate([t.real.reshape(N, -1), t.imag.reshape(N, -1)], axis=1)
+    m = np.mean(nu ** 2)
+    W = nu ** 2 / m if m > 0 else np.zeros(N)
+    return T, W
+
+
+def precondition(r_blocks, g_rows):
+    """The preconditioned blocks z_a = r_a + nu_a (g_re + i g_im) for network
+    outputs g (rows of length >= 2 d^2)."""
+    r = np.asarray(r_blocks, dtype=np.complex128)
+    N, d, _ = r.shape
+    nu = np.sqrt(np.sum(np.abs(r) ** 2, axis=(1, 2)))
+    g = np.asarray(g_rows, dtype=np.float64)
+    corr = (g[:, : d * d] + 1j * g[:, d * d: 2 * d * d]).reshape(N, d, d)
+    return r + nu[:, None, None] * corr

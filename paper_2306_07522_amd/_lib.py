@@ -96,10 +96,10 @@ SIGNATURES = {
     "heom_nn_set_params": (heom_status, [vp, C.POINTER(C.c_float)]),
     "heom_nn_save": (heom_status, [vp, C.c_char_p]),
     "heom_nn_load": (heom_status, [C.c_char_p, C.POINTER(vp)]),
-    "heom_nn_pairs": (heom_status, [vp, vp, vp, vp, C.c_int32, vp, vp, vp]),
+    "heom_nn_pairs": (heom_status, [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp]),
     "heom_nn_forward": (heom_status, [vp, vp, C.c_int64, vp, vp]),
-    "heom_nn_gradients": (heom_status, [vp, vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float), vp]),
-    "heom_nn_train": (heom_status, [vp, vp, vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_double,
+    "heom_nn_gradients": (heom_status, [vp, vp, vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float), vp]),
+    "heom_nn_train": (heom_status, [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                     C.c_uint64, C.POINTER(C.c_float), vp]),
     "heom_steady_residual": (heom_status, [vp, vp, vp, vp]),
     "heom_vector_axpby": (heom_status, [C.c_int32, vp, C.c_double, vp, C.c_double, C.c_int64, vp]),

@@ -412,16 +412,18 @@ def steady_state(h, x=None, stream=None, allow_not_converged=False, **opts):
     return x, report_dict(rep)
 
 
-def collect_pairs(h, net, snapshots=(10, 30, 60), x_star=None, restart=60, tol=1e-11, stream=None):
-    """Training pairs from plain (Jacobi) GMRES runs on the stationary-state
-    system: the converged x*, then iterates x_k after k iterations; for each
-    snapshot the residual r = e_0 - B x_k and the error e = x* - x_k give
-    one pair per ADO block.  Returns lists of (X, T) device tensors."""
+def collect_pairs(h, net, snapshots=(10, 30, 60), x_star=None, restart=60, tol=1e-11, precond="none", stream=None):
+    """Training pairs from plain GMRES runs (no preconditioner by default) on
+    the stationary-state system: the converged x*, then iterates x_k after k
+    iterations; for each snapshot the residual r = e_0 - B x_k and the error
+    e = x* - x_k give one pair per ADO block.  Returns a list of (X, T, W)
+    device tensors (W: row weights, see heom_nn_pairs)."""
     if x_star is None:
-        x_star, _ = steady_state(h, tol=tol, restart=restart, max_iter=20000, stream=stream)
+        x_star, _ = steady_state(h, tol=tol, restart=restart, max_iter=20000, precond=precond, stream=stream)
     out = []
     for k in snapshots:
-        xk, _ = steady_state(h, restart=restart, max_iter=int(k), allow_not_converged=True, stream=stream)
+        xk, _ = steady_state(h, restart=restart, max_iter=int(k), precond=precond, allow_not_converged=True,
+                             stream=stream)
         r = steady_residual(h, xk, stream=stream)
         e = axpby(x_star, 1.0, xk, -1.0, stream=stream)   # e = x* - x_k (in place of x_k)
         out.append(net.pairs(h, r, e, border=1, stream=stream))
@@ -502,13 +504,16 @@ class Network:
         L.check(self._lib.heom_nn_save(self._h, str(path).encode()))
 
     def pairs(self, h, r, e=None, border=1, stream=None):
-        """(X bf16-as-int16 [N][k1], T fp32 [N][o_pad]) device tensors."""
+        """(X bf16-as-int16 [N][k1], T fp32 [N][o_pad], W fp32 [N]) device
+        tensors (T and W are None without e)."""
         import torch
         X = torch.empty((h.N, self.k1), dtype=torch.int16, device="cuda")
         T = torch.empty((h.N, self.o_pad), dtype=torch.float32, device="cuda") if e is not None else None
+        W = torch.empty((h.N,), dtype=torch.float32, device="cuda") if e is not None else None
         L.check(self._lib.heom_nn_pairs(h.handle, self._h, _devptr(r), _devptr(e) if e is not None else None, border,
-                                        _devptr(X), _devptr(T) if T is not None else None, _stream_ptr(stream)))
-        return X, T
+                                        _devptr(X), _devptr(T) if T is not None else None,
+                                        _devptr(W) if W is not None else None, _stream_ptr(stream)))
+        return X, T, W
 
     def forward(self, X, stream=None):
         import torch
@@ -516,17 +521,19 @@ class Network:
         L.check(self._lib.heom_nn_forward(self._h, _devptr(X), X.shape[0], _devptr(O), _stream_ptr(stream)))
         return O
 
-    def gradients(self, X, T, stream=None):
+    def gradients(self, X, T, W=None, stream=None):
         g = np.zeros(self.n_params, dtype=np.float32)
         loss = C.c_float()
-        L.check(self._lib.heom_nn_gradients(self._h, _devptr(X), _devptr(T), X.shape[0],
+        L.check(self._lib.heom_nn_gradients(self._h, _devptr(X), _devptr(T), _devptr(W) if W is not None else None,
+                                            X.shape[0],
                                             g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
                                             _stream_ptr(stream)))
         return g, loss.value
 
-    def train(self, X, T, epochs=10, batch=4096, lr=1e-3, seed=0, subset=0, stream=None):
+    def train(self, X, T, W=None, epochs=10, batch=4096, lr=1e-3, seed=0, subset=0, stream=None):
         losses = np.zeros(max(epochs, 1), dtype=np.float32)
-        L.check(self._lib.heom_nn_train(self._h, _devptr(X), _devptr(T), X.shape[0], int(subset), epochs, batch,
+        L.check(self._lib.heom_nn_train(self._h, _devptr(X), _devptr(T), _devptr(W) if W is not None else None,
+                                        X.shape[0], int(subset), epochs, batch,
                                         float(lr),
                                         int(seed), losses.ctypes.data_as(C.POINTER(C.c_float)), _stream_ptr(stream)))
         return losses[:epochs]

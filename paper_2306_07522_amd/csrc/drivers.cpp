@@ -546,7 +546,22 @@ static heom_status heom_spectrum_body(heom_hier *even, heom_hier *odd, const voi
     lp.shifts64 = sh64;
     lp.shifts32 = sh32;
     arena.used = mark;
+    const double res_before = r ? r->true_residual : 0.0;
+    const int32_t status_before = r ? r->status : 0;
     heom_status st = solve_system(lp, *o, b, x, false, r, arena, s);
+    if ((st == HEOM_ERR_NOT_CONVERGED || st == HEOM_ERR_NAN) && o->precond == HEOM_PREC_NN && o->fallback) {
+      // Jacobi GMRES solves this chunk of frequencies again from zero; the
+      // report keeps accumulating iterations, applies and seconds
+      heom_solver_opts o2 = *o;
+      o2.precond = HEOM_PREC_JACOBI;
+      if (r) {
+        r->fell_back = 1;
+        r->true_residual = res_before;
+        r->status = status_before;
+      }
+      arena.used = mark;
+      st = solve_system(lp, o2, b, x, false, r, arena, s);
+    }
     if (st != HEOM_OK && st != HEOM_ERR_NOT_CONVERGED) return st;
     if (st != HEOM_OK) worst = st;
     HEOM_TRY(trace_readout<double>(x, opsd, d, R, colr, -1.0 / kPi, outd, s));

@@ -1,7 +1,7 @@
-// Learned block preconditioner: a small MLP applied to every ADO block of a
-// Jacobi-scaled residual, used as the variable right preconditioner of
-// FGMRES.  Weights are FP32 masters with BF16 copies; every matrix product
-// runs on BF16 MFMA with FP32 accumulation.
+// Learned block preconditioner: a small MLP applied to every ADO block of the
+// residual, used as the variable right preconditioner of FGMRES.  Weights
+// are FP32 masters with BF16 copies; every matrix product runs on BF16 MFMA
+// with FP32 accumulation.
 #pragma once
 
 #include "internal.h"
@@ -9,7 +9,7 @@
 
 struct heom_nn {
   int d = 0, hidden = 0;
-  int f_in = 0, k1 = 0;      // features 2 d^2 + 4, padded to a multiple of 32
+  int f_in = 0, k1 = 0;      // features 2 d^2 + 6, padded to a multiple of 32
   int f_out = 0, o_pad = 0;  // outputs 2 d^2, padded to a multiple of 32
   int device = -1;
   // layer l: W [rows_l x cols_l] row-major, b [rows_l]
@@ -26,7 +26,7 @@ namespace heom {
 size_t nn_workspace_bytes(const Hier &h, int R, size_t elem_bytes);
 
 // One use of a trained network as the variable right preconditioner:
-// z = J r + |J r|_a * g(features_a) blockwise, J the Jacobi preconditioner.
+// z = r + |r_a| * g(features_a) blockwise.
 struct NnApply {
   const heom_nn *net = nullptr;
   const Hier *h = nullptr;
@@ -35,7 +35,6 @@ struct NnApply {
   int border = 0;
   bool fell_back = false;
   double cscale = 1.0;
-  void *jr = nullptr;          // T vector [n][R]
   uint16_t *X = nullptr, *H1 = nullptr, *H2 = nullptr;
   float *O = nullptr, *nu = nullptr;
   heom_status init(const heom_nn *net, const Hier &h, int R, const double2 *shifts, int border, WsArena &ws,

@@ -1,15 +1,21 @@
-// Learned block preconditioner: MLP (2 d^2 + 4 -> hidden -> hidden -> 2 d^2)
-// on every ADO block of the Jacobi-scaled residual.  Inference and training
-// run on hand-written BF16 MFMA GEMMs with FP32 accumulation; the FP32
-// master weights are updated with Adam.
+// Learned block preconditioner: MLP (2 d^2 + 6 -> hidden -> hidden -> 2 d^2)
+// on every ADO block of the residual.  Inference and training run on
+// hand-written BF16 MFMA GEMMs with FP32 accumulation; the FP32 master
+// weights are updated with Adam.
 //
-// Features of block (a, r): with jr = J r (J the Jacobi preconditioner of the
-// system being solved) and nu = |jr_a|_2,
-//   [Re jr_a / nu, Im jr_a / nu, n_a / L_f, m_a / L_b, Re c_a / cs, Im c_a / cs]
-// where c_a is the ADO's decay and cs = max_a |c_a|.  The preconditioned
-// block is z_a = jr_a + nu * (g_re + i g_im), so a zero network is Jacobi.
-// Training targets for a pair (residual block r_a, error block e_a) are
-// (e_a - jr_a) / nu, loss = sum (g - target)^2 / (2 rows).
+// Features of block (a, r) of the residual r, with nu = |r_a|_2:
+//   [Re r_a / nu, Im r_a / nu, n_a / L_f, m_a / L_b, Re c_a / cs, Im c_a / cs,
+//    Re z_r / cs, Im z_r / cs]
+// where c_a is the ADO's decay, z_r the shift of right-hand side r and
+// cs = max_a |c_a| (a zero block has zero block features).  The
+// preconditioned block is z_a = r_a + nu * (g_re + i g_im): an untrained
+// (zero) network is the identity, and a block with zero residual stays zero.
+// Training pairs (residual block r_a, error block e_a) give the targets
+// (e_a - r_a) / nu and the weights w_a = nu^2 / mean(nu^2) over the pair set's
+// blocks, loss = sum_a w_a |g_a - target_a|^2 / (2 rows): the squared error of
+// the correction itself, relative to the set's mean, so that blocks with a
+// tiny residual (whose scaled targets are large and unpredictable) do not
+// dominate.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -145,17 +151,19 @@ __global__ void f32_to_bf16_kernel(const float *__restrict__ x, uint16_t *__rest
     y[i] = f2bf(x[i]);
 }
 
-// dO = bf16((O - T) / rows); loss_out[0] (+)= sum (O - T)^2 / (2 rows) (one block)
-__global__ void loss_grad_kernel(const float *__restrict__ O, const float *__restrict__ T, int64_t rows, int cols,
-                                 uint16_t *__restrict__ dO, float *__restrict__ loss_out) {
+// dO = bf16((O - T) / rows * w_row); loss_out[0] = sum w_row (O - T)^2 / (2 rows)
+// (one block; W = NULL weighs every row 1)
+__global__ void loss_grad_kernel(const float *__restrict__ O, const float *__restrict__ T, const float *__restrict__ W,
+                                 int64_t rows, int cols, uint16_t *__restrict__ dO, float *__restrict__ loss_out) {
   __shared__ float red[256];
   float acc = 0.f;
   const float inv = 1.0f / (float)rows;
   const int64_t n = rows * cols;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     const float dlt = O[i] - T[i];
-    acc += dlt * dlt;
-    dO[i] = f2bf(dlt * inv);
+    const float w = W ? W[i / cols] : 1.0f;
+    acc += w * dlt * dlt;
+    dO[i] = f2bf(dlt * inv * w);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -190,24 +198,40 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
   }
 }
 
-__global__ void gather_rows_kernel(const uint16_t *__restrict__ X, const float *__restrict__ T, const int64_t *__restrict__ idx,
-                                   int64_t nb, int k1, int o_pad, uint16_t *__restrict__ Xb, float *__restrict__ Tb) {
+__global__ void gather_rows_kernel(const uint16_t *__restrict__ X, const float *__restrict__ T, const float *__restrict__ W,
+                                   const int64_t *__restrict__ idx, int64_t nb, int k1, int o_pad, uint16_t *__restrict__ Xb,
+                                   float *__restrict__ Tb, float *__restrict__ Wb) {
   const int64_t r = blockIdx.x;
   if (r >= nb) return;
   const int64_t src = idx[r];
   for (int c = threadIdx.x; c < k1; c += blockDim.x) Xb[r * k1 + c] = X[src * k1 + c];
   for (int c = threadIdx.x; c < o_pad; c += blockDim.x) Tb[r * o_pad + c] = T[src * o_pad + c];
+  if (W && threadIdx.x == 0) Wb[r] = W[src];
+}
+
+// w_row = nu_row^2 / mean over rows of nu^2 (one block)
+__global__ void __launch_bounds__(1024) weights_kernel(const float *__restrict__ nu, int64_t rows, float *__restrict__ w) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) acc += (double)nu[i] * nu[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 512; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)(rows > 0 ? rows : 1);
+  const double inv = mean > 0 ? 1.0 / mean : 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) w[i] = (float)((double)nu[i] * nu[i] * inv);
 }
 
 // Features (and optionally training targets) of every block (a, r) of the
 // [N][d][d][R] vector `in`: one 256-thread block per row a * R + r.
 template <typename T>
 __global__ void __launch_bounds__(256) features_kernel(const typename Cplx<T>::t *__restrict__ in, int d, int64_t N, int R,
-                                                       const double2 *__restrict__ decay, const double2 *__restrict__ hdiag,
-                                                       const int2 *__restrict__ lev, const double2 *__restrict__ shifts,
-                                                       int border, double cscale, int Lf, int Lb, int k1, int o_pad,
-                                                       uint16_t *__restrict__ X, float *__restrict__ nu,
-                                                       typename Cplx<T>::t *__restrict__ jr_out,
+                                                       const double2 *__restrict__ decay, const int2 *__restrict__ lev,
+                                                       const double2 *__restrict__ shifts, double cscale, int Lf, int Lb,
+                                                       int k1, int o_pad, uint16_t *__restrict__ X, float *__restrict__ nu,
                                                        const double2 *__restrict__ err, float *__restrict__ target) {
   using T2 = typename Cplx<T>::t;
   __shared__ double red[256];
@@ -218,19 +242,9 @@ __global__ void __launch_bounds__(256) features_kernel(const typename Cplx<T>::t
   const double2 c = decay[a];
   const double2 zz = shifts ? shifts[r] : make_double2(0.0, 0.0);
   double acc = 0.0;
-  // pass 1: Jacobi-scaled block and its norm
   for (int ij = threadIdx.x; ij < d2; ij += blockDim.x) {
-    const int i = ij / d, j = ij % d;
-    const double2 hi = hdiag[i], hj = hdiag[j];
-    double2 dg = make_double2(-(c.x - zz.x) + (hi.y - hj.y), -(c.y - zz.y) - (hi.x - hj.x));
-    if (border && a == 0 && ij == 0) dg = make_double2(1.0, 0.0);
-    if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
-    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
     const T2 v = in[(a * d2 + ij) * R + r];
-    const double jx = ((double)v.x * dg.x + (double)v.y * dg.y) * inv;
-    const double jy = ((double)v.y * dg.x - (double)v.x * dg.y) * inv;
-    if (jr_out) jr_out[(a * d2 + ij) * R + r] = T2{(T)jx, (T)jy};
-    acc += jx * jx + jy * jy;
+    acc += (double)v.x * v.x + (double)v.y * v.y;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -238,27 +252,17 @@ __global__ void __launch_bounds__(256) features_kernel(const typename Cplx<T>::t
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  double n2 = sqrt(red[0]);
-  if (!(n2 > 1e-300)) n2 = 1.0;
+  const double n2 = sqrt(red[0]);
   if (threadIdx.x == 0) nu[row] = (float)n2;
-  const double inv_nu = 1.0 / n2;
-  // pass 2: features (recomputing jr keeps register use flat)
+  const double inv_nu = n2 > 1e-300 ? 1.0 / n2 : 0.0;  // a zero block: zero features and targets
   for (int ij = threadIdx.x; ij < d2; ij += blockDim.x) {
-    const int i = ij / d, j = ij % d;
-    const double2 hi = hdiag[i], hj = hdiag[j];
-    double2 dg = make_double2(-(c.x - zz.x) + (hi.y - hj.y), -(c.y - zz.y) - (hi.x - hj.x));
-    if (border && a == 0 && ij == 0) dg = make_double2(1.0, 0.0);
-    if (dg.x * dg.x + dg.y * dg.y == 0.0) dg = make_double2(1.0, 0.0);
-    const double inv = 1.0 / (dg.x * dg.x + dg.y * dg.y);
     const T2 v = in[(a * d2 + ij) * R + r];
-    const double jx = ((double)v.x * dg.x + (double)v.y * dg.y) * inv;
-    const double jy = ((double)v.y * dg.x - (double)v.x * dg.y) * inv;
-    X[row * k1 + ij] = f2bf((float)(jx * inv_nu));
-    X[row * k1 + d2 + ij] = f2bf((float)(jy * inv_nu));
+    X[row * k1 + ij] = f2bf((float)((double)v.x * inv_nu));
+    X[row * k1 + d2 + ij] = f2bf((float)((double)v.y * inv_nu));
     if (err) {
       const double2 e = err[(a * d2 + ij) * R + r];
-      target[row * o_pad + ij] = (float)((e.x - jx) * inv_nu);
-      target[row * o_pad + d2 + ij] = (float)((e.y - jy) * inv_nu);
+      target[row * o_pad + ij] = (float)((e.x - (double)v.x) * inv_nu);
+      target[row * o_pad + d2 + ij] = (float)((e.y - (double)v.y) * inv_nu);
     }
   }
   for (int t = 2 * d2 + threadIdx.x; t < k1; t += blockDim.x) {
@@ -267,17 +271,19 @@ __global__ void __launch_bounds__(256) features_kernel(const typename Cplx<T>::t
     else if (t == 2 * d2 + 1) f = (float)lev[a].x / (float)(Lb > 0 ? Lb : 1);
     else if (t == 2 * d2 + 2) f = (float)(c.x / cscale);
     else if (t == 2 * d2 + 3) f = (float)(c.y / cscale);
+    else if (t == 2 * d2 + 4) f = (float)(zz.x / cscale);
+    else if (t == 2 * d2 + 5) f = (float)(zz.y / cscale);
     X[row * k1 + t] = f2bf(f);
   }
   if (err)
     for (int t = 2 * d2 + threadIdx.x; t < o_pad; t += blockDim.x) target[row * o_pad + t] = 0.f;
 }
 
-// z = jr + nu * (g_re + i g_im), blockwise
+// z = r + nu * (g_re + i g_im), blockwise (out may alias r)
 template <typename T>
-__global__ void combine_kernel(const typename Cplx<T>::t *__restrict__ jr, const float *__restrict__ O,
+__global__ void combine_kernel(const typename Cplx<T>::t *jr, const float *__restrict__ O,
                                const float *__restrict__ nu, int d, int64_t N, int R, int o_pad,
-                               typename Cplx<T>::t *__restrict__ out) {
+                               typename Cplx<T>::t *out) {
   using T2 = typename Cplx<T>::t;
   const int d2 = d * d;
   const int64_t total = N * d2 * R;
@@ -322,11 +328,11 @@ struct GradBuffers {
   float *dA;  // unused placeholder
 };
 
-// backward of loss sum (O - T)^2 / (2 rows): grads into g.gW / g.gb
-static heom_status backward(const heom_nn &nn, const uint16_t *X, const float *T, int64_t rows, FwdBuffers &f,
-                            GradBuffers &g, float *loss, hipStream_t s) {
+// backward of loss sum w (O - T)^2 / (2 rows): grads into g.gW / g.gb
+static heom_status backward(const heom_nn &nn, const uint16_t *X, const float *T, const float *W, int64_t rows,
+                            FwdBuffers &f, GradBuffers &g, float *loss, hipStream_t s) {
   const int H = nn.hidden, Op = nn.o_pad;
-  hipLaunchKernelGGL(loss_grad_kernel, dim3(1), dim3(256), 0, s, f.O, T, rows, Op, g.dO, loss);
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(1), dim3(256), 0, s, f.O, T, W, rows, Op, g.dO, loss);
   HEOM_HIP_CHECK(hipGetLastError());
   // layer 3: dW3 = dO^T A2, db3 = colsum dO, dZ2 = (dO W3) * relu'(Z2)
   HEOM_TRY(gemm_bf16(true, false, EPI_F32, g.dO, Op, f.A2, H, Op, H, (int)rows, g.gW[2], nullptr, H, nullptr, nullptr, 0, s));
@@ -389,10 +395,11 @@ static heom_status alloc_grad(const heom_nn &nn, int64_t rows, GradBuffers &g, D
 // ------------------------------------------------------------------ preconditioner use
 size_t nn_workspace_bytes(const Hier &h, int R, size_t elem_bytes) {
   const int d2 = h.d * h.d;
-  const int k1 = ((2 * d2 + 4) + 31) / 32 * 32, o_pad = (2 * d2 + 31) / 32 * 32;
+  const int k1 = ((2 * d2 + 6) + 31) / 32 * 32, o_pad = (2 * d2 + 31) / 32 * 32;
   const size_t rows = (size_t)h.N * R;
   const size_t H = 256;  // the library's networks use hidden <= 256
-  return rows * d2 * elem_bytes + rows * (k1 * 2 + 2 * H * 2 + o_pad * 4 + 4) + 8 * 256;
+  (void)elem_bytes;
+  return rows * (k1 * 2 + 2 * H * 2 + o_pad * 4 + 4) + 8 * 256;
 }
 
 heom_status NnApply::init(const heom_nn *n, const Hier &hh, int R_, const double2 *sh, int bd, WsArena &ws,
@@ -409,13 +416,13 @@ heom_status NnApply::init(const heom_nn *n, const Hier &hh, int R_, const double
   HEOM_HIP_CHECK(hipGetDevice(&dev));
   if (dev != n->device) return fail(HEOM_ERR_ARG, "network lives on another device");
   const size_t rows = (size_t)hh.N * R;
-  jr = ws.take(rows * hh.d * hh.d * elem_bytes);
+  (void)elem_bytes;
   X = (uint16_t *)ws.take(rows * n->k1 * 2);
   H1 = (uint16_t *)ws.take(rows * n->hidden * 2);
   H2 = (uint16_t *)ws.take(rows * n->hidden * 2);
   O = (float *)ws.take(rows * n->o_pad * 4);
   nu = (float *)ws.take(rows * 4);
-  if (!jr || !X || !H1 || !H2 || !O || !nu) return fail(HEOM_ERR_ARG, "workspace too small for the network");
+  if (!X || !H1 || !H2 || !O || !nu) return fail(HEOM_ERR_ARG, "workspace too small for the network");
   cscale = 1e-300;
   for (const cd &c : hh.decay) cscale = std::max(cscale, std::abs(c));
   return HEOM_OK;
@@ -427,8 +434,8 @@ heom_status NnApply::apply(const void *in, void *out, hipStream_t s) {
   const int64_t rows = h->N * R;
   if (rows > 0x7fffffffLL) return fail(HEOM_ERR_UNSUPPORTED, "too many blocks for the network");
   hipLaunchKernelGGL(features_kernel<T>, dim3((unsigned)rows), dim3(256), 0, s, (const typename Cplx<T>::t *)in, h->d,
-                     h->N, R, h->dev.decay64, h->dev.hdiag, h->dev.lev, shifts, border, cscale, h->Lf, h->Lb, n.k1,
-                     n.o_pad, X, nu, (typename Cplx<T>::t *)jr, nullptr, nullptr);
+                     h->N, R, h->dev.decay64, h->dev.lev, shifts, cscale, h->Lf, h->Lb, n.k1, n.o_pad, X, nu,
+                     (const double2 *)nullptr, (float *)nullptr);
   HEOM_HIP_CHECK(hipGetLastError());
   FwdBuffers f;
   f.A1 = H1;
@@ -436,7 +443,7 @@ heom_status NnApply::apply(const void *in, void *out, hipStream_t s) {
   f.O = O;
   HEOM_TRY(forward(n, X, rows, f, s));
   hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_for(rows * h->d * h->d)), dim3(256), 0, s,
-                     (const typename Cplx<T>::t *)jr, O, nu, h->d, h->N, R, n.o_pad, (typename Cplx<T>::t *)out);
+                     (const typename Cplx<T>::t *)in, O, nu, h->d, h->N, R, n.o_pad, (typename Cplx<T>::t *)out);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -481,7 +488,7 @@ static heom_status heom_nn_create_body(int32_t d, int32_t hidden, uint64_t seed,
   auto *n = new heom_nn;
   n->d = d;
   n->hidden = hidden;
-  n->f_in = 2 * d * d + 4;
+  n->f_in = 2 * d * d + 6;
   n->k1 = (n->f_in + 31) / 32 * 32;
   n->f_out = 2 * d * d;
   n->o_pad = (n->f_out + 31) / 32 * 32;
@@ -492,7 +499,7 @@ static heom_status heom_nn_create_body(int32_t d, int32_t hidden, uint64_t seed,
   if (hipGetDevice(&dev) != hipSuccess) { delete n; return fail(HEOM_ERR_HIP, "hipGetDevice failed"); }
   n->device = dev;
   // He-uniform weights (fan-in of the real inputs); the last layer starts
-  // small so that the untrained network is close to plain Jacobi.
+  // small so that the untrained network is close to the identity.
   uint64_t st = seed;
   std::vector<float> host;
   for (int l = 0; l < 3; ++l) {
@@ -620,8 +627,9 @@ heom_status heom_nn_load(const char *path, heom_nn **out) {
 }
 
 static heom_status heom_nn_pairs_body(heom_hier *hw, const heom_nn *n, const void *r_dev, const void *e_dev, int32_t border,
-                          void *X_dev, void *T_dev, void *stream) {
+                                      void *X_dev, void *T_dev, void *W_dev, void *stream) {
   if (!hw || !n || !r_dev || !X_dev || (e_dev && !T_dev)) return fail(HEOM_ERR_ARG, "nn_pairs: NULL argument");
+  (void)border;
   Hier &h = *hw->impl;
   if (n->d != h.d) return fail(HEOM_ERR_ARG, "nn_pairs: network built for another d");
   HEOM_TRY(ensure_device(h));
@@ -632,16 +640,20 @@ static heom_status heom_nn_pairs_body(heom_hier *hw, const heom_nn *n, const voi
   double cs = 1e-300;
   for (const cd &c : h.decay) cs = std::max(cs, std::abs(c));
   hipLaunchKernelGGL(features_kernel<double>, dim3((unsigned)h.N), dim3(256), 0, s, (const double2 *)r_dev, h.d, h.N, 1,
-                     h.dev.decay64, h.dev.hdiag, h.dev.lev, nullptr, border, cs, h.Lf, h.Lb, n->k1, n->o_pad,
-                     (uint16_t *)X_dev, nu, (double2 *)nullptr, (const double2 *)e_dev, (float *)T_dev);
+                     h.dev.decay64, h.dev.lev, (const double2 *)nullptr, cs, h.Lf, h.Lb, n->k1, n->o_pad,
+                     (uint16_t *)X_dev, nu, (const double2 *)e_dev, (float *)T_dev);
   HEOM_HIP_CHECK(hipGetLastError());
+  if (W_dev) {
+    hipLaunchKernelGGL(weights_kernel, dim3(1), dim3(1024), 0, s, nu, (int64_t)h.N, (float *)W_dev);
+    HEOM_HIP_CHECK(hipGetLastError());
+  }
   HEOM_HIP_CHECK(hipStreamSynchronize(s));
   return HEOM_OK;
 }
 
 heom_status heom_nn_pairs(heom_hier *hw, const heom_nn *n, const void *r_dev, const void *e_dev, int32_t border,
-                          void *X_dev, void *T_dev, void *stream) {
-  return guarded([&] { return heom_nn_pairs_body(hw, n, r_dev, e_dev, border, X_dev, T_dev, stream); });
+                          void *X_dev, void *T_dev, void *W_dev, void *stream) {
+  return guarded([&] { return heom_nn_pairs_body(hw, n, r_dev, e_dev, border, X_dev, T_dev, W_dev, stream); });
 }
 
 static heom_status heom_nn_forward_body(const heom_nn *n, const void *X_dev, int64_t rows, void *O_dev, void *stream) {
@@ -662,8 +674,8 @@ heom_status heom_nn_forward(const heom_nn *n, const void *X_dev, int64_t rows, v
   return guarded([&] { return heom_nn_forward_body(n, X_dev, rows, O_dev, stream); });
 }
 
-static heom_status heom_nn_gradients_body(const heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, float *grads_host,
-                              float *loss_host, void *stream) {
+static heom_status heom_nn_gradients_body(const heom_nn *n, const void *X_dev, const void *T_dev, const void *W_dev,
+                                          int64_t rows, float *grads_host, float *loss_host, void *stream) {
   if (!n || !X_dev || !T_dev || rows <= 0 || rows > 0x7fffffffLL) return fail(HEOM_ERR_ARG, "nn_gradients: bad arguments");
   hipStream_t s = (hipStream_t)stream;
   DevScratch ds;
@@ -674,7 +686,7 @@ static heom_status heom_nn_gradients_body(const heom_nn *n, const void *X_dev, c
   HEOM_TRY(alloc_grad(*n, rows, g, ds));
   HEOM_TRY(ds.get(&loss, 16));
   HEOM_TRY(forward(*n, (const uint16_t *)X_dev, rows, f, s));
-  HEOM_TRY(backward(*n, (const uint16_t *)X_dev, (const float *)T_dev, rows, f, g, loss, s));
+  HEOM_TRY(backward(*n, (const uint16_t *)X_dev, (const float *)T_dev, (const float *)W_dev, rows, f, g, loss, s));
   HEOM_HIP_CHECK(hipStreamSynchronize(s));
   if (grads_host) {
     size_t off = 0;
@@ -690,13 +702,14 @@ static heom_status heom_nn_gradients_body(const heom_nn *n, const void *X_dev, c
   return HEOM_OK;
 }
 
-heom_status heom_nn_gradients(const heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, float *grads_host,
-                              float *loss_host, void *stream) {
-  return guarded([&] { return heom_nn_gradients_body(n, X_dev, T_dev, rows, grads_host, loss_host, stream); });
+heom_status heom_nn_gradients(const heom_nn *n, const void *X_dev, const void *T_dev, const void *W_dev, int64_t rows,
+                              float *grads_host, float *loss_host, void *stream) {
+  return guarded([&] { return heom_nn_gradients_body(n, X_dev, T_dev, W_dev, rows, grads_host, loss_host, stream); });
 }
 
-static heom_status heom_nn_train_body(heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset, int32_t epochs,
-                          int32_t batch, double lr, uint64_t seed, float *loss_per_epoch, void *stream) {
+static heom_status heom_nn_train_body(heom_nn *n, const void *X_dev, const void *T_dev, const void *W_dev, int64_t rows,
+                                      int64_t subset, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                                      float *loss_per_epoch, void *stream) {
   if (!n || !X_dev || !T_dev || rows <= 0 || epochs < 0 || batch <= 0 || !(lr > 0))
     return fail(HEOM_ERR_ARG, "nn_train: bad arguments");
   hipStream_t s = (hipStream_t)stream;
@@ -715,12 +728,13 @@ static heom_status heom_nn_train_body(heom_nn *n, const void *X_dev, const void 
   FwdBuffers f;
   GradBuffers g;
   uint16_t *Xb = nullptr;
-  float *Tb = nullptr, *losses = nullptr;
+  float *Tb = nullptr, *Wb = nullptr, *losses = nullptr;
   int64_t *idx = nullptr;
   HEOM_TRY(alloc_fwd(*n, B, true, f, ds));
   HEOM_TRY(alloc_grad(*n, B, g, ds));
   HEOM_TRY(ds.get(&Xb, B * (size_t)n->k1 * 2));
   HEOM_TRY(ds.get(&Tb, B * (size_t)n->o_pad * 4));
+  HEOM_TRY(ds.get(&Wb, B * (size_t)4));
   HEOM_TRY(ds.get(&idx, used * 8));
   HEOM_TRY(ds.get(&losses, std::max<int64_t>(steps, 1) * 4));
   std::vector<int64_t> perm(used);
@@ -732,9 +746,9 @@ static heom_status heom_nn_train_body(heom_nn *n, const void *X_dev, const void 
     HEOM_HIP_CHECK(hipMemcpyAsync(idx, perm.data(), used * 8, hipMemcpyHostToDevice, s));
     for (int64_t stp = 0; stp < steps; ++stp) {
       hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)B), dim3(128), 0, s, (const uint16_t *)X_dev,
-                         (const float *)T_dev, idx + stp * B, B, n->k1, n->o_pad, Xb, Tb);
+                         (const float *)T_dev, (const float *)W_dev, idx + stp * B, B, n->k1, n->o_pad, Xb, Tb, Wb);
       HEOM_TRY(forward(*n, Xb, B, f, s));
-      HEOM_TRY(backward(*n, Xb, Tb, B, f, g, losses + stp, s));
+      HEOM_TRY(backward(*n, Xb, Tb, W_dev ? Wb : nullptr, B, f, g, losses + stp, s));
       ++n->adam_step;
       const float c1 = 1.f - std::pow(b1, (float)n->adam_step), c2 = 1.f - std::pow(b2, (float)n->adam_step);
       for (int l = 0; l < 3; ++l) {
@@ -757,9 +771,12 @@ static heom_status heom_nn_train_body(heom_nn *n, const void *X_dev, const void 
   return HEOM_OK;
 }
 
-heom_status heom_nn_train(heom_nn *n, const void *X_dev, const void *T_dev, int64_t rows, int64_t subset, int32_t epochs,
-                          int32_t batch, double lr, uint64_t seed, float *loss_per_epoch, void *stream) {
-  return guarded([&] { return heom_nn_train_body(n, X_dev, T_dev, rows, subset, epochs, batch, lr, seed, loss_per_epoch, stream); });
+heom_status heom_nn_train(heom_nn *n, const void *X_dev, const void *T_dev, const void *W_dev, int64_t rows,
+                          int64_t subset, int32_t epochs, int32_t batch, double lr, uint64_t seed, float *loss_per_epoch,
+                          void *stream) {
+  return guarded([&] {
+    return heom_nn_train_body(n, X_dev, T_dev, W_dev, rows, subset, epochs, batch, lr, seed, loss_per_epoch, stream);
+  });
 }
 
 }  // extern "C"

@@ -3,8 +3,9 @@ network, and its use inside FGMRES.
 
 Bars: forward and gradients within 1e-2 of the largest element per layer and
 1e-3 relative on norms (BF16 operands, FP32 accumulation, compared with the
-oracle's BF16 emulation); features within one BF16 rounding; FGMRES with the
-network reaches a 1e-8 true residual."""
+oracle's BF16 emulation); features within one BF16 rounding; training on the
+method's own (residual, error) pairs halves the held-out loss; FGMRES with the
+network reaches the true-residual tolerance."""
 import numpy as np
 import pytest
 
@@ -59,14 +60,15 @@ def test_forward_and_gradients_match_oracle(d, rows):
     p = net.get_params()
     net.set_params(p + np.float32(0.05) * rng.standard_normal(p.size).astype(np.float32))
     X = onn.bf16(rng.standard_normal((rows, net.k1)).astype(np.float32))
-    X[:, 2 * d * d + 4:] = 0
+    X[:, 2 * d * d + 6:] = 0
     T = rng.standard_normal((rows, net.o_pad)).astype(np.float32)
+    W = rng.uniform(0.05, 3.0, rows).astype(np.float32)
     layers = _layers(net)
     O_ref, _ = onn.forward_bf16(layers, X)
     O = net.forward(_bits(X)).cpu().numpy()
     _close(O, O_ref, "forward")
-    g, loss = net.gradients(_bits(X), torch.from_numpy(T).cuda())
-    g_ref, loss_ref = onn.grads_bf16(layers, X, T)
+    g, loss = net.gradients(_bits(X), torch.from_numpy(T).cuda(), torch.from_numpy(W).cuda())
+    g_ref, loss_ref = onn.grads_bf16(layers, X, T, W)
     assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
     off = 0
     for l, (gW, gb) in enumerate(g_ref):
@@ -85,23 +87,24 @@ def test_features_and_targets_match_oracle():
     net = api.Network(d=4, hidden=64, seed=1)
     rng = np.random.default_rng(3)
     r_o = wl.random_vector(rng, om.N, om.d)
+    r_o[5] = 0  # a converged block
     e_o = wl.random_vector(rng, om.N, om.d)
     r_l, e_l = np.empty_like(r_o), np.empty_like(e_o)
     r_l[perm], e_l[perm] = r_o, e_o
-    X, T = net.pairs(lm, torch.from_numpy(r_l).cuda(), torch.from_numpy(e_l).cuda(), border=1)
+    X, T, W = net.pairs(lm, torch.from_numpy(r_l).cuda(), torch.from_numpy(e_l).cuda())
     Xg = _from_bits(X)[perm]
     Tg = T.cpu().numpy()[perm]
-    diag = to_blocks(om.assemble().diagonal(), om.N, om.d)
+    Wg = W.cpu().numpy()[perm]
     lev_n = np.array([len(q) for _, q in om.hier.ados])
     lev_m = np.array([len(j) for j, _ in om.hier.ados])
     decay = np.array([sum(om.ferm[x]["gamma"] for x in q) for _, q in om.hier.ados])
-    Xo, nu, jr = onn.features(r_o, diag, lev_n, lev_m, decay, 2, 0, net.k1, border=True)
+    Xo, nu = onn.features(r_o, lev_n, lev_m, decay, 2, 0, net.k1)
     assert np.abs(Xg - Xo).max() <= 2.0 ** -7 * max(1.0, np.abs(Xo).max())
-    d2 = om.d * om.d
-    To = np.zeros_like(Tg)
-    To[:, :d2] = ((e_o - jr).real / nu[:, None, None]).reshape(om.N, -1)
-    To[:, d2: 2 * d2] = ((e_o - jr).imag / nu[:, None, None]).reshape(om.N, -1)
-    assert np.abs(Tg - To).max() <= 1e-5 * np.abs(To).max()
+    To, Wo = onn.targets(r_o, e_o)
+    assert np.abs(Tg[:, : To.shape[1]] - To).max() <= 1e-5 * np.abs(To).max()
+    assert np.all(Tg[:, To.shape[1]:] == 0)
+    assert np.abs(Wg - Wo).max() <= 1e-5 * Wo.max()
+    assert Wg[5] == 0 and np.all(Xg[5, : 2 * om.d * om.d] == 0)
 
 
 def test_training_fits_a_learnable_map():
@@ -112,7 +115,7 @@ def test_training_fits_a_learnable_map():
     rng = np.random.default_rng(8)
     rows = 16384
     X = onn.bf16(rng.standard_normal((rows, net.k1)).astype(np.float32))
-    X[:, 2 * 16 + 4:] = 0
+    X[:, 2 * 16 + 6:] = 0
     Mfix = rng.standard_normal((net.k1, net.o_pad)).astype(np.float32) / np.sqrt(36.0)
     T = (X @ Mfix).astype(np.float32)
     losses = net.train(_bits(X), torch.from_numpy(T).cuda(), epochs=40, batch=1024, lr=3e-3, seed=2)
@@ -120,45 +123,75 @@ def test_training_fits_a_learnable_map():
     assert losses[-1] < 0.1 * losses[0], losses
 
 
-def test_zero_network_reproduces_jacobi_gmres():
-    """z = J r + nu * 0: FGMRES with the network is GMRES with Jacobi."""
+def test_zero_network_is_the_identity():
+    """z = r + nu * 0: FGMRES with a zero network is GMRES without a
+    preconditioner, iteration for iteration."""
     torch, api = _torch(), _api()
     cfg = wl.siam()
     h = library_model(cfg, parity_op=cfg["parity_op"])
     net = api.Network(d=4, hidden=64, seed=0)
     net.set_params(np.zeros(net.n_params, dtype=np.float32))
-    x_n, rep_n = api.steady_state(h, tol=1e-10, precond="nn", nn=net, fallback=0, restart=30)
-    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="jacobi", restart=30)
+    x_n, rep_n = api.steady_state(h, tol=1e-10, precond="nn", nn=net, fallback=0, restart=30, max_iter=3000)
+    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="none", restart=30, max_iter=3000)
     assert rep_n["iterations"] == rep_j["iterations"] and rep_n["fell_back"] == 0
-    assert (x_n - x_j).abs().max().item() <= 1e-12 * x_j.abs().max().item()
+    assert (x_n - x_j).abs().max().item() <= 1e-10 * x_j.abs().max().item()
+
+
+def _siam_pairs(api, net, seeds, snapshots=(10, 30, 60)):
+    """(X, T, W) from plain GMRES on seeded perturbations of the Anderson
+    impurity model at tier 2 (eps, U, Gamma, mu each times e^{0.1 Z})."""
+    import torch
+    Xs, Ts, Ws = [], [], []
+    for s in seeds:
+        z = np.exp(0.1 * np.random.default_rng(s).standard_normal(4))
+        pc = wl.siam(eps=-5.0 * z[0], U=10.0 * z[1], Gamma=2.0 * z[2], mus=(z[3], -z[3]), n_max=2)
+        hp = library_model(pc, parity_op=pc["parity_op"])
+        for X, T, W in api.collect_pairs(hp, net, snapshots=snapshots, restart=20):
+            Xs.append(X)
+            Ts.append(T)
+            Ws.append(W)
+        hp.close()
+    return torch.cat(Xs), torch.cat(Ts), torch.cat(Ws)
+
+
+def test_training_on_solver_pairs_halves_held_out_loss():
+    """The network trained on (residual, error) pairs that plain GMRES
+    generates on 16 seeded perturbations of the Anderson impurity model:
+    the weighted loss on pairs from 4 other seeds (never trained on) falls
+    by at least 2x from the untrained network's."""
+    torch, api = _torch(), _api()
+    net = api.Network(d=4, hidden=256, seed=3)
+    Xtr, Ttr, Wtr = _siam_pairs(api, net, range(1000, 1016))
+    Xte, Tte, Wte = _siam_pairs(api, net, range(2000, 2004))
+    _, before = net.gradients(Xte, Tte, Wte)
+    losses = net.train(Xtr, Ttr, Wtr, epochs=120, batch=1024, lr=1e-3, seed=7)
+    _, after = net.gradients(Xte, Tte, Wte)
+    print(f"\ntrain rows {Xtr.shape[0]}, held-out rows {Xte.shape[0]}: held-out loss {before:.4g} -> {after:.4g}; "
+          f"training loss {losses[0]:.4g} -> {losses[-1]:.4g}")
+    assert np.all(np.isfinite(losses))
+    assert after <= 0.5 * before, (before, after)
 
 
 def test_trained_network_in_fgmres():
     """Pairs from plain GMRES on perturbed models, GPU training, then the
-    stationary state with the network: the answer is the Jacobi one to the
-    true-residual tolerance, whether the network converges itself or hands
-    over to Jacobi on stagnation.  Its gain is measured, not asserted."""
+    stationary state with the network: the answer is the unpreconditioned
+    one to the true-residual tolerance, whether the network converges itself
+    or hands over to Jacobi on stagnation.  Its gain is measured, not
+    asserted."""
     torch, api = _torch(), _api()
-    cfg = wl.siam()
+    cfg = wl.siam(n_max=2)
     net = api.Network(d=4, hidden=128, seed=0)
-    Xs, Ts = [], []
-    for s in range(3):
-        z = np.exp(0.1 * np.random.default_rng(1000 + s).standard_normal(2))
-        pc = wl.siam(eps=-5.0 * z[0], U=10.0 * z[1])
-        hp = library_model(pc, parity_op=pc["parity_op"])
-        for X, T in api.collect_pairs(hp, net, snapshots=(10, 40)):
-            Xs.append(X)
-            Ts.append(T)
-    losses = net.train(torch.cat(Xs), torch.cat(Ts), epochs=8, batch=4096, lr=1e-3, seed=5, subset=20000)
+    X, T, W = _siam_pairs(api, net, range(1000, 1004), snapshots=(10, 40))
+    losses = net.train(X, T, W, epochs=8, batch=4096, lr=1e-3, seed=5)
     assert np.all(np.isfinite(losses))
     h = library_model(cfg, parity_op=cfg["parity_op"])
     x_nn, rep_nn = api.steady_state(h, tol=1e-10, precond="nn", nn=net, restart=30)
-    x_j, rep_j = api.steady_state(h, tol=1e-10, precond="jacobi", restart=30)
+    x_0, rep_0 = api.steady_state(h, tol=1e-10, precond="none", restart=30, max_iter=5000)
     assert rep_nn["status"] == 0 and rep_nn["true_residual"] <= 1e-10, rep_nn
-    assert (x_nn - x_j).abs().max().item() <= 1e-8 * x_j.abs().max().item()
+    assert (x_nn - x_0).abs().max().item() <= 1e-8 * x_0.abs().max().item()
     print(f"\nloss {losses[0]:.3g} -> {losses[-1]:.3g}; iterations nn {rep_nn['iterations']} "
-          f"(fell back: {rep_nn['fell_back']}, {rep_nn['seconds']:.3f} s) / jacobi {rep_j['iterations']} "
-          f"({rep_j['seconds']:.3f} s)")
+          f"(fell back: {rep_nn['fell_back']}, {rep_nn['seconds']:.3f} s) / none {rep_0['iterations']} "
+          f"({rep_0['seconds']:.3f} s)")
 
 
 def test_nan_network_falls_back_to_jacobi():
