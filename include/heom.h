@@ -481,6 +481,19 @@ heom_status heom_nn_train(heom_nn *nn, const void *X_dev, const void *T_dev, con
 heom_status heom_current(heom_hier *h, const void *x_dev, int32_t n_rec, const int32_t *records, double *out,
                          void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * current as heom_current, with the term list and the terms' operators kept
+ * in a library-owned device array instead of per-call allocations.  No
+ * hipMalloc / hipFree; the array (about 1 MB) is held on every GPU the call
+ * runs on until the process ends.  Limits: d <= 32 (HEOM_ERR_UNSUPPORTED
+ * beyond).  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (other threads or streams) race and must be serialised by the
+ * caller.  Synchronises the stream; the host arrays it copies from live on
+ * the call's stack or in the handle. */
+heom_status heom_current_noalloc(heom_hier *h, const void *x_dev, int32_t n_rec, const int32_t *records, double *out,
+                                 void *stream);
+
 /* z = P^{-1} r for a fixed preconditioner precond (HEOM_PREC_JACOBI,
  * HEOM_PREC_SCALED or HEOM_PREC_BLOCK), the map the solvers apply on the
  * right.  r_dev, z_dev: device [N][d][d][n_rhs] complex vectors of the given

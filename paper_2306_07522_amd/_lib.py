@@ -112,6 +112,7 @@ SIGNATURES = {
                                             C.c_int32, dp, heom_drive_fn, vp, vp, C.c_size_t, vp]),
     "heom_hierarchy_set_lindblad": (heom_status, [vp, C.c_int32, dp]),
     "heom_current": (heom_status, [vp, vp, C.c_int32, i32p, dp, vp]),
+    "heom_current_noalloc": (heom_status, [vp, vp, C.c_int32, i32p, dp, vp]),
     "heom_precondition": (heom_status, [vp, C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, C.c_int32, vp]),
     "heom_batch_workspace_size": (heom_status, [vp, C.POINTER(heom_solver_opts), C.POINTER(C.c_size_t)]),
     "heom_batch_steady": (heom_status, [vp, vp, C.POINTER(heom_solver_opts), C.POINTER(heom_solver_report),

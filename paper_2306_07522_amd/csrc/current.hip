@@ -7,6 +7,7 @@
 // to the index of its single-exponent ADO through the hierarchy dictionary and
 // prepares the matrices i (-1)^{delta_{nu,-}} d^{nu-bar}; one workgroup sums
 // Tr[O_t X_{a_t}] over all terms with a fixed-order reduction.
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -14,10 +15,12 @@
 
 namespace heom {
 
-// out = sum_t sum_{i,j} O_t[i][j] X_{a_t}[j][i]  (X row-major d x d blocks)
+// out = sum_t sum_{i,j} O_t[i][j] X_{a_t}[j][i]  (X row-major d x d blocks).
+// With neg = NULL the O_t carry their coefficient; otherwise O_t is the
+// plain operator times i, or times -i where neg[t] is set.
 __global__ void __launch_bounds__(256) current_kernel(const double2 *__restrict__ x, int d, int n_terms,
                                                       const int64_t *__restrict__ ado, const double2 *__restrict__ ops,
-                                                      double2 *__restrict__ out) {
+                                                      const int32_t *__restrict__ neg, double2 *__restrict__ out) {
   __shared__ double sx[256], sy[256];
   const int dd = d * d;
   const int64_t total = (int64_t)n_terms * dd;
@@ -25,7 +28,8 @@ __global__ void __launch_bounds__(256) current_kernel(const double2 *__restrict_
   for (int64_t k = threadIdx.x; k < total; k += blockDim.x) {
     const int t = (int)(k / dd), e = (int)(k % dd);
     const int i = e / d, j = e % d;
-    const double2 o = ops[k];
+    double2 o = ops[k];
+    if (neg) o = neg[t] ? make_double2(o.y, -o.x) : make_double2(-o.y, o.x);  // -i O or i O
     const double2 v = x[ado[t] * dd + j * d + i];
     ax += o.x * v.x - o.y * v.y;
     ay += o.x * v.y + o.y * v.x;
@@ -47,8 +51,8 @@ __global__ void __launch_bounds__(256) current_kernel(const double2 *__restrict_
 
 using namespace heom;
 
-static heom_status heom_current_body(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
-                                    double *out, void *stream) {
+static heom_status check_current_args(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
+                                      double *out) {
   if (!hw || !x_dev || !records || !out || n_rec < 1) return fail(HEOM_ERR_ARG, "current: NULL argument");
   Hier &h = *hw->impl;
   if (h.parity != 1) return fail(HEOM_ERR_ARG, "current: needs the even-parity hierarchy of the stationary state");
@@ -59,6 +63,13 @@ static heom_status heom_current_body(heom_hier *hw, const void *x_dev, int32_t n
     for (int q = 0; q < r; ++q)
       if (records[q] == b) return fail(HEOM_ERR_ARG, "current: repeated bath index");
   }
+  return HEOM_OK;
+}
+
+static heom_status heom_current_body(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
+                                    double *out, void *stream) {
+  HEOM_TRY(check_current_args(hw, x_dev, n_rec, records, out));
+  Hier &h = *hw->impl;
   out[0] = out[1] = 0.0;
   const int d = h.d, dd = d * d;
   std::vector<int64_t> ado;
@@ -95,7 +106,7 @@ static heom_status heom_current_body(heom_hier *hw, const void *x_dev, int32_t n
       st = fail(HEOM_ERR_HIP, "current: copy to the device failed");
     } else {
       hipLaunchKernelGGL(current_kernel, dim3(1), dim3(256), 0, s, (const double2 *)x_dev, d, (int)ado.size(), d_ado,
-                         d_ops, d_out);
+                         d_ops, (const int32_t *)nullptr, d_out);
       if (hipGetLastError() != hipSuccess ||
           hipMemcpyAsync(&res, d_out, sizeof(double2), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
@@ -113,4 +124,95 @@ static heom_status heom_current_body(heom_hier *hw, const void *x_dev, int32_t n
 extern "C" heom_status heom_current(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
                                     double *out, void *stream) {
   return guarded([&] { return heom_current_body(hw, x_dev, n_rec, records, out, stream); });
+}
+
+// ------------------------------------------------------------------ no-allocation variant
+// heom_current_noalloc keeps the term list and the terms' operators in a
+// file-scope device array instead of per-call allocations: at most
+// kCurTerms terms (every fermionic exponent is at most one term, and there
+// are at most 64) of d <= kCurMaxD.  Layout: ado[kCurTerms] (int64),
+// neg[kCurTerms] (int32), the result (double2), then the operators,
+// kCurTerms x d^2 double2 (row-major, term-major).
+namespace heom {
+constexpr int kCurTerms = 64, kCurMaxD = 32;
+constexpr size_t kCurOpsOff = 1024;  // past ado (512 B), neg (256 B) and the result, 256-byte aligned
+constexpr size_t kCurScratchBytes = kCurOpsOff + (size_t)kCurTerms * kCurMaxD * kCurMaxD * sizeof(double2);
+}  // namespace heom
+
+static __device__ __align__(256) unsigned char scratch[heom::kCurScratchBytes];
+
+namespace heom {
+// device address of `scratch` on each device, taken once per device with
+// that device current (each device holds its own copy of the array)
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+static heom_status scratch_on_current_device(unsigned char **ptr) {
+  int dev = 0;
+  HEOM_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HEOM_ERR_UNSUPPORTED, "current_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HEOM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HEOM_ERR_HIP, "current_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = (unsigned char *)g_scratch_ptr[dev];
+  return HEOM_OK;
+}
+}  // namespace heom
+
+static heom_status heom_current_noalloc_body(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
+                                            double *out, void *stream) {
+  HEOM_TRY(check_current_args(hw, x_dev, n_rec, records, out));
+  Hier &h = *hw->impl;
+  out[0] = out[1] = 0.0;
+  const int d = h.d, dd = d * d;
+  if (d > kCurMaxD) return fail(HEOM_ERR_UNSUPPORTED, "current_noalloc: d above 32 exceeds the scratch array");
+  // the terms, staged on the stack: ADO, sign of the coefficient, operator
+  int64_t ado[kCurTerms];
+  int32_t neg[kCurTerms];
+  const std::vector<cd> *opm[kCurTerms];
+  int n_terms = 0;
+  for (int q = 0; q < h.Kf; ++q) {
+    const auto &f = h.fexp[q];
+    bool in_lead = false;
+    for (int r = 0; r < n_rec; ++r) in_lead = in_lead || f.bath == records[r];
+    if (!in_lead) continue;
+    const int64_t a = lookup_ado(h, 1ull << q, 0);
+    if (a < 0) continue;
+    if (n_terms >= kCurTerms) return fail(HEOM_ERR_UNSUPPORTED, "current_noalloc: more than 64 terms");
+    ado[n_terms] = a;
+    neg[n_terms] = f.nu == +1 ? 0 : 1;  // coefficient i for nu = +1, -i for nu = -1
+    opm[n_terms] = &h.ops[f.nu == +1 ? f.op_ann : f.op_ann + 1];
+    ++n_terms;
+  }
+  if (n_terms == 0) return HEOM_OK;
+  unsigned char *base = nullptr;
+  HEOM_TRY(scratch_on_current_device(&base));
+  int64_t *d_ado = (int64_t *)base;
+  int32_t *d_neg = (int32_t *)(base + kCurTerms * sizeof(int64_t));
+  double2 *d_out = (double2 *)(base + kCurTerms * (sizeof(int64_t) + sizeof(int32_t)));
+  double2 *d_ops = (double2 *)(base + kCurOpsOff);
+  hipStream_t s = (hipStream_t)stream;
+  HEOM_HIP_CHECK(hipMemcpyAsync(d_ado, ado, sizeof(int64_t) * n_terms, hipMemcpyHostToDevice, s));
+  HEOM_HIP_CHECK(hipMemcpyAsync(d_neg, neg, sizeof(int32_t) * n_terms, hipMemcpyHostToDevice, s));
+  for (int t = 0; t < n_terms; ++t)  // std::complex<double> is laid out as (re, im)
+    HEOM_HIP_CHECK(hipMemcpyAsync(d_ops + (size_t)t * dd, opm[t]->data(), sizeof(double2) * dd,
+                                  hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(current_kernel, dim3(1), dim3(256), 0, s, (const double2 *)x_dev, d, n_terms,
+                     (const int64_t *)d_ado, (const double2 *)d_ops, (const int32_t *)d_neg, d_out);
+  HEOM_HIP_CHECK(hipGetLastError());
+  double2 res = make_double2(0.0, 0.0);
+  HEOM_HIP_CHECK(hipMemcpyAsync(&res, d_out, sizeof(double2), hipMemcpyDeviceToHost, s));
+  HEOM_HIP_CHECK(hipStreamSynchronize(s));
+  out[0] = res.x;
+  out[1] = res.y;
+  return HEOM_OK;
+}
+
+extern "C" heom_status heom_current_noalloc(heom_hier *hw, const void *x_dev, int32_t n_rec, const int32_t *records,
+                                            double *out, void *stream) {
+  return guarded([&] { return heom_current_noalloc_body(hw, x_dev, n_rec, records, out, stream); });
 }
