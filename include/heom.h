@@ -385,7 +385,9 @@ int32_t heom_spectrum_chunk(const heom_hier *h, const heom_solver_opts *o);
 heom_status heom_workspace_size(const heom_hier *h, int32_t op, const heom_solver_opts *o, int64_t n_rhs,
                                 size_t *bytes);
 
-/* Stationary state: solves B x = e_0 where B is M (even parity) with the
+/* Stationary state of all ADOs (Package architecture, panel (d) of the
+ * package figure: M x = 0 for the even-parity HEOMLS of eq:HEOM, normalised
+ * by Tr rho_0 = 1).  Solves B x = e_0 where B is M (even parity) with the
  * equation of element (0,0) of ADO 0 replaced by Tr rho_0 = 1.  x_dev:
  * FP64 [N][d][d] (initial guess if o->use_x0).  Synchronises the stream at
  * every convergence check. */

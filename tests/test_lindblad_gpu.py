@@ -121,3 +121,23 @@ def test_thermal_oscillator_through_the_library():
     p = (nbar / (nbar + 1)) ** np.arange(n_f)
     p /= p.sum()
     assert np.abs(x.cpu().numpy()[0] - np.diag(p)).max() <= 1e-11
+
+
+@pytest.mark.parametrize("mode", ["fp64", "shifted"])
+def test_psd_of_damped_oscillator_closed_form(mode):
+    """The library's power spectrum of the thermally damped oscillator
+    against S(w) = (n / pi) (kappa/2) / ((kappa/2)^2 + (w - w_c)^2), a
+    Lorentzian at +w_c (quantum regression), on an asymmetric grid: per
+    frequency (FP64 GMRES) and from one Krylov space (multi-shift)."""
+    _torch()
+    from paper_2306_07522_amd import api
+    n_f, wc, kappa, nbar = 14, 1.0, 0.2, 0.05
+    a = np.diag(np.sqrt(np.arange(1, n_f)), 1).astype(complex)
+    h = api.Hierarchy(wc * a.conj().T @ a, [], 0, 0,
+                      lindblad=[np.sqrt(kappa * (nbar + 1)) * a, np.sqrt(kappa * nbar) * a.conj().T])
+    x, rep = api.steady_state(h, tol=1e-13, precond="none", restart=60, max_iter=4000)
+    grid = np.linspace(0.2, 2.5, 47)
+    S, rep = api.spectrum(h, None, x, a, grid, kind="psd", tol=1e-12, mode=mode, precond="none", restart=60,
+                          max_iter=20000)
+    ref = nbar / np.pi * (kappa / 2) / ((kappa / 2) ** 2 + (grid - wc) ** 2)
+    assert np.abs(S - ref).max() <= 1e-8 * ref.max(), (mode, np.abs(S - ref).max())

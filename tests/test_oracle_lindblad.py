@@ -68,3 +68,33 @@ def test_lindblad_with_baths_keeps_trace_and_ado_count():
         Fd = F.conj().T
         L += np.kron(Fd.T, F) - 0.5 * np.kron(np.eye(2), Fd @ F) - 0.5 * np.kron((Fd @ F).T, np.eye(2))
     assert np.abs(D - L).max() < 1e-15
+
+
+def test_psd_orientation_damped_oscillator_closed_form():
+    """Frequency orientation of the power spectrum (Methods, "Numerical
+    computation of the spectrum": pi S(w) = -Re Tr[a^dag x] with
+    (M - i w) x = a rho_ss).  For the thermally damped oscillator
+    H = w_c a^dag a, F1 = sqrt(kappa (n+1)) a, F2 = sqrt(kappa n) a^dag, the
+    quantum regression theorem gives <a^dag(t) a(0)> = n e^{(i w_c - kappa/2) t},
+    and x = -int_0^inf e^{(M - i w) t} a rho_ss dt, so
+        S(w) = (n / pi) (kappa/2) / ((kappa/2)^2 + (w - w_c)^2):
+    a Lorentzian of weight <a^dag a> = n at +w_c.  The grid is asymmetric
+    (w in [0.2, 2.5]), so a flipped sign of i w (a peak at -w_c) fails.  The
+    Fock truncation only enters through the top level's population,
+    (n / (n + 1))^13 ~ 1e-17."""
+    n_f, wc, kappa, nbar = 14, 1.0, 0.2, 0.05
+    a = np.diag(np.sqrt(np.arange(1, n_f)), 1).astype(complex)
+    H = wc * a.conj().T @ a
+    F = [np.sqrt(kappa * (nbar + 1)) * a, np.sqrt(kappa * nbar) * a.conj().T]
+    om = OracleHEOM(H, [], 0, 0, lindblad=F)
+    M = om.assemble()
+    x = osv.steady_state(M, om.d)
+    grid = np.linspace(0.2, 2.5, 47)
+    S = osv.psd(M, x, a, grid, 1, n_f)
+    ref = nbar / np.pi * (kappa / 2) / ((kappa / 2) ** 2 + (grid - wc) ** 2)
+    assert np.abs(S - ref).max() <= 1e-9 * ref.max(), np.abs(S - ref).max()
+    assert S.argmax() == np.argmin(np.abs(grid - wc))
+    # the mirror frequency -w_c carries only the Lorentzian's far tail
+    S_mirror = osv.psd(M, x, a, [-wc], 1, n_f)[0]
+    tail = nbar / np.pi * (kappa / 2) / ((kappa / 2) ** 2 + (2 * wc) ** 2)
+    assert abs(S_mirror - tail) <= 1e-9 * ref.max()

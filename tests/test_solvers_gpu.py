@@ -198,6 +198,28 @@ def test_psd_cavity_vs_oracle(mode):
     assert np.abs(S - So).max() <= 1e-9 * np.abs(So).max(), (S, So)
 
 
+@pytest.mark.parametrize("mode", ["fp64", "block"])
+def test_psd_cavity_configured_bath_vs_oracle(mode):
+    """The cavity emission spectrum with the bath parameters of the full
+    charge-cavity workload (Drude-Lorentz lambda 0.01, gamma 0.1, T 0.1 as a
+    J pole plus 3 Matsubara terms; leads Gamma 0.01, tier 2 each way), cut
+    to 2 photons and 2 lead exponents so that the oracle's sparse LU stays
+    within seconds.  The frequencies straddle the cavity resonance."""
+    torch, api = _torch(), _api()
+    cfg = wl.charge_cavity(n_photon=2, n_fexp=2)
+    he = library_model(cfg, +1)
+    oe = oracle_model(cfg, +1)
+    x, _ = api.steady_state(he, tol=1e-12)
+    om = np.array([0.5, 0.9, 0.95, 1.0, 1.05, 1.5])
+    # the unpreconditioned shifted solver stalls here (lead width 0.01)
+    extra = dict(precond="block") if mode == "block" else {}
+    S, rep = api.spectrum(he, None, x, cfg["aop"], om, kind="psd", tol=1e-12, rhs_chunk=6, mode="fp64", **extra)
+    assert rep["true_residual"] <= 1e-11, rep
+    xs = osv.steady_state(oe.assemble(), oe.d)
+    So = osv.psd(oe.assemble(), xs, cfg["aop"], om, oe.N, oe.d)
+    assert np.abs(S - So).max() <= 1e-9 * np.abs(So).max(), (S, So)
+
+
 @pytest.mark.parametrize("restart,deflate", [(12, 4), (60, 0), (60, 8)])
 def test_dos_invariant_krylov_space_vs_oracle(restart, deflate):
     """A 36-element odd hierarchy (resonant level, two exponents per lead,
