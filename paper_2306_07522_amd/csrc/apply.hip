@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) apply_cell_kernel(ApplyParams<T> P) {
       for (int ii = 0; ii < d; ++ii) tr = cadd(tr, in(0, ii, ii));
       acc = tr;
     }
-    P.y[out] = acc;
+    P.y[out] = epilogue(P, out, acc);
   }
 }
 
@@ -294,6 +294,12 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   P.shifts = (const T2 *)a.shifts;
   P.shift0 = T2{(T)a.shift0.real(), (T)a.shift0.imag()};
   P.border = a.border;
+  P.epi = a.epi ? 1 : 0;
+  for (int j = 0; j < 4; ++j) {
+    P.ev[j] = (const T2 *)a.ev[j];
+    P.ec[j] = (T)a.ec[j];
+  }
+  P.eacc = (T)a.eacc;
   const int d = h.d;
   const size_t tab_bytes = (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 16 + (size_t)d * sizeof(T2);
   const size_t smem = 4 * (size_t)d * d * sizeof(T2) + tab_bytes;
@@ -371,6 +377,8 @@ heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int pl
     default:
       return fail(HEOM_ERR_ARG, "apply: unknown plan");
   }
+  if (a.epi && (slab || a.n_rhs != 1 || !h.lind.empty()))
+    return fail(HEOM_ERR_UNSUPPORTED, "apply: the epilogue needs the pull plan, one right-hand side, no Lindblad terms");
   if (slab) HEOM_TRY(launch_apply_slab(h, precision, a, s));
   else HEOM_TRY(run_plan(h, precision, a, h.dev.base, s));
   return launch_lindblad(h, precision, a, s);
@@ -382,6 +390,7 @@ heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t
 
 heom_status launch_apply_tiled(Hier &h, int precision, const ApplyArgs &a, int n_chunks, hipStream_t s) {
   HEOM_TRY(check_apply(h, precision, a));
+  if (a.epi) return fail(HEOM_ERR_UNSUPPORTED, "apply: the tiled plan has no epilogue");
   if (n_chunks <= 0) {
     // keep each chunk's leaf blocks around 96 MB so they stay in the
     // 256 MB last-level cache while the lower tiers re-read them

@@ -39,7 +39,28 @@ struct ApplyParams {
   const T2 *shifts;
   T2 shift0;
   int border;
+  // epilogue: y = eacc * acc + sum_j ec[j] * ev[j] (ev[j] may alias y)
+  int epi;
+  const T2 *ev[4];
+  T ec[4];
+  T eacc;
 };
+
+// The output element after the optional epilogue.
+template <typename T>
+__device__ __forceinline__ typename Cplx<T>::t epilogue(const ApplyParams<T> &P, int64_t idx,
+                                                        typename Cplx<T>::t v) {
+  if (!P.epi) return v;
+  typename Cplx<T>::t r{P.eacc * v.x, P.eacc * v.y};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (!P.ev[j]) continue;
+    const typename Cplx<T>::t q = P.ev[j][idx];
+    r.x = fma(P.ec[j], q.x, r.x);
+    r.y = fma(P.ec[j], q.y, r.y);
+  }
+  return r;
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -264,7 +285,8 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
     if (!LaneMap<T, D>::on(lane, s)) continue;
     T2 v = acc[s];
     if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;  // element 0 in both maps
-    P.y[abase + LaneMap<T, D>::elem(lane, s)] = v;
+    const int64_t idx = abase + LaneMap<T, D>::elem(lane, s);
+    P.y[idx] = epilogue(P, idx, v);
   }
 }
 

@@ -312,24 +312,65 @@ static heom_status heom_propagate_body(heom_hier *hw, int32_t precision, void *x
   if (!k[0] || !k[1] || !k[2] || !k[3] || !u || !counter) return fail(HEOM_ERR_ARG, "propagate: workspace too small");
   HEOM_TRY(fill_int(counter, 0, 1, s));
   const int64_t n_saves = save_every > 0 ? n_steps / save_every : 0;
-  auto step = [&](int64_t idx) -> heom_status {
+  // Without Lindblad terms every stage's apply ends in an epilogue that
+  // writes the next stage input, u_s = x + c_s k_s, in place of k_s.  The
+  // last stage writes the new state over x: with c_1 = c_2 = dt/2 and
+  // c_3 = dt, x + dt/6 (k1 + 2 k2 + 2 k3 + k4) equals
+  // (u_1 + 2 u_2 + u_3 - x) / 3 + dt/6 k4.  Stage 4 gathers only from u_3,
+  // and each element of x is read and then overwritten by the same lane, so
+  // the update is safe in place.  A step then moves the four applies plus
+  // five vector reads (x in stages 2 and 3; u_1, u_2, x in stage 4) instead
+  // of three stage-input passes and a five-vector combine.
+  const bool fused = h.lind.empty();
+  void *us[3] = {k[0], k[1], k[2]};
+  auto fused_step = [&]() -> heom_status {
     ApplyArgs a;
     a.n_rhs = 1;
-    a.x = x_dev;
-    a.y = k[0];
-    HEOM_TRY(launch_apply(h, precision, a, s));
+    a.epi = true;
     const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
-    for (int st = 1; st < 4; ++st) {
-      // one pass forms x + c k; the apply then gathers one block per
-      // neighbour instead of two
-      if (precision == HEOM_FP64) HEOM_TRY(stage_input<double>(x_dev, k[st - 1], cs[st - 1], u, n, s));
-      else HEOM_TRY(stage_input<float>(x_dev, k[st - 1], cs[st - 1], u, n, s));
-      a.x = u;
-      a.y = k[st];
+    for (int st = 0; st < 3; ++st) {
+      a.x = st == 0 ? x_dev : us[st - 1];
+      a.y = us[st];
+      a.ev[0] = x_dev;
+      a.ec[0] = 1.0;
+      a.eacc = cs[st];
       HEOM_TRY(launch_apply(h, precision, a, s));
     }
-    if (precision == HEOM_FP64) HEOM_TRY(rk4_combine<double>(x_dev, k[0], k[1], k[2], k[3], dt, n, s));
-    else HEOM_TRY(rk4_combine<float>(x_dev, k[0], k[1], k[2], k[3], dt, n, s));
+    a.x = us[2];
+    a.y = x_dev;
+    a.ev[0] = us[0];
+    a.ev[1] = us[1];
+    a.ev[2] = us[2];
+    a.ev[3] = x_dev;
+    a.ec[0] = 1.0 / 3.0;
+    a.ec[1] = 2.0 / 3.0;
+    a.ec[2] = 1.0 / 3.0;
+    a.ec[3] = -1.0 / 3.0;
+    a.eacc = dt / 6.0;
+    return launch_apply(h, precision, a, s);
+  };
+  auto step = [&](int64_t idx) -> heom_status {
+    if (fused) {
+      HEOM_TRY(fused_step());
+    } else {
+      ApplyArgs a;
+      a.n_rhs = 1;
+      a.x = x_dev;
+      a.y = k[0];
+      HEOM_TRY(launch_apply(h, precision, a, s));
+      const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
+      for (int st = 1; st < 4; ++st) {
+        // one pass forms x + c k; the apply then gathers one block per
+        // neighbour instead of two
+        if (precision == HEOM_FP64) HEOM_TRY(stage_input<double>(x_dev, k[st - 1], cs[st - 1], u, n, s));
+        else HEOM_TRY(stage_input<float>(x_dev, k[st - 1], cs[st - 1], u, n, s));
+        a.x = u;
+        a.y = k[st];
+        HEOM_TRY(launch_apply(h, precision, a, s));
+      }
+      if (precision == HEOM_FP64) HEOM_TRY(rk4_combine<double>(x_dev, k[0], k[1], k[2], k[3], dt, n, s));
+      else HEOM_TRY(rk4_combine<float>(x_dev, k[0], k[1], k[2], k[3], dt, n, s));
+    }
     if (save_every > 0 && (idx + 1) % save_every == 0) {
       if (precision == HEOM_FP64) HEOM_TRY(save_rho0<double>(x_dev, traj_dev, h.d * h.d, counter, n_saves, s));
       else HEOM_TRY(save_rho0<float>(x_dev, traj_dev, h.d * h.d, counter, n_saves, s));

@@ -218,6 +218,13 @@ struct ApplyArgs {
   const void *shifts = nullptr; // device complex[n_rhs] of the precision, or null
   cd shift0 = 0.0;              // used when shifts == null
   int border = 0;               // 1: replace y[0][0][0] by Tr rho_0 (steady-state row)
+  // Optional epilogue (one right-hand side, pull plan, no Lindblad terms):
+  // y = eacc * (M x) + sum_j ec[j] * ev[j], elementwise.  An ev[j] may be
+  // y itself (each element is read before it is written, by the same lane).
+  bool epi = false;
+  const void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double ec[4] = {0.0, 0.0, 0.0, 0.0};
+  double eacc = 1.0;
 };
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
 // as launch_apply with an explicit plan (HEOM_PLAN_*)

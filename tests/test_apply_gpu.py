@@ -307,3 +307,47 @@ def test_apply_multi_rhs_column_counts(name, R):
     assert rel_err(y32[perm].astype(np.complex128), yo32) <= FP32_TOL
     yt = lm.apply(torch.from_numpy(xl).cuda(), shift=torch.from_numpy(shifts).cuda(), n_rhs=R, tiled=3).cpu().numpy()
     assert rel_err(yt[perm], yo) <= FP64_TOL
+
+
+@pytest.mark.parametrize("n_threads", [2, 4])
+def test_concurrent_first_apply_on_one_handle(n_threads):
+    """Several host threads make the first apply on one fresh handle at the
+    same moment, each on its own stream, so that they race for the one-time
+    upload of the device tables.  Every thread's output must match the
+    oracle; the upload is done once and shared."""
+    import threading
+    torch = _torch()
+    cfg = wl.two_orbital_anderson(n_max=2)
+    om, lm = oracle_model(cfg), library_model(cfg)
+    perm = oracle_to_library_perm(om, lm)
+    M = om.assemble()
+    xs, ys, streams = [], [], []
+    for t in range(n_threads):
+        xo = wl.random_vector(np.random.default_rng(40 + t), om.N, om.d)
+        xl = np.empty_like(xo)
+        xl[perm] = xo
+        xs.append((xo, torch.from_numpy(xl).cuda()))
+        streams.append(torch.cuda.Stream())
+    torch.cuda.synchronize()
+    gate = threading.Barrier(n_threads)
+    errors = []
+
+    def run(t):
+        try:
+            gate.wait()
+            with torch.cuda.stream(streams[t]):
+                ys.append((t, lm.apply(xs[t][1], stream=streams[t])))
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(t,)) for t in range(n_threads)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    assert len(ys) == n_threads
+    for t, y in ys:
+        yo = to_blocks(M @ from_blocks(xs[t][0]), om.N, om.d)
+        assert rel_err(y.cpu().numpy()[perm], yo) <= FP64_TOL, t

@@ -72,10 +72,16 @@ def test_rk4_graph_equals_eager():
     assert torch.equal(xa, xb) and torch.equal(ta, tb)
 
 
-@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small", "siam_tier1", "cavity_d20"])
+@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small", "siam_tier1", "siam_tier2", "cavity_d20"])
 def test_rk4_workloads(name):
+    """Every stage's apply ends in the RK4 epilogue (wave kernel for d = 8,
+    16, 20; cell kernel for the d = 4 tier-2 model; the one-workgroup kernel
+    for the tier-1 model).  FP64 against the oracle's RK4 at 1e-12, FP32
+    at 1e-5."""
     torch, api = _torch(), _api()
-    if name == "charge_cavity":
+    if name == "siam_tier2":
+        cfg = wl.siam(n_max=2)                                    # d = 4: cell kernel
+    elif name == "charge_cavity":
         cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=3)   # d = 8: wave kernel with fused stages
     elif name == "siam_tier1":
         cfg = wl.siam(n_max=1)                                    # 41 ADOs x 16: one-workgroup RK4 kernel
@@ -94,6 +100,10 @@ def test_rk4_workloads(name):
     ref, _ = osv.rk4(om.assemble(), from_blocks(xo), 0.01, 20)
     e = rel_err(x.cpu().numpy()[perm], to_blocks(ref, om.N, om.d))
     assert e <= 1e-12, e
+    x32 = torch.from_numpy(xl.astype(np.complex64)).cuda()
+    api.propagate(lm, x32, 0.01, 20)
+    e32 = rel_err(x32.cpu().numpy()[perm].astype(complex), to_blocks(ref, om.N, om.d))
+    assert e32 <= 1e-5, e32
 
 
 def _steady_check(cfg, mode, precond, tol_err, lu=True):
