@@ -146,6 +146,38 @@ def other_precision_apply(h, precision, tiled_arg, steps=20, warmup=3):
             "frac_of_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def multi_rhs_apply_bench(api, wl, widths=(1, 64, 128, 256, 512), steps=5):
+    """The charge-cavity apply (d = 20, 3,165 ADOs) over R right-hand sides
+    with one shift per column, as the frequency chunks of the spectra use
+    it: average kernel time (HIP events on the launch stream) and
+    algorithmic GB/s per width."""
+    import torch
+    cfg = wl.charge_cavity()
+    h = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity_op=cfg["parity_op"])
+    out = {"n_ado": h.N, "d": h.d, "widths": {}}
+    stream = torch.cuda.current_stream()
+    g = torch.Generator(device="cuda").manual_seed(3)
+    for R in widths:
+        x = torch.randn((h.N, h.d, h.d, R), dtype=torch.complex128, device="cuda", generator=g)
+        y = torch.empty_like(x)
+        shifts = 1j * torch.linspace(0.0, 2.0, R, dtype=torch.float64, device="cuda").to(torch.complex128)
+        h.apply(x, y, shift=shifts, n_rhs=R, stream=stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            h.apply(x, y, shift=shifts, n_rhs=R, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+        nbytes = algorithmic_bytes(h, 16, R)
+        out["widths"][str(R)] = {"kernel_ms_avg": round(ms, 4), "gbs_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                 "us_per_column": round(ms * 1e3 / R, 2)}
+        del x, y
+    h.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def _progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -643,14 +675,80 @@ def solve_benchmarks(which):
     return out
 
 
-def cpu_baseline(seconds):
+def _oracle_perm(om, h):
+    """perm[k] = library index of the oracle's ADO k (both sides store the
+    same ADO sets; matched by bosonic occupations and fermionic label set)."""
+    import numpy as np
+    occ, mask, _ = h.ados()
+    key = {(tuple(int(v) for v in occ[a]), int(mask[a])): a for a in range(h.N)}
+    perm = np.empty(om.N, dtype=np.int64)
+    for k, (j, q) in enumerate(om.hier.ados):
+        o = [0] * h.Kb
+        for t in j:
+            o[t] += 1
+        m = 0
+        for t in q:
+            m |= 1 << t
+        perm[k] = key[(tuple(o), m)]
+    return perm
+
+
+def _cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def superlu_child_main(which):
+    """Child-process body of _superlu_bounded: prints unknowns and seconds."""
+    from oracle import exponents as ox, solvers as osv
+    from oracle.liouvillian import OracleHEOM
+    from paper_2306_07522_amd import workloads as wl
+    cfg = {"siam_tier2": lambda: wl.siam(n_max=2), "siam_tier3": lambda: wl.siam(n_max=3),
+           "two_orbital_tier2": lambda: wl.two_orbital_anderson(n_max=2)}[which]()
+    om = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), cfg["m_max"], cfg["n_max"])
+    M = om.assemble()
+    t0 = time.perf_counter()
+    osv.steady_state(M, om.d)
+    print(json.dumps({"unknowns": int(M.shape[0]), "seconds": time.perf_counter() - t0}), flush=True)
+
+
+def _superlu_bounded(which, limit):
+    """SuperLU stationary state in a fresh interpreter (no GPU use), stopped
+    after `limit` seconds: sparse LU fill on these hierarchies grows much
+    faster than the hierarchy."""
+    import subprocess
+    code = f"import sys; sys.path.insert(0, {ROOT!r}); import bench; bench.superlu_child_main({which!r})"
+    try:
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=limit)
+    except subprocess.TimeoutExpired:
+        return {"finished": False, "limit_s": limit}
+    try:
+        rec = json.loads(r.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return {"finished": False, "error": r.stderr[-300:]}
+    return {"finished": True, "unknowns": rec["unknowns"], "seconds": round(rec["seconds"], 2)}
+
+
+def cpu_baseline(seconds, h=None, solves=True):
     """Oracle apply on the host: the assembled HEOMLS restricted to a seeded
     sample of block rows of the same tier-4 hierarchy, multiplied with the
     C OpenMP CSR SpMV on every host core; throughput is scaled to GB/s with
-    the same per-ADO algorithmic bytes as the GPU."""
+    the same per-ADO algorithmic bytes as the GPU.  With h (the library's
+    tier-4 hierarchy) the GPU apply is compared with the oracle on those
+    rows; with solves, the oracle's solvers are timed (scipy GMRES with a
+    Jacobi preconditioner, SuperLU with a time limit) and the GPU's
+    stationary state and density of states are compared with them."""
     import numpy as np
     from oracle import exponents as ox, spmv_c
-    from oracle.liouvillian import OracleHEOM
+    from oracle.liouvillian import OracleHEOM, from_blocks
     from paper_2306_07522_amd import workloads as wl
 
     cfg = wl.two_orbital_anderson()
@@ -669,9 +767,111 @@ def cpu_baseline(seconds):
     d = om.d
     rows_per_s = len(rows) / dt
     gbs = rows_per_s * (2 * d * d * 16) / 1e9
-    return dict(value=gbs, unit="GB/s", cores=spmv_c.threads(), kind="oracle",
-                sample=f"{len(rows)} seeded block rows of the 213,053-ADO tier-4 HEOMLS (CSR, {A.nnz} nonzeros), "
-                       f"C OpenMP SpMV, {n} reps in {seconds:.0f} s; GB/s = rows/s x 2 d^2 x 16 B")
+    out = dict(value=gbs, unit="GB/s", cores=spmv_c.threads(), kind="oracle",
+               sample=f"{len(rows)} seeded block rows of the 213,053-ADO tier-4 HEOMLS (CSR, {A.nnz} nonzeros), "
+                      f"C OpenMP SpMV, {n} reps in {seconds:.0f} s; GB/s = rows/s x 2 d^2 x 16 B",
+               cpu=_cpu_info())
+    if h is not None:
+        out["errors_vs_oracle"] = _apply_errors(om, h, A, rows)
+    if solves:
+        out["solves"] = _solve_baselines()
+    return out
+
+
+def _apply_errors(om, h, A, rows):
+    """Relative l2 error of the GPU apply (FP64 and FP32) on the oracle's
+    sampled block rows, same seeded input."""
+    import numpy as np
+    import torch
+    from oracle.liouvillian import from_blocks
+    perm = _oracle_perm(om, h)
+    rng = np.random.default_rng(11)
+    xl = rng.standard_normal((h.N, h.d, h.d)) + 1j * rng.standard_normal((h.N, h.d, h.d))
+    res = {}
+    for name, dt in (("fp64", np.complex128), ("fp32", np.complex64)):
+        xin = xl.astype(dt)
+        y = h.apply(torch.from_numpy(xin).cuda()).cpu().numpy().astype(np.complex128)
+        xo = xin.astype(np.complex128)[perm]
+        yo = (A @ from_blocks(xo)).reshape(len(rows), h.d, h.d).transpose(0, 2, 1)
+        yg = y[perm[rows]]
+        res[f"two_orbital_tier4_apply_{name}_rows"] = float(np.linalg.norm(yg - yo) / np.linalg.norm(yo))
+    res["rows_sampled"] = int(len(rows))
+    return res
+
+
+def _solve_baselines():
+    """CPU solve times of the oracle (bounded) and the GPU results' errors
+    against the oracle's own solves."""
+    import numpy as np
+    import scipy.sparse as sparse
+    from oracle import exponents as ox, solvers as osv
+    from oracle.liouvillian import OracleHEOM, from_blocks
+    from paper_2306_07522_amd import api, workloads as wl
+    res = {"gmres": "scipy.sparse.linalg.gmres, restart 30, Jacobi (diagonal) preconditioner; "
+                    "callback residual = relative preconditioned residual"}
+    # single-impurity Anderson model, tier 3 (10,701 ADOs, 171,216 unknowns):
+    # stationary state to 1e-8 (timed) and on to 1e-10 (reference)
+    cfg = wl.siam()
+    oe = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), cfg["m_max"], cfg["n_max"], parity=+1)
+    Me = oe.assemble()
+    B = osv.bordered_matrix(Me, oe.d).tocsr()
+    b = np.zeros(B.shape[0], dtype=np.complex128)
+    b[0] = 1.0
+    xs, rec = osv.gmres_jacobi_timed(B, b, tol=1e-10, mark=1e-8, max_seconds=60)
+    res["siam_tier3_steady_cpu"] = {"unknowns": int(B.shape[0]), "seconds_to_1e-8": rec["mark_seconds"],
+                                    "iterations_to_1e-8": rec["mark_iteration"], "seconds_to_1e-10": rec["seconds"],
+                                    "iterations": rec["iterations"], "converged": rec["info"] == 0}
+    he = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=+1)
+    ho = api.Hierarchy(cfg["H"], cfg["baths"], cfg["m_max"], cfg["n_max"], parity=-1)
+    xg, rep = api.steady_state(he, tol=1e-11, restart=60, max_iter=20000)
+    perm = _oracle_perm(oe, he)
+    xg_o = from_blocks(xg.cpu().numpy()[perm])
+    err = {"siam_tier3_steady_oracle_residual": float(np.linalg.norm(B @ xg_o - b) / np.linalg.norm(b))}
+    if xs is not None and rec["info"] == 0:
+        err["siam_tier3_steady_vs_cpu_gmres_1e-10"] = float(np.linalg.norm(xg_o - xs) / np.linalg.norm(xs))
+    # density of states at one frequency: two shifted odd-parity solves
+    oo = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), cfg["m_max"], cfg["n_max"], parity=-1)
+    Mo = oo.assemble().tocsr()
+    dop = cfg["dops"][0]
+    w = [0.0]
+    tcpu = {"s": 0.0, "iters": 0, "ok": True}
+
+    def gm(Ash, rhs):
+        z, r = osv.gmres_jacobi_timed(sparse.csr_matrix(Ash), rhs, tol=1e-10, mark=1e-8, max_seconds=60)
+        tcpu["s"] += r["seconds"]
+        tcpu["iters"] += r["iterations"]
+        tcpu["ok"] = tcpu["ok"] and r["info"] == 0
+        return z if z is not None else np.zeros_like(rhs)
+
+    if xs is not None:
+        A_cpu = osv.dos(Mo, xs, dop, w, oo.N, oo.d, solve=gm)
+        res["siam_tier3_dos_cpu"] = {"omegas": w, "seconds": round(tcpu["s"], 2), "iterations": tcpu["iters"],
+                                     "converged": tcpu["ok"]}
+        A_gpu, _ = api.spectrum(he, ho, xg, dop, np.array(w), kind="dos", tol=1e-11)
+        err["siam_tier3_dos_abs_vs_cpu_gmres_1e-10"] = float(np.abs(A_gpu - A_cpu).max())
+        err["siam_tier3_dos_value"] = float(A_cpu[0])
+    he.close()
+    ho.close()
+    # two-orbital model, tier 3 (18,473 ADOs, 4.7 M unknowns): iteration cost
+    cfg = wl.two_orbital_anderson(n_max=3)
+    o3 = OracleHEOM(cfg["H"], ox.exponent_records(cfg["baths"]), cfg["m_max"], cfg["n_max"], parity=+1)
+    t0 = time.perf_counter()
+    B3 = osv.bordered_matrix(o3.assemble(), o3.d).tocsr()
+    t_asm = time.perf_counter() - t0
+    b3 = np.zeros(B3.shape[0], dtype=np.complex128)
+    b3[0] = 1.0
+    _, r3 = osv.gmres_jacobi_timed(B3, b3, tol=1e-8, max_seconds=15)
+    res["two_orbital_tier3_steady_cpu_sample"] = {
+        "unknowns": int(B3.shape[0]), "assembly_s": round(t_asm, 2), "iterations": r3["iterations"],
+        "seconds": round(r3["seconds"], 2), "s_per_iteration": round(r3["seconds"] / max(r3["iterations"], 1), 3),
+        "residual_reached": r3["last_residual"], "stopped_at_time_limit": r3["info"] is None}
+    del B3
+    # SuperLU with a time limit
+    res["superlu_steady"] = {"siam_tier2": _superlu_bounded("siam_tier2", 30),
+                             "siam_tier3": _superlu_bounded("siam_tier3", 20),
+                             "two_orbital_tier2": _superlu_bounded("two_orbital_tier2", 20)}
+    res["errors_vs_oracle"] = err
+    return res
 
 
 def main():
@@ -715,9 +915,13 @@ def main():
                                                          args.tiled)
     _progress(f"apply in {out['apply_other_precision']['precision']}: "
               f"{out['apply_other_precision']['kernel_ms_avg']:.3f} ms average kernel time")
+    from paper_2306_07522_amd import api as hapi, workloads as hwl
+    out["cavity_multi_rhs_apply"] = multi_rhs_apply_bench(hapi, hwl)
+    _progress("cavity multi-RHS apply: " + ", ".join(
+        f"R={k} {v['gbs_algorithmic']} GB/s" for k, v in out["cavity_multi_rhs_apply"]["widths"].items()))
     if not args.no_cpu:
         _progress("oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, h=h, solves=args.solves != "none")
         _progress(f"oracle CPU baseline: {out['cpu_baseline']['value']:.3f} GB/s")
     if args.solves != "none":
         del r

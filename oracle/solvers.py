@@ -67,20 +67,25 @@ def rk4_driven(M0, drives, f, x0, t0, dt, n_steps):
 
 def bordered_matrix(M, d):
     """Replace the row of element (0,0) of ADO 0 by the trace row."""
-    M = sp.lil_matrix(M)
-    M.rows[0] = []
-    M.data[0] = []
-    for i in range(d):
-        M[0, i + i * d] = 1.0       # column-stacked index of rho_0[i, i]
-    return M.tocsc()
+    M = sp.csr_matrix(M, dtype=np.complex128, copy=True)
+    M.data[M.indptr[0]:M.indptr[1]] = 0.0   # drop row 0
+    M.eliminate_zeros()
+    cols = [i + i * d for i in range(d)]    # column-stacked index of rho_0[i, i]
+    trace_row = sp.csr_matrix((np.ones(d, dtype=np.complex128), ([0] * d, cols)), shape=M.shape)
+    return (M + trace_row).tocsc()
 
 
-def steady_state(M, d):
+def _splu_solve(A, b):
+    return spla.splu(sp.csc_matrix(A)).solve(b)
+
+
+def steady_state(M, d, solve=None):
+    """Stationary state: B x = e_0 with the bordered matrix B.  solve(A, b)
+    is the linear solver, sparse LU by default."""
     B = bordered_matrix(M, d)
     b = np.zeros(M.shape[0], dtype=np.complex128)
     b[0] = 1.0
-    lu = spla.splu(B)
-    return lu.solve(b)
+    return (solve or _splu_solve)(B, b)
 
 
 def left_multiply_all(x, op, N, d):
@@ -89,29 +94,33 @@ def left_multiply_all(x, op, N, d):
     return from_blocks(np.einsum("ik,akj->aij", op, blocks))
 
 
-def dos(M_odd, x_ss, dop, omegas, N, d):
-    """Density of states A(w) of the fermionic operator d (odd-parity M)."""
+def dos(M_odd, x_ss, dop, omegas, N, d, solve=None):
+    """Density of states A(w) of the fermionic operator d (odd-parity M).
+    solve(A, b) is the linear solver, sparse LU by default."""
+    solve = solve or _splu_solve
     dd = dop.conj().T
     b_plus = left_multiply_all(x_ss, dd, N, d)
     b_minus = left_multiply_all(x_ss, dop, N, d)
     I = sp.identity(M_odd.shape[0], format="csc", dtype=np.complex128)
     out = []
     for w in omegas:
-        xp = spla.splu((M_odd + 1j * w * I).tocsc()).solve(b_plus)
-        xm = spla.splu((M_odd - 1j * w * I).tocsc()).solve(b_minus)
+        xp = solve(M_odd + 1j * w * I, b_plus)
+        xm = solve(M_odd - 1j * w * I, b_minus)
         r0p = xp[: d * d].reshape(d, d, order="F")
         r0m = xm[: d * d].reshape(d, d, order="F")
         out.append(-(np.trace(dop @ r0p) + np.trace(dd @ r0m)).real / np.pi)
     return np.array(out)
 
 
-def psd(M_even, x_ss, aop, omegas, N, d):
-    """Power spectral density S(w) of the bosonic operator a (even M)."""
+def psd(M_even, x_ss, aop, omegas, N, d, solve=None):
+    """Power spectral density S(w) of the bosonic operator a (even M).
+    solve(A, b) is the linear solver, sparse LU by default."""
+    solve = solve or _splu_solve
     b = left_multiply_all(x_ss, aop, N, d)
     I = sp.identity(M_even.shape[0], format="csc", dtype=np.complex128)
     out = []
     for w in omegas:
-        x = spla.splu((M_even - 1j * w * I).tocsc()).solve(b)
+        x = solve(M_even - 1j * w * I, b)
         r0 = x[: d * d].reshape(d, d, order="F")
         out.append(-(np.trace(aop.conj().T @ r0)).real / np.pi)
     return np.array(out)
@@ -131,3 +140,40 @@ def gmres_jacobi(A, b, tol=1e-8, restart=30, maxiter=2000):
     x, info = spla.gmres(A, b, rtol=tol, restart=restart, maxiter=maxiter, M=Pinv, callback=cb,
                          callback_type="pr_norm")
     return x, info, it[0]
+
+
+class _OutOfTime(Exception):
+    pass
+
+
+def gmres_jacobi_timed(A, b, tol=1e-10, mark=1e-8, restart=30, maxiter=100000, max_seconds=None):
+    """gmres_jacobi with a clock: the returned record holds the iteration and
+    the elapsed seconds at which the relative preconditioned residual first
+    fell to `mark`, and the total.  With max_seconds the solve stops once
+    that much time has passed (x is then None): a bounded sample of the
+    iteration cost."""
+    import time
+    dg = A.diagonal().copy()
+    dg[np.abs(dg) < 1e-300] = 1.0
+    Pinv = spla.LinearOperator(A.shape, matvec=lambda v: v / dg, dtype=np.complex128)
+    rec = {"iterations": 0, "mark": mark, "mark_iteration": None, "mark_seconds": None, "last_residual": None}
+    t0 = time.perf_counter()
+
+    def cb(r):
+        rec["iterations"] += 1
+        rec["last_residual"] = float(r)
+        el = time.perf_counter() - t0
+        if rec["mark_iteration"] is None and r <= mark:
+            rec["mark_iteration"], rec["mark_seconds"] = rec["iterations"], el
+        if max_seconds is not None and el > max_seconds:
+            raise _OutOfTime
+
+    x, info = None, None
+    try:
+        x, info = spla.gmres(A, b, rtol=tol, restart=restart, maxiter=maxiter, M=Pinv, callback=cb,
+                             callback_type="pr_norm")
+    except _OutOfTime:
+        pass
+    rec["seconds"] = time.perf_counter() - t0
+    rec["info"] = info
+    return x, rec

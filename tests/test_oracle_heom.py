@@ -10,6 +10,7 @@ import itertools
 import math
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 import scipy.sparse.linalg as spla
 
@@ -176,6 +177,44 @@ def test_resonant_level_dos_closed_form():
         A = osv.dos(mo.assemble(), x_ss, cfg["dops"][0], omegas, me.N, me.d)
         exact = _dos_closed_form(omegas, eps, 2.0, 10.0, (1.0, -1.0))
         assert np.abs(A - exact).max() < 1e-10, (A, exact)
+
+
+def test_iterative_solver_path_matches_closed_form():
+    """The CPU timing path (scipy GMRES with a Jacobi preconditioner, timed)
+    solves the same systems: the U = 0 density of states from its steady
+    state and shifted solves matches the closed form, and the clock records
+    the 1e-8 crossing before the end."""
+    cfg = wl.resonant_level(eps=0.3, n_exp=3, n_max=2)
+    me, mo = _heom(cfg, +1), _heom(cfg, -1)
+    recs = []
+
+    def gm(A, b):
+        z, rec = osv.gmres_jacobi_timed(sp.csr_matrix(A), b, tol=1e-13, mark=1e-8)
+        recs.append(rec)
+        return z
+
+    x = osv.steady_state(me.assemble(), me.d, solve=gm)
+    om = np.array([-2.0, 0.0, 1.3])
+    A = osv.dos(mo.assemble(), x, cfg["dops"][0], om, me.N, me.d, solve=gm)
+    exact = _dos_closed_form(om, 0.3, 2.0, 10.0, (1.0, -1.0))
+    assert np.abs(A - exact).max() < 1e-9, (A, exact)
+    for rec in recs:
+        assert rec["info"] == 0
+        assert rec["mark_iteration"] is not None and rec["mark_iteration"] <= rec["iterations"]
+        assert rec["mark_seconds"] <= rec["seconds"]
+
+
+def test_bordered_matrix_rows():
+    """The bordered system: row 0 is the trace row (ones on the diagonal
+    elements of rho_0 in column-stacked order), every other row is M's."""
+    m = _heom(wl.siam(n_max=1))
+    M = m.assemble().tocsr()
+    B = osv.bordered_matrix(M, m.d).tocsr()
+    row0 = B[0].toarray().ravel()
+    want = np.zeros(M.shape[1], dtype=complex)
+    want[[i + i * m.d for i in range(m.d)]] = 1.0
+    assert np.array_equal(row0, want)
+    assert abs(B[1:] - M[1:]).max() == 0
 
 
 def test_resonant_level_dos_closes_at_tier2():
