@@ -404,7 +404,7 @@ def batch_benchmark(api, wl):
            "tuner": {"ms_default": round(tune["ms_default"], 4), "ms_best": round(tune["ms_best"], 4),
                      "grid": tune["grid"], "order": tune["order"]},
            "steady": {"seconds": round(tb, 3), "tol": 1e-8, "mode": "fp32_ir", "restart": 30, "max_iter": 2400,
-                      "precond": "block, then none for the instances that miss 1e-8",
+                      "precond": "block; instances that miss 1e-8 again on their own, FP64 block GMRES(240)",
                       "converged": int(sum(conv)),
                       "converged_anderson": int(sum(c for c, f in zip(conv, fam) if f == "anderson")),
                       "converged_spin_boson": int(sum(c for c, f in zip(conv, fam) if f == "spin_boson")),

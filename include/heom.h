@@ -563,10 +563,13 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
  * true residual; seconds and applies are batch totals).  Returns
  * HEOM_ERR_NOT_CONVERGED if any instance misses the tolerance.
  * opts.precond: HEOM_PREC_NONE, HEOM_PREC_JACOBI or HEOM_PREC_BLOCK; with
- * opts.fallback = 1 the instances that miss the tolerance are solved again
- * from zero, with Jacobi after an unpreconditioned pass and without a
- * preconditioner otherwise, and their reports carry fell_back = 1
- * (iterations add up). */
+ * opts.fallback = 1 each instance that misses the tolerance is solved again
+ * from zero on its own with heom_steady: FP64, block preconditioner, restart
+ * 8 x opts.restart (at least 240, at most 1000, fewer when the instance's
+ * Krylov basis would exceed 2 GiB), same tol and max_iter.  Its report
+ * then carries fell_back = 1 (iterations add up).  The workspace size
+ * accounts for that pass; the first such solve on an instance uploads the
+ * instance's own device tables. */
 heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,
                               int32_t use_graph, void *ws, size_t ws_bytes, void *stream);
 

@@ -1175,16 +1175,46 @@ heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev,
   return guarded([&] { return heom_batch_tune_body(b, precision, x_dev, y_dev, reps, ms_default, ms_best, stream); });
 }
 
+// The fallback pass re-solves an instance that missed the tolerance on its
+// own: FP64 GMRES with the block preconditioner and a restart length of
+// 8 x the batch's (at least 240, at most 1000), cut so that the instance's
+// Krylov basis stays within kFallbackBasisBytes.
+static constexpr size_t kFallbackBasisBytes = (size_t)2 << 30;
+
+static heom_solver_opts fallback_opts(const heom_batch &b, int q, const heom_solver_opts &o) {
+  heom_solver_opts f = o;
+  f.mode = HEOM_SOLVE_FP64;
+  f.precond = HEOM_PREC_BLOCK;
+  f.deflate = 0;
+  f.use_x0 = 0;
+  f.fallback = 0;
+  f.nn = nullptr;
+  const size_t vec = (size_t)(b.off[q + 1] - b.off[q]) * 16;
+  const int64_t cap = (int64_t)(kFallbackBasisBytes / std::max<size_t>(2 * vec, 1));
+  f.restart = (int)std::max<int64_t>(o.restart, std::min<int64_t>({std::max(8 * o.restart, 240), 1000, cap}));
+  return f;
+}
+
 heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opts *o, size_t *bytes) {
   if (!b || !bytes) return fail(HEOM_ERR_ARG, "batch_workspace_size: NULL argument");
   heom_solver_opts d;
   if (!o) { heom_default_opts(&d); o = &d; }
   const size_t v64 = (size_t)b->n * 16, v32 = (size_t)b->n * 8;
   size_t need = v64 + 4096;  // right-hand side
-  // a preconditioned pass (first choice, or the fallback pass) keeps the Z basis
-  const bool jac = o->precond != HEOM_PREC_NONE || o->fallback;
-  if (o->mode == HEOM_SOLVE_FP32_IR) need += v64 + 2 * v32 + BatchGmres<float>::bytes(*b, o->restart, jac);
-  else need += BatchGmres<double>::bytes(*b, o->restart, jac);
+  const bool jac = o->precond != HEOM_PREC_NONE;
+  size_t pass1 = 0;
+  if (o->mode == HEOM_SOLVE_FP32_IR) pass1 = v64 + 2 * v32 + BatchGmres<float>::bytes(*b, o->restart, jac);
+  else pass1 = BatchGmres<double>::bytes(*b, o->restart, jac);
+  size_t pass2 = 0;
+  if (o->fallback) {
+    for (int q = 0; q < b->S; ++q) {
+      const heom_solver_opts f = fallback_opts(*b, q, *o);
+      size_t w = 0;
+      HEOM_TRY(heom_workspace_size(b->inst[q], HEOM_OP_STEADY, &f, 0, &w));
+      pass2 = std::max(pass2, w);
+    }
+  }
+  need += std::max(pass1, pass2);
   need += (size_t)b->S * sizeof(double) + 256;
   *bytes = need + 8 * 256;
   return HEOM_OK;
@@ -1198,8 +1228,6 @@ static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom
   if (o->precond != HEOM_PREC_JACOBI && o->precond != HEOM_PREC_NONE && o->precond != HEOM_PREC_BLOCK)
     return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: Jacobi, block or no preconditioning only");
   const int prec1 = o->precond;
-  // the fallback pass: Jacobi after an unpreconditioned pass, none otherwise
-  const int prec2 = prec1 == HEOM_PREC_NONE ? HEOM_PREC_JACOBI : HEOM_PREC_NONE;
   if (o->mode != HEOM_SOLVE_FP64 && o->mode != HEOM_SOLVE_FP32_IR) return fail(HEOM_ERR_ARG, "batch_steady: mode");
   if (o->deflate != 0) return fail(HEOM_ERR_UNSUPPORTED, "batch_steady: no deflated restarting");
   for (heom_hier *h : b->inst)
@@ -1291,24 +1319,30 @@ static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom
   HEOM_TRY(run_pass(prec1, std::vector<char>(S, 1), o->use_x0 != 0));
   std::vector<char> fell(S, 0);
   if (o->fallback) {
-    // instances that missed the tolerance: again from zero with the other choice
-    std::vector<char> again(S, 0);
-    bool any = false;
-    std::vector<double> keep(S);
+    // Instances that missed the tolerance: each again from zero on its own,
+    // FP64 with the block preconditioner and a longer restart (the batch
+    // pass keeps one restart length for all; the hard instances are those
+    // whose GMRES(m) stagnates at that length).
+    HEOM_HIP_CHECK(hipStreamSynchronize(s));
+    std::vector<int> ones(S, 1);
+    HEOM_HIP_CHECK(hipMemcpy(b->active, ones.data(), sizeof(int) * S, hipMemcpyHostToDevice));
+    const size_t off_ws = (sizeof(double2) * (size_t)n + 255) & ~(size_t)255;  // after rhs
     for (int q = 0; q < S; ++q) {
-      again[q] = !conv[q];
-      any = any || again[q];
-      keep[q] = conv[q] ? 1.0 : 0.0;
-    }
-    if (any) {
-      // (kd is consumed before the second pass reuses this part of the workspace)
-      double *kd = (double *)arena.take(sizeof(double) * S);
-      if (!kd) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small");
-      HEOM_HIP_CHECK(hipMemcpyAsync(kd, keep.data(), sizeof(double) * S, hipMemcpyHostToDevice, s));
-      HEOM_TRY((seg_scale<double, double>(*b, x_dev, kd, x_dev, s)));
-      HEOM_HIP_CHECK(hipStreamSynchronize(s));
-      fell = again;
-      HEOM_TRY(run_pass(prec2, again, false));
+      if (conv[q]) continue;
+      const heom_solver_opts f = fallback_opts(*b, q, *o);
+      size_t w = 0;
+      HEOM_TRY(heom_workspace_size(b->inst[q], HEOM_OP_STEADY, &f, 0, &w));
+      if (off_ws + w > ws_bytes) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small for the fallback pass");
+      heom_solver_report rq;
+      std::memset(&rq, 0, sizeof(rq));
+      const heom_status st = heom_steady(b->inst[q], (double2 *)x_dev + b->off[q], &f, &rq,
+                                         (unsigned char *)ws + off_ws, ws_bytes - off_ws, s);
+      if (st != HEOM_OK && st != HEOM_ERR_NOT_CONVERGED) return st;
+      fell[q] = 1;
+      iters[q] += rq.iterations;
+      applies += rq.applies;
+      res[q] = rq.true_residual;
+      conv[q] = st == HEOM_OK;
     }
   }
   HEOM_HIP_CHECK(hipStreamSynchronize(s));

@@ -107,6 +107,64 @@ def test_batch_apply_matches_oracle():
         assert np.abs(ys[perm] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
 
 
+def _pick_d16(n, max_n_ado):
+    """The first n instances with d = 16 and at most max_n_ado ADOs."""
+    from paper_2306_07522_amd import api
+    out = []
+    for c in _instances():
+        if c["d"] != 16:
+            continue
+        h = api.Hierarchy(c["H"], c["baths"], c["m_max"], c["n_max"], parity_op=c.get("parity_op"))
+        if h.N <= max_n_ado:
+            out.append(c)
+        h.close()
+        if len(out) == n:
+            break
+    return out
+
+
+def test_batch_apply_with_d16_matches_oracle():
+    """d = 16 instances (dense random H, both families) in one batch with
+    smaller ones, FP64 and FP32, against the oracle's assembled HEOMLS."""
+    torch = _torch()
+    d16 = _pick_d16(4, max_n_ado=60)
+    assert len(d16) == 4 and {c["family"] for c in d16} == {"spin_boson", "anderson"}
+    cfgs = d16 + [c for c in _pick(30, max_n_ado=200) if c["d"] <= 8][:3]
+    hs, b = _build(cfgs)
+    rng = np.random.default_rng(6)
+    xs = [wl.random_vector(rng, h.N, h.d) for h in hs]
+    x = torch.from_numpy(np.concatenate([v.reshape(-1) for v in xs])).cuda()
+    y = b.apply(x).cpu().numpy()
+    y32 = b.apply(x.to(torch.complex64)).cpu().numpy().astype(np.complex128)
+    for s, (c, h) in enumerate(zip(cfgs, hs)):
+        om = oracle_model(c)
+        perm = oracle_to_library_perm(om, h)
+        M = om.assemble()
+        ref = to_blocks(M @ from_blocks(xs[s][perm]), om.N, om.d)
+        ys = y[b.offsets[s]: b.offsets[s + 1]].reshape(h.N, h.d, h.d)[perm]
+        assert np.linalg.norm(ys - ref) <= 1e-12 * np.linalg.norm(ref), (s, c["d"])
+        x32 = xs[s].astype(np.complex64).astype(np.complex128)
+        ref32 = to_blocks(M @ from_blocks(x32[perm]), om.N, om.d)
+        ys32 = y32[b.offsets[s]: b.offsets[s + 1]].reshape(h.N, h.d, h.d)[perm]
+        assert np.linalg.norm(ys32 - ref32) <= 1e-5 * np.linalg.norm(ref32), (s, c["d"])
+
+
+def test_batch_steady_with_d16_matches_oracle_direct_solve():
+    """Stationary states of d = 16 instances solved in a batch (FP64 block
+    preconditioner) against the oracle's sparse LU."""
+    torch = _torch()
+    cfgs = _pick_d16(3, max_n_ado=40)
+    hs, b = _build(cfgs)
+    x, reps = b.steady_state(tol=1e-11, restart=60, max_iter=6000, precond="block", fallback=1)
+    assert all(r["status"] == 0 for r in reps), reps
+    for s, (c, h) in enumerate(zip(cfgs, hs)):
+        om = oracle_model(c)
+        perm = oracle_to_library_perm(om, h)
+        ref = to_blocks(oracle_steady(om.assemble(), om.d), om.N, om.d)
+        xs = x[b.offsets[s]: b.offsets[s + 1]].cpu().numpy().reshape(h.N, h.d, h.d)[perm]
+        assert np.abs(xs - ref).max() <= 1e-8 * np.abs(ref).max(), (s, np.abs(xs - ref).max())
+
+
 @pytest.mark.parametrize("mode", ["fp64", "fp32_ir"])
 def test_batch_steady_matches_single_solves(mode):
     torch = _torch()
@@ -232,12 +290,14 @@ def test_autotuner_keeps_results():
 
 def test_full_batch_of_512_instances():
     """The full seeded batch (512 instances, d in {2,4,8,16}, tiers 2-6, 3-12
-    exponents) in FP32 with FP64 refinement, the block preconditioner first
-    and no preconditioner for the instances that miss 1e-8.  The test checks
-    that every converged report is true (plain FP64 single-instance apply on
-    a sample), that both families converge, and that nearly all of the
-    batch does (without the block preconditioner most weakly damped
-    spin-boson instances stall)."""
+    exponents) in FP32 with FP64 refinement and the block preconditioner;
+    the instances that miss 1e-8 are solved again on their own in FP64 with
+    a longer restart.  Every converged report must be true (plain FP64
+    single-instance apply on a sample).  All instances but one converge:
+    instance 53 (Anderson, d = 4, tier 5, lead exponents with amplitudes
+    near 125 that nearly cancel) stalls at a true residual of about 1.5e-8
+    in every solver and precision tried, at the rounding floor of its FP64
+    residual (the oracle's sparse LU solution leaves a larger one)."""
     torch = _torch()
     from paper_2306_07522_amd import api
     cfgs = _instances()
@@ -247,7 +307,9 @@ def test_full_batch_of_512_instances():
                              allow_not_converged=True)
     conv = np.array([r["status"] == 0 for r in reps])
     fam = np.array([c["family"] for c in cfgs])
-    assert conv.sum() >= 490, conv.sum()
+    assert conv.sum() >= 511, (conv.sum(), np.flatnonzero(~conv))
+    assert set(np.flatnonzero(~conv)) <= {53}
+    assert max(r["true_residual"] for r in reps) < 3e-8
     assert conv[fam == "anderson"].mean() >= 0.99
     assert conv[fam == "spin_boson"].mean() >= 0.95
     for r in reps:
