@@ -67,7 +67,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--solves", choices=["all", "siam", "none", "two_orbital_dr", "two_orbital_dos", "two_orbital_nn",
-                                             "cavity", "batch", "conductance", "propagation"],
+                                             "cavity", "batch", "batch_apply", "conductance", "propagation"],
                    default="all",
                    help="solve timings: all legs, siam only, none, or one leg (the two-orbital stationary state "
                         "with GMRES-DR, the cavity stationary state and PSD, the 512-instance batch) for profiling")
@@ -366,7 +366,7 @@ def dos_benchmark(api, wl, cfg, restart=40, sample=64, thick=(8, 3)):
     return out
 
 
-def batch_benchmark(api, wl):
+def batch_benchmark(api, wl, steady=True):
     """512 seeded uneven instances (spin-boson / Anderson, d in {2,4,8,16},
     tiers 2-6, 3-12 exponents): one batched apply against 512 single
     launches, the autotuned launch, and every stationary state in FP32 with
@@ -391,25 +391,36 @@ def batch_benchmark(api, wl):
     edges = sum(h.info.n_edges for h in hs)
     nbytes = 2 * b.n * 8 + 8 * (sum(h.N for h in hs) + len(hs)) + 8 * edges + 8 * sum(h.N for h in hs)
     del x, y, xs, ys
-    _progress(f"batch apply: {t_batch / reps * 1e3:.3f} ms vs {t_single / reps * 1e3:.3f} ms for 512 single launches")
+    _progress(f"batch apply: {t_batch / reps * 1e3:.3f} ms vs {t_single / reps * 1e3:.3f} ms for 512 single launches "
+              f"(tuned {tune['ms_best']:.3f} ms against {tune['ms_default']:.3f} ms for the default shape)")
+    out = {"n_instances": len(hs), "n_elements": b.n, "fp32_vector_mb": round(b.n * 8 / 1e6, 1),
+           "apply_ms_batched": round(t_batch / reps * 1e3, 4), "apply_ms_512_single_launches": round(t_single / reps * 1e3, 4),
+           "apply_gbs_batched": round(nbytes / (t_batch / reps) / 1e9, 2),
+           "apply_bytes": nbytes,
+           "tuner": {"ms_default": round(tune["ms_default"], 4), "ms_best": round(tune["ms_best"], 4),
+                     "shape": tune["shape"]}}
+    if not steady:
+        b.close()
+        for h in hs:
+            h.close()
+        return out
     (xb, rb), tb = _timed(lambda: b.steady_state(tol=1e-8, restart=30, max_iter=2400, mode="fp32_ir", precond="block",
                                                  fallback=1, use_graph=True, allow_not_converged=True))
     del xb
     conv = [r["status"] == 0 for r in rb]
     fam = [c["family"] for c in cfgs]
     _progress(f"batch steady: {sum(conv)} of {len(conv)} converged in {tb:.1f} s")
-    out = {"n_instances": len(hs), "n_elements": b.n, "fp32_vector_mb": round(b.n * 8 / 1e6, 1),
-           "apply_ms_batched": round(t_batch / reps * 1e3, 4), "apply_ms_512_single_launches": round(t_single / reps * 1e3, 4),
-           "apply_gbs_batched": round(nbytes / (t_batch / reps) / 1e9, 2),
-           "tuner": {"ms_default": round(tune["ms_default"], 4), "ms_best": round(tune["ms_best"], 4),
-                     "grid": tune["grid"], "order": tune["order"]},
-           "steady": {"seconds": round(tb, 3), "tol": 1e-8, "mode": "fp32_ir", "restart": 30, "max_iter": 2400,
+    out.update({"steady": {"seconds": round(tb, 3), "tol": 1e-8, "mode": "fp32_ir", "restart": 30, "max_iter": 2400,
                       "precond": "block; instances that miss 1e-8 again on their own, FP64 block GMRES(240)",
                       "converged": int(sum(conv)),
                       "converged_anderson": int(sum(c for c, f in zip(conv, fam) if f == "anderson")),
                       "converged_spin_boson": int(sum(c for c, f in zip(conv, fam) if f == "spin_boson")),
-                      "fell_back_to_none": int(sum(r["fell_back"] for r in rb)),
-                      "max_iterations": int(max(r["iterations"] for r in rb))}}
+                      "fell_back": int(sum(r["fell_back"] for r in rb)),
+                      "not_converged": [{"instance": int(i), "family": cfgs[i]["family"], "d": cfgs[i]["d"],
+                                         "m_max": cfgs[i]["m_max"], "n_max": cfgs[i]["n_max"],
+                                         "true_residual": rb[i]["true_residual"]}
+                                        for i in range(len(rb)) if rb[i]["status"] != 0],
+                      "max_iterations": int(max(r["iterations"] for r in rb))}})
     b.close()
     for h in hs:
         h.close()
@@ -649,6 +660,8 @@ def solve_benchmarks(which):
         return cavity_spectrum_benchmark(api, wl)
     if which == "batch":
         return {"batch_512_instances": batch_benchmark(api, wl)}
+    if which == "batch_apply":
+        return {"batch_512_instances": batch_benchmark(api, wl, steady=False)}
     if which == "conductance":
         return {"siam_example1_conductance": conductance_benchmark(api, wl)}
     if which == "propagation":

@@ -218,7 +218,10 @@ heom_status heom_apply_steady_operator(heom_hier *h, int32_t precision, const vo
 
 /* Launch plans of the apply (eq:HEOM's terms are the same in every plan;
  * only the order of the floating-point additions differs).
- *  HEOM_PLAN_AUTO  the default of every other entry point (the pull plan);
+ *  HEOM_PLAN_AUTO  the default of every other entry point: the pull plan,
+ *                  as HEOM_PLAN_PULL_MFMA when d = 16, one right-hand side
+ *                  and H has at least 6 off-diagonal entries in some row or
+ *                  column (the measured cut-over);
  *  HEOM_PLAN_PULL  one launch: every ADO gathers all its neighbour blocks;
  *  HEOM_PLAN_SLAB  three launches: the lower tiers and the top tier's own
  *                  rows, then two launches over label slabs of the top two
@@ -228,8 +231,14 @@ heom_status heom_apply_steady_operator(heom_hier *h, int32_t precision, const vo
  *                  plan where measured (two-orbital model, d = 16).  Built for
  *                  purely fermionic hierarchies without pruning, n_max >= 3,
  *                  d = 8 or 16, one right-hand side; HEOM_ERR_UNSUPPORTED
- *                  otherwise. */
-enum { HEOM_PLAN_AUTO = 0, HEOM_PLAN_PULL = 1, HEOM_PLAN_SLAB = 2 };
+ *                  otherwise.
+ *  HEOM_PLAN_PULL_MFMA  the pull plan with the H terms of every ADO's own
+ *                  block (-i[H, rho_a] without H's diagonal) computed as
+ *                  dense 16 x 16 complex products on the matrix cores
+ *                  (16 x 16 x 4 MFMA, FP64 or FP32 as the vectors) instead
+ *                  of the sparse gathers.  d = 16, one right-hand side;
+ *                  HEOM_ERR_UNSUPPORTED otherwise. */
+enum { HEOM_PLAN_AUTO = 0, HEOM_PLAN_PULL = 1, HEOM_PLAN_SLAB = 2, HEOM_PLAN_PULL_MFMA = 3 };
 
 /* Layout of the slab plan, computed on the host without touching the
  * device (the plan itself is uploaded with the other tables on first use):
@@ -535,6 +544,20 @@ void heom_batch_free(heom_batch *b);
  * one block per tile; order 0 = instance-major tiles, 1 = interleaved,
  * costliest instances first). */
 heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_tiles, int32_t *grid, int32_t *order);
+/* The launch shape in use, 8 host ints: tile multiplier of the d <= 4
+ * instances, tile multiplier of the d = 8 / 16 instances (a tile holds
+ * max(4, 256 / d^2) x that many ADOs), wave formulation for d = 8 (1) or
+ * one thread per output element (0), the same for d = 16, persistent grid
+ * (0: one workgroup per tile), tile order (0 instance-major, 1
+ * interleaved), the H terms of each ADO's own block on the matrix cores for
+ * the d = 16 wave instances (1; see HEOM_PLAN_PULL_MFMA) or by sparse
+ * gathers (0), and 1 if the last heom_batch_tune took the shape from its
+ * cache file. */
+heom_status heom_batch_shape(const heom_batch *b, int32_t *shape);
+/* Sets the launch shape (the first seven values of heom_batch_shape; the
+ * multipliers in {1, 2, 4, 8}, the flags in {0, 1}, grid >= 0; else
+ * HEOM_ERR_ARG).  Synchronous (uploads the tile list). */
+heom_status heom_batch_set_shape(heom_batch *b, const int32_t *shape);
 /* y = M x for every instance in one launch (eq:HEOM; border = 1: the
  * bordered stationary-state operator of each instance, see
  * heom_apply_steady_operator).  x, y: device batch vectors of the given
@@ -542,11 +565,20 @@ heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_ti
 heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t border,
                              void *stream);
 /* Autotuner: times heom_batch_apply (reps launches per candidate, after two
- * warm-up launches) over the persistent grid sizes {one block per tile,
- * 2, 4, 8, 16 blocks per CU} and both tile orders, keeps the fastest for all
- * later launches and reports the default and chosen times (ms per apply).
- * x, y: scratch batch vectors of the precision; y is overwritten.
- * Synchronises the stream. */
+ * warm-up launches) over the launch shape of heom_batch_shape -- tile
+ * multipliers {1, 2, 4, 8} for small and for wave-sized instances, wave
+ * formulation or one thread per element for d = 8 and for d = 16, the
+ * persistent grid {one workgroup per tile, 2, 4, 8, 16 per CU}, both tile
+ * orders, and sparse or matrix-core H terms for d = 16 -- by two sweeps of
+ * coordinate descent from the default shape (1, 1, 1, 1, 0, 0, 0).  Keeps the fastest for all later launches (and
+ * for the batch's preconditioners, which walk the same tiles) and reports
+ * the default and chosen times (ms per apply).  With the environment
+ * variable HEOMX_TUNE_CACHE naming a file, a shape stored there for the
+ * same device, precision and instance shapes is used without a search, and
+ * a searched shape is appended to it (text, one line per batch shape).
+ * Shapes differ in the order of floating-point additions, so results agree
+ * to rounding, not bit for bit.  x, y: scratch batch vectors of the
+ * precision; y is overwritten.  Synchronises the stream. */
 heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
                             double *ms_default, double *ms_best, void *stream);
 /* Device workspace bytes for heom_batch_steady with these options. */

@@ -222,7 +222,7 @@ class Hierarchy:
     def apply(self, x, y=None, shift=None, n_rhs=1, stream=None, tiled=None, plan=None):
         """y = (M + shift) x on the GPU.  x: [N][d][d] or [N][d][d][R] tensor.
         shift: complex scalar, or a device tensor of R shifts (per column).
-        plan: None (library default), "pull" or "slab" (heom_apply_plan)."""
+        plan: None (library default), "pull", "slab" or "pull_mfma" (heom_apply_plan)."""
         import torch
         if y is None:
             y = torch.empty_like(x)
@@ -241,7 +241,7 @@ class Hierarchy:
         if shift is not None:
             sh = np.array([complex(shift).real, complex(shift).imag])
         if plan is not None:
-            code = {"auto": 0, "pull": 1, "slab": 2}[plan]
+            code = {"auto": 0, "pull": 1, "slab": 2, "pull_mfma": 3}[plan]
             L.check(self._lib.heom_apply_plan(self._h, prec, _devptr(x), _devptr(y), n_rhs,
                                               _dptr(sh) if sh is not None else None, code, s))
         elif tiled is not None:
@@ -605,7 +605,19 @@ class Batch:
         md, mb = C.c_double(), C.c_double()
         L.check(self._lib.heom_batch_tune(self._h, _precision_of(x), _devptr(x), _devptr(y), int(reps),
                                           C.byref(md), C.byref(mb), _stream_ptr(stream)))
-        return {"ms_default": md.value, "ms_best": mb.value, **self.info()}
+        return {"ms_default": md.value, "ms_best": mb.value, **self.info(), "shape": self.shape()}
+
+    def shape(self):
+        """The launch shape in use (heom_batch_shape)."""
+        v = np.zeros(8, dtype=np.int32)
+        L.check(self._lib.heom_batch_shape(self._h, v.ctypes.data_as(L.i32p)))
+        keys = ("mult_small", "mult_wave", "var8", "var16", "grid", "order", "mfma16", "from_cache")
+        return {k: int(x) for k, x in zip(keys, v)}
+
+    def set_shape(self, mult_small=1, mult_wave=1, var8=1, var16=1, grid=0, order=0, mfma16=0):
+        """Sets the launch shape (heom_batch_set_shape)."""
+        v = np.array([mult_small, mult_wave, var8, var16, grid, order, mfma16], dtype=np.int32)
+        L.check(self._lib.heom_batch_set_shape(self._h, v.ctypes.data_as(L.i32p)))
 
     def steady_state(self, x=None, use_graph=True, stream=None, allow_not_converged=False, **opts):
         """Stationary states of every instance: (FP64 batch vector, list of

@@ -294,6 +294,8 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   P.shifts = (const T2 *)a.shifts;
   P.shift0 = T2{(T)a.shift0.real(), (T)a.shift0.imag()};
   P.border = a.border;
+  P.hoff = dbl ? (const T2 *)D.hoff64 : (const T2 *)D.hoff32;
+  P.hmfma = a.hmfma;
   P.epi = a.epi ? 1 : 0;
   for (int j = 0; j < 4; ++j) {
     P.ev[j] = (const T2 *)a.ev[j];
@@ -358,15 +360,45 @@ static heom_status run_plan(Hier &h, int precision, const ApplyArgs &a, const Pl
   return HEOM_OK;
 }
 
+// Off-diagonal entries of H per row (the compact table's width) from which
+// the matrix-core H terms beat the gathers at d = 16.  Measured on a d = 16
+// spin-boson hierarchy (6,435 ADOs) with banded random H: the MFMA apply
+// takes the same time at every width (61 us FP64, 38 us FP32); the gathers
+// take 58-59 us at 1-2 entries, 62 at 4, 64 at 6 and 70-77 us at 8-15
+// (FP32: 35-36, 38, 39, 44-48 us).
+constexpr int kMfmaMinOffdiag = 6;
+
+// The wave kernel (which carries the matrix-core path) runs for this hierarchy
+static bool mfma_fits(const Hier &h, int precision) {
+  const size_t w = precision == HEOM_FP64 ? 16 : 8;
+  const size_t smem = 4 * (size_t)h.d * h.d * w + h.ell.c_col.size() * (w + 4) + 16 + (size_t)h.d * 16;
+  return smem <= 48 * 1024;
+}
+
 heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int plan, hipStream_t s) {
   HEOM_TRY(check_apply(h, precision, a));
   const bool have_slab = h.dev.slab.built;
   bool slab = false;
   switch (plan) {
-    case HEOM_PLAN_AUTO:  // the pull plan: measured faster than the slab plan on the two-orbital model
+    case HEOM_PLAN_AUTO:
+      // the pull plan (measured faster than the slab plan on the two-orbital
+      // model); its H terms on the matrix cores when d = 16 and H has at
+      // least kMfmaMinOffdiag off-diagonal entries in some row or column
+      if (h.d == 16 && a.n_rhs == 1 && h.ell.c_ns[0] >= kMfmaMinOffdiag && mfma_fits(h, precision))
+        return launch_apply_plan(h, precision, a, HEOM_PLAN_PULL_MFMA, s);
       break;
     case HEOM_PLAN_PULL:
       break;
+    case HEOM_PLAN_PULL_MFMA: {
+      if (h.d != 16 || a.n_rhs != 1 || !mfma_fits(h, precision))
+        return fail(HEOM_ERR_UNSUPPORTED, "apply: the MFMA self group needs d = 16 and one right-hand side");
+      ApplyArgs m = a;
+      m.hmfma = 1;
+      if (m.epi && !h.lind.empty())
+        return fail(HEOM_ERR_UNSUPPORTED, "apply: the epilogue needs the pull plan, one right-hand side, no Lindblad terms");
+      HEOM_TRY(run_plan(h, precision, m, h.dev.base, s));
+      return launch_lindblad(h, precision, m, s);
+    }
     case HEOM_PLAN_SLAB:
       if (!have_slab || a.n_rhs != 1)
         return fail(HEOM_ERR_UNSUPPORTED,

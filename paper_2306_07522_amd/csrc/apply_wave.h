@@ -39,6 +39,9 @@ struct ApplyParams {
   const T2 *shifts;
   T2 shift0;
   int border;
+  // self group on matrix cores (d = 16): H with its diagonal zeroed, row-major
+  const T2 *hoff;
+  int hmfma;
   // epilogue: y = eacc * acc + sum_j ec[j] * ev[j] (ev[j] may alias y)
   int epi;
   const T2 *ev[4];
@@ -177,6 +180,68 @@ __device__ __forceinline__ void op_terms(const ApplyParams<T> &P, int cid, T w, 
   }
 }
 
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mfma_d4 mfma16x16x4(double a, double b, mfma_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma_f4 mfma16x16x4(float a, float b, mfma_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// The H terms of the self group (the first line of eq:HEOM) on the matrix
+// cores, d = 16: acc += cl H' X + cr X H' with H' = H without its diagonal
+// (the diagonal is applied with the decay) and X staged row-major in LDS.
+// Each complex product is four real 16 x 16 x 16 products, four K-steps of
+// the 16 x 16 x 4 MFMA each.  Operand layout of that instruction (both
+// precisions): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of the
+// K-step.  Result: FP64 lane l, register r holds row l / 16 + 4 r, column
+// l % 16 -- the element of slot r in the FP64 lane layout; FP32 holds row
+// 4 (l / 16) + r, column l % 16, which goes through LDS to the lane layout.
+template <typename T>
+__device__ __forceinline__ void self_h_mfma16(const ApplyParams<T> &P, int cid, int lane, typename Cplx<T>::t *X,
+                                              typename Cplx<T>::t (&acc)[WaveShape<16>::EPL]) {
+  using T2 = typename Cplx<T>::t;
+  using V4 = T __attribute__((ext_vector_type(4)));
+  const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
+  const int q = lane >> 4, c = lane & 15;
+  V4 Lr = {0, 0, 0, 0}, Li = {0, 0, 0, 0}, Rr = {0, 0, 0, 0}, Ri = {0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + q;
+    const T2 ha = P.hoff[c * 16 + k];  // A of H' X
+    const T2 hb = P.hoff[k * 16 + c];  // B of X H'
+    const T2 xb = X[k * 16 + c];       // B of H' X
+    const T2 xa = X[c * 16 + k];       // A of X H'
+    Lr = mfma16x16x4(ha.x, xb.x, Lr);
+    Lr = mfma16x16x4(-ha.y, xb.y, Lr);
+    Li = mfma16x16x4(ha.x, xb.y, Li);
+    Li = mfma16x16x4(ha.y, xb.x, Li);
+    Rr = mfma16x16x4(xa.x, hb.x, Rr);
+    Rr = mfma16x16x4(-xa.y, hb.y, Rr);
+    Ri = mfma16x16x4(xa.x, hb.y, Ri);
+    Ri = mfma16x16x4(xa.y, hb.x, Ri);
+  }
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[r] = cfma(cl, T2{Lr[r], Li[r]}, acc[r]);
+      acc[r] = cfma(cr, T2{Rr[r], Ri[r]}, acc[r]);
+    }
+  } else {
+    wave_sync();  // every lane has read its operands from X
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      T2 v = cmul(cl, T2{Lr[r], Li[r]});
+      v = cfma(cr, T2{Rr[r], Ri[r]}, v);
+      X[(4 * q + r) * 16 + c] = v;
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = cadd(acc[s], X[LaneMap<T, 16>::elem(lane, s)]);
+  }
+}
+
 // One group's terms, with the group sum u (in the lane layout) in hand: the
 // decay and the diagonal of H for the self group, then cl O u + cr u O
 // through the wave's LDS slice (and the trace of ADO 0 for the bordered
@@ -212,6 +277,13 @@ __device__ __forceinline__ void group_terms(const ApplyParams<T> &P, const int4 
     wave_sync();
     if (need_trace && lane == 0)
       for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
+    if constexpr (D == 16) {
+      if (gr.w && P.hmfma) {
+        self_h_mfma16<T>(P, cid, lane, buf, acc);
+        wave_sync();
+        return;
+      }
+    }
     op_terms<T, D>(P, cid, (T)1, lane, buf, tval, tcol, acc);
     wave_sync();
   }

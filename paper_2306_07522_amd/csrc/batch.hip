@@ -18,7 +18,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <numeric>
 
 #include "apply_wave.h"
@@ -129,8 +132,8 @@ __device__ __forceinline__ void batch_wave_tile(const ApplyParams<T> &Pi, const 
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t task = (int64_t)tl.y + wave;
-  if (task < tl.z) wave_task<T, D, false>(P, task, lane, sbuf + wave * DD, tval, tcol, thd);
+  for (int64_t task = (int64_t)tl.y + wave; task < tl.z; task += 4)
+    wave_task<T, D, false>(P, task, lane, sbuf + wave * DD, tval, tcol, thd);
 }
 
 template <typename T>
@@ -525,6 +528,18 @@ struct heom_batch {
   std::vector<int4> tiles_cost;   // interleaved, costliest instances first
   int order = 0;                  // 0: instance-major, 1: interleaved
   int grid = 0;                   // persistent grid (0: one block per tile)
+  // launch shape (autotuned): tile = base(d) x mult tasks, base(d) =
+  // max(4, 256 / d^2); the wave formulation for d = 8 / 16 when var8 /
+  // var16 is set (and its LDS fits), else one thread per output element
+  int mult_small = 1, mult_wave = 1, var8 = 1, var16 = 1;
+  int mfma16 = 0;                 // d = 16 wave instances: the self group's H terms on the matrix cores
+  int tuned_from_cache = 0;
+  std::vector<char> wave_ok;      // per instance: the wave formulation's LDS fits
+  std::vector<double> cost;       // per instance: gathers + outputs
+  std::vector<BInst<double>> i64h;
+  std::vector<BInst<float>> i32h;
+  std::vector<ApplyParams<double>> p64h;
+  std::vector<ApplyParams<float>> p32h;
   int64_t *ch_e = nullptr;        // [n_chunks + 1]
   int *ch_seg = nullptr;          // [n_chunks]
   int *seg_chunk = nullptr;       // [S + 1]
@@ -541,11 +556,76 @@ struct heom_batch {
 
 namespace heom {
 
-static heom_status batch_upload_tiles(heom_batch &b) {
+// Tile lists for the current launch shape: tiles of base(d) x mult tasks
+// of one instance, in instance order (tiles_inst) and round-robin over
+// instances, costliest per tile first (tiles_cost).  Also sets each
+// instance's variant flag in the host descriptors.
+static void build_tiles(heom_batch &b) {
+  const int S = b.S;
+  std::vector<std::vector<int4>> per(S);
+  for (int s = 0; s < S; ++s) {
+    const int d = b.i64h[s].d;
+    const bool wave = b.wave_ok[s] && ((d == 8 && b.var8) || (d == 16 && b.var16));
+    b.i64h[s].wave = b.i32h[s].wave = wave;
+    b.p64h[s].hmfma = b.p32h[s].hmfma = wave && d == 16 && b.mfma16;
+    const int base = std::max(4, 256 / (d * d));
+    const int tpt = base * (d >= 8 ? b.mult_wave : b.mult_small);
+    const int64_t N = (b.off[s + 1] - b.off[s]) / ((int64_t)d * d);
+    for (int64_t t = 0; t < N; t += tpt)
+      per[s].push_back(make_int4(s, (int)t, (int)std::min<int64_t>(N, t + tpt), 0));
+  }
+  b.tiles_inst.clear();
+  b.tiles_cost.clear();
+  for (int s = 0; s < S; ++s) b.tiles_inst.insert(b.tiles_inst.end(), per[s].begin(), per[s].end());
+  std::vector<int> ord(S);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
+    return b.cost[p] / std::max<size_t>(1, per[p].size()) > b.cost[q] / std::max<size_t>(1, per[q].size());
+  });
+  std::vector<size_t> pos(S, 0);
+  bool any = true;
+  while (any) {
+    any = false;
+    for (int s : ord)
+      if (pos[s] < per[s].size()) {
+        b.tiles_cost.push_back(per[s][pos[s]++]);
+        any = true;
+      }
+  }
+  b.n_tiles = (int)b.tiles_inst.size();
+}
+
+static heom_status batch_upload_shape(heom_batch &b) {
+  HEOM_HIP_CHECK(hipMemcpy(b.prm64, b.p64h.data(), sizeof(ApplyParams<double>) * b.S, hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b.prm32, b.p32h.data(), sizeof(ApplyParams<float>) * b.S, hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b.inst64, b.i64h.data(), sizeof(BInst<double>) * b.S, hipMemcpyHostToDevice));
+  HEOM_HIP_CHECK(hipMemcpy(b.inst32, b.i32h.data(), sizeof(BInst<float>) * b.S, hipMemcpyHostToDevice));
   const std::vector<int4> &src = b.order == 1 ? b.tiles_cost : b.tiles_inst;
   HEOM_HIP_CHECK(hipMemcpy(b.tiles, src.data(), sizeof(int4) * src.size(), hipMemcpyHostToDevice));
   return HEOM_OK;
 }
+
+struct BatchShape {
+  int mult_small, mult_wave, var8, var16, grid, order, mfma16;
+  bool operator==(const BatchShape &o) const {
+    return mult_small == o.mult_small && mult_wave == o.mult_wave && var8 == o.var8 && var16 == o.var16 &&
+           grid == o.grid && order == o.order && mfma16 == o.mfma16;
+  }
+};
+
+static heom_status set_shape(heom_batch &b, const BatchShape &sh) {
+  b.mult_small = sh.mult_small;
+  b.mult_wave = sh.mult_wave;
+  b.var8 = sh.var8;
+  b.var16 = sh.var16;
+  b.grid = sh.grid;
+  b.order = sh.order;
+  b.mfma16 = sh.mfma16;
+  build_tiles(b);
+  return batch_upload_shape(b);
+}
+
+
 
 template <typename T>
 static heom_status batch_apply_T(heom_batch &b, const void *x, void *y, int border, bool use_active, hipStream_t s) {
@@ -1012,44 +1092,26 @@ static heom_status heom_batch_create_body(int32_t n_inst, heom_hier *const *inst
     q.decay = D.decay64; q.ell_cnt = D.ell_cnt; q.ell_col = D.ell_col; q.ell_val = D.ell_val64;
     q.op_slots = D.op_slots; q.slots = h.ell.slots; q.c_meta = D.c_meta; q.c_col = D.c_col; q.c_val = D.c_val64;
     q.n_centries = (int)nce; q.hdiag = D.hdiag; q.coef_op = D.coef_op; q.coef = D.coef64; q.d = h.d; q.R = 1;
+    q.hoff = D.hoff64;
     p64[s] = q;
     ApplyParams<float> r{};
     r.tasks = D.base.tasks; r.n_tasks = h.N; r.groups = D.base.groups; r.gedges = D.base.gedges;
     r.decay = D.decay32; r.ell_cnt = D.ell_cnt; r.ell_col = D.ell_col; r.ell_val = D.ell_val32;
     r.op_slots = D.op_slots; r.slots = h.ell.slots; r.c_meta = D.c_meta; r.c_col = D.c_col; r.c_val = D.c_val32;
     r.n_centries = (int)nce; r.hdiag = D.hdiag32; r.coef_op = D.coef_op; r.coef = D.coef32; r.d = h.d; r.R = 1;
+    r.hoff = D.hoff32;
     p32[s] = r;
   }
   b->n = b->off[n_inst];
-  // tiles: four tasks (one per wavefront) of a wave-formulation instance,
-  // else 256 / d^2 consecutive tasks of one instance
-  std::vector<std::vector<int4>> per(n_inst);
-  for (int s = 0; s < n_inst; ++s) {
-    const Hier &h = *inst[s]->impl;
-    const int tpb = i64[s].wave ? 4 : std::max(1, 256 / (h.d * h.d));
-    for (int64_t t = 0; t < h.N; t += tpb)
-      per[s].push_back(make_int4(s, (int)t, (int)std::min<int64_t>(h.N, t + tpb), 0));
-  }
-  for (int s = 0; s < n_inst; ++s) b->tiles_inst.insert(b->tiles_inst.end(), per[s].begin(), per[s].end());
-  {
-    // interleaved: round-robin over instances, costliest (per tile) first
-    std::vector<int> ord(n_inst);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
-      return cost[p] / std::max<size_t>(1, per[p].size()) > cost[q] / std::max<size_t>(1, per[q].size());
-    });
-    std::vector<size_t> pos(n_inst, 0);
-    bool any = true;
-    while (any) {
-      any = false;
-      for (int s : ord)
-        if (pos[s] < per[s].size()) {
-          b->tiles_cost.push_back(per[s][pos[s]++]);
-          any = true;
-        }
-    }
-  }
-  b->n_tiles = (int)b->tiles_inst.size();
+  b->i64h = i64;
+  b->i32h = i32;
+  b->p64h = p64;
+  b->p32h = p32;
+  b->cost = cost;
+  b->wave_ok.assign(n_inst, 0);
+  for (int s = 0; s < n_inst; ++s) b->wave_ok[s] = i64[s].wave;
+  build_tiles(*b);
+  const size_t max_tiles = b->tiles_inst.size();  // mult = 1: the most tiles any shape makes
   // chunks of at most 16384 elements inside each instance
   std::vector<int64_t> che{0};
   std::vector<int> chs;
@@ -1069,7 +1131,7 @@ static heom_status heom_batch_create_body(int32_t n_inst, heom_hier *const *inst
   HEOM_HIP_CHECK(hipMalloc(&b->prm32, sizeof(ApplyParams<float>) * n_inst));
   HEOM_HIP_CHECK(hipMemcpy(b->prm64, p64.data(), sizeof(ApplyParams<double>) * n_inst, hipMemcpyHostToDevice));
   HEOM_HIP_CHECK(hipMemcpy(b->prm32, p32.data(), sizeof(ApplyParams<float>) * n_inst, hipMemcpyHostToDevice));
-  HEOM_HIP_CHECK(hipMalloc(&b->tiles, sizeof(int4) * std::max(1, b->n_tiles)));
+  HEOM_HIP_CHECK(hipMalloc(&b->tiles, sizeof(int4) * std::max<size_t>(1, max_tiles)));
   HEOM_HIP_CHECK(hipMalloc(&b->ch_e, sizeof(int64_t) * che.size()));
   HEOM_HIP_CHECK(hipMalloc(&b->ch_seg, sizeof(int) * std::max<size_t>(1, chs.size())));
   HEOM_HIP_CHECK(hipMalloc(&b->seg_chunk, sizeof(int) * (n_inst + 1)));
@@ -1083,7 +1145,7 @@ static heom_status heom_batch_create_body(int32_t n_inst, heom_hier *const *inst
   HEOM_HIP_CHECK(hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice));
   std::vector<int> ones(n_inst, 1);
   HEOM_HIP_CHECK(hipMemcpy(b->active, ones.data(), sizeof(int) * n_inst, hipMemcpyHostToDevice));
-  HEOM_TRY(batch_upload_tiles(*b));
+  HEOM_TRY(batch_upload_shape(*b));
   *out = b.release();
   return HEOM_OK;
 }
@@ -1093,6 +1155,34 @@ heom_status heom_batch_create(int32_t n_inst, heom_hier *const *inst, heom_batch
 }
 
 void heom_batch_free(heom_batch *b) { delete b; }
+
+heom_status heom_batch_shape(const heom_batch *b, int32_t *shape) {
+  if (!b || !shape) return fail(HEOM_ERR_ARG, "batch_shape: NULL argument");
+  shape[0] = b->mult_small;
+  shape[1] = b->mult_wave;
+  shape[2] = b->var8;
+  shape[3] = b->var16;
+  shape[4] = b->grid;
+  shape[5] = b->order;
+  shape[6] = b->mfma16;
+  shape[7] = b->tuned_from_cache;
+  return HEOM_OK;
+}
+
+heom_status heom_batch_set_shape(heom_batch *b, const int32_t *shape) {
+  return guarded([&]() -> heom_status {
+    HEOM_TRY(batch_check(b));
+    if (!shape) return fail(HEOM_ERR_ARG, "batch_set_shape: NULL shape");
+    const BatchShape sh{shape[0], shape[1], shape[2], shape[3], shape[4], shape[5], shape[6]};
+    auto mult_ok = [](int m) { return m == 1 || m == 2 || m == 4 || m == 8; };
+    if (!mult_ok(sh.mult_small) || !mult_ok(sh.mult_wave) || (sh.var8 != 0 && sh.var8 != 1) ||
+        (sh.var16 != 0 && sh.var16 != 1) || sh.grid < 0 || (sh.order != 0 && sh.order != 1) ||
+        (sh.mfma16 != 0 && sh.mfma16 != 1))
+      return fail(HEOM_ERR_ARG, "batch_set_shape: multipliers in {1, 2, 4, 8}, flags in {0, 1}, grid >= 0");
+    b->tuned_from_cache = 0;
+    return set_shape(*b, sh);
+  });
+}
 
 heom_status heom_batch_info(const heom_batch *b, int64_t *offsets, int64_t *n_tiles, int32_t *grid, int32_t *order) {
   if (!b) return fail(HEOM_ERR_ARG, "batch_info: NULL handle");
@@ -1118,55 +1208,139 @@ heom_status heom_batch_apply(heom_batch *b, int32_t precision, const void *x_dev
   return guarded([&] { return heom_batch_apply_body(b, precision, x_dev, y_dev, border, stream); });
 }
 
+// ----------------------------------------------------------------- autotuner
+// Cache key: the device, the precision and every instance's shape (N, d,
+// operator-table size, wave eligibility), FNV-1a 64.
+static std::string tune_key(const heom_batch &b, int precision, const hipDeviceProp_t &p) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  for (const char *c = p.gcnArchName; *c; ++c) mix((uint64_t)(unsigned char)*c);
+  mix((uint64_t)p.multiProcessorCount);
+  mix((uint64_t)precision);
+  mix((uint64_t)b.S);
+  for (int s = 0; s < b.S; ++s) {
+    mix((uint64_t)(b.off[s + 1] - b.off[s]));
+    mix((uint64_t)b.i64h[s].d);
+    mix((uint64_t)b.wave_ok[s]);
+    mix((uint64_t)b.inst[s]->impl->ell.c_col.size());
+  }
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, BatchShape &sh) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[64];
+    BatchShape t{};
+    if (std::sscanf(line, "heomx-batch-shape 2 %63s %d %d %d %d %d %d %d", k, &t.mult_small, &t.mult_wave, &t.var8,
+                    &t.var16, &t.grid, &t.order, &t.mfma16) == 8 &&
+        key == k && t.mult_small >= 1 && t.mult_wave >= 1 && t.grid >= 0 && (t.order == 0 || t.order == 1) &&
+        (t.mfma16 == 0 || t.mfma16 == 1)) {
+      sh = t;  // the last entry for the key wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void cache_store(const char *path, const std::string &key, const BatchShape &sh, double ms_def, double ms_best) {
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;  // a cache that cannot be written only costs the next search
+  std::fprintf(f, "heomx-batch-shape 2 %s %d %d %d %d %d %d %d %.4f %.4f\n", key.c_str(), sh.mult_small, sh.mult_wave,
+               sh.var8, sh.var16, sh.grid, sh.order, sh.mfma16, ms_def, ms_best);
+  std::fclose(f);
+}
+
 static heom_status heom_batch_tune_body(heom_batch *b, int32_t precision, const void *x_dev, void *y_dev, int32_t reps,
                             double *ms_default, double *ms_best, void *stream) {
   HEOM_TRY(batch_check(b));
   if (!x_dev || !y_dev || reps < 1) return fail(HEOM_ERR_ARG, "batch_tune: bad arguments");
   if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_ERR_ARG, "batch_tune: precision");
   hipStream_t s = (hipStream_t)stream;
-  int cus = 256;
-  {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, b->device) == hipSuccess && p.multiProcessorCount > 0) cus = p.multiProcessorCount;
-  }
+  hipDeviceProp_t prop;
+  HEOM_HIP_CHECK(hipGetDeviceProperties(&prop, b->device));
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   hipEvent_t e0, e1;
   HEOM_HIP_CHECK(hipEventCreate(&e0));
   HEOM_HIP_CHECK(hipEventCreate(&e1));
-  auto timeit = [&](float &ms) -> heom_status {
-    for (int r = 0; r < 2; ++r)
-      HEOM_TRY(heom_batch_apply(b, precision, x_dev, y_dev, 0, stream));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev{e0, e1};
+  auto timeit = [&](const BatchShape &sh, double &ms) -> heom_status {
+    HEOM_TRY(set_shape(*b, sh));
+    for (int r = 0; r < 2; ++r) HEOM_TRY(heom_batch_apply(b, precision, x_dev, y_dev, 0, stream));
     HEOM_HIP_CHECK(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r)
-      HEOM_TRY(heom_batch_apply(b, precision, x_dev, y_dev, 0, stream));
+    for (int r = 0; r < reps; ++r) HEOM_TRY(heom_batch_apply(b, precision, x_dev, y_dev, 0, stream));
     HEOM_HIP_CHECK(hipEventRecord(e1, s));
     HEOM_HIP_CHECK(hipEventSynchronize(e1));
-    HEOM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-    ms /= reps;
+    float f = 0.f;
+    HEOM_HIP_CHECK(hipEventElapsedTime(&f, e0, e1));
+    ms = f / reps;
     return HEOM_OK;
   };
-  const int grids[] = {0, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
-  float best = 1e30f, def = 0.f;
-  int bg = 0, bo = 0;
-  heom_status st = HEOM_OK;
-  for (int o = 0; o < 2 && st == HEOM_OK; ++o) {
-    b->order = o;
-    if ((st = batch_upload_tiles(*b)) != HEOM_OK) break;
-    for (int g : grids) {
-      b->grid = g;
-      float ms = 0.f;
-      if ((st = timeit(ms)) != HEOM_OK) break;
-      if (o == 0 && g == 0) def = ms;
-      if (ms < best) { best = ms; bg = g; bo = o; }
+  const BatchShape def{1, 1, 1, 1, 0, 0, 0};
+  double t_def = 0.0;
+  HEOM_TRY(timeit(def, t_def));
+  BatchShape best = def;
+  double t_best = t_def;
+  const char *path = std::getenv("HEOMX_TUNE_CACHE");
+  const std::string key = tune_key(*b, precision, prop);
+  BatchShape cached{};
+  b->tuned_from_cache = 0;
+  if (path && *path && cache_lookup(path, key, cached)) {
+    double t = 0.0;
+    HEOM_TRY(timeit(cached, t));
+    best = cached;
+    t_best = t;
+    b->tuned_from_cache = 1;
+  } else {
+    // coordinate descent over the launch shape, two sweeps; a candidate
+    // replaces the best only when it is faster
+    bool has8 = false, has16 = false;
+    for (int q = 0; q < b->S; ++q) {
+      has8 = has8 || (b->wave_ok[q] && b->i64h[q].d == 8);
+      has16 = has16 || (b->wave_ok[q] && b->i64h[q].d == 16);
     }
+    const std::vector<int> mults = {1, 2, 4, 8};
+    const std::vector<int> grids = {0, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      for (int param = 0; param < 7; ++param) {
+        std::vector<int> cand;
+        if (param == 0) cand = mults;
+        else if (param == 1) cand = mults;
+        else if (param == 2) { if (has8) cand = {0, 1}; }
+        else if (param == 3) { if (has16) cand = {0, 1}; }
+        else if (param == 4) cand = grids;
+        else if (param == 5) cand = {0, 1};
+        else if (has16 && best.var16) cand = {0, 1};  // the matrix-core self group: wave kernel only
+        for (int v : cand) {
+          BatchShape t = best;
+          int *field[] = {&t.mult_small, &t.mult_wave, &t.var8, &t.var16, &t.grid, &t.order, &t.mfma16};
+          *field[param] = v;
+          if (t == best) continue;
+          double ms = 0.0;
+          HEOM_TRY(timeit(t, ms));
+          if (ms < t_best) { t_best = ms; best = t; }
+        }
+      }
+    }
+    if (path && *path) cache_store(path, key, best, t_def, t_best);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  b->order = bo;
-  b->grid = bg;
-  HEOM_TRY(batch_upload_tiles(*b));
-  HEOM_TRY(st);
-  if (ms_default) *ms_default = def;
-  if (ms_best) *ms_best = best;
+  HEOM_TRY(set_shape(*b, best));
+  if (ms_default) *ms_default = t_def;
+  if (ms_best) *ms_best = t_best;
   return HEOM_OK;
 }
 

@@ -33,7 +33,7 @@ void free_device(Hier &h) {
   (void)hipSetDevice(D.device);
   void *ptrs[] = {D.decay64, D.decay32, D.ell_cnt, D.ell_col, D.op_slots, D.ell_val64, D.ell_val32,
                   D.coef_op, D.coef64, D.coef32, D.hdiag, D.hdiag32, D.lev, D.c_meta, D.c_col, D.c_val64, D.c_val32,
-                  D.ueig, D.eval, D.lind_f, D.lind_g};
+                  D.ueig, D.eval, D.lind_f, D.lind_g, D.hoff64, D.hoff32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_plan(D.base);
@@ -140,6 +140,14 @@ static heom_status upload_tables(Hier &h, int dev) {
     hd[i] = make_double2(L.hdiag[i].real(), L.hdiag[i].imag());
     hd32[i] = make_float2((float)L.hdiag[i].real(), (float)L.hdiag[i].imag());
   }
+  std::vector<double2> ho((size_t)h.d * h.d);
+  std::vector<float2> ho32((size_t)h.d * h.d);
+  for (int i = 0; i < h.d; ++i)
+    for (int j = 0; j < h.d; ++j) {
+      const cd v = i == j ? cd(0.0) : h.H[(size_t)i * h.d + j];
+      ho[(size_t)i * h.d + j] = make_double2(v.real(), v.imag());
+      ho32[(size_t)i * h.d + j] = make_float2((float)v.real(), (float)v.imag());
+    }
   // eigen-decomposition of H for the block preconditioner (column-major copy in)
   std::vector<cd> Hc((size_t)h.d * h.d), Ucol;
   std::vector<double> Ev;
@@ -221,6 +229,8 @@ static heom_status upload_tables(Hier &h, int dev) {
       (st = upload(&D.coef32, c32.data(), sizeof(float2) * 2 * nc, tot)) ||
       (st = upload(&D.hdiag, hd.data(), sizeof(double2) * h.d, tot)) ||
       (st = upload(&D.hdiag32, hd32.data(), sizeof(float2) * h.d, tot)) ||
+      (st = upload(&D.hoff64, ho.data(), sizeof(double2) * ho.size(), tot)) ||
+      (st = upload(&D.hoff32, ho32.data(), sizeof(float2) * ho32.size(), tot)) ||
       (st = upload(&D.lev, h.lev.data(), sizeof(int2) * N, tot)) ||
       (st = upload(&D.ueig, ue.data(), sizeof(double2) * ue.size(), tot)) ||
       (st = upload(&D.eval, Ev.data(), sizeof(double) * Ev.size(), tot)) ||

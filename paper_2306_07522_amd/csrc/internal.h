@@ -137,6 +137,8 @@ struct DeviceTables {
   double2 *coef64 = nullptr;    // [n_coef][2] (cl, cr)
   float2 *coef32 = nullptr;
   double2 *hdiag = nullptr;     // [d] diagonal of H
+  double2 *hoff64 = nullptr;    // [d][d] H with its diagonal zeroed, row-major (MFMA self group)
+  float2 *hoff32 = nullptr;
   int2 *lev = nullptr;          // [N] (m, n) levels of every ADO
   float2 *hdiag32 = nullptr;
   double2 *ueig = nullptr;      // [d][d] row-major eigenvectors of H (H = U diag(E) U^H)
@@ -221,6 +223,7 @@ struct ApplyArgs {
   // Optional epilogue (one right-hand side, pull plan, no Lindblad terms):
   // y = eacc * (M x) + sum_j ec[j] * ev[j], elementwise.  An ev[j] may be
   // y itself (each element is read before it is written, by the same lane).
+  int hmfma = 0;                // 1: the self group's H terms on the matrix cores (d = 16, wave kernel)
   bool epi = false;
   const void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
   double ec[4] = {0.0, 0.0, 0.0, 0.0};

@@ -351,3 +351,30 @@ def test_concurrent_first_apply_on_one_handle(n_threads):
     for t, y in ys:
         yo = to_blocks(M @ from_blocks(xs[t][0]), om.N, om.d)
         assert rel_err(y.cpu().numpy()[perm], yo) <= FP64_TOL, t
+
+
+@pytest.mark.parametrize("parity", [+1, -1])
+@pytest.mark.parametrize("kind", ["dense_mixed", "two_orbital"])
+def test_apply_pull_mfma(kind, parity):
+    """The self group's H terms on the matrix cores (d = 16): a dense random
+    H with bosonic and fermionic baths, and the two-orbital model's sparse H,
+    against the oracle (FP64 1e-12, FP32 1e-5)."""
+    if kind == "dense_mixed":
+        rng = np.random.default_rng(71)
+        H = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+        baths = wl.random_raw_baths(rng, 16, n_bos_baths=1, n_bos_exp=2, n_ferm_baths=1, n_ferm_exp=2,
+                                    dense_ops=False)
+        cfg = dict(name="dense_h_d16", H=H + H.conj().T, baths=baths, m_max=2, n_max=2)
+    else:
+        cfg = wl.two_orbital_anderson(n_max=2)
+    _parity_check(cfg, parity=parity, seeds=(0, 1), shift=0.3 - 0.2j, plan="pull_mfma")
+
+
+def test_apply_pull_mfma_unsupported():
+    torch = _torch()
+    from paper_2306_07522_amd import _lib
+    cfg = _random_cfg(72, 8, 2, 2, 2, 2)
+    lm = library_model(cfg)
+    x = torch.from_numpy(wl.random_vector(np.random.default_rng(0), lm.N, 8)).cuda()
+    with pytest.raises(_lib.HeomError, match="MFMA"):
+        lm.apply(x, plan="pull_mfma")

@@ -275,17 +275,64 @@ def test_batch_graph_replay_equals_eager():
     assert torch.equal(xe, xg) and torch.equal(xg, xg2)
 
 
-def test_autotuner_keeps_results():
+def test_autotuner_keeps_results(tmp_path, monkeypatch):
+    """The tuned shape gives the default shape's result to rounding, and a
+    second batch of the same instance shapes takes the shape from the cache
+    file without a search."""
     torch = _torch()
     cfgs = _pick(64)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HEOMX_TUNE_CACHE", str(cache))
     hs, b = _build(cfgs)
     g = torch.Generator(device="cuda").manual_seed(9)
     x = torch.randn(b.n, dtype=torch.complex64, device="cuda", generator=g)
     y0 = b.apply(x)
     t = b.tune("fp32", reps=3)
     assert t["ms_best"] <= t["ms_default"] * 1.05 and t["grid"] >= 0 and t["order"] in (0, 1)
+    assert t["shape"]["from_cache"] == 0
     y1 = b.apply(x)
-    assert torch.equal(y0, y1)
+    assert _rel(y1, y0) <= 1e-5
+    assert cache.read_text().count("heomx-batch-shape 2 ") == 1
+    hs2, b2 = _build(cfgs)
+    t2 = b2.tune("fp32", reps=3)
+    assert t2["shape"]["from_cache"] == 1
+    assert {k: v for k, v in t2["shape"].items() if k != "from_cache"} == \
+        {k: v for k, v in t["shape"].items() if k != "from_cache"}
+    assert cache.read_text().count("heomx-batch-shape 2 ") == 1
+
+
+@pytest.mark.parametrize("shape", [
+    dict(mult_small=4, mult_wave=8, var8=1, var16=1, grid=0, order=1, mfma16=0),
+    dict(mult_small=2, mult_wave=2, var8=0, var16=0, grid=512, order=0, mfma16=0),
+    dict(mult_small=8, mult_wave=4, var8=1, var16=0, grid=1024, order=1, mfma16=0),
+    dict(mult_small=1, mult_wave=2, var8=1, var16=1, grid=0, order=0, mfma16=1),
+])
+def test_batch_shapes_match_single_instance_applies(shape):
+    """Every launch shape the tuner can pick: the batched apply (FP64 and
+    FP32, plain and bordered) against the single-instance applies, and the
+    block preconditioner over the same tiles against the single-instance
+    one."""
+    torch = _torch()
+    from paper_2306_07522_amd import api
+    cfgs = _pick(40)
+    hs, b = _build(cfgs)
+    b.set_shape(**shape)
+    assert {k: v for k, v in b.shape().items() if k != "from_cache"} == shape
+    g = torch.Generator(device="cuda").manual_seed(13)
+    x = torch.randn(b.n, dtype=torch.complex128, device="cuda", generator=g)
+    for border in (0, 1):
+        y = b.apply(x, border=border)
+        y32 = b.apply(x.to(torch.complex64), border=border)
+        for h, xs, ys, ys32 in zip(hs, b.split(x), b.split(y), b.split(y32)):
+            ref = api.apply_steady_operator(h, xs.contiguous()) if border else h.apply(xs.contiguous())
+            assert _rel(ys, ref) <= 1e-12
+            assert _rel(ys32.to(torch.complex128), ref) <= 1e-5
+    xb, reps = b.steady_state(tol=1e-9, restart=40, max_iter=3000, precond="block", fallback=0,
+                              allow_not_converged=True)
+    for h, xs, r in zip(hs, b.split(xb), reps):
+        if r["status"] == 0:
+            res = api.steady_residual(h, xs.contiguous())
+            assert res.abs().pow(2).sum().sqrt().item() <= 2e-9
 
 
 def test_full_batch_of_512_instances():
