@@ -220,8 +220,8 @@ heom_status heom_apply_steady_operator(heom_hier *h, int32_t precision, const vo
  * only the order of the floating-point additions differs).
  *  HEOM_PLAN_AUTO  the default of every other entry point: the pull plan,
  *                  as HEOM_PLAN_PULL_MFMA when d = 16, one right-hand side
- *                  and H has at least 6 off-diagonal entries in some row or
- *                  column (the measured cut-over);
+ *                  and H has at least 8 (FP64) or 12 (FP32) off-diagonal
+ *                  entries in some row or column (the measured cut-over);
  *  HEOM_PLAN_PULL  one launch: every ADO gathers all its neighbour blocks;
  *  HEOM_PLAN_SLAB  three launches: the lower tiers and the top tier's own
  *                  rows, then two launches over label slabs of the top two

@@ -31,8 +31,9 @@ namespace heom {
 // runs on XCD b % 8) walks a contiguous run of tasks, which share parents.  Within a
 // task the next group's first neighbour block is prefetched while the
 // current group is finished; multi-edge groups stream two blocks at a time.
-template <typename T, int D, bool FUSE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WaveShape<D>::EPL > 4 ? 2 : 4)))
+template <typename T, int D, bool FUSE, bool MF = false>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(WaveShape<D>::EPL > 4 ? 2 : (MF && sizeof(T) == 8 ? 3 : 4))))
 apply_wave_kernel(ApplyParams<T> P) {
   using T2 = typename Cplx<T>::t;
   constexpr int DD = D * D;
@@ -63,7 +64,7 @@ apply_wave_kernel(ApplyParams<T> P) {
   for (int it = 0; it < P.tpw; ++it) {
     const int64_t task = first + 4 * it;
     if (task >= P.n_tasks) break;
-    wave_task<T, D, FUSE>(P, task, lane, buf, tval, tcol, thd);
+    wave_task<T, D, FUSE, true, MF>(P, task, lane, buf, tval, tcol, thd);
   }
 }
 
@@ -317,6 +318,9 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
     } else if (d == 20) {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 20, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 20, false>), g, b, smem, s, P);
+    } else if (P.hmfma) {
+      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true, true>), g, b, smem, s, P);
+      else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, true>), g, b, smem, s, P);
     } else {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false>), g, b, smem, s, P);
@@ -361,12 +365,13 @@ static heom_status run_plan(Hier &h, int precision, const ApplyArgs &a, const Pl
 }
 
 // Off-diagonal entries of H per row (the compact table's width) from which
-// the matrix-core H terms beat the gathers at d = 16.  Measured on a d = 16
-// spin-boson hierarchy (6,435 ADOs) with banded random H: the MFMA apply
-// takes the same time at every width (61 us FP64, 38 us FP32); the gathers
-// take 58-59 us at 1-2 entries, 62 at 4, 64 at 6 and 70-77 us at 8-15
-// (FP32: 35-36, 38, 39, 44-48 us).
-constexpr int kMfmaMinOffdiag = 6;
+// the matrix-core H terms beat the gathers at d = 16, per precision.
+// Measured on a d = 16 spin-boson hierarchy (6,435 ADOs) with banded random
+// H (median of 20 applies): the MFMA apply takes the same time at every
+// width, 52.5 us FP64 and 40 us FP32 (it runs at 3 and 4 waves per SIMD
+// against 4 and 6 for the gathers); the gathers take 46 / 49 / 51 / 56-62 us
+// FP64 and 31 / 34 / 35 / 39-43 us FP32 at 1-2 / 4 / 6 / 8-15 entries.
+constexpr int kMfmaMinOffdiag64 = 8, kMfmaMinOffdiag32 = 12;
 
 // The wave kernel (which carries the matrix-core path) runs for this hierarchy
 static bool mfma_fits(const Hier &h, int precision) {
@@ -383,8 +388,9 @@ heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int pl
     case HEOM_PLAN_AUTO:
       // the pull plan (measured faster than the slab plan on the two-orbital
       // model); its H terms on the matrix cores when d = 16 and H has at
-      // least kMfmaMinOffdiag off-diagonal entries in some row or column
-      if (h.d == 16 && a.n_rhs == 1 && h.ell.c_ns[0] >= kMfmaMinOffdiag && mfma_fits(h, precision))
+      // least the cut-over's off-diagonal entries in some row or column
+      if (h.d == 16 && a.n_rhs == 1 && mfma_fits(h, precision) &&
+          h.ell.c_ns[0] >= (precision == HEOM_FP64 ? kMfmaMinOffdiag64 : kMfmaMinOffdiag32))
         return launch_apply_plan(h, precision, a, HEOM_PLAN_PULL_MFMA, s);
       break;
     case HEOM_PLAN_PULL:

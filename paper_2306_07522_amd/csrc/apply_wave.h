@@ -39,9 +39,10 @@ struct ApplyParams {
   const T2 *shifts;
   T2 shift0;
   int border;
-  // self group on matrix cores (d = 16): H with its diagonal zeroed, row-major
+  // self group on the matrix cores (d = 16; the kernel instantiation with
+  // MF set): H with its diagonal zeroed, row-major
   const T2 *hoff;
-  int hmfma;
+  int hmfma;  // launch choice, read on the host
   // epilogue: y = eacc * acc + sum_j ec[j] * ev[j] (ev[j] may alias y)
   int epi;
   const T2 *ev[4];
@@ -205,37 +206,36 @@ __device__ __forceinline__ void self_h_mfma16(const ApplyParams<T> &P, int cid, 
   using V4 = T __attribute__((ext_vector_type(4)));
   const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
   const int q = lane >> 4, c = lane & 15;
-  V4 Lr = {0, 0, 0, 0}, Li = {0, 0, 0, 0}, Rr = {0, 0, 0, 0}, Ri = {0, 0, 0, 0};
+  // two passes (H' X, then X H') so that only one complex accumulator pair
+  // is live at a time
+  T2 v[4];
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
-    const int k = 4 * ks + q;
-    const T2 ha = P.hoff[c * 16 + k];  // A of H' X
-    const T2 hb = P.hoff[k * 16 + c];  // B of X H'
-    const T2 xb = X[k * 16 + c];       // B of H' X
-    const T2 xa = X[c * 16 + k];       // A of X H'
-    Lr = mfma16x16x4(ha.x, xb.x, Lr);
-    Lr = mfma16x16x4(-ha.y, xb.y, Lr);
-    Li = mfma16x16x4(ha.x, xb.y, Li);
-    Li = mfma16x16x4(ha.y, xb.x, Li);
-    Rr = mfma16x16x4(xa.x, hb.x, Rr);
-    Rr = mfma16x16x4(-xa.y, hb.y, Rr);
-    Ri = mfma16x16x4(xa.x, hb.y, Ri);
-    Ri = mfma16x16x4(xa.y, hb.x, Ri);
-  }
-  if constexpr (sizeof(T) == 8) {
+  for (int side = 0; side < 2; ++side) {
+    V4 Pr = {0, 0, 0, 0}, Pi = {0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      acc[r] = cfma(cl, T2{Lr[r], Li[r]}, acc[r]);
-      acc[r] = cfma(cr, T2{Rr[r], Ri[r]}, acc[r]);
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k = 4 * ks + q;
+      // side 0: A = H'[c][k], B = X[k][c]; side 1: A = X[c][k], B = H'[k][c]
+      const T2 a = side == 0 ? P.hoff[c * 16 + k] : X[c * 16 + k];
+      const T2 b = side == 0 ? X[k * 16 + c] : P.hoff[k * 16 + c];
+      Pr = mfma16x16x4(a.x, b.x, Pr);
+      Pr = mfma16x16x4(-a.y, b.y, Pr);
+      Pi = mfma16x16x4(a.x, b.y, Pi);
+      Pi = mfma16x16x4(a.y, b.x, Pi);
     }
-  } else {
+    const T2 cf = side == 0 ? cl : cr;
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = cfma(cf, T2{Pr[r], Pi[r]}, acc[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = side == 0 ? cmul(cf, T2{Pr[r], Pi[r]}) : cfma(cf, T2{Pr[r], Pi[r]}, v[r]);
+    }
+  }
+  if constexpr (sizeof(T) == 4) {
     wave_sync();  // every lane has read its operands from X
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      T2 v = cmul(cl, T2{Lr[r], Li[r]});
-      v = cfma(cr, T2{Rr[r], Ri[r]}, v);
-      X[(4 * q + r) * 16 + c] = v;
-    }
+    for (int r = 0; r < 4; ++r) X[(4 * q + r) * 16 + c] = v[r];
     wave_sync();
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[s] = cadd(acc[s], X[LaneMap<T, 16>::elem(lane, s)]);
@@ -246,7 +246,7 @@ __device__ __forceinline__ void self_h_mfma16(const ApplyParams<T> &P, int cid, 
 // decay and the diagonal of H for the self group, then cl O u + cr u O
 // through the wave's LDS slice (and the trace of ADO 0 for the bordered
 // operator).
-template <typename T, int D>
+template <typename T, int D, bool MF = false>
 __device__ __forceinline__ void group_terms(const ApplyParams<T> &P, const int4 &gr, int64_t a, int lane,
                                             const typename Cplx<T>::t (&u)[WaveShape<D>::EPL],
                                             typename Cplx<T>::t *buf, const typename Cplx<T>::t *tval,
@@ -277,8 +277,8 @@ __device__ __forceinline__ void group_terms(const ApplyParams<T> &P, const int4 
     wave_sync();
     if (need_trace && lane == 0)
       for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
-    if constexpr (D == 16) {
-      if (gr.w && P.hmfma) {
+    if constexpr (D == 16 && MF) {
+      if (gr.w) {
         self_h_mfma16<T>(P, cid, lane, buf, acc);
         wave_sync();
         return;
@@ -293,7 +293,7 @@ __device__ __forceinline__ void group_terms(const ApplyParams<T> &P, const int4 
 // ADO (see wave_task).
 // PAIRS = false streams multi-edge groups one block at a time (fewer
 // registers; for callers that hold other blocks in registers meanwhile).
-template <typename T, int D, bool FUSE, bool PAIRS = true>
+template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false>
 __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                               const typename Cplx<T>::t *tval, const int *tcol,
                                               const typename Cplx<T>::t *thd,
@@ -348,7 +348,7 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
           u[s].y = fma(w0, v0[s].y, u[s].y);
         }
       }
-      group_terms<T, D>(P, gr, a, lane, u, buf, tval, tcol, thd, acc, trace);
+      group_terms<T, D, MF>(P, gr, a, lane, u, buf, tval, tcol, thd, acc, trace);
       gr = grn;
     }
   }
@@ -369,7 +369,7 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
 // and the operator products gather from it through the compact tables
 // (tval, tcol) and the H diagonal (thd) held in LDS.  A task flagged
 // TASK_ACC adds to the output instead of overwriting it.
-template <typename T, int D, bool FUSE, bool PAIRS = true>
+template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false>
 __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                           const typename Cplx<T>::t *tval, const int *tcol,
                                           const typename Cplx<T>::t *thd) {
@@ -382,7 +382,7 @@ __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task,
 #pragma unroll
   for (int s = 0; s < EPL; ++s)
     acc[s] = (tk.w & TASK_ACC) && LaneMap<T, D>::on(lane, s) ? P.y[abase + LaneMap<T, D>::elem(lane, s)] : T2{0, 0};
-  wave_task_add<T, D, FUSE, PAIRS>(P, task, lane, buf, tval, tcol, thd, acc);
+  wave_task_add<T, D, FUSE, PAIRS, MF>(P, task, lane, buf, tval, tcol, thd, acc);
 }
 
 }  // namespace heom

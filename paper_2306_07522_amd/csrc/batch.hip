@@ -109,7 +109,7 @@ __device__ __forceinline__ void batch_cell_tile(const BInst<T> &I, const int4 &t
   }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool MF = false>
 __device__ __forceinline__ void batch_wave_tile(const ApplyParams<T> &Pi, const BInst<T> &I, const int4 &tl,
                                                 const typename Cplx<T>::t *x, typename Cplx<T>::t *y, int border,
                                                 unsigned char *smem) {
@@ -133,10 +133,13 @@ __device__ __forceinline__ void batch_wave_tile(const ApplyParams<T> &Pi, const 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int64_t task = (int64_t)tl.y + wave; task < tl.z; task += 4)
-    wave_task<T, D, false>(P, task, lane, sbuf + wave * DD, tval, tcol, thd);
+    wave_task<T, D, false, true, MF>(P, task, lane, sbuf + wave * DD, tval, tcol, thd);
 }
 
-template <typename T>
+// MF16: the d = 16 wave instances compute their own block's H terms on the
+// matrix cores (a separate instantiation, so that the other keeps its
+// register budget).
+template <typename T, bool MF16>
 __global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__restrict__ inst,
                                                           const ApplyParams<T> *__restrict__ prm,
                                                           const int4 *__restrict__ tiles, int n_tiles,
@@ -148,7 +151,7 @@ __global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__rest
     const int4 tl = tiles[t];
     if (active && !active[tl.x]) continue;
     const BInst<T> &I = inst[tl.x];
-    if (I.wave && I.d == 16) batch_wave_tile<T, 16>(prm[tl.x], I, tl, x, y, border, smem);
+    if (I.wave && I.d == 16) batch_wave_tile<T, 16, MF16>(prm[tl.x], I, tl, x, y, border, smem);
     else if (I.wave && I.d == 8) batch_wave_tile<T, 8>(prm[tl.x], I, tl, x, y, border, smem);
     else batch_cell_tile<T>(I, tl, x, y, border);
   }
@@ -567,7 +570,7 @@ static void build_tiles(heom_batch &b) {
     const int d = b.i64h[s].d;
     const bool wave = b.wave_ok[s] && ((d == 8 && b.var8) || (d == 16 && b.var16));
     b.i64h[s].wave = b.i32h[s].wave = wave;
-    b.p64h[s].hmfma = b.p32h[s].hmfma = wave && d == 16 && b.mfma16;
+
     const int base = std::max(4, 256 / (d * d));
     const int tpt = base * (d >= 8 ? b.mult_wave : b.mult_small);
     const int64_t N = (b.off[s + 1] - b.off[s]) / ((int64_t)d * d);
@@ -634,9 +637,14 @@ static heom_status batch_apply_T(heom_batch &b, const void *x, void *y, int bord
   constexpr bool dbl = std::is_same<T, double>::value;
   const BInst<T> *I = dbl ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
   const ApplyParams<T> *Pm = dbl ? (const ApplyParams<T> *)b.prm64 : (const ApplyParams<T> *)b.prm32;
-  hipLaunchKernelGGL(batch_apply_kernel<T>, dim3(grid), dim3(256), dbl ? b.smem64 : b.smem32, s, I, Pm, b.tiles,
-                     b.n_tiles, use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x, (typename Cplx<T>::t *)y,
-                     border);
+  if (b.mfma16)
+    hipLaunchKernelGGL((batch_apply_kernel<T, true>), dim3(grid), dim3(256), dbl ? b.smem64 : b.smem32, s, I, Pm,
+                       b.tiles, b.n_tiles, use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x,
+                       (typename Cplx<T>::t *)y, border);
+  else
+    hipLaunchKernelGGL((batch_apply_kernel<T, false>), dim3(grid), dim3(256), dbl ? b.smem64 : b.smem32, s, I, Pm,
+                       b.tiles, b.n_tiles, use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x,
+                       (typename Cplx<T>::t *)y, border);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
