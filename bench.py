@@ -918,7 +918,9 @@ def main():
                    "n_ado": h.N, "d": h.d, "n_edges": h.info.n_edges, "precision": args.precision,
                    "apply": "untiled" if args.tiled < 0 else f"tiled({args.tiled})"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "achieved_basis": "algorithmic bytes / average kernel time (HIP events)",
+                     "traffic_gbs": None if traffic is None else round(traffic / (r["avg_kernel_ms"] * 1e-3) / 1e9, 2)},
         "kernel_ms": {"avg": round(r["avg_kernel_ms"], 4), "median": round(r["median_kernel_ms"], 4)},
         "bytes_per_step": r["bytes"],
     }
