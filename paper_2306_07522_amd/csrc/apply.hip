@@ -368,9 +368,10 @@ static heom_status run_plan(Hier &h, int precision, const ApplyArgs &a, const Pl
 // the matrix-core H terms beat the gathers at d = 16, per precision.
 // Measured on a d = 16 spin-boson hierarchy (6,435 ADOs) with banded random
 // H (median of 20 applies): the MFMA apply takes the same time at every
-// width, 52.5 us FP64 and 40 us FP32 (it runs at 3 and 4 waves per SIMD
-// against 4 and 6 for the gathers); the gathers take 46 / 49 / 51 / 56-62 us
-// FP64 and 31 / 34 / 35 / 39-43 us FP32 at 1-2 / 4 / 6 / 8-15 entries.
+// width, 48.5-50 us FP64 and 36.5-37.5 us FP32 (it runs at 3 and 4 waves per
+// SIMD against 4 and 6 for the gathers); the gathers take 42-44 / 46 / 47 /
+// 53-59 us FP64 at 1-2 / 4 / 6 / 8-15 entries, and 28-29 / 31 / 33 / 37 /
+// 40-41 us FP32 at 1-2 / 4 / 6 / 8-10 / 12-15.
 constexpr int kMfmaMinOffdiag64 = 8, kMfmaMinOffdiag32 = 12;
 
 // The wave kernel (which carries the matrix-core path) runs for this hierarchy

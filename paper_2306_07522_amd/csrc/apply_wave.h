@@ -337,7 +337,104 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
           u[s].y = fma(w0, v0[s].y, fma(w1, v1[s].y, u[s].y));
         }
       }
-      for (; e < gr.y; ++e) {
+      if constexpr (PAIRS) {
+        // at most one edge is left
+        if (e < gr.y) {
+          const int2 e0 = P.gedges[e];
+          T2 v0[EPL];
+          load_block<T, D, FUSE>(P, e0.x, lane, v0);
+          const T w0 = (T)e0.y;
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) {
+            u[s].x = fma(w0, v0[s].x, u[s].x);
+            u[s].y = fma(w0, v0[s].y, u[s].y);
+          }
+        }
+      } else {
+        for (; e < gr.y; ++e) {
+          const int2 e0 = P.gedges[e];
+          T2 v0[EPL];
+          load_block<T, D, FUSE>(P, e0.x, lane, v0);
+          const T w0 = (T)e0.y;
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) {
+            u[s].x = fma(w0, v0[s].x, u[s].x);
+            u[s].y = fma(w0, v0[s].y, u[s].y);
+          }
+        }
+      }
+      group_terms<T, D, MF>(P, gr, a, lane, u, buf, tval, tcol, thd, acc, trace);
+      gr = grn;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < EPL; ++s) {
+    if (!LaneMap<T, D>::on(lane, s)) continue;
+    T2 v = acc[s];
+    if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;  // element 0 in both maps
+    const int64_t idx = abase + LaneMap<T, D>::elem(lane, s);
+    P.y[idx] = epilogue(P, idx, v);
+  }
+}
+
+// One output ADO (task) of the pull kernel, as a single body: the task's
+// groups stream their neighbour blocks (the next group's first block
+// prefetched while the current one is finished, multi-edge groups two blocks
+// at a time), each group sum is staged in the wave's LDS slice `buf`, and the
+// operator products gather from it through the compact tables (tval, tcol)
+// and the H diagonal (thd) held in LDS.  It computes what wave_task_add does;
+// the split form (op_terms / group_terms, which the slab kernel uses)
+// compiled to a pull apply 10 % slower on the
+// two-orbital tier-4 model (1.39 against 1.25 ms FP64, 0.87 against 0.76 ms
+// FP32, same box), so the hot path keeps this form.
+template <typename T, int D, bool FUSE, bool MF = false>
+__device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
+                                          const typename Cplx<T>::t *tval, const int *tcol,
+                                          const typename Cplx<T>::t *thd) {
+  using T2 = typename Cplx<T>::t;
+  using W = WaveShape<D>;
+  constexpr int DD = D * D;
+  constexpr int EPL = W::EPL;
+  const int4 tk = P.tasks[task];
+  const int64_t a = tk.x;
+  const int flags = tk.w;
+  const int64_t abase = a * DD;
+  T2 acc[EPL];
+#pragma unroll
+  for (int s = 0; s < EPL; ++s)
+    acc[s] = (flags & TASK_ACC) && LaneMap<T, D>::on(lane, s) ? P.y[abase + LaneMap<T, D>::elem(lane, s)] : T2{0, 0};
+  T2 trace{0, 0};
+  int g = tk.y;
+  if (g < tk.z) {
+    int4 gr = P.groups[g];
+    T2 vnext[EPL];
+    load_block<T, D, FUSE>(P, P.gedges[gr.x].x, lane, vnext);
+    for (; g < tk.z; ++g) {
+      T2 u[EPL];
+      {
+        const T w0 = (T)P.gedges[gr.x].y;
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) u[s] = T2{w0 * vnext[s].x, w0 * vnext[s].y};
+      }
+      int4 grn = gr;
+      if (g + 1 < tk.z) {  // prefetch the next group's first neighbour block
+        grn = P.groups[g + 1];
+        load_block<T, D, FUSE>(P, P.gedges[grn.x].x, lane, vnext);
+      }
+      int e = gr.x + 1;
+      for (; e + 1 < gr.y; e += 2) {
+        const int2 e0 = P.gedges[e], e1 = P.gedges[e + 1];
+        T2 v0[EPL], v1[EPL];
+        load_block<T, D, FUSE>(P, e0.x, lane, v0);
+        load_block<T, D, FUSE>(P, e1.x, lane, v1);
+        const T w0 = (T)e0.y, w1 = (T)e1.y;
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+          u[s].x = fma(w0, v0[s].x, fma(w1, v1[s].x, u[s].x));
+          u[s].y = fma(w0, v0[s].y, fma(w1, v1[s].y, u[s].y));
+        }
+      }
+      if (e < gr.y) {
         const int2 e0 = P.gedges[e];
         T2 v0[EPL];
         load_block<T, D, FUSE>(P, e0.x, lane, v0);
@@ -348,7 +445,67 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
           u[s].y = fma(w0, v0[s].y, u[s].y);
         }
       }
-      group_terms<T, D, MF>(P, gr, a, lane, u, buf, tval, tcol, thd, acc, trace);
+      if (gr.w) {
+        // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
+        const T2 z = P.shifts ? P.shifts[0] : P.shift0;
+        const T2 c = csub(P.decay[a], z);
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+          const T2 dh = csub(thd[LaneMap<T, D>::elem(lane, s) / D], thd[LaneMap<T, D>::col(lane, s)]);
+          const T2 f{c.x - dh.y, c.y + dh.x};  // c + i (H_ii - H_jj)
+          acc[s] = csub(acc[s], cmul(f, u[s]));
+        }
+      }
+      const int cid = gr.z;
+      const int op = P.coef_op[cid];
+      const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
+      const bool need_trace = gr.w && P.border && a == 0;
+      if (ns > 0 || need_trace) {
+#pragma unroll
+        for (int s = 0; s < EPL; ++s)
+          if (LaneMap<T, D>::on(lane, s)) buf[LaneMap<T, D>::elem(lane, s)] = u[s];
+        wave_sync();
+        if (need_trace && lane == 0)
+          for (int i = 0; i < D; ++i) trace = cadd(trace, buf[i * (D + 1)]);
+        bool on_mfma = false;
+        if constexpr (MF && D == 16) {
+          if (gr.w) {  // the H terms on the matrix cores
+            self_h_mfma16<T>(P, cid, lane, buf, acc);
+            on_mfma = true;
+          }
+        }
+        if (ns > 0 && !on_mfma) {
+          const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
+#pragma unroll
+          for (int s = 0; s < EPL; ++s) {
+            if (!LaneMap<T, D>::on(lane, s)) continue;
+            const int i = LaneMap<T, D>::elem(lane, s) / D;
+            const int j = LaneMap<T, D>::col(lane, s);
+            const int rbase = off + (D + j) * ns;
+            const int lbase = off + i * ns;
+            T2 L{0, 0}, Rv{0, 0};
+            if (isreal) {
+#pragma unroll 1
+              for (int t = 0; t < ns; ++t) {
+                const T vl = tval[lbase + t].x, vr = tval[rbase + t].x;
+                const T2 bl = buf[tcol[lbase + t] * D + j];
+                const T2 br = buf[i * D + tcol[rbase + t]];
+                L.x = fma(vl, bl.x, L.x); L.y = fma(vl, bl.y, L.y);
+                Rv.x = fma(vr, br.x, Rv.x); Rv.y = fma(vr, br.y, Rv.y);
+              }
+            } else {
+#pragma unroll 1
+              for (int t = 0; t < ns; ++t) {
+                L = cfma(tval[lbase + t], buf[tcol[lbase + t] * D + j], L);
+                Rv = cfma(buf[i * D + tcol[rbase + t]], tval[rbase + t], Rv);
+              }
+            }
+            acc[s] = cfma(cl, L, acc[s]);
+            acc[s] = cfma(cr, Rv, acc[s]);
+          }
+        }
+        wave_sync();
+      }
       gr = grn;
     }
   }
@@ -373,6 +530,10 @@ template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false>
 __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                           const typename Cplx<T>::t *tval, const int *tcol,
                                           const typename Cplx<T>::t *thd) {
+  if constexpr (PAIRS) {
+    wave_task_pull<T, D, FUSE, MF>(P, task, lane, buf, tval, tcol, thd);
+    return;
+  }
   using T2 = typename Cplx<T>::t;
   constexpr int DD = D * D;
   constexpr int EPL = WaveShape<D>::EPL;
