@@ -189,6 +189,14 @@ heom_status heom_ado_index(const heom_hier *h, const int32_t *bos_occ, const int
 heom_status heom_hierarchy_tables(const heom_hier *h, double *decay, int64_t *row_ptr, int32_t *col,
                                   int32_t *kind, int32_t *exp, int32_t *mult);
 
+/* Uploads the hierarchy's device tables and launch plans to the current
+ * device now, instead of on the first device call.  Allocates device memory
+ * (held by the handle until heom_free); call it before capturing work that
+ * uses the handle into a hipGraph, since a capture cannot allocate.  Safe to
+ * call from several threads on one handle: the upload runs once.
+ * HEOM_ERR_ARG if the tables already live on another device. */
+heom_status heom_prepare(heom_hier *h);
+
 /* ------------------------------------------------------------------------
  * Liouvillian apply (eq:HEOM; the HEOMLS M acting on the ADO vector)
  * ---------------------------------------------------------------------- */

@@ -109,6 +109,7 @@ SIGNATURES = {
     "heom_batch_apply": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, vp]),
     "heom_batch_tune": (heom_status, [vp, C.c_int32, vp, vp, C.c_int32, dp, dp, vp]),
     "heom_batch_shape": (heom_status, [vp, i32p]),
+    "heom_prepare": (heom_status, [vp]),
     "heom_batch_set_shape": (heom_status, [vp, i32p]),
     "heom_propagate_driven": (heom_status, [vp, C.c_int32, vp, C.c_double, C.c_double, C.c_int64, C.c_int64, vp,
                                             C.c_int32, dp, heom_drive_fn, vp, vp, C.c_size_t, vp]),

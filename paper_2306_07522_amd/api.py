@@ -219,6 +219,10 @@ class Hierarchy:
                     xcd_cost=[list(st.xcd_cost[l]) for l in range(2)])
 
     # ------------------------------------------------------------ device work
+    def prepare(self):
+        """Upload the device tables now (heom_prepare)."""
+        L.check(self._lib.heom_prepare(self._h))
+
     def apply(self, x, y=None, shift=None, n_rhs=1, stream=None, tiled=None, plan=None):
         """y = (M + shift) x on the GPU.  x: [N][d][d] or [N][d][d][R] tensor.
         shift: complex scalar, or a device tensor of R shifts (per column).

@@ -71,6 +71,20 @@ static void *query_thread(void *p) {
   return NULL;
 }
 
+long stub_device_allocations(void);
+
+typedef struct {
+  heom_hier *h;
+  int ok;
+} prep_arg;
+
+/* The first heom_prepare on a fresh handle, from several threads at once. */
+static void *prepare_thread(void *p) {
+  prep_arg *a = (prep_arg *)p;
+  a->ok = heom_prepare(a->h) == HEOM_OK;
+  return NULL;
+}
+
 int main(void) {
   /* ---- exponents */
   double kappa[8], zeta[8];
@@ -162,6 +176,31 @@ int main(void) {
     CHECK(heom_ado_index(h, NULL, ids2, 3, &i2, &s2) == HEOM_OK && i2 == i1 && s1 == -s2, "one swap flips the sign");
     int32_t dup[2] = {3, 3};
     CHECK(heom_ado_index(h, NULL, dup, 2, &i1, &s1) != HEOM_OK || i1 == -1, "repeated exponent is no ADO");
+    /* the table upload: once, whatever the number of threads asking */
+    if (parity == 1) {
+      long before = stub_device_allocations();
+      CHECK(heom_prepare(h) == HEOM_OK, "prepare: %s", heom_last_error());
+      long one = stub_device_allocations() - before;
+      CHECK(one > 0, "prepare allocated the tables");
+      CHECK(heom_prepare(h) == HEOM_OK && stub_device_allocations() - before == one, "second prepare is free");
+      heom_hier *h2 = NULL;
+      CHECK(heom_build_hierarchy(4, H4, 4, fb, 0, 3, parity, P4, &h2) == HEOM_OK, "second handle");
+      before = stub_device_allocations();
+      pthread_t tp[4];
+      prep_arg pa[4];
+      for (int t = 0; t < 4; ++t) {
+        pa[t].h = h2; pa[t].ok = 0;
+        pthread_create(&tp[t], NULL, prepare_thread, &pa[t]);
+      }
+      for (int t = 0; t < 4; ++t) {
+        pthread_join(tp[t], NULL);
+        CHECK(pa[t].ok, "concurrent prepare %d: %s", t, heom_last_error());
+      }
+      CHECK(stub_device_allocations() - before == one, "concurrent first prepares upload once: %ld vs %ld",
+            stub_device_allocations() - before, one);
+      heom_free(h2);
+    }
+    CHECK(heom_prepare(NULL) == HEOM_ERR_ARG, "prepare NULL");
     /* several threads on one handle */
     pthread_t th[4];
     thread_arg ta[4];

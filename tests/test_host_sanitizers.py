@@ -1,10 +1,13 @@
 """Host code under the sanitizers: the library's host files (exponents,
-hierarchy enumeration and pruning, neighbour tables, dictionary, argument
-checks, error plumbing) built with g++ under AddressSanitizer +
-UndefinedBehaviorSanitizer (leak checks on), and under ThreadSanitizer, and
-driven through the C ABI by tests/sanitize/host_driver.c, which also queries
-one handle from four threads at once.  Device entry points are replaced by
-stubs that fail (tests/sanitize/host_stubs.cpp); no GPU is used."""
+hierarchy enumeration and pruning, neighbour tables, dictionary, the
+one-time table and plan upload, argument checks, error plumbing) built with
+g++ under AddressSanitizer + UndefinedBehaviorSanitizer (leak checks on), and
+under ThreadSanitizer, and driven through the C ABI by
+tests/sanitize/host_driver.c.  The driver queries one handle from four
+threads at once, and has four threads make the first heom_prepare on one
+fresh handle at the same moment (the upload must run once).  Kernel launches
+are replaced by stubs that fail and device memory by host memory
+(tests/sanitize/host_stubs.cpp); no GPU is used."""
 import os
 import shutil
 import subprocess
@@ -14,8 +17,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2306_07522_amd", "csrc")
 SAN = os.path.join(ROOT, "tests", "sanitize")
-HOST_FILES = [os.path.join(CSRC, "host_hierarchy.cpp"), os.path.join(CSRC, "abi.cpp"),
-              os.path.join(SAN, "host_stubs.cpp")]
+HOST_FILES = [os.path.join(CSRC, "host_hierarchy.cpp"), os.path.join(CSRC, "device_tables.cpp"),
+              os.path.join(CSRC, "dense.cpp"), os.path.join(CSRC, "abi.cpp"), os.path.join(SAN, "host_stubs.cpp")]
 
 
 def _build(tmp_path, flags):
