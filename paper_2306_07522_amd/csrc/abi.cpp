@@ -262,4 +262,11 @@ heom_status heom_apply_tiled(heom_hier *hw, int32_t precision, const void *x_dev
   return guarded([&] { return heom_apply_tiled_body(hw, precision, x_dev, y_dev, n_rhs, shift, n_chunks, stream); });
 }
 
+heom_status heom_prepare(heom_hier *hw) {
+  return guarded([&]() -> heom_status {
+    if (!hw) return fail(HEOM_ERR_ARG, "prepare: NULL handle");
+    return ensure_device(*hw->impl);
+  });
+}
+
 }  // extern "C"

@@ -619,14 +619,6 @@ static heom_status build_slab_plan(const Hier &h, SlabPlan *out, size_t &tot, he
 
 }  // namespace heom
 
-extern "C" heom_status heom_prepare(heom_hier *hw) {
-  using namespace heom;
-  return guarded([&]() -> heom_status {
-    if (!hw) return fail(HEOM_ERR_ARG, "prepare: NULL handle");
-    return ensure_device(*hw->impl);
-  });
-}
-
 extern "C" heom_status heom_slab_plan_stats(const heom_hier *hw, heom_slab_stats *out) {
   using namespace heom;
   return guarded([&]() -> heom_status {
