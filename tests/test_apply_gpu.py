@@ -378,3 +378,29 @@ def test_apply_pull_mfma_unsupported():
     x = torch.from_numpy(wl.random_vector(np.random.default_rng(0), lm.N, 8)).cuda()
     with pytest.raises(_lib.HeomError, match="MFMA"):
         lm.apply(x, plan="pull_mfma")
+
+
+def test_prepare_from_threads_then_apply():
+    """heom_prepare from four threads at once on a fresh handle (the upload
+    runs once), then a plain apply against the oracle."""
+    import threading
+    torch = _torch()
+    cfg = wl.two_orbital_anderson(n_max=2)
+    om, lm = oracle_model(cfg), library_model(cfg)
+    gate = threading.Barrier(4)
+    errors = []
+
+    def run():
+        try:
+            gate.wait()
+            lm.prepare()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=run) for _ in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    _parity_check(cfg, seeds=(3,), om=om, lm=lm, fp32=False)
