@@ -26,7 +26,7 @@
 
 namespace heom {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // round-to-nearest-even FP32 -> BF16 (quiet NaN kept)
@@ -41,14 +41,14 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // ------------------------------------------------------------------ GEMM
 // C[M x N] = op(A)[M x K] op(B)[K x N]; op(A)[m][k] = TA ? A[k lda + m] :
 // A[m lda + k]; op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n].  Block tile
-// 64 x 64 x 32, four waves of 32 x 32, each 2 x 2 MFMA 16x16x16 tiles.
+// 64 x 64 x 32, four waves of 32 x 32, each 2 x 2 MFMA 16x16x32 tiles.
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(const uint16_t *__restrict__ A, int lda, const uint16_t *__restrict__ B,
                                                    int ldb, int M, int N, int K, float *__restrict__ Cf,
                                                    uint16_t *__restrict__ Cb, int ldc, const float *__restrict__ bias,
                                                    const float *__restrict__ pre, int ldp) {
-  __shared__ uint16_t As[64][40];  // [m][k]
-  __shared__ uint16_t Bs[64][40];  // [n][k]
+  __shared__ __align__(16) uint16_t As[64][40];  // [m][k]; rows of 80 B keep 16-byte reads aligned
+  __shared__ __align__(16) uint16_t Bs[64][40];  // [n][k]
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -77,21 +77,25 @@ __global__ void __launch_bounds__(256) gemm_kernel(const uint16_t *__restrict__ 
       Bs[nn][kk] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 32; ks += 16) {
-      const int kb = ks + (lane >> 4) * 4;
-      short4_t af[2], bfr[2];
+    {
+      // one 16 x 16 x 32 BF16 MFMA per output tile and K step: lane l holds
+      // row (or column) l % 16 and the eight k values 8 (l / 16) .. + 7 of A
+      // and B alike (one 16-byte LDS read each)
+      const int kb = (lane >> 4) * 8;
+      bf16x8_t af[2], bfr[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm * 32 + i * 16 + (lane & 15);
-        af[i] = short4_t{(short)As[row][kb], (short)As[row][kb + 1], (short)As[row][kb + 2], (short)As[row][kb + 3]};
         const int col = wn * 32 + i * 16 + (lane & 15);
-        bfr[i] = short4_t{(short)Bs[col][kb], (short)Bs[col][kb + 1], (short)Bs[col][kb + 2], (short)Bs[col][kb + 3]};
+        const uint4 qa = *reinterpret_cast<const uint4 *>(&As[row][kb]);
+        const uint4 qb = *reinterpret_cast<const uint4 *>(&Bs[col][kb]);
+        __builtin_memcpy(&af[i], &qa, 16);
+        __builtin_memcpy(&bfr[i], &qb, 16);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
