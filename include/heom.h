@@ -603,8 +603,9 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
  * true residual; seconds and applies are batch totals).  Returns
  * HEOM_ERR_NOT_CONVERGED if any instance misses the tolerance.
  * opts.precond: HEOM_PREC_NONE, HEOM_PREC_JACOBI or HEOM_PREC_BLOCK; with
- * opts.fallback = 1 each instance that misses the tolerance is solved again
- * from zero on its own with heom_steady: FP64, block preconditioner, restart
+ * opts.fallback = 1 the batched pass stops each instance after at most
+ * 20 x opts.restart iterations, and each instance that misses the tolerance
+ * is solved again from zero on its own with heom_steady: FP64, block preconditioner, restart
  * 8 x opts.restart (at least 240, at most 1000, fewer when the instance's
  * Krylov basis would exceed 2 GiB), same tol and max_iter.  Its report
  * then carries fell_back = 1 (iterations add up).  The workspace size

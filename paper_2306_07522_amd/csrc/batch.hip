@@ -1428,6 +1428,12 @@ static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom
   std::vector<double> res(S, 0.0);
   std::vector<char> conv(S, 0);
   int64_t applies = 0;
+  // With the fallback on, the batched pass gives each instance at most 20
+  // restart cycles; the instances it leaves are solved on their own with the
+  // full max_iter.  (The 512-instance workload: 90 % of the instances converge
+  // within 480 iterations at restart 30, and a few stagnating ones would
+  // otherwise keep the batch running to max_iter on a tiny active set.)
+  const int pass_max = o->fallback ? std::min(o->max_iter, 20 * o->restart) : o->max_iter;
   // One pass solves the instances flagged in `want` (from zero unless
   // from_x) with preconditioner prec_pass.
   auto run_pass = [&](int prec_pass, std::vector<char> want, bool from_x) -> heom_status {
@@ -1439,7 +1445,7 @@ static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom
       std::vector<int> it;
       std::vector<double> rs;
       std::vector<char> cv;
-      HEOM_TRY(gm.solve(rhs, (double2 *)x_dev, want, o->tol, o->max_iter, 1, !from_x, it, rs, cv, applies, s));
+      HEOM_TRY(gm.solve(rhs, (double2 *)x_dev, want, o->tol, pass_max, 1, !from_x, it, rs, cv, applies, s));
       for (int q = 0; q < S; ++q)
         if (want[q]) { iters[q] += it[q]; res[q] = rs[q]; conv[q] = cv[q]; }
       return HEOM_OK;
@@ -1468,7 +1474,7 @@ static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom
         if (!std::isfinite(rel)) return fail(HEOM_ERR_NAN, "batch_steady: non-finite residual");
         res[q] = rel;
         if (rel <= o->tol) { conv[q] = 1; want[q] = 0; }
-        else if (ref >= o->max_refine || it0[q] >= o->max_iter) want[q] = 0;
+        else if (ref >= o->max_refine || it0[q] >= pass_max) want[q] = 0;
         any = any || want[q];
       }
       if (!any) break;
