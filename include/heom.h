@@ -607,8 +607,9 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
  * 20 x opts.restart iterations, and each instance that misses the tolerance
  * is solved again from zero on its own with heom_steady: FP64, block preconditioner, restart
  * 8 x opts.restart (at least 240, at most 1000, fewer when the instance's
- * Krylov basis would exceed 2 GiB), same tol and max_iter.  Its report
- * then carries fell_back = 1 (iterations add up).  The workspace size
+ * Krylov basis would exceed 2 GiB), same tol and max_iter; up to eight such
+ * solves run at once on host threads, each on a stream of its own.  Its
+ * report then carries fell_back = 1 (iterations add up).  The workspace size
  * accounts for that pass; the first such solve on an instance uploads the
  * instance's own device tables. */
 heom_status heom_batch_steady(heom_batch *b, void *x_dev, const heom_solver_opts *o, heom_solver_report *r,

@@ -21,8 +21,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <string>
+#include <atomic>
 #include <numeric>
+#include <string>
+#include <thread>
 
 #include "apply_wave.h"
 #include "blas.h"
@@ -1362,6 +1364,7 @@ heom_status heom_batch_tune(heom_batch *b, int32_t precision, const void *x_dev,
 // 8 x the batch's (at least 240, at most 1000), cut so that the instance's
 // Krylov basis stays within kFallbackBasisBytes.
 static constexpr size_t kFallbackBasisBytes = (size_t)2 << 30;
+static constexpr int kFallbackWorkers = 8;
 
 static heom_solver_opts fallback_opts(const heom_batch &b, int q, const heom_solver_opts &o) {
   heom_solver_opts f = o;
@@ -1389,12 +1392,14 @@ heom_status heom_batch_workspace_size(const heom_batch *b, const heom_solver_opt
   else pass1 = BatchGmres<double>::bytes(*b, o->restart, jac);
   size_t pass2 = 0;
   if (o->fallback) {
+    size_t w_max = 0;
     for (int q = 0; q < b->S; ++q) {
       const heom_solver_opts f = fallback_opts(*b, q, *o);
       size_t w = 0;
       HEOM_TRY(heom_workspace_size(b->inst[q], HEOM_OP_STEADY, &f, 0, &w));
-      pass2 = std::max(pass2, w);
+      w_max = std::max(w_max, (w + 255) & ~(size_t)255);
     }
+    pass2 = (size_t)std::min(kFallbackWorkers, b->S) * w_max;
   }
   need += std::max(pass1, pass2);
   need += (size_t)b->S * sizeof(double) + 256;
@@ -1515,22 +1520,64 @@ static heom_status heom_batch_steady_body(heom_batch *b, void *x_dev, const heom
     std::vector<int> ones(S, 1);
     HEOM_HIP_CHECK(hipMemcpy(b->active, ones.data(), sizeof(int) * S, hipMemcpyHostToDevice));
     const size_t off_ws = (sizeof(double2) * (size_t)n + 255) & ~(size_t)255;  // after rhs
+    std::vector<int> todo;
+    std::vector<heom_solver_opts> fo(S);
+    size_t w_max = 0;
     for (int q = 0; q < S; ++q) {
       if (conv[q]) continue;
-      const heom_solver_opts f = fallback_opts(*b, q, *o);
+      fo[q] = fallback_opts(*b, q, *o);
       size_t w = 0;
-      HEOM_TRY(heom_workspace_size(b->inst[q], HEOM_OP_STEADY, &f, 0, &w));
-      if (off_ws + w > ws_bytes) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small for the fallback pass");
-      heom_solver_report rq;
-      std::memset(&rq, 0, sizeof(rq));
-      const heom_status st = heom_steady(b->inst[q], (double2 *)x_dev + b->off[q], &f, &rq,
-                                         (unsigned char *)ws + off_ws, ws_bytes - off_ws, s);
-      if (st != HEOM_OK && st != HEOM_ERR_NOT_CONVERGED) return st;
+      HEOM_TRY(heom_workspace_size(b->inst[q], HEOM_OP_STEADY, &fo[q], 0, &w));
+      w_max = std::max(w_max, (w + 255) & ~(size_t)255);
+      todo.push_back(q);
+    }
+    // The solves are independent and mostly small (latency-bound): up to
+    // kFallbackWorkers host threads run them at once, each on its own
+    // stream with its own slice of the workspace.
+    const size_t avail = ws_bytes > off_ws ? ws_bytes - off_ws : 0;
+    const int n_work = (int)std::min<size_t>({(size_t)kFallbackWorkers, todo.size(), w_max ? avail / w_max : 0});
+    if (!todo.empty() && n_work < 1) return fail(HEOM_ERR_ARG, "batch_steady: workspace too small for the fallback pass");
+    std::atomic<size_t> next{0};
+    std::vector<heom_status> wst(n_work, HEOM_OK);
+    std::vector<std::string> wmsg(n_work);
+    std::vector<heom_solver_report> rep(S);
+    std::vector<heom_status> qst(S, HEOM_OK);
+    auto worker = [&](int k) {
+      hipStream_t ks = nullptr;
+      if (hipSetDevice(b->device) != hipSuccess || hipStreamCreateWithFlags(&ks, hipStreamNonBlocking) != hipSuccess) {
+        wst[k] = HEOM_ERR_HIP;
+        wmsg[k] = "batch_steady: fallback stream";
+        return;
+      }
+      unsigned char *wk = (unsigned char *)ws + off_ws + (size_t)k * w_max;
+      for (size_t i = next++; i < todo.size(); i = next++) {
+        const int q = todo[i];
+        std::memset(&rep[q], 0, sizeof(rep[q]));
+        qst[q] = heom_steady(b->inst[q], (double2 *)x_dev + b->off[q], &fo[q], &rep[q], wk, w_max, ks);
+        if (qst[q] != HEOM_OK && qst[q] != HEOM_ERR_NOT_CONVERGED) {
+          wst[k] = qst[q];
+          wmsg[k] = heom_last_error();
+          break;
+        }
+      }
+      if (hipStreamSynchronize(ks) != hipSuccess && wst[k] == HEOM_OK) {
+        wst[k] = HEOM_ERR_HIP;
+        wmsg[k] = "batch_steady: fallback stream synchronisation";
+      }
+      (void)hipStreamDestroy(ks);
+    };
+    std::vector<std::thread> pool;
+    for (int k = 1; k < n_work; ++k) pool.emplace_back(worker, k);
+    if (n_work > 0) worker(0);
+    for (auto &t : pool) t.join();
+    for (int k = 0; k < n_work; ++k)
+      if (wst[k] != HEOM_OK) return fail(wst[k], wmsg[k]);
+    for (int q : todo) {
       fell[q] = 1;
-      iters[q] += rq.iterations;
-      applies += rq.applies;
-      res[q] = rq.true_residual;
-      conv[q] = st == HEOM_OK;
+      iters[q] += rep[q].iterations;
+      applies += rep[q].applies;
+      res[q] = rep[q].true_residual;
+      conv[q] = qst[q] == HEOM_OK;
     }
   }
   HEOM_HIP_CHECK(hipStreamSynchronize(s));
