@@ -9,12 +9,13 @@
 //              element (256 / d^2 ADOs per tile);
 //   chunks     contiguous element ranges that never straddle two instances,
 //              the unit of the segmented reductions of the batched GMRES.
-// The apply is one persistent launch that walks the tile list; the Jacobi
-// preconditioner walks the same list.  Per-instance GMRES scalars (the
+// The apply is one launch that walks the tile list (one workgroup per tile,
+// or a persistent grid); the preconditioners walk the same list.  Per-instance GMRES scalars (the
 // Arnoldi coefficients, Givens rotations, residual norms) come from
 // segmented reductions; an Arnoldi step's device work can be captured once
 // per basis size into a hipGraph and replayed.  An autotuner picks the
-// persistent grid size and the tile order by timing the batched apply.
+// launch shape (tile size, kernel variant, grid, tile order, matrix-core H
+// terms) by timing the batched apply.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
