@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "75eb15905be97c84", "bytes": 6_752_501_146},
-    ("fp32", "untiled"): {"apply_sha256_prefix": "75eb15905be97c84", "bytes": 3_238_282_547},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "17883e2c139031de", "bytes": 6_754_518_835},
+    ("fp32", "untiled"): {"apply_sha256_prefix": "17883e2c139031de", "bytes": 3_239_942_554},
 }
 
 
@@ -81,6 +81,15 @@ def algorithmic_bytes(h, w, n_rhs=1):
     row pointers (8 B/ADO), edges (8 B/edge) and decay (w B/ADO)."""
     N, d = h.N, h.d
     return 2 * N * d * d * w * n_rhs + 8 * (N + 1) + 8 * h.info.n_edges + w * N
+
+
+def rk4_step_bytes(h, w):
+    """Algorithmic bytes of one RK4 step: four applies, each ending in the
+    stage epilogue, plus the vector passes those epilogues add: x read in
+    stages 2 and 3, the partial sum q = (u_1 + 2 u_2 - x)/3 written in stage 2
+    and read in stage 4 (stage 1 and stage 4 fold their own input in through
+    the shift)."""
+    return 4 * algorithmic_bytes(h, w) + 4 * h.N * h.d * h.d * w
 
 
 def gpu_apply_bench(args):
@@ -462,8 +471,7 @@ def propagation_benchmarks(api, wl):
     n_steps, dt = 20000, 0.01
     api.propagate(h, x.clone(), dt, 50, graph_steps=50)
     traj, t = _timed(lambda: api.propagate(h, x, dt, n_steps, save_every=100, graph_steps=100))
-    # four applies, three stage inputs x + c k (read 2, write 1) and the combine (read 5, write 1)
-    step_bytes = 4 * algorithmic_bytes(h, 16) + 15 * h.N * h.d * h.d * 16
+    step_bytes = rk4_step_bytes(h, 16)
     out["charge_cavity_rk4"] = {"n_ado": h.N, "d": h.d, "steps": n_steps, "dt": dt, "seconds": round(t, 3),
                                 "us_per_step": round(t / n_steps * 1e6, 3),
                                 "gbs_algorithmic": round(step_bytes * n_steps / t / 1e9, 2),
@@ -479,9 +487,7 @@ def propagation_benchmarks(api, wl):
     n_steps, dt = 40, 0.01
     api.propagate(h, x.clone(), dt, 4)
     traj, t = _timed(lambda: api.propagate(h, x, dt, n_steps, save_every=n_steps))
-    # four applies, each ending in the stage epilogue, plus the five vector
-    # reads the epilogues add (x in stages 2 and 3; u_1, u_2, x in stage 4)
-    step_bytes = 4 * algorithmic_bytes(h, 16) + 5 * h.N * h.d * h.d * 16
+    step_bytes = rk4_step_bytes(h, 16)
     x32 = torch.zeros((h.N, h.d, h.d), dtype=torch.complex64, device="cuda")
     x32[0] = torch.eye(h.d, dtype=torch.complex64, device="cuda") / h.d
     api.propagate(h, x32.clone(), dt, 4)

@@ -31,7 +31,7 @@ namespace heom {
 // runs on XCD b % 8) walks a contiguous run of tasks, which share parents.  Within a
 // task the next group's first neighbour block is prefetched while the
 // current group is finished; multi-edge groups stream two blocks at a time.
-template <typename T, int D, bool FUSE, bool MF = false>
+template <typename T, int D, bool FUSE, bool MF = false, bool EPI = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WaveShape<D>::EPL > 4 ? 2 : (MF && sizeof(T) == 8 ? 3 : 4))))
 apply_wave_kernel(ApplyParams<T> P) {
@@ -64,7 +64,7 @@ apply_wave_kernel(ApplyParams<T> P) {
   for (int it = 0; it < P.tpw; ++it) {
     const int64_t task = first + 4 * it;
     if (task >= P.n_tasks) break;
-    wave_task<T, D, FUSE, true, MF>(P, task, lane, buf, tval, tcol, thd);
+    wave_task<T, D, FUSE, true, MF, EPI>(P, task, lane, buf, tval, tcol, thd);
   }
 }
 
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) apply_cell_kernel(ApplyParams<T> P) {
       for (int ii = 0; ii < d; ++ii) tr = cadd(tr, in(0, ii, ii));
       acc = tr;
     }
-    P.y[out] = epilogue(P, out, acc);
+    store_out<true>(P, out, acc);
   }
 }
 
@@ -303,6 +303,9 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
     P.ec[j] = (T)a.ec[j];
   }
   P.eacc = (T)a.eacc;
+  P.y2 = (T2 *)a.y2;
+  for (int j = 0; j < 4; ++j) P.ec2[j] = (T)a.ec2[j];
+  P.eacc2 = (T)a.eacc2;
   const int d = h.d;
   const size_t tab_bytes = (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 16 + (size_t)d * sizeof(T2);
   const size_t smem = 4 * (size_t)d * d * sizeof(T2) + tab_bytes;
@@ -312,17 +315,23 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
     const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
     if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
     dim3 g((unsigned)grid), b(256);
+    // the epilogue (never together with a stage-input vector) has kernels of
+    // its own, so that the plain apply carries none of its code
     if (d == 8) {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 8, true>), g, b, smem, s, P);
+      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 8, false, false, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 8, false>), g, b, smem, s, P);
     } else if (d == 20) {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 20, true>), g, b, smem, s, P);
+      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 20, false, false, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 20, false>), g, b, smem, s, P);
     } else if (P.hmfma) {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true, true>), g, b, smem, s, P);
+      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, true, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, true>), g, b, smem, s, P);
     } else {
       if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true>), g, b, smem, s, P);
+      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, false, true>), g, b, smem, s, P);
       else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false>), g, b, smem, s, P);
     }
   } else {
@@ -401,7 +410,7 @@ heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int pl
         return fail(HEOM_ERR_UNSUPPORTED, "apply: the MFMA self group needs d = 16 and one right-hand side");
       ApplyArgs m = a;
       m.hmfma = 1;
-      if (m.epi && !h.lind.empty())
+      if (m.epi && (!h.lind.empty() || m.k))
         return fail(HEOM_ERR_UNSUPPORTED, "apply: the epilogue needs the pull plan, one right-hand side, no Lindblad terms");
       HEOM_TRY(run_plan(h, precision, m, h.dev.base, s));
       return launch_lindblad(h, precision, m, s);
@@ -416,7 +425,7 @@ heom_status launch_apply_plan(Hier &h, int precision, const ApplyArgs &a, int pl
     default:
       return fail(HEOM_ERR_ARG, "apply: unknown plan");
   }
-  if (a.epi && (slab || a.n_rhs != 1 || !h.lind.empty()))
+  if (a.epi && (slab || a.n_rhs != 1 || !h.lind.empty() || a.k))
     return fail(HEOM_ERR_UNSUPPORTED, "apply: the epilogue needs the pull plan, one right-hand side, no Lindblad terms");
   if (slab) HEOM_TRY(launch_apply_slab(h, precision, a, s));
   else HEOM_TRY(run_plan(h, precision, a, h.dev.base, s));

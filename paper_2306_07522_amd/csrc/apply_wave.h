@@ -43,27 +43,42 @@ struct ApplyParams {
   // MF set): H with its diagonal zeroed, row-major
   const T2 *hoff;
   int hmfma;  // launch choice, read on the host
-  // epilogue: y = eacc * acc + sum_j ec[j] * ev[j] (ev[j] may alias y)
+  // epilogue: y = eacc * acc + sum_j ec[j] * ev[j] (ev[j] may alias y), and
+  // when y2 is set also y2 = eacc2 * acc + sum_j ec2[j] * ev[j]
   int epi;
   const T2 *ev[4];
   T ec[4];
   T eacc;
+  T2 *y2;
+  T ec2[4];
+  T eacc2;
 };
 
-// The output element after the optional epilogue.
-template <typename T>
-__device__ __forceinline__ typename Cplx<T>::t epilogue(const ApplyParams<T> &P, int64_t idx,
-                                                        typename Cplx<T>::t v) {
-  if (!P.epi) return v;
+// Stores one output element, through the epilogue when EPI is set and the
+// launch asks for one (kernels built without EPI store plainly).
+template <bool EPI, typename T>
+__device__ __forceinline__ void store_out(const ApplyParams<T> &P, int64_t idx, typename Cplx<T>::t v) {
+  if constexpr (!EPI) {
+    P.y[idx] = v;
+    return;
+  }
+  if (!P.epi) {
+    P.y[idx] = v;
+    return;
+  }
   typename Cplx<T>::t r{P.eacc * v.x, P.eacc * v.y};
+  typename Cplx<T>::t r2{P.eacc2 * v.x, P.eacc2 * v.y};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (!P.ev[j]) continue;
     const typename Cplx<T>::t q = P.ev[j][idx];
     r.x = fma(P.ec[j], q.x, r.x);
     r.y = fma(P.ec[j], q.y, r.y);
+    r2.x = fma(P.ec2[j], q.x, r2.x);
+    r2.y = fma(P.ec2[j], q.y, r2.y);
   }
-  return r;
+  P.y[idx] = r;
+  if (P.y2) P.y2[idx] = r2;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -373,7 +388,7 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
     T2 v = acc[s];
     if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;  // element 0 in both maps
     const int64_t idx = abase + LaneMap<T, D>::elem(lane, s);
-    P.y[idx] = epilogue(P, idx, v);
+    store_out<true>(P, idx, v);
   }
 }
 
@@ -387,7 +402,7 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
 // compiled to a pull apply 10 % slower on the
 // two-orbital tier-4 model (1.39 against 1.25 ms FP64, 0.87 against 0.76 ms
 // FP32, same box), so the hot path keeps this form.
-template <typename T, int D, bool FUSE, bool MF = false>
+template <typename T, int D, bool FUSE, bool MF = false, bool EPI = false>
 __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                           const typename Cplx<T>::t *tval, const int *tcol,
                                           const typename Cplx<T>::t *thd) {
@@ -515,7 +530,7 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
     T2 v = acc[s];
     if (s == 0 && lane == 0 && P.border && a == 0 && (flags & TASK_DIAG)) v = trace;  // element 0 in both maps
     const int64_t idx = abase + LaneMap<T, D>::elem(lane, s);
-    P.y[idx] = epilogue(P, idx, v);
+    store_out<EPI>(P, idx, v);
   }
 }
 
@@ -526,12 +541,12 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
 // and the operator products gather from it through the compact tables
 // (tval, tcol) and the H diagonal (thd) held in LDS.  A task flagged
 // TASK_ACC adds to the output instead of overwriting it.
-template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false>
+template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false, bool EPI = false>
 __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                           const typename Cplx<T>::t *tval, const int *tcol,
                                           const typename Cplx<T>::t *thd) {
   if constexpr (PAIRS) {
-    wave_task_pull<T, D, FUSE, MF>(P, task, lane, buf, tval, tcol, thd);
+    wave_task_pull<T, D, FUSE, MF, EPI>(P, task, lane, buf, tval, tcol, thd);
     return;
   }
   using T2 = typename Cplx<T>::t;

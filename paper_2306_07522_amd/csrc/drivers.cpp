@@ -313,40 +313,65 @@ static heom_status heom_propagate_body(heom_hier *hw, int32_t precision, void *x
   HEOM_TRY(fill_int(counter, 0, 1, s));
   const int64_t n_saves = save_every > 0 ? n_steps / save_every : 0;
   // Without Lindblad terms every stage's apply ends in an epilogue that
-  // writes the next stage input, u_s = x + c_s k_s, in place of k_s.  The
-  // last stage writes the new state over x: with c_1 = c_2 = dt/2 and
-  // c_3 = dt, x + dt/6 (k1 + 2 k2 + 2 k3 + k4) equals
-  // (u_1 + 2 u_2 + u_3 - x) / 3 + dt/6 k4.  Stage 4 gathers only from u_3,
-  // and each element of x is read and then overwritten by the same lane, so
-  // the update is safe in place.  A step then moves the four applies plus
-  // five vector reads (x in stages 2 and 3; u_1, u_2, x in stage 4) instead
-  // of three stage-input passes and a five-vector combine.
-  const bool fused = h.lind.empty();
+  // writes the next stage input u_s = x + c_s k_s (c_1 = c_2 = dt/2,
+  // c_3 = dt) instead of k_s, and the last stage writes the new state over x.
+  // With q = (u_1 + 2 u_2 - x) / 3, x + dt/6 (k_1 + 2 k_2 + 2 k_3 + k_4)
+  // equals q + u_3 / 3 + dt/6 k_4.  The stages then read:
+  //   1: u_1 = dt/2 (M + 2/dt) x             the shift supplies x, no extra read
+  //   2: u_2 = x + dt/2 M u_1,  q = (x + u_1)/3 + dt/3 M u_1
+  //                                          reads x and u_1 (the input's own
+  //                                          block, mostly still in L2), writes q
+  //   3: u_3 = x + dt M u_2                  reads x
+  //   4: x <- q + dt/6 (M + 2/dt) u_3        reads q
+  // so a step moves the four applies plus three vector reads and one write
+  // beyond the stage outputs.  Stage 4 gathers only from u_3, and each
+  // element of x is written by the lane that owns it, so the update is safe
+  // in place.
+  // (the shift 2/dt needs a step that is not vanishingly small)
+  const bool fused = h.lind.empty() && std::fabs(dt) >= 1e-30;
   void *us[3] = {k[0], k[1], k[2]};
+  void *q = k[3];
   auto fused_step = [&]() -> heom_status {
     ApplyArgs a;
     a.n_rhs = 1;
     a.epi = true;
-    const double cs[3] = {0.5 * dt, 0.5 * dt, dt};
-    for (int st = 0; st < 3; ++st) {
-      a.x = st == 0 ? x_dev : us[st - 1];
-      a.y = us[st];
-      a.ev[0] = x_dev;
-      a.ec[0] = 1.0;
-      a.eacc = cs[st];
-      HEOM_TRY(launch_apply(h, precision, a, s));
-    }
+    a.x = x_dev;
+    a.y = us[0];
+    a.eacc = 0.5 * dt;
+    a.shift0 = 2.0 / dt;
+    HEOM_TRY(launch_apply(h, precision, a, s));
+    a = ApplyArgs{};
+    a.n_rhs = 1;
+    a.epi = true;
+    a.x = us[0];
+    a.y = us[1];
+    a.ev[0] = x_dev;
+    a.ev[1] = us[0];
+    a.ec[0] = 1.0;
+    a.eacc = 0.5 * dt;
+    a.y2 = q;
+    a.ec2[0] = 1.0 / 3.0;
+    a.ec2[1] = 1.0 / 3.0;
+    a.eacc2 = dt / 3.0;
+    HEOM_TRY(launch_apply(h, precision, a, s));
+    a = ApplyArgs{};
+    a.n_rhs = 1;
+    a.epi = true;
+    a.x = us[1];
+    a.y = us[2];
+    a.ev[0] = x_dev;
+    a.ec[0] = 1.0;
+    a.eacc = dt;
+    HEOM_TRY(launch_apply(h, precision, a, s));
+    a = ApplyArgs{};
+    a.n_rhs = 1;
+    a.epi = true;
     a.x = us[2];
     a.y = x_dev;
-    a.ev[0] = us[0];
-    a.ev[1] = us[1];
-    a.ev[2] = us[2];
-    a.ev[3] = x_dev;
-    a.ec[0] = 1.0 / 3.0;
-    a.ec[1] = 2.0 / 3.0;
-    a.ec[2] = 1.0 / 3.0;
-    a.ec[3] = -1.0 / 3.0;
+    a.ev[0] = q;
+    a.ec[0] = 1.0;
     a.eacc = dt / 6.0;
+    a.shift0 = 2.0 / dt;
     return launch_apply(h, precision, a, s);
   };
   auto step = [&](int64_t idx) -> heom_status {

@@ -221,13 +221,17 @@ struct ApplyArgs {
   cd shift0 = 0.0;              // used when shifts == null
   int border = 0;               // 1: replace y[0][0][0] by Tr rho_0 (steady-state row)
   // Optional epilogue (one right-hand side, pull plan, no Lindblad terms):
-  // y = eacc * (M x) + sum_j ec[j] * ev[j], elementwise.  An ev[j] may be
-  // y itself (each element is read before it is written, by the same lane).
+  // y = eacc * (M x) + sum_j ec[j] * ev[j], elementwise, and when y2 is set
+  // also y2 = eacc2 * (M x) + sum_j ec2[j] * ev[j].  An ev[j] may be y itself
+  // (each element is read before it is written, by the same lane).
   int hmfma = 0;                // 1: the self group's H terms on the matrix cores (d = 16, wave kernel)
   bool epi = false;
   const void *ev[4] = {nullptr, nullptr, nullptr, nullptr};
   double ec[4] = {0.0, 0.0, 0.0, 0.0};
   double eacc = 1.0;
+  void *y2 = nullptr;
+  double ec2[4] = {0.0, 0.0, 0.0, 0.0};
+  double eacc2 = 0.0;
 };
 heom_status launch_apply(Hier &h, int precision, const ApplyArgs &a, hipStream_t s);
 // as launch_apply with an explicit plan (HEOM_PLAN_*)

@@ -72,14 +72,22 @@ def test_rk4_graph_equals_eager():
     assert torch.equal(xa, xb) and torch.equal(ta, tb)
 
 
-@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small", "siam_tier1", "siam_tier2", "cavity_d20"])
+@pytest.mark.parametrize("name", ["charge_cavity", "two_orbital_small", "siam_tier1", "siam_tier2", "cavity_d20",
+                                  "dense_h_d16"])
 def test_rk4_workloads(name):
     """Every stage's apply ends in the RK4 epilogue (wave kernel for d = 8,
-    16, 20; cell kernel for the d = 4 tier-2 model; the one-workgroup kernel
-    for the tier-1 model).  FP64 against the oracle's RK4 at 1e-12, FP32
-    at 1e-5."""
+    16, 20; the matrix-core self group for a dense d = 16 H; cell kernel for
+    the d = 4 tier-2 model; the one-workgroup kernel for the tier-1 model).
+    FP64 against the oracle's RK4 at 1e-12, FP32 at 1e-5."""
     torch, api = _torch(), _api()
-    if name == "siam_tier2":
+    if name == "dense_h_d16":                                     # d = 16, dense H: matrix-core self group
+        rng = np.random.default_rng(71)
+        H = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+        H = (H + H.conj().T) / np.linalg.norm(H + H.conj().T, 2)
+        baths = wl.random_raw_baths(rng, 16, n_bos_baths=1, n_bos_exp=2, n_ferm_baths=1, n_ferm_exp=2,
+                                    dense_ops=False)
+        cfg = dict(name="dense_h_d16", H=H, baths=baths, m_max=2, n_max=2)
+    elif name == "siam_tier2":
         cfg = wl.siam(n_max=2)                                    # d = 4: cell kernel
     elif name == "charge_cavity":
         cfg = wl.charge_cavity(n_photon=4, n_bexp=3, n_fexp=3)   # d = 8: wave kernel with fused stages
@@ -104,6 +112,21 @@ def test_rk4_workloads(name):
     api.propagate(lm, x32, 0.01, 20)
     e32 = rel_err(x32.cpu().numpy()[perm].astype(complex), to_blocks(ref, om.N, om.d))
     assert e32 <= 1e-5, e32
+
+
+@pytest.mark.parametrize("name", ["two_orbital_small", "siam_tier2"])
+def test_rk4_zero_step(name):
+    """dt = 0 (where the fused stages' shift 2/dt does not exist) takes the
+    unfused step, which leaves the state exactly as it was."""
+    torch, api = _torch(), _api()
+    cfg = wl.two_orbital_anderson(n_max=2) if name == "two_orbital_small" else wl.siam(n_max=2)
+    lm = library_model(cfg)
+    x0 = wl.random_vector(np.random.default_rng(6), lm.N, lm.d)
+    for dt in (torch.complex128, torch.complex64):
+        x = torch.from_numpy(x0).to(dt).cuda()
+        ref = x.clone()
+        api.propagate(lm, x, 0.0, 3)
+        assert torch.equal(x, ref)
 
 
 def _steady_check(cfg, mode, precond, tol_err, lu=True):
