@@ -31,23 +31,40 @@ namespace heom {
 // runs on XCD b % 8) walks a contiguous run of tasks, which share parents.  Within a
 // task the next group's first neighbour block is prefetched while the
 // current group is finished; multi-edge groups stream two blocks at a time.
-template <typename T, int D, bool FUSE, bool MF = false, bool EPI = false>
+template <typename T, int D, bool FUSE, bool MF = false, bool EPI = false, bool LT = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WaveShape<D>::EPL > 4 ? 2 : (MF && sizeof(T) == 8 ? 3 : 4))))
 apply_wave_kernel(ApplyParams<T> P) {
   using T2 = typename Cplx<T>::t;
   constexpr int DD = D * D;
   extern __shared__ __align__(16) unsigned char smem[];
+  // The LDS layout is built from byte offsets into smem (no integer round
+  // trip of the addresses), so every access below stays an LDS access; a
+  // generic (flat) access would also wait on the outstanding block loads.
   T2 *sbuf = reinterpret_cast<T2 *>(smem);              // [4][DD] group staging, one slice per wave
   T2 *tval = sbuf + 4 * DD;                             // compact operator values
   int *tcol = reinterpret_cast<int *>(tval + P.n_centries);
   // H diagonal, after the column table (16-byte aligned)
-  T2 *thd = reinterpret_cast<T2 *>((reinterpret_cast<uintptr_t>(tcol + P.n_centries) + 15) & ~(uintptr_t)15);
+  const size_t o_thd = (4 * DD * sizeof(T2) + (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 15) & ~(size_t)15;
+  T2 *thd = reinterpret_cast<T2 *>(smem + o_thd);
   for (int e = threadIdx.x; e < P.n_centries; e += 256) {
     tval[e] = P.c_val[e];
     tcol[e] = P.c_col[e];
   }
   if (threadIdx.x < D) thd[threadIdx.x] = P.hdiag[threadIdx.x];
+  // LT: per coefficient entry, the operator's packed table slot / width /
+  // realness and the two coefficients, after the H diagonal
+  int *cmeta = reinterpret_cast<int *>(thd + D);
+  const size_t o_cfs = (o_thd + D * sizeof(T2) + (size_t)P.n_coef * sizeof(int) + 15) & ~(size_t)15;
+  T2 *cfs = reinterpret_cast<T2 *>(smem + o_cfs);
+  if constexpr (LT) {
+    for (int e = threadIdx.x; e < P.n_coef; e += 256) {
+      const int op = P.coef_op[e];
+      cmeta[e] = P.c_meta[3 * op] | (P.c_meta[3 * op + 1] << 20) | ((P.c_meta[3 * op + 2] ? 1 : 0) << 30);
+      cfs[2 * e] = P.coef[2 * e];
+      cfs[2 * e + 1] = P.coef[2 * e + 1];
+    }
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   // the task index is uniform across the wave: keep every table lookup scalar
@@ -64,7 +81,7 @@ apply_wave_kernel(ApplyParams<T> P) {
   for (int it = 0; it < P.tpw; ++it) {
     const int64_t task = first + 4 * it;
     if (task >= P.n_tasks) break;
-    wave_task<T, D, FUSE, true, MF, EPI>(P, task, lane, buf, tval, tcol, thd);
+    wave_task<T, D, FUSE, true, MF, EPI, LT>(P, task, lane, buf, tval, tcol, thd, cmeta, cfs);
   }
 }
 
@@ -261,6 +278,18 @@ heom_status launch_rk4_small(Hier &h, int precision, void *x, double dt, int64_t
   return launch_rk4_small_T<float>(h, x, dt, steps, save_every, step0, n_saves, traj, s);
 }
 
+// One instantiation of the wave kernel: the stage-input form (kvec), or the
+// plain or epilogue form, each with the task tables in lanes when every task
+// of the plan has at most 64 groups and 64 edges.
+template <typename T, int D, bool MF>
+static void launch_wave(dim3 g, dim3 b, size_t smem, hipStream_t s, const ApplyParams<T> &P, bool lt) {
+  if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, D, true, MF>), g, b, smem, s, P);
+  else if (P.epi && lt) hipLaunchKernelGGL((apply_wave_kernel<T, D, false, MF, true, true>), g, b, smem, s, P);
+  else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, D, false, MF, true, false>), g, b, smem, s, P);
+  else if (lt) hipLaunchKernelGGL((apply_wave_kernel<T, D, false, MF, false, true>), g, b, smem, s, P);
+  else hipLaunchKernelGGL((apply_wave_kernel<T, D, false, MF, false, false>), g, b, smem, s, P);
+}
+
 template <typename T>
 static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t t0, int64_t t1, hipStream_t s) {
   using T2 = typename Cplx<T>::t;
@@ -317,23 +346,18 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
     dim3 g((unsigned)grid), b(256);
     // the epilogue (never together with a stage-input vector) has kernels of
     // its own, so that the plain apply carries none of its code
-    if (d == 8) {
-      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 8, true>), g, b, smem, s, P);
-      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 8, false, false, true>), g, b, smem, s, P);
-      else hipLaunchKernelGGL((apply_wave_kernel<T, 8, false>), g, b, smem, s, P);
-    } else if (d == 20) {
-      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 20, true>), g, b, smem, s, P);
-      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 20, false, false, true>), g, b, smem, s, P);
-      else hipLaunchKernelGGL((apply_wave_kernel<T, 20, false>), g, b, smem, s, P);
-    } else if (P.hmfma) {
-      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true, true>), g, b, smem, s, P);
-      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, true, true>), g, b, smem, s, P);
-      else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, true>), g, b, smem, s, P);
-    } else {
-      if (P.kvec) hipLaunchKernelGGL((apply_wave_kernel<T, 16, true>), g, b, smem, s, P);
-      else if (P.epi) hipLaunchKernelGGL((apply_wave_kernel<T, 16, false, false, true>), g, b, smem, s, P);
-      else hipLaunchKernelGGL((apply_wave_kernel<T, 16, false>), g, b, smem, s, P);
-    }
+    // task tables in lanes when every task has at most 64 groups and edges,
+    // and the packed operator metadata fits (20-bit slot, 10-bit width) along
+    // with the coefficients in the LDS budget
+    P.n_coef = (int)h.coefs.size();
+    const size_t smem_lt = smem + (size_t)P.n_coef * sizeof(int) + 16 + 2 * (size_t)P.n_coef * sizeof(T2);
+    const bool lt = pl.max_groups <= 64 && pl.max_edges <= 64 && P.n_centries < (1 << 20) && d < 1024 &&
+                    smem_lt <= 48 * 1024;
+    const size_t sm = lt ? smem_lt : smem;
+    if (d == 8) launch_wave<T, 8, false>(g, b, sm, s, P, lt);
+    else if (d == 20) launch_wave<T, 20, false>(g, b, sm, s, P, lt);
+    else if (P.hmfma) launch_wave<T, 16, true>(g, b, sm, s, P, lt);
+    else launch_wave<T, 16, false>(g, b, sm, s, P, lt);
   } else {
     const int cells = d * d * a.n_rhs;
     const int64_t grid = cells <= 256 ? (n_tasks + (256 / cells) - 1) / (256 / cells) : n_tasks;

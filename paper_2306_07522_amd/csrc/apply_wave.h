@@ -30,6 +30,7 @@ struct ApplyParams {
   int xchunk;  // XCD remap super-chunk in blocks (multiple of 8; 0 = off)
   const int32_t *coef_op;
   const T2 *coef;
+  int n_coef;  // coefficient entries (coef holds two per entry)
   const T2 *x;
   const T2 *kvec;
   T kc;
@@ -402,10 +403,11 @@ __device__ __forceinline__ void wave_task_add(const ApplyParams<T> &P, int64_t t
 // compiled to a pull apply 10 % slower on the
 // two-orbital tier-4 model (1.39 against 1.25 ms FP64, 0.87 against 0.76 ms
 // FP32, same box), so the hot path keeps this form.
-template <typename T, int D, bool FUSE, bool MF = false, bool EPI = false>
+template <typename T, int D, bool FUSE, bool MF = false, bool EPI = false, bool LT = false>
 __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                           const typename Cplx<T>::t *tval, const int *tcol,
-                                          const typename Cplx<T>::t *thd) {
+                                          const typename Cplx<T>::t *thd, const int *cmeta = nullptr,
+                                          const typename Cplx<T>::t *cfs = nullptr) {
   using T2 = typename Cplx<T>::t;
   using W = WaveShape<D>;
   constexpr int DD = D * D;
@@ -419,26 +421,66 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
   for (int s = 0; s < EPL; ++s)
     acc[s] = (flags & TASK_ACC) && LaneMap<T, D>::on(lane, s) ? P.y[abase + LaneMap<T, D>::elem(lane, s)] : T2{0, 0};
   T2 trace{0, 0};
+  // LT: the self group's c_a - z is read here, ahead of the block loads
+  T2 cself{0, 0};
+  if constexpr (LT) cself = csub(P.decay[a], P.shifts ? P.shifts[0] : P.shift0);
   int g = tk.y;
   if (g < tk.z) {
-    int4 gr = P.groups[g];
+    // LT: the task's group entries and edges sit one per lane (at most 64
+    // of each, checked on the host) and are read with readlane, so no
+    // dependent table load stalls the group loop.
+    int4 lg{0, 0, 0, 0};
+    int2 le{0, 0};
+    int e_first = 0;
+    if constexpr (LT) {
+      const int ng = tk.z - tk.y;
+      if (lane < ng) lg = P.groups[tk.y + lane];
+      e_first = __builtin_amdgcn_readlane(lg.x, 0);
+      const int e_end = __builtin_amdgcn_readlane(lg.y, ng - 1);
+      if (lane < e_end - e_first) le = P.gedges[e_first + lane];
+    }
+    auto group_at = [&](int gg) -> int4 {
+      if constexpr (LT) {
+        const int k = gg - tk.y;
+        return make_int4(__builtin_amdgcn_readlane(lg.x, k), __builtin_amdgcn_readlane(lg.y, k),
+                         __builtin_amdgcn_readlane(lg.z, k), __builtin_amdgcn_readlane(lg.w, k));
+      } else {
+        return P.groups[gg];
+      }
+    };
+    auto edge_at = [&](int e) -> int2 {
+      if constexpr (LT) {
+        const int k = e - e_first;
+        return make_int2(__builtin_amdgcn_readlane(le.x, k), __builtin_amdgcn_readlane(le.y, k));
+      } else {
+        return P.gedges[e];
+      }
+    };
+    int4 gr = group_at(g);
     T2 vnext[EPL];
-    load_block<T, D, FUSE>(P, P.gedges[gr.x].x, lane, vnext);
+    load_block<T, D, FUSE>(P, edge_at(gr.x).x, lane, vnext);
     for (; g < tk.z; ++g) {
       T2 u[EPL];
       {
-        const T w0 = (T)P.gedges[gr.x].y;
+        const T w0 = (T)edge_at(gr.x).y;
 #pragma unroll
         for (int s = 0; s < EPL; ++s) u[s] = T2{w0 * vnext[s].x, w0 * vnext[s].y};
       }
       int4 grn = gr;
-      if (g + 1 < tk.z) {  // prefetch the next group's first neighbour block
+      if constexpr (LT) {
+        // prefetch the next group's first neighbour block; the last group
+        // loads its own first block again (a cache hit), so that no branch
+        // joins ahead of the edge loop and the prefetch stays in flight
+        const bool more = g + 1 < tk.z;
+        grn = group_at(more ? g + 1 : g);
+        load_block<T, D, FUSE>(P, edge_at(grn.x).x, lane, vnext);
+      } else if (g + 1 < tk.z) {  // prefetch the next group's first neighbour block
         grn = P.groups[g + 1];
         load_block<T, D, FUSE>(P, P.gedges[grn.x].x, lane, vnext);
       }
       int e = gr.x + 1;
       for (; e + 1 < gr.y; e += 2) {
-        const int2 e0 = P.gedges[e], e1 = P.gedges[e + 1];
+        const int2 e0 = edge_at(e), e1 = edge_at(e + 1);
         T2 v0[EPL], v1[EPL];
         load_block<T, D, FUSE>(P, e0.x, lane, v0);
         load_block<T, D, FUSE>(P, e1.x, lane, v1);
@@ -450,7 +492,7 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
         }
       }
       if (e < gr.y) {
-        const int2 e0 = P.gedges[e];
+        const int2 e0 = edge_at(e);
         T2 v0[EPL];
         load_block<T, D, FUSE>(P, e0.x, lane, v0);
         const T w0 = (T)e0.y;
@@ -462,8 +504,9 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
       }
       if (gr.w) {
         // self group: u = x_a.  -(c_a - z) x - i (H_ii - H_jj) x
-        const T2 z = P.shifts ? P.shifts[0] : P.shift0;
-        const T2 c = csub(P.decay[a], z);
+        T2 c;
+        if constexpr (LT) c = cself;
+        else c = csub(P.decay[a], P.shifts ? P.shifts[0] : P.shift0);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
           const T2 dh = csub(thd[LaneMap<T, D>::elem(lane, s) / D], thd[LaneMap<T, D>::col(lane, s)]);
@@ -472,8 +515,18 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
         }
       }
       const int cid = gr.z;
-      const int op = P.coef_op[cid];
-      const int off = P.c_meta[3 * op], ns = P.c_meta[3 * op + 1], isreal = P.c_meta[3 * op + 2];
+      int off, ns, isreal;
+      if constexpr (LT) {  // the operator's table slot, width and realness, packed in LDS
+        const int m = cmeta[cid];
+        off = m & 0xfffff;
+        ns = (m >> 20) & 0x3ff;
+        isreal = (m >> 30) & 1;
+      } else {
+        const int op = P.coef_op[cid];
+        off = P.c_meta[3 * op];
+        ns = P.c_meta[3 * op + 1];
+        isreal = P.c_meta[3 * op + 2];
+      }
       const bool need_trace = gr.w && P.border && a == 0;
       if (ns > 0 || need_trace) {
 #pragma unroll
@@ -490,7 +543,7 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
           }
         }
         if (ns > 0 && !on_mfma) {
-          const T2 cl = P.coef[2 * cid], cr = P.coef[2 * cid + 1];
+          const T2 cl = LT ? cfs[2 * cid] : P.coef[2 * cid], cr = LT ? cfs[2 * cid + 1] : P.coef[2 * cid + 1];
 #pragma unroll
           for (int s = 0; s < EPL; ++s) {
             if (!LaneMap<T, D>::on(lane, s)) continue;
@@ -541,12 +594,13 @@ __device__ __forceinline__ void wave_task_pull(const ApplyParams<T> &P, int64_t 
 // and the operator products gather from it through the compact tables
 // (tval, tcol) and the H diagonal (thd) held in LDS.  A task flagged
 // TASK_ACC adds to the output instead of overwriting it.
-template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false, bool EPI = false>
+template <typename T, int D, bool FUSE, bool PAIRS = true, bool MF = false, bool EPI = false, bool LT = false>
 __device__ __forceinline__ void wave_task(const ApplyParams<T> &P, int64_t task, int lane, typename Cplx<T>::t *buf,
                                           const typename Cplx<T>::t *tval, const int *tcol,
-                                          const typename Cplx<T>::t *thd) {
+                                          const typename Cplx<T>::t *thd, const int *cmeta = nullptr,
+                                          const typename Cplx<T>::t *cfs = nullptr) {
   if constexpr (PAIRS) {
-    wave_task_pull<T, D, FUSE, MF, EPI>(P, task, lane, buf, tval, tcol, thd);
+    wave_task_pull<T, D, FUSE, MF, EPI, LT>(P, task, lane, buf, tval, tcol, thd, cmeta, cfs);
     return;
   }
   using T2 = typename Cplx<T>::t;

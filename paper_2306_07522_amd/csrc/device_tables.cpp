@@ -97,6 +97,12 @@ struct PlanBuilder {
     HEOM_TRY(upload(&P.groups, groups.data(), sizeof(int4) * groups.size(), tot));
     HEOM_TRY(upload(&P.gedges, gedges.data(), sizeof(int2) * gedges.size(), tot));
     P.bytes = sizeof(int4) * (tasks.size() + groups.size()) + sizeof(int2) * gedges.size();
+    P.max_groups = P.max_edges = 0;
+    for (const int4 &t : tasks) {
+      if (t.z <= t.y) continue;
+      P.max_groups = std::max(P.max_groups, t.z - t.y);
+      P.max_edges = std::max(P.max_edges, groups[t.z - 1].y - groups[t.y].x);
+    }
     return HEOM_OK;
   }
 };

@@ -89,6 +89,8 @@ struct Plan {
   int2 *gedges = nullptr;        // {b, w}
   std::vector<int64_t> task_off; // [n_launch + 1]
   size_t bytes = 0;
+  int max_groups = 0;            // largest number of groups of one task
+  int max_edges = 0;             // largest number of edges of one task
 };
 
 // Slab passes of the apply (built in device_tables.cpp, run by

@@ -58,6 +58,16 @@ def _random_cfg(seed, d, nb, nf, m_max, n_max, n_bos_baths=1, n_ferm_baths=1):
     return dict(name=f"random_d{d}", H=H + H.conj().T, baths=baths, m_max=m_max, n_max=n_max)
 
 
+@pytest.mark.parametrize("d", [8, 16])
+def test_apply_wide_tasks(d):
+    """A task with more than 64 edges (the tier-0 ADO of 40 bosonic and 30
+    fermionic exponents at tier 1: 70 children) keeps the plan's task tables
+    in memory instead of in lanes: the wave kernel's other instantiation,
+    against the oracle."""
+    cfg = _random_cfg(300 + d, d, 40, 15, 1, 1)
+    _parity_check(cfg, parity=+1, seeds=(0,), shift=0.2 + 0.1j)
+
+
 @pytest.mark.parametrize("d,nb,nf,m_max,n_max", [
     (2, 3, 2, 3, 3),       # many ADOs per block, ragged tail
     (3, 2, 2, 2, 2),       # generic-d kernel
