@@ -112,7 +112,7 @@ __device__ __forceinline__ void batch_cell_tile(const BInst<T> &I, const int4 &t
   }
 }
 
-template <typename T, int D, bool MF = false>
+template <typename T, int D, bool MF = false, bool LT = false>
 __device__ __forceinline__ void batch_wave_tile(const ApplyParams<T> &Pi, const BInst<T> &I, const int4 &tl,
                                                 const typename Cplx<T>::t *x, typename Cplx<T>::t *y, int border,
                                                 unsigned char *smem) {
@@ -122,27 +122,42 @@ __device__ __forceinline__ void batch_wave_tile(const ApplyParams<T> &Pi, const 
   P.x = x + I.off;
   P.y = y + I.off;
   P.border = border;
+  // LDS layout from byte offsets (the accesses stay LDS accesses), as in the
+  // single-hierarchy wave kernel; with LT also the packed operator metadata
+  // and the coefficients
   T2 *sbuf = reinterpret_cast<T2 *>(smem);
   T2 *tval = sbuf + 4 * DD;
   int *tcol = reinterpret_cast<int *>(tval + P.n_centries);
-  T2 *thd = reinterpret_cast<T2 *>((reinterpret_cast<uintptr_t>(tcol + P.n_centries) + 15) & ~(uintptr_t)15);
+  const size_t o_thd = (4 * DD * sizeof(T2) + (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 15) & ~(size_t)15;
+  T2 *thd = reinterpret_cast<T2 *>(smem + o_thd);
+  int *cmeta = reinterpret_cast<int *>(thd + D);
+  const size_t o_cfs = (o_thd + D * sizeof(T2) + (size_t)P.n_coef * sizeof(int) + 15) & ~(size_t)15;
+  T2 *cfs = reinterpret_cast<T2 *>(smem + o_cfs);
   __syncthreads();  // the previous tile is done with the tables
   for (int e = threadIdx.x; e < P.n_centries; e += 256) {
     tval[e] = P.c_val[e];
     tcol[e] = P.c_col[e];
   }
   if (threadIdx.x < D) thd[threadIdx.x] = P.hdiag[threadIdx.x];
+  if constexpr (LT) {
+    for (int e = threadIdx.x; e < P.n_coef; e += 256) {
+      const int op = P.coef_op[e];
+      cmeta[e] = P.c_meta[3 * op] | (P.c_meta[3 * op + 1] << 20) | ((P.c_meta[3 * op + 2] ? 1 : 0) << 30);
+      cfs[2 * e] = P.coef[2 * e];
+      cfs[2 * e + 1] = P.coef[2 * e + 1];
+    }
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int64_t task = (int64_t)tl.y + wave; task < tl.z; task += 4)
-    wave_task<T, D, false, true, MF>(P, task, lane, sbuf + wave * DD, tval, tcol, thd);
+    wave_task<T, D, false, true, MF, false, LT>(P, task, lane, sbuf + wave * DD, tval, tcol, thd, cmeta, cfs);
 }
 
 // MF16: the d = 16 wave instances compute their own block's H terms on the
 // matrix cores (a separate instantiation, so that the other keeps its
 // register budget).
-template <typename T, bool MF16>
+template <typename T, bool MF16, bool LT>
 __global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__restrict__ inst,
                                                           const ApplyParams<T> *__restrict__ prm,
                                                           const int4 *__restrict__ tiles, int n_tiles,
@@ -154,8 +169,8 @@ __global__ void __launch_bounds__(256) batch_apply_kernel(const BInst<T> *__rest
     const int4 tl = tiles[t];
     if (active && !active[tl.x]) continue;
     const BInst<T> &I = inst[tl.x];
-    if (I.wave && I.d == 16) batch_wave_tile<T, 16, MF16>(prm[tl.x], I, tl, x, y, border, smem);
-    else if (I.wave && I.d == 8) batch_wave_tile<T, 8>(prm[tl.x], I, tl, x, y, border, smem);
+    if (I.wave && I.d == 16) batch_wave_tile<T, 16, MF16, LT>(prm[tl.x], I, tl, x, y, border, smem);
+    else if (I.wave && I.d == 8) batch_wave_tile<T, 8, false, LT>(prm[tl.x], I, tl, x, y, border, smem);
     else batch_cell_tile<T>(I, tl, x, y, border);
   }
 }
@@ -528,6 +543,10 @@ struct heom_batch {
   ApplyParams<double> *prm64 = nullptr;  // wave-formulation tables per instance
   ApplyParams<float> *prm32 = nullptr;
   size_t smem64 = 0, smem32 = 0;         // LDS of the batched apply launch
+  // every wave instance has at most 64 groups and edges per task and room for
+  // its packed operator metadata and coefficients: task tables in lanes
+  bool lt = true;
+  size_t smem64_lt = 0, smem32_lt = 0;
   int4 *tiles = nullptr;
   int n_tiles = 0;
   std::vector<int4> tiles_inst;   // instance-major order
@@ -640,14 +659,22 @@ static heom_status batch_apply_T(heom_batch &b, const void *x, void *y, int bord
   constexpr bool dbl = std::is_same<T, double>::value;
   const BInst<T> *I = dbl ? (const BInst<T> *)b.inst64 : (const BInst<T> *)b.inst32;
   const ApplyParams<T> *Pm = dbl ? (const ApplyParams<T> *)b.prm64 : (const ApplyParams<T> *)b.prm32;
-  if (b.mfma16)
-    hipLaunchKernelGGL((batch_apply_kernel<T, true>), dim3(grid), dim3(256), dbl ? b.smem64 : b.smem32, s, I, Pm,
-                       b.tiles, b.n_tiles, use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x,
-                       (typename Cplx<T>::t *)y, border);
+  const size_t sm = b.lt ? (dbl ? b.smem64_lt : b.smem32_lt) : (dbl ? b.smem64 : b.smem32);
+  const int *act = use_active ? b.active : nullptr;
+  const auto *xv = (const typename Cplx<T>::t *)x;
+  auto *yv = (typename Cplx<T>::t *)y;
+  if (b.mfma16 && b.lt)
+    hipLaunchKernelGGL((batch_apply_kernel<T, true, true>), dim3(grid), dim3(256), sm, s, I, Pm, b.tiles, b.n_tiles, act,
+                       xv, yv, border);
+  else if (b.mfma16)
+    hipLaunchKernelGGL((batch_apply_kernel<T, true, false>), dim3(grid), dim3(256), sm, s, I, Pm, b.tiles, b.n_tiles,
+                       act, xv, yv, border);
+  else if (b.lt)
+    hipLaunchKernelGGL((batch_apply_kernel<T, false, true>), dim3(grid), dim3(256), sm, s, I, Pm, b.tiles, b.n_tiles,
+                       act, xv, yv, border);
   else
-    hipLaunchKernelGGL((batch_apply_kernel<T, false>), dim3(grid), dim3(256), dbl ? b.smem64 : b.smem32, s, I, Pm,
-                       b.tiles, b.n_tiles, use_active ? b.active : nullptr, (const typename Cplx<T>::t *)x,
-                       (typename Cplx<T>::t *)y, border);
+    hipLaunchKernelGGL((batch_apply_kernel<T, false, false>), dim3(grid), dim3(256), sm, s, I, Pm, b.tiles, b.n_tiles,
+                       act, xv, yv, border);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }
@@ -1097,12 +1124,18 @@ static heom_status heom_batch_create_body(int32_t n_inst, heom_hier *const *inst
     if (wave) {
       b->smem64 = std::max(b->smem64, lds64);
       b->smem32 = std::max(b->smem32, lds32);
+      const size_t nco = h.coefs.size();
+      const size_t lt64 = lds64 + nco * 4 + 16 + 2 * nco * 16, lt32 = lds32 + nco * 4 + 16 + 2 * nco * 8;
+      if (D.base.max_groups > 64 || D.base.max_edges > 64 || nce >= (1u << 20) || lt64 > kLdsMax) b->lt = false;
+      b->smem64_lt = std::max(b->smem64_lt, lt64);
+      b->smem32_lt = std::max(b->smem32_lt, lt32);
     }
     ApplyParams<double> q{};
     q.tasks = D.base.tasks; q.n_tasks = h.N; q.groups = D.base.groups; q.gedges = D.base.gedges;
     q.decay = D.decay64; q.ell_cnt = D.ell_cnt; q.ell_col = D.ell_col; q.ell_val = D.ell_val64;
     q.op_slots = D.op_slots; q.slots = h.ell.slots; q.c_meta = D.c_meta; q.c_col = D.c_col; q.c_val = D.c_val64;
     q.n_centries = (int)nce; q.hdiag = D.hdiag; q.coef_op = D.coef_op; q.coef = D.coef64; q.d = h.d; q.R = 1;
+    q.n_coef = (int)h.coefs.size();
     q.hoff = D.hoff64;
     p64[s] = q;
     ApplyParams<float> r{};
@@ -1110,6 +1143,7 @@ static heom_status heom_batch_create_body(int32_t n_inst, heom_hier *const *inst
     r.decay = D.decay32; r.ell_cnt = D.ell_cnt; r.ell_col = D.ell_col; r.ell_val = D.ell_val32;
     r.op_slots = D.op_slots; r.slots = h.ell.slots; r.c_meta = D.c_meta; r.c_col = D.c_col; r.c_val = D.c_val32;
     r.n_centries = (int)nce; r.hdiag = D.hdiag32; r.coef_op = D.coef_op; r.coef = D.coef32; r.d = h.d; r.R = 1;
+    r.n_coef = (int)h.coefs.size();
     r.hoff = D.hoff32;
     p32[s] = r;
   }
