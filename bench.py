@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "17883e2c139031de", "bytes": 6_754_518_835},
-    ("fp32", "untiled"): {"apply_sha256_prefix": "17883e2c139031de", "bytes": 3_239_942_554},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "bb81de3badffa602", "bytes": 6_689_796_096},
+    ("fp32", "untiled"): {"apply_sha256_prefix": "bb81de3badffa602", "bytes": 3_163_983_667},
 }
 
 
