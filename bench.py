@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--prewarm-s", type=float, default=0.5,
+                   help="seconds of untimed applies before the warm-up steps (clock ramp of a cold GPU)")
     p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     p.add_argument("--tiled", type=int, default=-1, help="-1: untiled apply; 0: default chunks; k: k chunks")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -105,6 +107,14 @@ def gpu_apply_bench(args):
     y = torch.empty_like(x)
     tiled = None if args.tiled < 0 else args.tiled
     stream = torch.cuda.current_stream()
+    # untimed load first: on a cold GPU the first few hundred milliseconds of
+    # applies run slower (the clocks ramp), so the warm-up steps proper start
+    # after at least --prewarm-s seconds of applies
+    t_pre = time.perf_counter()
+    while time.perf_counter() - t_pre < args.prewarm_s:
+        for _ in range(20):
+            h.apply(x, y, tiled=tiled, stream=stream)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         h.apply(x, y, tiled=tiled, stream=stream)
     torch.cuda.synchronize()
@@ -141,6 +151,7 @@ def other_precision_apply(h, precision, tiled_arg, steps=20, warmup=3):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         h.apply(x, y, tiled=tiled, stream=stream)
+    torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for e0, e1 in evs:
         e0.record(stream)
