@@ -190,6 +190,52 @@ __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T
   }
 }
 
+// The same update for one right-hand side and k <= kUpdate1MaxK: the
+// coefficients sit in LDS, and each thread issues the loads of four basis
+// vectors before it uses them, so several reads per thread are in flight
+// (one load and its wait per vector otherwise).  The sum runs over i in
+// the same order as the general kernel.
+constexpr int kUpdate1MaxK = 1024;
+template <typename T>
+__global__ void __launch_bounds__(256) basis_update1_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv,
+                                                            int k, const double2 *__restrict__ h,
+                                                            typename Cplx<T>::t *__restrict__ w, int64_t n,
+                                                            double sign, const double2 *__restrict__ post) {
+  using T2 = typename Cplx<T>::t;
+  __shared__ double2 hs[kUpdate1MaxK];
+  for (int i = threadIdx.x; i < k; i += 256) hs[i] = h[i];
+  __syncthreads();
+  const double scale = post ? post[0].x : 1.0;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    const T2 o = w[idx];
+    double sx = 0, sy = 0;
+    int i = 0;
+    for (; i + 4 <= k; i += 4) {
+      T2 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = V[(int64_t)(i + q) * ldv + idx];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 c = hs[i + q];
+        sx += (double)a[q].x * c.x - (double)a[q].y * c.y;
+        sy += (double)a[q].x * c.y + (double)a[q].y * c.x;
+      }
+    }
+    for (; i < k; ++i) {
+      const T2 a = V[(int64_t)i * ldv + idx];
+      const double2 c = hs[i];
+      sx += (double)a.x * c.x - (double)a.y * c.y;
+      sy += (double)a.x * c.y + (double)a.y * c.x;
+    }
+    double ox = (double)o.x + sign * sx, oy = (double)o.y + sign * sy;
+    if (post) {  // fused normalisation
+      ox *= scale;
+      oy *= scale;
+    }
+    w[idx] = T2{(T)ox, (T)oy};
+  }
+}
+
 // V_c <- sum_i V_i Q[i, c] for c < n_out (Q column-major, n_in x n_out,
 // n_out <= MAXC <= kRotateMax), in place: each thread reads all n_in entries
 // of its element before it writes any, and no other thread touches that
@@ -489,8 +535,12 @@ template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
                          hipStream_t s, const double2 *post) {
   if (k <= 0 && !post) return HEOM_OK;
-  hipLaunchKernelGGL(basis_update_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
-                     k, h, (typename Cplx<T>::t *)w, n, R, sign, post);
+  if (R == 1 && k <= kUpdate1MaxK)
+    hipLaunchKernelGGL(basis_update1_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
+                       k, h, (typename Cplx<T>::t *)w, n, sign, post);
+  else
+    hipLaunchKernelGGL(basis_update_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)V,
+                       ldv, k, h, (typename Cplx<T>::t *)w, n, R, sign, post);
   HEOM_HIP_CHECK(hipGetLastError());
   return HEOM_OK;
 }

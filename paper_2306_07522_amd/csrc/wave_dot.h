@@ -44,12 +44,16 @@ __device__ __forceinline__ void wave_mdot2_chunk(WaveDotShared &sh, const typena
   double ww = 0.0;
   if (!on) e1 = e0;  // no sub-blocks: zeros
   for (int64_t base = e0 + (int64_t)wave * 64 * P; base < e1; base += (int64_t)4 * 64 * P) {
+    // a whole sub-block (every sub-block but the ragged last) loads without
+    // per-element guards, so its P loads per vector are in flight together
+    // instead of one guarded load at a time
+    const bool full = base + 64 * P <= e1;
     double wx[P], wy[P], ux[P], uy[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t e = base + lane + 64 * p;
       wx[p] = wy[p] = ux[p] = uy[p] = 0.0;
-      if (e < e1) {
+      if (full || e < e1) {
         const T2 bw = w[e], bu = u[e];
         wx[p] = bw.x; wy[p] = bw.y; ux[p] = bu.x; uy[p] = bu.y;
         ww += wx[p] * wx[p] + wy[p] * wy[p];
@@ -64,17 +68,24 @@ __device__ __forceinline__ void wave_mdot2_chunk(WaveDotShared &sh, const typena
         const int q = 4 * g + c;
         double dx = 0.0, dy = 0.0, fx = 0.0, fy = 0.0;
         if (q < k) {
+          T2 a[P];
+          if (full) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) a[p] = V[(int64_t)q * ldv + base + lane + 64 * p];
+          } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              const int64_t e = base + lane + 64 * p;
+              a[p] = e < e1 ? V[(int64_t)q * ldv + e] : T2{0, 0};
+            }
+          }
 #pragma unroll
           for (int p = 0; p < P; ++p) {
-            const int64_t e = base + lane + 64 * p;
-            if (e < e1) {
-              const T2 a = V[(int64_t)q * ldv + e];
-              const double ax = a.x, ay = a.y;
-              dx += ax * wx[p] + ay * wy[p];
-              dy += ax * wy[p] - ay * wx[p];
-              fx += ax * ux[p] + ay * uy[p];
-              fy += ax * uy[p] - ay * ux[p];
-            }
+            const double ax = a[p].x, ay = a[p].y;
+            dx += ax * wx[p] + ay * wy[p];
+            dy += ax * wy[p] - ay * wx[p];
+            fx += ax * ux[p] + ay * uy[p];
+            fy += ax * uy[p] - ay * ux[p];
           }
         }
         v[4 * c] = dx; v[4 * c + 1] = dy; v[4 * c + 2] = fx; v[4 * c + 3] = fy;
