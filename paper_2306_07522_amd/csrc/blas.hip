@@ -191,12 +191,12 @@ __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T
 }
 
 // The same update for one right-hand side and k <= kUpdate1MaxK: the
-// coefficients sit in LDS, and each thread issues the loads of four basis
+// coefficients sit in LDS, and each thread issues the loads of U basis
 // vectors before it uses them, so several reads per thread are in flight
 // (one load and its wait per vector otherwise).  The sum runs over i in
 // the same order as the general kernel.
 constexpr int kUpdate1MaxK = 1024;
-template <typename T>
+template <typename T, int U>
 __global__ void __launch_bounds__(256) basis_update1_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv,
                                                             int k, const double2 *__restrict__ h,
                                                             typename Cplx<T>::t *__restrict__ w, int64_t n,
@@ -210,12 +210,12 @@ __global__ void __launch_bounds__(256) basis_update1_kernel(const typename Cplx<
     const T2 o = w[idx];
     double sx = 0, sy = 0;
     int i = 0;
-    for (; i + 4 <= k; i += 4) {
-      T2 a[4];
+    for (; i + U <= k; i += U) {
+      T2 a[U];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = V[(int64_t)(i + q) * ldv + idx];
+      for (int q = 0; q < U; ++q) a[q] = V[(int64_t)(i + q) * ldv + idx];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < U; ++q) {
         const double2 c = hs[i + q];
         sx += (double)a[q].x * c.x - (double)a[q].y * c.y;
         sy += (double)a[q].x * c.y + (double)a[q].y * c.x;
@@ -535,9 +535,14 @@ template <typename T>
 heom_status basis_update(const void *V, int64_t ldv, int k, const double2 *h, void *w, int64_t n, int R, double sign,
                          hipStream_t s, const double2 *post) {
   if (k <= 0 && !post) return HEOM_OK;
-  if (R == 1 && k <= kUpdate1MaxK)
-    hipLaunchKernelGGL(basis_update1_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, (const typename Cplx<T>::t *)V, ldv,
-                       k, h, (typename Cplx<T>::t *)w, n, sign, post);
+  // FP32 gains from four reads in flight per thread; FP64 (twice the bytes
+  // per element) keeps the general kernel, which measured faster there
+  // (two-orbital tier-4 GMRES-DR: 1.243 s, against 1.273 s with one, two or
+  // four reads in flight from this kernel)
+  constexpr int U = std::is_same<T, double>::value ? 0 : 4;
+  if (R == 1 && k <= kUpdate1MaxK && U > 0)
+    hipLaunchKernelGGL((basis_update1_kernel<T, (U > 0 ? U : 1)>), dim3(grid_for(n)), dim3(256), 0, s,
+                       (const typename Cplx<T>::t *)V, ldv, k, h, (typename Cplx<T>::t *)w, n, sign, post);
   else
     hipLaunchKernelGGL(basis_update_kernel<T>, dim3(grid_for(n * R)), dim3(256), 0, s, (const typename Cplx<T>::t *)V,
                        ldv, k, h, (typename Cplx<T>::t *)w, n, R, sign, post);
