@@ -289,16 +289,23 @@ __global__ void __launch_bounds__(256) seg_mdot_kernel(const typename Cplx<T>::t
   double ax[NI], ay[NI];
 #pragma unroll
   for (int q = 0; q < NI; ++q) ax[q] = ay[q] = 0.0;
+  const bool full = i0 + NI <= k;  // whole groups load together, unguarded
   if (on) {
     for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
       const T2 b = w[e];
+      T2 a[NI];
+      if (full) {
 #pragma unroll
-      for (int q = 0; q < NI; ++q)
-        if (i0 + q < k) {
-          const T2 a = V[(i0 + q) * ldv + e];
-          ax[q] += (double)a.x * b.x + (double)a.y * b.y;
-          ay[q] += (double)a.x * b.y - (double)a.y * b.x;
-        }
+        for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e] : T2{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        ax[q] += (double)a[q].x * b.x + (double)a[q].y * b.y;
+        ay[q] += (double)a[q].x * b.y - (double)a[q].y * b.x;
+      }
     }
   }
 #pragma unroll
@@ -350,19 +357,28 @@ __global__ void __launch_bounds__(256) seg_mdot2_kernel(const typename Cplx<T>::
   double ax[NI], ay[NI], cx[NI], cy[NI], ww = 0.0;
 #pragma unroll
   for (int q = 0; q < NI; ++q) ax[q] = ay[q] = cx[q] = cy[q] = 0.0;
+  // a group of NI whole basis vectors loads them together, without a
+  // per-vector guard (a guarded load is waited for on its own)
+  const bool full = i0 + NI <= k;
   if (on) {
     for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
       const T2 bw = w[e], bu = u[e];
       if (blockIdx.y == 0) ww += (double)bw.x * bw.x + (double)bw.y * bw.y;
+      T2 a[NI];
+      if (full) {
 #pragma unroll
-      for (int q = 0; q < NI; ++q)
-        if (i0 + q < k) {
-          const T2 a = V[(i0 + q) * ldv + e];
-          ax[q] += (double)a.x * bw.x + (double)a.y * bw.y;
-          ay[q] += (double)a.x * bw.y - (double)a.y * bw.x;
-          cx[q] += (double)a.x * bu.x + (double)a.y * bu.y;
-          cy[q] += (double)a.x * bu.y - (double)a.y * bu.x;
-        }
+        for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e] : T2{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        ax[q] += (double)a[q].x * bw.x + (double)a[q].y * bw.y;
+        ay[q] += (double)a[q].x * bw.y - (double)a[q].y * bw.x;
+        cx[q] += (double)a[q].x * bu.x + (double)a[q].y * bu.y;
+        cy[q] += (double)a[q].x * bu.y - (double)a[q].y * bu.x;
+      }
     }
   }
 #pragma unroll
@@ -459,6 +475,7 @@ __global__ void __launch_bounds__(64) batch_gram_kernel(double2 *__restrict__ G,
 // w += sign * sum_{i < k} V_i h[i * S + seg]; with post, instances whose
 // post[seg].x > 0 write the result times post[seg].x to vnext instead
 // (fused normalisation; w is left as it was)
+constexpr int kSegUpdateMaxK = 1024;  // basis columns of one batched Arnoldi step (the launcher checks)
 template <typename T>
 __global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>::t *__restrict__ V, int64_t ldv, int k,
                                                          const double2 *__restrict__ h, int S,
@@ -468,18 +485,52 @@ __global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>:
                                                          const double2 *__restrict__ post,
                                                          typename Cplx<T>::t *__restrict__ vnext) {
   using T2 = typename Cplx<T>::t;
+  // this instance's nonzero coefficients, compacted in LDS in their order
+  // (columns past the instance's basis may hold garbage and are skipped), so
+  // that the element loop issues four basis reads before it uses them
+  __shared__ double2 hs[kSegUpdateMaxK];
+  __shared__ int hi[kSegUpdateMaxK];
+  __shared__ int n_nz;
+  // (hs first holds all k coefficients; one thread then compacts it in
+  // place, writing slot m <= the slot i it reads)
   const int c = blockIdx.x;
   const int s = ch_seg[c];
   if (active && !active[s]) return;
   const double sc = post ? post[s].x : 0.0;
   T2 *dst = sc > 0.0 ? vnext : w;
   const double f = sc > 0.0 ? sc : 1.0;
+  for (int i = threadIdx.x; i < k; i += 256) hs[i] = h[(int64_t)i * S + s];  // all loads at once
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int i = 0; i < k; ++i) {
+      const double2 hh = hs[i];
+      if (hh.x == 0.0 && hh.y == 0.0) continue;
+      hs[m] = hh;
+      hi[m] = i;
+      ++m;
+    }
+    n_nz = m;
+  }
+  __syncthreads();
+  const int m = n_nz;
   for (int64_t e = ch_e[c] + threadIdx.x; e < ch_e[c + 1]; e += 256) {
     double ax = w[e].x, ay = w[e].y;
-    for (int i = 0; i < k; ++i) {
-      const double2 hh = h[(int64_t)i * S + s];
-      if (hh.x == 0.0 && hh.y == 0.0) continue;  // columns past this instance's basis may hold garbage
-      const T2 v = V[i * ldv + e];
+    int j = 0;
+    for (; j + 4 <= m; j += 4) {
+      T2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = V[hi[j + q] * ldv + e];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 hh = hs[j + q];
+        ax += sign * ((double)v[q].x * hh.x - (double)v[q].y * hh.y);
+        ay += sign * ((double)v[q].x * hh.y + (double)v[q].y * hh.x);
+      }
+    }
+    for (; j < m; ++j) {
+      const T2 v = V[hi[j] * ldv + e];
+      const double2 hh = hs[j];
       ax += sign * ((double)v.x * hh.x - (double)v.y * hh.y);
       ay += sign * ((double)v.x * hh.y + (double)v.y * hh.x);
     }
@@ -743,6 +794,7 @@ template <typename T>
 static heom_status seg_update(heom_batch &b, const void *V, int64_t ldv, int k, const double2 *h, void *w,
                               double sign, hipStream_t s, const double2 *post = nullptr, void *vnext = nullptr) {
   using T2 = typename Cplx<T>::t;
+  if (k > kSegUpdateMaxK) return fail(HEOM_ERR_UNSUPPORTED, "batch: Krylov basis too large for the segmented update");
   hipLaunchKernelGGL(seg_update_kernel<T>, dim3(b.n_chunks), dim3(256), 0, s, (const T2 *)V, ldv, k, h, b.S, (T2 *)w,
                      b.ch_e, b.ch_seg, b.active, sign, post, (T2 *)vnext);
   HEOM_HIP_CHECK(hipGetLastError());
