@@ -35,15 +35,21 @@ __global__ void __launch_bounds__(256) mdot_kernel(const typename Cplx<T>::t *__
 #pragma unroll
     for (int q = 0; q < NI; ++q) ax[q] = ay[q] = 0.0;
     if (trow < rows_per_pass && r < R) {
+      const bool full = i0 + NI <= k;  // whole groups load together, unguarded
       for (int64_t e = e0 + trow; e < e1; e += rows_per_pass) {
         const T2 b = w[e * R + r];
+        T2 a[NI];
+        if (full) {
+#pragma unroll
+          for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e * R + r];
+        } else {
+#pragma unroll
+          for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e * R + r] : T2{0, 0};
+        }
 #pragma unroll
         for (int q = 0; q < NI; ++q) {
-          if (i0 + q < k) {
-            const T2 a = V[(i0 + q) * ldv + e * R + r];
-            ax[q] += (double)a.x * b.x + (double)a.y * b.y;
-            ay[q] += (double)a.x * b.y - (double)a.y * b.x;
-          }
+          ax[q] += (double)a[q].x * b.x + (double)a[q].y * b.y;
+          ay[q] += (double)a[q].x * b.y - (double)a[q].y * b.x;
         }
       }
     }
@@ -83,18 +89,25 @@ __global__ void __launch_bounds__(256) mdot2_kernel(const typename Cplx<T>::t *_
   double ax[NI], ay[NI], cx[NI], cy[NI], ww = 0.0;
 #pragma unroll
   for (int q = 0; q < NI; ++q) ax[q] = ay[q] = cx[q] = cy[q] = 0.0;
+  const bool full = i0 + NI <= k;  // whole groups load together, unguarded
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const T2 bw = w[e], bu = u[e];
     if (blockIdx.y == 0) ww += (double)bw.x * bw.x + (double)bw.y * bw.y;
+    T2 a[NI];
+    if (full) {
 #pragma unroll
-    for (int q = 0; q < NI; ++q)
-      if (i0 + q < k) {
-        const T2 a = V[(i0 + q) * ldv + e];
-        ax[q] += (double)a.x * bw.x + (double)a.y * bw.y;
-        ay[q] += (double)a.x * bw.y - (double)a.y * bw.x;
-        cx[q] += (double)a.x * bu.x + (double)a.y * bu.y;
-        cy[q] += (double)a.x * bu.y - (double)a.y * bu.x;
-      }
+      for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e] : T2{0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      ax[q] += (double)a[q].x * bw.x + (double)a[q].y * bw.y;
+      ay[q] += (double)a[q].x * bw.y - (double)a[q].y * bw.x;
+      cx[q] += (double)a[q].x * bu.x + (double)a[q].y * bu.y;
+      cy[q] += (double)a[q].x * bu.y - (double)a[q].y * bu.x;
+    }
   }
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
