@@ -91,6 +91,28 @@ def test_batch_apply_matches_single_instance_applies(border):
         assert _rel(ys32.to(torch.complex128), ref) <= 1e-5
 
 
+def test_batch_apply_with_a_wide_task_matches_single_instance_applies():
+    """One d = 8 instance whose tier-0 task has 70 children (40 bosonic and
+    30 fermionic exponents at tier 1) keeps the whole batch on the wave
+    tiles that read their task tables from memory; the other instances and
+    the wide one still match their single-instance applies."""
+    torch = _torch()
+    rng = np.random.default_rng(308)
+    H = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    baths = wl.random_raw_baths(rng, 8, n_bos_baths=1, n_bos_exp=40, n_ferm_baths=1, n_ferm_exp=15)
+    wide = dict(name="wide_d8", d=8, H=H + H.conj().T, baths=baths, m_max=1, n_max=1)
+    cfgs = [c for c in _pick(40) if c["d"] in (8, 16)][:4] + [wide]
+    hs, b = _build(cfgs)
+    g = torch.Generator(device="cuda").manual_seed(4)
+    x = torch.randn(b.n, dtype=torch.complex128, device="cuda", generator=g)
+    y = b.apply(x)
+    y32 = b.apply(x.to(torch.complex64))
+    for h, xs, ys, ys32 in zip(hs, b.split(x), b.split(y), b.split(y32)):
+        ref = h.apply(xs.contiguous())
+        assert _rel(ys, ref) <= 1e-12
+        assert _rel(ys32.to(torch.complex128), ref) <= 1e-5
+
+
 def test_batch_apply_matches_oracle():
     torch = _torch()
     cfgs = [c for c in _pick(60, max_n_ado=300) if c["d"] <= 8][:6]
