@@ -339,11 +339,13 @@ static heom_status launch_T(Hier &h, const ApplyArgs &a, const Plan &pl, int64_t
   const size_t tab_bytes = (size_t)P.n_centries * (sizeof(T2) + sizeof(int)) + 16 + (size_t)d * sizeof(T2);
   const size_t smem = 4 * (size_t)d * d * sizeof(T2) + tab_bytes;
   if (a.n_rhs == 1 && (d == 8 || d == 16 || d == 20) && smem <= 48 * 1024) {
-    // two tasks per wave on large plans: each workgroup's table staging then
-    // serves eight tasks (two-orbital tier 4: 0.956 -> 0.945 ms FP64, 0.502
-    // -> 0.493 ms FP32; four per wave: 1.02 ms); small plans keep one task per
-    // wave so that every CU gets work
-    P.tpw = n_tasks >= (int64_t)1 << 16 ? 2 : 1;
+    // two tasks per wave for the FP32 and the RK4-stage (epilogue) kernels on
+    // large plans: each workgroup's table staging then serves eight tasks.
+    // Two-orbital tier 4, same box: FP32 apply 0.505 -> 0.494 ms, FP64 RK4
+    // step 4.43 -> 4.25 ms; the plain FP64 apply keeps one task per wave
+    // (0.913 against 0.932 ms with two), and small plans keep one so that
+    // every CU gets work.
+    P.tpw = n_tasks >= (int64_t)1 << 16 && (sizeof(T) == 4 || a.epi) ? 2 : 1;
     P.xchunk = 64;
     const int64_t grid = (n_tasks + 4 * P.tpw - 1) / (4 * P.tpw);
     if (grid > 0x7fffffff) return fail(HEOM_ERR_UNSUPPORTED, "apply grid too large");
