@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) seg_mdot_kernel(const typename Cplx<T>::t
       T2 a[NI];
       if (full) {
 #pragma unroll
-        for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e];
+        for (int q = 0; q < NI; ++q) a[q] = load_stream<T>(&V[(i0 + q) * ldv + e]);
       } else {
 #pragma unroll
         for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e] : T2{0, 0};
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(256) seg_mdot2_kernel(const typename Cplx<T>::
       T2 a[NI];
       if (full) {
 #pragma unroll
-        for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e];
+        for (int q = 0; q < NI; ++q) a[q] = load_stream<T>(&V[(i0 + q) * ldv + e]);
       } else {
 #pragma unroll
         for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e] : T2{0, 0};
@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(256) seg_update_kernel(const typename Cplx<T>:
     for (; j + 4 <= m; j += 4) {
       T2 v[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = V[hi[j + q] * ldv + e];
+      for (int q = 0; q < 4; ++q) v[q] = load_stream<T>(&V[hi[j + q] * ldv + e]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const double2 hh = hs[j + q];

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) mdot_kernel(const typename Cplx<T>::t *__
         T2 a[NI];
         if (full) {
 #pragma unroll
-          for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e * R + r];
+          for (int q = 0; q < NI; ++q) a[q] = load_stream<T>(&V[(i0 + q) * ldv + e * R + r]);
         } else {
 #pragma unroll
           for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e * R + r] : T2{0, 0};
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(256) mdot2_kernel(const typename Cplx<T>::t *_
     T2 a[NI];
     if (full) {
 #pragma unroll
-      for (int q = 0; q < NI; ++q) a[q] = V[(i0 + q) * ldv + e];
+      for (int q = 0; q < NI; ++q) a[q] = load_stream<T>(&V[(i0 + q) * ldv + e]);
     } else {
 #pragma unroll
       for (int q = 0; q < NI; ++q) a[q] = i0 + q < k ? V[(i0 + q) * ldv + e] : T2{0, 0};
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) basis_update_kernel(const typename Cplx<T
     const int r = (int)(idx % R);
     double sx = 0, sy = 0;
     for (int i = 0; i < k; ++i) {
-      const T2 a = V[i * ldv + idx];
+      const T2 a = load_stream<T>(&V[i * ldv + idx]);
       const double2 c = h[(int64_t)i * R + r];
       sx += (double)a.x * c.x - (double)a.y * c.y;
       sy += (double)a.x * c.y + (double)a.y * c.x;
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) basis_update1_kernel(const typename Cplx<
     for (; i + U <= k; i += U) {
       T2 a[U];
 #pragma unroll
-      for (int q = 0; q < U; ++q) a[q] = V[(int64_t)(i + q) * ldv + idx];
+      for (int q = 0; q < U; ++q) a[q] = load_stream<T>(&V[(int64_t)(i + q) * ldv + idx]);
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         const double2 c = hs[i + q];

@@ -71,7 +71,7 @@ __device__ __forceinline__ void wave_mdot2_chunk(WaveDotShared &sh, const typena
           T2 a[P];
           if (full) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) a[p] = V[(int64_t)q * ldv + base + lane + 64 * p];
+            for (int p = 0; p < P; ++p) a[p] = load_stream<T>(&V[(int64_t)q * ldv + base + lane + 64 * p]);
           } else {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
