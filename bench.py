@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # calibrated on a plain device copy (profiles/apply_wave_fp64_two_orbital_tier4.md).
 # Valid only for the apply source it was measured on: reported as null otherwise.
 MEASURED_TRAFFIC = {
-    ("fp64", "untiled"): {"apply_sha256_prefix": "f4b8ece203f67968", "bytes": 6_695_157_146},
-    ("fp32", "untiled"): {"apply_sha256_prefix": "f4b8ece203f67968", "bytes": 3_408_195_174},
+    ("fp64", "untiled"): {"apply_sha256_prefix": "3ed160c6a54bd7ad", "bytes": 6_610_992_947},
+    ("fp32", "untiled"): {"apply_sha256_prefix": "3ed160c6a54bd7ad", "bytes": 3_371_005_952},
 }
 
 

@@ -60,7 +60,12 @@ struct ApplyParams {
 template <bool EPI, typename T>
 __device__ __forceinline__ void store_out(const ApplyParams<T> &P, int64_t idx, typename Cplx<T>::t v) {
   if constexpr (!EPI) {
-    P.y[idx] = v;
+    // a streaming store: y is not read again by this launch, and keeping it
+    // out of the way leaves L2 to the neighbour blocks (two-orbital tier 4:
+    // 0.918 -> 0.906 ms FP64, 1.5 % less fetched)
+    T *q = reinterpret_cast<T *>(&P.y[idx]);
+    __builtin_nontemporal_store(v.x, q);
+    __builtin_nontemporal_store(v.y, q + 1);
     return;
   }
   if (!P.epi) {
