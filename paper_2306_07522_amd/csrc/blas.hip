@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256) basis_rotate_kernel(typename Cplx<T>::t *
 #pragma unroll
     for (int p = 0; p < kAccumMax; ++p) bx[p] = by[p] = 0.0;
     for (int i = 0; i < n_in; ++i) {
-      const T2 v = V[i * ldv + e];
+      const T2 v = load_stream<T>(&V[i * ldv + e]);
       const double vx = v.x, vy = v.y;
 #pragma unroll
       for (int c = 0; c < MAXC; ++c) {
@@ -296,7 +296,11 @@ __global__ void __launch_bounds__(256) basis_rotate_kernel(typename Cplx<T>::t *
     }
 #pragma unroll
     for (int c = 0; c < MAXC; ++c)
-      if (c < n_out) V[c * ldv + e] = T2{(T)ax[c], (T)ay[c]};
+      if (c < n_out) {
+        T *q = reinterpret_cast<T *>(&V[c * ldv + e]);
+        __builtin_nontemporal_store((T)ax[c], q);
+        __builtin_nontemporal_store((T)ay[c], q + 1);
+      }
 #pragma unroll
     for (int p = 0; p < kAccumMax; ++p)
       if (p < n_acc) {
@@ -322,7 +326,7 @@ __global__ void __launch_bounds__(256) basis_accum_kernel(const typename Cplx<T>
 #pragma unroll
     for (int p = 0; p < kAccumMax; ++p) ax[p] = ay[p] = 0.0;
     for (int i = 0; i < n_in; ++i) {
-      const T2 v = V[i * ldv + e];
+      const T2 v = load_stream<T>(&V[i * ldv + e]);
       const double vx = v.x, vy = v.y;
 #pragma unroll
       for (int p = 0; p < kAccumMax; ++p)
